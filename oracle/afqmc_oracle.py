@@ -1,0 +1,302 @@
+"""Plain FP64 CPU oracle of the phaseless-AFQMC walker step.
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module.  The product
+path (the HIP library and its binding) never calls it, and it shares no
+code with that path.
+
+What it computes follows arXiv 2209.04015 (ipie):
+
+* Hamiltonian and its Cholesky form: Sec. II.B, Eq. (Habinitio) and the
+  factorisation (pr|qs) = sum_a L^a_pr L^a_qs written under it.
+* Propagator, importance function, overlap ratio, optimal force bias,
+  phaseless projection and weight update: Sec. II.B, Eqs. (Bx), (import),
+  (ovl), the force-bias definition, (ph), (theta) and the two update
+  equations that close the section.
+* Overlap: Sec. III.A, the single-determinant overlap det(C_psi0^dagger C_phi).
+* Green's function, half-rotated Cholesky vectors and force bias:
+  Sec. III.B, Eqs. (fb), (gf), (halfgf), (rfb).
+* Local energy (one-body, Coulomb, exchange): Sec. III.C, the E_L
+  definition, the exchange formula and the T intermediate.
+
+Readings where the paper is silent (each is listed in the design doc as well):
+
+* R1  The one-body operator inside B(x): H is rewritten as
+      sum h'_pq a+_p a_q + 1/2 sum_g v_g^2 with v_g = sum L_g,pq a+_p a_q and
+      h' = h1 - 1/2 sum_g L_g L_g (exact for real symmetric L_g).
+* R2  Symmetric Trotter split B = e^{-dt h'/2} e^{VHS} e^{-dt h'/2}, with the
+      scalar e^{-dt mu/2} factored out of each half step: P = e^{-dt (h'-mu)/2}.
+* R3  Weights are kept as log w.  The per-step constant
+      -dt (mu (n_a + n_b) - E_T) (mu factored out of P, E_T the energy
+      shift) is added to every walker.
+* R4  v' = i v (Hubbard-Stratonovich of e^{-dt v^2/2}); vbias = sum G L (Eq. fb);
+      xbar = -i sqrt(dt) vbias; VHS = i sqrt(dt) sum_g (x_g - xbar_g) L_g.
+* R5  No cap on the force bias.
+* R6  exp(VHS) is the Taylor series truncated after the order-6 term.
+* R7  Determinants through LU with partial pivoting, kept as complex logs.
+* R8  The phase is theta = arg(O_z) of the overlap ratio alone.
+* R9  QR re-orthogonalisation: phi = Q R, phi <- Q D with D = diag(R_ii/|R_ii|);
+      log overlap -= sum ln |R_ii|.
+* R10 E1 = sum_s tr(hh^s theta^s); EJ = 1/2 sum_g (sum_s tr T^s_g)^2;
+      EK = -1/2 sum_s sum_g tr(T^s_g T^s_g); no nuclear term.
+* R11 G_pq = <a+_p a_q> = (phi S^-1 PhiT^T)_qp with S = PhiT^T phi.
+
+Array conventions: walkers phi are [W, N, n] complex128 per spin; the trial
+PhiT is [N, n] float64 per spin; theta = phi S^-1 is [W, N, n];
+Lh^s[g, i, p] = sum_q PhiT^s[q, i] L[g, q, p].
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+__all__ = [
+    "OracleHamiltonian",
+    "setup",
+    "log_det",
+    "theta_and_logdet",
+    "overlap",
+    "full_green",
+    "force_bias",
+    "shift",
+    "vhs",
+    "taylor_apply",
+    "propagate",
+    "local_energy",
+    "orthogonalise",
+    "step",
+]
+
+
+@dataclasses.dataclass
+class OracleHamiltonian:
+    h1: np.ndarray          # [N, N] one-body integrals (used by the energy)
+    L: np.ndarray           # [K, N, N] Cholesky vectors
+    phiT_a: np.ndarray      # [N, na]
+    phiT_b: np.ndarray      # [N, nb]
+    dt: float
+    taylor_order: int
+    hprime: np.ndarray      # [N, N] h' of R1
+    mu: float               # scalar factored out of the one-body half step (R2)
+    P: np.ndarray           # [N, N] exp(-dt/2 (h' - mu))
+    Lh_a: np.ndarray        # [K, na, N] half-rotated Cholesky vectors (Sec. III.B)
+    Lh_b: np.ndarray        # [K, nb, N]
+    hh_a: np.ndarray        # [na, N] PhiT_a^T h1
+    hh_b: np.ndarray        # [nb, N]
+    e_shift: float          # E_T of R3
+
+    @property
+    def N(self):
+        return self.h1.shape[0]
+
+    @property
+    def K(self):
+        return self.L.shape[0]
+
+    @property
+    def nelec(self):
+        return self.phiT_a.shape[1] + self.phiT_b.shape[1]
+
+
+def setup(h1, L, phiT_a, phiT_b=None, dt=0.005, taylor_order=6, mu=None, e_shift=None):
+    """Precompute the step-independent arrays (run once).
+
+    h' follows R1; P follows R2 with mu = tr(h')/N unless given; the
+    half-rotated vectors follow Sec. III.B; E_T defaults to the local
+    energy of the trial itself.
+    """
+    h1 = np.asarray(h1, dtype=np.float64)
+    L = np.asarray(L, dtype=np.float64)
+    phiT_a = np.asarray(phiT_a, dtype=np.float64)
+    phiT_b = phiT_a if phiT_b is None else np.asarray(phiT_b, dtype=np.float64)
+    K, N, _ = L.shape
+    # sum_g L_g L_g as one matrix product: [N, (g, r)] x [(g, r), N]
+    LL = L.transpose(1, 0, 2).reshape(N, K * N) @ L.reshape(K * N, N)
+    hprime = h1 - 0.5 * LL
+    if mu is None:
+        mu = float(np.trace(hprime)) / N
+    evals, evecs = np.linalg.eigh(hprime)
+    P = (evecs * np.exp(-0.5 * dt * (evals - mu))) @ evecs.T
+    Lh_a = np.matmul(phiT_a.T[None, :, :], L)
+    Lh_b = np.matmul(phiT_b.T[None, :, :], L)
+    ham = OracleHamiltonian(
+        h1=h1, L=L, phiT_a=phiT_a, phiT_b=phiT_b, dt=float(dt),
+        taylor_order=int(taylor_order), hprime=hprime, mu=float(mu), P=P,
+        Lh_a=Lh_a, Lh_b=Lh_b, hh_a=phiT_a.T @ h1, hh_b=phiT_b.T @ h1,
+        e_shift=0.0,
+    )
+    if e_shift is None:
+        e = local_energy(ham, phiT_a[None].astype(np.complex128),
+                         phiT_b[None].astype(np.complex128))
+        e_shift = float(np.real(e[0].sum()))
+    ham.e_shift = float(e_shift)
+    return ham
+
+
+# ---------------------------------------------------------------------------
+# Overlap and Green's function (Sec. III.A, III.B)
+# ---------------------------------------------------------------------------
+
+def log_det(S):
+    """Complex log det of a stack of square matrices via LU with partial pivoting (R7).
+
+    Returns log|det| + i arg(det); the phase is defined modulo 2 pi.
+    """
+    sign, logabs = np.linalg.slogdet(S)
+    return logabs + 1j * np.angle(sign)
+
+
+def theta_and_logdet(phiT, phi):
+    """theta = phi (PhiT^T phi)^{-1} and log det(PhiT^T phi) for each walker.
+
+    theta[z, p, j] is the paper's theta^z_jp (Eq. halfgf), stored N x n.
+    """
+    S = np.einsum("pi,zpj->zij", phiT, phi)          # S = PhiT^T phi  [W, n, n]
+    ld = log_det(S)
+    # theta S = phi  <=>  S^T theta^T = phi^T
+    theta = np.linalg.solve(np.swapaxes(S, 1, 2), np.swapaxes(phi, 1, 2))
+    return np.swapaxes(theta, 1, 2), ld
+
+
+def overlap(ham, phi_a, phi_b):
+    """log <Psi_T|phi_z> = sum over spins of log det(PhiT^T phi) (Sec. III.A)."""
+    _, la = theta_and_logdet(ham.phiT_a, phi_a)
+    _, lb = theta_and_logdet(ham.phiT_b, phi_b)
+    return la + lb
+
+
+def full_green(phiT, phi):
+    """G[z, p, q] = <Psi_T|a+_p a_q|phi_z>/<Psi_T|phi_z> = (phi S^-1 PhiT^T)_qp (Eq. halfgf, R11)."""
+    theta, _ = theta_and_logdet(phiT, phi)
+    Gcal = np.einsum("zpj,qj->zpq", theta, phiT)     # phi S^-1 PhiT^T
+    return np.swapaxes(Gcal, 1, 2)
+
+
+def force_bias(ham, phi_a, phi_b):
+    """vbias[z, g] = sum_s sum_{i,p} Lh^s[g, i, p] theta^s_z[p, i] (Eq. rfb; = sum_pq G_pq L^g_pq, Eq. fb)."""
+    ta, _ = theta_and_logdet(ham.phiT_a, phi_a)
+    tb, _ = theta_and_logdet(ham.phiT_b, phi_b)
+    K = ham.K
+    W = phi_a.shape[0]
+    # [K, (i,p)] x [(i,p), W] with theta transposed to (i, p) order
+    va = ham.Lh_a.reshape(K, -1) @ np.swapaxes(ta, 1, 2).reshape(W, -1).T
+    vb = ham.Lh_b.reshape(K, -1) @ np.swapaxes(tb, 1, 2).reshape(W, -1).T
+    return (va + vb).T
+
+
+# ---------------------------------------------------------------------------
+# Propagation and weights (Sec. II.B)
+# ---------------------------------------------------------------------------
+
+def shift(ham, vbias, x):
+    """xbar = -i sqrt(dt) vbias (R4); xs = x - xbar; a_z = sum_g (x xbar - xbar^2 / 2) (Eq. import)."""
+    sdt = math.sqrt(ham.dt)
+    xbar = -1j * sdt * vbias
+    xs = x - xbar
+    a = np.sum(x * xbar - 0.5 * xbar * xbar, axis=1)
+    return xs, a
+
+
+def vhs(ham, xs):
+    """VHS_z = i sqrt(dt) sum_g xs_zg L_g, an N x N complex symmetric matrix per walker (R4)."""
+    K, N, _ = ham.L.shape
+    Lf = ham.L.reshape(K, N * N)
+    v = (xs.real @ Lf) + 1j * (xs.imag @ Lf)
+    return 1j * math.sqrt(ham.dt) * v.reshape(-1, N, N)
+
+
+def taylor_apply(A, phi, order):
+    """sum_{k=0}^{order} A^k phi / k!, formed as t_0 = phi, t_k = A t_{k-1} / k (R6)."""
+    t = phi
+    acc = phi.copy()
+    for k in range(1, order + 1):
+        t = np.matmul(A, t) / k
+        acc = acc + t
+    return acc
+
+
+def _b_apply(ham, V, phi):
+    """B(x - xbar) phi with the scalar e^{-dt mu/2} of each half step removed (R2)."""
+    t = np.matmul(ham.P[None], phi)
+    t = taylor_apply(V, t, ham.taylor_order)
+    return np.matmul(ham.P[None], t)
+
+
+def propagate(ham, phi_a, phi_b, log_ovlp, log_w, x):
+    """One importance-sampled phaseless step for every walker (Sec. II.B).
+
+    Returns new (phi_a, phi_b, log_ovlp, log_w).  x is [W, K] real.
+    Order: theta -> vbias -> xbar, xs, a -> VHS -> phi' = B phi ->
+    ln O_z = log<Psi_T|phi'> - log<Psi_T|phi> -> phase -> log w.
+    """
+    vb = force_bias(ham, phi_a, phi_b)
+    xs, a = shift(ham, vb, x)
+    V = vhs(ham, xs)
+    na = _b_apply(ham, V, phi_a)
+    nb = _b_apply(ham, V, phi_b)
+    new_lo = overlap(ham, na, nb)
+    ln_o = new_lo - log_ovlp
+    theta_ph = np.imag(ln_o)                       # arg O_z (Eq. theta, R8)
+    cos_t = np.cos(theta_ph)
+    const = -ham.dt * (ham.mu * ham.nelec - ham.e_shift)      # R3
+    with np.errstate(divide="ignore"):
+        log_cos = np.where(cos_t > 0.0, np.log(np.where(cos_t > 0.0, cos_t, 1.0)), -np.inf)
+    new_lw = log_w + np.real(ln_o) + np.real(a) + const + log_cos     # Eqs. (import), (ph)
+    return na, nb, new_lo, new_lw
+
+
+# ---------------------------------------------------------------------------
+# Local energy (Sec. III.C)
+# ---------------------------------------------------------------------------
+
+def _energy_spin(Lh, hh, theta):
+    """(E1, sum_g tr T_g, EK) for one spin and one walker; T_g = Lh_g theta (n x n)."""
+    e1 = np.sum(hh * theta.T)                      # tr(hh theta)
+    T = np.matmul(Lh, theta[None])                 # [K, n, n], T_ij = sum_p Lh_ip theta_pj
+    tr = np.trace(T, axis1=1, axis2=2)             # [K]
+    ek = -0.5 * np.sum(T * np.swapaxes(T, 1, 2))   # -1/2 sum_g sum_ij T_ij T_ji
+    return e1, tr, ek
+
+
+def local_energy(ham, phi_a, phi_b):
+    """E_L split as [W, 3] complex: (E1, EJ, EK) (Sec. III.C, R10)."""
+    ta, _ = theta_and_logdet(ham.phiT_a, phi_a)
+    tb, _ = theta_and_logdet(ham.phiT_b, phi_b)
+    W = phi_a.shape[0]
+    out = np.zeros((W, 3), dtype=np.complex128)
+    for z in range(W):                             # direct algorithm: T per walker, consumed at once
+        e1a, tra, eka = _energy_spin(ham.Lh_a, ham.hh_a, ta[z])
+        e1b, trb, ekb = _energy_spin(ham.Lh_b, ham.hh_b, tb[z])
+        out[z, 0] = e1a + e1b
+        out[z, 1] = 0.5 * np.sum((tra + trb) ** 2)
+        out[z, 2] = eka + ekb
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Re-orthogonalisation
+# ---------------------------------------------------------------------------
+
+def orthogonalise(phi_a, phi_b, log_ovlp):
+    """QR of every walker and spin (R9); returns new (phi_a, phi_b, log_ovlp)."""
+    out = []
+    corr = np.zeros(phi_a.shape[0])
+    for phi in (phi_a, phi_b):
+        q, r = np.linalg.qr(phi)                   # Householder (LAPACK geqrf/ungqr)
+        d = np.diagonal(r, axis1=1, axis2=2)
+        ad = np.abs(d)
+        out.append(q * (d / ad)[:, None, :])
+        corr += np.sum(np.log(ad), axis=1)
+    return out[0], out[1], log_ovlp - corr
+
+
+def step(ham, phi_a, phi_b, log_ovlp, log_w, x, do_qr):
+    """One full step in the order of the method: propagate, optional QR, local energy."""
+    phi_a, phi_b, log_ovlp, log_w = propagate(ham, phi_a, phi_b, log_ovlp, log_w, x)
+    if do_qr:
+        phi_a, phi_b, log_ovlp = orthogonalise(phi_a, phi_b, log_ovlp)
+    e = local_energy(ham, phi_a, phi_b)
+    return phi_a, phi_b, log_ovlp, log_w, e

@@ -1,0 +1,131 @@
+"""Seeded synthetic inputs for the phaseless-AFQMC walker step.
+
+The paper measures on real molecules (acenes, Cu2O2) whose integrals and
+trial wavefunctions are not available; these generators stand in for them
+with the same array shapes and structure:
+
+* ``h1``: real symmetric N x N one-body matrix, off-diagonal and diagonal
+  entries ~ N(0, 0.1) (the upper triangle is drawn and mirrored) plus
+  ``diag(linspace(-2, 0, N))``.
+* ``L``: K real symmetric N x N Cholesky-like vectors, each the mirror of an
+  N(0, 1) draw scaled by ``exp(-gamma / decay)``, so that sum_g L_g (x) L_g is
+  positive semidefinite, as a factorised two-electron tensor is
+  (Sec. II.B, the Cholesky factorisation below the ab initio Hamiltonian).
+* ``phiT``: the n lowest eigenvectors of ``h1`` (a restricted, single
+  determinant trial as in Sec. III), each column's sign fixed so that its
+  largest-magnitude entry is positive.
+* ``fields``: auxiliary fields ~ N(0, 1), shape (steps, W, K) (Eq. Bx).
+
+Seeding: ``SeedSequence(seed).spawn(3)`` gives independent streams for the
+Hamiltonian, the fields and auxiliary draws (walker perturbations).  All
+streams are numpy PCG64 ``default_rng``.
+
+This module holds none of the method's arithmetic: it only draws and shapes
+inputs.  Both the oracle tests and the GPU tests take their inputs from it.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+__all__ = [
+    "Config",
+    "CONFIGS",
+    "hamiltonian",
+    "trial",
+    "fields",
+    "walkers_at_trial",
+    "walkers_perturbed",
+]
+
+
+@dataclasses.dataclass(frozen=True)
+class Config:
+    """One synthetic workload: sizes, time step and schedule."""
+
+    name: str
+    N: int          # spatial orbitals
+    n: int          # electrons per spin (n_alpha = n_beta)
+    K: int          # Cholesky vectors (N_aux in the paper)
+    decay: float    # L_gamma scale exp(-gamma / decay)
+    W: int          # walkers
+    steps: int
+    qr_interval: int
+    dt: float = 0.005
+    taylor_order: int = 6
+
+
+CONFIGS = {
+    # CPU-oracle size: every array is < 0.2 MB.
+    "n20": Config("n20", N=20, n=5, K=60, decay=15.0, W=16, steps=10, qr_interval=5),
+    # FP64 GPU baseline; 640 walkers and dt = 0.005 as in the Cu2O2 runs (Sec. IV).
+    "n100": Config("n100", N=100, n=20, K=400, decay=80.0, W=640, steps=200, qr_interval=5),
+    # Mixed-precision size.
+    "n200": Config("n200", N=200, n=32, K=1000, decay=200.0, W=1000, steps=100, qr_interval=1),
+    # The (52e, 290o) shape of the largest Cu2O2 active space (Tables III-IV).
+    "n290": Config("n290", N=290, n=26, K=2900, decay=580.0, W=512, steps=50, qr_interval=1),
+}
+
+
+def _streams(seed: int):
+    ham_ss, field_ss, aux_ss = np.random.SeedSequence(seed).spawn(3)
+    return ham_ss, field_ss, aux_ss
+
+
+def _mirror(a: np.ndarray) -> np.ndarray:
+    return np.triu(a) + np.triu(a, 1).T
+
+
+def hamiltonian(N: int, K: int, decay: float, seed: int = 0):
+    """Return ``(h1 [N,N], L [K,N,N])`` as float64, drawn from the Hamiltonian stream."""
+    ham_ss, _, _ = _streams(seed)
+    rng = np.random.default_rng(ham_ss)
+    h1 = _mirror(rng.normal(0.0, 0.1, size=(N, N))) + np.diag(np.linspace(-2.0, 0.0, N))
+    L = np.empty((K, N, N), dtype=np.float64)
+    for g in range(K):
+        L[g] = _mirror(rng.standard_normal((N, N))) * np.exp(-g / decay)
+    return h1, L
+
+
+def trial(h1: np.ndarray, n: int) -> np.ndarray:
+    """The n lowest eigenvectors of h1 as an [N, n] float64 array (sign-fixed)."""
+    _, vecs = np.linalg.eigh(h1)
+    phi = np.array(vecs[:, :n], dtype=np.float64, copy=True)
+    for j in range(n):
+        k = int(np.argmax(np.abs(phi[:, j])))
+        if phi[k, j] < 0:
+            phi[:, j] = -phi[:, j]
+    return phi
+
+
+def fields(W: int, K: int, steps: int, seed: int = 0) -> np.ndarray:
+    """Auxiliary fields x ~ N(0, 1), shape (steps, W, K), float64."""
+    _, field_ss, _ = _streams(seed)
+    rng = np.random.default_rng(field_ss)
+    return rng.standard_normal((steps, W, K))
+
+
+def walkers_at_trial(phiT: np.ndarray, W: int) -> np.ndarray:
+    """W walkers equal to the trial determinant, [W, N, n] complex128."""
+    return np.repeat(phiT[None, :, :].astype(np.complex128), W, axis=0)
+
+
+def walkers_perturbed(phiT: np.ndarray, W: int, scale: float, seed: int = 0,
+                      stream: int = 0, complex_noise: bool = True) -> np.ndarray:
+    """Walkers ``phiT + scale * R`` with R drawn from the auxiliary stream.
+
+    ``stream`` selects an independent child of the auxiliary stream so that
+    several perturbed sets (e.g. alpha and beta) can be drawn from one seed.
+    With ``complex_noise`` R = (R1 + i R2) / sqrt(2), else R real.
+    """
+    _, _, aux_ss = _streams(seed)
+    child = aux_ss.spawn(stream + 1)[stream]
+    rng = np.random.default_rng(child)
+    N, n = phiT.shape
+    if complex_noise:
+        r = (rng.standard_normal((W, N, n)) + 1j * rng.standard_normal((W, N, n))) / np.sqrt(2.0)
+    else:
+        r = rng.standard_normal((W, N, n)).astype(np.complex128)
+    return phiT[None, :, :] + scale * r
