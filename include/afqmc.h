@@ -1,0 +1,154 @@
+/*
+ * afqmc.h -- C ABI of the MI355X phaseless-AFQMC walker-step library.
+ *
+ * Method: phaseless auxiliary-field quantum Monte Carlo as described in
+ * arXiv 2209.04015 (ipie), Sec. II.B (propagator, importance sampling,
+ * phaseless weights) and Sec. III (overlap, Green's function, force bias,
+ * local energy) for a single-determinant trial.
+ *
+ * Conventions used by every call
+ *   N        number of spatial orbitals (the paper's M)
+ *   na, nb   electrons of spin alpha / beta (the paper's N splits into these)
+ *   K        number of Cholesky vectors (the paper's N_aux)
+ *   nw       number of walkers in a call, 0 <= nw <= max_walkers
+ *   complex  numbers are interleaved (re, im) pairs of double ("double2")
+ *   arrays   are dense, row-major, with the shapes given in brackets
+ *
+ * Memory: arguments named host_* are host pointers.  Every other array
+ * argument is a DEVICE pointer on the device that was current when the
+ * Hamiltonian was created, and must be 16-byte aligned (any torch
+ * allocation is).  The library never frees caller memory and never writes
+ * arrays passed as const.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = null stream).
+ * afqmc_init_hamiltonian may allocate and synchronise.  All other calls
+ * except afqmc_get_status are asynchronous on `stream`, do not allocate and
+ * do not synchronise.  One Hamiltonian handle serves one stream at a time:
+ * its workspace is shared by all calls on it.
+ *
+ * Errors: every call returns 0 (AFQMC_OK) or an AFQMC_E* code; the text of
+ * the last error of the calling thread is available from afqmc_last_error().
+ * Numerical events inside kernels (singular overlap, non-finite values) do
+ * not fail a call: they set bits of a device status word (afqmc_get_status)
+ * and the affected walker gets log weight -inf, which is how the method
+ * discards a walker (Eq. ph: max(0, cos theta) = 0).
+ */
+#ifndef AFQMC_H
+#define AFQMC_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  AFQMC_OK = 0,
+  AFQMC_EINVAL = 1,        /* bad argument or shape */
+  AFQMC_ENOMEM = 2,        /* device allocation failed (init only) */
+  AFQMC_EHIP = 3,          /* a HIP runtime call failed */
+  AFQMC_EUNSUPPORTED = 4   /* shape outside what the kernels support */
+};
+
+/* Working precision of the contractions (force bias, VHS, Taylor products,
+ * exchange).  Overlaps, determinants, inverses, weights, QR, the one-body
+ * half steps and all energy sums are FP64 in both modes. */
+enum { AFQMC_FP64 = 0, AFQMC_FP32 = 1 };
+
+/* Status-word bits (afqmc_get_status). */
+enum {
+  AFQMC_STATUS_SINGULAR = 1,   /* a walker's overlap matrix PhiT^T phi was singular */
+  AFQMC_STATUS_NONFINITE = 2,  /* a NaN appeared in an overlap or a weight */
+  AFQMC_STATUS_QR_ZERO = 4     /* a walker orbital vanished in re-orthogonalisation */
+};
+
+typedef struct afqmc_params {
+  int N, na, nb, K;     /* sizes; 1 <= na <= 45, 0 <= nb <= 45, na, nb <= N */
+  double dt;            /* imaginary time step (Eq. Bx) */
+  int taylor_order;     /* terms of the exp(VHS) series beyond 1 (default 6) */
+  int precision;        /* AFQMC_FP64 or AFQMC_FP32 */
+  int max_walkers;      /* workspace is sized for this many walkers */
+  double mu;            /* scalar factored out of the one-body half step; NaN -> tr(h')/N */
+  double e_shift;       /* energy shift E_T of the weights; NaN -> E_L(PhiT) computed in FP64 */
+} afqmc_params;
+
+/* Walker ensemble (Eq. stat_wfs), caller-owned device arrays. */
+typedef struct afqmc_walkers {
+  void* phi_a;      /* complex [nw][N][na]: orbitals of spin alpha        */
+  void* phi_b;      /* complex [nw][N][nb]: orbitals of spin beta         */
+  void* log_ovlp;   /* complex [nw]: log <Psi_T|phi_z> (log|.| + i arg)   */
+  double* log_w;    /* [nw]: log of the walker weight w_z; -inf = discarded */
+} afqmc_walkers;
+
+typedef struct afqmc_ham afqmc_ham;
+
+/* Build the step-independent data (run once).
+ *   host_h1     [N][N]      one-body integrals h_pq (Eq. Habinitio), real symmetric
+ *   host_chol   [K][N][N]   Cholesky vectors L^g_pr, (pr|qs) = sum_g L^g_pr L^g_qs,
+ *                           each real symmetric
+ *   host_phiT_a [N][na]     trial orbitals of spin alpha (real, Sec. III, N_det = 1)
+ *   host_phiT_b [N][nb]     trial orbitals of spin beta (may equal host_phiT_a)
+ * Computes h' = h1 - 1/2 sum_g L_g L_g, mu, P = exp(-dt (h' - mu) / 2),
+ * the half-rotated vectors Lh^s_g = PhiT_s^T L_g (Sec. III.B), PhiT_s^T h1,
+ * the packed L used by the VHS build, and E_T.  Allocates the workspace.
+ * On success *out owns device memory until afqmc_destroy. */
+int afqmc_init_hamiltonian(const afqmc_params* params, const double* host_h1,
+                           const double* host_chol, const double* host_phiT_a,
+                           const double* host_phiT_b, void* stream, afqmc_ham** out);
+
+/* log_ovlp[z] = sum_s log det(PhiT_s^T phi_s)  (Sec. III.A, SD overlap). */
+int afqmc_overlap(afqmc_ham* ham, const afqmc_walkers* w, int nw, void* stream);
+
+/* vbias[z][g] = sum_pq G^z_pq L^g_pq = sum_s tr(Lh^s_g theta^s_z)  (Eqs. fb, rfb).
+ *   vbias  complex [nw][K], written. */
+int afqmc_force_bias(afqmc_ham* ham, const afqmc_walkers* w, int nw, void* vbias, void* stream);
+
+/* One importance-sampled phaseless step (Sec. II.B) for every walker:
+ *   xbar = -i sqrt(dt) vbias, VHS = i sqrt(dt) sum_g (x_g - xbar_g) L_g,
+ *   phi' = P T(VHS) P phi with T the truncated Taylor series of exp,
+ *   ln O_z = log<Psi_T|phi'> - log<Psi_T|phi>  (Eq. ovl, e^{-dt mu/2} factors removed),
+ *   log w += Re ln O_z + Re(x.xbar - xbar.xbar/2) - dt (mu (na+nb) - E_T)
+ *            + ln max(0, cos Im ln O_z)  (Eqs. import, ph, theta).
+ *   fields  [nw][K] auxiliary fields x ~ N(0,1), read.
+ * phi_a, phi_b, log_ovlp and log_w are updated in place. */
+int afqmc_propagate(afqmc_ham* ham, afqmc_walkers* w, int nw, const double* fields,
+                    void* stream);
+
+/* Local energy split (Sec. III.C):
+ *   e[z][0] = E1 = sum_pq h_pq G_pq,  e[z][1] = EJ = 1/2 sum_g vbias_g^2,
+ *   e[z][2] = EK = -1/2 sum_s sum_g sum_ij T_ij T_ji,  T^s_g = Lh^s_g theta^s.
+ *   e  complex [nw][3], written.  E_L = e0 + e1 + e2 (complex). */
+int afqmc_local_energy(afqmc_ham* ham, const afqmc_walkers* w, int nw, void* e, void* stream);
+
+/* Re-orthogonalise every walker and spin: phi = Q R (Householder),
+ * phi <- Q diag(R_ii/|R_ii|), log_ovlp -= sum ln |R_ii|.  E_L and theta are
+ * unchanged by this, up to rounding. */
+int afqmc_orthogonalise(afqmc_ham* ham, afqmc_walkers* w, int nw, void* stream);
+
+/* One full step: afqmc_propagate, then afqmc_orthogonalise if do_qr, then
+ * (if e != NULL) afqmc_local_energy of the new walkers into e [nw][3].
+ * The Green's function and force bias of the new walkers are kept in the
+ * workspace; with flags & AFQMC_STEP_REUSE the next afqmc_step on the same
+ * walker arrays and nw starts from them instead of recomputing them.  Only
+ * pass AFQMC_STEP_REUSE if the walkers were not changed in between by
+ * anything but afqmc_step on this handle.
+ * When do_qr is set the overlap and Green's function are taken on the
+ * re-orthogonalised walker, and ln O_z adds back sum ln |R_ii|. */
+enum { AFQMC_STEP_REUSE = 1 };
+int afqmc_step(afqmc_ham* ham, afqmc_walkers* w, int nw, const double* fields, int do_qr,
+               void* e, int flags, void* stream);
+
+/* Synchronise `stream`, return the accumulated status bits in *out and clear them. */
+int afqmc_get_status(afqmc_ham* ham, void* stream, int* out);
+
+/* Setup results for inspection: host_P [N][N] (may be NULL), *mu, *e_shift
+ * (either may be NULL).  Synchronises the device. */
+int afqmc_get_setup(afqmc_ham* ham, double* host_P, double* mu, double* e_shift);
+
+void afqmc_destroy(afqmc_ham* ham);
+const char* afqmc_last_error(void);
+int afqmc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AFQMC_H */

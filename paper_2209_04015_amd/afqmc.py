@@ -1,0 +1,296 @@
+"""ctypes binding of the C ABI in ``include/afqmc.h`` (argument marshalling only).
+
+Device arrays are torch tensors on the GPU (PyTorch is used for device memory
+and streams only); every step of the method runs in the HIP library
+``_lib/libafqmc.so``.  If that library is missing, :func:`load` raises: there
+is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional
+
+import numpy as np
+
+__all__ = ["FP64", "FP32", "AfqmcError", "load", "Hamiltonian", "Walkers", "LIB_PATH"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libafqmc.so")
+
+FP64 = 0
+FP32 = 1
+STEP_REUSE = 1
+_PRECISIONS = {"fp64": FP64, "fp32": FP32, FP64: FP64, FP32: FP32}
+
+EXPORTED = (
+    "afqmc_init_hamiltonian",
+    "afqmc_overlap",
+    "afqmc_force_bias",
+    "afqmc_propagate",
+    "afqmc_local_energy",
+    "afqmc_orthogonalise",
+    "afqmc_step",
+    "afqmc_get_status",
+    "afqmc_get_setup",
+    "afqmc_destroy",
+    "afqmc_last_error",
+    "afqmc_version",
+)
+
+
+class AfqmcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"afqmc error {code}: {msg}")
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int),
+        ("na", ctypes.c_int),
+        ("nb", ctypes.c_int),
+        ("K", ctypes.c_int),
+        ("dt", ctypes.c_double),
+        ("taylor_order", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("max_walkers", ctypes.c_int),
+        ("mu", ctypes.c_double),
+        ("e_shift", ctypes.c_double),
+    ]
+
+
+class _Walkers(ctypes.Structure):
+    _fields_ = [
+        ("phi_a", ctypes.c_void_p),
+        ("phi_b", ctypes.c_void_p),
+        ("log_ovlp", ctypes.c_void_p),
+        ("log_w", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is missing; build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
+    P = ctypes.POINTER
+    lib.afqmc_init_hamiltonian.argtypes = [P(_Params), vp, vp, vp, vp, vp, P(vp)]
+    lib.afqmc_overlap.argtypes = [vp, P(_Walkers), ip, vp]
+    lib.afqmc_force_bias.argtypes = [vp, P(_Walkers), ip, vp, vp]
+    lib.afqmc_propagate.argtypes = [vp, P(_Walkers), ip, vp, vp]
+    lib.afqmc_local_energy.argtypes = [vp, P(_Walkers), ip, vp, vp]
+    lib.afqmc_orthogonalise.argtypes = [vp, P(_Walkers), ip, vp]
+    lib.afqmc_step.argtypes = [vp, P(_Walkers), ip, vp, ip, vp, ip, vp]
+    lib.afqmc_get_status.argtypes = [vp, vp, P(ip)]
+    lib.afqmc_get_setup.argtypes = [vp, vp, dp, dp]
+    lib.afqmc_destroy.argtypes = [vp]
+    lib.afqmc_destroy.restype = None
+    lib.afqmc_last_error.argtypes = []
+    lib.afqmc_last_error.restype = ctypes.c_char_p
+    lib.afqmc_version.argtypes = []
+    for name in EXPORTED:
+        f = getattr(lib, name)
+        if name not in ("afqmc_destroy", "afqmc_last_error"):
+            f.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise AfqmcError(rc, _lib.afqmc_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _host(a, shape, name):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != shape:
+        raise ValueError(f"{name} has shape {a.shape}, expected {shape}")
+    return a
+
+
+def _dev(t, dtype, shape, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Walkers:
+    """Walker ensemble on the device: phi_a [W,N,na], phi_b [W,N,nb] complex128,
+    log_ovlp [W] complex128, log_w [W] float64 (torch tensors)."""
+
+    def __init__(self, phi_a, phi_b, log_ovlp=None, log_w=None):
+        import torch
+
+        self.phi_a = phi_a
+        self.phi_b = phi_b
+        W = phi_a.shape[0]
+        dev = phi_a.device
+        self.log_ovlp = log_ovlp if log_ovlp is not None else torch.zeros(W, dtype=torch.complex128, device=dev)
+        self.log_w = log_w if log_w is not None else torch.zeros(W, dtype=torch.float64, device=dev)
+
+    @property
+    def W(self):
+        return self.phi_a.shape[0]
+
+    @classmethod
+    def from_numpy(cls, phi_a, phi_b, log_ovlp=None, log_w=None, device="cuda"):
+        import torch
+
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=device)
+        return cls(
+            t(phi_a, torch.complex128),
+            t(phi_b, torch.complex128),
+            None if log_ovlp is None else t(log_ovlp, torch.complex128),
+            None if log_w is None else t(log_w, torch.float64),
+        )
+
+    def _struct(self, ham, nw):
+        import torch
+
+        N, na, nb = ham.N, ham.na, ham.nb
+        s = _Walkers()
+        s.phi_a = _dev(self.phi_a, torch.complex128, (self.W, N, na), "phi_a").value
+        s.phi_b = _dev(self.phi_b, torch.complex128, (self.W, N, nb), "phi_b").value
+        s.log_ovlp = _dev(self.log_ovlp, torch.complex128, (self.W,), "log_ovlp").value
+        s.log_w = _dev(self.log_w, torch.float64, (self.W,), "log_w").value
+        if nw > self.W:
+            raise ValueError(f"nw = {nw} exceeds the {self.W} walkers held")
+        return s
+
+
+class Hamiltonian:
+    """A Hamiltonian handle (afqmc_init_hamiltonian) and its workspace."""
+
+    def __init__(self, h1, chol, phiT_a, phiT_b=None, *, dt, max_walkers, taylor_order=6,
+                 precision="fp64", mu=None, e_shift=None, stream=None):
+        lib = load()
+        h1 = np.asarray(h1)
+        N = h1.shape[0]
+        chol = np.asarray(chol)
+        K = chol.shape[0]
+        phiT_a = np.asarray(phiT_a)
+        na = phiT_a.shape[1]
+        phiT_b = phiT_a if phiT_b is None else np.asarray(phiT_b)
+        nb = phiT_b.shape[1]
+        self._h1 = _host(h1, (N, N), "h1")
+        self._chol = _host(chol, (K, N, N), "chol")
+        self._pa = _host(phiT_a, (N, na), "phiT_a")
+        self._pb = _host(phiT_b, (N, nb), "phiT_b")
+        self.N, self.na, self.nb, self.K = N, na, nb, K
+        self.precision = _PRECISIONS[precision]
+        self.max_walkers = int(max_walkers)
+        p = _Params(N, na, nb, K, float(dt), int(taylor_order), self.precision, self.max_walkers,
+                    math.nan if mu is None else float(mu), math.nan if e_shift is None else float(e_shift))
+        h = ctypes.c_void_p()
+        _check(lib.afqmc_init_hamiltonian(
+            ctypes.byref(p), self._h1.ctypes.data, self._chol.ctypes.data, self._pa.ctypes.data,
+            self._pb.ctypes.data, _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        # host copies are not needed after init
+        self._chol = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.afqmc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _nw(self, w, nw):
+        return w.W if nw is None else int(nw)
+
+    def overlap(self, w: Walkers, nw=None, stream=None):
+        nw = self._nw(w, nw)
+        s = w._struct(self, nw)
+        _check(_lib.afqmc_overlap(self._h, ctypes.byref(s), nw, _stream_ptr(stream)))
+
+    def force_bias(self, w: Walkers, out=None, nw=None, stream=None):
+        import torch
+
+        nw = self._nw(w, nw)
+        if out is None:
+            out = torch.empty((nw, self.K), dtype=torch.complex128, device=w.phi_a.device)
+        ptr = _dev(out, torch.complex128, (nw, self.K), "vbias")
+        s = w._struct(self, nw)
+        _check(_lib.afqmc_force_bias(self._h, ctypes.byref(s), nw, ptr, _stream_ptr(stream)))
+        return out
+
+    def propagate(self, w: Walkers, fields, nw=None, stream=None):
+        import torch
+
+        nw = self._nw(w, nw)
+        fp = _dev(fields, torch.float64, (nw, self.K), "fields")
+        s = w._struct(self, nw)
+        _check(_lib.afqmc_propagate(self._h, ctypes.byref(s), nw, fp, _stream_ptr(stream)))
+
+    def local_energy(self, w: Walkers, out=None, nw=None, stream=None):
+        import torch
+
+        nw = self._nw(w, nw)
+        if out is None:
+            out = torch.empty((nw, 3), dtype=torch.complex128, device=w.phi_a.device)
+        ptr = _dev(out, torch.complex128, (nw, 3), "energy")
+        s = w._struct(self, nw)
+        _check(_lib.afqmc_local_energy(self._h, ctypes.byref(s), nw, ptr, _stream_ptr(stream)))
+        return out
+
+    def orthogonalise(self, w: Walkers, nw=None, stream=None):
+        nw = self._nw(w, nw)
+        s = w._struct(self, nw)
+        _check(_lib.afqmc_orthogonalise(self._h, ctypes.byref(s), nw, _stream_ptr(stream)))
+
+    def step(self, w: Walkers, fields, do_qr=False, energy_out=None, reuse=False, nw=None,
+             stream=None):
+        import torch
+
+        nw = self._nw(w, nw)
+        fp = _dev(fields, torch.float64, (nw, self.K), "fields")
+        eptr = None
+        if energy_out is not None:
+            eptr = _dev(energy_out, torch.complex128, (nw, 3), "energy")
+        s = w._struct(self, nw)
+        _check(_lib.afqmc_step(self._h, ctypes.byref(s), nw, fp, int(bool(do_qr)), eptr,
+                               STEP_REUSE if reuse else 0, _stream_ptr(stream)))
+        return energy_out
+
+    def status(self, stream=None) -> int:
+        v = ctypes.c_int()
+        _check(_lib.afqmc_get_status(self._h, _stream_ptr(stream), ctypes.byref(v)))
+        return v.value
+
+    def setup(self):
+        """(P [N,N], mu, e_shift) as computed at init."""
+        P = np.zeros((self.N, self.N))
+        mu = ctypes.c_double()
+        es = ctypes.c_double()
+        _check(_lib.afqmc_get_setup(self._h, P.ctypes.data_as(ctypes.c_void_p), ctypes.byref(mu), ctypes.byref(es)))
+        return P, mu.value, es.value

@@ -1,0 +1,579 @@
+// C ABI of the walker-step library: argument checking, workspace ownership
+// and the kernel sequence of each call.  No arithmetic of the method runs on
+// the host; every step is a kernel from step_kernels.hip / setup_kernels.hip.
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/afqmc.h"
+#include "common.h"
+#include "kernels.h"
+#include "setup.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(AFQMC_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),   \
+                  __FILE__, __LINE__);                                                 \
+  } while (0)
+
+}  // namespace
+
+struct afqmc_ham {
+  afqmc_params prm{};
+  StepDims d{};
+  int device = 0;
+  int prec = AFQMC_FP64;
+  double mu = 0.0, e_shift = 0.0, cst = 0.0, sdt = 0.0;
+  size_t tsize = 8;  // bytes of the working precision
+  // Hamiltonian data
+  double* P = nullptr;      // [N][ldP]
+  void* Lh = nullptr;       // T [2][K][nmax][ldN]
+  void* LT = nullptr;       // T [Npk][ldK]
+  int2* pq = nullptr;       // [Npk]
+  double* phiT = nullptr;   // [2][N][nmax]
+  double* hh = nullptr;     // [2][nmax][N]
+  // workspace (sized for max_walkers)
+  void* theta = nullptr;    // T [W][2][2][nmax][ldN]
+  double2* logdet = nullptr;  // [W][2]
+  double2* e1 = nullptr;      // [W][2]
+  double2* vbias = nullptr;   // [W][K]
+  void* xs = nullptr;         // T [W][2][ldK]
+  double2* a = nullptr;       // [W]
+  void* vhs = nullptr;        // T [W][N][ldV]
+  double* acc = nullptr;      // [W][N][ncolp]
+  void* t0 = nullptr;         // T [W][N][ncolp]
+  void* t1 = nullptr;
+  unsigned* tmax = nullptr;   // [W]
+  double2* part = nullptr;    // [2][ntg][W]
+  double* corr = nullptr;     // [W][2]
+  int* status = nullptr;
+  int ntg = 0;
+  std::vector<void*> allocs;
+  // afqmc_step cache
+  const void* c_phi_a = nullptr;
+  const void* c_phi_b = nullptr;
+  int c_nw = -1;
+  bool c_valid = false;
+};
+
+namespace {
+
+int dalloc(afqmc_ham* h, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) return fail(AFQMC_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  h->allocs.push_back(*p);
+  e = hipMemset(*p, 0, bytes);
+  if (e != hipSuccess) return fail(AFQMC_EHIP, "hipMemset failed: %s", hipGetErrorString(e));
+  return AFQMC_OK;
+}
+
+template <typename T>
+int dalloc_t(afqmc_ham* h, T** p, size_t count) {
+  return dalloc(h, reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+void free_all(afqmc_ham* h) {
+  for (void* p : h->allocs) (void)hipFree(p);
+  h->allocs.clear();
+}
+
+int check_walkers(const afqmc_ham* h, const afqmc_walkers* w, int nw) {
+  if (!h) return fail(AFQMC_EINVAL, "null Hamiltonian handle");
+  if (nw < 0 || nw > h->prm.max_walkers)
+    return fail(AFQMC_EINVAL, "nw = %d outside [0, max_walkers = %d]", nw, h->prm.max_walkers);
+  if (nw == 0) return AFQMC_OK;
+  if (!w) return fail(AFQMC_EINVAL, "null walkers");
+  if (!w->phi_a || (h->d.nb > 0 && !w->phi_b) || !w->log_ovlp || !w->log_w)
+    return fail(AFQMC_EINVAL, "null walker array");
+  return AFQMC_OK;
+}
+
+int set_device(const afqmc_ham* h) {
+  HIP_TRY(hipSetDevice(h->device));
+  return AFQMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// step sequences, per working precision
+// ---------------------------------------------------------------------------
+
+template <typename T>
+int seq_theta(afqmc_ham* h, const afqmc_walkers* w, int nw, bool want_e1, hipStream_t s) {
+  HIP_TRY((launch_gf<T>(h->d, nw, (const double2*)w->phi_a, (const double2*)w->phi_b, h->phiT, h->hh,
+                        (T*)h->theta, h->logdet, want_e1 ? h->e1 : nullptr, h->status, s)));
+  return AFQMC_OK;
+}
+
+template <typename T>
+int seq_force_bias(afqmc_ham* h, int nw, double2* vbias, hipStream_t s) {
+  HIP_TRY((launch_force_bias<T>(h->d, nw, (const T*)h->Lh, (const T*)h->theta, vbias, s)));
+  return AFQMC_OK;
+}
+
+template <typename T>
+int seq_energy_from_theta(afqmc_ham* h, int nw, double2* e_out, hipStream_t s) {
+  int ntg = 0;
+  HIP_TRY((launch_exchange<T>(h->d, nw, (const T*)h->Lh, (const T*)h->theta, h->part, &ntg, s)));
+  HIP_TRY(launch_energy(h->d, nw, h->e1, h->vbias, h->part, ntg, e_out, s));
+  return AFQMC_OK;
+}
+
+// phi' = P T(VHS) P phi with vbias (of phi) already in h->vbias.
+template <typename T>
+int seq_propagate_core(afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields, hipStream_t s) {
+  const StepDims& d = h->d;
+  HIP_TRY((launch_shift<T>(d, nw, h->vbias, fields, (T*)h->xs, h->a, h->tmax, h->sdt, s)));
+  HIP_TRY((launch_vhs<T>(d, nw, (const T*)h->xs, (const T*)h->LT, h->pq, (T*)h->vhs, h->sdt, s)));
+  HIP_TRY(launch_pphi(d, nw, h->P, (const double2*)w->phi_a, (const double2*)w->phi_b, h->acc,
+                      nullptr, nullptr, h->tmax, 0, s));
+  const int order = h->prm.taylor_order;
+  T* bufs[2] = {(T*)h->t0, (T*)h->t1};
+  for (int k = 1; k <= order; ++k) {
+    const T* tin = k == 1 ? nullptr : bufs[(k - 2) & 1];
+    T* tout = bufs[(k - 1) & 1];
+    HIP_TRY((launch_taylor<T>(d, nw, (const T*)h->vhs, tin, tout, h->acc, h->tmax, k, order, s)));
+  }
+  HIP_TRY(launch_pphi(d, nw, h->P, nullptr, nullptr, h->acc, (double2*)w->phi_a, (double2*)w->phi_b,
+                      nullptr, 1, s));
+  return AFQMC_OK;
+}
+
+template <typename T>
+int seq_propagate(afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields, hipStream_t s) {
+  int rc;
+  if ((rc = seq_theta<T>(h, w, nw, false, s))) return rc;
+  if ((rc = seq_force_bias<T>(h, nw, h->vbias, s))) return rc;
+  if ((rc = seq_propagate_core<T>(h, w, nw, fields, s))) return rc;
+  if ((rc = seq_theta<T>(h, w, nw, false, s))) return rc;
+  HIP_TRY(launch_weight(nw, h->logdet, nullptr, h->a, (double2*)w->log_ovlp, w->log_w, h->cst,
+                        h->status, s));
+  h->c_valid = false;
+  return AFQMC_OK;
+}
+
+template <typename T>
+int seq_local_energy(afqmc_ham* h, const afqmc_walkers* w, int nw, double2* e, hipStream_t s) {
+  int rc;
+  if ((rc = seq_theta<T>(h, w, nw, true, s))) return rc;
+  if ((rc = seq_force_bias<T>(h, nw, h->vbias, s))) return rc;
+  if ((rc = seq_energy_from_theta<T>(h, nw, e, s))) return rc;
+  h->c_valid = false;
+  return AFQMC_OK;
+}
+
+template <typename T>
+int seq_step(afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields, int do_qr, double2* e,
+             int flags, hipStream_t s) {
+  int rc;
+  const bool reuse = (flags & AFQMC_STEP_REUSE) && h->c_valid && h->c_phi_a == w->phi_a &&
+                     h->c_phi_b == w->phi_b && h->c_nw == nw;
+  if (!reuse) {
+    if ((rc = seq_theta<T>(h, w, nw, false, s))) return rc;
+    if ((rc = seq_force_bias<T>(h, nw, h->vbias, s))) return rc;
+  }
+  if ((rc = seq_propagate_core<T>(h, w, nw, fields, s))) return rc;
+  if (do_qr) HIP_TRY(launch_qr(h->d, nw, (double2*)w->phi_a, (double2*)w->phi_b, h->corr, h->status, s));
+  if ((rc = seq_theta<T>(h, w, nw, e != nullptr, s))) return rc;
+  HIP_TRY(launch_weight(nw, h->logdet, do_qr ? h->corr : nullptr, h->a, (double2*)w->log_ovlp,
+                        w->log_w, h->cst, h->status, s));
+  if ((rc = seq_force_bias<T>(h, nw, h->vbias, s))) return rc;
+  if (e) {
+    if ((rc = seq_energy_from_theta<T>(h, nw, e, s))) return rc;
+  }
+  h->c_valid = true;
+  h->c_phi_a = w->phi_a;
+  h->c_phi_b = w->phi_b;
+  h->c_nw = nw;
+  return AFQMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+
+template <typename T>
+int build_working_arrays(afqmc_ham* h, const double* dL, const double* Y_a, const double* Y_b,
+                         hipStream_t s) {
+  const StepDims& d = h->d;
+  int rc;
+  if ((rc = dalloc(h, &h->Lh, (size_t)2 * d.K * d.nmax * d.ldN * sizeof(T)))) return rc;
+  HIP_TRY((setup_pack_lh<T>(d.K, d.N, d.na, d.nmax, d.ldN, Y_a, (T*)h->Lh, s)));
+  if (d.nb > 0)
+    HIP_TRY((setup_pack_lh<T>(d.K, d.N, d.nb, d.nmax, d.ldN, Y_b,
+                              (T*)h->Lh + (size_t)d.K * d.nmax * d.ldN, s)));
+  if ((rc = dalloc(h, &h->LT, (size_t)d.Npk * d.ldK * sizeof(T)))) return rc;
+  HIP_TRY((setup_pack_lt<T>(d.K, d.N, d.Npk, d.ldK, h->pq, dL, (T*)h->LT, s)));
+  return AFQMC_OK;
+}
+
+// E_T = E_L(PhiT), always evaluated with FP64 contractions.
+int trial_energy_fp64(afqmc_ham* h, const double* Y_a, const double* Y_b, hipStream_t s, double* et) {
+  const StepDims& d = h->d;
+  int rc;
+  void* Lh64 = h->Lh;
+  void* theta64 = h->theta;
+  double* tmp_lh = nullptr;
+  double* tmp_theta = nullptr;
+  if (h->prec != AFQMC_FP64) {
+    HIP_TRY(hipMalloc(&tmp_lh, (size_t)2 * d.K * d.nmax * d.ldN * sizeof(double)));
+    HIP_TRY(hipMemset(tmp_lh, 0, (size_t)2 * d.K * d.nmax * d.ldN * sizeof(double)));
+    HIP_TRY(hipMalloc(&tmp_theta, (size_t)4 * d.nmax * d.ldN * sizeof(double)));
+    HIP_TRY(hipMemset(tmp_theta, 0, (size_t)4 * d.nmax * d.ldN * sizeof(double)));
+    HIP_TRY((setup_pack_lh<double>(d.K, d.N, d.na, d.nmax, d.ldN, Y_a, tmp_lh, s)));
+    if (d.nb > 0)
+      HIP_TRY((setup_pack_lh<double>(d.K, d.N, d.nb, d.nmax, d.ldN, Y_b,
+                                     tmp_lh + (size_t)d.K * d.nmax * d.ldN, s)));
+    Lh64 = tmp_lh;
+    theta64 = tmp_theta;
+  }
+  double2 *wa = nullptr, *wb = nullptr, *e = nullptr;
+  HIP_TRY(hipMalloc(&wa, (size_t)d.N * d.nmax * sizeof(double2)));
+  HIP_TRY(hipMalloc(&wb, (size_t)d.N * d.nmax * sizeof(double2)));
+  HIP_TRY(hipMalloc(&e, 3 * sizeof(double2)));
+  HIP_TRY(setup_trial_walker(d.N, d.na, d.nmax, h->phiT, wa, s));
+  HIP_TRY(setup_trial_walker(d.N, d.nb, d.nmax, h->phiT + (size_t)d.N * d.nmax, wb, s));
+  HIP_TRY((launch_gf<double>(d, 1, wa, wb, h->phiT, h->hh, (double*)theta64, h->logdet, h->e1,
+                             h->status, s)));
+  HIP_TRY((launch_force_bias<double>(d, 1, (const double*)Lh64, (const double*)theta64, h->vbias, s)));
+  int ntg = 0;
+  HIP_TRY((launch_exchange<double>(d, 1, (const double*)Lh64, (const double*)theta64, h->part, &ntg, s)));
+  HIP_TRY(launch_energy(d, 1, h->e1, h->vbias, h->part, ntg, e, s));
+  double2 he[3];
+  HIP_TRY(hipMemcpyAsync(he, e, sizeof he, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *et = he[0].x + he[1].x + he[2].x;
+  (void)hipFree(wa);
+  (void)hipFree(wb);
+  (void)hipFree(e);
+  if (tmp_lh) (void)hipFree(tmp_lh);
+  if (tmp_theta) (void)hipFree(tmp_theta);
+  (void)rc;
+  return AFQMC_OK;
+}
+
+int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, const double* host_pa,
+              const double* host_pb, hipStream_t s) {
+  const afqmc_params& p = h->prm;
+  StepDims& d = h->d;
+  int rc;
+  HIP_TRY(hipGetDevice(&h->device));
+  d.N = p.N;
+  d.na = p.na;
+  d.nb = p.nb;
+  d.nmax = p.na > p.nb ? p.na : p.nb;
+  d.K = p.K;
+  d.ldN = round_up(p.N, 16);
+  d.ldK = round_up(p.K, 16);
+  d.ldV = round_up(2 * p.N, 16);
+  d.ldP = round_up(p.N, 16);
+  d.ncol = 2 * (p.na + p.nb);
+  d.ncolp = round_up(d.ncol, 4);
+  d.Npk = p.N * (p.N + 1) / 2;
+  h->prec = p.precision;
+  h->tsize = p.precision == AFQMC_FP32 ? sizeof(float) : sizeof(double);
+  h->sdt = sqrt(p.dt);
+  HIP_TRY(set_kernel_attributes(d));
+
+  const int N = d.N, K = d.K, nmax = d.nmax;
+  const size_t NN = (size_t)N * N;
+  // ---- inputs ----
+  double *dh1 = nullptr, *dL = nullptr;
+  HIP_TRY(hipMalloc(&dh1, NN * sizeof(double)));
+  HIP_TRY(hipMemcpy(dh1, host_h1, NN * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMalloc(&dL, (size_t)K * NN * sizeof(double)));
+  HIP_TRY(hipMemcpy(dL, host_chol, (size_t)K * NN * sizeof(double), hipMemcpyHostToDevice));
+  if ((rc = dalloc_t(h, &h->phiT, (size_t)2 * N * nmax))) return rc;
+  {
+    // index packing only: [N][ns] -> [2][N][nmax]
+    std::vector<double> pk((size_t)2 * N * nmax, 0.0);
+    for (int q = 0; q < N; ++q) {
+      for (int j = 0; j < d.na; ++j) pk[(size_t)q * nmax + j] = host_pa[(size_t)q * d.na + j];
+      for (int j = 0; j < d.nb; ++j) pk[(size_t)N * nmax + (size_t)q * nmax + j] = host_pb[(size_t)q * d.nb + j];
+    }
+    HIP_TRY(hipMemcpy(h->phiT, pk.data(), pk.size() * sizeof(double), hipMemcpyHostToDevice));
+    std::vector<int2> tab(d.Npk);
+    size_t c = 0;
+    for (int a = 0; a < N; ++a)
+      for (int b = a; b < N; ++b) tab[c++] = make_int2(a, b);
+    if ((rc = dalloc_t(h, &h->pq, (size_t)d.Npk))) return rc;
+    HIP_TRY(hipMemcpy(h->pq, tab.data(), tab.size() * sizeof(int2), hipMemcpyHostToDevice));
+  }
+
+  // ---- h' = h1 - 1/2 sum_g L_g L_g, mu ----
+  double *LL = nullptr, *hp = nullptr, *scal = nullptr, *scratch = nullptr;
+  HIP_TRY(hipMalloc(&LL, NN * sizeof(double)));
+  HIP_TRY(hipMalloc(&hp, NN * sizeof(double)));
+  HIP_TRY(hipMalloc(&scal, 4 * sizeof(double)));
+  const int nchunk = 64;
+  HIP_TRY(hipMalloc(&scratch, (size_t)nchunk * NN * sizeof(double)));
+  HIP_TRY(setup_gemm(N, N, K * N, 2, dL, N, dL, N, LL, N, scratch, nchunk, s));
+  HIP_TRY(setup_hprime(N, dh1, LL, hp, scal, s));
+  double tr = 0.0;
+  HIP_TRY(hipMemcpyAsync(&tr, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  h->mu = isnan(p.mu) ? tr / N : p.mu;
+
+  // ---- P = exp(-dt/2 (h' - mu)) ----
+  double *A = LL, *R = nullptr, *T = scratch;
+  HIP_TRY(setup_expm_arg(N, hp, h->mu, -0.5 * p.dt, A, scal + 1, s));
+  double nrm = 0.0;
+  HIP_TRY(hipMemcpyAsync(&nrm, scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  int sq = 0;
+  while (nrm > 0.5 && sq < 60) {
+    nrm *= 0.5;
+    ++sq;
+  }
+  HIP_TRY(hipMalloc(&R, NN * sizeof(double)));
+  HIP_TRY(setup_expm(N, A, sq, 18, R, T, s));
+  if ((rc = dalloc_t(h, &h->P, (size_t)N * d.ldP))) return rc;
+  HIP_TRY(setup_copy_pad(N, N, R, N, h->P, d.ldP, s));
+
+  // ---- half-rotated vectors: Y_s = [K N][N] x PhiT_s -> Lh ----
+  double *Y_a = nullptr, *Y_b = nullptr, *pa_dense = nullptr, *pb_dense = nullptr;
+  HIP_TRY(hipMalloc(&Y_a, (size_t)K * N * (d.na > 0 ? d.na : 1) * sizeof(double)));
+  HIP_TRY(hipMalloc(&Y_b, (size_t)K * N * (d.nb > 0 ? d.nb : 1) * sizeof(double)));
+  HIP_TRY(hipMalloc(&pa_dense, (size_t)N * (d.na > 0 ? d.na : 1) * sizeof(double)));
+  HIP_TRY(hipMalloc(&pb_dense, (size_t)N * (d.nb > 0 ? d.nb : 1) * sizeof(double)));
+  HIP_TRY(hipMemcpy(pa_dense, host_pa, (size_t)N * d.na * sizeof(double), hipMemcpyHostToDevice));
+  if (d.nb > 0) HIP_TRY(hipMemcpy(pb_dense, host_pb, (size_t)N * d.nb * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(setup_gemm(K * N, d.na, N, 0, dL, N, pa_dense, d.na, Y_a, d.na, nullptr, 1, s));
+  if (d.nb > 0) HIP_TRY(setup_gemm(K * N, d.nb, N, 0, dL, N, pb_dense, d.nb, Y_b, d.nb, nullptr, 1, s));
+  if ((rc = dalloc_t(h, &h->hh, (size_t)2 * nmax * N))) return rc;
+  HIP_TRY(setup_hh(N, d.na, nmax, h->phiT, dh1, h->hh, s));
+  HIP_TRY(setup_hh(N, d.nb, nmax, h->phiT + (size_t)N * nmax, dh1, h->hh + (size_t)nmax * N, s));
+  if (h->prec == AFQMC_FP32)
+    rc = build_working_arrays<float>(h, dL, Y_a, Y_b, s);
+  else
+    rc = build_working_arrays<double>(h, dL, Y_a, Y_b, s);
+  if (rc) return rc;
+
+  // ---- workspace ----
+  const size_t W = (size_t)p.max_walkers;
+  // the FP64 trial-energy pass may use the FP64 tile even in the mixed path
+  const ExTile t32 = exchange_tile<float>(nmax), t64 = exchange_tile<double>(nmax);
+  h->ntg = ceil_div(K, t32.G < t64.G ? t32.G : t64.G);
+  const size_t ts = h->tsize;
+  const size_t wtheta = (W > 1 ? W : 1);
+  if ((rc = dalloc(h, &h->theta, wtheta * 4 * nmax * d.ldN * ts))) return rc;
+  if ((rc = dalloc_t(h, &h->logdet, wtheta * 2))) return rc;
+  if ((rc = dalloc_t(h, &h->e1, wtheta * 2))) return rc;
+  if ((rc = dalloc_t(h, &h->vbias, wtheta * K))) return rc;
+  if ((rc = dalloc(h, &h->xs, W * 2 * d.ldK * ts))) return rc;
+  if ((rc = dalloc_t(h, &h->a, W))) return rc;
+  if ((rc = dalloc(h, &h->vhs, W * N * d.ldV * ts))) return rc;
+  if ((rc = dalloc_t(h, &h->acc, W * N * d.ncolp))) return rc;
+  if ((rc = dalloc(h, &h->t0, W * N * d.ncolp * ts))) return rc;
+  if ((rc = dalloc(h, &h->t1, W * N * d.ncolp * ts))) return rc;
+  if ((rc = dalloc_t(h, &h->tmax, W))) return rc;
+  if ((rc = dalloc_t(h, &h->part, (size_t)2 * h->ntg * wtheta))) return rc;
+  if ((rc = dalloc_t(h, &h->corr, W * 2))) return rc;
+  if ((rc = dalloc_t(h, &h->status, (size_t)1))) return rc;
+
+  // ---- E_T ----
+  if (isnan(p.e_shift)) {
+    double et = 0.0;
+    if ((rc = trial_energy_fp64(h, Y_a, Y_b, s, &et))) return rc;
+    h->e_shift = et;
+  } else {
+    h->e_shift = p.e_shift;
+  }
+  h->cst = -p.dt * (h->mu * (d.na + d.nb) - h->e_shift);
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemset(h->status, 0, sizeof(int)));
+  (void)hipFree(dh1);
+  (void)hipFree(dL);
+  (void)hipFree(LL);
+  (void)hipFree(hp);
+  (void)hipFree(scal);
+  (void)hipFree(scratch);
+  (void)hipFree(R);
+  (void)hipFree(Y_a);
+  (void)hipFree(Y_b);
+  (void)hipFree(pa_dense);
+  (void)hipFree(pb_dense);
+  return AFQMC_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// exported entry points
+// ===========================================================================
+
+extern "C" {
+
+int afqmc_version(void) { return 1; }
+
+const char* afqmc_last_error(void) { return g_last_error.c_str(); }
+
+int afqmc_init_hamiltonian(const afqmc_params* params, const double* host_h1,
+                           const double* host_chol, const double* host_phiT_a,
+                           const double* host_phiT_b, void* stream, afqmc_ham** out) {
+  if (!out) return fail(AFQMC_EINVAL, "null output handle pointer");
+  *out = nullptr;
+  if (!params || !host_h1 || !host_chol || !host_phiT_a)
+    return fail(AFQMC_EINVAL, "null input pointer");
+  const afqmc_params& p = *params;
+  if (p.N < 1 || p.K < 1 || p.na < 1 || p.nb < 0 || p.na > p.N || p.nb > p.N)
+    return fail(AFQMC_EINVAL, "bad sizes N=%d na=%d nb=%d K=%d", p.N, p.na, p.nb, p.K);
+  if (p.nb > 0 && !host_phiT_b) return fail(AFQMC_EINVAL, "null host_phiT_b with nb > 0");
+  if (p.na > 45 || p.nb > 45)
+    return fail(AFQMC_EUNSUPPORTED, "at most 45 electrons per spin are supported (got %d, %d)", p.na, p.nb);
+  if (!(p.dt > 0.0)) return fail(AFQMC_EINVAL, "dt must be positive");
+  if (p.taylor_order < 1 || p.taylor_order > 30) return fail(AFQMC_EINVAL, "taylor_order must be in [1, 30]");
+  if (p.precision != AFQMC_FP64 && p.precision != AFQMC_FP32)
+    return fail(AFQMC_EINVAL, "unknown precision %d", p.precision);
+  if (p.max_walkers < 1) return fail(AFQMC_EINVAL, "max_walkers must be >= 1");
+  const int nmax = p.na > p.nb ? p.na : p.nb;
+  if ((size_t)p.N * nmax * sizeof(double2) + 4096 > 160 * 1024)
+    return fail(AFQMC_EUNSUPPORTED, "N * max(na, nb) too large for the in-LDS QR (N=%d, n=%d)", p.N, nmax);
+  {
+    const ExTile t = p.precision == AFQMC_FP32 ? exchange_tile<float>(nmax) : exchange_tile<double>(nmax);
+    if (t.G < 1 || t.Z < 1) return fail(AFQMC_EUNSUPPORTED, "electron count %d too large for the exchange tile", nmax);
+  }
+  afqmc_ham* h = new afqmc_ham();
+  h->prm = p;
+  const int rc = init_impl(h, host_h1, host_chol, host_phiT_a, p.nb > 0 ? host_phiT_b : host_phiT_a,
+                           (hipStream_t)stream);
+  if (rc) {
+    free_all(h);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return AFQMC_OK;
+}
+
+int afqmc_overlap(afqmc_ham* h, const afqmc_walkers* w, int nw, void* stream) {
+  int rc = check_walkers(h, w, nw);
+  if (rc || nw == 0) return rc;
+  if ((rc = set_device(h))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY((launch_gf<double>(h->d, nw, (const double2*)w->phi_a, (const double2*)w->phi_b, h->phiT,
+                             h->hh, nullptr, h->logdet, nullptr, h->status, s)));
+  HIP_TRY(launch_overlap_store(nw, h->logdet, (double2*)w->log_ovlp, s));
+  return AFQMC_OK;
+}
+
+int afqmc_force_bias(afqmc_ham* h, const afqmc_walkers* w, int nw, void* vbias, void* stream) {
+  int rc = check_walkers(h, w, nw);
+  if (rc || nw == 0) return rc;
+  if (!vbias) return fail(AFQMC_EINVAL, "null vbias");
+  if ((rc = set_device(h))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (h->prec == AFQMC_FP32) {
+    if ((rc = seq_theta<float>(h, w, nw, false, s))) return rc;
+    rc = seq_force_bias<float>(h, nw, (double2*)vbias, s);
+  } else {
+    if ((rc = seq_theta<double>(h, w, nw, false, s))) return rc;
+    rc = seq_force_bias<double>(h, nw, (double2*)vbias, s);
+  }
+  h->c_valid = false;
+  return rc;
+}
+
+int afqmc_propagate(afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields, void* stream) {
+  int rc = check_walkers(h, w, nw);
+  if (rc || nw == 0) return rc;
+  if (!fields) return fail(AFQMC_EINVAL, "null fields");
+  if ((rc = set_device(h))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  return h->prec == AFQMC_FP32 ? seq_propagate<float>(h, w, nw, fields, s)
+                               : seq_propagate<double>(h, w, nw, fields, s);
+}
+
+int afqmc_local_energy(afqmc_ham* h, const afqmc_walkers* w, int nw, void* e, void* stream) {
+  int rc = check_walkers(h, w, nw);
+  if (rc || nw == 0) return rc;
+  if (!e) return fail(AFQMC_EINVAL, "null energy output");
+  if ((rc = set_device(h))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  return h->prec == AFQMC_FP32 ? seq_local_energy<float>(h, w, nw, (double2*)e, s)
+                               : seq_local_energy<double>(h, w, nw, (double2*)e, s);
+}
+
+int afqmc_orthogonalise(afqmc_ham* h, afqmc_walkers* w, int nw, void* stream) {
+  int rc = check_walkers(h, w, nw);
+  if (rc || nw == 0) return rc;
+  if ((rc = set_device(h))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_qr(h->d, nw, (double2*)w->phi_a, (double2*)w->phi_b, h->corr, h->status, s));
+  HIP_TRY(launch_ortho_update(nw, h->corr, (double2*)w->log_ovlp, s));
+  // theta is invariant under re-orthogonalisation; the cached force bias stays valid.
+  return AFQMC_OK;
+}
+
+int afqmc_step(afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields, int do_qr, void* e,
+               int flags, void* stream) {
+  int rc = check_walkers(h, w, nw);
+  if (rc || nw == 0) return rc;
+  if (!fields) return fail(AFQMC_EINVAL, "null fields");
+  if ((rc = set_device(h))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  return h->prec == AFQMC_FP32 ? seq_step<float>(h, w, nw, fields, do_qr, (double2*)e, flags, s)
+                               : seq_step<double>(h, w, nw, fields, do_qr, (double2*)e, flags, s);
+}
+
+int afqmc_get_status(afqmc_ham* h, void* stream, int* out) {
+  if (!h || !out) return fail(AFQMC_EINVAL, "null argument");
+  int rc;
+  if ((rc = set_device(h))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  int v = 0;
+  HIP_TRY(hipMemcpyAsync(&v, h->status, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int zero = 0;
+  HIP_TRY(hipMemcpyAsync(h->status, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = v;
+  return AFQMC_OK;
+}
+
+int afqmc_get_setup(afqmc_ham* h, double* host_P, double* mu, double* e_shift) {
+  if (!h) return fail(AFQMC_EINVAL, "null Hamiltonian handle");
+  int rc;
+  if ((rc = set_device(h))) return rc;
+  HIP_TRY(hipDeviceSynchronize());
+  if (host_P) {
+    std::vector<double> tmp((size_t)h->d.N * h->d.ldP);
+    HIP_TRY(hipMemcpy(tmp.data(), h->P, tmp.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int r = 0; r < h->d.N; ++r)
+      memcpy(host_P + (size_t)r * h->d.N, tmp.data() + (size_t)r * h->d.ldP, h->d.N * sizeof(double));
+  }
+  if (mu) *mu = h->mu;
+  if (e_shift) *e_shift = h->e_shift;
+  return AFQMC_OK;
+}
+
+void afqmc_destroy(afqmc_ham* h) {
+  if (!h) return;
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  free_all(h);
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Internal launchers of the walker-step kernels (host-callable).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+// Sizes shared by every kernel of one Hamiltonian.
+struct StepDims {
+  int N;      // spatial orbitals
+  int na, nb; // electrons per spin
+  int nmax;   // max(na, nb)
+  int K;      // Cholesky vectors
+  int ldN;    // padded orbital stride of theta / Lh rows (multiple of 16)
+  int ldK;    // padded Cholesky stride of xs / LT rows (multiple of 16)
+  int ldV;    // padded row stride (in real elements) of VHS rows, >= 2N, multiple of 16
+  int ldP;    // padded row stride of P (multiple of 16)
+  int ncol;   // 2 (na + nb): real columns of a walker's spin-concatenated orbitals
+  int ncolp;  // ncol rounded up to a multiple of 4
+  int Npk;    // N (N + 1) / 2 packed (p <= q) pairs
+};
+
+// Exchange tile choice: G Cholesky vectors x Z walkers per workgroup.
+struct ExTile {
+  int G, Z;
+};
+
+// --- Green's function / overlap --------------------------------------------
+// theta: working-precision planar [W][2 re/im][2 spin][nmax][ldN] (nullable)
+// logdet: [W][2] complex log det(PhiT^T phi) per spin; e1: [W][2] (nullable)
+template <typename T>
+hipError_t launch_gf(const StepDims& d, int W, const double2* phi_a, const double2* phi_b,
+                     const double* phiT, const double* hh, T* theta, double2* logdet,
+                     double2* e1, int* status, hipStream_t s);
+
+template <typename T>
+hipError_t launch_force_bias(const StepDims& d, int W, const T* Lh, const T* theta,
+                             double2* vbias, hipStream_t s);
+
+template <typename T>
+hipError_t launch_shift(const StepDims& d, int W, const double2* vbias, const double* x, T* xs,
+                        double2* a, unsigned* tmax, double sdt, hipStream_t s);
+
+template <typename T>
+hipError_t launch_vhs(const StepDims& d, int W, const T* xs, const T* LT, const int2* pq, T* vhs,
+                      double sdt, hipStream_t s);
+
+// out = P in, FP64.  mode 0: in = caller walkers, out -> acc (+ per-walker max |.| into tmax)
+//                     mode 1: in = acc, out -> caller walkers
+hipError_t launch_pphi(const StepDims& d, int W, const double* P, const double2* phi_a_in,
+                       const double2* phi_b_in, double* acc, double2* phi_a_out,
+                       double2* phi_b_out, unsigned* tmax, int mode, hipStream_t s);
+
+// t_out = VHS t_in / k; k == 1 reads t_in from acc (= P phi).  Launch k adds
+// term k-1 to acc, the last launch (k == order) also adds term k.
+template <typename T>
+hipError_t launch_taylor(const StepDims& d, int W, const T* vhs, const T* t_in, T* t_out,
+                         double* acc, const unsigned* tmax, int k, int order, hipStream_t s);
+
+hipError_t launch_weight(int W, const double2* logdet, const double* corr, const double2* a,
+                         double2* log_ovlp, double* log_w, double cst, int* status,
+                         hipStream_t s);
+
+hipError_t launch_overlap_store(int W, const double2* logdet, double2* log_ovlp, hipStream_t s);
+
+template <typename T>
+ExTile exchange_tile(int n);
+template <typename T>
+hipError_t launch_exchange(const StepDims& d, int W, const T* Lh, const T* theta, double2* part,
+                           int* ntg_out, hipStream_t s);
+
+hipError_t launch_energy(const StepDims& d, int W, const double2* e1, const double2* vbias,
+                         const double2* part, int ntg, double2* e_out, hipStream_t s);
+
+// Householder QR of every walker and spin; corr[W][2] = sum ln |R_ii|.
+hipError_t launch_qr(const StepDims& d, int W, double2* phi_a, double2* phi_b, double* corr,
+                     int* status, hipStream_t s);
+hipError_t launch_ortho_update(int W, const double* corr, double2* log_ovlp, hipStream_t s);
+
+hipError_t set_kernel_attributes(const StepDims& d);
+size_t qr_lds_bytes(const StepDims& d);

@@ -1,0 +1,987 @@
+// Kernels of one phaseless-AFQMC walker step (arXiv 2209.04015, Secs. II.B and III).
+//
+// Working precision T is double (FP64 path) or float (mixed path: the
+// contractions run on FP32 MFMA; overlaps, inverses, weights, QR, the
+// one-body half steps and every energy accumulation stay FP64).
+
+#include <math.h>
+
+#include "common.h"
+#include "kernels.h"
+#include "mfma_tile.h"
+
+template <typename T> struct Cplx;
+template <> struct Cplx<float> { using t = float2; };
+template <> struct Cplx<double> { using t = double2; };
+
+// ===========================================================================
+// Green's function: S = PhiT^T phi, log det S, theta = phi S^-1, E1 = tr(hh theta)
+// (Sec. III.A overlap; Eq. halfgf; one-body energy of Sec. III.C)
+//
+// One workgroup per (walker, spin).  S is built from 32-row chunks of phi
+// staged in LDS; the inverse comes from Gauss-Jordan elimination with
+// partial pivoting on [S | I] in LDS, which also yields log det S as the sum
+// of the complex logs of the pivots plus i pi per row swap.
+// ===========================================================================
+
+constexpr int GF_THREADS = 256;
+constexpr int GF_CHUNK = 32;
+constexpr int GF_SACC = 8;  // S entries per thread: n * n <= 8 * 256, n <= 45
+
+static size_t gf_lds_bytes(int n) {
+  return (size_t)n * 2 * n * sizeof(double2)       // [S | I]
+         + (size_t)GF_CHUNK * n * sizeof(double2)  // phi chunk
+         + (size_t)GF_CHUNK * n * sizeof(double)   // PhiT chunk
+         + (size_t)n * sizeof(double2)             // elimination factors
+         + 8 * sizeof(double2) + 16;               // reductions, pivot
+}
+
+template <typename T>
+__global__ __launch_bounds__(GF_THREADS) void gf_kernel(
+    StepDims d, const double2* __restrict__ phi_a, const double2* __restrict__ phi_b,
+    const double* __restrict__ phiT, const double* __restrict__ hh, T* __restrict__ theta,
+    double2* __restrict__ logdet, double2* __restrict__ e1, int* __restrict__ status) {
+  extern __shared__ double2 gf_lds[];
+  const int z = blockIdx.x;
+  const int sp = blockIdx.y;
+  const int n = sp == 0 ? d.na : d.nb;
+  const int N = d.N;
+  const int tid = threadIdx.x;
+  const int n2 = 2 * n;
+  double2* aug = gf_lds;                               // n x 2n
+  double2* ch = aug + n * n2;                          // CHUNK x n
+  double* tch = reinterpret_cast<double*>(ch + GF_CHUNK * n);  // CHUNK x n
+  double2* fac = reinterpret_cast<double2*>(tch + GF_CHUNK * n);
+  double2* red = fac + n;
+  int* sh_piv = reinterpret_cast<int*>(red + 8);
+
+  if (n == 0) {
+    if (tid == 0) {
+      logdet[2 * z + sp] = make_double2(0.0, 0.0);
+      if (e1) e1[2 * z + sp] = make_double2(0.0, 0.0);
+    }
+    return;
+  }
+  const double2* phi = (sp == 0 ? phi_a : phi_b) + (size_t)z * N * n;
+  const double* pT = phiT + (size_t)sp * N * d.nmax;
+
+  // ---- S = PhiT^T phi ----
+  double2 sacc[GF_SACC];
+#pragma unroll
+  for (int r = 0; r < GF_SACC; ++r) sacc[r] = make_double2(0.0, 0.0);
+  for (int p0 = 0; p0 < N; p0 += GF_CHUNK) {
+    const int rows = min(GF_CHUNK, N - p0);
+    __syncthreads();
+    for (int e = tid; e < rows * n; e += GF_THREADS) {
+      const int pr = e / n, j = e % n;
+      ch[e] = phi[(size_t)(p0 + pr) * n + j];
+      tch[e] = pT[(size_t)(p0 + pr) * d.nmax + j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < GF_SACC; ++r) {
+      const int e = tid + r * GF_THREADS;
+      if (e < n * n) {
+        const int i = e / n, j = e % n;
+        double2 s = sacc[r];
+        for (int pr = 0; pr < rows; ++pr) {
+          const double t = tch[pr * n + i];
+          const double2 f = ch[pr * n + j];
+          s.x += t * f.x;
+          s.y += t * f.y;
+        }
+        sacc[r] = s;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < GF_SACC; ++r) {
+    const int e = tid + r * GF_THREADS;
+    if (e < n * n) {
+      const int i = e / n, j = e % n;
+      aug[i * n2 + j] = sacc[r];
+      aug[i * n2 + n + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    }
+  }
+  __syncthreads();
+
+  // ---- Gauss-Jordan with partial pivoting ----
+  double2 ld = make_double2(0.0, 0.0);  // meaningful in thread 0
+  bool singular = false;
+  for (int k = 0; k < n; ++k) {
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = k;
+      for (int i = k + tid; i < n; i += 64) {
+        const double v = cabs2(aug[i * n2 + k]);
+        if (v > best) { best = v; bi = i; }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (tid == 0) *sh_piv = bi;
+    }
+    __syncthreads();
+    const int piv = *sh_piv;
+    if (piv != k) {
+      for (int c = tid; c < n2; c += GF_THREADS) {
+        const double2 t = aug[k * n2 + c];
+        aug[k * n2 + c] = aug[piv * n2 + c];
+        aug[piv * n2 + c] = t;
+      }
+      if (tid == 0) ld.y += M_PI;
+    }
+    __syncthreads();
+    double2 pv = aug[k * n2 + k];
+    if (cabs2(pv) == 0.0) {
+      singular = true;
+      pv = make_double2(1.0, 0.0);
+    }
+    if (tid == 0) ld = cadd(ld, clog(pv));
+    const double2 ipv = cinv(pv);
+    for (int i = tid; i < n; i += GF_THREADS) fac[i] = aug[i * n2 + k];
+    __syncthreads();
+    for (int c = tid; c < n2; c += GF_THREADS) aug[k * n2 + c] = cmul(aug[k * n2 + c], ipv);
+    __syncthreads();
+    for (int e = tid; e < n * n2; e += GF_THREADS) {
+      const int i = e / n2, c = e % n2;
+      if (i != k) aug[e] = csub(aug[e], cmul(fac[i], aug[k * n2 + c]));
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (singular) {
+      ld = make_double2(-INFINITY, 0.0);
+      atomicOr(status, AFQMC_STATUS_SINGULAR);
+    }
+    logdet[2 * z + sp] = ld;
+  }
+
+  // ---- theta = phi S^-1 and E1 = sum_{j,p} hh[j][p] theta[p][j] ----
+  const double* hs = hh + (size_t)sp * d.nmax * N;
+  double2 eacc = make_double2(0.0, 0.0);
+  const size_t plane = (size_t)d.nmax * d.ldN;
+  T* th_re = theta ? theta + ((size_t)(2 * z + 0) * 2 + sp) * plane : nullptr;
+  T* th_im = theta ? theta + ((size_t)(2 * z + 1) * 2 + sp) * plane : nullptr;
+  for (int p0 = 0; p0 < N; p0 += GF_CHUNK) {
+    const int rows = min(GF_CHUNK, N - p0);
+    __syncthreads();
+    for (int e = tid; e < rows * n; e += GF_THREADS) {
+      const int pr = e / n, j = e % n;
+      ch[e] = phi[(size_t)(p0 + pr) * n + j];
+    }
+    __syncthreads();
+    for (int e = tid; e < rows * n; e += GF_THREADS) {
+      const int j = e / rows, pr = e % rows;
+      double2 t = make_double2(0.0, 0.0);
+      if (!singular) {
+        for (int k = 0; k < n; ++k) t = cadd(t, cmul(ch[pr * n + k], aug[k * n2 + n + j]));
+      }
+      const int p = p0 + pr;
+      const double h = hs[(size_t)j * N + p];
+      eacc.x += h * t.x;
+      eacc.y += h * t.y;
+      if (theta) {
+        th_re[(size_t)j * d.ldN + p] = (T)t.x;
+        th_im[(size_t)j * d.ldN + p] = (T)t.y;
+      }
+    }
+  }
+  if (e1) {
+    const double2 s = block_sum2(eacc, red);
+    if (tid == 0) e1[2 * z + sp] = s;
+  }
+}
+
+template <typename T>
+hipError_t launch_gf(const StepDims& d, int W, const double2* phi_a, const double2* phi_b,
+                     const double* phiT, const double* hh, T* theta, double2* logdet,
+                     double2* e1, int* status, hipStream_t s) {
+  const size_t lds = gf_lds_bytes(d.nmax);
+  hipLaunchKernelGGL(gf_kernel<T>, dim3(W, 2), dim3(GF_THREADS), lds, s, d, phi_a, phi_b, phiT,
+                     hh, theta, logdet, e1, status);
+  return hipGetLastError();
+}
+template hipError_t launch_gf<float>(const StepDims&, int, const double2*, const double2*,
+                                     const double*, const double*, float*, double2*, double2*,
+                                     int*, hipStream_t);
+template hipError_t launch_gf<double>(const StepDims&, int, const double2*, const double2*,
+                                      const double*, const double*, double*, double2*, double2*,
+                                      int*, hipStream_t);
+
+// ===========================================================================
+// Force bias: vbias[z][g] = sum_s sum_{j,p} Lh^s[g][j][p] theta^s_z[p][j] (Eq. rfb)
+// A GEMM over all walkers at once with the real Lh as A (rows g) and the
+// planar real and imaginary parts of theta as B (rows (z, re|im)), so Lh is
+// never converted to complex.
+// ===========================================================================
+
+template <typename T>
+struct FbProb {
+  using vec_t = typename MF<T>::vec_t;
+  const T* Lh;
+  const T* theta;
+  int K, W;
+  int plane;  // nmax * ldN
+  __device__ vec_t load_a(int, int g, int k) const {
+    if (g >= K) return MF<T>::vzero();
+    const int s = k >= plane ? 1 : 0;
+    const int rest = k - s * plane;
+    return *reinterpret_cast<const vec_t*>(Lh + ((size_t)s * K + g) * plane + rest);
+  }
+  __device__ vec_t load_b(int, int col, int k) const {
+    if (col >= 2 * W) return MF<T>::vzero();
+    return *reinterpret_cast<const vec_t*>(theta + (size_t)col * 2 * plane + k);
+  }
+};
+
+template <typename T, int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(WM* WN * 64) void fb_kernel(FbProb<T> p, double2* __restrict__ vbias) {
+  __shared__ __attribute__((aligned(16))) T lds[TileLds<T, BM, BN, BK>::ELEMS];
+  typename MF<T>::acc_t acc[BM / WM / 16][BN / WN / 16];
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  mfma_tile_mainloop<T, BM, BN, BK, WM, WN, false>(p, 0, m0, n0, 2 * p.plane, acc, lds);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wm = wid / WN, wn = wid % WN;
+#pragma unroll
+  for (int i = 0; i < BM / WM / 16; ++i)
+#pragma unroll
+    for (int j = 0; j < BN / WN / 16; ++j) {
+      const int mb = m0 + wm * (BM / WM) + i * 16 + 4 * (lane >> 4);
+      const int col = n0 + wn * (BN / WN) + j * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double v = (double)acc[i][j][r];
+        const double o = __shfl_xor(v, 1, 64);
+        const int g = mb + r;
+        if ((col & 1) == 0 && g < p.K && (col >> 1) < p.W)
+          vbias[(size_t)(col >> 1) * p.K + g] = make_double2(v, o);
+      }
+    }
+}
+
+template <typename T>
+hipError_t launch_force_bias(const StepDims& d, int W, const T* Lh, const T* theta,
+                             double2* vbias, hipStream_t s) {
+  constexpr int BM = 64, BN = 64, BK = sizeof(T) == 4 ? 32 : 16, WM = 2, WN = 2;
+  FbProb<T> p{Lh, theta, d.K, W, d.nmax * d.ldN};
+  dim3 grid(ceil_div(d.K, BM), ceil_div(2 * W, BN));
+  hipLaunchKernelGGL((fb_kernel<T, BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p, vbias);
+  return hipGetLastError();
+}
+template hipError_t launch_force_bias<float>(const StepDims&, int, const float*, const float*,
+                                             double2*, hipStream_t);
+template hipError_t launch_force_bias<double>(const StepDims&, int, const double*, const double*,
+                                              double2*, hipStream_t);
+
+// ===========================================================================
+// Shift: xbar = -i sqrt(dt) vbias, xs = x - xbar, a_z = sum_g (x xbar - xbar^2/2)
+// (Eq. import and the optimal force bias of Sec. II.B)
+// ===========================================================================
+
+template <typename T>
+__global__ __launch_bounds__(256) void shift_kernel(int K, int ldK, const double2* __restrict__ vbias,
+                                                    const double* __restrict__ x, T* __restrict__ xs,
+                                                    double2* __restrict__ a, unsigned* __restrict__ tmax,
+                                                    double sdt) {
+  __shared__ double2 red[4];
+  const int z = blockIdx.x;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int g = threadIdx.x; g < K; g += 256) {
+    const double2 v = vbias[(size_t)z * K + g];
+    const double2 xb = make_double2(sdt * v.y, -sdt * v.x);
+    const double xv = x[(size_t)z * K + g];
+    xs[(size_t)(2 * z) * ldK + g] = (T)(xv - xb.x);
+    xs[(size_t)(2 * z + 1) * ldK + g] = (T)(-xb.y);
+    acc.x += xv * xb.x - 0.5 * (xb.x * xb.x - xb.y * xb.y);
+    acc.y += xv * xb.y - xb.x * xb.y;
+  }
+  const double2 s = block_sum2(acc, red);
+  if (threadIdx.x == 0) {
+    a[z] = s;
+    if (tmax) tmax[z] = 0u;
+  }
+}
+
+template <typename T>
+hipError_t launch_shift(const StepDims& d, int W, const double2* vbias, const double* x, T* xs,
+                        double2* a, unsigned* tmax, double sdt, hipStream_t s) {
+  hipLaunchKernelGGL(shift_kernel<T>, dim3(W), dim3(256), 0, s, d.K, d.ldK, vbias, x, xs, a, tmax,
+                     sdt);
+  return hipGetLastError();
+}
+template hipError_t launch_shift<float>(const StepDims&, int, const double2*, const double*,
+                                        float*, double2*, unsigned*, double, hipStream_t);
+template hipError_t launch_shift<double>(const StepDims&, int, const double2*, const double*,
+                                         double*, double2*, unsigned*, double, hipStream_t);
+
+// ===========================================================================
+// VHS build: VHS_z = i sqrt(dt) sum_g xs_zg L_g over the packed (p <= q)
+// triangle, mirrored on store (the symmetric L_g make VHS complex symmetric).
+// A = xs planar rows (z, re|im); B = packed L rows (p, q), K contiguous.
+// ===========================================================================
+
+template <typename T>
+struct VhsProb {
+  using vec_t = typename MF<T>::vec_t;
+  const T* xs;
+  const T* LT;
+  int W, Npk, ldK;
+  __device__ vec_t load_a(int, int m, int k) const {
+    if (m >= 2 * W) return MF<T>::vzero();
+    return *reinterpret_cast<const vec_t*>(xs + (size_t)m * ldK + k);
+  }
+  __device__ vec_t load_b(int, int n, int k) const {
+    if (n >= Npk) return MF<T>::vzero();
+    return *reinterpret_cast<const vec_t*>(LT + (size_t)n * ldK + k);
+  }
+};
+
+template <typename T, int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(WM* WN * 64) void vhs_kernel(VhsProb<T> p, const int2* __restrict__ pq,
+                                                          T* __restrict__ vhs, int N, int ldV,
+                                                          double sdt) {
+  using C2 = typename Cplx<T>::t;
+  __shared__ __attribute__((aligned(16))) T lds[TileLds<T, BM, BN, BK>::ELEMS];
+  typename MF<T>::acc_t acc[BM / WM / 16][BN / WN / 16];
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  mfma_tile_mainloop<T, BM, BN, BK, WM, WN, false>(p, 0, m0, n0, p.ldK, acc, lds);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wm = wid / WN, wn = wid % WN;
+#pragma unroll
+  for (int j = 0; j < BN / WN / 16; ++j) {
+    const int col = n0 + wn * (BN / WN) + j * 16 + (lane & 15);
+    if (col >= p.Npk) continue;
+    const int2 ij = pq[col];
+#pragma unroll
+    for (int i = 0; i < BM / WM / 16; ++i) {
+      const int mb = m0 + wm * (BM / WM) + i * 16 + 4 * (lane >> 4);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int z = (mb >> 1) + h;
+        if (z >= p.W) continue;
+        const double cr = (double)acc[i][j][2 * h], ci = (double)acc[i][j][2 * h + 1];
+        C2 v;
+        v.x = (T)(-sdt * ci);
+        v.y = (T)(sdt * cr);
+        *reinterpret_cast<C2*>(vhs + ((size_t)z * N + ij.x) * ldV + 2 * ij.y) = v;
+        if (ij.x != ij.y) *reinterpret_cast<C2*>(vhs + ((size_t)z * N + ij.y) * ldV + 2 * ij.x) = v;
+      }
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_vhs(const StepDims& d, int W, const T* xs, const T* LT, const int2* pq, T* vhs,
+                      double sdt, hipStream_t s) {
+  constexpr int BM = 64, BN = 64, BK = sizeof(T) == 4 ? 32 : 16, WM = 2, WN = 2;
+  VhsProb<T> p{xs, LT, W, d.Npk, d.ldK};
+  dim3 grid(ceil_div(2 * W, BM), ceil_div(d.Npk, BN));
+  hipLaunchKernelGGL((vhs_kernel<T, BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p, pq,
+                     vhs, d.N, d.ldV, sdt);
+  return hipGetLastError();
+}
+template hipError_t launch_vhs<float>(const StepDims&, int, const float*, const float*, const int2*,
+                                      float*, double, hipStream_t);
+template hipError_t launch_vhs<double>(const StepDims&, int, const double*, const double*,
+                                       const int2*, double*, double, hipStream_t);
+
+// ===========================================================================
+// One-body half step (R2 of the design: P = exp(-dt (h' - mu) / 2)), FP64:
+// out_z = P in_z for every walker, both spins side by side as real columns.
+// ===========================================================================
+
+struct PphiProb {
+  using vec_t = double2;
+  const double* P;
+  int N, ldP, ncolp, na, nb;
+  const double* in_a;  // mode 0
+  const double* in_b;
+  const double* acc;   // mode 1
+  int mode;
+  __device__ vec_t load_a(int, int r, int k) const {
+    if (r >= N) return make_double2(0.0, 0.0);
+    return *reinterpret_cast<const double2*>(P + (size_t)r * ldP + k);
+  }
+  __device__ vec_t load_b_km(int z, int q, int col) const {
+    if (q >= N || col >= ncolp) return make_double2(0.0, 0.0);
+    if (mode == 1) return *reinterpret_cast<const double2*>(acc + ((size_t)z * N + q) * ncolp + col);
+    if (col < 2 * na) return *reinterpret_cast<const double2*>(in_a + ((size_t)z * N + q) * 2 * na + col);
+    const int c = col - 2 * na;
+    if (c >= 2 * nb) return make_double2(0.0, 0.0);
+    return *reinterpret_cast<const double2*>(in_b + ((size_t)z * N + q) * 2 * nb + c);
+  }
+};
+
+template <int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(WM* WN * 64) void pphi_kernel(PphiProb p, double* __restrict__ acc_out,
+                                                           double2* __restrict__ out_a,
+                                                           double2* __restrict__ out_b,
+                                                           unsigned* __restrict__ tmax) {
+  __shared__ __attribute__((aligned(16))) double lds[TileLds<double, BM, BN, BK>::ELEMS];
+  doublex4 acc[BM / WM / 16][BN / WN / 16];
+  const int z = blockIdx.z;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  mfma_tile_mainloop<double, BM, BN, BK, WM, WN, true>(p, z, m0, n0, p.ldP, acc, lds);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wm = wid / WN, wn = wid % WN;
+  const int ncol = 2 * (p.na + p.nb);
+  float vmax = 0.f;
+#pragma unroll
+  for (int i = 0; i < BM / WM / 16; ++i)
+#pragma unroll
+    for (int j = 0; j < BN / WN / 16; ++j) {
+      const int mb = m0 + wm * (BM / WM) + i * 16 + 4 * (lane >> 4);
+      const int col = n0 + wn * (BN / WN) + j * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = mb + r;
+        if (row >= p.N || col >= ncol) continue;
+        const double v = acc[i][j][r];
+        if (p.mode == 0) {
+          acc_out[((size_t)z * p.N + row) * p.ncolp + col] = v;
+          vmax = fmaxf(vmax, (float)fabs(v));
+        } else {
+          double* dst;
+          if (col < 2 * p.na)
+            dst = reinterpret_cast<double*>(out_a) + ((size_t)z * p.N + row) * 2 * p.na + col;
+          else
+            dst = reinterpret_cast<double*>(out_b) + ((size_t)z * p.N + row) * 2 * p.nb + (col - 2 * p.na);
+          *dst = v;
+        }
+      }
+    }
+  if (p.mode == 0 && tmax) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o, 64));
+    if (lane == 0) atomicMax(tmax + z, __float_as_uint(vmax));
+  }
+}
+
+hipError_t launch_pphi(const StepDims& d, int W, const double* P, const double2* phi_a_in,
+                       const double2* phi_b_in, double* acc, double2* phi_a_out,
+                       double2* phi_b_out, unsigned* tmax, int mode, hipStream_t s) {
+  constexpr int BM = 64, BN = 64, BK = 16, WM = 2, WN = 2;
+  PphiProb p{P, d.N, d.ldP, d.ncolp, d.na, d.nb,
+             reinterpret_cast<const double*>(phi_a_in), reinterpret_cast<const double*>(phi_b_in),
+             acc, mode};
+  dim3 grid(ceil_div(d.N, BM), ceil_div(d.ncolp, BN), W);
+  hipLaunchKernelGGL((pphi_kernel<BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p, acc,
+                     phi_a_out, phi_b_out, tmax);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// Taylor term: t_k = VHS t_{k-1} / k, acc += t_k (R6: exp(VHS) truncated at k = 6).
+// Complex product as a real GEMM: A = VHS rows with interleaved (re, im)
+// along the contraction, B rows (q, re|im) built on the fly from t:
+//   row (q, re) = t[q][:]              (tr, ti pairs)
+//   row (q, im) = t[q][:] with each pair (tr, ti) -> (-ti, tr)
+// so that C[p][(j, re)] = sum Vr tr - Vi ti and C[p][(j, im)] = sum Vr ti + Vi tr.
+// In the mixed path t is FP32 with a per-walker power-of-two scale taken
+// from max |P phi| (exact; the FP64 accumulator holds unscaled values).
+// ===========================================================================
+
+template <typename T>
+__device__ __forceinline__ double taylor_scale_exp(const unsigned* tmax, int z) {
+  if constexpr (sizeof(T) == 8) {
+    return 0.0;
+  } else {
+    const float m = __uint_as_float(tmax[z]);
+    return (m > 0.f && isfinite(m)) ? (double)ilogbf(m) : 0.0;
+  }
+}
+
+template <typename T>
+struct TaylorProb {
+  using vec_t = typename MF<T>::vec_t;
+  const T* vhs;
+  int N, ldV, ncolp;
+  const double* acc;  // first term: FP64 source
+  const T* t_in;
+  const unsigned* tmax;
+  int first;
+  __device__ vec_t load_a(int z, int r, int k) const {
+    if (r >= N) return MF<T>::vzero();
+    return *reinterpret_cast<const vec_t*>(vhs + ((size_t)z * N + r) * ldV + k);
+  }
+  __device__ vec_t load_b_km(int z, int k, int col) const {
+    const int q = k >> 1, c = k & 1;
+    if (q >= N || col >= ncolp) return MF<T>::vzero();
+    vec_t v;
+    if (first) {
+      const double sc = ldexp(1.0, -(int)taylor_scale_exp<T>(tmax, z));
+      const double* src = acc + ((size_t)z * N + q) * ncolp + col;
+      if constexpr (MF<T>::VEC == 4) {
+        const double2 x0 = *reinterpret_cast<const double2*>(src);
+        const double2 x1 = *reinterpret_cast<const double2*>(src + 2);
+        v = make_float4((float)(x0.x * sc), (float)(x0.y * sc), (float)(x1.x * sc), (float)(x1.y * sc));
+      } else {
+        v = *reinterpret_cast<const double2*>(src);
+      }
+    } else {
+      v = *reinterpret_cast<const vec_t*>(t_in + ((size_t)z * N + q) * ncolp + col);
+    }
+    if (c) {
+      if constexpr (MF<T>::VEC == 4) {
+        v = make_float4(-v.y, v.x, -v.w, v.z);
+      } else {
+        v = make_double2(-v.y, v.x);
+      }
+    }
+    return v;
+  }
+};
+
+template <typename T, int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(WM* WN * 64) void taylor_kernel(TaylorProb<T> p, T* __restrict__ t_out,
+                                                             double* __restrict__ acc_out, int ncol,
+                                                             double inv_k, int add_prev,
+                                                             int add_this) {
+  __shared__ __attribute__((aligned(16))) T lds[TileLds<T, BM, BN, BK>::ELEMS];
+  typename MF<T>::acc_t acc[BM / WM / 16][BN / WN / 16];
+  const int z = blockIdx.z;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  mfma_tile_mainloop<T, BM, BN, BK, WM, WN, true>(p, z, m0, n0, p.ldV, acc, lds);
+  const double unscale = ldexp(1.0, (int)taylor_scale_exp<T>(p.tmax, z));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wm = wid / WN, wn = wid % WN;
+#pragma unroll
+  for (int i = 0; i < BM / WM / 16; ++i)
+#pragma unroll
+    for (int j = 0; j < BN / WN / 16; ++j) {
+      const int mb = m0 + wm * (BM / WM) + i * 16 + 4 * (lane >> 4);
+      const int col = n0 + wn * (BN / WN) + j * 16 + (lane & 15);
+      if (col >= ncol) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = mb + r;
+        if (row >= p.N) continue;
+        const double v = (double)acc[i][j][r] * inv_k;
+        const size_t o = ((size_t)z * p.N + row) * p.ncolp + col;
+        const T tv = (T)v;
+        // The first term reads the accumulator as its operand, so no launch
+        // writes the accumulator while reading it: launch k adds term k-1,
+        // and the last launch also adds its own term.
+        double add = 0.0;
+        if (add_prev) add += (double)p.t_in[o];
+        if (add_this) add += (double)tv;
+        if (add_prev | add_this) acc_out[o] += add * unscale;
+        t_out[o] = tv;
+      }
+    }
+}
+
+template <typename T>
+__global__ void taylor_last_kernel(int W, int N, int ncolp, int ncol, const T* __restrict__ t,
+                                   double* __restrict__ acc, const unsigned* __restrict__ tmax) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t per = (size_t)N * ncolp;
+  if (e >= per * W) return;
+  const int z = (int)(e / per);
+  if ((int)(e % ncolp) >= ncol) return;
+  acc[e] += (double)t[e] * ldexp(1.0, (int)taylor_scale_exp<T>(tmax, z));
+}
+
+template <typename T>
+hipError_t launch_taylor(const StepDims& d, int W, const T* vhs, const T* t_in, T* t_out,
+                         double* acc, const unsigned* tmax, int k, int order, hipStream_t s) {
+  constexpr int BM = 64, BN = 64, BK = sizeof(T) == 4 ? 32 : 16, WM = 2, WN = 2;
+  TaylorProb<T> p{vhs, d.N, d.ldV, d.ncolp, acc, t_in, tmax, k == 1 ? 1 : 0};
+  dim3 grid(ceil_div(d.N, BM), ceil_div(d.ncolp, BN), W);
+  const int add_prev = k >= 2 ? 1 : 0;
+  const int add_this = (k == order && k >= 2) ? 1 : 0;
+  hipLaunchKernelGGL((taylor_kernel<T, BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p,
+                     t_out, acc, d.ncol, 1.0 / k, add_prev, add_this);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !(k == order && k == 1)) return e;
+  const size_t tot = (size_t)W * d.N * d.ncolp;
+  hipLaunchKernelGGL(taylor_last_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                     W, d.N, d.ncolp, d.ncol, t_out, acc, tmax);
+  return hipGetLastError();
+}
+template hipError_t launch_taylor<float>(const StepDims&, int, const float*, const float*, float*,
+                                         double*, const unsigned*, int, int, hipStream_t);
+template hipError_t launch_taylor<double>(const StepDims&, int, const double*, const double*,
+                                          double*, double*, const unsigned*, int, int, hipStream_t);
+
+// ===========================================================================
+// Weights (Eqs. import, ovl, ph, theta):
+//   ln O_z = log<Psi_T|phi'> - log<Psi_T|phi>, theta_z = Im ln O_z,
+//   log w += Re ln O_z + Re a_z + cst + ln max(0, cos theta_z)
+// ===========================================================================
+
+__global__ void weight_kernel(int W, const double2* __restrict__ logdet, const double* __restrict__ corr,
+                              const double2* __restrict__ a, double2* __restrict__ log_ovlp,
+                              double* __restrict__ log_w, double cst, int* __restrict__ status) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= W) return;
+  const double2 l0 = logdet[2 * z], l1 = logdet[2 * z + 1];
+  const double2 ld = cadd(l0, l1);
+  const double c = corr ? corr[2 * z] + corr[2 * z + 1] : 0.0;
+  const double2 lo = log_ovlp[z];
+  const double lnr = ld.x + c - lo.x;
+  const double lni = ld.y - lo.y;
+  const double ct = cos(lni);
+  const double lw0 = log_w[z];
+  double lw;
+  if (lw0 == -INFINITY || ld.x == -INFINITY || !(ct > 0.0)) {
+    lw = -INFINITY;
+  } else {
+    lw = lw0 + lnr + a[z].x + cst + log(ct);
+  }
+  if (isnan(lw) || isnan(ld.x) || isnan(ld.y)) {
+    atomicOr(status, AFQMC_STATUS_NONFINITE);
+    lw = -INFINITY;
+  }
+  log_ovlp[z] = ld;
+  log_w[z] = lw;
+}
+
+hipError_t launch_weight(int W, const double2* logdet, const double* corr, const double2* a,
+                         double2* log_ovlp, double* log_w, double cst, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(weight_kernel, dim3(ceil_div(W, 256)), dim3(256), 0, s, W, logdet, corr, a,
+                     log_ovlp, log_w, cst, status);
+  return hipGetLastError();
+}
+
+__global__ void overlap_store_kernel(int W, const double2* __restrict__ logdet, double2* __restrict__ log_ovlp) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z < W) log_ovlp[z] = cadd(logdet[2 * z], logdet[2 * z + 1]);
+}
+
+hipError_t launch_overlap_store(int W, const double2* logdet, double2* log_ovlp, hipStream_t s) {
+  hipLaunchKernelGGL(overlap_store_kernel, dim3(ceil_div(W, 256)), dim3(256), 0, s, W, logdet, log_ovlp);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// Exchange energy (Sec. III.C): E_K = -1/2 sum_s sum_g sum_ij T_ij T_ji,
+// T^{s}_{z g} = Lh^s_g theta^s_z (n x n), formed tile by tile on MFMA and
+// consumed in LDS without ever reaching HBM.  A workgroup owns G whole
+// Cholesky blocks (rows (g, i)) and Z whole walkers (columns (z, re|im, j)),
+// so every T_ij meets its partner T_ji inside the tile.  Per-tile partial
+// sums go to part[s][g-tile][z] and are reduced in a fixed order later.
+// ===========================================================================
+
+template <typename T>
+struct ExProb {
+  using vec_t = typename MF<T>::vec_t;
+  const T* Lh;      // spin block [K][nmax][ldN]
+  const T* theta;
+  int K, W, n, nmax, ldN, sp, G, Z;
+  __device__ vec_t load_a(int, int r, int k) const {
+    if (r >= G * n) return MF<T>::vzero();
+    const int g = blockIdx.y * G + r / n;
+    if (g >= K) return MF<T>::vzero();
+    return *reinterpret_cast<const vec_t*>(Lh + ((size_t)g * nmax + r % n) * ldN + k);
+  }
+  __device__ vec_t load_b(int, int c, int k) const {
+    const int n2 = 2 * n;
+    if (c >= Z * n2) return MF<T>::vzero();
+    const int z = blockIdx.x * Z + c / n2;
+    if (z >= W) return MF<T>::vzero();
+    const int cc = c % n2;
+    const int comp = cc >= n ? 1 : 0;
+    const int j = cc - comp * n;
+    return *reinterpret_cast<const vec_t*>(
+        theta + (((size_t)z * 2 + comp) * 2 + sp) * (size_t)nmax * ldN + (size_t)j * ldN + k);
+  }
+};
+
+template <typename T> struct ExCfg;
+template <> struct ExCfg<float> {
+  static constexpr int BM = 192, BN = 160, BK = 32, WM = 2, WN = 2;
+};
+template <> struct ExCfg<double> {
+  static constexpr int BM = 192, BN = 160, BK = 16, WM = 4, WN = 2;
+};
+
+template <typename T>
+static size_t ex_lds_bytes(int G, int n) {
+  using C = ExCfg<T>;
+  const size_t stage = TileLds<T, C::BM, C::BN, C::BK>::BYTES;
+  const size_t epi = (size_t)G * n * (2 * n + 1) * sizeof(T);
+  return (stage > epi ? stage : epi) + 16 * sizeof(double2);
+}
+
+template <typename T>
+__global__ __launch_bounds__(ExCfg<T>::WM* ExCfg<T>::WN * 64) void exchange_kernel(
+    ExProb<T> p, double2* __restrict__ part, int ntg, int red_off) {
+  using C = ExCfg<T>;
+  constexpr int BM = C::BM, BN = C::BN, BK = C::BK, WM = C::WM, WN = C::WN;
+  constexpr int NT = WM * WN * 64;
+  extern __shared__ double2 ex_lds_raw[];
+  T* lds = reinterpret_cast<T*>(ex_lds_raw);
+  typename MF<T>::acc_t acc[BM / WM / 16][BN / WN / 16];
+  mfma_tile_mainloop<T, BM, BN, BK, WM, WN, false>(p, 0, 0, 0, p.ldN, acc, lds);
+
+  const int n = p.n, n2 = 2 * n, TS = n2 + 1;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wm = wid / WN, wn = wid % WN;
+  const int rows = p.G * n;
+  double2* red = reinterpret_cast<double2*>(reinterpret_cast<char*>(ex_lds_raw) + red_off);
+  for (int zz = 0; zz < p.Z; ++zz) {
+    const int z = blockIdx.x * p.Z + zz;
+    if (z >= p.W) break;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < BM / WM / 16; ++i)
+#pragma unroll
+      for (int j = 0; j < BN / WN / 16; ++j) {
+        const int mb = wm * (BM / WM) + i * 16 + 4 * (lane >> 4);
+        const int col = wn * (BN / WN) + j * 16 + (lane & 15) - zz * n2;
+        if (col < 0 || col >= n2) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (mb + r < rows) lds[(mb + r) * TS + col] = acc[i][j][r];
+      }
+    __syncthreads();
+    double2 s = make_double2(0.0, 0.0);
+    const int nn = n * n;
+    for (int e = threadIdx.x; e < p.G * nn; e += NT) {
+      const int g = e / nn, ij = e % nn, i = ij / n, j = ij % n;
+      const T* ri = lds + (g * n + i) * TS;
+      const T* rj = lds + (g * n + j) * TS;
+      const double ar = ri[j], ai = ri[n + j];
+      const double br = rj[i], bi = rj[n + i];
+      s.x += ar * br - ai * bi;
+      s.y += ar * bi + ai * br;
+    }
+    s = block_sum2(s, red);
+    if (threadIdx.x == 0) part[((size_t)p.sp * ntg + blockIdx.y) * p.W + z] = s;
+  }
+}
+
+template <typename T>
+ExTile exchange_tile(int n) {
+  using C = ExCfg<T>;
+  ExTile t;
+  t.G = n > 0 ? C::BM / n : 0;
+  t.Z = n > 0 ? C::BN / (2 * n) : 0;
+  return t;
+}
+template ExTile exchange_tile<float>(int);
+template ExTile exchange_tile<double>(int);
+
+template <typename T>
+hipError_t launch_exchange(const StepDims& d, int W, const T* Lh, const T* theta, double2* part,
+                           int* ntg_out, hipStream_t s) {
+  using C = ExCfg<T>;
+  const ExTile t = exchange_tile<T>(d.nmax);
+  if (t.G < 1 || t.Z < 1) return hipErrorInvalidValue;
+  const int ntg = ceil_div(d.K, t.G);
+  *ntg_out = ntg;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int n = sp == 0 ? d.na : d.nb;
+    ExProb<T> p{Lh + (size_t)sp * d.K * d.nmax * d.ldN, theta, d.K, W, n, d.nmax, d.ldN, sp, t.G, t.Z};
+    if (n == 0) {
+      continue;
+    }
+    // A spin with fewer electrons reuses the tile shape of the larger one.
+    const size_t lds = ex_lds_bytes<T>(t.G, n);
+    dim3 grid(ceil_div(W, t.Z), ntg);
+    const int red_off = (int)(lds - 16 * sizeof(double2));
+    hipLaunchKernelGGL(exchange_kernel<T>, grid, dim3(C::WM * C::WN * 64), lds, s, p, part, ntg,
+                       red_off);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+template hipError_t launch_exchange<float>(const StepDims&, int, const float*, const float*,
+                                           double2*, int*, hipStream_t);
+template hipError_t launch_exchange<double>(const StepDims&, int, const double*, const double*,
+                                            double2*, int*, hipStream_t);
+
+// ===========================================================================
+// Energy assembly (R10 of the design): E1 from the Green's function pass,
+// EJ = 1/2 sum_g vbias_g^2, EK = -1/2 sum of the exchange partials.
+// ===========================================================================
+
+__global__ __launch_bounds__(256) void energy_kernel(int W, int K, int ntg, int nb_zero,
+                                                     const double2* __restrict__ e1,
+                                                     const double2* __restrict__ vbias,
+                                                     const double2* __restrict__ part,
+                                                     double2* __restrict__ e_out) {
+  __shared__ double2 red[4];
+  const int z = blockIdx.x;
+  double2 ej = make_double2(0.0, 0.0);
+  for (int g = threadIdx.x; g < K; g += 256) {
+    const double2 v = vbias[(size_t)z * K + g];
+    ej = cadd(ej, cmul(v, v));
+  }
+  ej = block_sum2(ej, red);
+  double2 ek = make_double2(0.0, 0.0);
+  const int nsp = nb_zero ? 1 : 2;
+  for (int e = threadIdx.x; e < nsp * ntg; e += 256) {
+    const int sp = e / ntg, t = e % ntg;
+    ek = cadd(ek, part[((size_t)sp * ntg + t) * W + z]);
+  }
+  ek = block_sum2(ek, red);
+  if (threadIdx.x == 0) {
+    e_out[3 * z + 0] = cadd(e1[2 * z], e1[2 * z + 1]);
+    e_out[3 * z + 1] = cscale(ej, 0.5);
+    e_out[3 * z + 2] = cscale(ek, -0.5);
+  }
+}
+
+hipError_t launch_energy(const StepDims& d, int W, const double2* e1, const double2* vbias,
+                         const double2* part, int ntg, double2* e_out, hipStream_t s) {
+  hipLaunchKernelGGL(energy_kernel, dim3(W), dim3(256), 0, s, W, d.K, ntg, d.nb == 0 ? 1 : 0, e1,
+                     vbias, part, e_out);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// Re-orthogonalisation (R9 of the design): Householder QR of each walker and
+// spin, phi <- Q D with D = diag(R_ii / |R_ii|) so that R' = D^* R has a
+// positive real diagonal; corr = sum ln |R_ii|.  The N x n block lives in
+// LDS column-major; waves own columns, lanes own rows.
+// ===========================================================================
+
+constexpr int QR_THREADS = 256;
+
+size_t qr_lds_bytes(const StepDims& d) {
+  return (size_t)d.N * d.nmax * sizeof(double2) + 2 * (size_t)d.nmax * sizeof(double2) + 64;
+}
+
+__global__ __launch_bounds__(QR_THREADS) void qr_kernel(StepDims d, double2* __restrict__ phi_a,
+                                                        double2* __restrict__ phi_b,
+                                                        double* __restrict__ corr,
+                                                        int* __restrict__ status) {
+  extern __shared__ double2 qr_lds[];
+  const int z = blockIdx.x, sp = blockIdx.y;
+  const int n = sp == 0 ? d.na : d.nb;
+  const int N = d.N;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  constexpr int NWAVE = QR_THREADS / 64;
+  if (n == 0) {
+    if (tid == 0) corr[2 * z + sp] = 0.0;
+    return;
+  }
+  double2* A = qr_lds;                        // A[j * N + p]
+  double2* alpha = A + (size_t)N * n;         // R_kk
+  double* beta = reinterpret_cast<double*>(alpha + n);
+  double2* phi = (sp == 0 ? phi_a : phi_b) + (size_t)z * N * n;
+
+  for (int e = tid; e < N * n; e += QR_THREADS) {
+    const int p = e / n, j = e % n;
+    A[j * N + p] = phi[e];
+  }
+  __syncthreads();
+
+  // ---- factorisation ----
+  for (int k = 0; k < n; ++k) {
+    if (wid == 0) {
+      double s = 0.0;
+      for (int p = k + lane; p < N; p += 64) s += cabs2(A[k * N + p]);
+      s = wave_sum(s);
+      const double xn = sqrt(s);
+      const double2 x0 = A[k * N + k];
+      const double a0 = sqrt(cabs2(x0));
+      const double2 ph = a0 > 0.0 ? cscale(x0, 1.0 / a0) : make_double2(1.0, 0.0);
+      const double2 al = cscale(ph, -xn);             // alpha = -e^{i arg x0} ||x||
+      const double2 v0 = csub(x0, al);
+      const double vn2 = s - a0 * a0 + cabs2(v0);
+      if (lane == 0) {
+        alpha[k] = al;
+        beta[k] = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+        A[k * N + k] = v0;
+        if (!(xn > 0.0)) atomicOr(status, AFQMC_STATUS_QR_ZERO);
+      }
+    }
+    __syncthreads();
+    const double bk = beta[k];
+    for (int j = k + 1 + wid; j < n; j += NWAVE) {
+      double2 w = make_double2(0.0, 0.0);
+      for (int p = k + lane; p < N; p += 64) w = cadd(w, cmul(cconj(A[k * N + p]), A[j * N + p]));
+      w = cscale(wave_sum2(w), bk);
+      for (int p = k + lane; p < N; p += 64) A[j * N + p] = csub(A[j * N + p], cmul(A[k * N + p], w));
+    }
+    __syncthreads();
+  }
+
+  // ---- explicit Q = H_0 ... H_{n-1} [I; 0], accumulated backwards in place ----
+  for (int e = tid; e < n * n; e += QR_THREADS) {
+    const int j = e / n, p = e % n;
+    if (p < j) A[j * N + p] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int i = n - 1; i >= 0; --i) {
+    const double bi = beta[i];
+    for (int j = i + 1 + wid; j < n; j += NWAVE) {
+      double2 w = make_double2(0.0, 0.0);
+      for (int p = i + lane; p < N; p += 64) w = cadd(w, cmul(cconj(A[i * N + p]), A[j * N + p]));
+      w = cscale(wave_sum2(w), bi);
+      for (int p = i + lane; p < N; p += 64) A[j * N + p] = csub(A[j * N + p], cmul(A[i * N + p], w));
+    }
+    __syncthreads();
+    if (wid == 0) {
+      const double2 v0c = cconj(A[i * N + i]);
+      for (int p = i + lane; p < N; p += 64) {
+        double2 q = cscale(cmul(A[i * N + p], v0c), -bi);
+        if (p == i) q.x += 1.0;
+        A[i * N + p] = q;
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- phi <- Q D, corr = sum ln |R_kk| ----
+  for (int e = tid; e < N * n; e += QR_THREADS) {
+    const int p = e / n, j = e % n;
+    const double2 al = alpha[j];
+    const double aa = sqrt(cabs2(al));
+    const double2 dj = aa > 0.0 ? cscale(al, 1.0 / aa) : make_double2(1.0, 0.0);
+    phi[e] = cmul(A[j * N + p], dj);
+  }
+  if (wid == 0) {
+    double s = 0.0;
+    for (int k = lane; k < n; k += 64) s += 0.5 * log(cabs2(alpha[k]));
+    s = wave_sum(s);
+    if (lane == 0) corr[2 * z + sp] = s;
+  }
+}
+
+hipError_t launch_qr(const StepDims& d, int W, double2* phi_a, double2* phi_b, double* corr,
+                     int* status, hipStream_t s) {
+  hipLaunchKernelGGL(qr_kernel, dim3(W, 2), dim3(QR_THREADS), qr_lds_bytes(d), s, d, phi_a, phi_b,
+                     corr, status);
+  return hipGetLastError();
+}
+
+__global__ void ortho_update_kernel(int W, const double* __restrict__ corr, double2* __restrict__ log_ovlp) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z < W) log_ovlp[z].x -= corr[2 * z] + corr[2 * z + 1];
+}
+
+hipError_t launch_ortho_update(int W, const double* corr, double2* log_ovlp, hipStream_t s) {
+  hipLaunchKernelGGL(ortho_update_kernel, dim3(ceil_div(W, 256)), dim3(256), 0, s, W, corr, log_ovlp);
+  return hipGetLastError();
+}
+
+hipError_t set_kernel_attributes(const StepDims& d) {
+  hipError_t e;
+  const int big = 160 * 1024;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(qr_kernel),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(gf_kernel<float>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(gf_kernel<double>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(exchange_kernel<float>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(exchange_kernel<double>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)d;
+  return e;
+}

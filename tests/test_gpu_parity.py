@@ -1,0 +1,258 @@
+"""Parity of the HIP walker step (through the C ABI) with the FP64 oracle.
+
+Every call is teacher-forced: the GPU call and the oracle call receive the
+same seeded inputs, and their outputs are compared element by element.
+
+Bars (the mixed bar is a stated bound relative to the energy scale
+S = |E1| + |EJ| + |EK| of each walker; the FP64 bar is rounding level):
+  FP64:  energies 1e-12 * S, vbias 1e-12 * max|vbias|, phi 1e-11 * max|phi|,
+         log overlap / log weight 1e-10 absolute.
+  FP32 (mixed):  energies 2e-6 * S, vbias 2e-6 * max|vbias|, phi and log
+         overlap as stated per test.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import afqmc_oracle as orc
+from paper_2209_04015_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+# A size that spans several tiles of every kernel and has ragged tails.
+RAGGED = inputs.Config("ragged", N=52, n=11, K=150, decay=40.0, W=37, steps=3, qr_interval=1)
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _system(cfg, seed=0, uhf=False):
+    h1, L = inputs.hamiltonian(cfg.N, cfg.K, cfg.decay, seed=seed)
+    phiT = inputs.trial(h1, cfg.n)
+    if uhf:
+        phiT_b = inputs.trial(h1 + np.diag(np.linspace(0.0, 0.4, cfg.N)), max(cfg.n - 2, 1))
+    else:
+        phiT_b = phiT
+    return h1, L, phiT, phiT_b
+
+
+def _walkers(phiT_a, phiT_b, W, seed=0, scale=0.3):
+    pa = inputs.walkers_perturbed(phiT_a, W, scale, seed=seed, stream=0)
+    pb = inputs.walkers_perturbed(phiT_b, W, scale, seed=seed, stream=1)
+    return pa, pb
+
+
+class Case:
+    def __init__(self, cfg, precision, uhf=False, seed=0):
+        from paper_2209_04015_amd import afqmc
+
+        torch = _torch()
+        self.cfg = cfg
+        self.precision = precision
+        self.h1, self.L, self.pa_T, self.pb_T = _system(cfg, seed=seed, uhf=uhf)
+        self.oh = orc.setup(self.h1, self.L, self.pa_T, self.pb_T, dt=cfg.dt)
+        self.ham = afqmc.Hamiltonian(self.h1, self.L, self.pa_T, self.pb_T, dt=cfg.dt,
+                                     max_walkers=cfg.W, precision=precision)
+        self.pa, self.pb = _walkers(self.pa_T, self.pb_T, cfg.W, seed=seed)
+        self.lo = orc.overlap(self.oh, self.pa, self.pb)
+        self.lw = np.linspace(-0.3, 0.2, cfg.W)
+        self.x = inputs.fields(cfg.W, cfg.K, 1, seed=seed)[0]
+        self.dev = torch.device("cuda:0")
+
+    def walkers(self, pa=None, pb=None, lo=None, lw=None):
+        from paper_2209_04015_amd import afqmc
+
+        return afqmc.Walkers.from_numpy(self.pa if pa is None else pa, self.pb if pb is None else pb,
+                                        self.lo if lo is None else lo, self.lw if lw is None else lw,
+                                        device=self.dev)
+
+
+_CASES = {}
+
+
+def case(name, precision, uhf=False):
+    key = (name, precision, uhf)
+    if key not in _CASES:
+        cfg = RAGGED if name == "ragged" else inputs.CONFIGS[name]
+        print(f"[gpu] building case {key}", flush=True)
+        _CASES[key] = Case(cfg, precision, uhf=uhf)
+    return _CASES[key]
+
+
+def _energy_tol(precision):
+    return 1e-12 if precision == "fp64" else 2e-6
+
+
+PARAMS = [("n20", "fp64", False), ("ragged", "fp64", False), ("ragged", "fp64", True),
+          ("n20", "fp32", False), ("ragged", "fp32", False), ("ragged", "fp32", True)]
+
+
+@pytest.mark.parametrize("name,precision,uhf", PARAMS)
+def test_setup_matches_oracle(name, precision, uhf):
+    c = case(name, precision, uhf)
+    P, mu, es = c.ham.setup()
+    assert mu == pytest.approx(c.oh.mu, rel=1e-13, abs=1e-13)
+    assert np.abs(P - c.oh.P).max() <= 1e-13 * np.abs(c.oh.P).max()
+    assert es == pytest.approx(c.oh.e_shift, rel=1e-12)
+
+
+@pytest.mark.parametrize("name,precision,uhf", PARAMS)
+def test_overlap_matches_oracle(name, precision, uhf):
+    c = case(name, precision, uhf)
+    w = c.walkers(lo=np.zeros(c.cfg.W, complex))
+    c.ham.overlap(w)
+    got = w.log_ovlp.cpu().numpy()
+    ref = c.lo
+    assert np.abs(got.real - ref.real).max() < 1e-11
+    assert np.abs(np.exp(1j * (got.imag - ref.imag)) - 1).max() < 1e-11
+
+
+@pytest.mark.parametrize("name,precision,uhf", PARAMS)
+def test_force_bias_matches_oracle(name, precision, uhf):
+    c = case(name, precision, uhf)
+    w = c.walkers()
+    got = c.ham.force_bias(w).cpu().numpy()
+    ref = orc.force_bias(c.oh, c.pa, c.pb)
+    tol = 1e-12 if precision == "fp64" else 2e-6
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name,precision,uhf", PARAMS)
+def test_local_energy_matches_oracle(name, precision, uhf):
+    c = case(name, precision, uhf)
+    w = c.walkers()
+    got = c.ham.local_energy(w).cpu().numpy()
+    ref = orc.local_energy(c.oh, c.pa, c.pb)
+    S = np.abs(ref).sum(axis=1)
+    err = np.abs(got.sum(axis=1) - ref.sum(axis=1))
+    tol = _energy_tol(precision)
+    print(f"[gpu] {name} {precision} uhf={uhf}: max |dE|/S = {(err / S).max():.3e}", flush=True)
+    assert np.all(err <= tol * S)
+    for k in range(3):   # each part to the same scale
+        assert np.all(np.abs(got[:, k] - ref[:, k]) <= tol * S)
+
+
+@pytest.mark.parametrize("name,precision,uhf", PARAMS)
+def test_propagate_matches_oracle(name, precision, uhf):
+    torch = _torch()
+    c = case(name, precision, uhf)
+    w = c.walkers()
+    c.ham.propagate(w, torch.as_tensor(c.x, device=c.dev))
+    na, nb, lo, lw = orc.propagate(c.oh, c.pa, c.pb, c.lo, c.lw, c.x)
+    ga, gb = w.phi_a.cpu().numpy(), w.phi_b.cpu().numpy()
+    glo, glw = w.log_ovlp.cpu().numpy(), w.log_w.cpu().numpy()
+    tol_phi = 1e-11 if precision == "fp64" else 1e-4
+    tol_log = 1e-10 if precision == "fp64" else 1e-3
+    for g, r in ((ga, na), (gb, nb)):
+        scale = np.abs(r).reshape(r.shape[0], -1).max(axis=1)
+        err = np.abs(g - r).reshape(r.shape[0], -1).max(axis=1)
+        print(f"[gpu] {name} {precision}: max rel phi err {(err / scale).max():.3e}", flush=True)
+        assert np.all(err <= tol_phi * scale)
+    assert np.abs(glo.real - lo.real).max() < tol_log
+    assert np.abs(np.exp(1j * (glo.imag - lo.imag)) - 1).max() < tol_log
+    alive = np.isfinite(lw)
+    assert np.array_equal(alive, np.isfinite(glw))
+    assert np.abs(glw[alive] - lw[alive]).max() < tol_log
+
+
+@pytest.mark.parametrize("name,precision,uhf", PARAMS)
+def test_orthogonalise_matches_oracle(name, precision, uhf):
+    c = case(name, precision, uhf)
+    pa = c.pa * np.exp(np.linspace(-3, 3, c.cfg.W))[:, None, None]
+    w = c.walkers(pa=pa)
+    c.ham.orthogonalise(w)
+    qa, qb, lo = orc.orthogonalise(pa, c.pb, c.lo)
+    assert np.abs(w.phi_a.cpu().numpy() - qa).max() < 1e-12
+    assert np.abs(w.phi_b.cpu().numpy() - qb).max() < 1e-12
+    assert np.abs(w.log_ovlp.cpu().numpy() - lo).max() < 1e-11
+
+
+@pytest.mark.parametrize("name,precision,uhf", PARAMS)
+def test_fused_step_matches_oracle(name, precision, uhf):
+    """afqmc_step (propagate, QR, energy) against the oracle's step, twice in a row
+    with the cached Green's function on the second call."""
+    torch = _torch()
+    c = case(name, precision, uhf)
+    w = c.walkers()
+    xs = inputs.fields(c.cfg.W, c.cfg.K, 2, seed=5)
+    pa, pb, lo, lw = c.pa, c.pb, c.lo, c.lw
+    e = torch.empty((c.cfg.W, 3), dtype=torch.complex128, device=c.dev)
+    tol = _energy_tol(precision)
+    for k in range(2):
+        c.ham.step(w, torch.as_tensor(xs[k], device=c.dev), do_qr=True, energy_out=e, reuse=(k > 0))
+        pa, pb, lo, lw, er = orc.step(c.oh, pa, pb, lo, lw, xs[k], do_qr=True)
+        if precision == "fp32":
+            # teacher forcing: restart both from the oracle state
+            w = c.walkers(pa=pa, pb=pb, lo=lo, lw=lw)
+            continue
+        got = e.cpu().numpy()
+        S = np.abs(er).sum(axis=1)
+        assert np.all(np.abs(got.sum(axis=1) - er.sum(axis=1)) <= 1e3 * tol * S)
+        assert np.abs(w.phi_a.cpu().numpy() - pa).max() < 1e-10
+        assert np.abs(w.log_w.cpu().numpy() - lw).max() < 1e-9
+
+
+def test_free_running_n20_fp64_first_steps():
+    """Free-running FP64 trajectory: energies within 1e-10 Ha for steps 0-3."""
+    torch = _torch()
+    c = case("n20", "fp64")
+    cfg = c.cfg
+    pa = inputs.walkers_at_trial(c.pa_T, cfg.W)
+    pb = pa.copy()
+    lo = orc.overlap(c.oh, pa, pb)
+    lw = np.zeros(cfg.W)
+    w = c.walkers(pa=pa, pb=pb, lo=lo, lw=lw)
+    xs = inputs.fields(cfg.W, cfg.K, 4, seed=0)
+    e = torch.empty((cfg.W, 3), dtype=torch.complex128, device=c.dev)
+    for k in range(4):
+        qr = (k + 1) % cfg.qr_interval == 0
+        c.ham.step(w, torch.as_tensor(xs[k], device=c.dev), do_qr=qr, energy_out=e, reuse=(k > 0))
+        pa, pb, lo, lw, er = orc.step(c.oh, pa, pb, lo, lw, xs[k], do_qr=qr)
+        got = e.cpu().numpy().sum(axis=1)
+        err = np.abs(got - er.sum(axis=1)).max()
+        print(f"[gpu] free-running n20 step {k}: max |dE| = {err:.3e} Ha", flush=True)
+        assert err < 1e-10
+
+
+def test_zero_walkers_is_a_no_op():
+    torch = _torch()
+    c = case("n20", "fp64")
+    w = c.walkers()
+    before = w.phi_a.clone()
+    c.ham.propagate(w, torch.zeros((0, c.cfg.K), dtype=torch.float64, device=c.dev), nw=0)
+    torch.cuda.synchronize()
+    assert torch.equal(before, w.phi_a)
+
+
+def test_singular_walker_is_discarded_not_fatal():
+    torch = _torch()
+    c = case("ragged", "fp64")
+    pa = c.pa.copy()
+    pa[3, :, 0] = 0.0        # a vanished orbital: zero overlap
+    w = c.walkers(pa=pa)
+    c.ham.status()           # clear
+    c.ham.propagate(w, torch.as_tensor(c.x, device=c.dev))
+    st = c.ham.status()
+    assert st & 1            # AFQMC_STATUS_SINGULAR
+    lw = w.log_w.cpu().numpy()
+    assert lw[3] == -np.inf
+    na, nb, lo, lwr = orc.propagate(c.oh, c.pa, c.pb, c.lo, c.lw, c.x)
+    others = [z for z in range(c.cfg.W) if z != 3]
+    assert np.abs(lw[others] - lwr[others]).max() < 1e-10
+
+
+def test_bad_shapes_raise():
+    torch = _torch()
+    c = case("n20", "fp64")
+    w = c.walkers()
+    with pytest.raises(ValueError):
+        c.ham.propagate(w, torch.zeros((c.cfg.W, c.cfg.K + 1), dtype=torch.float64, device=c.dev))
+    from paper_2209_04015_amd.afqmc import AfqmcError
+
+    with pytest.raises((AfqmcError, ValueError)):
+        c.ham.local_energy(w, nw=c.cfg.W + 1)
