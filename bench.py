@@ -1,0 +1,239 @@
+"""Throughput of the phaseless-AFQMC walker step on one MI355X.
+
+One step = one full walker step for every walker: Green's function, force
+bias, VHS, propagation (two one-body half steps around a 6-term Taylor
+series), overlap ratio and phaseless weight, QR re-orthogonalisation on the
+workload's schedule, and the local energy (E1, EJ, EK) of every walker.
+
+The headline is the mixed path (FP32-MFMA contractions, FP64 elsewhere); the
+FP64 path runs on the same seeded inputs and is reported beside it.  Inputs
+are synthetic (seeded generators), resident in HBM before timing starts.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "walker-steps/s at N=290 mixed vs FP64 on 1 GPU; energy err vs FP64 oracle"
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X dense matrix peaks
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def exchange_flops_per_launch(cfg, W):
+    # one launch = one spin: T = Lh_g theta_z for every (g, z): K * n^2 * N real x complex
+    # multiply-adds (4 flops each); the T_ij T_ji pairing adds 8 K n^2 flops per walker.
+    return W * (4.0 * cfg.K * cfg.n * cfg.n * cfg.N + 8.0 * cfg.K * cfg.n * cfg.n)
+
+
+def step_flops(cfg):
+    """Algorithmic flops of one walker-step (both spins), by part."""
+    N, n, K = cfg.N, cfg.n, cfg.K
+    return {
+        "green": 2 * (8 * N * n * n + 5.3 * n ** 3 + 8 * N * n * n),
+        "force_bias": 8.0 * K * N * n,
+        "vhs": 2.0 * K * N * (N + 1),
+        "one_body": 16.0 * N * N * n,
+        "taylor": 96.0 * N * N * n,
+        "exchange": 8.0 * K * n * n * N + 16.0 * K * n * n,
+    }
+
+
+def run_gpu(cfg, h1, L, phiT, precision, steps, warmup, fields_dev, device):
+    import torch
+
+    from paper_2209_04015_amd import afqmc
+
+    W = cfg.W
+    t = time.time()
+    ham = afqmc.Hamiltonian(h1, L, phiT, phiT, dt=cfg.dt, max_walkers=W, precision=precision,
+                            taylor_order=cfg.taylor_order)
+    log(f"{precision}: init {time.time() - t:.1f} s")
+    pa = torch.as_tensor(np.repeat(phiT[None].astype(np.complex128), W, axis=0), device=device)
+    w = afqmc.Walkers(pa, pa.clone())
+    ham.overlap(w)
+    e = torch.empty((W, 3), dtype=torch.complex128, device=device)
+    stream = torch.cuda.current_stream()
+    for i in range(warmup):
+        ham.step(w, fields_dev[i], do_qr=((i + 1) % cfg.qr_interval == 0), energy_out=e, reuse=(i > 0))
+    torch.cuda.synchronize()
+    log(f"{precision}: warmup done")
+    ham.profile_enable(steps * 40)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for i in range(warmup, warmup + steps):
+        ham.step(w, fields_dev[i], do_qr=((i + 1) % cfg.qr_interval == 0), energy_out=e, reuse=True)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    phases = ham.profile_read()
+    ham.profile_enable(0)
+    status = ham.status()
+    log(f"{precision}: {steps} steps in {ms:.1f} ms ({ms / steps:.2f} ms/step), status {status}")
+    return ham, w, e, ms, phases, status
+
+
+def roofline(cfg, phases, precision):
+    ms, launches = phases["exchange"]
+    if launches == 0:
+        return None
+    avg_ms = ms / launches
+    flops = exchange_flops_per_launch(cfg, cfg.W)
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[precision]
+    return {"kernel": "exchange_kernel", "bound": "mfma", "achieved": round(achieved, 2),
+            "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": flops}
+
+
+def cpu_baseline_and_energy_error(cfg, h1, L, phiT, gpu_states, sample, x_sample):
+    """The FP64 oracle: its walker-step rate on a bounded sample, and the per-walker
+    energy error of each GPU path against it on sampled walkers."""
+    from oracle import afqmc_oracle as orc
+
+    t = time.time()
+    oh = orc.setup(h1, L, phiT, phiT, dt=cfg.dt, taylor_order=cfg.taylor_order)
+    log(f"oracle setup {time.time() - t:.1f} s")
+    out = {}
+    for prec, (pa, pb, e_gpu) in gpu_states.items():
+        e_ref = orc.local_energy(oh, pa, pb)
+        S = np.abs(e_ref).sum(axis=1)
+        err = np.abs(e_gpu.sum(axis=1) - e_ref.sum(axis=1))
+        out[prec] = {"max_abs_Ha": float(err.max()), "max_rel_to_S": float((err / S).max()),
+                     "walkers": int(len(err)), "E_scale_Ha": float(np.abs(e_ref.sum(axis=1)).max())}
+        log(f"energy error {prec}: {err.max():.3e} Ha ({(err / S).max():.2e} of S)")
+    # timed oracle sample: full steps (propagate, QR, energy) of `sample` walkers
+    pa = np.repeat(phiT[None].astype(np.complex128), sample, axis=0)
+    pb = pa.copy()
+    lo = orc.overlap(oh, pa, pb)
+    lw = np.zeros(sample)
+    t = time.time()
+    orc.step(oh, pa, pb, lo, lw, x_sample, do_qr=True)
+    dt = time.time() - t
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max((d.get("num_threads", 0) for d in threadpool_info()), default=None)
+    except Exception:
+        pass
+    cpu = {"value": round(sample / dt, 3), "unit": "walker-steps/s",
+           "cores": threads or os.cpu_count(), "kind": "oracle",
+           "sample": f"{sample} walkers x 1 full step (propagate, QR, local energy) of the same "
+                     f"workload, FP64 NumPy oracle; setup not timed; {dt:.1f} s"}
+    log(f"oracle: {sample} walker-steps in {dt:.1f} s")
+    return cpu, out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="n290")
+    ap.add_argument("--cpu-sample", type=int, default=2, help="walkers in the timed oracle sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the walker-parallel "
+              "multi-GPU layout is described in DESIGN.md and not run here.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2209_04015_amd import inputs
+
+    cfg = inputs.CONFIGS[args.config]
+    device = torch.device("cuda:0")
+    t = time.time()
+    h1, L = inputs.hamiltonian(cfg.N, cfg.K, cfg.decay, seed=0)
+    phiT = inputs.trial(h1, cfg.n)
+    nsteps = args.warmup + args.steps
+    fields = inputs.fields(cfg.W, cfg.K, nsteps, seed=0)
+    fields_dev = torch.as_tensor(fields, device=device)
+    log(f"inputs {cfg.name}: N={cfg.N} n={cfg.n} K={cfg.K} W={cfg.W} generated in {time.time() - t:.1f} s")
+
+    results = {}
+    states = {}
+    sample = min(args.cpu_sample, cfg.W)
+    for precision in ("fp64", "fp32"):
+        ham, w, e, ms, phases, status = run_gpu(cfg, h1, L, phiT, precision, args.steps, args.warmup,
+                                                fields_dev, device)
+        results[precision] = (ms, phases, status)
+        # energies of sampled walkers from this path's own final states
+        pa = w.phi_a[:sample].cpu().numpy()
+        pb = w.phi_b[:sample].cpu().numpy()
+        e_s = ham.local_energy(w).cpu().numpy()[:sample]
+        states[precision] = (pa, pb, e_s)
+        ham.close()
+        del w, e
+        torch.cuda.empty_cache()
+
+    cpu = None
+    eerr = None
+    if not args.no_cpu:
+        cpu, eerr = cpu_baseline_and_energy_error(cfg, h1, L, phiT, states, sample,
+                                                  fields[0, :sample])
+
+    W = cfg.W
+    def rate(ms):
+        return W * args.steps / (ms * 1e-3)
+
+    def phase_table(phases):
+        return {k: round(v[0] / args.steps, 4) for k, v in phases.items() if v[1] > 0}
+
+    ms32, ph32, st32 = results["fp32"]
+    ms64, ph64, st64 = results["fp64"]
+    fl = step_flops(cfg)
+    line = {
+        "metric": METRIC,
+        "value": round(rate(ms32), 2),
+        "unit": "walker-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms32 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 contractions (MFMA) + f64 overlaps/solves/QR/weights/energy sums",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{cfg.name}: ph-AFQMC full walker step (propagate + QR + local energy every "
+                        f"step), N={cfg.N} orbitals, na=nb={cfg.n}, K={cfg.K} Cholesky vectors, "
+                        f"{W} walkers, dt={cfg.dt}, Taylor order {cfg.taylor_order}, QR every "
+                        f"{cfg.qr_interval} step(s)",
+            "walkers": W, "N": cfg.N, "n_per_spin": cfg.n, "K": cfg.K,
+        },
+        "roofline": roofline(cfg, ph32, "fp32"),
+        "cpu_baseline": cpu,
+        "fp64": {"value": round(rate(ms64), 2), "unit": "walker-steps/s",
+                 "ms_per_step": round(ms64 / args.steps, 4), "roofline": roofline(cfg, ph64, "fp64"),
+                 "phases_ms_per_step": phase_table(ph64), "status": st64},
+        "mixed_over_fp64": round(ms64 / ms32, 3),
+        "energy_error_vs_fp64_oracle": eerr,
+        "phases_ms_per_step": phase_table(ph32),
+        "algorithmic_gflop_per_walker_step": {k: round(v / 1e9, 4) for k, v in fl.items()},
+        "status": st32,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -143,6 +143,29 @@ int afqmc_get_status(afqmc_ham* ham, void* stream, int* out);
  * (either may be NULL).  Synchronises the device. */
 int afqmc_get_setup(afqmc_ham* ham, double* host_P, double* mu, double* e_shift);
 
+/* Kernel-phase timing.  afqmc_profile_enable(ham, n) creates 2 n HIP events
+ * (n = 0 turns timing off); afterwards every kernel phase of every call on
+ * `ham` is bracketed by two events recorded on the call's stream, up to n
+ * phases.  afqmc_profile_read synchronises on the recorded events, writes
+ * the summed milliseconds and the number of recorded launches of each phase
+ * into ms[AFQMC_NPHASE] and launches[AFQMC_NPHASE] (host arrays), and starts
+ * a new recording.  Enabling synchronises the device and may allocate. */
+enum {
+  AFQMC_PH_GREEN = 0,    /* overlap, Green's function theta, one-body energy */
+  AFQMC_PH_FORCE_BIAS,   /* vbias = Lh . theta */
+  AFQMC_PH_SHIFT,        /* xbar, x - xbar, importance exponent */
+  AFQMC_PH_VHS,          /* VHS = i sqrt(dt) sum_g (x - xbar)_g L_g */
+  AFQMC_PH_ONE_BODY,     /* P phi (one launch per half step) */
+  AFQMC_PH_TAYLOR,       /* one launch per Taylor term */
+  AFQMC_PH_QR,           /* re-orthogonalisation */
+  AFQMC_PH_WEIGHT,       /* overlap ratio, phase, log weight */
+  AFQMC_PH_EXCHANGE,     /* one launch per spin */
+  AFQMC_PH_ENERGY,       /* assembly of E1, EJ, EK */
+  AFQMC_NPHASE
+};
+int afqmc_profile_enable(afqmc_ham* ham, int max_records);
+int afqmc_profile_read(afqmc_ham* ham, double* ms, int* launches);
+
 void afqmc_destroy(afqmc_ham* ham);
 const char* afqmc_last_error(void);
 int afqmc_version(void);

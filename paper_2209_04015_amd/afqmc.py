@@ -34,10 +34,17 @@ EXPORTED = (
     "afqmc_step",
     "afqmc_get_status",
     "afqmc_get_setup",
+    "afqmc_profile_enable",
+    "afqmc_profile_read",
     "afqmc_destroy",
     "afqmc_last_error",
     "afqmc_version",
 )
+
+
+# kernel phases of afqmc_profile_read, in header order
+PHASES = ("green", "force_bias", "shift", "vhs", "one_body", "taylor", "qr", "weight",
+          "exchange", "energy")
 
 
 class AfqmcError(RuntimeError):
@@ -92,6 +99,8 @@ def load(path: str = LIB_PATH):
     lib.afqmc_step.argtypes = [vp, P(_Walkers), ip, vp, ip, vp, ip, vp]
     lib.afqmc_get_status.argtypes = [vp, vp, P(ip)]
     lib.afqmc_get_setup.argtypes = [vp, vp, dp, dp]
+    lib.afqmc_profile_enable.argtypes = [vp, ip]
+    lib.afqmc_profile_read.argtypes = [vp, vp, vp]
     lib.afqmc_destroy.argtypes = [vp]
     lib.afqmc_destroy.restype = None
     lib.afqmc_last_error.argtypes = []
@@ -286,6 +295,18 @@ class Hamiltonian:
         v = ctypes.c_int()
         _check(_lib.afqmc_get_status(self._h, _stream_ptr(stream), ctypes.byref(v)))
         return v.value
+
+    def profile_enable(self, max_records: int):
+        """Bracket every kernel phase with HIP events on its stream (0 turns it off)."""
+        _check(_lib.afqmc_profile_enable(self._h, int(max_records)))
+
+    def profile_read(self):
+        """{phase: (total ms, launches)} since the last read; synchronises."""
+        ms = np.zeros(len(PHASES))
+        n = np.zeros(len(PHASES), dtype=np.int32)
+        _check(_lib.afqmc_profile_read(self._h, ms.ctypes.data_as(ctypes.c_void_p),
+                                       n.ctypes.data_as(ctypes.c_void_p)))
+        return {p: (float(ms[i]), int(n[i])) for i, p in enumerate(PHASES)}
 
     def setup(self):
         """(P [N,N], mu, e_shift) as computed at init."""

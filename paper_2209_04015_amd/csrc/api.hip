@@ -70,6 +70,11 @@ struct afqmc_ham {
   int* status = nullptr;
   int ntg = 0;
   std::vector<void*> allocs;
+  // phase timing (afqmc_profile_enable)
+  std::vector<hipEvent_t> ev;
+  int ev_used = 0;
+  struct Rec { int phase, e0, e1; };
+  std::vector<Rec> recs;
   // afqmc_step cache
   const void* c_phi_a = nullptr;
   const void* c_phi_b = nullptr;
@@ -97,6 +102,8 @@ int dalloc_t(afqmc_ham* h, T** p, size_t count) {
 void free_all(afqmc_ham* h) {
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  h->ev.clear();
 }
 
 int check_walkers(const afqmc_ham* h, const afqmc_walkers* w, int nw) {
@@ -115,28 +122,51 @@ int set_device(const afqmc_ham* h) {
   return AFQMC_OK;
 }
 
+// Phase timing: an event before and after each kernel phase, on the call's stream.
+int prof_mark(afqmc_ham* h, hipStream_t s) {
+  if (h->ev.empty() || h->ev_used + 2 > (int)h->ev.size()) return -1;
+  if (hipEventRecord(h->ev[h->ev_used], s) != hipSuccess) return -1;
+  return h->ev_used++;
+}
+void prof_close(afqmc_ham* h, int phase, int e0, hipStream_t s) {
+  if (e0 < 0) return;
+  if (hipEventRecord(h->ev[h->ev_used], s) != hipSuccess) return;
+  h->recs.push_back({phase, e0, h->ev_used++});
+}
+
+#define PHASE(h, ph, s, expr)            \
+  do {                                   \
+    const int e0__ = prof_mark((h), (s)); \
+    HIP_TRY(expr);                       \
+    prof_close((h), (ph), e0__, (s));    \
+  } while (0)
+
 // ---------------------------------------------------------------------------
 // step sequences, per working precision
 // ---------------------------------------------------------------------------
 
 template <typename T>
 int seq_theta(afqmc_ham* h, const afqmc_walkers* w, int nw, bool want_e1, hipStream_t s) {
-  HIP_TRY((launch_gf<T>(h->d, nw, (const double2*)w->phi_a, (const double2*)w->phi_b, h->phiT, h->hh,
-                        (T*)h->theta, h->logdet, want_e1 ? h->e1 : nullptr, h->status, s)));
+  PHASE(h, AFQMC_PH_GREEN, s,
+        (launch_gf<T>(h->d, nw, (const double2*)w->phi_a, (const double2*)w->phi_b, h->phiT, h->hh,
+                      (T*)h->theta, h->logdet, want_e1 ? h->e1 : nullptr, h->status, s)));
   return AFQMC_OK;
 }
 
 template <typename T>
 int seq_force_bias(afqmc_ham* h, int nw, double2* vbias, hipStream_t s) {
-  HIP_TRY((launch_force_bias<T>(h->d, nw, (const T*)h->Lh, (const T*)h->theta, vbias, s)));
+  PHASE(h, AFQMC_PH_FORCE_BIAS, s,
+        (launch_force_bias<T>(h->d, nw, (const T*)h->Lh, (const T*)h->theta, vbias, s)));
   return AFQMC_OK;
 }
 
 template <typename T>
 int seq_energy_from_theta(afqmc_ham* h, int nw, double2* e_out, hipStream_t s) {
   int ntg = 0;
-  HIP_TRY((launch_exchange<T>(h->d, nw, (const T*)h->Lh, (const T*)h->theta, h->part, &ntg, s)));
-  HIP_TRY(launch_energy(h->d, nw, h->e1, h->vbias, h->part, ntg, e_out, s));
+  for (int sp = 0; sp < 2; ++sp)
+    PHASE(h, AFQMC_PH_EXCHANGE, s,
+          (launch_exchange<T>(h->d, nw, (const T*)h->Lh, (const T*)h->theta, h->part, sp, &ntg, s)));
+  PHASE(h, AFQMC_PH_ENERGY, s, launch_energy(h->d, nw, h->e1, h->vbias, h->part, ntg, e_out, s));
   return AFQMC_OK;
 }
 
@@ -144,19 +174,24 @@ int seq_energy_from_theta(afqmc_ham* h, int nw, double2* e_out, hipStream_t s) {
 template <typename T>
 int seq_propagate_core(afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields, hipStream_t s) {
   const StepDims& d = h->d;
-  HIP_TRY((launch_shift<T>(d, nw, h->vbias, fields, (T*)h->xs, h->a, h->tmax, h->sdt, s)));
-  HIP_TRY((launch_vhs<T>(d, nw, (const T*)h->xs, (const T*)h->LT, h->pq, (T*)h->vhs, h->sdt, s)));
-  HIP_TRY(launch_pphi(d, nw, h->P, (const double2*)w->phi_a, (const double2*)w->phi_b, h->acc,
-                      nullptr, nullptr, h->tmax, 0, s));
+  PHASE(h, AFQMC_PH_SHIFT, s,
+        (launch_shift<T>(d, nw, h->vbias, fields, (T*)h->xs, h->a, h->tmax, h->sdt, s)));
+  PHASE(h, AFQMC_PH_VHS, s,
+        (launch_vhs<T>(d, nw, (const T*)h->xs, (const T*)h->LT, h->pq, (T*)h->vhs, h->sdt, s)));
+  PHASE(h, AFQMC_PH_ONE_BODY, s,
+        launch_pphi(d, nw, h->P, (const double2*)w->phi_a, (const double2*)w->phi_b, h->acc, nullptr,
+                    nullptr, h->tmax, 0, s));
   const int order = h->prm.taylor_order;
   T* bufs[2] = {(T*)h->t0, (T*)h->t1};
   for (int k = 1; k <= order; ++k) {
     const T* tin = k == 1 ? nullptr : bufs[(k - 2) & 1];
     T* tout = bufs[(k - 1) & 1];
-    HIP_TRY((launch_taylor<T>(d, nw, (const T*)h->vhs, tin, tout, h->acc, h->tmax, k, order, s)));
+    PHASE(h, AFQMC_PH_TAYLOR, s,
+          (launch_taylor<T>(d, nw, (const T*)h->vhs, tin, tout, h->acc, h->tmax, k, order, s)));
   }
-  HIP_TRY(launch_pphi(d, nw, h->P, nullptr, nullptr, h->acc, (double2*)w->phi_a, (double2*)w->phi_b,
-                      nullptr, 1, s));
+  PHASE(h, AFQMC_PH_ONE_BODY, s,
+        launch_pphi(d, nw, h->P, nullptr, nullptr, h->acc, (double2*)w->phi_a, (double2*)w->phi_b,
+                    nullptr, 1, s));
   return AFQMC_OK;
 }
 
@@ -167,8 +202,9 @@ int seq_propagate(afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields, 
   if ((rc = seq_force_bias<T>(h, nw, h->vbias, s))) return rc;
   if ((rc = seq_propagate_core<T>(h, w, nw, fields, s))) return rc;
   if ((rc = seq_theta<T>(h, w, nw, false, s))) return rc;
-  HIP_TRY(launch_weight(nw, h->logdet, nullptr, h->a, (double2*)w->log_ovlp, w->log_w, h->cst,
-                        h->status, s));
+  PHASE(h, AFQMC_PH_WEIGHT, s,
+        launch_weight(nw, h->logdet, nullptr, h->a, (double2*)w->log_ovlp, w->log_w, h->cst,
+                      h->status, s));
   h->c_valid = false;
   return AFQMC_OK;
 }
@@ -194,10 +230,13 @@ int seq_step(afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields, int d
     if ((rc = seq_force_bias<T>(h, nw, h->vbias, s))) return rc;
   }
   if ((rc = seq_propagate_core<T>(h, w, nw, fields, s))) return rc;
-  if (do_qr) HIP_TRY(launch_qr(h->d, nw, (double2*)w->phi_a, (double2*)w->phi_b, h->corr, h->status, s));
+  if (do_qr)
+    PHASE(h, AFQMC_PH_QR, s,
+          launch_qr(h->d, nw, (double2*)w->phi_a, (double2*)w->phi_b, h->corr, h->status, s));
   if ((rc = seq_theta<T>(h, w, nw, e != nullptr, s))) return rc;
-  HIP_TRY(launch_weight(nw, h->logdet, do_qr ? h->corr : nullptr, h->a, (double2*)w->log_ovlp,
-                        w->log_w, h->cst, h->status, s));
+  PHASE(h, AFQMC_PH_WEIGHT, s,
+        launch_weight(nw, h->logdet, do_qr ? h->corr : nullptr, h->a, (double2*)w->log_ovlp,
+                      w->log_w, h->cst, h->status, s));
   if ((rc = seq_force_bias<T>(h, nw, h->vbias, s))) return rc;
   if (e) {
     if ((rc = seq_energy_from_theta<T>(h, nw, e, s))) return rc;
@@ -258,7 +297,9 @@ int trial_energy_fp64(afqmc_ham* h, const double* Y_a, const double* Y_b, hipStr
                              h->status, s)));
   HIP_TRY((launch_force_bias<double>(d, 1, (const double*)Lh64, (const double*)theta64, h->vbias, s)));
   int ntg = 0;
-  HIP_TRY((launch_exchange<double>(d, 1, (const double*)Lh64, (const double*)theta64, h->part, &ntg, s)));
+  for (int sp = 0; sp < 2; ++sp)
+    HIP_TRY((launch_exchange<double>(d, 1, (const double*)Lh64, (const double*)theta64, h->part, sp,
+                                     &ntg, s)));
   HIP_TRY(launch_energy(d, 1, h->e1, h->vbias, h->part, ntg, e, s));
   double2 he[3];
   HIP_TRY(hipMemcpyAsync(he, e, sizeof he, hipMemcpyDeviceToHost, s));
@@ -520,7 +561,8 @@ int afqmc_orthogonalise(afqmc_ham* h, afqmc_walkers* w, int nw, void* stream) {
   if (rc || nw == 0) return rc;
   if ((rc = set_device(h))) return rc;
   hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(launch_qr(h->d, nw, (double2*)w->phi_a, (double2*)w->phi_b, h->corr, h->status, s));
+  PHASE(h, AFQMC_PH_QR, s,
+        launch_qr(h->d, nw, (double2*)w->phi_a, (double2*)w->phi_b, h->corr, h->status, s));
   HIP_TRY(launch_ortho_update(nw, h->corr, (double2*)w->log_ovlp, s));
   // theta is invariant under re-orthogonalisation; the cached force bias stays valid.
   return AFQMC_OK;
@@ -565,6 +607,45 @@ int afqmc_get_setup(afqmc_ham* h, double* host_P, double* mu, double* e_shift) {
   }
   if (mu) *mu = h->mu;
   if (e_shift) *e_shift = h->e_shift;
+  return AFQMC_OK;
+}
+
+int afqmc_profile_enable(afqmc_ham* h, int max_records) {
+  if (!h) return fail(AFQMC_EINVAL, "null Hamiltonian handle");
+  if (max_records < 0) return fail(AFQMC_EINVAL, "max_records must be >= 0");
+  int rc;
+  if ((rc = set_device(h))) return rc;
+  HIP_TRY(hipDeviceSynchronize());
+  for (hipEvent_t e : h->ev) HIP_TRY(hipEventDestroy(e));
+  h->ev.clear();
+  h->recs.clear();
+  h->ev_used = 0;
+  for (int i = 0; i < 2 * max_records; ++i) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    h->ev.push_back(e);
+  }
+  h->recs.reserve(max_records);
+  return AFQMC_OK;
+}
+
+int afqmc_profile_read(afqmc_ham* h, double* ms, int* launches) {
+  if (!h || !ms || !launches) return fail(AFQMC_EINVAL, "null argument");
+  int rc;
+  if ((rc = set_device(h))) return rc;
+  for (int p = 0; p < AFQMC_NPHASE; ++p) {
+    ms[p] = 0.0;
+    launches[p] = 0;
+  }
+  for (const auto& r : h->recs) {
+    HIP_TRY(hipEventSynchronize(h->ev[r.e1]));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, h->ev[r.e0], h->ev[r.e1]));
+    ms[r.phase] += t;
+    launches[r.phase] += 1;
+  }
+  h->recs.clear();
+  h->ev_used = 0;
   return AFQMC_OK;
 }
 

@@ -63,9 +63,10 @@ hipError_t launch_overlap_store(int W, const double2* logdet, double2* log_ovlp,
 
 template <typename T>
 ExTile exchange_tile(int n);
+// one spin (sp = 0 alpha, 1 beta) of the exchange energy; part[s][g-tile][z]
 template <typename T>
 hipError_t launch_exchange(const StepDims& d, int W, const T* Lh, const T* theta, double2* part,
-                           int* ntg_out, hipStream_t s);
+                           int sp, int* ntg_out, hipStream_t s);
 
 hipError_t launch_energy(const StepDims& d, int W, const double2* e1, const double2* vbias,
                          const double2* part, int ntg, double2* e_out, hipStream_t s);

