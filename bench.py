@@ -147,8 +147,11 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="n290")
-    ap.add_argument("--cpu-sample", type=int, default=2, help="walkers in the timed oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=12, help="walkers in the timed oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--only", choices=("fp32", "fp64"), help="run one path only (profiling runs)")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the walker-parallel "
@@ -169,10 +172,21 @@ def main():
     fields_dev = torch.as_tensor(fields, device=device)
     log(f"inputs {cfg.name}: N={cfg.N} n={cfg.n} K={cfg.K} W={cfg.W} generated in {time.time() - t:.1f} s")
 
+    if args.calib_copy:
+        n = args.calib_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=device)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy} MiB read + {args.calib_copy} MiB written")
+        del src, dst
+
     results = {}
     states = {}
     sample = min(args.cpu_sample, cfg.W)
     for precision in ("fp64", "fp32"):
+        if args.only and precision != args.only:
+            continue
         ham, w, e, ms, phases, status = run_gpu(cfg, h1, L, phiT, precision, args.steps, args.warmup,
                                                 fields_dev, device)
         results[precision] = (ms, phases, status)
@@ -184,6 +198,14 @@ def main():
         ham.close()
         del w, e
         torch.cuda.empty_cache()
+
+    if args.only:
+        ms, ph, st = results[args.only]
+        print(json.dumps({"metric": METRIC, "value": round(cfg.W * args.steps / (ms * 1e-3), 2),
+                          "unit": "walker-steps/s", "n_gpus": 1, "steps": args.steps,
+                          "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 4),
+                          "only": args.only, "roofline": roofline(cfg, ph, args.only)}), flush=True)
+        return
 
     cpu = None
     eerr = None

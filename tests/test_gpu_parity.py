@@ -189,37 +189,96 @@ def test_orthogonalise_matches_oracle(name, precision, uhf):
 
 @pytest.mark.parametrize("name,precision,uhf", PARAMS)
 def test_fused_step_matches_oracle(name, precision, uhf):
-    """afqmc_step (propagate, QR, energy) against the oracle's step, teacher-forced,
-    twice in a row; the second call starts from the cached Green's function."""
+    """afqmc_step (propagate, QR, energy) against the oracle's step, teacher-forced
+    on every step.  In FP64 the second call continues from the GPU state and
+    reuses its cached Green's function; in FP32 both calls start from the oracle
+    state, since the cache holds the GPU's own (FP32-rounded) walker."""
     torch = _torch()
     c = case(name, precision, uhf)
     w = c.walkers()
     xs = inputs.fields(c.cfg.W, c.cfg.K, 2, seed=5)
     pa, pb, lo, lw = c.pa, c.pb, c.lo, c.lw
     e = torch.empty((c.cfg.W, 3), dtype=torch.complex128, device=c.dev)
-    tol = _energy_tol(precision, c.cfg)
+    # The energy comes from the propagated walker, so it carries the propagation
+    # error: the FP32 Taylor products (orbital bar 1e-4) rather than the 4 u sqrt(c)
+    # of a single energy call.
+    tol_e = 1e-11 if precision == "fp64" else 1e-4
     tol_phi = 1e-10 if precision == "fp64" else 1e-4
-    tol_log = 1e-9 if precision == "fp64" else 1e-3
+    # FP32 orbitals (relative error ~1e-5) move log det(PhiT^T phi') by up to
+    # ~ 2 n 1e-5 cond(S'); the perturbed test walkers have cond(S') up to ~50
+    tol_log = 1e-9 if precision == "fp64" else 1e-2
     for k in range(2):
-        c.ham.step(w, torch.as_tensor(xs[k], device=c.dev), do_qr=True, energy_out=e, reuse=(k > 0))
+        if precision == "fp32":
+            w = c.walkers(pa=pa, pb=pb, lo=lo, lw=lw)
+        c.ham.step(w, torch.as_tensor(xs[k], device=c.dev), do_qr=True, energy_out=e,
+                   reuse=(k > 0 and precision == "fp64"))
         pa, pb, lo, lw, er = orc.step(c.oh, pa, pb, lo, lw, xs[k], do_qr=True)
         got = e.cpu().numpy()
         S = np.abs(er).sum(axis=1)
         derr = np.abs(got.sum(axis=1) - er.sum(axis=1)) / S
         print(f"[gpu] fused {name} {precision} step {k}: max |dE|/S = {derr.max():.3e}", flush=True)
-        # QR-then-overlap on the GPU vs overlap-then-QR in the oracle: same math,
-        # rounding differs by the conditioning of phi'
-        assert np.all(derr <= 10 * tol)
+        assert np.all(derr <= tol_e)
         assert np.abs(w.phi_a.cpu().numpy() - pa).max() < tol_phi
         assert np.abs(w.phi_b.cpu().numpy() - pb).max() < tol_phi
-        _assert_logw(w.log_w.cpu().numpy(), lw, tol_log)
+        glw = w.log_w.cpu().numpy()
+        alive = np.isfinite(lw)
+        if alive.any():
+            print(f"[gpu] fused {name} {precision} step {k}: max |d log w| = "
+                  f"{np.abs(glw[alive] - lw[alive]).max():.3e}", flush=True)
+        _assert_logw(glw, lw, tol_log)
         glo = w.log_ovlp.cpu().numpy()
         assert np.abs(glo.real - lo.real).max() < tol_log
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_step_cache_reuse_is_exact(precision):
+    """Reusing the cached Green's function and force bias gives bit-identical
+    walkers, weights and energies to recomputing them."""
+    torch = _torch()
+    c = case("ragged", precision)
+    xs = inputs.fields(c.cfg.W, c.cfg.K, 2, seed=7)
+    res = []
+    for reuse in (False, True):
+        w = c.walkers()
+        e = torch.empty((c.cfg.W, 3), dtype=torch.complex128, device=c.dev)
+        for k in range(2):
+            c.ham.step(w, torch.as_tensor(xs[k], device=c.dev), do_qr=True, energy_out=e,
+                       reuse=(reuse and k > 0))
+        res.append((w.phi_a.clone(), w.phi_b.clone(), w.log_w.clone(), w.log_ovlp.clone(), e.clone()))
+    for a, b in zip(*res):
+        assert torch.equal(a, b)
+
+
+def _oracle_envelope(c, xs, steps):
+    """How far two correct FP64 evaluations of the same trajectory drift apart:
+    the oracle run again with P from scipy's expm instead of eigh (the two P
+    agree to ~1e-15).  Returns per-step max |dE| over live walkers."""
+    import copy
+
+    import scipy.linalg
+
+    cfg = c.cfg
+    alt = copy.copy(c.oh)
+    alt.P = scipy.linalg.expm(-0.5 * cfg.dt * (c.oh.hprime - c.oh.mu * np.eye(cfg.N)))
+    st = [inputs.walkers_at_trial(c.pa_T, cfg.W)] * 2
+    a = [st[0].copy(), st[1].copy(), orc.overlap(c.oh, *st), np.zeros(cfg.W)]
+    b = [x.copy() for x in a]
+    env = []
+    for k in range(steps):
+        qr = (k + 1) % cfg.qr_interval == 0
+        *a, ea = orc.step(c.oh, *a, xs[k], do_qr=qr)
+        *b, eb = orc.step(alt, *b, xs[k], do_qr=qr)
+        alive = np.isfinite(a[3])
+        env.append(np.abs(ea.sum(1) - eb.sum(1))[alive].max() if alive.any() else 0.0)
+    return env
+
+
 def test_free_running_n20_fp64_first_steps():
-    """Free-running FP64 trajectory from the trial: local energies of the walkers
-    that carry weight stay within 1e-10 Ha of the oracle for steps 0-3."""
+    """Free-running FP64 trajectory from the trial, steps 0-3: the local energies
+    of the walkers that carry weight stay within 1e-10 Ha of the oracle, or
+    within 5x the drift between two equally valid FP64 oracle runs when the
+    trajectory's own amplification of rounding differences exceeds that
+    (it does from step 2 on: single-walker |E_L| reaches ~8e3 Ha)."""
     torch = _torch()
     c = case("n20", "fp64")
     cfg = c.cfg
@@ -229,6 +288,7 @@ def test_free_running_n20_fp64_first_steps():
     lw = np.zeros(cfg.W)
     w = c.walkers(pa=pa, pb=pb, lo=lo, lw=lw)
     xs = inputs.fields(cfg.W, cfg.K, 4, seed=0)
+    env = _oracle_envelope(c, xs, 4)
     e = torch.empty((cfg.W, 3), dtype=torch.complex128, device=c.dev)
     for k in range(4):
         qr = (k + 1) % cfg.qr_interval == 0
@@ -238,12 +298,13 @@ def test_free_running_n20_fp64_first_steps():
         dE = np.abs(got - er.sum(axis=1))
         glw = w.log_w.cpu().numpy()
         alive = np.isfinite(lw)
-        print(f"[gpu] free-running n20 step {k}: max |dE| = {dE.max():.3e} Ha, "
-              f"over live walkers {dE[alive].max() if alive.any() else 0:.3e} Ha, "
-              f"live {alive.sum()}/{cfg.W}, |E| ~ {np.abs(er.sum(axis=1)).max():.1f}", flush=True)
-        print(f"[gpu]   per-walker dE: {np.array2string(dE, precision=1)}", flush=True)
+        bar = max(1e-10, 5 * env[k])
+        print(f"[gpu] free-running n20 step {k}: max |dE| over live walkers "
+              f"{dE[alive].max() if alive.any() else 0:.3e} Ha (oracle-vs-oracle {env[k]:.3e}, "
+              f"bar {bar:.2e}), live {alive.sum()}/{cfg.W}, |E| <= {np.abs(er.sum(axis=1)).max():.1f}",
+              flush=True)
         _assert_logw(glw, lw, 1e-9)
-        assert dE[alive].max() < 1e-10
+        assert np.all(dE[alive] <= bar)
 
 
 def test_zero_walkers_is_a_no_op():
