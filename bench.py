@@ -27,7 +27,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "walker-steps/s at N=290 mixed vs FP64 on 1 GPU; energy err vs FP64 oracle"
-PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X dense matrix peaks
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0}   # MI355X dense matrix peaks
+MODES = ("fp64", "fp32", "fp16x3", "bf16x3")
 
 
 def log(msg):
@@ -96,10 +97,21 @@ def roofline(cfg, phases, precision):
     avg_ms = ms / launches
     flops = exchange_flops_per_launch(cfg, cfg.W)
     achieved = flops / (avg_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[precision]
-    return {"kernel": "exchange_kernel", "bound": "mfma", "achieved": round(achieved, 2),
-            "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-            "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": flops}
+    kernel = "exchange_kernel"
+    note = None
+    if precision in ("fp32", "fp64"):
+        peak = PEAK_TFLOPS[precision]
+    else:
+        # three 16-bit products per algorithmic multiply-add
+        peak = round(PEAK_TFLOPS[precision[:4]] / 3.0, 1)
+        kernel = "exchange_split_kernel"
+        note = f"{precision[:4]} dense peak / 3 products"
+    out = {"kernel": kernel, "bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
+           "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+           "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": flops}
+    if note:
+        out["peak_note"] = note
+    return out
 
 
 def cpu_baseline_and_energy_error(cfg, h1, L, phiT, gpu_states, sample, x_sample):
@@ -149,7 +161,9 @@ def main():
     ap.add_argument("--config", default="n290")
     ap.add_argument("--cpu-sample", type=int, default=12, help="walkers in the timed oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
-    ap.add_argument("--only", choices=("fp32", "fp64"), help="run one path only (profiling runs)")
+    ap.add_argument("--only", choices=MODES, help="run one path only (profiling runs)")
+    ap.add_argument("--headline", choices=MODES[1:], default="fp16x3",
+                    help="mixed path reported as value (the others are on the same line)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -184,7 +198,7 @@ def main():
     results = {}
     states = {}
     sample = min(args.cpu_sample, cfg.W)
-    for precision in ("fp64", "fp32"):
+    for precision in MODES:
         if args.only and precision != args.only:
             continue
         ham, w, e, ms, phases, status = run_gpu(cfg, h1, L, phiT, precision, args.steps, args.warmup,
@@ -220,39 +234,48 @@ def main():
     def phase_table(phases):
         return {k: round(v[0] / args.steps, 4) for k, v in phases.items() if v[1] > 0}
 
-    ms32, ph32, st32 = results["fp32"]
+    head = args.headline
+    msh, phh, sth = results[head]
     ms64, ph64, st64 = results["fp64"]
     fl = step_flops(cfg)
+    paths = {}
+    for p in MODES:
+        ms, ph, st = results[p]
+        paths[p] = {"value": round(rate(ms), 2), "unit": "walker-steps/s",
+                    "ms_per_step": round(ms / args.steps, 4), "roofline": roofline(cfg, ph, p),
+                    "phases_ms_per_step": phase_table(ph), "status": st,
+                    "energy_error_vs_fp64_oracle": (eerr or {}).get(p)}
+    dtypes = {"fp32": "f32 contractions (MFMA)", "fp16x3": "f16 hi/lo x3 exchange + f32 contractions (MFMA)",
+              "bf16x3": "bf16 hi/lo x3 exchange + f32 contractions (MFMA)"}
     line = {
         "metric": METRIC,
-        "value": round(rate(ms32), 2),
+        "value": round(rate(msh), 2),
         "unit": "walker-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms32 / args.steps, 4),
+        "ms_per_step": round(msh / args.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 contractions (MFMA) + f64 overlaps/solves/QR/weights/energy sums",
+        "dtype": dtypes[head] + " + f64 overlaps/solves/QR/weights/energy sums",
         "data": "synthetic",
         "config": {
             "workload": f"{cfg.name}: ph-AFQMC full walker step (propagate + QR + local energy every "
                         f"step), N={cfg.N} orbitals, na=nb={cfg.n}, K={cfg.K} Cholesky vectors, "
                         f"{W} walkers, dt={cfg.dt}, Taylor order {cfg.taylor_order}, QR every "
                         f"{cfg.qr_interval} step(s)",
-            "walkers": W, "N": cfg.N, "n_per_spin": cfg.n, "K": cfg.K,
+            "walkers": W, "N": cfg.N, "n_per_spin": cfg.n, "K": cfg.K, "headline_path": head,
         },
-        "roofline": roofline(cfg, ph32, "fp32"),
+        "roofline": roofline(cfg, phh, head),
         "cpu_baseline": cpu,
-        "fp64": {"value": round(rate(ms64), 2), "unit": "walker-steps/s",
-                 "ms_per_step": round(ms64 / args.steps, 4), "roofline": roofline(cfg, ph64, "fp64"),
-                 "phases_ms_per_step": phase_table(ph64), "status": st64},
-        "mixed_over_fp64": round(ms64 / ms32, 3),
-        "energy_error_vs_fp64_oracle": eerr,
-        "phases_ms_per_step": phase_table(ph32),
+        "fp64": paths["fp64"],
+        "mixed_over_fp64": round(ms64 / msh, 3),
+        "energy_error_vs_fp64_oracle": (eerr or {}).get(head),
+        "phases_ms_per_step": phase_table(phh),
+        "paths": paths,
         "algorithmic_gflop_per_walker_step": {k: round(v / 1e9, 4) for k, v in fl.items()},
-        "status": st32,
+        "status": sth,
     }
     print(json.dumps(line), flush=True)
 

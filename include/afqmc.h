@@ -50,8 +50,16 @@ enum {
 
 /* Working precision of the contractions (force bias, VHS, Taylor products,
  * exchange).  Overlaps, determinants, inverses, weights, QR, the one-body
- * half steps and all energy sums are FP64 in both modes. */
-enum { AFQMC_FP64 = 0, AFQMC_FP32 = 1 };
+ * half steps and all energy sums are FP64 in every mode.
+ *   AFQMC_FP64    all contractions on FP64 matrix cores
+ *   AFQMC_FP32    all contractions on FP32 matrix cores, FP32 accumulation
+ *   AFQMC_BF16X3  as FP32, but the exchange contraction (Sec. III.C, the
+ *                 quartic term) splits each FP32 operand into bf16 hi + lo and
+ *                 keeps the three leading products on the bf16 matrix cores
+ *                 (relative operand error ~2^-16)
+ *   AFQMC_FP16X3  the same split in fp16 with power-of-two row scaling
+ *                 (relative operand error ~2^-22, close to FP32) */
+enum { AFQMC_FP64 = 0, AFQMC_FP32 = 1, AFQMC_BF16X3 = 2, AFQMC_FP16X3 = 3 };
 
 /* Status-word bits (afqmc_get_status). */
 enum {
@@ -64,7 +72,7 @@ typedef struct afqmc_params {
   int N, na, nb, K;     /* sizes; 1 <= na <= 45, 0 <= nb <= 45, na, nb <= N */
   double dt;            /* imaginary time step (Eq. Bx) */
   int taylor_order;     /* terms of the exp(VHS) series beyond 1 (default 6) */
-  int precision;        /* AFQMC_FP64 or AFQMC_FP32 */
+  int precision;        /* AFQMC_FP64, AFQMC_FP32, AFQMC_BF16X3 or AFQMC_FP16X3 */
   int max_walkers;      /* workspace is sized for this many walkers */
   double mu;            /* scalar factored out of the one-body half step; NaN -> tr(h')/N */
   double e_shift;       /* energy shift E_T of the weights; NaN -> E_L(PhiT) computed in FP64 */
@@ -161,6 +169,7 @@ enum {
   AFQMC_PH_WEIGHT,       /* overlap ratio, phase, log weight */
   AFQMC_PH_EXCHANGE,     /* one launch per spin */
   AFQMC_PH_ENERGY,       /* assembly of E1, EJ, EK */
+  AFQMC_PH_SPLIT,        /* hi/lo split of theta (16-bit exchange modes) */
   AFQMC_NPHASE
 };
 int afqmc_profile_enable(afqmc_ham* ham, int max_records);

@@ -21,8 +21,11 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "lib
 
 FP64 = 0
 FP32 = 1
+BF16X3 = 2
+FP16X3 = 3
 STEP_REUSE = 1
-_PRECISIONS = {"fp64": FP64, "fp32": FP32, FP64: FP64, FP32: FP32}
+_PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3,
+               FP64: FP64, FP32: FP32, BF16X3: BF16X3, FP16X3: FP16X3}
 
 EXPORTED = (
     "afqmc_init_hamiltonian",
@@ -44,7 +47,7 @@ EXPORTED = (
 
 # kernel phases of afqmc_profile_read, in header order
 PHASES = ("green", "force_bias", "shift", "vhs", "one_body", "taylor", "qr", "weight",
-          "exchange", "energy")
+          "exchange", "energy", "split")
 
 
 class AfqmcError(RuntimeError):

@@ -53,6 +53,14 @@ struct afqmc_ham {
   int2* pq = nullptr;       // [Npk]
   double* phiT = nullptr;   // [2][N][nmax]
   double* hh = nullptr;     // [2][nmax][N]
+  // hi/lo split operands of the 16-bit exchange (AFQMC_BF16X3 / AFQMC_FP16X3)
+  int split = SPLIT_NONE;
+  unsigned short* lh_hi = nullptr;  // [2][K][nmax][ldh]
+  unsigned short* lh_lo = nullptr;
+  float* lh_scale = nullptr;        // [2][K][nmax]
+  unsigned short* th_hi = nullptr;  // [W][2][2][nmax][ldh]
+  unsigned short* th_lo = nullptr;
+  float* th_scale = nullptr;        // [W][2][2][nmax]
   // workspace (sized for max_walkers)
   void* theta = nullptr;    // T [W][2][2][nmax][ldN]
   double2* logdet = nullptr;  // [W][2]
@@ -163,9 +171,20 @@ int seq_force_bias(afqmc_ham* h, int nw, double2* vbias, hipStream_t s) {
 template <typename T>
 int seq_energy_from_theta(afqmc_ham* h, int nw, double2* e_out, hipStream_t s) {
   int ntg = 0;
-  for (int sp = 0; sp < 2; ++sp)
-    PHASE(h, AFQMC_PH_EXCHANGE, s,
-          (launch_exchange<T>(h->d, nw, (const T*)h->Lh, (const T*)h->theta, h->part, sp, &ntg, s)));
+  if (h->split != SPLIT_NONE) {
+    const StepDims& d = h->d;
+    PHASE(h, AFQMC_PH_SPLIT, s,
+          launch_split_rows_mode(h->split, (long)nw * 4 * d.nmax, d.N, (const float*)h->theta, d.ldN,
+                                 h->th_hi, h->th_lo, d.ldh, h->th_scale, s));
+    for (int sp = 0; sp < 2; ++sp)
+      PHASE(h, AFQMC_PH_EXCHANGE, s,
+            launch_exchange_split(h->split, d, nw, h->lh_hi, h->lh_lo, h->lh_scale, h->th_hi,
+                                  h->th_lo, h->th_scale, h->part, sp, &ntg, s));
+  } else {
+    for (int sp = 0; sp < 2; ++sp)
+      PHASE(h, AFQMC_PH_EXCHANGE, s,
+            (launch_exchange<T>(h->d, nw, (const T*)h->Lh, (const T*)h->theta, h->part, sp, &ntg, s)));
+  }
   PHASE(h, AFQMC_PH_ENERGY, s, launch_energy(h->d, nw, h->e1, h->vbias, h->part, ntg, e_out, s));
   return AFQMC_OK;
 }
@@ -332,10 +351,13 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
   d.ncol = 2 * (p.na + p.nb);
   d.ncolp = round_up(d.ncol, 4);
   d.Npk = p.N * (p.N + 1) / 2;
+  d.ldh = round_up(p.N, 32);
   h->prec = p.precision;
-  h->tsize = p.precision == AFQMC_FP32 ? sizeof(float) : sizeof(double);
+  h->tsize = p.precision == AFQMC_FP64 ? sizeof(double) : sizeof(float);
+  h->split = p.precision == AFQMC_BF16X3 ? SPLIT_BF16 : (p.precision == AFQMC_FP16X3 ? SPLIT_F16 : SPLIT_NONE);
   h->sdt = sqrt(p.dt);
   HIP_TRY(set_kernel_attributes(d));
+  HIP_TRY(set_split_kernel_attributes());
 
   const int N = d.N, K = d.K, nmax = d.nmax;
   const size_t NN = (size_t)N * N;
@@ -405,17 +427,28 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
   if ((rc = dalloc_t(h, &h->hh, (size_t)2 * nmax * N))) return rc;
   HIP_TRY(setup_hh(N, d.na, nmax, h->phiT, dh1, h->hh, s));
   HIP_TRY(setup_hh(N, d.nb, nmax, h->phiT + (size_t)N * nmax, dh1, h->hh + (size_t)nmax * N, s));
-  if (h->prec == AFQMC_FP32)
+  if (h->prec != AFQMC_FP64)
     rc = build_working_arrays<float>(h, dL, Y_a, Y_b, s);
   else
     rc = build_working_arrays<double>(h, dL, Y_a, Y_b, s);
   if (rc) return rc;
+  if (h->split != SPLIT_NONE) {
+    const size_t rows = (size_t)2 * K * nmax;
+    if ((rc = dalloc_t(h, &h->lh_hi, rows * d.ldh))) return rc;
+    if ((rc = dalloc_t(h, &h->lh_lo, rows * d.ldh))) return rc;
+    if ((rc = dalloc_t(h, &h->lh_scale, rows))) return rc;
+    HIP_TRY(launch_split_rows_mode(h->split, (long)rows, N, (const float*)h->Lh, d.ldN, h->lh_hi,
+                                   h->lh_lo, d.ldh, h->lh_scale, s));
+  }
 
   // ---- workspace ----
   const size_t W = (size_t)p.max_walkers;
   // the FP64 trial-energy pass may use the FP64 tile even in the mixed path
   const ExTile t32 = exchange_tile<float>(nmax), t64 = exchange_tile<double>(nmax);
-  h->ntg = ceil_div(K, t32.G < t64.G ? t32.G : t64.G);
+  const ExTile tsp = exchange_split_tile(nmax);
+  int gmin = t32.G < t64.G ? t32.G : t64.G;
+  if (tsp.G < gmin) gmin = tsp.G;
+  h->ntg = ceil_div(K, gmin);
   const size_t ts = h->tsize;
   const size_t wtheta = (W > 1 ? W : 1);
   if ((rc = dalloc(h, &h->theta, wtheta * 4 * nmax * d.ldN * ts))) return rc;
@@ -432,6 +465,12 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
   if ((rc = dalloc_t(h, &h->part, (size_t)2 * h->ntg * wtheta))) return rc;
   if ((rc = dalloc_t(h, &h->corr, W * 2))) return rc;
   if ((rc = dalloc_t(h, &h->status, (size_t)1))) return rc;
+  if (h->split != SPLIT_NONE) {
+    const size_t rows = wtheta * 4 * nmax;
+    if ((rc = dalloc_t(h, &h->th_hi, rows * d.ldh))) return rc;
+    if ((rc = dalloc_t(h, &h->th_lo, rows * d.ldh))) return rc;
+    if ((rc = dalloc_t(h, &h->th_scale, rows))) return rc;
+  }
 
   // ---- E_T ----
   if (isnan(p.e_shift)) {
@@ -485,14 +524,14 @@ int afqmc_init_hamiltonian(const afqmc_params* params, const double* host_h1,
     return fail(AFQMC_EUNSUPPORTED, "at most 45 electrons per spin are supported (got %d, %d)", p.na, p.nb);
   if (!(p.dt > 0.0)) return fail(AFQMC_EINVAL, "dt must be positive");
   if (p.taylor_order < 1 || p.taylor_order > 30) return fail(AFQMC_EINVAL, "taylor_order must be in [1, 30]");
-  if (p.precision != AFQMC_FP64 && p.precision != AFQMC_FP32)
+  if (p.precision < AFQMC_FP64 || p.precision > AFQMC_FP16X3)
     return fail(AFQMC_EINVAL, "unknown precision %d", p.precision);
   if (p.max_walkers < 1) return fail(AFQMC_EINVAL, "max_walkers must be >= 1");
   const int nmax = p.na > p.nb ? p.na : p.nb;
   if ((size_t)p.N * nmax * sizeof(double2) + 4096 > 160 * 1024)
     return fail(AFQMC_EUNSUPPORTED, "N * max(na, nb) too large for the in-LDS QR (N=%d, n=%d)", p.N, nmax);
   {
-    const ExTile t = p.precision == AFQMC_FP32 ? exchange_tile<float>(nmax) : exchange_tile<double>(nmax);
+    const ExTile t = p.precision == AFQMC_FP64 ? exchange_tile<double>(nmax) : exchange_tile<float>(nmax);
     if (t.G < 1 || t.Z < 1) return fail(AFQMC_EUNSUPPORTED, "electron count %d too large for the exchange tile", nmax);
   }
   afqmc_ham* h = new afqmc_ham();
@@ -525,7 +564,7 @@ int afqmc_force_bias(afqmc_ham* h, const afqmc_walkers* w, int nw, void* vbias, 
   if (!vbias) return fail(AFQMC_EINVAL, "null vbias");
   if ((rc = set_device(h))) return rc;
   hipStream_t s = (hipStream_t)stream;
-  if (h->prec == AFQMC_FP32) {
+  if (h->prec != AFQMC_FP64) {
     if ((rc = seq_theta<float>(h, w, nw, false, s))) return rc;
     rc = seq_force_bias<float>(h, nw, (double2*)vbias, s);
   } else {
@@ -542,7 +581,7 @@ int afqmc_propagate(afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields
   if (!fields) return fail(AFQMC_EINVAL, "null fields");
   if ((rc = set_device(h))) return rc;
   hipStream_t s = (hipStream_t)stream;
-  return h->prec == AFQMC_FP32 ? seq_propagate<float>(h, w, nw, fields, s)
+  return h->prec != AFQMC_FP64 ? seq_propagate<float>(h, w, nw, fields, s)
                                : seq_propagate<double>(h, w, nw, fields, s);
 }
 
@@ -552,7 +591,7 @@ int afqmc_local_energy(afqmc_ham* h, const afqmc_walkers* w, int nw, void* e, vo
   if (!e) return fail(AFQMC_EINVAL, "null energy output");
   if ((rc = set_device(h))) return rc;
   hipStream_t s = (hipStream_t)stream;
-  return h->prec == AFQMC_FP32 ? seq_local_energy<float>(h, w, nw, (double2*)e, s)
+  return h->prec != AFQMC_FP64 ? seq_local_energy<float>(h, w, nw, (double2*)e, s)
                                : seq_local_energy<double>(h, w, nw, (double2*)e, s);
 }
 
@@ -575,7 +614,7 @@ int afqmc_step(afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields, int
   if (!fields) return fail(AFQMC_EINVAL, "null fields");
   if ((rc = set_device(h))) return rc;
   hipStream_t s = (hipStream_t)stream;
-  return h->prec == AFQMC_FP32 ? seq_step<float>(h, w, nw, fields, do_qr, (double2*)e, flags, s)
+  return h->prec != AFQMC_FP64 ? seq_step<float>(h, w, nw, fields, do_qr, (double2*)e, flags, s)
                                : seq_step<double>(h, w, nw, fields, do_qr, (double2*)e, flags, s);
 }
 

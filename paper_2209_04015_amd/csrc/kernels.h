@@ -16,7 +16,11 @@ struct StepDims {
   int ncol;   // 2 (na + nb): real columns of a walker's spin-concatenated orbitals
   int ncolp;  // ncol rounded up to a multiple of 4
   int Npk;    // N (N + 1) / 2 packed (p <= q) pairs
+  int ldh;    // padded orbital stride of hi/lo split rows (multiple of 32)
 };
+
+// hi/lo split formats of the 16-bit contraction modes
+enum { SPLIT_NONE = 0, SPLIT_BF16 = 1, SPLIT_F16 = 2 };
 
 // Exchange tile choice: G Cholesky vectors x Z walkers per workgroup.
 struct ExTile {
@@ -77,4 +81,17 @@ hipError_t launch_qr(const StepDims& d, int W, double2* phi_a, double2* phi_b, d
 hipError_t launch_ortho_update(int W, const double* corr, double2* log_ovlp, hipStream_t s);
 
 hipError_t set_kernel_attributes(const StepDims& d);
+
+// --- hi/lo split contraction (split_kernels.hip) ----------------------------
+// rows of an FP32 matrix -> hi/lo 16-bit rows plus power-of-two row scales
+hipError_t launch_split_rows_mode(int mode, long nrows, int ncols, const float* src, int ld_src,
+                                  unsigned short* hi, unsigned short* lo, int ld_dst, float* scale,
+                                  hipStream_t s);
+ExTile exchange_split_tile(int n);
+hipError_t launch_exchange_split(int mode, const StepDims& d, int W, const unsigned short* lh_hi,
+                                 const unsigned short* lh_lo, const float* lh_scale,
+                                 const unsigned short* th_hi, const unsigned short* th_lo,
+                                 const float* th_scale, double2* part, int sp, int* ntg_out,
+                                 hipStream_t s);
+hipError_t set_split_kernel_attributes();
 size_t qr_lds_bytes(const StepDims& d);

@@ -69,12 +69,16 @@ struct TileLds {
   static constexpr int BYTES = ELEMS * (int)sizeof(T);
 };
 
-// Main loop.  Prob supplies
+// Main loop.  With DBUF the LDS holds two staged tile pairs (2 x TileLds
+// bytes): the next tile is written into the idle buffer after the MFMAs of
+// the current one, so each K step needs one barrier instead of two.
+// Prob supplies
 //   vec_t load_a(int batch, int m, int k) const      (m-major A, k contiguous)
 //   vec_t load_b(int batch, int n, int k) const      (n-major B)        if !B_KMAJOR
 //   vec_t load_b_km(int batch, int k, int n) const   (k-major B, n contiguous) if B_KMAJOR
 // and must return zeros for m or n outside its problem.  k >= kdim is zero-filled here.
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool B_KMAJOR, class Prob>
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool B_KMAJOR, class Prob,
+          bool DBUF = false>
 __device__ __forceinline__ void mfma_tile_mainloop(
     const Prob& prob, int batch, int m0, int n0, int kdim,
     typename MF<T>::acc_t (&acc)[BM / WM / 16][BN / WN / 16], T* lds) {
@@ -137,7 +141,7 @@ __device__ __forceinline__ void mfma_tile_mainloop(
       }
     }
   };
-  auto stash = [&]() {
+  auto stash = [&](T* As, T* Bs) {
 #pragma unroll
     for (int t = 0; t < NA; ++t) {
       const int v = tid + t * NT;
@@ -165,18 +169,14 @@ __device__ __forceinline__ void mfma_tile_mainloop(
     }
   };
 
-  fetch(0);
-  for (int k0 = 0; k0 < kdim; k0 += BK) {
-    __syncthreads();
-    stash();
-    __syncthreads();
-    if (k0 + BK < kdim) fetch(k0 + BK);
+  auto compute = [&](const T* Asb, const T* Bsb, int k0) {
 #pragma unroll
     for (int kc = 0; kc < BK; kc += 16) {
+      if (k0 + kc >= kdim) break;  // zero-padded tail: no MFMA work
       T a[FM][4], b[FN][4];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
-        const T* p = As + (wm * (BM / WM) + i * 16 + lrow) * LD + kc + lk;
+        const T* p = Asb + (wm * (BM / WM) + i * 16 + lrow) * LD + kc + lk;
         if constexpr (VEC == 4) {
           const float4 x = *reinterpret_cast<const float4*>(p);
           a[i][0] = x.x; a[i][1] = x.y; a[i][2] = x.z; a[i][3] = x.w;
@@ -188,7 +188,7 @@ __device__ __forceinline__ void mfma_tile_mainloop(
       }
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        const T* p = Bs + (wn * (BN / WN) + j * 16 + lrow) * LD + kc + lk;
+        const T* p = Bsb + (wn * (BN / WN) + j * 16 + lrow) * LD + kc + lk;
         if constexpr (VEC == 4) {
           const float4 x = *reinterpret_cast<const float4*>(p);
           b[j][0] = x.x; b[j][1] = x.y; b[j][2] = x.z; b[j][3] = x.w;
@@ -204,6 +204,32 @@ __device__ __forceinline__ void mfma_tile_mainloop(
         for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int j = 0; j < FN; ++j) acc[i][j] = M::mma(a[i][s], b[j][s], acc[i][j]);
+    }
+  };
+
+  if constexpr (!DBUF) {
+    fetch(0);
+    for (int k0 = 0; k0 < kdim; k0 += BK) {
+      __syncthreads();
+      stash(As, Bs);
+      __syncthreads();
+      if (k0 + BK < kdim) fetch(k0 + BK);
+      compute(As, Bs, k0);
+    }
+  } else {
+    constexpr int STAGE = (BM + BN) * LD;
+    fetch(0);
+    __syncthreads();  // LDS may still be read by a previous use of the buffer
+    stash(As, Bs);
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = 0; k0 < kdim; k0 += BK) {
+      const bool more = k0 + BK < kdim;
+      if (more) fetch(k0 + BK);
+      compute(lds + cur * STAGE, lds + cur * STAGE + BM * LD, k0);
+      if (more) stash(lds + (cur ^ 1) * STAGE, lds + (cur ^ 1) * STAGE + BM * LD);
+      __syncthreads();
+      cur ^= 1;
     }
   }
 }

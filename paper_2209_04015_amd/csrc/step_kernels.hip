@@ -9,6 +9,7 @@
 #include "common.h"
 #include "kernels.h"
 #include "mfma_tile.h"
+#include "tile_order.h"
 
 template <typename T> struct Cplx;
 template <> struct Cplx<float> { using t = float2; };
@@ -674,16 +675,17 @@ struct ExProb {
   const T* Lh;      // spin block [K][nmax][ldN]
   const T* theta;
   int K, W, n, nmax, ldN, sp, G, Z;
+  int gt, wt;       // this workgroup's Cholesky tile and walker tile
   __device__ vec_t load_a(int, int r, int k) const {
     if (r >= G * n) return MF<T>::vzero();
-    const int g = blockIdx.y * G + r / n;
+    const int g = gt * G + r / n;
     if (g >= K) return MF<T>::vzero();
     return *reinterpret_cast<const vec_t*>(Lh + ((size_t)g * nmax + r % n) * ldN + k);
   }
   __device__ vec_t load_b(int, int c, int k) const {
     const int n2 = 2 * n;
     if (c >= Z * n2) return MF<T>::vzero();
-    const int z = blockIdx.x * Z + c / n2;
+    const int z = wt * Z + c / n2;
     if (z >= W) return MF<T>::vzero();
     const int cc = c % n2;
     const int comp = cc >= n ? 1 : 0;
@@ -693,67 +695,101 @@ struct ExProb {
   }
 };
 
+// Tile shapes.  GS = Cholesky tiles per L2 group in the XCD-aware order (the
+// A tiles of one group plus the walker tiles in flight fit one XCD's 4 MB L2).
 template <typename T> struct ExCfg;
 template <> struct ExCfg<float> {
-  static constexpr int BM = 192, BN = 160, BK = 32, WM = 2, WN = 2;
+  static constexpr int BM = 192, BN = 160, BK = 32, WM = 4, WN = 2, GS = 8;
 };
 template <> struct ExCfg<double> {
-  static constexpr int BM = 192, BN = 160, BK = 16, WM = 4, WN = 2;
+  static constexpr int BM = 192, BN = 160, BK = 16, WM = 4, WN = 2, GS = 4;
 };
 
+// Walkers whose T blocks go through LDS together in one epilogue pass.
+constexpr size_t EX_EPI_BUDGET = 150 * 1024;
 template <typename T>
-static size_t ex_lds_bytes(int G, int n) {
+static int ex_walkers_per_pass(int G, int Z, int n) {
+  const size_t per = (size_t)G * n * (2 * n + 1) * sizeof(T);
+  int zp = (int)(EX_EPI_BUDGET / per);
+  const int slots = 64 / (ExCfg<T>::WM * ExCfg<T>::WN);  // cross-wave reduction slots
+  if (zp > slots) zp = slots;
+  if (zp < 1) zp = 1;
+  return zp < Z ? zp : Z;
+}
+
+template <typename T>
+static size_t ex_lds_bytes(int G, int Z, int n) {
   using C = ExCfg<T>;
-  const size_t stage = TileLds<T, C::BM, C::BN, C::BK>::BYTES;
-  const size_t epi = (size_t)G * n * (2 * n + 1) * sizeof(T);
-  return (stage > epi ? stage : epi) + 16 * sizeof(double2);
+  const size_t stage = 2 * (size_t)TileLds<T, C::BM, C::BN, C::BK>::BYTES;  // double buffered
+  const size_t epi = (size_t)ex_walkers_per_pass<T>(G, Z, n) * G * n * (2 * n + 1) * sizeof(T);
+  return (stage > epi ? stage : epi) + 64 * sizeof(double2);
 }
 
 template <typename T>
 __global__ __launch_bounds__(ExCfg<T>::WM* ExCfg<T>::WN * 64) void exchange_kernel(
-    ExProb<T> p, double2* __restrict__ part, int ntg, int red_off) {
+    ExProb<T> p0, double2* __restrict__ part, int ntg, int nwt, int red_off, int zpp) {
   using C = ExCfg<T>;
   constexpr int BM = C::BM, BN = C::BN, BK = C::BK, WM = C::WM, WN = C::WN;
   constexpr int NT = WM * WN * 64;
+  ExProb<T> p = p0;
+  if (!xcd_tile(blockIdx.x, ntg, nwt, C::GS, p.gt, p.wt)) return;
   extern __shared__ double2 ex_lds_raw[];
   T* lds = reinterpret_cast<T*>(ex_lds_raw);
   typename MF<T>::acc_t acc[BM / WM / 16][BN / WN / 16];
-  mfma_tile_mainloop<T, BM, BN, BK, WM, WN, false>(p, 0, 0, 0, p.ldN, acc, lds);
+  mfma_tile_mainloop<T, BM, BN, BK, WM, WN, false, ExProb<T>, true>(p, 0, 0, 0, p.ldN, acc, lds);
 
+  // Epilogue: T blocks of up to zpp walkers go to LDS at once, laid out
+  // [walker][row (g, i)][col (re|im, j)] with an odd row stride; each thread
+  // pairs T_ij with T_ji in FP64, and one cross-wave reduction per pass
+  // yields the partial sums of all walkers of the pass.
   const int n = p.n, n2 = 2 * n, TS = n2 + 1;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int wm = wid / WN, wn = wid % WN;
   const int rows = p.G * n;
+  const int blk = rows * TS;  // LDS elements per walker
+  const int nn = n * n;
+  constexpr int NWAVE = NT / 64;
   double2* red = reinterpret_cast<double2*>(reinterpret_cast<char*>(ex_lds_raw) + red_off);
-  for (int zz = 0; zz < p.Z; ++zz) {
-    const int z = blockIdx.x * p.Z + zz;
-    if (z >= p.W) break;
+  for (int z0 = 0; z0 < p.Z; z0 += zpp) {
+    const int zn = min(zpp, p.Z - z0);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < BM / WM / 16; ++i)
 #pragma unroll
       for (int j = 0; j < BN / WN / 16; ++j) {
         const int mb = wm * (BM / WM) + i * 16 + 4 * (lane >> 4);
-        const int col = wn * (BN / WN) + j * 16 + (lane & 15) - zz * n2;
-        if (col < 0 || col >= n2) continue;
+        const int c = wn * (BN / WN) + j * 16 + (lane & 15) - z0 * n2;
+        if (c < 0 || c >= zn * n2) continue;
+        const int zz = c / n2, col = c - zz * n2;
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          if (mb + r < rows) lds[(mb + r) * TS + col] = acc[i][j][r];
+          if (mb + r < rows) lds[zz * blk + (mb + r) * TS + col] = acc[i][j][r];
       }
     __syncthreads();
-    double2 s = make_double2(0.0, 0.0);
-    const int nn = n * n;
-    for (int e = threadIdx.x; e < p.G * nn; e += NT) {
-      const int g = e / nn, ij = e % nn, i = ij / n, j = ij % n;
-      const T* ri = lds + (g * n + i) * TS;
-      const T* rj = lds + (g * n + j) * TS;
-      const double ar = ri[j], ai = ri[n + j];
-      const double br = rj[i], bi = rj[n + i];
-      s.x += ar * br - ai * bi;
-      s.y += ar * bi + ai * br;
+    for (int zz = 0; zz < zn; ++zz) {
+      const T* tb = lds + zz * blk;
+      double2 s = make_double2(0.0, 0.0);
+      for (int e = threadIdx.x; e < p.G * nn; e += NT) {
+        const int g = e / nn, ij = e % nn, i = ij / n, j = ij % n;
+        const T* ri = tb + (g * n + i) * TS;
+        const T* rj = tb + (g * n + j) * TS;
+        const double ar = ri[j], ai = ri[n + j];
+        const double br = rj[i], bi = rj[n + i];
+        s.x += ar * br - ai * bi;
+        s.y += ar * bi + ai * br;
+      }
+      s = wave_sum2(s);
+      if (lane == 0) red[zz * NWAVE + wid] = s;
     }
-    s = block_sum2(s, red);
-    if (threadIdx.x == 0) part[((size_t)p.sp * ntg + blockIdx.y) * p.W + z] = s;
+    __syncthreads();
+    if (threadIdx.x < zn) {
+      const int z = p.wt * p.Z + z0 + threadIdx.x;
+      if (z < p.W) {
+        double2 t = make_double2(0.0, 0.0);
+        for (int w = 0; w < NWAVE; ++w) t = cadd(t, red[threadIdx.x * NWAVE + w]);  // fixed order
+        part[((size_t)p.sp * ntg + p.gt) * p.W + z] = t;
+      }
+    }
   }
 }
 
@@ -775,16 +811,20 @@ hipError_t launch_exchange(const StepDims& d, int W, const T* Lh, const T* theta
   const ExTile t = exchange_tile<T>(d.nmax);
   if (t.G < 1 || t.Z < 1) return hipErrorInvalidValue;
   const int ntg = ceil_div(d.K, t.G);
+  const int nwt = ceil_div(W, t.Z);
   *ntg_out = ntg;
   const int n = sp == 0 ? d.na : d.nb;
   if (n == 0) return hipSuccess;
   // A spin with fewer electrons reuses the tile shape of the larger one.
-  ExProb<T> p{Lh + (size_t)sp * d.K * d.nmax * d.ldN, theta, d.K, W, n, d.nmax, d.ldN, sp, t.G, t.Z};
-  const size_t lds = ex_lds_bytes<T>(t.G, n);
-  const int red_off = (int)(lds - 16 * sizeof(double2));
-  dim3 grid(ceil_div(W, t.Z), ntg);
-  hipLaunchKernelGGL(exchange_kernel<T>, grid, dim3(C::WM * C::WN * 64), lds, s, p, part, ntg,
-                     red_off);
+  ExProb<T> p{Lh + (size_t)sp * d.K * d.nmax * d.ldN, theta, d.K, W, n, d.nmax, d.ldN, sp, t.G, t.Z,
+              0, 0};
+  const size_t lds = ex_lds_bytes<T>(t.G, t.Z, n);
+  const int red_off = (int)(lds - 64 * sizeof(double2));
+  const int zpp = ex_walkers_per_pass<T>(t.G, t.Z, n);
+  if (zpp * (C::WM * C::WN) > 64) return hipErrorInvalidValue;  // reduction slots
+  const int per = ceil_div(ntg * nwt, 8);
+  hipLaunchKernelGGL(exchange_kernel<T>, dim3(8 * per), dim3(C::WM * C::WN * 64), lds, s, p, part,
+                     ntg, nwt, red_off, zpp);
   return hipGetLastError();
 }
 template hipError_t launch_exchange<float>(const StepDims&, int, const float*, const float*,

@@ -95,6 +95,12 @@ U32 = 2.0 ** -24
 def _energy_tol(precision, cfg):
     if precision == "fp64":
         return 1e-12
+    if precision == "bf16x3":
+        # exchange operands carry 16 significant bits (bf16 hi + lo): the bound
+        # proposed for this mode, 1e-4 S
+        return 1e-4
+    # fp32, and fp16x3 whose hi + lo carry 22 bits, below the FP32 rounding of
+    # the accumulator: 4 u sqrt(c) with c = 2 n N
     return 4 * U32 * math.sqrt(2 * cfg.n * cfg.N)
 
 
@@ -107,6 +113,8 @@ def _assert_logw(got, ref, tol):
 
 PARAMS = [("n20", "fp64", False), ("ragged", "fp64", False), ("ragged", "fp64", True),
           ("n20", "fp32", False), ("ragged", "fp32", False), ("ragged", "fp32", True)]
+SPLIT_PARAMS = [("n20", "fp16x3", False), ("ragged", "fp16x3", False), ("ragged", "fp16x3", True),
+                ("n20", "bf16x3", False), ("ragged", "bf16x3", False), ("ragged", "bf16x3", True)]
 
 
 @pytest.mark.parametrize("name,precision,uhf", PARAMS)
@@ -139,7 +147,7 @@ def test_force_bias_matches_oracle(name, precision, uhf):
     assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("name,precision,uhf", PARAMS)
+@pytest.mark.parametrize("name,precision,uhf", PARAMS + SPLIT_PARAMS)
 def test_local_energy_matches_oracle(name, precision, uhf):
     c = case(name, precision, uhf)
     w = c.walkers()
@@ -187,7 +195,7 @@ def test_orthogonalise_matches_oracle(name, precision, uhf):
     assert np.abs(w.log_ovlp.cpu().numpy() - lo).max() < 1e-11
 
 
-@pytest.mark.parametrize("name,precision,uhf", PARAMS)
+@pytest.mark.parametrize("name,precision,uhf", PARAMS + SPLIT_PARAMS)
 def test_fused_step_matches_oracle(name, precision, uhf):
     """afqmc_step (propagate, QR, energy) against the oracle's step, teacher-forced
     on every step.  In FP64 the second call continues from the GPU state and
@@ -230,7 +238,7 @@ def test_fused_step_matches_oracle(name, precision, uhf):
         assert np.abs(glo.real - lo.real).max() < tol_log
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16x3", "bf16x3"])
 def test_step_cache_reuse_is_exact(precision):
     """Reusing the cached Green's function and force bias gives bit-identical
     walkers, weights and energies to recomputing them."""
