@@ -175,6 +175,46 @@ enum {
 int afqmc_profile_enable(afqmc_ham* ham, int max_records);
 int afqmc_profile_read(afqmc_ham* ham, double* ms, int* launches);
 
+/* ---- uneven multi-system batch (several Hamiltonians, one graph launch) ----
+ *
+ * A batch owns one HIP stream per system and advances every system by one
+ * full walker step (afqmc_step semantics, with AFQMC_STEP_REUSE) per step.
+ * With use_graph the kernel sequences of all systems are captured once into
+ * one hipGraph whose branches (one per system) run concurrently, and each
+ * step is one hipGraphLaunch; a device step counter inside the graph selects
+ * the step's fields and energy slots.  The graph is recaptured when the
+ * field / energy arrays, do_qr or a tuning choice change.
+ *   hams[i]  Hamiltonians (same device; sizes may differ)
+ *   ws[i]    their walker arrays (caller-owned, kept alive while the batch is)
+ *   nw[i]    walkers per system, 1 <= nw[i] <= max_walkers of hams[i]
+ * The batch does not own the Hamiltonians. */
+typedef struct afqmc_batch afqmc_batch;
+typedef struct afqmc_batch_opts {
+  int use_graph;    /* 1: capture + replay a hipGraph; 0: eager launches on the system streams */
+  int reserved[7];
+} afqmc_batch_opts;
+
+int afqmc_batch_create(afqmc_ham* const* hams, const afqmc_walkers* ws, const int* nw, int nsys,
+                       const afqmc_batch_opts* opts, afqmc_batch** out);
+
+/* Advance all systems by nsteps steps on `stream`.
+ *   fields[i]  device [nsteps][nw[i]][K_i] auxiliary fields of system i
+ *   e[i]       device complex [nsteps][nw[i]][3] local energies, or NULL (no
+ *              energy for system i); e itself may be NULL
+ *   do_qr      re-orthogonalise every step (1) or never (0)
+ * Asynchronous; the first call (and any call that recaptures) allocates the
+ * graph and synchronises. */
+int afqmc_batch_step(afqmc_batch* b, const double* const* fields, void* const* e, int nsteps,
+                     int do_qr, void* stream);
+
+/* Choose per system the tile-order group size of the exchange kernel by
+ * timing the candidates on the current walkers (or by reading cache_path, a
+ * text file of "key choice" lines, when it holds the system's key); new
+ * results are appended to cache_path (NULL: no cache).  Synchronises. */
+int afqmc_autotune(afqmc_batch* b, const char* cache_path);
+
+void afqmc_batch_destroy(afqmc_batch* b);
+
 void afqmc_destroy(afqmc_ham* ham);
 const char* afqmc_last_error(void);
 int afqmc_version(void);

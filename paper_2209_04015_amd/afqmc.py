@@ -15,7 +15,7 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["FP64", "FP32", "AfqmcError", "load", "Hamiltonian", "Walkers", "LIB_PATH"]
+__all__ = ["FP64", "FP32", "BF16X3", "FP16X3", "AfqmcError", "load", "Hamiltonian", "Walkers", "Batch", "LIB_PATH"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libafqmc.so")
 
@@ -39,6 +39,10 @@ EXPORTED = (
     "afqmc_get_setup",
     "afqmc_profile_enable",
     "afqmc_profile_read",
+    "afqmc_batch_create",
+    "afqmc_batch_step",
+    "afqmc_autotune",
+    "afqmc_batch_destroy",
     "afqmc_destroy",
     "afqmc_last_error",
     "afqmc_version",
@@ -69,6 +73,10 @@ class _Params(ctypes.Structure):
         ("mu", ctypes.c_double),
         ("e_shift", ctypes.c_double),
     ]
+
+
+class _BatchOpts(ctypes.Structure):
+    _fields_ = [("use_graph", ctypes.c_int), ("reserved", ctypes.c_int * 7)]
 
 
 class _Walkers(ctypes.Structure):
@@ -104,6 +112,11 @@ def load(path: str = LIB_PATH):
     lib.afqmc_get_setup.argtypes = [vp, vp, dp, dp]
     lib.afqmc_profile_enable.argtypes = [vp, ip]
     lib.afqmc_profile_read.argtypes = [vp, vp, vp]
+    lib.afqmc_batch_create.argtypes = [vp, vp, vp, ip, P(_BatchOpts), P(vp)]
+    lib.afqmc_batch_step.argtypes = [vp, vp, vp, ip, ip, vp]
+    lib.afqmc_autotune.argtypes = [vp, ctypes.c_char_p]
+    lib.afqmc_batch_destroy.argtypes = [vp]
+    lib.afqmc_batch_destroy.restype = None
     lib.afqmc_destroy.argtypes = [vp]
     lib.afqmc_destroy.restype = None
     lib.afqmc_last_error.argtypes = []
@@ -111,7 +124,7 @@ def load(path: str = LIB_PATH):
     lib.afqmc_version.argtypes = []
     for name in EXPORTED:
         f = getattr(lib, name)
-        if name not in ("afqmc_destroy", "afqmc_last_error"):
+        if name not in ("afqmc_destroy", "afqmc_last_error", "afqmc_batch_destroy"):
             f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -318,3 +331,59 @@ class Hamiltonian:
         es = ctypes.c_double()
         _check(_lib.afqmc_get_setup(self._h, P.ctypes.data_as(ctypes.c_void_p), ctypes.byref(mu), ctypes.byref(es)))
         return P, mu.value, es.value
+
+
+class Batch:
+    """Several Hamiltonians (of uneven sizes) advanced together, one hipGraph
+    launch per step (afqmc_batch_create / afqmc_batch_step)."""
+
+    def __init__(self, hams, walkers, nw=None, use_graph=True):
+        load()
+        self.hams = list(hams)
+        self.walkers = list(walkers)
+        n = len(self.hams)
+        self.nw = [w.W for w in self.walkers] if nw is None else [int(x) for x in nw]
+        ws = (_Walkers * n)()
+        for i, (h, w) in enumerate(zip(self.hams, self.walkers)):
+            ws[i] = w._struct(h, self.nw[i])
+        hp = (ctypes.c_void_p * n)(*[h._h.value for h in self.hams])
+        nwa = (ctypes.c_int * n)(*self.nw)
+        opts = _BatchOpts(1 if use_graph else 0)
+        b = ctypes.c_void_p()
+        _check(_lib.afqmc_batch_create(ctypes.cast(hp, ctypes.c_void_p), ctypes.cast(ws, ctypes.c_void_p),
+                                       ctypes.cast(nwa, ctypes.c_void_p), n, ctypes.byref(opts), ctypes.byref(b)))
+        self._b = b
+        self._keep = (ws, hp, nwa)
+
+    def step(self, fields, energies=None, do_qr=True, stream=None):
+        """fields[i]: [nsteps, nw_i, K_i] float64; energies[i]: [nsteps, nw_i, 3] complex128 or None."""
+        import torch
+
+        n = len(self.hams)
+        nsteps = fields[0].shape[0]
+        fp = []
+        for i in range(n):
+            fp.append(_dev(fields[i], torch.float64, (nsteps, self.nw[i], self.hams[i].K), f"fields[{i}]").value)
+        ep = [None] * n
+        if energies is not None:
+            for i in range(n):
+                if energies[i] is not None:
+                    ep[i] = _dev(energies[i], torch.complex128, (nsteps, self.nw[i], 3), f"energies[{i}]").value
+        fa = (ctypes.c_void_p * n)(*fp)
+        ea = (ctypes.c_void_p * n)(*ep)
+        _check(_lib.afqmc_batch_step(self._b, ctypes.cast(fa, ctypes.c_void_p), ctypes.cast(ea, ctypes.c_void_p),
+                                     int(nsteps), int(bool(do_qr)), _stream_ptr(stream)))
+
+    def autotune(self, cache_path=None):
+        _check(_lib.afqmc_autotune(self._b, None if cache_path is None else str(cache_path).encode()))
+
+    def close(self):
+        if getattr(self, "_b", None):
+            _lib.afqmc_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -7,6 +7,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -77,6 +80,8 @@ struct afqmc_ham {
   double* corr = nullptr;     // [W][2]
   int* status = nullptr;
   int ntg = 0;
+  int ex_gs = 0;         // exchange tile-order group size (0: built-in default; set by the autotuner)
+  bool capturing = false;  // inside a graph capture: no phase-timing events
   std::vector<void*> allocs;
   // phase timing (afqmc_profile_enable)
   std::vector<hipEvent_t> ev;
@@ -132,7 +137,7 @@ int set_device(const afqmc_ham* h) {
 
 // Phase timing: an event before and after each kernel phase, on the call's stream.
 int prof_mark(afqmc_ham* h, hipStream_t s) {
-  if (h->ev.empty() || h->ev_used + 2 > (int)h->ev.size()) return -1;
+  if (h->capturing || h->ev.empty() || h->ev_used + 2 > (int)h->ev.size()) return -1;
   if (hipEventRecord(h->ev[h->ev_used], s) != hipSuccess) return -1;
   return h->ev_used++;
 }
@@ -168,8 +173,18 @@ int seq_force_bias(afqmc_ham* h, int nw, double2* vbias, hipStream_t s) {
   return AFQMC_OK;
 }
 
+// Per-step inputs and outputs: fields = fields_base + ctr[0] * fstep and
+// e = e_base + ctr[0] * estep when ctr (device) is set, else the bases.
+struct StepIO {
+  const double* fields = nullptr;
+  double2* e = nullptr;
+  const int* ctr = nullptr;
+  long fstep = 0, estep = 0;
+};
+
 template <typename T>
-int seq_energy_from_theta(afqmc_ham* h, int nw, double2* e_out, hipStream_t s) {
+int seq_energy_from_theta(afqmc_ham* h, int nw, double2* e_out, hipStream_t s,
+                          const int* ctr = nullptr, long estep = 0) {
   int ntg = 0;
   if (h->split != SPLIT_NONE) {
     const StepDims& d = h->d;
@@ -179,22 +194,25 @@ int seq_energy_from_theta(afqmc_ham* h, int nw, double2* e_out, hipStream_t s) {
     for (int sp = 0; sp < 2; ++sp)
       PHASE(h, AFQMC_PH_EXCHANGE, s,
             launch_exchange_split(h->split, d, nw, h->lh_hi, h->lh_lo, h->lh_scale, h->th_hi,
-                                  h->th_lo, h->th_scale, h->part, sp, &ntg, s));
+                                  h->th_lo, h->th_scale, h->part, sp, &ntg, s, h->ex_gs));
   } else {
     for (int sp = 0; sp < 2; ++sp)
       PHASE(h, AFQMC_PH_EXCHANGE, s,
-            (launch_exchange<T>(h->d, nw, (const T*)h->Lh, (const T*)h->theta, h->part, sp, &ntg, s)));
+            (launch_exchange<T>(h->d, nw, (const T*)h->Lh, (const T*)h->theta, h->part, sp, &ntg, s,
+                                h->ex_gs)));
   }
-  PHASE(h, AFQMC_PH_ENERGY, s, launch_energy(h->d, nw, h->e1, h->vbias, h->part, ntg, e_out, s));
+  PHASE(h, AFQMC_PH_ENERGY, s,
+        launch_energy(h->d, nw, h->e1, h->vbias, h->part, ntg, e_out, ctr, estep, s));
   return AFQMC_OK;
 }
 
 // phi' = P T(VHS) P phi with vbias (of phi) already in h->vbias.
 template <typename T>
-int seq_propagate_core(afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields, hipStream_t s) {
+int seq_propagate_core(afqmc_ham* h, afqmc_walkers* w, int nw, const StepIO& io, hipStream_t s) {
   const StepDims& d = h->d;
   PHASE(h, AFQMC_PH_SHIFT, s,
-        (launch_shift<T>(d, nw, h->vbias, fields, (T*)h->xs, h->a, h->tmax, h->sdt, s)));
+        (launch_shift<T>(d, nw, h->vbias, io.fields, io.ctr, io.fstep, (T*)h->xs, h->a, h->tmax,
+                         h->sdt, s)));
   PHASE(h, AFQMC_PH_VHS, s,
         (launch_vhs<T>(d, nw, (const T*)h->xs, (const T*)h->LT, h->pq, (T*)h->vhs, h->sdt, s)));
   PHASE(h, AFQMC_PH_ONE_BODY, s,
@@ -219,7 +237,9 @@ int seq_propagate(afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields, 
   int rc;
   if ((rc = seq_theta<T>(h, w, nw, false, s))) return rc;
   if ((rc = seq_force_bias<T>(h, nw, h->vbias, s))) return rc;
-  if ((rc = seq_propagate_core<T>(h, w, nw, fields, s))) return rc;
+  StepIO io;
+  io.fields = fields;
+  if ((rc = seq_propagate_core<T>(h, w, nw, io, s))) return rc;
   if ((rc = seq_theta<T>(h, w, nw, false, s))) return rc;
   PHASE(h, AFQMC_PH_WEIGHT, s,
         launch_weight(nw, h->logdet, nullptr, h->a, (double2*)w->log_ovlp, w->log_w, h->cst,
@@ -239,8 +259,8 @@ int seq_local_energy(afqmc_ham* h, const afqmc_walkers* w, int nw, double2* e, h
 }
 
 template <typename T>
-int seq_step(afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields, int do_qr, double2* e,
-             int flags, hipStream_t s) {
+int seq_step(afqmc_ham* h, afqmc_walkers* w, int nw, const StepIO& io, int do_qr, int flags,
+             hipStream_t s) {
   int rc;
   const bool reuse = (flags & AFQMC_STEP_REUSE) && h->c_valid && h->c_phi_a == w->phi_a &&
                      h->c_phi_b == w->phi_b && h->c_nw == nw;
@@ -248,17 +268,17 @@ int seq_step(afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields, int d
     if ((rc = seq_theta<T>(h, w, nw, false, s))) return rc;
     if ((rc = seq_force_bias<T>(h, nw, h->vbias, s))) return rc;
   }
-  if ((rc = seq_propagate_core<T>(h, w, nw, fields, s))) return rc;
+  if ((rc = seq_propagate_core<T>(h, w, nw, io, s))) return rc;
   if (do_qr)
     PHASE(h, AFQMC_PH_QR, s,
           launch_qr(h->d, nw, (double2*)w->phi_a, (double2*)w->phi_b, h->corr, h->status, s));
-  if ((rc = seq_theta<T>(h, w, nw, e != nullptr, s))) return rc;
+  if ((rc = seq_theta<T>(h, w, nw, io.e != nullptr, s))) return rc;
   PHASE(h, AFQMC_PH_WEIGHT, s,
         launch_weight(nw, h->logdet, do_qr ? h->corr : nullptr, h->a, (double2*)w->log_ovlp,
                       w->log_w, h->cst, h->status, s));
   if ((rc = seq_force_bias<T>(h, nw, h->vbias, s))) return rc;
-  if (e) {
-    if ((rc = seq_energy_from_theta<T>(h, nw, e, s))) return rc;
+  if (io.e) {
+    if ((rc = seq_energy_from_theta<T>(h, nw, io.e, s, io.ctr, io.estep))) return rc;
   }
   h->c_valid = true;
   h->c_phi_a = w->phi_a;
@@ -319,7 +339,7 @@ int trial_energy_fp64(afqmc_ham* h, const double* Y_a, const double* Y_b, hipStr
   for (int sp = 0; sp < 2; ++sp)
     HIP_TRY((launch_exchange<double>(d, 1, (const double*)Lh64, (const double*)theta64, h->part, sp,
                                      &ntg, s)));
-  HIP_TRY(launch_energy(d, 1, h->e1, h->vbias, h->part, ntg, e, s));
+  HIP_TRY(launch_energy(d, 1, h->e1, h->vbias, h->part, ntg, e, nullptr, 0, s));
   double2 he[3];
   HIP_TRY(hipMemcpyAsync(he, e, sizeof he, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -614,8 +634,11 @@ int afqmc_step(afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields, int
   if (!fields) return fail(AFQMC_EINVAL, "null fields");
   if ((rc = set_device(h))) return rc;
   hipStream_t s = (hipStream_t)stream;
-  return h->prec != AFQMC_FP64 ? seq_step<float>(h, w, nw, fields, do_qr, (double2*)e, flags, s)
-                               : seq_step<double>(h, w, nw, fields, do_qr, (double2*)e, flags, s);
+  StepIO io;
+  io.fields = fields;
+  io.e = (double2*)e;
+  return h->prec != AFQMC_FP64 ? seq_step<float>(h, w, nw, io, do_qr, flags, s)
+                               : seq_step<double>(h, w, nw, io, do_qr, flags, s);
 }
 
 int afqmc_get_status(afqmc_ham* h, void* stream, int* out) {
@@ -694,6 +717,312 @@ void afqmc_destroy(afqmc_ham* h) {
   (void)hipDeviceSynchronize();
   free_all(h);
   delete h;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// uneven multi-system batch
+// ===========================================================================
+
+struct afqmc_batch {
+  std::vector<afqmc_ham*> hams;
+  std::vector<afqmc_walkers> ws;
+  std::vector<int> nw;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> joins;
+  hipEvent_t fork = nullptr;
+  hipStream_t origin = nullptr;
+  int* ctr = nullptr;
+  int use_graph = 1;
+  int device = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  // what the current graph was captured for
+  std::vector<const double*> g_fields;
+  std::vector<void*> g_e;
+  int g_qr = -1;
+};
+
+namespace {
+
+void batch_drop_graph(afqmc_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->g_qr = -1;
+}
+
+int batch_step_one(afqmc_batch* b, size_t i, const StepIO& io, int do_qr, hipStream_t s) {
+  afqmc_ham* h = b->hams[i];
+  afqmc_walkers* w = &b->ws[i];
+  return h->prec != AFQMC_FP64 ? seq_step<float>(h, w, b->nw[i], io, do_qr, AFQMC_STEP_REUSE, s)
+                               : seq_step<double>(h, w, b->nw[i], io, do_qr, AFQMC_STEP_REUSE, s);
+}
+
+// theta and vbias of the current walkers of every system (the captured
+// step starts from them)
+int batch_prime(afqmc_batch* b, hipStream_t s) {
+  int rc;
+  for (size_t i = 0; i < b->hams.size(); ++i) {
+    afqmc_ham* h = b->hams[i];
+    afqmc_walkers* w = &b->ws[i];
+    if (h->prec != AFQMC_FP64) {
+      if ((rc = seq_theta<float>(h, w, b->nw[i], false, s))) return rc;
+      if ((rc = seq_force_bias<float>(h, b->nw[i], h->vbias, s))) return rc;
+    } else {
+      if ((rc = seq_theta<double>(h, w, b->nw[i], false, s))) return rc;
+      if ((rc = seq_force_bias<double>(h, b->nw[i], h->vbias, s))) return rc;
+    }
+    h->c_valid = true;
+    h->c_phi_a = w->phi_a;
+    h->c_phi_b = w->phi_b;
+    h->c_nw = b->nw[i];
+  }
+  return AFQMC_OK;
+}
+
+StepIO batch_io(const afqmc_batch* b, size_t i, const double* const* fields, void* const* e,
+                const int* ctr, int step) {
+  const afqmc_ham* h = b->hams[i];
+  StepIO io;
+  const long fstep = (long)b->nw[i] * h->d.K, estep = (long)b->nw[i] * 3;
+  io.ctr = ctr;
+  io.fstep = fstep;
+  io.estep = estep;
+  io.fields = fields[i] + (ctr ? 0 : (size_t)step * fstep);
+  double2* eb = (e && e[i]) ? (double2*)e[i] : nullptr;
+  io.e = eb ? eb + (ctr ? 0 : (size_t)step * estep) : nullptr;
+  return io;
+}
+
+int batch_capture(afqmc_batch* b, const double* const* fields, void* const* e, int do_qr) {
+  batch_drop_graph(b);
+  HIP_TRY(hipStreamBeginCapture(b->origin, hipStreamCaptureModeThreadLocal));
+  int rc = AFQMC_OK;
+  hipError_t he = hipEventRecord(b->fork, b->origin);
+  for (size_t i = 0; i < b->hams.size() && he == hipSuccess && rc == AFQMC_OK; ++i) {
+    he = hipStreamWaitEvent(b->streams[i], b->fork, 0);
+    if (he != hipSuccess) break;
+    b->hams[i]->capturing = true;
+    rc = batch_step_one(b, i, batch_io(b, i, fields, e, b->ctr, 0), do_qr, b->streams[i]);
+    b->hams[i]->capturing = false;
+    if (rc) break;
+    he = hipEventRecord(b->joins[i], b->streams[i]);
+    if (he == hipSuccess) he = hipStreamWaitEvent(b->origin, b->joins[i], 0);
+  }
+  if (he == hipSuccess && rc == AFQMC_OK) he = launch_counter_advance(b->ctr, b->origin);
+  hipGraph_t g = nullptr;
+  const hipError_t he2 = hipStreamEndCapture(b->origin, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (he != hipSuccess || he2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(AFQMC_EHIP, "graph capture failed: %s",
+                hipGetErrorString(he != hipSuccess ? he : he2));
+  }
+  b->graph = g;
+  HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  b->g_fields.assign(fields, fields + b->hams.size());
+  b->g_e.assign(b->hams.size(), nullptr);
+  if (e)
+    for (size_t i = 0; i < b->hams.size(); ++i) b->g_e[i] = e[i];
+  b->g_qr = do_qr;
+  return AFQMC_OK;
+}
+
+std::string tune_key(const afqmc_ham* h, int nw) {
+  hipDeviceProp_t prop;
+  std::string dev = "gfx";
+  if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) dev = prop.gcnArchName;
+  std::ostringstream k;
+  k << "exchange_gs:" << dev << ":N" << h->d.N << ":na" << h->d.na << ":nb" << h->d.nb << ":K"
+    << h->d.K << ":W" << nw << ":p" << h->prec;
+  return k.str();
+}
+
+}  // namespace
+
+extern "C" {
+
+int afqmc_batch_create(afqmc_ham* const* hams, const afqmc_walkers* ws, const int* nw, int nsys,
+                       const afqmc_batch_opts* opts, afqmc_batch** out) {
+  if (!out) return fail(AFQMC_EINVAL, "null output batch pointer");
+  *out = nullptr;
+  if (!hams || !ws || !nw || nsys < 1) return fail(AFQMC_EINVAL, "empty or null batch description");
+  for (int i = 0; i < nsys; ++i) {
+    if (!hams[i]) return fail(AFQMC_EINVAL, "null Hamiltonian %d", i);
+    if (hams[i]->device != hams[0]->device) return fail(AFQMC_EINVAL, "systems on different devices");
+    if (nw[i] < 1) return fail(AFQMC_EINVAL, "system %d: nw must be >= 1", i);
+    int rc = check_walkers(hams[i], &ws[i], nw[i]);
+    if (rc) return rc;
+    for (int j = 0; j < i; ++j)
+      if (hams[j] == hams[i]) return fail(AFQMC_EINVAL, "Hamiltonian %d appears twice (its workspace is per handle)", i);
+  }
+  afqmc_batch* b = new afqmc_batch();
+  b->device = hams[0]->device;
+  b->use_graph = opts ? opts->use_graph : 1;
+  b->hams.assign(hams, hams + nsys);
+  b->ws.assign(ws, ws + nsys);
+  b->nw.assign(nw, nw + nsys);
+  auto cleanup = [b]() { afqmc_batch_destroy(b); };
+  if (hipSetDevice(b->device) != hipSuccess) { cleanup(); return fail(AFQMC_EHIP, "hipSetDevice failed"); }
+  hipError_t e = hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  for (int i = 0; i < nsys && e == hipSuccess; ++i) {
+    hipStream_t s;
+    hipEvent_t ev;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) break;
+    b->streams.push_back(s);
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) break;
+    b->joins.push_back(ev);
+  }
+  if (e == hipSuccess) e = hipMalloc(&b->ctr, sizeof(int));
+  if (e == hipSuccess) e = hipMemset(b->ctr, 0, sizeof(int));
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(AFQMC_EHIP, "batch setup failed: %s", hipGetErrorString(e));
+  }
+  *out = b;
+  return AFQMC_OK;
+}
+
+int afqmc_batch_step(afqmc_batch* b, const double* const* fields, void* const* e, int nsteps,
+                     int do_qr, void* stream) {
+  if (!b) return fail(AFQMC_EINVAL, "null batch");
+  if (nsteps < 0) return fail(AFQMC_EINVAL, "nsteps must be >= 0");
+  if (nsteps == 0) return AFQMC_OK;
+  if (!fields) return fail(AFQMC_EINVAL, "null fields array");
+  for (size_t i = 0; i < b->hams.size(); ++i)
+    if (!fields[i]) return fail(AFQMC_EINVAL, "null fields of system %zu", i);
+  HIP_TRY(hipSetDevice(b->device));
+  hipStream_t s = (hipStream_t)stream;
+  int rc;
+  if ((rc = batch_prime(b, s))) return rc;
+  if (!b->use_graph) {
+    // eager: each step forks the systems onto their streams and joins them
+    for (int k = 0; k < nsteps; ++k) {
+      HIP_TRY(hipEventRecord(b->fork, s));
+      for (size_t i = 0; i < b->hams.size(); ++i) {
+        HIP_TRY(hipStreamWaitEvent(b->streams[i], b->fork, 0));
+        if ((rc = batch_step_one(b, i, batch_io(b, i, fields, e, nullptr, k), do_qr, b->streams[i])))
+          return rc;
+        HIP_TRY(hipEventRecord(b->joins[i], b->streams[i]));
+        HIP_TRY(hipStreamWaitEvent(s, b->joins[i], 0));
+      }
+    }
+    return AFQMC_OK;
+  }
+  bool same = b->exec && b->g_qr == do_qr;
+  for (size_t i = 0; same && i < b->hams.size(); ++i) {
+    void* ei = (e && e[i]) ? e[i] : nullptr;
+    same = b->g_fields[i] == fields[i] && b->g_e[i] == ei;
+  }
+  if (!same) {
+    HIP_TRY(hipStreamSynchronize(s));
+    if ((rc = batch_capture(b, fields, e, do_qr))) return rc;
+  }
+  HIP_TRY(launch_counter_set(b->ctr, 0, s));
+  for (int k = 0; k < nsteps; ++k) HIP_TRY(hipGraphLaunch(b->exec, s));
+  return AFQMC_OK;
+}
+
+int afqmc_autotune(afqmc_batch* b, const char* cache_path) {
+  if (!b) return fail(AFQMC_EINVAL, "null batch");
+  HIP_TRY(hipSetDevice(b->device));
+  std::map<std::string, int> cache;
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string key;
+    int v;
+    while (in >> key >> v) cache[key] = v;
+  }
+  static const int cand[] = {1, 2, 4, 8, 16, 32};
+  hipEvent_t t0, t1;
+  HIP_TRY(hipEventCreate(&t0));
+  HIP_TRY(hipEventCreate(&t1));
+  std::vector<std::pair<std::string, int>> fresh;
+  int rc = AFQMC_OK;
+  for (size_t i = 0; i < b->hams.size() && rc == AFQMC_OK; ++i) {
+    afqmc_ham* h = b->hams[i];
+    const std::string key = tune_key(h, b->nw[i]);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      h->ex_gs = it->second;
+      continue;
+    }
+    hipStream_t s = b->streams[i];
+    // theta of the current walkers, then the exchange alone per candidate
+    rc = h->prec != AFQMC_FP64 ? seq_theta<float>(h, &b->ws[i], b->nw[i], false, s)
+                               : seq_theta<double>(h, &b->ws[i], b->nw[i], false, s);
+    if (rc) break;
+    if (h->split != SPLIT_NONE) {
+      const StepDims& d = h->d;
+      HIP_TRY(launch_split_rows_mode(h->split, (long)b->nw[i] * 4 * d.nmax, d.N, (const float*)h->theta,
+                                     d.ldN, h->th_hi, h->th_lo, d.ldh, h->th_scale, s));
+    }
+    float best = 1e30f;
+    int best_gs = 0;
+    for (int gs : cand) {
+      float tot = 0.f;
+      for (int rep = 0; rep < 3; ++rep) {
+        HIP_TRY(hipEventRecord(t0, s));
+        int ntg = 0;
+        for (int sp = 0; sp < 2; ++sp) {
+          hipError_t he;
+          if (h->split != SPLIT_NONE)
+            he = launch_exchange_split(h->split, h->d, b->nw[i], h->lh_hi, h->lh_lo, h->lh_scale,
+                                       h->th_hi, h->th_lo, h->th_scale, h->part, sp, &ntg, s, gs);
+          else if (h->prec != AFQMC_FP64)
+            he = launch_exchange<float>(h->d, b->nw[i], (const float*)h->Lh, (const float*)h->theta,
+                                        h->part, sp, &ntg, s, gs);
+          else
+            he = launch_exchange<double>(h->d, b->nw[i], (const double*)h->Lh,
+                                         (const double*)h->theta, h->part, sp, &ntg, s, gs);
+          HIP_TRY(he);
+        }
+        HIP_TRY(hipEventRecord(t1, s));
+        HIP_TRY(hipEventSynchronize(t1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
+        if (rep > 0) tot += ms;  // first launch warms up
+      }
+      if (tot < best) {
+        best = tot;
+        best_gs = gs;
+      }
+    }
+    h->ex_gs = best_gs;
+    fresh.emplace_back(key, best_gs);
+    h->c_valid = false;  // theta was recomputed outside a step
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (rc) return rc;
+  if (cache_path && !fresh.empty()) {
+    std::ofstream outf(cache_path, std::ios::app);
+    for (auto& kv : fresh) outf << kv.first << " " << kv.second << "\n";
+  }
+  batch_drop_graph(b);  // tile choices are baked into a captured graph
+  return AFQMC_OK;
+}
+
+void afqmc_batch_destroy(afqmc_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  (void)hipDeviceSynchronize();
+  batch_drop_graph(b);
+  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : b->joins) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->origin) (void)hipStreamDestroy(b->origin);
+  if (b->ctr) (void)hipFree(b->ctr);
+  delete b;
 }
 
 }  // extern "C"

@@ -39,9 +39,10 @@ template <typename T>
 hipError_t launch_force_bias(const StepDims& d, int W, const T* Lh, const T* theta,
                              double2* vbias, hipStream_t s);
 
+// x = x_base + (ctr ? ctr[0] * x_step : 0)
 template <typename T>
-hipError_t launch_shift(const StepDims& d, int W, const double2* vbias, const double* x, T* xs,
-                        double2* a, unsigned* tmax, double sdt, hipStream_t s);
+hipError_t launch_shift(const StepDims& d, int W, const double2* vbias, const double* x, const int* ctr,
+                        long x_step, T* xs, double2* a, unsigned* tmax, double sdt, hipStream_t s);
 
 template <typename T>
 hipError_t launch_vhs(const StepDims& d, int W, const T* xs, const T* LT, const int2* pq, T* vhs,
@@ -68,12 +69,18 @@ hipError_t launch_overlap_store(int W, const double2* logdet, double2* log_ovlp,
 template <typename T>
 ExTile exchange_tile(int n);
 // one spin (sp = 0 alpha, 1 beta) of the exchange energy; part[s][g-tile][z]
+// gs: Cholesky tiles per L2 group of the XCD-aware tile order (< 1: default)
 template <typename T>
 hipError_t launch_exchange(const StepDims& d, int W, const T* Lh, const T* theta, double2* part,
-                           int sp, int* ntg_out, hipStream_t s);
+                           int sp, int* ntg_out, hipStream_t s, int gs = 0);
 
+// e = e_out + (ctr ? ctr[0] * e_step : 0)
 hipError_t launch_energy(const StepDims& d, int W, const double2* e1, const double2* vbias,
-                         const double2* part, int ntg, double2* e_out, hipStream_t s);
+                         const double2* part, int ntg, double2* e_out, const int* ctr, long e_step,
+                         hipStream_t s);
+// device step counter of captured graphs (a kernel, not a memset node)
+hipError_t launch_counter_advance(int* ctr, hipStream_t s);
+hipError_t launch_counter_set(int* ctr, int v, hipStream_t s);
 
 // Householder QR of every walker and spin; corr[W][2] = sum ln |R_ii|.
 hipError_t launch_qr(const StepDims& d, int W, double2* phi_a, double2* phi_b, double* corr,
@@ -92,6 +99,6 @@ hipError_t launch_exchange_split(int mode, const StepDims& d, int W, const unsig
                                  const unsigned short* lh_lo, const float* lh_scale,
                                  const unsigned short* th_hi, const unsigned short* th_lo,
                                  const float* th_scale, double2* part, int sp, int* ntg_out,
-                                 hipStream_t s);
+                                 hipStream_t s, int gs = 0);
 hipError_t set_split_kernel_attributes();
 size_t qr_lds_bytes(const StepDims& d);

@@ -69,7 +69,7 @@ struct TileLds {
   static constexpr int BYTES = ELEMS * (int)sizeof(T);
 };
 
-// Main loop.  With DBUF the LDS holds two staged tile pairs (2 x TileLds
+// Main loop.  With PIPE 2 the LDS holds two staged tile pairs (2 x TileLds
 // bytes): the next tile is written into the idle buffer after the MFMAs of
 // the current one, so each K step needs one barrier instead of two.
 // Prob supplies
@@ -77,8 +77,11 @@ struct TileLds {
 //   vec_t load_b(int batch, int n, int k) const      (n-major B)        if !B_KMAJOR
 //   vec_t load_b_km(int batch, int k, int n) const   (k-major B, n contiguous) if B_KMAJOR
 // and must return zeros for m or n outside its problem.  k >= kdim is zero-filled here.
+// PIPE: 0 = no prefetch (load, stage, compute: fewest registers, for two
+// workgroups per CU that cover each other's memory waits), 1 = the next tile
+// is prefetched into registers during the MFMAs, 2 = 1 plus double-buffered LDS.
 template <typename T, int BM, int BN, int BK, int WM, int WN, bool B_KMAJOR, class Prob,
-          bool DBUF = false>
+          int PIPE = 1>
 __device__ __forceinline__ void mfma_tile_mainloop(
     const Prob& prob, int batch, int m0, int n0, int kdim,
     typename MF<T>::acc_t (&acc)[BM / WM / 16][BN / WN / 16], T* lds) {
@@ -207,7 +210,15 @@ __device__ __forceinline__ void mfma_tile_mainloop(
     }
   };
 
-  if constexpr (!DBUF) {
+  if constexpr (PIPE == 0) {
+    for (int k0 = 0; k0 < kdim; k0 += BK) {
+      fetch(k0);
+      __syncthreads();
+      stash(As, Bs);
+      __syncthreads();
+      compute(As, Bs, k0);
+    }
+  } else if constexpr (PIPE == 1) {
     fetch(0);
     for (int k0 = 0; k0 < kdim; k0 += BK) {
       __syncthreads();

@@ -9,6 +9,7 @@
 #include "kernels.h"
 #include "split_tile.h"
 #include "tile_order.h"
+#include "exchange_epilogue.h"
 
 // ---------------------------------------------------------------------------
 // Row splitting: src rows (FP32, stride ld_src, ncols valid) -> hi/lo rows
@@ -58,8 +59,12 @@ hipError_t launch_split_rows_mode(int mode, long nrows, int ncols, const float* 
 // ---------------------------------------------------------------------------
 // Exchange on split operands.
 // ---------------------------------------------------------------------------
+// 4-wave workgroups, single-buffered LDS under 80 KB: two workgroups per CU.
 struct ExSplitCfg {
-  static constexpr int BM = 192, BN = 160, BK = 32, WM = 4, WN = 2, GS = 8;
+  static constexpr int BM = 192, BN = 160, BK = 32, WM = 2, WN = 2, GS = 8;
+  static constexpr int PIPE = 0;
+  static constexpr bool DBUF = false;
+  static constexpr int WAVES_PER_EU = 2;
 };
 
 struct ExSplitProb {
@@ -94,7 +99,7 @@ struct ExSplitProb {
   }
 };
 
-constexpr size_t EXS_EPI_BUDGET = 150 * 1024;
+constexpr size_t EXS_EPI_BUDGET = 64 * 1024;
 
 static int exs_walkers_per_pass(int G, int Z, int n) {
   const size_t per = (size_t)G * n * (2 * n + 1) * sizeof(float);
@@ -105,84 +110,38 @@ static int exs_walkers_per_pass(int G, int Z, int n) {
   return zp < Z ? zp : Z;
 }
 
-static size_t exs_lds_bytes(int G, int Z, int n) {
+static size_t exs_tab_off(int G, int Z, int n) {
   using C = ExSplitCfg;
-  const size_t stage = 2 * (size_t)SplitLds<C::BM, C::BN, C::BK>::BYTES;
+  const size_t stage = (C::DBUF ? 2 : 1) * (size_t)SplitLds<C::BM, C::BN, C::BK>::BYTES;
   const size_t epi = (size_t)exs_walkers_per_pass(G, Z, n) * G * n * (2 * n + 1) * sizeof(float);
-  return (stage > epi ? stage : epi) + 64 * sizeof(double2);
+  return (stage > epi ? stage : epi + 15) / 16 * 16;
+}
+static size_t exs_lds_bytes(int G, int Z, int n) {
+  return exs_tab_off(G, Z, n) + EX_TAB_BYTES + EX_RED_BYTES;
 }
 
 template <class H>
-__global__ __launch_bounds__(ExSplitCfg::WM* ExSplitCfg::WN * 64) void exchange_split_kernel(
-    ExSplitProb p0, double2* __restrict__ part, int ntg, int nwt, int red_off, int zpp) {
+__global__ __launch_bounds__(ExSplitCfg::WM* ExSplitCfg::WN * 64, ExSplitCfg::WAVES_PER_EU) void exchange_split_kernel(
+    ExSplitProb p0, double2* __restrict__ part, int ntg, int nwt, int tab_off, int zpp, int gs) {
   using C = ExSplitCfg;
   constexpr int BM = C::BM, BN = C::BN, BK = C::BK, WM = C::WM, WN = C::WN;
-  constexpr int NT = WM * WN * 64;
   ExSplitProb p = p0;
-  if (!xcd_tile(blockIdx.x, ntg, nwt, C::GS, p.gt, p.wt)) return;
+  if (!xcd_tile(blockIdx.x, ntg, nwt, gs, p.gt, p.wt)) return;
   extern __shared__ double2 exs_lds_raw[];
   floatx4 acc[BM / WM / 16][BN / WN / 16];
-  split_tile_mainloop<H, BM, BN, BK, WM, WN>(p, p.ldh, acc,
-                                             reinterpret_cast<unsigned short*>(exs_lds_raw));
-
-  float* lds = reinterpret_cast<float*>(exs_lds_raw);
-  const int n = p.n, n2 = 2 * n, TS = n2 + 1;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int wm = wid / WN, wn = wid % WN;
-  const int rows = p.G * n;
-  const int blk = rows * TS;
-  const int nn = n * n;
-  constexpr int NWAVE = NT / 64;
-  double2* red = reinterpret_cast<double2*>(reinterpret_cast<char*>(exs_lds_raw) + red_off);
-  for (int z0 = 0; z0 < p.Z; z0 += zpp) {
-    const int zn = min(zpp, p.Z - z0);
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < BM / WM / 16; ++i)
-#pragma unroll
-      for (int j = 0; j < BN / WN / 16; ++j) {
-        const int mb = wm * (BM / WM) + i * 16 + 4 * (lane >> 4);
-        const int cg = wn * (BN / WN) + j * 16 + (lane & 15);
-        const int c = cg - z0 * n2;
-        if (c < 0 || c >= zn * n2) continue;
-        if (p.wt * p.Z + cg / n2 >= p.W) continue;
-        const int zz = c / n2, col = c - zz * n2;
-        const float cs = 1.0f / p.b_scale[p.b_row(cg)];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = mb + r;
-          if (row >= rows) continue;
-          const int g = p.gt * p.G + row / n;
-          const float rs = g < p.K ? 1.0f / p.a_scale[(size_t)g * p.nmax + row % n] : 0.f;
-          lds[zz * blk + row * TS + col] = acc[i][j][r] * rs * cs;  // exact: powers of two
-        }
-      }
-    __syncthreads();
-    for (int zz = 0; zz < zn; ++zz) {
-      const float* tb = lds + zz * blk;
-      double2 s = make_double2(0.0, 0.0);
-      for (int e = threadIdx.x; e < p.G * nn; e += NT) {
-        const int g = e / nn, ij = e % nn, i = ij / n, j = ij % n;
-        const float* ri = tb + (g * n + i) * TS;
-        const float* rj = tb + (g * n + j) * TS;
-        const double ar = ri[j], ai = ri[n + j];
-        const double br = rj[i], bi = rj[n + i];
-        s.x += ar * br - ai * bi;
-        s.y += ar * bi + ai * br;
-      }
-      s = wave_sum2(s);
-      if (lane == 0) red[zz * NWAVE + wid] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < zn) {
-      const int z = p.wt * p.Z + z0 + threadIdx.x;
-      if (z < p.W) {
-        double2 t = make_double2(0.0, 0.0);
-        for (int w = 0; w < NWAVE; ++w) t = cadd(t, red[threadIdx.x * NWAVE + w]);
-        part[((size_t)p.sp * ntg + p.gt) * p.W + z] = t;
-      }
-    }
-  }
+  split_tile_mainloop<H, BM, BN, BK, WM, WN, ExSplitProb, C::PIPE>(
+      p, p.ldh, acc, reinterpret_cast<unsigned short*>(exs_lds_raw));
+  const ExTileGeom q{p.n, p.G, p.Z, p.K, p.W, p.gt, p.wt};
+  const float* as = p.a_scale;
+  const float* bs = p.b_scale;
+  const int nmax = p.nmax, sp = p.sp;
+  auto rscale = [as, nmax](int g, int i) { return as[(size_t)g * nmax + i]; };
+  auto cscale = [bs, nmax, sp](int z, int comp, int j) {
+    return bs[(((size_t)z * 2 + comp) * 2 + sp) * nmax + j];
+  };
+  exchange_epilogue<float, floatx4, BM, BN, WM, WN>(acc, reinterpret_cast<char*>(exs_lds_raw), tab_off,
+                                                   tab_off + EX_TAB_BYTES, q, zpp, H::SCALED, rscale,
+                                                   cscale, part, p.sp, ntg);
 }
 
 ExTile exchange_split_tile(int n) {
@@ -196,8 +155,9 @@ hipError_t launch_exchange_split(int mode, const StepDims& d, int W, const unsig
                                  const unsigned short* lh_lo, const float* lh_scale,
                                  const unsigned short* th_hi, const unsigned short* th_lo,
                                  const float* th_scale, double2* part, int sp, int* ntg_out,
-                                 hipStream_t s) {
+                                 hipStream_t s, int gs) {
   using C = ExSplitCfg;
+  if (gs < 1) gs = C::GS;
   const ExTile t = exchange_split_tile(d.nmax);
   if (t.G < 1 || t.Z < 1) return hipErrorInvalidValue;
   const int ntg = ceil_div(d.K, t.G);
@@ -209,15 +169,15 @@ hipError_t launch_exchange_split(int mode, const StepDims& d, int W, const unsig
   ExSplitProb p{lh_hi + sp * sblk * d.ldh, lh_lo + sp * sblk * d.ldh, lh_scale + sp * sblk,
                 th_hi, th_lo, th_scale, d.K, W, n, d.nmax, d.ldh, sp, t.G, t.Z, 0, 0};
   const size_t lds = exs_lds_bytes(t.G, t.Z, n);
-  const int red_off = (int)(lds - 64 * sizeof(double2));
+  const int tab_off = (int)exs_tab_off(t.G, t.Z, n);
   const int zpp = exs_walkers_per_pass(t.G, t.Z, n);
   const int per = ceil_div(ntg * nwt, 8);
   if (mode == SPLIT_BF16)
     hipLaunchKernelGGL(exchange_split_kernel<HalfBF16>, dim3(8 * per), dim3(C::WM * C::WN * 64), lds, s,
-                       p, part, ntg, nwt, red_off, zpp);
+                       p, part, ntg, nwt, tab_off, zpp, gs);
   else
     hipLaunchKernelGGL(exchange_split_kernel<HalfF16>, dim3(8 * per), dim3(C::WM * C::WN * 64), lds, s,
-                       p, part, ntg, nwt, red_off, zpp);
+                       p, part, ntg, nwt, tab_off, zpp, gs);
   return hipGetLastError();
 }
 

@@ -70,12 +70,13 @@ struct SplitLds {
   static constexpr int BYTES = ELEMS * 2;
 };
 
-// Main loop of C[BM x BN] = A B^T with split operands, double-buffered LDS.
+// Main loop of C[BM x BN] = A B^T with split operands.
 // Prob supplies (row, k) -> 16-byte vectors of 8 raw 16-bit values:
 //   uint4 load_a(int m, int k, int part) const   part 0 = hi, 1 = lo
 //   uint4 load_b(int n, int k, int part) const
 // returning zeros outside the problem.  k is a multiple of 8; kdim of 32.
-template <class H, int BM, int BN, int BK, int WM, int WN, class Prob>
+// PIPE as in mfma_tile.h: 0 no prefetch, 1 register prefetch, 2 + double-buffered LDS.
+template <class H, int BM, int BN, int BK, int WM, int WN, class Prob, int PIPE = 2>
 __device__ __forceinline__ void split_tile_mainloop(const Prob& prob, int kdim,
                                                     floatx4 (&acc)[BM / WM / 16][BN / WN / 16],
                                                     unsigned short* lds) {
@@ -153,7 +154,7 @@ __device__ __forceinline__ void split_tile_mainloop(const Prob& prob, int kdim,
 #pragma unroll
     for (int kc = 0; kc < BK; kc += 32) {
       if (k0 + kc >= kdim) break;
-      vec8 ah[FM], al[FM], bh[FN], bl[FN];
+      vec8 ah[FM], al[FM];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
         const int r = wm * (BM / WM) + i * 16 + lrow;
@@ -163,31 +164,48 @@ __device__ __forceinline__ void split_tile_mainloop(const Prob& prob, int kdim,
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
         const int r = wn * (BN / WN) + j * 16 + lrow;
-        bh[j] = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(s + (2 * BM + r) * LD + kc + lk));
-        bl[j] = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(s + (2 * BM + BN + r) * LD + kc + lk));
-      }
+        const vec8 bh = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(s + (2 * BM + r) * LD + kc + lk));
+        const vec8 bl = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(s + (2 * BM + BN + r) * LD + kc + lk));
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          acc[i][j] = H::mma(al[i], bh[j], acc[i][j]);
-          acc[i][j] = H::mma(ah[i], bl[j], acc[i][j]);
-          acc[i][j] = H::mma(ah[i], bh[j], acc[i][j]);
+        for (int i = 0; i < FM; ++i) {
+          acc[i][j] = H::mma(al[i], bh, acc[i][j]);
+          acc[i][j] = H::mma(ah[i], bl, acc[i][j]);
+          acc[i][j] = H::mma(ah[i], bh, acc[i][j]);
         }
+      }
     }
   };
 
-  fetch(0);
-  __syncthreads();
-  stash(lds);
-  __syncthreads();
-  int cur = 0;
-  for (int k0 = 0; k0 < kdim; k0 += BK) {
-    const bool more = k0 + BK < kdim;
-    if (more) fetch(k0 + BK);
-    compute(lds + cur * STAGE, k0);
-    if (more) stash(lds + (cur ^ 1) * STAGE);
+  if constexpr (PIPE == 0) {
+    for (int k0 = 0; k0 < kdim; k0 += BK) {
+      fetch(k0);
+      __syncthreads();
+      stash(lds);
+      __syncthreads();
+      compute(lds, k0);
+    }
+  } else if constexpr (PIPE == 1) {
+    fetch(0);
+    for (int k0 = 0; k0 < kdim; k0 += BK) {
+      __syncthreads();
+      stash(lds);
+      __syncthreads();
+      if (k0 + BK < kdim) fetch(k0 + BK);
+      compute(lds, k0);
+    }
+  } else {
+    fetch(0);
     __syncthreads();
-    cur ^= 1;
+    stash(lds);
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = 0; k0 < kdim; k0 += BK) {
+      const bool more = k0 + BK < kdim;
+      if (more) fetch(k0 + BK);
+      compute(lds + cur * STAGE, k0);
+      if (more) stash(lds + (cur ^ 1) * STAGE);
+      __syncthreads();
+      cur ^= 1;
+    }
   }
 }

@@ -10,6 +10,7 @@
 #include "kernels.h"
 #include "mfma_tile.h"
 #include "tile_order.h"
+#include "exchange_epilogue.h"
 
 template <typename T> struct Cplx;
 template <> struct Cplx<float> { using t = float2; };
@@ -284,13 +285,18 @@ template hipError_t launch_force_bias<double>(const StepDims&, int, const double
 // (Eq. import and the optimal force bias of Sec. II.B)
 // ===========================================================================
 
+// `ctr` (optional, device) selects the step inside a stacked field array:
+// x = x_base + ctr[0] * x_step.  A captured graph replays one step many
+// times with a counter it advances itself.
 template <typename T>
 __global__ __launch_bounds__(256) void shift_kernel(int K, int ldK, const double2* __restrict__ vbias,
-                                                    const double* __restrict__ x, T* __restrict__ xs,
-                                                    double2* __restrict__ a, unsigned* __restrict__ tmax,
-                                                    double sdt) {
+                                                    const double* __restrict__ x_base,
+                                                    const int* __restrict__ ctr, long x_step,
+                                                    T* __restrict__ xs, double2* __restrict__ a,
+                                                    unsigned* __restrict__ tmax, double sdt) {
   __shared__ double2 red[4];
   const int z = blockIdx.x;
+  const double* x = x_base + (ctr ? (size_t)ctr[0] * x_step : 0);
   double2 acc = make_double2(0.0, 0.0);
   for (int g = threadIdx.x; g < K; g += 256) {
     const double2 v = vbias[(size_t)z * K + g];
@@ -309,16 +315,18 @@ __global__ __launch_bounds__(256) void shift_kernel(int K, int ldK, const double
 }
 
 template <typename T>
-hipError_t launch_shift(const StepDims& d, int W, const double2* vbias, const double* x, T* xs,
-                        double2* a, unsigned* tmax, double sdt, hipStream_t s) {
-  hipLaunchKernelGGL(shift_kernel<T>, dim3(W), dim3(256), 0, s, d.K, d.ldK, vbias, x, xs, a, tmax,
-                     sdt);
+hipError_t launch_shift(const StepDims& d, int W, const double2* vbias, const double* x, const int* ctr,
+                        long x_step, T* xs, double2* a, unsigned* tmax, double sdt, hipStream_t s) {
+  hipLaunchKernelGGL(shift_kernel<T>, dim3(W), dim3(256), 0, s, d.K, d.ldK, vbias, x, ctr, x_step, xs,
+                     a, tmax, sdt);
   return hipGetLastError();
 }
 template hipError_t launch_shift<float>(const StepDims&, int, const double2*, const double*,
-                                        float*, double2*, unsigned*, double, hipStream_t);
+                                        const int*, long, float*, double2*, unsigned*, double,
+                                        hipStream_t);
 template hipError_t launch_shift<double>(const StepDims&, int, const double2*, const double*,
-                                         double*, double2*, unsigned*, double, hipStream_t);
+                                         const int*, long, double*, double2*, unsigned*, double,
+                                         hipStream_t);
 
 // ===========================================================================
 // VHS build: VHS_z = i sqrt(dt) sum_g xs_zg L_g over the packed (p <= q)
@@ -698,99 +706,67 @@ struct ExProb {
 // Tile shapes.  GS = Cholesky tiles per L2 group in the XCD-aware order (the
 // A tiles of one group plus the walker tiles in flight fit one XCD's 4 MB L2).
 template <typename T> struct ExCfg;
+// FP32: 4-wave workgroups, single-buffered LDS under 80 KB and at most 256
+// registers per wave, so two independent workgroups share a CU (their
+// barriers do not line up, one computes while the other waits on memory).
+// FP64: the 8-byte accumulators need 8 waves; one double-buffered workgroup per CU.
 template <> struct ExCfg<float> {
-  static constexpr int BM = 192, BN = 160, BK = 32, WM = 4, WN = 2, GS = 8;
+  static constexpr int BM = 192, BN = 160, BK = 32, WM = 2, WN = 2, GS = 8;
+  static constexpr int PIPE = 0;
+  static constexpr bool DBUF = false;
+  static constexpr int WAVES_PER_EU = 2;
+  static constexpr size_t EPI_BUDGET = 72 * 1024;
 };
 template <> struct ExCfg<double> {
   static constexpr int BM = 192, BN = 160, BK = 16, WM = 4, WN = 2, GS = 4;
+  static constexpr int PIPE = 2;
+  static constexpr bool DBUF = true;
+  static constexpr int WAVES_PER_EU = 2;
+  static constexpr size_t EPI_BUDGET = 150 * 1024;
 };
 
 // Walkers whose T blocks go through LDS together in one epilogue pass.
-constexpr size_t EX_EPI_BUDGET = 150 * 1024;
 template <typename T>
 static int ex_walkers_per_pass(int G, int Z, int n) {
   const size_t per = (size_t)G * n * (2 * n + 1) * sizeof(T);
-  int zp = (int)(EX_EPI_BUDGET / per);
+  int zp = (int)(ExCfg<T>::EPI_BUDGET / per);
   const int slots = 64 / (ExCfg<T>::WM * ExCfg<T>::WN);  // cross-wave reduction slots
   if (zp > slots) zp = slots;
   if (zp < 1) zp = 1;
   return zp < Z ? zp : Z;
 }
 
+// LDS: max(operand staging, T blocks of one epilogue pass), then the
+// epilogue tables and the reduction slots.
+template <typename T>
+static size_t ex_tab_off(int G, int Z, int n) {
+  using C = ExCfg<T>;
+  const size_t stage = (C::DBUF ? 2 : 1) * (size_t)TileLds<T, C::BM, C::BN, C::BK>::BYTES;
+  const size_t epi = (size_t)ex_walkers_per_pass<T>(G, Z, n) * G * n * (2 * n + 1) * sizeof(T);
+  return (stage > epi ? stage : epi + 15) / 16 * 16;
+}
 template <typename T>
 static size_t ex_lds_bytes(int G, int Z, int n) {
-  using C = ExCfg<T>;
-  const size_t stage = 2 * (size_t)TileLds<T, C::BM, C::BN, C::BK>::BYTES;  // double buffered
-  const size_t epi = (size_t)ex_walkers_per_pass<T>(G, Z, n) * G * n * (2 * n + 1) * sizeof(T);
-  return (stage > epi ? stage : epi) + 64 * sizeof(double2);
+  return ex_tab_off<T>(G, Z, n) + EX_TAB_BYTES + EX_RED_BYTES;
 }
 
 template <typename T>
-__global__ __launch_bounds__(ExCfg<T>::WM* ExCfg<T>::WN * 64) void exchange_kernel(
-    ExProb<T> p0, double2* __restrict__ part, int ntg, int nwt, int red_off, int zpp) {
+__global__ __launch_bounds__(ExCfg<T>::WM* ExCfg<T>::WN * 64, ExCfg<T>::WAVES_PER_EU) void exchange_kernel(
+    ExProb<T> p0, double2* __restrict__ part, int ntg, int nwt, int tab_off, int zpp, int gs) {
   using C = ExCfg<T>;
   constexpr int BM = C::BM, BN = C::BN, BK = C::BK, WM = C::WM, WN = C::WN;
-  constexpr int NT = WM * WN * 64;
   ExProb<T> p = p0;
-  if (!xcd_tile(blockIdx.x, ntg, nwt, C::GS, p.gt, p.wt)) return;
+  if (!xcd_tile(blockIdx.x, ntg, nwt, gs, p.gt, p.wt)) return;
   extern __shared__ double2 ex_lds_raw[];
   T* lds = reinterpret_cast<T*>(ex_lds_raw);
   typename MF<T>::acc_t acc[BM / WM / 16][BN / WN / 16];
-  mfma_tile_mainloop<T, BM, BN, BK, WM, WN, false, ExProb<T>, true>(p, 0, 0, 0, p.ldN, acc, lds);
-
-  // Epilogue: T blocks of up to zpp walkers go to LDS at once, laid out
-  // [walker][row (g, i)][col (re|im, j)] with an odd row stride; each thread
-  // pairs T_ij with T_ji in FP64, and one cross-wave reduction per pass
-  // yields the partial sums of all walkers of the pass.
-  const int n = p.n, n2 = 2 * n, TS = n2 + 1;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int wm = wid / WN, wn = wid % WN;
-  const int rows = p.G * n;
-  const int blk = rows * TS;  // LDS elements per walker
-  const int nn = n * n;
-  constexpr int NWAVE = NT / 64;
-  double2* red = reinterpret_cast<double2*>(reinterpret_cast<char*>(ex_lds_raw) + red_off);
-  for (int z0 = 0; z0 < p.Z; z0 += zpp) {
-    const int zn = min(zpp, p.Z - z0);
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < BM / WM / 16; ++i)
-#pragma unroll
-      for (int j = 0; j < BN / WN / 16; ++j) {
-        const int mb = wm * (BM / WM) + i * 16 + 4 * (lane >> 4);
-        const int c = wn * (BN / WN) + j * 16 + (lane & 15) - z0 * n2;
-        if (c < 0 || c >= zn * n2) continue;
-        const int zz = c / n2, col = c - zz * n2;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (mb + r < rows) lds[zz * blk + (mb + r) * TS + col] = acc[i][j][r];
-      }
-    __syncthreads();
-    for (int zz = 0; zz < zn; ++zz) {
-      const T* tb = lds + zz * blk;
-      double2 s = make_double2(0.0, 0.0);
-      for (int e = threadIdx.x; e < p.G * nn; e += NT) {
-        const int g = e / nn, ij = e % nn, i = ij / n, j = ij % n;
-        const T* ri = tb + (g * n + i) * TS;
-        const T* rj = tb + (g * n + j) * TS;
-        const double ar = ri[j], ai = ri[n + j];
-        const double br = rj[i], bi = rj[n + i];
-        s.x += ar * br - ai * bi;
-        s.y += ar * bi + ai * br;
-      }
-      s = wave_sum2(s);
-      if (lane == 0) red[zz * NWAVE + wid] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < zn) {
-      const int z = p.wt * p.Z + z0 + threadIdx.x;
-      if (z < p.W) {
-        double2 t = make_double2(0.0, 0.0);
-        for (int w = 0; w < NWAVE; ++w) t = cadd(t, red[threadIdx.x * NWAVE + w]);  // fixed order
-        part[((size_t)p.sp * ntg + p.gt) * p.W + z] = t;
-      }
-    }
-  }
+  mfma_tile_mainloop<T, BM, BN, BK, WM, WN, false, ExProb<T>, C::PIPE>(p, 0, 0, 0, p.ldN, acc, lds);
+  const ExTileGeom q{p.n, p.G, p.Z, p.K, p.W, p.gt, p.wt};
+  auto one3 = [](int, int, int) { return 1.0f; };
+  auto one2 = [](int, int) { return 1.0f; };
+  exchange_epilogue<T, typename MF<T>::acc_t, BM, BN, WM, WN>(
+      acc, reinterpret_cast<char*>(ex_lds_raw), tab_off, tab_off + EX_TAB_BYTES, q, zpp, false, one2,
+      one3, part, p.sp, ntg);
 }
 
 template <typename T>
@@ -806,7 +782,7 @@ template ExTile exchange_tile<double>(int);
 
 template <typename T>
 hipError_t launch_exchange(const StepDims& d, int W, const T* Lh, const T* theta, double2* part,
-                           int sp, int* ntg_out, hipStream_t s) {
+                           int sp, int* ntg_out, hipStream_t s, int gs) {
   using C = ExCfg<T>;
   const ExTile t = exchange_tile<T>(d.nmax);
   if (t.G < 1 || t.Z < 1) return hipErrorInvalidValue;
@@ -819,18 +795,19 @@ hipError_t launch_exchange(const StepDims& d, int W, const T* Lh, const T* theta
   ExProb<T> p{Lh + (size_t)sp * d.K * d.nmax * d.ldN, theta, d.K, W, n, d.nmax, d.ldN, sp, t.G, t.Z,
               0, 0};
   const size_t lds = ex_lds_bytes<T>(t.G, t.Z, n);
-  const int red_off = (int)(lds - 64 * sizeof(double2));
+  const int tab_off = (int)ex_tab_off<T>(t.G, t.Z, n);
   const int zpp = ex_walkers_per_pass<T>(t.G, t.Z, n);
   if (zpp * (C::WM * C::WN) > 64) return hipErrorInvalidValue;  // reduction slots
   const int per = ceil_div(ntg * nwt, 8);
+  if (gs < 1) gs = C::GS;
   hipLaunchKernelGGL(exchange_kernel<T>, dim3(8 * per), dim3(C::WM * C::WN * 64), lds, s, p, part,
-                     ntg, nwt, red_off, zpp);
+                     ntg, nwt, tab_off, zpp, gs);
   return hipGetLastError();
 }
 template hipError_t launch_exchange<float>(const StepDims&, int, const float*, const float*,
-                                           double2*, int, int*, hipStream_t);
+                                           double2*, int, int*, hipStream_t, int);
 template hipError_t launch_exchange<double>(const StepDims&, int, const double*, const double*,
-                                            double2*, int, int*, hipStream_t);
+                                            double2*, int, int*, hipStream_t, int);
 
 // ===========================================================================
 // Energy assembly (R10 of the design): E1 from the Green's function pass,
@@ -841,9 +818,11 @@ __global__ __launch_bounds__(256) void energy_kernel(int W, int K, int ntg, int 
                                                      const double2* __restrict__ e1,
                                                      const double2* __restrict__ vbias,
                                                      const double2* __restrict__ part,
-                                                     double2* __restrict__ e_out) {
+                                                     double2* __restrict__ e_base,
+                                                     const int* __restrict__ ctr, long e_step) {
   __shared__ double2 red[4];
   const int z = blockIdx.x;
+  double2* e_out = e_base + (ctr ? (size_t)ctr[0] * e_step : 0);
   double2 ej = make_double2(0.0, 0.0);
   for (int g = threadIdx.x; g < K; g += 256) {
     const double2 v = vbias[(size_t)z * K + g];
@@ -865,9 +844,25 @@ __global__ __launch_bounds__(256) void energy_kernel(int W, int K, int ntg, int 
 }
 
 hipError_t launch_energy(const StepDims& d, int W, const double2* e1, const double2* vbias,
-                         const double2* part, int ntg, double2* e_out, hipStream_t s) {
+                         const double2* part, int ntg, double2* e_out, const int* ctr, long e_step,
+                         hipStream_t s) {
   hipLaunchKernelGGL(energy_kernel, dim3(W), dim3(256), 0, s, W, d.K, ntg, d.nb == 0 ? 1 : 0, e1,
-                     vbias, part, e_out);
+                     vbias, part, e_out, ctr, e_step);
+  return hipGetLastError();
+}
+
+__global__ void counter_advance_kernel(int* ctr) {
+  if (threadIdx.x == 0) ctr[0] += 1;
+}
+__global__ void counter_set_kernel(int* ctr, int v) {
+  if (threadIdx.x == 0) ctr[0] = v;
+}
+hipError_t launch_counter_advance(int* ctr, hipStream_t s) {
+  hipLaunchKernelGGL(counter_advance_kernel, dim3(1), dim3(64), 0, s, ctr);
+  return hipGetLastError();
+}
+hipError_t launch_counter_set(int* ctr, int v, hipStream_t s) {
+  hipLaunchKernelGGL(counter_set_kernel, dim3(1), dim3(64), 0, s, ctr, v);
   return hipGetLastError();
 }
 
