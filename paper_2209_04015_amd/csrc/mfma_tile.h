@@ -95,7 +95,12 @@ __device__ __forceinline__ void mfma_tile_mainloop(
   constexpr int VA = BM * BK / VEC;  // vectors per A tile
   constexpr int VB = BN * BK / VEC;
   constexpr int NA = (VA + NT - 1) / NT;
-  constexpr int NB = (VB + NT - 1) / NT;
+  // k-major B is moved in VEC x VEC blocks (VEC k rows of VEC n values),
+  // transposed in registers and stored as vectors along k
+  constexpr int KBLK = BK / VEC, NBLK = BN / VEC;
+  constexpr int VBB = B_KMAJOR ? KBLK * NBLK : VB;
+  constexpr int NB = (VBB + NT - 1) / NT;
+  constexpr int RB = B_KMAJOR ? VEC : 1;  // vectors held per block
   static_assert(BK % 16 == 0, "BK must be a multiple of 16");
   static_assert(BM % (16 * WM) == 0 && BN % (16 * WN) == 0, "tile/wave mismatch");
 
@@ -114,7 +119,7 @@ __device__ __forceinline__ void mfma_tile_mainloop(
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = M::zero();
 
-  vec_t ra[NA], rb[NB];
+  vec_t ra[NA], rb[NB][RB];
 
   auto fetch = [&](int k0) {
 #pragma unroll
@@ -130,16 +135,20 @@ __device__ __forceinline__ void mfma_tile_mainloop(
 #pragma unroll
     for (int t = 0; t < NB; ++t) {
       const int v = tid + t * NT;
-      rb[t] = M::vzero();
-      if (v < VB) {
+#pragma unroll
+      for (int e = 0; e < RB; ++e) rb[t][e] = M::vzero();
+      if (v < VBB) {
         if constexpr (!B_KMAJOR) {
           const int r = v / (BK / VEC);
           const int k = k0 + (v % (BK / VEC)) * VEC;
-          if (k < kdim) rb[t] = prob.load_b(batch, n0 + r, k);
+          if (k < kdim) rb[t][0] = prob.load_b(batch, n0 + r, k);
         } else {
-          const int kr = v / (BN / VEC);
-          const int n = (v % (BN / VEC)) * VEC;
-          if (k0 + kr < kdim) rb[t] = prob.load_b_km(batch, k0 + kr, n0 + n);
+          const int kb = v % KBLK, nb = v / KBLK;
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) {
+            const int k = k0 + kb * VEC + e;
+            if (k < kdim) rb[t][e] = prob.load_b_km(batch, k, n0 + nb * VEC);
+          }
         }
       }
     }
@@ -157,16 +166,23 @@ __device__ __forceinline__ void mfma_tile_mainloop(
 #pragma unroll
     for (int t = 0; t < NB; ++t) {
       const int v = tid + t * NT;
-      if (v < VB) {
+      if (v < VBB) {
         if constexpr (!B_KMAJOR) {
           const int r = v / (BK / VEC);
           const int k = (v % (BK / VEC)) * VEC;
-          *reinterpret_cast<vec_t*>(Bs + r * LD + k) = rb[t];
+          *reinterpret_cast<vec_t*>(Bs + r * LD + k) = rb[t][0];
         } else {
-          const int kr = v / (BN / VEC);
-          const int n = (v % (BN / VEC)) * VEC;
+          const int kb = v % KBLK, nb = v / KBLK;
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) Bs[(n + e) * LD + kr] = vget(rb[t], e);
+          for (int c = 0; c < VEC; ++c) {
+            vec_t w;
+            if constexpr (VEC == 4) {
+              w = make_float4(vget(rb[t][0], c), vget(rb[t][1], c), vget(rb[t][2], c), vget(rb[t][3], c));
+            } else {
+              w = make_double2(vget(rb[t][0], c), vget(rb[t][1], c));
+            }
+            *reinterpret_cast<vec_t*>(Bs + (nb * VEC + c) * LD + kb * VEC) = w;
+          }
         }
       }
     }

@@ -474,13 +474,20 @@ __global__ __launch_bounds__(WM* WN * 64) void pphi_kernel(PphiProb p, double* _
 hipError_t launch_pphi(const StepDims& d, int W, const double* P, const double2* phi_a_in,
                        const double2* phi_b_in, double* acc, double2* phi_a_out,
                        double2* phi_b_out, unsigned* tmax, int mode, hipStream_t s) {
-  constexpr int BM = 64, BN = 64, BK = 16, WM = 2, WN = 2;
   PphiProb p{P, d.N, d.ldP, d.ncolp, d.na, d.nb,
              reinterpret_cast<const double*>(phi_a_in), reinterpret_cast<const double*>(phi_b_in),
              acc, mode};
-  dim3 grid(ceil_div(d.N, BM), ceil_div(d.ncolp, BN), W);
-  hipLaunchKernelGGL((pphi_kernel<BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p, acc,
-                     phi_a_out, phi_b_out, tmax);
+  if (d.ncolp <= 112) {
+    constexpr int BM = 64, BN = 112, BK = 16, WM = 4, WN = 1;
+    dim3 grid(ceil_div(d.N, BM), 1, W);
+    hipLaunchKernelGGL((pphi_kernel<BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p, acc,
+                       phi_a_out, phi_b_out, tmax);
+  } else {
+    constexpr int BM = 64, BN = 64, BK = 16, WM = 2, WN = 2;
+    dim3 grid(ceil_div(d.N, BM), ceil_div(d.ncolp, BN), W);
+    hipLaunchKernelGGL((pphi_kernel<BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p, acc,
+                       phi_a_out, phi_b_out, tmax);
+  }
   return hipGetLastError();
 }
 
@@ -599,13 +606,22 @@ __global__ void taylor_last_kernel(int W, int N, int ncolp, int ncol, const T* _
 template <typename T>
 hipError_t launch_taylor(const StepDims& d, int W, const T* vhs, const T* t_in, T* t_out,
                          double* acc, const unsigned* tmax, int k, int order, hipStream_t s) {
-  constexpr int BM = 64, BN = 64, BK = sizeof(T) == 4 ? 32 : 16, WM = 2, WN = 2;
+  constexpr int BK = sizeof(T) == 4 ? 32 : 16;
   TaylorProb<T> p{vhs, d.N, d.ldV, d.ncolp, acc, t_in, tmax, k == 1 ? 1 : 0};
-  dim3 grid(ceil_div(d.N, BM), ceil_div(d.ncolp, BN), W);
   const int add_prev = k >= 2 ? 1 : 0;
   const int add_this = (k == order && k >= 2) ? 1 : 0;
-  hipLaunchKernelGGL((taylor_kernel<T, BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p,
-                     t_out, acc, d.ncol, 1.0 / k, add_prev, add_this);
+  if (d.ncolp <= 112) {
+    // all walker columns (both spins) in one tile: 4 waves of 16 rows x 112 columns
+    constexpr int BM = 64, BN = 112, WM = 4, WN = 1;
+    dim3 grid(ceil_div(d.N, BM), 1, W);
+    hipLaunchKernelGGL((taylor_kernel<T, BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p,
+                       t_out, acc, d.ncol, 1.0 / k, add_prev, add_this);
+  } else {
+    constexpr int BM = 64, BN = 64, WM = 2, WN = 2;
+    dim3 grid(ceil_div(d.N, BM), ceil_div(d.ncolp, BN), W);
+    hipLaunchKernelGGL((taylor_kernel<T, BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p,
+                       t_out, acc, d.ncol, 1.0 / k, add_prev, add_this);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !(k == order && k == 1)) return e;
   const size_t tot = (size_t)W * d.N * d.ncolp;

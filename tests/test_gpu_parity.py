@@ -199,8 +199,9 @@ def test_orthogonalise_matches_oracle(name, precision, uhf):
 def test_fused_step_matches_oracle(name, precision, uhf):
     """afqmc_step (propagate, QR, energy) against the oracle's step, teacher-forced
     on every step.  In FP64 the second call continues from the GPU state and
-    reuses its cached Green's function; in FP32 both calls start from the oracle
-    state, since the cache holds the GPU's own (FP32-rounded) walker."""
+    reuses its cached Green's function; in the mixed modes both calls start
+    from the oracle state, since the cache holds the GPU's own (FP32-rounded)
+    walker."""
     torch = _torch()
     c = case(name, precision, uhf)
     w = c.walkers()
@@ -216,7 +217,7 @@ def test_fused_step_matches_oracle(name, precision, uhf):
     # ~ 2 n 1e-5 cond(S'); the perturbed test walkers have cond(S') up to ~50
     tol_log = 1e-9 if precision == "fp64" else 1e-2
     for k in range(2):
-        if precision == "fp32":
+        if precision != "fp64":
             w = c.walkers(pa=pa, pb=pb, lo=lo, lw=lw)
         c.ham.step(w, torch.as_tensor(xs[k], device=c.dev), do_qr=True, energy_out=e,
                    reuse=(k > 0 and precision == "fp64"))
