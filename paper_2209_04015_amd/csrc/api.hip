@@ -58,12 +58,10 @@ struct afqmc_ham {
   double* hh = nullptr;     // [2][nmax][N]
   // hi/lo split operands of the 16-bit exchange (AFQMC_BF16X3 / AFQMC_FP16X3)
   int split = SPLIT_NONE;
-  unsigned short* lh_hi = nullptr;  // [2][K][nmax][ldh]
-  unsigned short* lh_lo = nullptr;
-  float* lh_scale = nullptr;        // [2][K][nmax]
-  unsigned short* th_hi = nullptr;  // [W][2][2][nmax][ldh]
-  unsigned short* th_lo = nullptr;
-  float* th_scale = nullptr;        // [W][2][2][nmax]
+  unsigned short* lh_split = nullptr;  // [2][K][nmax][2 ldh] split rows
+  float* lh_unscale = nullptr;           // [2][K][nmax]
+  unsigned short* th_split = nullptr;  // [W][2][2][nmax][2 ldh]
+  float* th_unscale = nullptr;           // [W][2][2][nmax]
   // workspace (sized for max_walkers)
   void* theta = nullptr;    // T [W][2][2][nmax][ldN]
   double2* logdet = nullptr;  // [W][2]
@@ -190,11 +188,11 @@ int seq_energy_from_theta(afqmc_ham* h, int nw, double2* e_out, hipStream_t s,
     const StepDims& d = h->d;
     PHASE(h, AFQMC_PH_SPLIT, s,
           launch_split_rows_mode(h->split, (long)nw * 4 * d.nmax, d.N, (const float*)h->theta, d.ldN,
-                                 h->th_hi, h->th_lo, d.ldh, h->th_scale, s));
+                                 h->th_split, d.ldh, h->th_unscale, s));
     for (int sp = 0; sp < 2; ++sp)
       PHASE(h, AFQMC_PH_EXCHANGE, s,
-            launch_exchange_split(h->split, d, nw, h->lh_hi, h->lh_lo, h->lh_scale, h->th_hi,
-                                  h->th_lo, h->th_scale, h->part, sp, &ntg, s, h->ex_gs));
+            launch_exchange_split(h->split, d, nw, h->lh_split, h->lh_unscale, h->th_split,
+                                  h->th_unscale, h->part, sp, &ntg, s, h->ex_gs));
   } else {
     for (int sp = 0; sp < 2; ++sp)
       PHASE(h, AFQMC_PH_EXCHANGE, s,
@@ -454,11 +452,10 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
   if (rc) return rc;
   if (h->split != SPLIT_NONE) {
     const size_t rows = (size_t)2 * K * nmax;
-    if ((rc = dalloc_t(h, &h->lh_hi, rows * d.ldh))) return rc;
-    if ((rc = dalloc_t(h, &h->lh_lo, rows * d.ldh))) return rc;
-    if ((rc = dalloc_t(h, &h->lh_scale, rows))) return rc;
-    HIP_TRY(launch_split_rows_mode(h->split, (long)rows, N, (const float*)h->Lh, d.ldN, h->lh_hi,
-                                   h->lh_lo, d.ldh, h->lh_scale, s));
+    if ((rc = dalloc_t(h, &h->lh_split, rows * 2 * d.ldh))) return rc;
+    if ((rc = dalloc_t(h, &h->lh_unscale, rows))) return rc;
+    HIP_TRY(launch_split_rows_mode(h->split, (long)rows, N, (const float*)h->Lh, d.ldN, h->lh_split,
+                                   d.ldh, h->lh_unscale, s));
   }
 
   // ---- workspace ----
@@ -487,9 +484,8 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
   if ((rc = dalloc_t(h, &h->status, (size_t)1))) return rc;
   if (h->split != SPLIT_NONE) {
     const size_t rows = wtheta * 4 * nmax;
-    if ((rc = dalloc_t(h, &h->th_hi, rows * d.ldh))) return rc;
-    if ((rc = dalloc_t(h, &h->th_lo, rows * d.ldh))) return rc;
-    if ((rc = dalloc_t(h, &h->th_scale, rows))) return rc;
+    if ((rc = dalloc_t(h, &h->th_split, rows * 2 * d.ldh))) return rc;
+    if ((rc = dalloc_t(h, &h->th_unscale, rows))) return rc;
   }
 
   // ---- E_T ----
@@ -964,7 +960,7 @@ int afqmc_autotune(afqmc_batch* b, const char* cache_path) {
     if (h->split != SPLIT_NONE) {
       const StepDims& d = h->d;
       HIP_TRY(launch_split_rows_mode(h->split, (long)b->nw[i] * 4 * d.nmax, d.N, (const float*)h->theta,
-                                     d.ldN, h->th_hi, h->th_lo, d.ldh, h->th_scale, s));
+                                     d.ldN, h->th_split, d.ldh, h->th_unscale, s));
     }
     float best = 1e30f;
     int best_gs = 0;
@@ -976,8 +972,8 @@ int afqmc_autotune(afqmc_batch* b, const char* cache_path) {
         for (int sp = 0; sp < 2; ++sp) {
           hipError_t he;
           if (h->split != SPLIT_NONE)
-            he = launch_exchange_split(h->split, h->d, b->nw[i], h->lh_hi, h->lh_lo, h->lh_scale,
-                                       h->th_hi, h->th_lo, h->th_scale, h->part, sp, &ntg, s, gs);
+            he = launch_exchange_split(h->split, h->d, b->nw[i], h->lh_split, h->lh_unscale,
+                                       h->th_split, h->th_unscale, h->part, sp, &ntg, s, gs);
           else if (h->prec != AFQMC_FP64)
             he = launch_exchange<float>(h->d, b->nw[i], (const float*)h->Lh, (const float*)h->theta,
                                         h->part, sp, &ntg, s, gs);

@@ -90,15 +90,14 @@ hipError_t launch_ortho_update(int W, const double* corr, double2* log_ovlp, hip
 hipError_t set_kernel_attributes(const StepDims& d);
 
 // --- hi/lo split contraction (split_kernels.hip) ----------------------------
-// rows of an FP32 matrix -> hi/lo 16-bit rows plus power-of-two row scales
+// rows of an FP32 matrix -> split rows (per block of 32 indices: 32 hi then
+// 32 lo 16-bit values, 2 ldh halves per row) plus the inverse power-of-two
+// row scales
 hipError_t launch_split_rows_mode(int mode, long nrows, int ncols, const float* src, int ld_src,
-                                  unsigned short* hi, unsigned short* lo, int ld_dst, float* scale,
-                                  hipStream_t s);
+                                  unsigned short* dst, int ldh, float* unscale, hipStream_t s);
 ExTile exchange_split_tile(int n);
-hipError_t launch_exchange_split(int mode, const StepDims& d, int W, const unsigned short* lh_hi,
-                                 const unsigned short* lh_lo, const float* lh_scale,
-                                 const unsigned short* th_hi, const unsigned short* th_lo,
-                                 const float* th_scale, double2* part, int sp, int* ntg_out,
-                                 hipStream_t s, int gs = 0);
+hipError_t launch_exchange_split(int mode, const StepDims& d, int W, const unsigned short* lh,
+                                 const float* lh_unscale, const unsigned short* th, const float* th_unscale,
+                                 double2* part, int sp, int* ntg_out, hipStream_t s, int gs = 0);
 hipError_t set_split_kernel_attributes();
 size_t qr_lds_bytes(const StepDims& d);

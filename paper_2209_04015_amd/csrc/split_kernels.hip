@@ -9,17 +9,19 @@
 #include "kernels.h"
 #include "split_tile.h"
 #include "tile_order.h"
-#include "exchange_epilogue.h"
+#include "exchange_tri.h"
 
 // ---------------------------------------------------------------------------
-// Row splitting: src rows (FP32, stride ld_src, ncols valid) -> hi/lo rows
-// (stride ld_dst, zero padded) and the power-of-two row scale.  One wave per row.
+// Row splitting: src rows (FP32, stride ld_src, ncols valid) -> split rows of
+// ldh (multiple of 32) contraction indices, stored per block of 32 as 32 hi
+// then 32 lo values (2 * ldh halves per row, zero padded), plus the inverse
+// of the power-of-two row scale (the factor that restores a product).  One
+// wave per row.
 // ---------------------------------------------------------------------------
 template <class H>
 __global__ __launch_bounds__(256) void split_rows_kernel(long nrows, int ncols, const float* __restrict__ src,
-                                                         int ld_src, unsigned short* __restrict__ hi,
-                                                         unsigned short* __restrict__ lo, int ld_dst,
-                                                         float* __restrict__ scale) {
+                                                         int ld_src, unsigned short* __restrict__ dst,
+                                                         int ldh, float* __restrict__ unscale) {
   const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= nrows) return;
@@ -29,119 +31,117 @@ __global__ __launch_bounds__(256) void split_rows_kernel(long nrows, int ncols, 
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
   const float sc = split_row_scale<H>(m);
-  unsigned short* h = hi + row * ld_dst;
-  unsigned short* l = lo + row * ld_dst;
-  for (int c = lane; c < ld_dst; c += 64) {
+  unsigned short* d = dst + row * 2 * ldh;
+  for (int c = lane; c < ldh; c += 64) {
     const float x = c < ncols ? s[c] * sc : 0.f;
     const unsigned short xh = H::from_float(x);
-    h[c] = xh;
-    l[c] = H::from_float(x - H::to_float(xh));
+    unsigned short* b = d + (c >> 5) * SPLIT_KB + (c & 31);
+    b[0] = xh;
+    b[32] = H::from_float(x - H::to_float(xh));
   }
-  if (lane == 0) scale[row] = sc;
+  if (lane == 0) unscale[row] = 1.0f / sc;  // power of two: exact
 }
 
 template <class H>
-hipError_t launch_split_rows(long nrows, int ncols, const float* src, int ld_src, unsigned short* hi,
-                             unsigned short* lo, int ld_dst, float* scale, hipStream_t s) {
+hipError_t launch_split_rows(long nrows, int ncols, const float* src, int ld_src, unsigned short* dst,
+                             int ldh, float* unscale, hipStream_t s) {
   if (nrows == 0) return hipSuccess;
+  if (ldh % 32 != 0 || ldh < ncols) return hipErrorInvalidValue;
   hipLaunchKernelGGL(split_rows_kernel<H>, dim3((unsigned)((nrows + 3) / 4)), dim3(256), 0, s, nrows,
-                     ncols, src, ld_src, hi, lo, ld_dst, scale);
+                     ncols, src, ld_src, dst, ldh, unscale);
   return hipGetLastError();
 }
 
 hipError_t launch_split_rows_mode(int mode, long nrows, int ncols, const float* src, int ld_src,
-                                  unsigned short* hi, unsigned short* lo, int ld_dst, float* scale,
-                                  hipStream_t s) {
-  return mode == SPLIT_BF16 ? launch_split_rows<HalfBF16>(nrows, ncols, src, ld_src, hi, lo, ld_dst, scale, s)
-                            : launch_split_rows<HalfF16>(nrows, ncols, src, ld_src, hi, lo, ld_dst, scale, s);
+                                  unsigned short* dst, int ldh, float* unscale, hipStream_t s) {
+  return mode == SPLIT_BF16 ? launch_split_rows<HalfBF16>(nrows, ncols, src, ld_src, dst, ldh, unscale, s)
+                            : launch_split_rows<HalfF16>(nrows, ncols, src, ld_src, dst, ldh, unscale, s);
 }
 
 // ---------------------------------------------------------------------------
 // Exchange on split operands.
 // ---------------------------------------------------------------------------
-// 4-wave workgroups, single-buffered LDS under 80 KB: two workgroups per CU.
+// 4-wave workgroups of 80 x 80 wave tiles; register prefetch of the next k
+// block, one LDS stage; two workgroups per CU, so that one workgroup's
+// epilogue runs beside the other's matrix-core work.
 struct ExSplitCfg {
-  static constexpr int BM = 192, BN = 160, BK = 32, WM = 2, WN = 2, GS = 8;
-  static constexpr int PIPE = 0;
-  static constexpr bool DBUF = false;
+  static constexpr int BM = 160, BN = 160, WM = 2, WN = 2, GS = 8;
+  static constexpr int NT = WM * WN * 64;
+  static constexpr int NA = BM * 8 / NT, NB = BN * 8 / NT;
   static constexpr int WAVES_PER_EU = 2;
 };
 
-struct ExSplitProb {
-  const unsigned short* a_hi;  // spin block [K][nmax][ldh]
-  const unsigned short* a_lo;
-  const float* a_scale;        // spin block [K][nmax]
-  const unsigned short* b_hi;  // theta [W][re|im][spin][nmax][ldh]
-  const unsigned short* b_lo;
-  const float* b_scale;        // [W][re|im][spin][nmax]
-  int K, W, n, nmax, ldh, sp, G, Z;
-  int gt, wt;
-  __device__ uint4 load_a(int r, int k, int part) const {
-    if (r >= G * n) return make_uint4(0, 0, 0, 0);
-    const int g = gt * G + r / n;
-    if (g >= K) return make_uint4(0, 0, 0, 0);
-    const unsigned short* base = part ? a_lo : a_hi;
-    return *reinterpret_cast<const uint4*>(base + ((size_t)g * nmax + r % n) * ldh + k);
-  }
-  __device__ size_t b_row(int c) const {  // -1 if outside
-    const int n2 = 2 * n;
-    const int z = wt * Z + c / n2;
-    const int cc = c % n2;
-    const int comp = cc >= n ? 1 : 0;
-    const int j = cc - comp * n;
-    return (((size_t)z * 2 + comp) * 2 + sp) * nmax + j;
-  }
-  __device__ uint4 load_b(int c, int k, int part) const {
-    if (c >= Z * 2 * n) return make_uint4(0, 0, 0, 0);
-    if (wt * Z + c / (2 * n) >= W) return make_uint4(0, 0, 0, 0);
-    const unsigned short* base = part ? b_lo : b_hi;
-    return *reinterpret_cast<const uint4*>(base + b_row(c) * ldh + k);
-  }
+struct ExSplitArgs {
+  const uint4* a;        // Lh split rows of this spin: [K][nmax][2 ldh] halves
+  const float* a_unscale;  // [K][nmax]
+  const uint4* b;        // theta split rows: [W][re|im][spin][nmax][2 ldh] halves
+  const float* b_unscale;  // [W][re|im][spin][nmax]
+  int K, W, n, nmax, rowv, sp, G, Z, nkb;  // rowv: uint4 per split row
 };
 
-constexpr size_t EXS_EPI_BUDGET = 64 * 1024;
+// LDS budget of the triangle store; with the operand stage this keeps a
+// workgroup under 80 KB (two per CU).
+constexpr size_t EXS_TRI_BUDGET = 64 * 1024;
 
 static int exs_walkers_per_pass(int G, int Z, int n) {
-  const size_t per = (size_t)G * n * (2 * n + 1) * sizeof(float);
-  int zp = (int)(EXS_EPI_BUDGET / per);
-  const int slots = 64 / (ExSplitCfg::WM * ExSplitCfg::WN);
-  if (zp > slots) zp = slots;
+  const size_t per = (size_t)ex_tri_block(G, n) * sizeof(float2);
+  int zp = (int)(EXS_TRI_BUDGET / per);
   if (zp < 1) zp = 1;
   return zp < Z ? zp : Z;
 }
 
-static size_t exs_tab_off(int G, int Z, int n) {
-  using C = ExSplitCfg;
-  const size_t stage = (C::DBUF ? 2 : 1) * (size_t)SplitLds<C::BM, C::BN, C::BK>::BYTES;
-  const size_t epi = (size_t)exs_walkers_per_pass(G, Z, n) * G * n * (2 * n + 1) * sizeof(float);
-  return (stage > epi ? stage : epi + 15) / 16 * 16;
-}
 static size_t exs_lds_bytes(int G, int Z, int n) {
-  return exs_tab_off(G, Z, n) + EX_TAB_BYTES + EX_RED_BYTES;
+  using C = ExSplitCfg;
+  size_t b = (size_t)SplitStage<C::BM, C::BN>::BYTES;
+  const size_t epi = (size_t)ex_tri_lds_bytes(exs_walkers_per_pass(G, Z, n), G, n, C::WM, C::BN);
+  if (epi > b) b = epi;
+  return (b + 15) / 16 * 16;
 }
 
 template <class H>
-__global__ __launch_bounds__(ExSplitCfg::WM* ExSplitCfg::WN * 64, ExSplitCfg::WAVES_PER_EU) void exchange_split_kernel(
-    ExSplitProb p0, double2* __restrict__ part, int ntg, int nwt, int tab_off, int zpp, int gs) {
+__global__ __launch_bounds__(ExSplitCfg::NT, ExSplitCfg::WAVES_PER_EU) void exchange_split_kernel(
+    ExSplitArgs p, double2* __restrict__ part, int ntg, int nwt, int zpp, int gs) {
   using C = ExSplitCfg;
-  constexpr int BM = C::BM, BN = C::BN, BK = C::BK, WM = C::WM, WN = C::WN;
-  ExSplitProb p = p0;
-  if (!xcd_tile(blockIdx.x, ntg, nwt, gs, p.gt, p.wt)) return;
+  int gt, wt;
+  if (!xcd_tile(blockIdx.x, ntg, nwt, gs, gt, wt)) return;
   extern __shared__ double2 exs_lds_raw[];
-  floatx4 acc[BM / WM / 16][BN / WN / 16];
-  split_tile_mainloop<H, BM, BN, BK, WM, WN, ExSplitProb, C::PIPE>(
-      p, p.ldh, acc, reinterpret_cast<unsigned short*>(exs_lds_raw));
-  const ExTileGeom q{p.n, p.G, p.Z, p.K, p.W, p.gt, p.wt};
-  const float* as = p.a_scale;
-  const float* bs = p.b_scale;
+  const int tid = threadIdx.x;
+  const int schunk = tid & 7, srow = tid >> 3;
+  const int n = p.n, n2 = 2 * n;
+  const float rn = 1.0f / (float)n, rn2 = 1.0f / (float)n2;
+  // rows staged by this thread (offsets in uint4, chunk included; -1 outside)
+  int a_off[C::NA], b_off[C::NB];
+#pragma unroll
+  for (int t = 0; t < C::NA; ++t) {
+    const int r = srow + t * (C::NT / 8);
+    const int gl = ex_div(r, rn);
+    const int g = gt * p.G + gl;
+    a_off[t] = (gl < p.G && g < p.K) ? (g * p.nmax + (r - gl * n)) * p.rowv + schunk : -1;
+  }
+#pragma unroll
+  for (int t = 0; t < C::NB; ++t) {
+    const int c = srow + t * (C::NT / 8);
+    const int zt = ex_div(c, rn2);
+    const int o = c - zt * n2;
+    const int comp = o >= n ? 1 : 0;
+    const int z = wt * p.Z + zt;
+    b_off[t] = (zt < p.Z && z < p.W)
+                   ? (((z * 2 + comp) * 2 + p.sp) * p.nmax + (o - comp * n)) * p.rowv + schunk
+                   : -1;
+  }
+  floatx4 acc[C::BM / C::WM / 16][C::BN / C::WN / 16];
+  split_tile_mainloop<H, C::BM, C::BN, C::WM, C::WN>(p.a, p.b, a_off, b_off, p.nkb, acc,
+                                                    reinterpret_cast<unsigned short*>(exs_lds_raw));
+  const ExTriGeom q{n, p.G, p.Z, p.K, p.W, gt, wt, p.nmax, p.sp, ntg};
+  const float* as = p.a_unscale;
+  const float* bs = p.b_unscale;
   const int nmax = p.nmax, sp = p.sp;
   auto rscale = [as, nmax](int g, int i) { return as[(size_t)g * nmax + i]; };
   auto cscale = [bs, nmax, sp](int z, int comp, int j) {
     return bs[(((size_t)z * 2 + comp) * 2 + sp) * nmax + j];
   };
-  exchange_epilogue<float, floatx4, BM, BN, WM, WN>(acc, reinterpret_cast<char*>(exs_lds_raw), tab_off,
-                                                   tab_off + EX_TAB_BYTES, q, zpp, H::SCALED, rscale,
-                                                   cscale, part, p.sp, ntg);
+  exchange_tri_epilogue<C::BM, C::BN, C::WM, C::WN, H::SCALED>(acc, reinterpret_cast<char*>(exs_lds_raw), zpp,
+                                                               q, rscale, cscale, part);
 }
 
 ExTile exchange_split_tile(int n) {
@@ -151,33 +151,35 @@ ExTile exchange_split_tile(int n) {
   return t;
 }
 
-hipError_t launch_exchange_split(int mode, const StepDims& d, int W, const unsigned short* lh_hi,
-                                 const unsigned short* lh_lo, const float* lh_scale,
-                                 const unsigned short* th_hi, const unsigned short* th_lo,
-                                 const float* th_scale, double2* part, int sp, int* ntg_out,
-                                 hipStream_t s, int gs) {
+hipError_t launch_exchange_split(int mode, const StepDims& d, int W, const unsigned short* lh,
+                                 const float* lh_unscale, const unsigned short* th, const float* th_unscale,
+                                 double2* part, int sp, int* ntg_out, hipStream_t s, int gs) {
   using C = ExSplitCfg;
   if (gs < 1) gs = C::GS;
   const ExTile t = exchange_split_tile(d.nmax);
-  if (t.G < 1 || t.Z < 1) return hipErrorInvalidValue;
+  if (t.G < 1 || t.Z < 1 || d.ldh % 32 != 0) return hipErrorInvalidValue;
   const int ntg = ceil_div(d.K, t.G);
   const int nwt = ceil_div(W, t.Z);
   *ntg_out = ntg;
   const int n = sp == 0 ? d.na : d.nb;
-  if (n == 0) return hipSuccess;
+  if (n == 0 || W == 0) return hipSuccess;
+  const int rowv = 2 * d.ldh / 8;
+  // 32-bit row offsets inside the kernel
+  if ((double)d.K * d.nmax * rowv >= 2147483647.0 || (double)W * 4 * d.nmax * rowv >= 2147483647.0)
+    return hipErrorInvalidValue;
   const size_t sblk = (size_t)d.K * d.nmax;
-  ExSplitProb p{lh_hi + sp * sblk * d.ldh, lh_lo + sp * sblk * d.ldh, lh_scale + sp * sblk,
-                th_hi, th_lo, th_scale, d.K, W, n, d.nmax, d.ldh, sp, t.G, t.Z, 0, 0};
+  ExSplitArgs p{reinterpret_cast<const uint4*>(lh + sp * sblk * 2 * d.ldh), lh_unscale + sp * sblk,
+                reinterpret_cast<const uint4*>(th), th_unscale, d.K, W, n, d.nmax, rowv, sp, t.G, t.Z,
+                d.ldh / 32};
   const size_t lds = exs_lds_bytes(t.G, t.Z, n);
-  const int tab_off = (int)exs_tab_off(t.G, t.Z, n);
   const int zpp = exs_walkers_per_pass(t.G, t.Z, n);
   const int per = ceil_div(ntg * nwt, 8);
   if (mode == SPLIT_BF16)
-    hipLaunchKernelGGL(exchange_split_kernel<HalfBF16>, dim3(8 * per), dim3(C::WM * C::WN * 64), lds, s,
-                       p, part, ntg, nwt, tab_off, zpp, gs);
+    hipLaunchKernelGGL(exchange_split_kernel<HalfBF16>, dim3(8 * per), dim3(C::NT), lds, s, p, part, ntg, nwt,
+                       zpp, gs);
   else
-    hipLaunchKernelGGL(exchange_split_kernel<HalfF16>, dim3(8 * per), dim3(C::WM * C::WN * 64), lds, s,
-                       p, part, ntg, nwt, tab_off, zpp, gs);
+    hipLaunchKernelGGL(exchange_split_kernel<HalfF16>, dim3(8 * per), dim3(C::NT), lds, s, p, part, ntg, nwt,
+                       zpp, gs);
   return hipGetLastError();
 }
 

@@ -7,6 +7,10 @@
 // FP16 and at 2^-16 relative for BF16), accumulated in FP32 by
 // v_mfma_f32_16x16x32_{bf16,f16}.
 //
+// Operand rows in memory: for every block of 32 contraction indices, 32 hi
+// values then the 32 matching lo values (128 bytes, one cache line), so one
+// k step of a tile reads whole lines.
+//
 // Lane layout of v_mfma_f32_16x16x32_*: lane l supplies row (or column)
 // l%16 and the eight consecutive k values 8*(l/16) .. 8*(l/16)+7 of a 32-wide
 // k chunk as one 16-byte LDS read; the output fragment is the same as the
@@ -62,35 +66,38 @@ __device__ __forceinline__ float split_row_scale(float rowmax) {
   }
 }
 
-// LDS footprint (16-bit elements) of one staged tile set (A_hi, A_lo, B_hi, B_lo).
-template <int BM, int BN, int BK>
-struct SplitLds {
-  static constexpr int LD = BK + 8;  // one 16-byte pad slot per row
-  static constexpr int ELEMS = 2 * (BM + BN) * LD;
-  static constexpr int BYTES = ELEMS * 2;
+// Half-precision elements per k block in memory (32 hi + 32 lo).
+constexpr int SPLIT_KB = 64;
+// LDS row of one staged k block: 64 halves plus one 16-byte pad slot, so
+// that the 16-byte fragment reads of 8 consecutive rows fall in 8 distinct
+// bank groups.
+constexpr int SPLIT_SLD = SPLIT_KB + 8;
+
+template <int BM, int BN>
+struct SplitStage {
+  static constexpr int BYTES = (BM + BN) * SPLIT_SLD * 2;
 };
 
-// Main loop of C[BM x BN] = A B^T with split operands.
-// Prob supplies (row, k) -> 16-byte vectors of 8 raw 16-bit values:
-//   uint4 load_a(int m, int k, int part) const   part 0 = hi, 1 = lo
-//   uint4 load_b(int n, int k, int part) const
-// returning zeros outside the problem.  k is a multiple of 8; kdim of 32.
-// PIPE as in mfma_tile.h: 0 no prefetch, 1 register prefetch, 2 + double-buffered LDS.
-template <class H, int BM, int BN, int BK, int WM, int WN, class Prob, int PIPE = 2>
-__device__ __forceinline__ void split_tile_mainloop(const Prob& prob, int kdim,
-                                                    floatx4 (&acc)[BM / WM / 16][BN / WN / 16],
+// Main loop of C[BM x BN] = A B^T with split operands, one k block (32
+// contraction indices) per stage, the next block prefetched into registers
+// while the matrix cores work on the current one.
+//   a_base / b_base: operand rows (uint4 units);
+//   a_off[t] / b_off[t]: uint4 offset of the row this thread stages in slot
+//   t (chunk included), or -1 for rows outside the problem (staged as zeros).
+// Thread tid stages chunk tid % 8 of rows tid / 8 + 32 t.
+template <class H, int BM, int BN, int WM, int WN>
+__device__ __forceinline__ void split_tile_mainloop(const uint4* __restrict__ a_base,
+                                                    const uint4* __restrict__ b_base,
+                                                    const int (&a_off)[BM * 8 / (WM * WN * 64)],
+                                                    const int (&b_off)[BN * 8 / (WM * WN * 64)],
+                                                    int nkb, floatx4 (&acc)[BM / WM / 16][BN / WN / 16],
                                                     unsigned short* lds) {
   constexpr int NT = WM * WN * 64;
   constexpr int FM = BM / WM / 16;
   constexpr int FN = BN / WN / 16;
-  constexpr int LD = SplitLds<BM, BN, BK>::LD;
-  constexpr int STAGE = SplitLds<BM, BN, BK>::ELEMS;
-  constexpr int KV = BK / 8;                // 16-byte vectors per row per part
-  constexpr int VA = 2 * BM * KV;           // hi and lo
-  constexpr int VB = 2 * BN * KV;
-  constexpr int NA = (VA + NT - 1) / NT;
-  constexpr int NB = (VB + NT - 1) / NT;
-  static_assert(BK % 32 == 0, "BK must be a multiple of 32");
+  constexpr int NA = BM * 8 / NT;
+  constexpr int NB = BN * 8 / NT;
+  static_assert(BM * 8 % NT == 0 && BN * 8 % NT == 0, "rows must split evenly over the threads");
   using vec8 = typename H::vec8;
 
   const int tid = threadIdx.x;
@@ -100,6 +107,7 @@ __device__ __forceinline__ void split_tile_mainloop(const Prob& prob, int kdim,
   const int wn = wid % WN;
   const int lrow = lane & 15;
   const int lk = 8 * (lane >> 4);
+  const int srow = tid >> 3, schunk = tid & 7;
 
 #pragma unroll
   for (int i = 0; i < FM; ++i)
@@ -107,105 +115,49 @@ __device__ __forceinline__ void split_tile_mainloop(const Prob& prob, int kdim,
     for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
   uint4 ra[NA], rb[NB];
-  auto fetch = [&](int k0) {
+  auto fetch = [&](int kb) {
+    const int o = kb * (SPLIT_KB / 8);
 #pragma unroll
-    for (int t = 0; t < NA; ++t) {
-      const int v = tid + t * NT;
-      ra[t] = make_uint4(0, 0, 0, 0);
-      if (v < VA) {
-        const int part = v / (BM * KV), w = v % (BM * KV);
-        const int r = w / KV, k = k0 + (w % KV) * 8;
-        if (k < kdim) ra[t] = prob.load_a(r, k, part);
-      }
-    }
+    for (int t = 0; t < NA; ++t) ra[t] = a_off[t] >= 0 ? a_base[a_off[t] + o] : make_uint4(0, 0, 0, 0);
 #pragma unroll
-    for (int t = 0; t < NB; ++t) {
-      const int v = tid + t * NT;
-      rb[t] = make_uint4(0, 0, 0, 0);
-      if (v < VB) {
-        const int part = v / (BN * KV), w = v % (BN * KV);
-        const int r = w / KV, k = k0 + (w % KV) * 8;
-        if (k < kdim) rb[t] = prob.load_b(r, k, part);
-      }
-    }
+    for (int t = 0; t < NB; ++t) rb[t] = b_off[t] >= 0 ? b_base[b_off[t] + o] : make_uint4(0, 0, 0, 0);
   };
-  // stage layout: A_hi [BM][LD], A_lo [BM][LD], B_hi [BN][LD], B_lo [BN][LD]
-  auto stash = [&](unsigned short* s) {
+  auto stash = [&]() {
 #pragma unroll
-    for (int t = 0; t < NA; ++t) {
-      const int v = tid + t * NT;
-      if (v < VA) {
-        const int part = v / (BM * KV), w = v % (BM * KV);
-        const int r = w / KV, k = (w % KV) * 8;
-        *reinterpret_cast<uint4*>(s + (part * BM + r) * LD + k) = ra[t];
-      }
-    }
+    for (int t = 0; t < NA; ++t)
+      *reinterpret_cast<uint4*>(lds + (srow + t * (NT / 8)) * SPLIT_SLD + schunk * 8) = ra[t];
 #pragma unroll
-    for (int t = 0; t < NB; ++t) {
-      const int v = tid + t * NT;
-      if (v < VB) {
-        const int part = v / (BN * KV), w = v % (BN * KV);
-        const int r = w / KV, k = (w % KV) * 8;
-        *reinterpret_cast<uint4*>(s + (2 * BM + part * BN + r) * LD + k) = rb[t];
-      }
-    }
+    for (int t = 0; t < NB; ++t)
+      *reinterpret_cast<uint4*>(lds + (BM + srow + t * (NT / 8)) * SPLIT_SLD + schunk * 8) = rb[t];
   };
-  auto compute = [&](const unsigned short* s, int k0) {
+  auto compute = [&]() {
+    vec8 ah[FM], al[FM];
 #pragma unroll
-    for (int kc = 0; kc < BK; kc += 32) {
-      if (k0 + kc >= kdim) break;
-      vec8 ah[FM], al[FM];
+    for (int i = 0; i < FM; ++i) {
+      const unsigned short* r = lds + (wm * (BM / WM) + i * 16 + lrow) * SPLIT_SLD + lk;
+      ah[i] = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r));
+      al[i] = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r + 32));
+    }
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const unsigned short* r = lds + (BM + wn * (BN / WN) + j * 16 + lrow) * SPLIT_SLD + lk;
+      const vec8 bh = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r));
+      const vec8 bl = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r + 32));
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
-        const int r = wm * (BM / WM) + i * 16 + lrow;
-        ah[i] = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(s + r * LD + kc + lk));
-        al[i] = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(s + (BM + r) * LD + kc + lk));
-      }
-#pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        const int r = wn * (BN / WN) + j * 16 + lrow;
-        const vec8 bh = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(s + (2 * BM + r) * LD + kc + lk));
-        const vec8 bl = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(s + (2 * BM + BN + r) * LD + kc + lk));
-#pragma unroll
-        for (int i = 0; i < FM; ++i) {
-          acc[i][j] = H::mma(al[i], bh, acc[i][j]);
-          acc[i][j] = H::mma(ah[i], bl, acc[i][j]);
-          acc[i][j] = H::mma(ah[i], bh, acc[i][j]);
-        }
+        acc[i][j] = H::mma(al[i], bh, acc[i][j]);
+        acc[i][j] = H::mma(ah[i], bl, acc[i][j]);
+        acc[i][j] = H::mma(ah[i], bh, acc[i][j]);
       }
     }
   };
 
-  if constexpr (PIPE == 0) {
-    for (int k0 = 0; k0 < kdim; k0 += BK) {
-      fetch(k0);
-      __syncthreads();
-      stash(lds);
-      __syncthreads();
-      compute(lds, k0);
-    }
-  } else if constexpr (PIPE == 1) {
-    fetch(0);
-    for (int k0 = 0; k0 < kdim; k0 += BK) {
-      __syncthreads();
-      stash(lds);
-      __syncthreads();
-      if (k0 + BK < kdim) fetch(k0 + BK);
-      compute(lds, k0);
-    }
-  } else {
-    fetch(0);
+  fetch(0);
+  for (int kb = 0; kb < nkb; ++kb) {
+    if (kb) __syncthreads();  // every wave is done with the previous stage
+    stash();
     __syncthreads();
-    stash(lds);
-    __syncthreads();
-    int cur = 0;
-    for (int k0 = 0; k0 < kdim; k0 += BK) {
-      const bool more = k0 + BK < kdim;
-      if (more) fetch(k0 + BK);
-      compute(lds + cur * STAGE, k0);
-      if (more) stash(lds + (cur ^ 1) * STAGE);
-      __syncthreads();
-      cur ^= 1;
-    }
+    if (kb + 1 < nkb) fetch(kb + 1);
+    compute();
   }
 }

@@ -477,17 +477,10 @@ hipError_t launch_pphi(const StepDims& d, int W, const double* P, const double2*
   PphiProb p{P, d.N, d.ldP, d.ncolp, d.na, d.nb,
              reinterpret_cast<const double*>(phi_a_in), reinterpret_cast<const double*>(phi_b_in),
              acc, mode};
-  if (d.ncolp <= 112) {
-    constexpr int BM = 64, BN = 112, BK = 16, WM = 4, WN = 1;
-    dim3 grid(ceil_div(d.N, BM), 1, W);
-    hipLaunchKernelGGL((pphi_kernel<BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p, acc,
-                       phi_a_out, phi_b_out, tmax);
-  } else {
-    constexpr int BM = 64, BN = 64, BK = 16, WM = 2, WN = 2;
-    dim3 grid(ceil_div(d.N, BM), ceil_div(d.ncolp, BN), W);
-    hipLaunchKernelGGL((pphi_kernel<BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p, acc,
-                       phi_a_out, phi_b_out, tmax);
-  }
+  constexpr int BM = 64, BN = 64, BK = 16, WM = 2, WN = 2;
+  dim3 grid(ceil_div(d.N, BM), ceil_div(d.ncolp, BN), W);
+  hipLaunchKernelGGL((pphi_kernel<BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p, acc,
+                     phi_a_out, phi_b_out, tmax);
   return hipGetLastError();
 }
 
@@ -610,18 +603,10 @@ hipError_t launch_taylor(const StepDims& d, int W, const T* vhs, const T* t_in, 
   TaylorProb<T> p{vhs, d.N, d.ldV, d.ncolp, acc, t_in, tmax, k == 1 ? 1 : 0};
   const int add_prev = k >= 2 ? 1 : 0;
   const int add_this = (k == order && k >= 2) ? 1 : 0;
-  if (d.ncolp <= 112) {
-    // all walker columns (both spins) in one tile: 4 waves of 16 rows x 112 columns
-    constexpr int BM = 64, BN = 112, WM = 4, WN = 1;
-    dim3 grid(ceil_div(d.N, BM), 1, W);
-    hipLaunchKernelGGL((taylor_kernel<T, BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p,
-                       t_out, acc, d.ncol, 1.0 / k, add_prev, add_this);
-  } else {
-    constexpr int BM = 64, BN = 64, WM = 2, WN = 2;
-    dim3 grid(ceil_div(d.N, BM), ceil_div(d.ncolp, BN), W);
-    hipLaunchKernelGGL((taylor_kernel<T, BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p,
-                       t_out, acc, d.ncol, 1.0 / k, add_prev, add_this);
-  }
+  constexpr int BM = 64, BN = 64, WM = 2, WN = 2;
+  dim3 grid(ceil_div(d.N, BM), ceil_div(d.ncolp, BN), W);
+  hipLaunchKernelGGL((taylor_kernel<T, BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p,
+                     t_out, acc, d.ncol, 1.0 / k, add_prev, add_this);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !(k == order && k == 1)) return e;
   const size_t tot = (size_t)W * d.N * d.ncolp;
