@@ -5,7 +5,7 @@
 //   sum_ij T_ij T_ji = sum_i T_ii^2 + 2 sum_{i<j} T_ij T_ji ,
 // so only the lower triangle (i >= j, complex) goes through LDS: its owners
 // store it, then the owners of i <= j read their partner T_ji from it and
-// accumulate in FP64.  Per column (z, re|im, j) a thread keeps
+// accumulate (FP32 FMAs over the 4 rows of a fragment, then FP64).  Per column (z, re|im, j) a thread keeps
 //   x = sum w v P.re,  y = sum w v P.im   (v its own element, P = T_ji,
 //   w = 2 off the diagonal, 1 on it),
 // and for a walker Re = sum_re-columns x - sum_im-columns y,
@@ -28,29 +28,36 @@ __device__ __forceinline__ int ex_div(int x, float rinv) {
   return (int)(((float)x + 0.5f) * rinv);
 }
 
-// Writes part[(sp * ntg + gt) * W + z] for the tile's walkers.  row_unscale(g,
-// i) and col_unscale(z, comp, j) give the power-of-two factors that undo the
-// operand scaling (used only if SCALED).  zpp walker slots per pass; LDS
-// needs ex_tri_lds_bytes.  Both passes are branch-free (masked lanes store
-// to a private dummy slot, or load a zero slot and weigh it by zero), so the
-// LDS accesses of a row issue back to back.
-__host__ __device__ inline int ex_tri_lds_bytes(int zpp, int G, int n, int WM, int BN) {
-  const int tri = zpp * ex_tri_block(G, n) * 8 + 64 * 4 + 16;  // + dummy slot per lane, zero slot
-  const int col = WM * BN * 16;
-  return tri > col ? tri : col;
+// LDS of the epilogue: [triangles zpp * blk * 8][dummy slot per lane 256]
+// [zero slot 16] ... [scale table (BM + BN) floats at tab_off]; the column
+// sums [4 row groups][WM][BN] double2 reuse the start.  tab_off lies past the
+// operand stage too, so the table can be filled while other waves still
+// read the stage.
+__host__ __device__ inline int ex_tri_area_bytes(int zpp, int G, int n) {
+  return zpp * ex_tri_block(G, n) * 8 + 64 * 4 + 16;
 }
+__host__ __device__ inline int ex_tri_colsum_bytes(int WM, int BN) { return 4 * WM * BN * 16; }
 
-template <int BM, int BN, int WM, int WN, bool SCALED, class RowScale, class ColScale>
+// Writes part[(sp * ntg + gt) * W + z] for the tile's walkers.  If SCALED,
+// pre_row / pre_col are this thread's entries of the scale table: the
+// factors that undo the operand scaling for tile row threadIdx.x (if < BM)
+// and tile column threadIdx.x (if < BN), 0 outside the problem.  zpp walker
+// slots per pass.  Both passes are branch-free (masked lanes store to a
+// private dummy slot, or load the zero slot), so the LDS accesses of a row
+// issue back to back.
+template <int BM, int BN, int WM, int WN, bool SCALED>
 __device__ __forceinline__ void exchange_tri_epilogue(floatx4 (&acc)[BM / WM / 16][BN / WN / 16],
-                                                      char* lds_raw, int zpp, const ExTriGeom& q,
-                                                      RowScale row_unscale, ColScale col_unscale,
+                                                      char* lds_raw, int tab_off, int zpp, const ExTriGeom& q,
+                                                      float pre_row, float pre_col,
                                                       double2* __restrict__ part) {
   constexpr int NT = WM * WN * 64;
   constexpr int NWAVE = NT / 64;
   constexpr int FM = BM / WM / 16;
   constexpr int FN = BN / WN / 16;
   constexpr int BIG = 1 << 20;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  static_assert(NT >= BM && NT >= BN, "one scale-table entry per thread");
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
   const int wm = wid / WN, wn = wid % WN;
   const int n = q.n, n2 = 2 * n;
   const int tri = n * (n + 1) / 2;
@@ -59,7 +66,12 @@ __device__ __forceinline__ void exchange_tri_epilogue(floatx4 (&acc)[BM / WM / 1
   const int rbase = wm * (BM / WM) + 4 * (lane >> 4);
   const unsigned dummy = (unsigned)(zpp * blk * 8 + lane * 4);  // byte offsets
   const unsigned zslot = (unsigned)(zpp * blk * 8 + 64 * 4);
+  float* tab = reinterpret_cast<float*>(lds_raw + tab_off);  // [BM] rows, [BN] columns
 
+  if constexpr (SCALED) {
+    if (tid < BM) tab[tid] = pre_row;
+    if (tid < BN) tab[BM + tid] = pre_col;
+  }
   // this thread's columns
   int cz[FN], cj[FN], cc[FN];
 #pragma unroll
@@ -73,29 +85,42 @@ __device__ __forceinline__ void exchange_tri_epilogue(floatx4 (&acc)[BM / WM / 1
     cj[f] = o - comp * n;
     cc[f] = comp;
   }
-  if constexpr (SCALED) {  // true T = acc * row factor * column factor (powers of two: exact)
-    float cs[FN];
+  // this thread's rows, one register each: bits 0-15 the row part of the
+  // load offset, 8 (gl tri + i) (below 64 KB), bits 16-23 i + 1 (0 outside)
+  unsigned rp[FM * 4];
 #pragma unroll
-    for (int f = 0; f < FN; ++f) cs[f] = cz[f] < BIG ? col_unscale(q.wt * q.Z + cz[f], cc[f], cj[f]) : 0.f;
+  for (int fi = 0; fi < FM; ++fi)
 #pragma unroll
-    for (int fi = 0; fi < FM; ++fi)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = rbase + fi * 16 + r;
-        const int gl = ex_div(row, rn);
-        const int g = q.gt * q.G + gl;
-        const float rs = (gl < q.G && g < q.K) ? row_unscale(g, row - gl * n) : 0.f;
-#pragma unroll
-        for (int f = 0; f < FN; ++f) acc[fi][f][r] *= rs * cs[f];
-      }
-  }
+    for (int r = 0; r < 4; ++r) {
+      const int row = rbase + fi * 16 + r;
+      const int gl = ex_div(row, rn);
+      const int i = row - gl * n;
+      const bool ok = gl < q.G && q.gt * q.G + gl < q.K;
+      rp[fi * 4 + r] = (ok ? (unsigned)(8 * (gl * tri + i)) : 0u) | ((ok ? (unsigned)(i + 1) : 0u) << 16);
+    }
   double2 s[FN];
 #pragma unroll
   for (int f = 0; f < FN; ++f) s[f] = make_double2(0.0, 0.0);
 
+  __syncthreads();  // LDS free (main loop done), scale table filled
+  if constexpr (SCALED) {  // true T = acc * row factor * column factor (powers of two: exact)
+    float cs[FN];
+#pragma unroll
+    for (int f = 0; f < FN; ++f) cs[f] = tab[BM + wn * (BN / WN) + f * 16 + (lane & 15)];
+#pragma unroll
+    for (int fi = 0; fi < FM; ++fi)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float rs = tab[rbase + fi * 16 + r];
+#pragma unroll
+        for (int f = 0; f < FN; ++f) acc[fi][f][r] *= rs * cs[f];
+      }
+  }
+
   for (int z0 = 0; z0 < q.Z; z0 += zpp) {
     // per pass and column: j bound for stores (i >= jw) and loads (i <= jr),
     // and the column's part of the LDS byte offsets
+    // (in terms of i + 1 as packed in rp)
     int jw[FN], jr[FN];
     unsigned cw[FN], cr[FN];
 #pragma unroll
@@ -103,90 +128,96 @@ __device__ __forceinline__ void exchange_tri_epilogue(floatx4 (&acc)[BM / WM / 1
       const int zl = cz[f] - z0;
       const bool in = zl >= 0 && zl < zpp;
       const int j = cj[f];
-      jw[f] = in ? j : BIG;
-      jr[f] = in ? j : -1;
+      jw[f] = in ? j + 1 : BIG;
+      jr[f] = in ? j + 1 : -1;
       cw[f] = in ? (unsigned)(8 * (zl * blk + j) + 4 * cc[f]) : 0u;
       cr[f] = in ? (unsigned)(8 * (zl * blk + j * (j + 1) / 2)) : 0u;
     }
-    // opaque per pass: keeps the per-row index arithmetic inside the pass
-    // loop (hoisted, it would hold registers per element)
-    int rb = rbase;
-    asm volatile("" : "+v"(rb));
-    __syncthreads();  // LDS free: main loop or previous pass done
-    if (threadIdx.x == 0) *reinterpret_cast<float2*>(lds_raw + zslot) = make_float2(0.f, 0.f);
+    // opaque per pass: the per-row values below stay inside the pass loop
+    // (hoisted, they would take registers per row and column)
+#pragma unroll
+    for (int e = 0; e < FM * 4; ++e) asm volatile("" : "+v"(rp[e]));
+    if (z0) __syncthreads();  // previous pass done with the LDS
+    if (tid == 0) *reinterpret_cast<float2*>(lds_raw + zslot) = make_float2(0.f, 0.f);
     // store the lower triangle (i >= j) of this pass's walker slots
 #pragma unroll
-    for (int fi = 0; fi < FM; ++fi)
+    for (int e = 0; e < FM * 4; ++e) {
+      const int i1 = (int)(rp[e] >> 16);
+      // 8 (gl tri + i (i + 1) / 2) = 8 (gl tri + i) + 4 i (i - 1)
+      const unsigned rw = (rp[e] & 0xffffu) + (unsigned)(4 * (i1 - 1) * (i1 - 2));
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = rb + fi * 16 + r;
-        const int gl = ex_div(row, rn);
-        const int i0 = row - gl * n;
-        const bool ok = gl < q.G && q.gt * q.G + gl < q.K;
-        const int i = ok ? i0 : -1;
-        const unsigned rw = (unsigned)(8 * (gl * tri + i0 * (i0 + 1) / 2));
-#pragma unroll
-        for (int f = 0; f < FN; ++f) {
-          const unsigned a = i >= jw[f] ? rw + cw[f] : dummy;
-          *reinterpret_cast<float*>(lds_raw + a) = acc[fi][f][r];
-        }
+      for (int f = 0; f < FN; ++f) {
+        const unsigned a = i1 >= jw[f] ? rw + cw[f] : dummy;  // i1 = 0 outside: never
+        *reinterpret_cast<float*>(lds_raw + a) = acc[e >> 2][f][e & 3];
       }
+    }
     __syncthreads();
-    // owners of i <= j pair with T_ji, weight 2 off the diagonal and 1 on it
-    // (the common factor 2 is applied at the end)
+    // halve the stored diagonal: below, every pair i < j counts once and the
+    // total is doubled
+    const int zn = min(zpp, q.Z - z0);
+    for (int e = tid; e < zn * q.G * n; e += NT) {
+      const int zg = ex_div(e, rn);
+      const int i = e - zg * n;
+      float2* d = reinterpret_cast<float2*>(lds_raw) + zg * tri + i * (i + 1) / 2 + i;
+      const float2 v = *d;
+      *d = make_float2(0.5f * v.x, 0.5f * v.y);
+    }
+    __syncthreads();
+    // owners of i <= j pair with T_ji: single-precision FMAs over the four
+    // rows of a fragment, added to the double-precision column sums
 #pragma unroll
-    for (int fi = 0; fi < FM; ++fi)
+    for (int fi = 0; fi < FM; ++fi) {
+      float2 t[FN];
+#pragma unroll
+      for (int f = 0; f < FN; ++f) t[f] = make_float2(0.f, 0.f);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = rb + fi * 16 + r;
-        const int gl = ex_div(row, rn);
-        const int i0 = row - gl * n;
-        const bool ok = gl < q.G && q.gt * q.G + gl < q.K;
-        const int i = ok ? i0 : BIG;
-        const unsigned rr = (unsigned)(8 * (gl * tri + i0));
+        const unsigned pr = rp[fi * 4 + r];
+        const int i1 = (int)(pr >> 16);
+        const int ir = i1 > 0 ? i1 : BIG;
+        const unsigned rr = pr & 0xffffu;
 #pragma unroll
         for (int f = 0; f < FN; ++f) {
-          const int d = jr[f] - i;  // > 0 above, 0 on, < 0 below the diagonal or masked
-          const unsigned a = d >= 0 ? rr + cr[f] : zslot;
+          const unsigned a = ir <= jr[f] ? rr + cr[f] : zslot;
           const float2 p = *reinterpret_cast<const float2*>(lds_raw + a);
-          const float t = (float)min(max(d, -1), 1);
-          const float v = 0.5f * fmaf(acc[fi][f][r], t, acc[fi][f][r]);  // 0, acc/2 or acc: exact
-          s[f].x = fma((double)v, (double)p.x, s[f].x);
-          s[f].y = fma((double)v, (double)p.y, s[f].y);
+          const float v = acc[fi][f][r];
+          t[f].x = fmaf(v, p.x, t[f].x);
+          t[f].y = fmaf(v, p.y, t[f].y);
         }
       }
+#pragma unroll
+      for (int f = 0; f < FN; ++f) {
+        s[f].x += (double)t[f].x;
+        s[f].y += (double)t[f].y;
+      }
+    }
   }
 
-  // column sums over the four row groups of the wave, then over the WM waves
+  // column sums: every lane's partial to LDS, then one wave per walker adds
+  // the 4 row groups x WM waves x 2n columns of its block in a fixed order
   __syncthreads();  // read passes done: LDS reused
-  double2* colsum = reinterpret_cast<double2*>(lds_raw);  // [WM][BN]
+  double2* colsum = reinterpret_cast<double2*>(lds_raw);  // [4][WM][BN]
 #pragma unroll
-  for (int f = 0; f < FN; ++f) {
-    double2 v = s[f];
-    v.x += __shfl_xor(v.x, 16, 64);
-    v.y += __shfl_xor(v.y, 16, 64);
-    v.x += __shfl_xor(v.x, 32, 64);
-    v.y += __shfl_xor(v.y, 32, 64);
-    if (lane < 16) colsum[wm * BN + wn * (BN / WN) + f * 16 + lane] = v;
-  }
+  for (int f = 0; f < FN; ++f)
+    colsum[((lane >> 4) * WM + wm) * BN + wn * (BN / WN) + f * 16 + (lane & 15)] = s[f];
   __syncthreads();
   for (int zt = wid; zt < q.Z; zt += NWAVE) {
     const int z = q.wt * q.Z + zt;
     if (z >= q.W) break;
     double2 t = make_double2(0.0, 0.0);
-    for (int w = 0; w < WM; ++w)
-      for (int o = lane; o < n2; o += 64) {
-        const double2 v = colsum[w * BN + zt * n2 + o];
-        if (o < n) {
-          t.x += v.x;
-          t.y += v.y;
-        } else {
-          t.x -= v.y;
-          t.y += v.x;
-        }
+    for (int o = lane; o < 4 * WM * n2; o += 64) {
+      const int gw = ex_div(o, rn2);  // row group x wave
+      const int cl = o - gw * n2;
+      const double2 v = colsum[gw * BN + zt * n2 + cl];
+      if (cl < n) {
+        t.x += v.x;
+        t.y += v.y;
+      } else {
+        t.x -= v.y;
+        t.y += v.x;
       }
+    }
     t = wave_sum2(t);
-    // weights above were 1 (off the diagonal) and 1/2 (on it) of the true 2 and 1
     if (lane == 0) part[((size_t)q.sp * q.ntg + q.gt) * q.W + z] = make_double2(2.0 * t.x, 2.0 * t.y);
   }
 }

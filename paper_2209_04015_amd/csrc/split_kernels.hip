@@ -90,17 +90,24 @@ static int exs_walkers_per_pass(int G, int Z, int n) {
   return zp < Z ? zp : Z;
 }
 
-static size_t exs_lds_bytes(int G, int Z, int n) {
+// Scale table offset: past the operand stage, the triangles and the column sums.
+static size_t exs_tab_off(int G, int Z, int n) {
   using C = ExSplitCfg;
   size_t b = (size_t)SplitStage<C::BM, C::BN>::BYTES;
-  const size_t epi = (size_t)ex_tri_lds_bytes(exs_walkers_per_pass(G, Z, n), G, n, C::WM, C::BN);
-  if (epi > b) b = epi;
+  const size_t tri = (size_t)ex_tri_area_bytes(exs_walkers_per_pass(G, Z, n), G, n);
+  const size_t col = (size_t)ex_tri_colsum_bytes(C::WM, C::BN);
+  if (tri > b) b = tri;
+  if (col > b) b = col;
   return (b + 15) / 16 * 16;
+}
+static size_t exs_lds_bytes(int G, int Z, int n) {
+  using C = ExSplitCfg;
+  return exs_tab_off(G, Z, n) + (C::BM + C::BN) * sizeof(float);
 }
 
 template <class H>
 __global__ __launch_bounds__(ExSplitCfg::NT, ExSplitCfg::WAVES_PER_EU) void exchange_split_kernel(
-    ExSplitArgs p, double2* __restrict__ part, int ntg, int nwt, int zpp, int gs) {
+    ExSplitArgs p, double2* __restrict__ part, int ntg, int nwt, int zpp, int tab_off, int gs) {
   using C = ExSplitCfg;
   int gt, wt;
   if (!xcd_tile(blockIdx.x, ntg, nwt, gs, gt, wt)) return;
@@ -129,19 +136,29 @@ __global__ __launch_bounds__(ExSplitCfg::NT, ExSplitCfg::WAVES_PER_EU) void exch
                    ? (((z * 2 + comp) * 2 + p.sp) * p.nmax + (o - comp * n)) * p.rowv + schunk
                    : -1;
   }
+  // operand scale factors of tile row / column tid, used by the epilogue
+  float pre_row = 0.f, pre_col = 0.f;
+  if constexpr (H::SCALED) {
+    if (tid < C::BM) {
+      const int gl = ex_div(tid, rn);
+      const int g = gt * p.G + gl;
+      if (gl < p.G && g < p.K) pre_row = p.a_unscale[(size_t)g * p.nmax + (tid - gl * n)];
+    }
+    if (tid < C::BN) {
+      const int zt = ex_div(tid, rn2);
+      const int o = tid - zt * n2;
+      const int comp = o >= n ? 1 : 0;
+      const int z = wt * p.Z + zt;
+      if (zt < p.Z && z < p.W)
+        pre_col = p.b_unscale[(((size_t)z * 2 + comp) * 2 + p.sp) * p.nmax + (o - comp * n)];
+    }
+  }
   floatx4 acc[C::BM / C::WM / 16][C::BN / C::WN / 16];
   split_tile_mainloop<H, C::BM, C::BN, C::WM, C::WN>(p.a, p.b, a_off, b_off, p.nkb, acc,
                                                     reinterpret_cast<unsigned short*>(exs_lds_raw));
   const ExTriGeom q{n, p.G, p.Z, p.K, p.W, gt, wt, p.nmax, p.sp, ntg};
-  const float* as = p.a_unscale;
-  const float* bs = p.b_unscale;
-  const int nmax = p.nmax, sp = p.sp;
-  auto rscale = [as, nmax](int g, int i) { return as[(size_t)g * nmax + i]; };
-  auto cscale = [bs, nmax, sp](int z, int comp, int j) {
-    return bs[(((size_t)z * 2 + comp) * 2 + sp) * nmax + j];
-  };
-  exchange_tri_epilogue<C::BM, C::BN, C::WM, C::WN, H::SCALED>(acc, reinterpret_cast<char*>(exs_lds_raw), zpp,
-                                                               q, rscale, cscale, part);
+  exchange_tri_epilogue<C::BM, C::BN, C::WM, C::WN, H::SCALED>(acc, reinterpret_cast<char*>(exs_lds_raw), tab_off,
+                                                               zpp, q, pre_row, pre_col, part);
 }
 
 ExTile exchange_split_tile(int n) {
@@ -172,14 +189,15 @@ hipError_t launch_exchange_split(int mode, const StepDims& d, int W, const unsig
                 reinterpret_cast<const uint4*>(th), th_unscale, d.K, W, n, d.nmax, rowv, sp, t.G, t.Z,
                 d.ldh / 32};
   const size_t lds = exs_lds_bytes(t.G, t.Z, n);
+  const int tab_off = (int)exs_tab_off(t.G, t.Z, n);
   const int zpp = exs_walkers_per_pass(t.G, t.Z, n);
   const int per = ceil_div(ntg * nwt, 8);
   if (mode == SPLIT_BF16)
     hipLaunchKernelGGL(exchange_split_kernel<HalfBF16>, dim3(8 * per), dim3(C::NT), lds, s, p, part, ntg, nwt,
-                       zpp, gs);
+                       zpp, tab_off, gs);
   else
     hipLaunchKernelGGL(exchange_split_kernel<HalfF16>, dim3(8 * per), dim3(C::NT), lds, s, p, part, ntg, nwt,
-                       zpp, gs);
+                       zpp, tab_off, gs);
   return hipGetLastError();
 }
 
