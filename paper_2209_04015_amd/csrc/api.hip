@@ -375,7 +375,6 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
   h->split = p.precision == AFQMC_BF16X3 ? SPLIT_BF16 : (p.precision == AFQMC_FP16X3 ? SPLIT_F16 : SPLIT_NONE);
   h->sdt = sqrt(p.dt);
   HIP_TRY(set_kernel_attributes(d));
-  HIP_TRY(set_split_kernel_attributes());
 
   const int N = d.N, K = d.K, nmax = d.nmax;
   const size_t NN = (size_t)N * N;

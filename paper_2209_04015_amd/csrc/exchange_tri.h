@@ -28,6 +28,11 @@ __device__ __forceinline__ int ex_div(int x, float rinv) {
   return (int)(((float)x + 0.5f) * rinv);
 }
 
+// Small non-negative index products (operands below 2^23): full-rate 24-bit
+// multiplies, and i (i + 1) / 2 by a shift.
+__device__ __forceinline__ int ex_mul(int a, int b) { return (int)__umul24((unsigned)a, (unsigned)b); }
+__device__ __forceinline__ int ex_tri(int i) { return (int)(__umul24((unsigned)i, (unsigned)(i + 1)) >> 1); }
+
 // LDS of the epilogue: [triangles zpp * blk * 8][dummy slot per lane 256]
 // [zero slot 16] ... [scale table (BM + BN) floats at tab_off]; the column
 // sums [4 row groups][WM][BN] double2 reuse the start.  tab_off lies past the
@@ -78,9 +83,9 @@ __device__ __forceinline__ void exchange_tri_epilogue(floatx4 (&acc)[BM / WM / 1
   for (int f = 0; f < FN; ++f) {
     const int c = wn * (BN / WN) + f * 16 + (lane & 15);
     const int zt = ex_div(c, rn2);
-    const int o = c - zt * n2;
+    const int o = c - ex_mul(zt, n2);
     const int comp = o >= n ? 1 : 0;
-    const int z = q.wt * q.Z + zt;
+    const int z = ex_mul(q.wt, q.Z) + zt;
     cz[f] = (zt < q.Z && z < q.W) ? zt : BIG;  // outside every pass
     cj[f] = o - comp * n;
     cc[f] = comp;
@@ -94,9 +99,9 @@ __device__ __forceinline__ void exchange_tri_epilogue(floatx4 (&acc)[BM / WM / 1
     for (int r = 0; r < 4; ++r) {
       const int row = rbase + fi * 16 + r;
       const int gl = ex_div(row, rn);
-      const int i = row - gl * n;
-      const bool ok = gl < q.G && q.gt * q.G + gl < q.K;
-      rp[fi * 4 + r] = (ok ? (unsigned)(8 * (gl * tri + i)) : 0u) | ((ok ? (unsigned)(i + 1) : 0u) << 16);
+      const int i = row - ex_mul(gl, n);
+      const bool ok = gl < q.G && ex_mul(q.gt, q.G) + gl < q.K;
+      rp[fi * 4 + r] = (ok ? (unsigned)(8 * (ex_mul(gl, tri) + i)) : 0u) | ((ok ? (unsigned)(i + 1) : 0u) << 16);
     }
   double2 s[FN];
 #pragma unroll
@@ -130,8 +135,8 @@ __device__ __forceinline__ void exchange_tri_epilogue(floatx4 (&acc)[BM / WM / 1
       const int j = cj[f];
       jw[f] = in ? j + 1 : BIG;
       jr[f] = in ? j + 1 : -1;
-      cw[f] = in ? (unsigned)(8 * (zl * blk + j) + 4 * cc[f]) : 0u;
-      cr[f] = in ? (unsigned)(8 * (zl * blk + j * (j + 1) / 2)) : 0u;
+      cw[f] = in ? (unsigned)(8 * (ex_mul(zl, blk) + j) + 4 * cc[f]) : 0u;
+      cr[f] = in ? (unsigned)(8 * (ex_mul(zl, blk) + ex_tri(j))) : 0u;
     }
     // opaque per pass: the per-row values below stay inside the pass loop
     // (hoisted, they would take registers per row and column)
@@ -144,7 +149,7 @@ __device__ __forceinline__ void exchange_tri_epilogue(floatx4 (&acc)[BM / WM / 1
     for (int e = 0; e < FM * 4; ++e) {
       const int i1 = (int)(rp[e] >> 16);
       // 8 (gl tri + i (i + 1) / 2) = 8 (gl tri + i) + 4 i (i - 1)
-      const unsigned rw = (rp[e] & 0xffffu) + (unsigned)(4 * (i1 - 1) * (i1 - 2));
+      const unsigned rw = (rp[e] & 0xffffu) + 8u * (unsigned)ex_tri(i1 - 2);  // masked if i1 = 0
 #pragma unroll
       for (int f = 0; f < FN; ++f) {
         const unsigned a = i1 >= jw[f] ? rw + cw[f] : dummy;  // i1 = 0 outside: never
@@ -157,8 +162,8 @@ __device__ __forceinline__ void exchange_tri_epilogue(floatx4 (&acc)[BM / WM / 1
     const int zn = min(zpp, q.Z - z0);
     for (int e = tid; e < zn * q.G * n; e += NT) {
       const int zg = ex_div(e, rn);
-      const int i = e - zg * n;
-      float2* d = reinterpret_cast<float2*>(lds_raw) + zg * tri + i * (i + 1) / 2 + i;
+      const int i = e - ex_mul(zg, n);
+      float2* d = reinterpret_cast<float2*>(lds_raw) + ex_mul(zg, tri) + ex_tri(i) + i;
       const float2 v = *d;
       *d = make_float2(0.5f * v.x, 0.5f * v.y);
     }

@@ -99,5 +99,4 @@ ExTile exchange_split_tile(int n);
 hipError_t launch_exchange_split(int mode, const StepDims& d, int W, const unsigned short* lh,
                                  const float* lh_unscale, const unsigned short* th, const float* th_unscale,
                                  double2* part, int sp, int* ntg_out, hipStream_t s, int gs = 0);
-hipError_t set_split_kernel_attributes();
 size_t qr_lds_bytes(const StepDims& d);

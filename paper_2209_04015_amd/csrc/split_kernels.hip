@@ -72,58 +72,48 @@ struct ExSplitCfg {
 };
 
 struct ExSplitArgs {
-  const uint4* a;        // Lh split rows of this spin: [K][nmax][2 ldh] halves
-  const float* a_unscale;  // [K][nmax]
-  const uint4* b;        // theta split rows: [W][re|im][spin][nmax][2 ldh] halves
-  const float* b_unscale;  // [W][re|im][spin][nmax]
-  int K, W, n, nmax, rowv, sp, G, Z, nkb;  // rowv: uint4 per split row
+  const unsigned short* a;  // Lh split rows of this spin: [K][nmax][2 ldh] halves
+  const float* a_unscale;   // [K][nmax]
+  const unsigned short* b;  // theta split rows: [W][re|im][spin][nmax][2 ldh] halves
+  const float* b_unscale;   // [W][re|im][spin][nmax]
+  int a_bytes, b_bytes;     // sizes of the two row blocks
+  int K, W, n, nmax, rowb, sp, G, Z, nkb;  // rowb: bytes per split row
 };
 
-// LDS budget of the triangle store; with the operand stage this keeps a
-// workgroup under 80 KB (two per CU).
-constexpr size_t EXS_TRI_BUDGET = 64 * 1024;
+// Static LDS of a workgroup (base address 0, so offsets fold into the LDS
+// instructions): the operand stage, or the triangles and column sums, then
+// the scale table at the end.  64 KB: two workgroups per CU.
+constexpr int EXS_LDS_BYTES = 64 * 1024;
+constexpr int EXS_TAB_OFF = EXS_LDS_BYTES - (ExSplitCfg::BM + ExSplitCfg::BN) * (int)sizeof(float);
+static_assert(SplitStage<ExSplitCfg::BM, ExSplitCfg::BN>::BYTES <= EXS_TAB_OFF, "operand stage fits");
+static_assert(4 * ExSplitCfg::WM * ExSplitCfg::BN * 16 <= EXS_TAB_OFF, "column sums fit");
 
+// Walker slots per epilogue pass (0 if one slot does not fit).
 static int exs_walkers_per_pass(int G, int Z, int n) {
-  const size_t per = (size_t)ex_tri_block(G, n) * sizeof(float2);
-  int zp = (int)(EXS_TRI_BUDGET / per);
-  if (zp < 1) zp = 1;
+  const int per = ex_tri_block(G, n) * (int)sizeof(float2);
+  const int zp = (EXS_TAB_OFF - ex_tri_area_bytes(0, G, n)) / per;
   return zp < Z ? zp : Z;
-}
-
-// Scale table offset: past the operand stage, the triangles and the column sums.
-static size_t exs_tab_off(int G, int Z, int n) {
-  using C = ExSplitCfg;
-  size_t b = (size_t)SplitStage<C::BM, C::BN>::BYTES;
-  const size_t tri = (size_t)ex_tri_area_bytes(exs_walkers_per_pass(G, Z, n), G, n);
-  const size_t col = (size_t)ex_tri_colsum_bytes(C::WM, C::BN);
-  if (tri > b) b = tri;
-  if (col > b) b = col;
-  return (b + 15) / 16 * 16;
-}
-static size_t exs_lds_bytes(int G, int Z, int n) {
-  using C = ExSplitCfg;
-  return exs_tab_off(G, Z, n) + (C::BM + C::BN) * sizeof(float);
 }
 
 template <class H>
 __global__ __launch_bounds__(ExSplitCfg::NT, ExSplitCfg::WAVES_PER_EU) void exchange_split_kernel(
-    ExSplitArgs p, double2* __restrict__ part, int ntg, int nwt, int zpp, int tab_off, int gs) {
+    ExSplitArgs p, double2* __restrict__ part, int ntg, int nwt, int zpp, int gs) {
   using C = ExSplitCfg;
   int gt, wt;
   if (!xcd_tile(blockIdx.x, ntg, nwt, gs, gt, wt)) return;
-  extern __shared__ double2 exs_lds_raw[];
+  __shared__ __attribute__((aligned(16))) char exs_lds[EXS_LDS_BYTES];
   const int tid = threadIdx.x;
   const int schunk = tid & 7, srow = tid >> 3;
   const int n = p.n, n2 = 2 * n;
   const float rn = 1.0f / (float)n, rn2 = 1.0f / (float)n2;
-  // rows staged by this thread (offsets in uint4, chunk included; -1 outside)
+  // rows staged by this thread (byte offsets, chunk included)
   int a_off[C::NA], b_off[C::NB];
 #pragma unroll
   for (int t = 0; t < C::NA; ++t) {
     const int r = srow + t * (C::NT / 8);
     const int gl = ex_div(r, rn);
     const int g = gt * p.G + gl;
-    a_off[t] = (gl < p.G && g < p.K) ? (g * p.nmax + (r - gl * n)) * p.rowv + schunk : -1;
+    a_off[t] = (gl < p.G && g < p.K) ? (g * p.nmax + (r - gl * n)) * p.rowb + schunk * 16 : SPLIT_ROW_NONE;
   }
 #pragma unroll
   for (int t = 0; t < C::NB; ++t) {
@@ -133,8 +123,8 @@ __global__ __launch_bounds__(ExSplitCfg::NT, ExSplitCfg::WAVES_PER_EU) void exch
     const int comp = o >= n ? 1 : 0;
     const int z = wt * p.Z + zt;
     b_off[t] = (zt < p.Z && z < p.W)
-                   ? (((z * 2 + comp) * 2 + p.sp) * p.nmax + (o - comp * n)) * p.rowv + schunk
-                   : -1;
+                   ? (((z * 2 + comp) * 2 + p.sp) * p.nmax + (o - comp * n)) * p.rowb + schunk * 16
+                   : SPLIT_ROW_NONE;
   }
   // operand scale factors of tile row / column tid, used by the epilogue
   float pre_row = 0.f, pre_col = 0.f;
@@ -154,11 +144,12 @@ __global__ __launch_bounds__(ExSplitCfg::NT, ExSplitCfg::WAVES_PER_EU) void exch
     }
   }
   floatx4 acc[C::BM / C::WM / 16][C::BN / C::WN / 16];
-  split_tile_mainloop<H, C::BM, C::BN, C::WM, C::WN>(p.a, p.b, a_off, b_off, p.nkb, acc,
-                                                    reinterpret_cast<unsigned short*>(exs_lds_raw));
+  split_tile_mainloop<H, C::BM, C::BN, C::WM, C::WN>(split_rsrc(p.a, p.a_bytes), split_rsrc(p.b, p.b_bytes),
+                                                    a_off, b_off, p.nkb, acc,
+                                                    reinterpret_cast<unsigned short*>(exs_lds));
   const ExTriGeom q{n, p.G, p.Z, p.K, p.W, gt, wt, p.nmax, p.sp, ntg};
-  exchange_tri_epilogue<C::BM, C::BN, C::WM, C::WN, H::SCALED>(acc, reinterpret_cast<char*>(exs_lds_raw), tab_off,
-                                                               zpp, q, pre_row, pre_col, part);
+  exchange_tri_epilogue<C::BM, C::BN, C::WM, C::WN, H::SCALED>(acc, exs_lds, EXS_TAB_OFF, zpp, q, pre_row,
+                                                               pre_col, part);
 }
 
 ExTile exchange_split_tile(int n) {
@@ -180,31 +171,21 @@ hipError_t launch_exchange_split(int mode, const StepDims& d, int W, const unsig
   *ntg_out = ntg;
   const int n = sp == 0 ? d.na : d.nb;
   if (n == 0 || W == 0) return hipSuccess;
-  const int rowv = 2 * d.ldh / 8;
-  // 32-bit row offsets inside the kernel
-  if ((double)d.K * d.nmax * rowv >= 2147483647.0 || (double)W * 4 * d.nmax * rowv >= 2147483647.0)
-    return hipErrorInvalidValue;
+  const int rowb = 2 * d.ldh * 2;
+  // byte offsets and buffer sizes below 2^31 (one bounds-checked buffer per operand)
+  const double a_bytes = (double)d.K * d.nmax * rowb, b_bytes = (double)W * 4 * d.nmax * rowb;
+  if (a_bytes >= (double)SPLIT_ROW_NONE || b_bytes >= (double)SPLIT_ROW_NONE) return hipErrorInvalidValue;
   const size_t sblk = (size_t)d.K * d.nmax;
-  ExSplitArgs p{reinterpret_cast<const uint4*>(lh + sp * sblk * 2 * d.ldh), lh_unscale + sp * sblk,
-                reinterpret_cast<const uint4*>(th), th_unscale, d.K, W, n, d.nmax, rowv, sp, t.G, t.Z,
-                d.ldh / 32};
-  const size_t lds = exs_lds_bytes(t.G, t.Z, n);
-  const int tab_off = (int)exs_tab_off(t.G, t.Z, n);
+  ExSplitArgs p{lh + sp * sblk * 2 * d.ldh, lh_unscale + sp * sblk, th, th_unscale, (int)a_bytes,
+                (int)b_bytes, d.K, W, n, d.nmax, rowb, sp, t.G, t.Z, d.ldh / 32};
   const int zpp = exs_walkers_per_pass(t.G, t.Z, n);
+  if (zpp < 1) return hipErrorInvalidValue;
   const int per = ceil_div(ntg * nwt, 8);
   if (mode == SPLIT_BF16)
-    hipLaunchKernelGGL(exchange_split_kernel<HalfBF16>, dim3(8 * per), dim3(C::NT), lds, s, p, part, ntg, nwt,
-                       zpp, tab_off, gs);
+    hipLaunchKernelGGL(exchange_split_kernel<HalfBF16>, dim3(8 * per), dim3(C::NT), 0, s, p, part, ntg, nwt,
+                       zpp, gs);
   else
-    hipLaunchKernelGGL(exchange_split_kernel<HalfF16>, dim3(8 * per), dim3(C::NT), lds, s, p, part, ntg, nwt,
-                       zpp, tab_off, gs);
+    hipLaunchKernelGGL(exchange_split_kernel<HalfF16>, dim3(8 * per), dim3(C::NT), 0, s, p, part, ntg, nwt,
+                       zpp, gs);
   return hipGetLastError();
-}
-
-hipError_t set_split_kernel_attributes() {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(exchange_split_kernel<HalfBF16>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(exchange_split_kernel<HalfF16>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }

@@ -78,16 +78,27 @@ struct SplitStage {
   static constexpr int BYTES = (BM + BN) * SPLIT_SLD * 2;
 };
 
+// Byte offset that lies outside every operand buffer: a bounds-checked
+// buffer load from it returns zeros.
+constexpr int SPLIT_ROW_NONE = 0x7fffffff;
+
+// Buffer resource over n_bytes (< 2^31) of split rows: raw (stride 0),
+// bounds-checked loads.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t split_rsrc(const void* base, int n_bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n_bytes, 0x00020000);
+}
+
 // Main loop of C[BM x BN] = A B^T with split operands, one k block (32
 // contraction indices) per stage, the next block prefetched into registers
 // while the matrix cores work on the current one.
-//   a_base / b_base: operand rows (uint4 units);
-//   a_off[t] / b_off[t]: uint4 offset of the row this thread stages in slot
-//   t (chunk included), or -1 for rows outside the problem (staged as zeros).
+//   a_rsrc / b_rsrc: buffer resources over the operand rows;
+//   a_off[t] / b_off[t]: byte offset of the 16-byte chunk this thread stages
+//   in slot t for the first k block, or SPLIT_ROW_NONE for rows outside the
+//   problem (the bounds check stages zeros).  k block kb lies kb * 128 bytes
+//   further (scalar offset).
 // Thread tid stages chunk tid % 8 of rows tid / 8 + 32 t.
 template <class H, int BM, int BN, int WM, int WN>
-__device__ __forceinline__ void split_tile_mainloop(const uint4* __restrict__ a_base,
-                                                    const uint4* __restrict__ b_base,
+__device__ __forceinline__ void split_tile_mainloop(__amdgpu_buffer_rsrc_t a_rsrc, __amdgpu_buffer_rsrc_t b_rsrc,
                                                     const int (&a_off)[BM * 8 / (WM * WN * 64)],
                                                     const int (&b_off)[BN * 8 / (WM * WN * 64)],
                                                     int nkb, floatx4 (&acc)[BM / WM / 16][BN / WN / 16],
@@ -116,11 +127,13 @@ __device__ __forceinline__ void split_tile_mainloop(const uint4* __restrict__ a_
 
   uint4 ra[NA], rb[NB];
   auto fetch = [&](int kb) {
-    const int o = kb * (SPLIT_KB / 8);
+    const int o = kb * (SPLIT_KB * 2);
 #pragma unroll
-    for (int t = 0; t < NA; ++t) ra[t] = a_off[t] >= 0 ? a_base[a_off[t] + o] : make_uint4(0, 0, 0, 0);
+    for (int t = 0; t < NA; ++t)
+      ra[t] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(a_rsrc, a_off[t], o, 0));
 #pragma unroll
-    for (int t = 0; t < NB; ++t) rb[t] = b_off[t] >= 0 ? b_base[b_off[t] + o] : make_uint4(0, 0, 0, 0);
+    for (int t = 0; t < NB; ++t)
+      rb[t] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(b_rsrc, b_off[t], o, 0));
   };
   auto stash = [&]() {
 #pragma unroll
