@@ -90,6 +90,47 @@ def run_gpu(cfg, h1, L, phiT, precision, steps, warmup, fields_dev, device):
     return ham, w, e, ms, phases, status
 
 
+# Sources that define each roofline kernel: its HBM traffic figure (from the
+# rocprofv3 counter summaries under profiles/) is used only while these are
+# unchanged since the counters were taken.
+KERNEL_SOURCES = {
+    "exchange_split_kernel": ["split_kernels.hip", "split_tile.h", "exchange_tri.h", "tile_order.h", "common.h"],
+    "exchange_kernel": ["step_kernels.hip", "mfma_tile.h", "exchange_epilogue.h", "tile_order.h", "common.h"],
+}
+
+
+def kernel_sources_sha256(kernel):
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2209_04015_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def hbm_traffic(kernel, instance, workload):
+    """HBM bytes per launch of `instance` on `workload` from the committed counter
+    summaries (lines 'hbm-traffic <instance> <workload> bytes_per_launch=...
+    sources_sha256=...'), or None if absent or the kernel changed since."""
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    sha = kernel_sources_sha256(kernel)
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith("_hbm.md"):
+            continue
+        with open(os.path.join(pdir, name)) as fh:
+            for line in fh:
+                f = line.strip().strip("`").split()
+                if len(f) < 4 or f[0] != "hbm-traffic" or f[1] != instance or f[2] != workload:
+                    continue
+                kv = dict(x.split("=", 1) for x in f[3:] if "=" in x)
+                if kv.get("sources_sha256") == sha:
+                    return int(kv["bytes_per_launch"])
+    return None
+
+
 def roofline(cfg, phases, precision):
     ms, launches = phases["exchange"]
     if launches == 0:
@@ -101,13 +142,16 @@ def roofline(cfg, phases, precision):
     note = None
     if precision in ("fp32", "fp64"):
         peak = PEAK_TFLOPS[precision]
+        instance = {"fp32": "exchange_kernel<float>", "fp64": "exchange_kernel<double>"}[precision]
     else:
         # three 16-bit products per algorithmic multiply-add
         peak = round(PEAK_TFLOPS[precision[:4]] / 3.0, 1)
         kernel = "exchange_split_kernel"
+        instance = {"fp16x3": "exchange_split_kernel<HalfF16>", "bf16x3": "exchange_split_kernel<HalfBF16>"}[precision]
         note = f"{precision[:4]} dense peak / 3 products"
     out = {"kernel": kernel, "bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
-           "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+           "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+           "traffic": hbm_traffic(kernel, instance, cfg.name),
            "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": flops}
     if note:
         out["peak_note"] = note
