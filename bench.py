@@ -289,7 +289,8 @@ def main():
                     "ms_per_step": round(ms / args.steps, 4), "roofline": roofline(cfg, ph, p),
                     "phases_ms_per_step": phase_table(ph), "status": st,
                     "energy_error_vs_fp64_oracle": (eerr or {}).get(p)}
-    dtypes = {"fp32": "f32 contractions (MFMA)", "fp16x3": "f16 hi/lo x3 exchange + f32 contractions (MFMA)",
+    dtypes = {"fp32": "f32 contractions (MFMA)",
+              "fp16x3": "f16 hi/lo x3 exchange and VHS + f32 contractions (MFMA)",
               "bf16x3": "bf16 hi/lo x3 exchange + f32 contractions (MFMA)"}
     line = {
         "metric": METRIC,

@@ -56,9 +56,10 @@ enum {
  *   AFQMC_BF16X3  as FP32, but the exchange contraction (Sec. III.C, the
  *                 quartic term) splits each FP32 operand into bf16 hi + lo and
  *                 keeps the three leading products on the bf16 matrix cores
- *                 (relative operand error ~2^-16)
+ *                 with FP32 accumulation (relative operand error ~2^-16)
  *   AFQMC_FP16X3  the same split in fp16 with power-of-two row scaling
- *                 (relative operand error ~2^-22, close to FP32) */
+ *                 (relative operand error ~2^-22, close to FP32), applied
+ *                 to the exchange and to the VHS build */
 enum { AFQMC_FP64 = 0, AFQMC_FP32 = 1, AFQMC_BF16X3 = 2, AFQMC_FP16X3 = 3 };
 
 /* Status-word bits (afqmc_get_status). */
@@ -169,7 +170,8 @@ enum {
   AFQMC_PH_WEIGHT,       /* overlap ratio, phase, log weight */
   AFQMC_PH_EXCHANGE,     /* one launch per spin */
   AFQMC_PH_ENERGY,       /* assembly of E1, EJ, EK */
-  AFQMC_PH_SPLIT,        /* hi/lo split of theta (16-bit exchange modes) */
+  AFQMC_PH_SPLIT,        /* hi/lo split of theta and of the shifted fields
+                            (16-bit split modes) */
   AFQMC_NPHASE
 };
 int afqmc_profile_enable(afqmc_ham* ham, int max_records);

@@ -61,6 +61,10 @@ struct afqmc_ham {
   unsigned short* lh_split = nullptr;  // [2][K][nmax][2 ldh] split rows
   float* lh_unscale = nullptr;           // [2][K][nmax]
   unsigned short* th_split = nullptr;  // [W][2][2][nmax][2 ldh]
+  unsigned short* lt_split = nullptr;  // [Npk][2 ldhK] split packed L (VHS)
+  float* lt_unscale = nullptr;         // [Npk]
+  unsigned short* xs_split = nullptr;  // [W][2][2 ldhK]
+  float* xs_unscale = nullptr;         // [W][2]
   float* th_unscale = nullptr;           // [W][2][2][nmax]
   // workspace (sized for max_walkers)
   void* theta = nullptr;    // T [W][2][2][nmax][ldN]
@@ -204,6 +208,12 @@ int seq_energy_from_theta(afqmc_ham* h, int nw, double2* e_out, hipStream_t s,
   return AFQMC_OK;
 }
 
+// The VHS build runs on split operands only in AFQMC_FP16X3, whose 22-bit
+// operands match FP32; bf16 operands (16 bits) would carry ~1e-5 relative
+// errors into every propagated walker, so AFQMC_BF16X3 splits the exchange
+// only.
+static bool vhs_split(const afqmc_ham* h) { return h->split == SPLIT_F16; }
+
 // phi' = P T(VHS) P phi with vbias (of phi) already in h->vbias.
 template <typename T>
 int seq_propagate_core(afqmc_ham* h, afqmc_walkers* w, int nw, const StepIO& io, hipStream_t s) {
@@ -211,8 +221,17 @@ int seq_propagate_core(afqmc_ham* h, afqmc_walkers* w, int nw, const StepIO& io,
   PHASE(h, AFQMC_PH_SHIFT, s,
         (launch_shift<T>(d, nw, h->vbias, io.fields, io.ctr, io.fstep, (T*)h->xs, h->a, h->tmax,
                          h->sdt, s)));
-  PHASE(h, AFQMC_PH_VHS, s,
-        (launch_vhs<T>(d, nw, (const T*)h->xs, (const T*)h->LT, h->pq, (T*)h->vhs, h->sdt, s)));
+  if (vhs_split(h)) {
+    PHASE(h, AFQMC_PH_SPLIT, s,
+          launch_split_rows_mode(h->split, (long)nw * 2, d.K, (const float*)h->xs, d.ldK, h->xs_split, d.ldhK,
+                                 h->xs_unscale, s));
+    PHASE(h, AFQMC_PH_VHS, s,
+          launch_vhs_split(h->split, d, nw, h->xs_split, h->xs_unscale, h->lt_split, h->lt_unscale, h->pq,
+                           (float*)h->vhs, h->sdt, s));
+  } else {
+    PHASE(h, AFQMC_PH_VHS, s,
+          (launch_vhs<T>(d, nw, (const T*)h->xs, (const T*)h->LT, h->pq, (T*)h->vhs, h->sdt, s)));
+  }
   PHASE(h, AFQMC_PH_ONE_BODY, s,
         launch_pphi(d, nw, h->P, (const double2*)w->phi_a, (const double2*)w->phi_b, h->acc, nullptr,
                     nullptr, h->tmax, 0, s));
@@ -299,8 +318,22 @@ int build_working_arrays(afqmc_ham* h, const double* dL, const double* Y_a, cons
   if (d.nb > 0)
     HIP_TRY((setup_pack_lh<T>(d.K, d.N, d.nb, d.nmax, d.ldN, Y_b,
                               (T*)h->Lh + (size_t)d.K * d.nmax * d.ldN, s)));
-  if ((rc = dalloc(h, &h->LT, (size_t)d.Npk * d.ldK * sizeof(T)))) return rc;
-  HIP_TRY((setup_pack_lt<T>(d.K, d.N, d.Npk, d.ldK, h->pq, dL, (T*)h->LT, s)));
+  if (!vhs_split(h)) {
+    if ((rc = dalloc(h, &h->LT, (size_t)d.Npk * d.ldK * sizeof(T)))) return rc;
+    HIP_TRY((setup_pack_lt<T>(d.K, d.N, d.Npk, d.ldK, h->pq, dL, (T*)h->LT, s)));
+    return AFQMC_OK;
+  }
+  // the split VHS keeps only the split packed L: the FP32 one is a temporary
+  if ((rc = dalloc_t(h, &h->lt_split, (size_t)d.Npk * 2 * d.ldhK))) return rc;
+  if ((rc = dalloc_t(h, &h->lt_unscale, (size_t)d.Npk))) return rc;
+  float* lt32 = nullptr;
+  HIP_TRY(hipMalloc(&lt32, (size_t)d.Npk * d.ldK * sizeof(float)));
+  hipError_t e = setup_pack_lt<float>(d.K, d.N, d.Npk, d.ldK, h->pq, dL, lt32, s);
+  if (e == hipSuccess)
+    e = launch_split_rows_mode(h->split, (long)d.Npk, d.K, lt32, d.ldK, h->lt_split, d.ldhK, h->lt_unscale, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(lt32);
+  HIP_TRY(e);
   return AFQMC_OK;
 }
 
@@ -370,6 +403,7 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
   d.ncolp = round_up(d.ncol, 4);
   d.Npk = p.N * (p.N + 1) / 2;
   d.ldh = round_up(p.N, 32);
+  d.ldhK = round_up(p.K, 32);
   h->prec = p.precision;
   h->tsize = p.precision == AFQMC_FP64 ? sizeof(double) : sizeof(float);
   h->split = p.precision == AFQMC_BF16X3 ? SPLIT_BF16 : (p.precision == AFQMC_FP16X3 ? SPLIT_F16 : SPLIT_NONE);
@@ -485,6 +519,10 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
     const size_t rows = wtheta * 4 * nmax;
     if ((rc = dalloc_t(h, &h->th_split, rows * 2 * d.ldh))) return rc;
     if ((rc = dalloc_t(h, &h->th_unscale, rows))) return rc;
+  }
+  if (vhs_split(h)) {
+    if ((rc = dalloc_t(h, &h->xs_split, W * 2 * 2 * d.ldhK))) return rc;
+    if ((rc = dalloc_t(h, &h->xs_unscale, W * 2))) return rc;
   }
 
   // ---- E_T ----

@@ -17,6 +17,7 @@ struct StepDims {
   int ncolp;  // ncol rounded up to a multiple of 4
   int Npk;    // N (N + 1) / 2 packed (p <= q) pairs
   int ldh;    // padded orbital stride of hi/lo split rows (multiple of 32)
+  int ldhK;   // padded Cholesky stride of hi/lo split rows (multiple of 32)
 };
 
 // hi/lo split formats of the 16-bit contraction modes
@@ -96,6 +97,9 @@ hipError_t set_kernel_attributes(const StepDims& d);
 hipError_t launch_split_rows_mode(int mode, long nrows, int ncols, const float* src, int ld_src,
                                   unsigned short* dst, int ldh, float* unscale, hipStream_t s);
 ExTile exchange_split_tile(int n);
+hipError_t launch_vhs_split(int mode, const StepDims& d, int W, const unsigned short* xs, const float* xs_unscale,
+                            const unsigned short* lt, const float* lt_unscale, const int2* pq, float* vhs,
+                            double sdt, hipStream_t s);
 hipError_t launch_exchange_split(int mode, const StepDims& d, int W, const unsigned short* lh,
                                  const float* lh_unscale, const unsigned short* th, const float* th_unscale,
                                  double2* part, int sp, int* ntg_out, hipStream_t s, int gs = 0);

@@ -76,7 +76,6 @@ struct ExSplitArgs {
   const float* a_unscale;   // [K][nmax]
   const unsigned short* b;  // theta split rows: [W][re|im][spin][nmax][2 ldh] halves
   const float* b_unscale;   // [W][re|im][spin][nmax]
-  int a_bytes, b_bytes;     // sizes of the two row blocks
   int K, W, n, nmax, rowb, sp, G, Z, nkb;  // rowb: bytes per split row
 };
 
@@ -106,14 +105,20 @@ __global__ __launch_bounds__(ExSplitCfg::NT, ExSplitCfg::WAVES_PER_EU) void exch
   const int schunk = tid & 7, srow = tid >> 3;
   const int n = p.n, n2 = 2 * n;
   const float rn = 1.0f / (float)n, rn2 = 1.0f / (float)n2;
-  // rows staged by this thread (byte offsets, chunk included)
+  // operand rows of this tile: buffers from the tile's first Cholesky vector
+  // and first walker; rows staged by this thread as byte offsets in them
+  const int g0 = gt * p.G, z0 = wt * p.Z;
+  const int ng = min(p.G, p.K - g0), nz = min(p.Z, p.W - z0);
+  const __amdgpu_buffer_rsrc_t a_rsrc =
+      split_rsrc(p.a + (size_t)g0 * p.nmax * (p.rowb / 2), ng * p.nmax * p.rowb);
+  const __amdgpu_buffer_rsrc_t b_rsrc =
+      split_rsrc(p.b + (size_t)z0 * 4 * p.nmax * (p.rowb / 2), nz * 4 * p.nmax * p.rowb);
   int a_off[C::NA], b_off[C::NB];
 #pragma unroll
   for (int t = 0; t < C::NA; ++t) {
     const int r = srow + t * (C::NT / 8);
     const int gl = ex_div(r, rn);
-    const int g = gt * p.G + gl;
-    a_off[t] = (gl < p.G && g < p.K) ? (g * p.nmax + (r - gl * n)) * p.rowb + schunk * 16 : SPLIT_ROW_NONE;
+    a_off[t] = gl < ng ? (gl * p.nmax + (r - gl * n)) * p.rowb + schunk * 16 : SPLIT_ROW_NONE;
   }
 #pragma unroll
   for (int t = 0; t < C::NB; ++t) {
@@ -121,10 +126,8 @@ __global__ __launch_bounds__(ExSplitCfg::NT, ExSplitCfg::WAVES_PER_EU) void exch
     const int zt = ex_div(c, rn2);
     const int o = c - zt * n2;
     const int comp = o >= n ? 1 : 0;
-    const int z = wt * p.Z + zt;
-    b_off[t] = (zt < p.Z && z < p.W)
-                   ? (((z * 2 + comp) * 2 + p.sp) * p.nmax + (o - comp * n)) * p.rowb + schunk * 16
-                   : SPLIT_ROW_NONE;
+    b_off[t] = zt < nz ? (((zt * 2 + comp) * 2 + p.sp) * p.nmax + (o - comp * n)) * p.rowb + schunk * 16
+                       : SPLIT_ROW_NONE;
   }
   // operand scale factors of tile row / column tid, used by the epilogue
   float pre_row = 0.f, pre_col = 0.f;
@@ -144,8 +147,7 @@ __global__ __launch_bounds__(ExSplitCfg::NT, ExSplitCfg::WAVES_PER_EU) void exch
     }
   }
   floatx4 acc[C::BM / C::WM / 16][C::BN / C::WN / 16];
-  split_tile_mainloop<H, C::BM, C::BN, C::WM, C::WN>(split_rsrc(p.a, p.a_bytes), split_rsrc(p.b, p.b_bytes),
-                                                    a_off, b_off, p.nkb, acc,
+  split_tile_mainloop<H, C::BM, C::BN, C::WM, C::WN>(a_rsrc, b_rsrc, a_off, b_off, p.nkb, acc,
                                                     reinterpret_cast<unsigned short*>(exs_lds));
   const ExTriGeom q{n, p.G, p.Z, p.K, p.W, gt, wt, p.nmax, p.sp, ntg};
   exchange_tri_epilogue<C::BM, C::BN, C::WM, C::WN, H::SCALED>(acc, exs_lds, EXS_TAB_OFF, zpp, q, pre_row,
@@ -172,12 +174,13 @@ hipError_t launch_exchange_split(int mode, const StepDims& d, int W, const unsig
   const int n = sp == 0 ? d.na : d.nb;
   if (n == 0 || W == 0) return hipSuccess;
   const int rowb = 2 * d.ldh * 2;
-  // byte offsets and buffer sizes below 2^31 (one bounds-checked buffer per operand)
-  const double a_bytes = (double)d.K * d.nmax * rowb, b_bytes = (double)W * 4 * d.nmax * rowb;
-  if (a_bytes >= (double)SPLIT_ROW_NONE || b_bytes >= (double)SPLIT_ROW_NONE) return hipErrorInvalidValue;
+  // per-tile buffers (G Cholesky vectors, Z walkers) below 2^31 bytes
+  if ((double)t.G * d.nmax * rowb >= (double)SPLIT_ROW_NONE ||
+      (double)t.Z * 4 * d.nmax * rowb >= (double)SPLIT_ROW_NONE)
+    return hipErrorInvalidValue;
   const size_t sblk = (size_t)d.K * d.nmax;
-  ExSplitArgs p{lh + sp * sblk * 2 * d.ldh, lh_unscale + sp * sblk, th, th_unscale, (int)a_bytes,
-                (int)b_bytes, d.K, W, n, d.nmax, rowb, sp, t.G, t.Z, d.ldh / 32};
+  ExSplitArgs p{lh + sp * sblk * 2 * d.ldh, lh_unscale + sp * sblk, th, th_unscale, d.K, W, n, d.nmax, rowb,
+                sp, t.G, t.Z, d.ldh / 32};
   const int zpp = exs_walkers_per_pass(t.G, t.Z, n);
   if (zpp < 1) return hipErrorInvalidValue;
   const int per = ceil_div(ntg * nwt, 8);
@@ -187,5 +190,91 @@ hipError_t launch_exchange_split(int mode, const StepDims& d, int W, const unsig
   else
     hipLaunchKernelGGL(exchange_split_kernel<HalfF16>, dim3(8 * per), dim3(C::NT), 0, s, p, part, ntg, nwt,
                        zpp, gs);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// VHS build on split operands (Eq. of the propagator: VHS_z = i sqrt(dt)
+// sum_g xs_zg L_g): C[(z, re|im)][pq] = sum_g xs[z][re|im][g] LT[pq][g] over
+// the packed p <= q triangle, mirrored on store.  A = xs split rows (2 W),
+// B = packed L split rows (N (N + 1) / 2), contraction over the Cholesky
+// index.
+// ---------------------------------------------------------------------------
+struct VhsSplitArgs {
+  const unsigned short* a;  // xs split rows [2 W][2 ldhK]
+  const float* a_unscale;   // [2 W]
+  const unsigned short* b;  // LT split rows [Npk][2 ldhK]
+  const float* b_unscale;   // [Npk]
+  const int2* pq;           // packed index -> (p, q)
+  float* vhs;               // [W][N][ldV] complex interleaved
+  int W, Npk, N, ldV, rowb, nkb;
+  float sdt;
+};
+
+template <class H>
+__global__ __launch_bounds__(ExSplitCfg::NT, ExSplitCfg::WAVES_PER_EU) void vhs_split_kernel(VhsSplitArgs p,
+                                                                                             int ntn, int ntm) {
+  using C = ExSplitCfg;
+  constexpr int FM = C::BM / C::WM / 16, FN = C::BN / C::WN / 16;
+  int tn, tm;  // consecutive tiles on one XCD share the packed-L tile
+  if (!xcd_tile(blockIdx.x, ntn, ntm, 1, tn, tm)) return;
+  __shared__ __attribute__((aligned(16))) unsigned short vs_lds[SplitStage<C::BM, C::BN>::BYTES / 2];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int wm = wid / C::WN, wn = wid % C::WN;
+  const int m0 = tm * C::BM, n0 = tn * C::BN;
+  const int nm = min(C::BM, 2 * p.W - m0), nn = min(C::BN, p.Npk - n0);
+  // rows past nm / nn fall outside the tile buffers: staged as zeros
+  const __amdgpu_buffer_rsrc_t a_rsrc = split_rsrc(p.a + (size_t)m0 * (p.rowb / 2), nm * p.rowb);
+  const __amdgpu_buffer_rsrc_t b_rsrc = split_rsrc(p.b + (size_t)n0 * (p.rowb / 2), nn * p.rowb);
+  int a_off[C::NA], b_off[C::NB];
+#pragma unroll
+  for (int t = 0; t < C::NA; ++t) a_off[t] = ((tid >> 3) + t * (C::NT / 8)) * p.rowb + (tid & 7) * 16;
+#pragma unroll
+  for (int t = 0; t < C::NB; ++t) b_off[t] = ((tid >> 3) + t * (C::NT / 8)) * p.rowb + (tid & 7) * 16;
+  floatx4 acc[FM][FN];
+  split_tile_mainloop<H, C::BM, C::BN, C::WM, C::WN>(a_rsrc, b_rsrc, a_off, b_off, p.nkb, acc, vs_lds);
+  // rows m = 2 z + (re|im): each lane's 4 consecutive rows are 2 whole walkers
+#pragma unroll
+  for (int f = 0; f < FN; ++f) {
+    const int col = n0 + wn * (C::BN / C::WN) + f * 16 + (lane & 15);
+    if (col >= p.Npk) continue;
+    const int2 ij = p.pq[col];
+    const float cs = H::SCALED ? p.b_unscale[col] : 1.0f;
+#pragma unroll
+    for (int fi = 0; fi < FM; ++fi) {
+      const int mb = m0 + wm * (C::BM / C::WM) + fi * 16 + 4 * (lane >> 4);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int z = (mb >> 1) + h;
+        if (z >= p.W) continue;
+        float cr = acc[fi][f][2 * h], ci = acc[fi][f][2 * h + 1];
+        if (H::SCALED) {  // powers of two: exact
+          cr *= p.a_unscale[2 * z] * cs;
+          ci *= p.a_unscale[2 * z + 1] * cs;
+        }
+        const float2 v = make_float2(-p.sdt * ci, p.sdt * cr);
+        *reinterpret_cast<float2*>(p.vhs + ((size_t)z * p.N + ij.x) * p.ldV + 2 * ij.y) = v;
+        if (ij.x != ij.y) *reinterpret_cast<float2*>(p.vhs + ((size_t)z * p.N + ij.y) * p.ldV + 2 * ij.x) = v;
+      }
+    }
+  }
+}
+
+hipError_t launch_vhs_split(int mode, const StepDims& d, int W, const unsigned short* xs, const float* xs_unscale,
+                            const unsigned short* lt, const float* lt_unscale, const int2* pq, float* vhs,
+                            double sdt, hipStream_t s) {
+  using C = ExSplitCfg;
+  if (W == 0) return hipSuccess;
+  if (d.ldhK % 32 != 0) return hipErrorInvalidValue;
+  const int rowb = 2 * d.ldhK * 2;
+  if ((double)C::BM * rowb >= (double)SPLIT_ROW_NONE) return hipErrorInvalidValue;
+  const int ntm = ceil_div(2 * W, C::BM), ntn = ceil_div(d.Npk, C::BN);
+  VhsSplitArgs p{xs, xs_unscale, lt, lt_unscale, pq, vhs, W, d.Npk, d.N, d.ldV, rowb, d.ldhK / 32, (float)sdt};
+  const int per = ceil_div(ntm * ntn, 8);
+  if (mode == SPLIT_BF16)
+    hipLaunchKernelGGL(vhs_split_kernel<HalfBF16>, dim3(8 * per), dim3(C::NT), 0, s, p, ntn, ntm);
+  else
+    hipLaunchKernelGGL(vhs_split_kernel<HalfF16>, dim3(8 * per), dim3(C::NT), 0, s, p, ntn, ntm);
   return hipGetLastError();
 }

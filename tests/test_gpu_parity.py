@@ -162,7 +162,7 @@ def test_local_energy_matches_oracle(name, precision, uhf):
         assert np.all(np.abs(got[:, k] - ref[:, k]) <= tol * S)
 
 
-@pytest.mark.parametrize("name,precision,uhf", PARAMS)
+@pytest.mark.parametrize("name,precision,uhf", PARAMS + SPLIT_PARAMS)
 def test_propagate_matches_oracle(name, precision, uhf):
     torch = _torch()
     c = case(name, precision, uhf)
