@@ -262,7 +262,9 @@ def main():
         print(json.dumps({"metric": METRIC, "value": round(cfg.W * args.steps / (ms * 1e-3), 2),
                           "unit": "walker-steps/s", "n_gpus": 1, "steps": args.steps,
                           "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 4),
-                          "only": args.only, "roofline": roofline(cfg, ph, args.only)}), flush=True)
+                          "only": args.only, "roofline": roofline(cfg, ph, args.only),
+                          "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in ph.items()
+                                                 if v[1] > 0}}), flush=True)
         return
 
     cpu = None

@@ -77,7 +77,7 @@ struct afqmc_ham {
   double* acc = nullptr;      // [W][N][ncolp]
   void* t0 = nullptr;         // T [W][N][ncolp]
   void* t1 = nullptr;
-  unsigned* tmax = nullptr;   // [W]
+  unsigned* tmax = nullptr;   // [taylor_order + 2][W] running maxima
   double2* part = nullptr;    // [2][ntg][W]
   double* corr = nullptr;     // [W][2]
   int* status = nullptr;
@@ -220,14 +220,14 @@ int seq_propagate_core(afqmc_ham* h, afqmc_walkers* w, int nw, const StepIO& io,
   const StepDims& d = h->d;
   PHASE(h, AFQMC_PH_SHIFT, s,
         (launch_shift<T>(d, nw, h->vbias, io.fields, io.ctr, io.fstep, (T*)h->xs, h->a, h->tmax,
-                         h->sdt, s)));
+                         h->prm.taylor_order + 2, h->prm.max_walkers, h->sdt, s)));
   if (vhs_split(h)) {
     PHASE(h, AFQMC_PH_SPLIT, s,
           launch_split_rows_mode(h->split, (long)nw * 2, d.K, (const float*)h->xs, d.ldK, h->xs_split, d.ldhK,
                                  h->xs_unscale, s));
     PHASE(h, AFQMC_PH_VHS, s,
           launch_vhs_split(h->split, d, nw, h->xs_split, h->xs_unscale, h->lt_split, h->lt_unscale, h->pq,
-                           (float*)h->vhs, h->sdt, s));
+                           (float*)h->vhs, h->tmax + h->prm.max_walkers, h->sdt, s));
   } else {
     PHASE(h, AFQMC_PH_VHS, s,
           (launch_vhs<T>(d, nw, (const T*)h->xs, (const T*)h->LT, h->pq, (T*)h->vhs, h->sdt, s)));
@@ -240,8 +240,13 @@ int seq_propagate_core(afqmc_ham* h, afqmc_walkers* w, int nw, const StepIO& io,
   for (int k = 1; k <= order; ++k) {
     const T* tin = k == 1 ? nullptr : bufs[(k - 2) & 1];
     T* tout = bufs[(k - 1) & 1];
-    PHASE(h, AFQMC_PH_TAYLOR, s,
-          (launch_taylor<T>(d, nw, (const T*)h->vhs, tin, tout, h->acc, h->tmax, k, order, s)));
+    if (vhs_split(h))
+      PHASE(h, AFQMC_PH_TAYLOR, s,
+            launch_taylor_split(h->split, d, nw, (const float*)h->vhs, (const float*)tin, (float*)tout, h->acc,
+                                h->tmax, h->prm.max_walkers, k, order, s));
+    else
+      PHASE(h, AFQMC_PH_TAYLOR, s,
+            (launch_taylor<T>(d, nw, (const T*)h->vhs, tin, tout, h->acc, h->tmax, k, order, s)));
   }
   PHASE(h, AFQMC_PH_ONE_BODY, s,
         launch_pphi(d, nw, h->P, nullptr, nullptr, h->acc, (double2*)w->phi_a, (double2*)w->phi_b,
@@ -511,7 +516,8 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
   if ((rc = dalloc_t(h, &h->acc, W * N * d.ncolp))) return rc;
   if ((rc = dalloc(h, &h->t0, W * N * d.ncolp * ts))) return rc;
   if ((rc = dalloc(h, &h->t1, W * N * d.ncolp * ts))) return rc;
-  if ((rc = dalloc_t(h, &h->tmax, W))) return rc;
+  // running maxima: slot 0 max |P phi|, 1 max |VHS|, 1 + k max |t_k|
+  if ((rc = dalloc_t(h, &h->tmax, W * (size_t)(p.taylor_order + 2)))) return rc;
   if ((rc = dalloc_t(h, &h->part, (size_t)2 * h->ntg * wtheta))) return rc;
   if ((rc = dalloc_t(h, &h->corr, W * 2))) return rc;
   if ((rc = dalloc_t(h, &h->status, (size_t)1))) return rc;

@@ -42,8 +42,10 @@ hipError_t launch_force_bias(const StepDims& d, int W, const T* Lh, const T* the
 
 // x = x_base + (ctr ? ctr[0] * x_step : 0)
 template <typename T>
+// tmax: tslots running-maximum slots of stride tstride, zeroed per walker
 hipError_t launch_shift(const StepDims& d, int W, const double2* vbias, const double* x, const int* ctr,
-                        long x_step, T* xs, double2* a, unsigned* tmax, double sdt, hipStream_t s);
+                        long x_step, T* xs, double2* a, unsigned* tmax, int tslots, int tstride, double sdt,
+                        hipStream_t s);
 
 template <typename T>
 hipError_t launch_vhs(const StepDims& d, int W, const T* xs, const T* LT, const int2* pq, T* vhs,
@@ -97,9 +99,13 @@ hipError_t set_kernel_attributes(const StepDims& d);
 hipError_t launch_split_rows_mode(int mode, long nrows, int ncols, const float* src, int ld_src,
                                   unsigned short* dst, int ldh, float* unscale, hipStream_t s);
 ExTile exchange_split_tile(int n);
+// vmax (optional): per-walker max |VHS| (atomic, bit patterns of floats)
 hipError_t launch_vhs_split(int mode, const StepDims& d, int W, const unsigned short* xs, const float* xs_unscale,
                             const unsigned short* lt, const float* lt_unscale, const int2* pq, float* vhs,
-                            double sdt, hipStream_t s);
+                            unsigned* vmax, double sdt, hipStream_t s);
+hipError_t launch_taylor_split(int mode, const StepDims& d, int W, const float* vhs, const float* t_in,
+                               float* t_out, double* acc, unsigned* tmax, int tstride, int k, int order,
+                               hipStream_t s);
 hipError_t launch_exchange_split(int mode, const StepDims& d, int W, const unsigned short* lh,
                                  const float* lh_unscale, const unsigned short* th, const float* th_unscale,
                                  double2* part, int sp, int* ntg_out, hipStream_t s, int gs = 0);

@@ -207,6 +207,7 @@ struct VhsSplitArgs {
   const float* b_unscale;   // [Npk]
   const int2* pq;           // packed index -> (p, q)
   float* vhs;               // [W][N][ldV] complex interleaved
+  unsigned* vmax;           // [W] max |VHS| (atomic), or null
   int W, Npk, N, ldV, rowb, nkb;
   float sdt;
 };
@@ -235,6 +236,9 @@ __global__ __launch_bounds__(ExSplitCfg::NT, ExSplitCfg::WAVES_PER_EU) void vhs_
   floatx4 acc[FM][FN];
   split_tile_mainloop<H, C::BM, C::BN, C::WM, C::WN>(a_rsrc, b_rsrc, a_off, b_off, p.nkb, acc, vs_lds);
   // rows m = 2 z + (re|im): each lane's 4 consecutive rows are 2 whole walkers
+  float wmax[FM][2];
+#pragma unroll
+  for (int fi = 0; fi < FM; ++fi) wmax[fi][0] = wmax[fi][1] = 0.f;
 #pragma unroll
   for (int f = 0; f < FN; ++f) {
     const int col = n0 + wn * (C::BN / C::WN) + f * 16 + (lane & 15);
@@ -256,25 +260,277 @@ __global__ __launch_bounds__(ExSplitCfg::NT, ExSplitCfg::WAVES_PER_EU) void vhs_
         const float2 v = make_float2(-p.sdt * ci, p.sdt * cr);
         *reinterpret_cast<float2*>(p.vhs + ((size_t)z * p.N + ij.x) * p.ldV + 2 * ij.y) = v;
         if (ij.x != ij.y) *reinterpret_cast<float2*>(p.vhs + ((size_t)z * p.N + ij.y) * p.ldV + 2 * ij.x) = v;
+        wmax[fi][h] = fmaxf(wmax[fi][h], fmaxf(fabsf(v.x), fabsf(v.y)));
       }
     }
+  }
+  if (p.vmax) {  // per walker: over the 16 lanes holding its rows, then one atomic
+#pragma unroll
+    for (int fi = 0; fi < FM; ++fi)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        float m = wmax[fi][h];
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+        const int z = ((m0 + wm * (C::BM / C::WM) + fi * 16 + 4 * (lane >> 4)) >> 1) + h;
+        if ((lane & 15) == 0 && z < p.W) atomicMax(p.vmax + z, __float_as_uint(m));
+      }
   }
 }
 
 hipError_t launch_vhs_split(int mode, const StepDims& d, int W, const unsigned short* xs, const float* xs_unscale,
                             const unsigned short* lt, const float* lt_unscale, const int2* pq, float* vhs,
-                            double sdt, hipStream_t s) {
+                            unsigned* vmax, double sdt, hipStream_t s) {
   using C = ExSplitCfg;
   if (W == 0) return hipSuccess;
   if (d.ldhK % 32 != 0) return hipErrorInvalidValue;
   const int rowb = 2 * d.ldhK * 2;
   if ((double)C::BM * rowb >= (double)SPLIT_ROW_NONE) return hipErrorInvalidValue;
   const int ntm = ceil_div(2 * W, C::BM), ntn = ceil_div(d.Npk, C::BN);
-  VhsSplitArgs p{xs, xs_unscale, lt, lt_unscale, pq, vhs, W, d.Npk, d.N, d.ldV, rowb, d.ldhK / 32, (float)sdt};
+  VhsSplitArgs p{xs, xs_unscale, lt, lt_unscale, pq, vhs, vmax, W, d.Npk, d.N, d.ldV, rowb, d.ldhK / 32, (float)sdt};
   const int per = ceil_div(ntm * ntn, 8);
   if (mode == SPLIT_BF16)
     hipLaunchKernelGGL(vhs_split_kernel<HalfBF16>, dim3(8 * per), dim3(C::NT), 0, s, p, ntn, ntm);
   else
     hipLaunchKernelGGL(vhs_split_kernel<HalfF16>, dim3(8 * per), dim3(C::NT), 0, s, p, ntn, ntm);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Taylor term on split operands (the propagator's exp(VHS) truncated at order
+// R6): t_k = VHS t_{k-1} / k for one walker per tile column, as a real GEMM
+// over k = (q, re|im) interleaved:
+//   A[p][2q + c]         = VHS_pq (c = 0 real, 1 imaginary part)
+//   B[(j, re)][2q, 2q+1] = ( Re t_qj, -Im t_qj)
+//   B[(j, im)][2q, 2q+1] = ( Im t_qj,  Re t_qj)
+// so that C[p][(j, re|im)] = (VHS t)_pj.  Both operands are read in FP32 (the
+// first term in FP64 from the accumulator) and split in registers with a
+// per-walker power-of-two scale from running maxima (per-walker unsigned
+// bit patterns of non-negative floats): max |VHS|, max |t_{k-1}|; each
+// launch records max |t_k| for the next.
+// ---------------------------------------------------------------------------
+struct TaylorSplitCfg {
+  static constexpr int BM = 160, BN = 128, WM = 2, WN = 2;
+  static constexpr int NT = WM * WN * 64;
+  static constexpr int FM = BM / WM / 16, FN = BN / WN / 16;
+  static constexpr int NA = BM * 8 / NT;   // float4 of A per thread per k block
+  static constexpr int NB = 16 * BN / 4 / NT;  // float4 of t per thread per k block (16 q values)
+};
+
+struct TaylorSplitArgs {
+  const float* vhs;         // [W][N][ldV] complex interleaved
+  const float* t_in;        // [W][N][ncolp] (k >= 2)
+  double* acc;              // [W][N][ncolp] FP64: operand of the first term, accumulator
+  float* t_out;             // [W][N][ncolp]
+  const unsigned* max_a;    // [W] max |VHS|
+  const unsigned* max_b;    // [W] max |operand term|
+  unsigned* max_out;        // [W] max |t_k| (atomic)
+  int N, ldV, ncolp, ncol, ntm, ntn, nkb, add_prev, add_this;
+  double inv_k;
+};
+
+template <class H>
+__device__ __forceinline__ float split_scale_of(unsigned bits) {
+  return split_row_scale<H>(__uint_as_float(bits));
+}
+
+// hi/lo of four scaled values as two 8-byte halves vectors
+template <class H>
+__device__ __forceinline__ void split4(float4 v, float s, uint2& hi, uint2& lo) {
+  const float x[4] = {v.x * s, v.y * s, v.z * s, v.w * s};
+  unsigned short h[4], l[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    h[e] = H::from_float(x[e]);
+    l[e] = H::from_float(x[e] - H::to_float(h[e]));
+  }
+  hi = make_uint2((unsigned)h[0] | ((unsigned)h[1] << 16), (unsigned)h[2] | ((unsigned)h[3] << 16));
+  lo = make_uint2((unsigned)l[0] | ((unsigned)l[1] << 16), (unsigned)l[2] | ((unsigned)l[3] << 16));
+}
+template <class H>
+__device__ __forceinline__ void split2(float a, float b, unsigned& hi, unsigned& lo) {
+  const unsigned short ha = H::from_float(a), hb = H::from_float(b);
+  const unsigned short la = H::from_float(a - H::to_float(ha)), lb = H::from_float(b - H::to_float(hb));
+  hi = (unsigned)ha | ((unsigned)hb << 16);
+  lo = (unsigned)la | ((unsigned)lb << 16);
+}
+
+template <class H, bool FIRST>
+__global__ __launch_bounds__(TaylorSplitCfg::NT, 2) void taylor_split_kernel(TaylorSplitArgs p) {
+  using C = TaylorSplitCfg;
+  using vec8 = typename H::vec8;
+  __shared__ __attribute__((aligned(16))) unsigned short ts_lds[(C::BM + C::BN) * SPLIT_SLD];
+  const int tiles = p.ntm * p.ntn;
+  const int z = blockIdx.x / tiles;
+  const int tr = blockIdx.x - z * tiles;
+  const int tm = tr % p.ntm, tn = tr / p.ntm;
+  const int m0 = tm * C::BM, n0 = tn * C::BN;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid / C::WN, wn = wid % C::WN;
+  const int lrow = lane & 15, lk = 8 * (lane >> 4);
+  const float sa = split_scale_of<H>(p.max_a[z]);
+  const float sb = split_scale_of<H>(p.max_b[z]);
+  const float* vz = p.vhs + (size_t)z * p.N * p.ldV;
+  const size_t tz = (size_t)z * p.N * p.ncolp;
+
+  floatx4 acc[C::FM][C::FN];
+#pragma unroll
+  for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  // A: thread stages float4 chunk (tid % 8) of rows tid / 8 + 32 t
+  // B: thread stages float4 u = tid + NT t of the 16 x BN / 4 block (q major)
+  float4 ra[C::NA], rb[C::NB];
+  auto fetch = [&](int kb) {
+#pragma unroll
+    for (int t = 0; t < C::NA; ++t) {
+      const int r = m0 + (tid >> 3) + t * (C::NT / 8);
+      const int k4 = kb * 32 + 4 * (tid & 7);
+      ra[t] = (r < p.N && k4 < 2 * p.N) ? *reinterpret_cast<const float4*>(vz + (size_t)r * p.ldV + k4)
+                                        : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int t = 0; t < C::NB; ++t) {
+      const int u = tid + t * C::NT;
+      const int q = kb * 16 + u / (C::BN / 4);
+      const int col = n0 + 4 * (u % (C::BN / 4));
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (q < p.N && col < p.ncol) {
+        if constexpr (FIRST) {
+          const double2 x0 = *reinterpret_cast<const double2*>(p.acc + tz + (size_t)q * p.ncolp + col);
+          const double2 x1 = *reinterpret_cast<const double2*>(p.acc + tz + (size_t)q * p.ncolp + col + 2);
+          v = make_float4((float)x0.x, (float)x0.y, (float)x1.x, (float)x1.y);
+        } else {
+          v = *reinterpret_cast<const float4*>(p.t_in + tz + (size_t)q * p.ncolp + col);
+        }
+      }
+      rb[t] = v;
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int t = 0; t < C::NA; ++t) {
+      uint2 hi, lo;
+      split4<H>(ra[t], sa, hi, lo);
+      unsigned short* row = ts_lds + ((tid >> 3) + t * (C::NT / 8)) * SPLIT_SLD + 4 * (tid & 7);
+      *reinterpret_cast<uint2*>(row) = hi;
+      *reinterpret_cast<uint2*>(row + 32) = lo;
+    }
+#pragma unroll
+    for (int t = 0; t < C::NB; ++t) {
+      const int u = tid + t * C::NT;
+      const int kk = 2 * (u / (C::BN / 4));   // k offset of q in this block
+      const int c = 4 * (u % (C::BN / 4));    // first of the 4 columns (2 complex)
+      const float4 v = rb[t];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const float re = (e ? v.z : v.x) * sb, im = (e ? v.w : v.y) * sb;
+        unsigned hi, lo;
+        unsigned short* r0 = ts_lds + (C::BM + c + 2 * e) * SPLIT_SLD + kk;
+        split2<H>(re, -im, hi, lo);  // (j, re) row
+        *reinterpret_cast<unsigned*>(r0) = hi;
+        *reinterpret_cast<unsigned*>(r0 + 32) = lo;
+        split2<H>(im, re, hi, lo);   // (j, im) row
+        *reinterpret_cast<unsigned*>(r0 + SPLIT_SLD) = hi;
+        *reinterpret_cast<unsigned*>(r0 + SPLIT_SLD + 32) = lo;
+      }
+    }
+  };
+  auto compute = [&]() {
+    vec8 ah[C::FM], al[C::FM];
+#pragma unroll
+    for (int i = 0; i < C::FM; ++i) {
+      const unsigned short* r = ts_lds + (wm * (C::BM / C::WM) + i * 16 + lrow) * SPLIT_SLD + lk;
+      ah[i] = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r));
+      al[i] = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r + 32));
+    }
+#pragma unroll
+    for (int j = 0; j < C::FN; ++j) {
+      const unsigned short* r = ts_lds + (C::BM + wn * (C::BN / C::WN) + j * 16 + lrow) * SPLIT_SLD + lk;
+      const vec8 bh = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r));
+      const vec8 bl = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r + 32));
+#pragma unroll
+      for (int i = 0; i < C::FM; ++i) {
+        acc[i][j] = H::mma(al[i], bh, acc[i][j]);
+        acc[i][j] = H::mma(ah[i], bl, acc[i][j]);
+        acc[i][j] = H::mma(ah[i], bh, acc[i][j]);
+      }
+    }
+  };
+  fetch(0);
+  for (int kb = 0; kb < p.nkb; ++kb) {
+    if (kb) __syncthreads();
+    stash();
+    __syncthreads();
+    if (kb + 1 < p.nkb) fetch(kb + 1);
+    compute();
+  }
+
+  // t_k = C / (sa sb k); the accumulator takes t_{k-1} (and t_k on the last
+  // order), so no launch writes the array the first term reads
+  const double unscale = p.inv_k / ((double)sa * (double)sb);
+  float vmax = 0.f;
+#pragma unroll
+  for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::FN; ++j) {
+      const int col = n0 + wn * (C::BN / C::WN) + j * 16 + (lane & 15);
+      const int mb = m0 + wm * (C::BM / C::WM) + i * 16 + 4 * (lane >> 4);
+      if (col >= p.ncol) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = mb + r;
+        if (row >= p.N) continue;
+        const size_t o = tz + (size_t)row * p.ncolp + col;
+        const double v = (double)acc[i][j][r] * unscale;
+        const float tv = (float)v;
+        double add = 0.0;
+        if (p.add_prev) add += (double)p.t_in[o];
+        if (p.add_this) add += (double)tv;
+        if (p.add_prev | p.add_this) p.acc[o] += add;
+        p.t_out[o] = tv;
+        vmax = fmaxf(vmax, fabsf(tv));
+      }
+    }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o, 64));
+  if (lane == 0) atomicMax(p.max_out + z, __float_as_uint(vmax));
+}
+
+// acc += t (the last term when the series stops at the first order)
+__global__ void taylor_split_add_kernel(size_t n, const float* __restrict__ t, double* __restrict__ acc) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) acc[e] += (double)t[e];
+}
+
+// One Taylor order k of the split path (FP16X3 / BF16X3 operands).  tmax has
+// order + 2 slots of stride tstride: 0 max |P phi|, 1 max |VHS|, 1 + k max |t_k|.
+hipError_t launch_taylor_split(int mode, const StepDims& d, int W, const float* vhs, const float* t_in,
+                               float* t_out, double* acc, unsigned* tmax, int tstride, int k, int order,
+                               hipStream_t s) {
+  using C = TaylorSplitCfg;
+  if (W == 0) return hipSuccess;
+  const int ntm = ceil_div(d.N, C::BM), ntn = ceil_div(d.ncol, C::BN);
+  const bool first = k == 1;
+  TaylorSplitArgs p{vhs, t_in, acc, t_out, tmax + tstride, tmax + (first ? 0 : k) * (size_t)tstride,
+                    tmax + (size_t)(1 + k) * tstride, d.N, d.ldV, d.ncolp, d.ncol, ntm, ntn,
+                    ceil_div(2 * d.N, 32), first ? 0 : 1, (k == order && !first) ? 1 : 0, 1.0 / k};
+  const dim3 grid((unsigned)(W * ntm * ntn));
+  if (mode == SPLIT_BF16) {
+    if (first)
+      hipLaunchKernelGGL((taylor_split_kernel<HalfBF16, true>), grid, dim3(C::NT), 0, s, p);
+    else
+      hipLaunchKernelGGL((taylor_split_kernel<HalfBF16, false>), grid, dim3(C::NT), 0, s, p);
+  } else {
+    if (first)
+      hipLaunchKernelGGL((taylor_split_kernel<HalfF16, true>), grid, dim3(C::NT), 0, s, p);
+    else
+      hipLaunchKernelGGL((taylor_split_kernel<HalfF16, false>), grid, dim3(C::NT), 0, s, p);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !(first && k == order)) return e;
+  const size_t n = (size_t)W * d.N * d.ncolp;
+  hipLaunchKernelGGL(taylor_split_add_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, t_out, acc);
   return hipGetLastError();
 }

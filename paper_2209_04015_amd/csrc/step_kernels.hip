@@ -293,7 +293,8 @@ __global__ __launch_bounds__(256) void shift_kernel(int K, int ldK, const double
                                                     const double* __restrict__ x_base,
                                                     const int* __restrict__ ctr, long x_step,
                                                     T* __restrict__ xs, double2* __restrict__ a,
-                                                    unsigned* __restrict__ tmax, double sdt) {
+                                                    unsigned* __restrict__ tmax, int tslots,
+                                                    int tstride, double sdt) {
   __shared__ double2 red[4];
   const int z = blockIdx.x;
   const double* x = x_base + (ctr ? (size_t)ctr[0] * x_step : 0);
@@ -310,23 +311,24 @@ __global__ __launch_bounds__(256) void shift_kernel(int K, int ldK, const double
   const double2 s = block_sum2(acc, red);
   if (threadIdx.x == 0) {
     a[z] = s;
-    if (tmax) tmax[z] = 0u;
+    for (int t = 0; t < tslots; ++t) tmax[(size_t)t * tstride + z] = 0u;  // running maxima of this step
   }
 }
 
 template <typename T>
 hipError_t launch_shift(const StepDims& d, int W, const double2* vbias, const double* x, const int* ctr,
-                        long x_step, T* xs, double2* a, unsigned* tmax, double sdt, hipStream_t s) {
+                        long x_step, T* xs, double2* a, unsigned* tmax, int tslots, int tstride, double sdt,
+                        hipStream_t s) {
   hipLaunchKernelGGL(shift_kernel<T>, dim3(W), dim3(256), 0, s, d.K, d.ldK, vbias, x, ctr, x_step, xs,
-                     a, tmax, sdt);
+                     a, tmax, tslots, tstride, sdt);
   return hipGetLastError();
 }
 template hipError_t launch_shift<float>(const StepDims&, int, const double2*, const double*,
-                                        const int*, long, float*, double2*, unsigned*, double,
+                                        const int*, long, float*, double2*, unsigned*, int, int, double,
                                         hipStream_t);
 template hipError_t launch_shift<double>(const StepDims&, int, const double2*, const double*,
-                                         const int*, long, double*, double2*, unsigned*, double,
-                                         hipStream_t);
+                                         const int*, long, double*, double2*, unsigned*, int, int,
+                                         double, hipStream_t);
 
 // ===========================================================================
 // VHS build: VHS_z = i sqrt(dt) sum_g xs_zg L_g over the packed (p <= q)
