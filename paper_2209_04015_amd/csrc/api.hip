@@ -65,6 +65,7 @@ struct afqmc_ham {
   float* lt_unscale = nullptr;         // [Npk]
   unsigned short* xs_split = nullptr;  // [W][2][2 ldhK]
   float* xs_unscale = nullptr;         // [W][2]
+  float* tk = nullptr;                 // [taylor_order][W][N][ncolp] Taylor terms (split path)
   float* th_unscale = nullptr;           // [W][2][2][nmax]
   // workspace (sized for max_walkers)
   void* theta = nullptr;    // T [W][2][2][nmax][ldN]
@@ -236,17 +237,23 @@ int seq_propagate_core(afqmc_ham* h, afqmc_walkers* w, int nw, const StepIO& io,
         launch_pphi(d, nw, h->P, (const double2*)w->phi_a, (const double2*)w->phi_b, h->acc, nullptr,
                     nullptr, h->tmax, 0, s));
   const int order = h->prm.taylor_order;
-  T* bufs[2] = {(T*)h->t0, (T*)h->t1};
-  for (int k = 1; k <= order; ++k) {
-    const T* tin = k == 1 ? nullptr : bufs[(k - 2) & 1];
-    T* tout = bufs[(k - 1) & 1];
-    if (vhs_split(h))
+  if (vhs_split(h)) {
+    // every term kept (tk[k - 1]), summed into acc once at the end
+    const size_t tsz = (size_t)nw * d.N * d.ncolp;
+    float* tk = h->tk;
+    for (int k = 1; k <= order; ++k)
       PHASE(h, AFQMC_PH_TAYLOR, s,
-            launch_taylor_split(h->split, d, nw, (const float*)h->vhs, (const float*)tin, (float*)tout, h->acc,
-                                h->tmax, h->prm.max_walkers, k, order, s));
-    else
+            launch_taylor_split(h->split, d, nw, (const float*)h->vhs, k == 1 ? nullptr : tk + (k - 2) * tsz,
+                                tk + (k - 1) * tsz, h->acc, h->tmax, h->prm.max_walkers, k, s));
+    PHASE(h, AFQMC_PH_TAYLOR, s, launch_taylor_split_sum(d, nw, order, tk, h->acc, s));
+  } else {
+    T* bufs[2] = {(T*)h->t0, (T*)h->t1};
+    for (int k = 1; k <= order; ++k) {
+      const T* tin = k == 1 ? nullptr : bufs[(k - 2) & 1];
+      T* tout = bufs[(k - 1) & 1];
       PHASE(h, AFQMC_PH_TAYLOR, s,
             (launch_taylor<T>(d, nw, (const T*)h->vhs, tin, tout, h->acc, h->tmax, k, order, s)));
+    }
   }
   PHASE(h, AFQMC_PH_ONE_BODY, s,
         launch_pphi(d, nw, h->P, nullptr, nullptr, h->acc, (double2*)w->phi_a, (double2*)w->phi_b,
@@ -402,7 +409,7 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
   d.K = p.K;
   d.ldN = round_up(p.N, 16);
   d.ldK = round_up(p.K, 16);
-  d.ldV = round_up(2 * p.N, 16);
+  d.ldV = round_up(2 * p.N, 32);  // whole 32-float k blocks per VHS row (zero padded)
   d.ldP = round_up(p.N, 16);
   d.ncol = 2 * (p.na + p.nb);
   d.ncolp = round_up(d.ncol, 4);
@@ -514,8 +521,10 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
   if ((rc = dalloc_t(h, &h->a, W))) return rc;
   if ((rc = dalloc(h, &h->vhs, W * N * d.ldV * ts))) return rc;
   if ((rc = dalloc_t(h, &h->acc, W * N * d.ncolp))) return rc;
-  if ((rc = dalloc(h, &h->t0, W * N * d.ncolp * ts))) return rc;
-  if ((rc = dalloc(h, &h->t1, W * N * d.ncolp * ts))) return rc;
+  if (!vhs_split(h)) {  // Taylor ping-pong terms (the split path keeps every term in tk)
+    if ((rc = dalloc(h, &h->t0, W * N * d.ncolp * ts))) return rc;
+    if ((rc = dalloc(h, &h->t1, W * N * d.ncolp * ts))) return rc;
+  }
   // running maxima: slot 0 max |P phi|, 1 max |VHS|, 1 + k max |t_k|
   if ((rc = dalloc_t(h, &h->tmax, W * (size_t)(p.taylor_order + 2)))) return rc;
   if ((rc = dalloc_t(h, &h->part, (size_t)2 * h->ntg * wtheta))) return rc;
@@ -529,6 +538,7 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
   if (vhs_split(h)) {
     if ((rc = dalloc_t(h, &h->xs_split, W * 2 * 2 * d.ldhK))) return rc;
     if ((rc = dalloc_t(h, &h->xs_unscale, W * 2))) return rc;
+    if ((rc = dalloc_t(h, &h->tk, (size_t)p.taylor_order * W * N * d.ncolp))) return rc;
   }
 
   // ---- E_T ----

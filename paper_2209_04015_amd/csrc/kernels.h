@@ -103,9 +103,13 @@ ExTile exchange_split_tile(int n);
 hipError_t launch_vhs_split(int mode, const StepDims& d, int W, const unsigned short* xs, const float* xs_unscale,
                             const unsigned short* lt, const float* lt_unscale, const int2* pq, float* vhs,
                             unsigned* vmax, double sdt, hipStream_t s);
+// Taylor order k on split operands: t_k = VHS t_{k-1} / k (t_0 = acc, FP64)
 hipError_t launch_taylor_split(int mode, const StepDims& d, int W, const float* vhs, const float* t_in,
-                               float* t_out, double* acc, unsigned* tmax, int tstride, int k, int order,
+                               float* t_out, const double* acc, unsigned* tmax, int tstride, int k,
                                hipStream_t s);
+// acc += t_1 + ... + t_order (terms [order][W][N][ncolp])
+hipError_t launch_taylor_split_sum(const StepDims& d, int W, int order, const float* terms, double* acc,
+                                   hipStream_t s);
 hipError_t launch_exchange_split(int mode, const StepDims& d, int W, const unsigned short* lh,
                                  const float* lh_unscale, const unsigned short* th, const float* th_unscale,
                                  double2* part, int sp, int* ntg_out, hipStream_t s, int gs = 0);

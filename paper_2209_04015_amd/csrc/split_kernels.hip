@@ -319,13 +319,13 @@ struct TaylorSplitCfg {
 
 struct TaylorSplitArgs {
   const float* vhs;         // [W][N][ldV] complex interleaved
-  const float* t_in;        // [W][N][ncolp] (k >= 2)
-  double* acc;              // [W][N][ncolp] FP64: operand of the first term, accumulator
-  float* t_out;             // [W][N][ncolp]
+  const float* t_in;        // [W][N][ncolp] t_{k-1} (k >= 2)
+  const double* acc;        // [W][N][ncolp] FP64 one-body product: operand of the first term
+  float* t_out;             // [W][N][ncolp] t_k
   const unsigned* max_a;    // [W] max |VHS|
   const unsigned* max_b;    // [W] max |operand term|
   unsigned* max_out;        // [W] max |t_k| (atomic)
-  int N, ldV, ncolp, ncol, ntm, ntn, nkb, add_prev, add_this;
+  int N, ldV, ncolp, ncol, ntm, ntn, nkb;
   double inv_k;
 };
 
@@ -355,11 +355,16 @@ __device__ __forceinline__ void split2(float a, float b, unsigned& hi, unsigned&
   lo = (unsigned)la | ((unsigned)lb << 16);
 }
 
+// LDS row of a Taylor stage: two k blocks (hi 32 | lo 32 each) and a 16-byte
+// pad; 272-byte rows put the fragment reads of 8 consecutive rows in 8
+// distinct bank groups.
+constexpr int TS_SLD = 2 * SPLIT_KB + 8;
+
 template <class H, bool FIRST>
 __global__ __launch_bounds__(TaylorSplitCfg::NT, 2) void taylor_split_kernel(TaylorSplitArgs p) {
   using C = TaylorSplitCfg;
   using vec8 = typename H::vec8;
-  __shared__ __attribute__((aligned(16))) unsigned short ts_lds[(C::BM + C::BN) * SPLIT_SLD];
+  __shared__ __attribute__((aligned(16))) unsigned short ts_lds[(C::BM + C::BN) * TS_SLD];
   const int tiles = p.ntm * p.ntn;
   const int z = blockIdx.x / tiles;
   const int tr = blockIdx.x - z * tiles;
@@ -370,8 +375,28 @@ __global__ __launch_bounds__(TaylorSplitCfg::NT, 2) void taylor_split_kernel(Tay
   const int lrow = lane & 15, lk = 8 * (lane >> 4);
   const float sa = split_scale_of<H>(p.max_a[z]);
   const float sb = split_scale_of<H>(p.max_b[z]);
-  const float* vz = p.vhs + (size_t)z * p.N * p.ldV;
   const size_t tz = (size_t)z * p.N * p.ncolp;
+  // per-walker bounds-checked buffers: rows past N (and the B columns past
+  // ncol, given an out-of-range offset) load as zeros; ldV is a multiple of
+  // 32, so every k block lies inside its (zero-padded) VHS row
+  constexpr int esz = FIRST ? 8 : 4;  // bytes per B element
+  const __amdgpu_buffer_rsrc_t a_rsrc = split_rsrc(p.vhs + (size_t)z * p.N * p.ldV, p.N * p.ldV * 4);
+  const __amdgpu_buffer_rsrc_t b_rsrc =
+      FIRST ? split_rsrc(p.acc + tz, p.N * p.ncolp * 8) : split_rsrc(p.t_in + tz, p.N * p.ncolp * 4);
+  // A: thread stages float4 chunk (tid % 8) of rows tid / 8 + 32 t
+  // B: thread stages float4 u = tid + NT t of the 16 x BN / 4 block, q
+  // fastest, so that the lanes of a wave store consecutive k of one row
+  // (distinct LDS banks)
+  int a_off[C::NA], b_off[C::NB];
+#pragma unroll
+  for (int t = 0; t < C::NA; ++t)
+    a_off[t] = ((m0 + (tid >> 3) + t * (C::NT / 8)) * p.ldV + 4 * (tid & 7)) * 4;
+#pragma unroll
+  for (int t = 0; t < C::NB; ++t) {
+    const int u = tid + t * C::NT;
+    const int col = n0 + 4 * (u >> 4);
+    b_off[t] = col < p.ncol ? ((u & 15) * p.ncolp + col) * esz : SPLIT_ROW_NONE;
+  }
 
   floatx4 acc[C::FM][C::FN];
 #pragma unroll
@@ -379,96 +404,102 @@ __global__ __launch_bounds__(TaylorSplitCfg::NT, 2) void taylor_split_kernel(Tay
 #pragma unroll
     for (int j = 0; j < C::FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  // A: thread stages float4 chunk (tid % 8) of rows tid / 8 + 32 t
-  // B: thread stages float4 u = tid + NT t of the 16 x BN / 4 block (q major)
-  float4 ra[C::NA], rb[C::NB];
-  auto fetch = [&](int kb) {
+  // one stage = k blocks 2 ks and 2 ks + 1, fetched a whole stage ahead
+  const int nks = (p.nkb + 1) / 2;
+  float4 ra[2][C::NA], rb[2][C::NB];
+  auto fetch = [&](int ks) {
 #pragma unroll
-    for (int t = 0; t < C::NA; ++t) {
-      const int r = m0 + (tid >> 3) + t * (C::NT / 8);
-      const int k4 = kb * 32 + 4 * (tid & 7);
-      ra[t] = (r < p.N && k4 < 2 * p.N) ? *reinterpret_cast<const float4*>(vz + (size_t)r * p.ldV + k4)
-                                        : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+    for (int h = 0; h < 2; ++h) {
+      const int kb = 2 * ks + h;
+      if (kb >= p.nkb) break;  // uniform
 #pragma unroll
-    for (int t = 0; t < C::NB; ++t) {
-      const int u = tid + t * C::NT;
-      const int q = kb * 16 + u / (C::BN / 4);
-      const int col = n0 + 4 * (u % (C::BN / 4));
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (q < p.N && col < p.ncol) {
+      for (int t = 0; t < C::NA; ++t)
+        ra[h][t] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(a_rsrc, a_off[t], kb * 128, 0));
+      const int bo = kb * 16 * p.ncolp * esz;
+#pragma unroll
+      for (int t = 0; t < C::NB; ++t) {
         if constexpr (FIRST) {
-          const double2 x0 = *reinterpret_cast<const double2*>(p.acc + tz + (size_t)q * p.ncolp + col);
-          const double2 x1 = *reinterpret_cast<const double2*>(p.acc + tz + (size_t)q * p.ncolp + col + 2);
-          v = make_float4((float)x0.x, (float)x0.y, (float)x1.x, (float)x1.y);
+          const double2 x0 =
+              __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(b_rsrc, b_off[t], bo, 0));
+          const double2 x1 =
+              __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(b_rsrc, b_off[t], bo + 16, 0));
+          rb[h][t] = make_float4((float)x0.x, (float)x0.y, (float)x1.x, (float)x1.y);
         } else {
-          v = *reinterpret_cast<const float4*>(p.t_in + tz + (size_t)q * p.ncolp + col);
+          rb[h][t] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(b_rsrc, b_off[t], bo, 0));
         }
       }
-      rb[t] = v;
     }
   };
-  auto stash = [&]() {
+  auto stash = [&](int ks) {
 #pragma unroll
-    for (int t = 0; t < C::NA; ++t) {
-      uint2 hi, lo;
-      split4<H>(ra[t], sa, hi, lo);
-      unsigned short* row = ts_lds + ((tid >> 3) + t * (C::NT / 8)) * SPLIT_SLD + 4 * (tid & 7);
-      *reinterpret_cast<uint2*>(row) = hi;
-      *reinterpret_cast<uint2*>(row + 32) = lo;
-    }
+    for (int h = 0; h < 2; ++h) {
+      if (2 * ks + h >= p.nkb) break;  // uniform
 #pragma unroll
-    for (int t = 0; t < C::NB; ++t) {
-      const int u = tid + t * C::NT;
-      const int kk = 2 * (u / (C::BN / 4));   // k offset of q in this block
-      const int c = 4 * (u % (C::BN / 4));    // first of the 4 columns (2 complex)
-      const float4 v = rb[t];
+      for (int t = 0; t < C::NA; ++t) {
+        uint2 hi, lo;
+        split4<H>(ra[h][t], sa, hi, lo);
+        unsigned short* row = ts_lds + ((tid >> 3) + t * (C::NT / 8)) * TS_SLD + h * SPLIT_KB + 4 * (tid & 7);
+        *reinterpret_cast<uint2*>(row) = hi;
+        *reinterpret_cast<uint2*>(row + 32) = lo;
+      }
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const float re = (e ? v.z : v.x) * sb, im = (e ? v.w : v.y) * sb;
-        unsigned hi, lo;
-        unsigned short* r0 = ts_lds + (C::BM + c + 2 * e) * SPLIT_SLD + kk;
-        split2<H>(re, -im, hi, lo);  // (j, re) row
-        *reinterpret_cast<unsigned*>(r0) = hi;
-        *reinterpret_cast<unsigned*>(r0 + 32) = lo;
-        split2<H>(im, re, hi, lo);   // (j, im) row
-        *reinterpret_cast<unsigned*>(r0 + SPLIT_SLD) = hi;
-        *reinterpret_cast<unsigned*>(r0 + SPLIT_SLD + 32) = lo;
+      for (int t = 0; t < C::NB; ++t) {
+        const int u = tid + t * C::NT;
+        const int kk = 2 * (u & 15);  // k offset of q in this block
+        const int c = 4 * (u >> 4);   // first of the 4 columns (2 complex)
+        const float4 v = rb[h][t];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const float re = (e ? v.z : v.x) * sb, im = (e ? v.w : v.y) * sb;
+          unsigned hi, lo;
+          unsigned short* r0 = ts_lds + (C::BM + c + 2 * e) * TS_SLD + h * SPLIT_KB + kk;
+          split2<H>(re, -im, hi, lo);  // (j, re) row
+          *reinterpret_cast<unsigned*>(r0) = hi;
+          *reinterpret_cast<unsigned*>(r0 + 32) = lo;
+          split2<H>(im, re, hi, lo);   // (j, im) row
+          *reinterpret_cast<unsigned*>(r0 + TS_SLD) = hi;
+          *reinterpret_cast<unsigned*>(r0 + TS_SLD + 32) = lo;
+        }
       }
     }
   };
-  auto compute = [&]() {
-    vec8 ah[C::FM], al[C::FM];
+  auto compute = [&](int ks) {
 #pragma unroll
-    for (int i = 0; i < C::FM; ++i) {
-      const unsigned short* r = ts_lds + (wm * (C::BM / C::WM) + i * 16 + lrow) * SPLIT_SLD + lk;
-      ah[i] = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r));
-      al[i] = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r + 32));
-    }
-#pragma unroll
-    for (int j = 0; j < C::FN; ++j) {
-      const unsigned short* r = ts_lds + (C::BM + wn * (C::BN / C::WN) + j * 16 + lrow) * SPLIT_SLD + lk;
-      const vec8 bh = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r));
-      const vec8 bl = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r + 32));
+    for (int h = 0; h < 2; ++h) {
+      if (2 * ks + h >= p.nkb) break;  // uniform
+      vec8 ah[C::FM], al[C::FM];
 #pragma unroll
       for (int i = 0; i < C::FM; ++i) {
-        acc[i][j] = H::mma(al[i], bh, acc[i][j]);
-        acc[i][j] = H::mma(ah[i], bl, acc[i][j]);
-        acc[i][j] = H::mma(ah[i], bh, acc[i][j]);
+        const unsigned short* r = ts_lds + (wm * (C::BM / C::WM) + i * 16 + lrow) * TS_SLD + h * SPLIT_KB + lk;
+        ah[i] = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r));
+        al[i] = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r + 32));
+      }
+#pragma unroll
+      for (int j = 0; j < C::FN; ++j) {
+        const unsigned short* r =
+            ts_lds + (C::BM + wn * (C::BN / C::WN) + j * 16 + lrow) * TS_SLD + h * SPLIT_KB + lk;
+        const vec8 bh = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r));
+        const vec8 bl = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r + 32));
+#pragma unroll
+        for (int i = 0; i < C::FM; ++i) {
+          acc[i][j] = H::mma(al[i], bh, acc[i][j]);
+          acc[i][j] = H::mma(ah[i], bl, acc[i][j]);
+          acc[i][j] = H::mma(ah[i], bh, acc[i][j]);
+        }
       }
     }
   };
   fetch(0);
-  for (int kb = 0; kb < p.nkb; ++kb) {
-    if (kb) __syncthreads();
-    stash();
+  for (int ks = 0; ks < nks; ++ks) {
+    if (ks) __syncthreads();  // every wave is done with the previous stage
+    stash(ks);
     __syncthreads();
-    if (kb + 1 < p.nkb) fetch(kb + 1);
-    compute();
+    if (ks + 1 < nks) fetch(ks + 1);
+    compute(ks);
   }
 
-  // t_k = C / (sa sb k); the accumulator takes t_{k-1} (and t_k on the last
-  // order), so no launch writes the array the first term reads
+  // t_k = C / (sa sb k), stored alone: the terms are summed into the
+  // accumulator once, after the last order
   const double unscale = p.inv_k / ((double)sa * (double)sb);
   float vmax = 0.f;
 #pragma unroll
@@ -483,12 +514,7 @@ __global__ __launch_bounds__(TaylorSplitCfg::NT, 2) void taylor_split_kernel(Tay
         const int row = mb + r;
         if (row >= p.N) continue;
         const size_t o = tz + (size_t)row * p.ncolp + col;
-        const double v = (double)acc[i][j][r] * unscale;
-        const float tv = (float)v;
-        double add = 0.0;
-        if (p.add_prev) add += (double)p.t_in[o];
-        if (p.add_this) add += (double)tv;
-        if (p.add_prev | p.add_this) p.acc[o] += add;
+        const float tv = (float)((double)acc[i][j][r] * unscale);
         p.t_out[o] = tv;
         vmax = fmaxf(vmax, fabsf(tv));
       }
@@ -498,16 +524,32 @@ __global__ __launch_bounds__(TaylorSplitCfg::NT, 2) void taylor_split_kernel(Tay
   if (lane == 0) atomicMax(p.max_out + z, __float_as_uint(vmax));
 }
 
-// acc += t (the last term when the series stops at the first order)
-__global__ void taylor_split_add_kernel(size_t n, const float* __restrict__ t, double* __restrict__ acc) {
+// acc += t_1 + ... + t_order in FP64, in order (terms of stride n)
+__global__ void taylor_split_sum_kernel(size_t n, int order, const float* __restrict__ t,
+                                        double* __restrict__ acc) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) acc[e] += (double)t[e];
+  if (e >= n) return;
+  float tv[32];
+  for (int k = 0; k < order; ++k) tv[k] = t[(size_t)k * n + e];  // independent loads
+  double a = acc[e];
+  for (int k = 0; k < order; ++k) a += (double)tv[k];
+  acc[e] = a;
+}
+
+hipError_t launch_taylor_split_sum(const StepDims& d, int W, int order, const float* terms, double* acc,
+                                   hipStream_t s) {
+  if (W == 0) return hipSuccess;
+  if (order > 32) return hipErrorInvalidValue;
+  const size_t n = (size_t)W * d.N * d.ncolp;
+  hipLaunchKernelGGL(taylor_split_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, order, terms,
+                     acc);
+  return hipGetLastError();
 }
 
 // One Taylor order k of the split path (FP16X3 / BF16X3 operands).  tmax has
 // order + 2 slots of stride tstride: 0 max |P phi|, 1 max |VHS|, 1 + k max |t_k|.
 hipError_t launch_taylor_split(int mode, const StepDims& d, int W, const float* vhs, const float* t_in,
-                               float* t_out, double* acc, unsigned* tmax, int tstride, int k, int order,
+                               float* t_out, const double* acc, unsigned* tmax, int tstride, int k,
                                hipStream_t s) {
   using C = TaylorSplitCfg;
   if (W == 0) return hipSuccess;
@@ -515,7 +557,7 @@ hipError_t launch_taylor_split(int mode, const StepDims& d, int W, const float* 
   const bool first = k == 1;
   TaylorSplitArgs p{vhs, t_in, acc, t_out, tmax + tstride, tmax + (first ? 0 : k) * (size_t)tstride,
                     tmax + (size_t)(1 + k) * tstride, d.N, d.ldV, d.ncolp, d.ncol, ntm, ntn,
-                    ceil_div(2 * d.N, 32), first ? 0 : 1, (k == order && !first) ? 1 : 0, 1.0 / k};
+                    ceil_div(2 * d.N, 32), 1.0 / k};
   const dim3 grid((unsigned)(W * ntm * ntn));
   if (mode == SPLIT_BF16) {
     if (first)
@@ -528,9 +570,5 @@ hipError_t launch_taylor_split(int mode, const StepDims& d, int W, const float* 
     else
       hipLaunchKernelGGL((taylor_split_kernel<HalfF16, false>), grid, dim3(C::NT), 0, s, p);
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !(first && k == order)) return e;
-  const size_t n = (size_t)W * d.N * d.ncolp;
-  hipLaunchKernelGGL(taylor_split_add_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, t_out, acc);
   return hipGetLastError();
 }
