@@ -597,7 +597,7 @@ int afqmc_init_hamiltonian(const afqmc_params* params, const double* host_h1,
     return fail(AFQMC_EINVAL, "unknown precision %d", p.precision);
   if (p.max_walkers < 1) return fail(AFQMC_EINVAL, "max_walkers must be >= 1");
   const int nmax = p.na > p.nb ? p.na : p.nb;
-  if ((size_t)p.N * nmax * sizeof(double2) + 4096 > 160 * 1024)
+  if (qr_lds_bytes_for(p.N, nmax) > 160 * 1024)
     return fail(AFQMC_EUNSUPPORTED, "N * max(na, nb) too large for the in-LDS QR (N=%d, n=%d)", p.N, nmax);
   {
     const ExTile t = p.precision == AFQMC_FP64 ? exchange_tile<double>(nmax) : exchange_tile<float>(nmax);

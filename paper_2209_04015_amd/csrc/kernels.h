@@ -114,3 +114,4 @@ hipError_t launch_exchange_split(int mode, const StepDims& d, int W, const unsig
                                  const float* lh_unscale, const unsigned short* th, const float* th_unscale,
                                  double2* part, int sp, int* ntg_out, hipStream_t s, int gs = 0);
 size_t qr_lds_bytes(const StepDims& d);
+size_t qr_lds_bytes_for(int N, int n);

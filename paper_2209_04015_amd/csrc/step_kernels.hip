@@ -870,114 +870,137 @@ hipError_t launch_counter_set(int* ctr, int v, hipStream_t s) {
 }
 
 // ===========================================================================
-// Re-orthogonalisation (R9 of the design): Householder QR of each walker and
-// spin, phi <- Q D with D = diag(R_ii / |R_ii|) so that R' = D^* R has a
-// positive real diagonal; corr = sum ln |R_ii|.  The N x n block lives in
-// LDS column-major; waves own columns, lanes own rows.
+// Re-orthogonalisation (R9 of the design): phi = Q R with R upper triangular
+// with a positive real diagonal (the unique such factorisation; Householder
+// QR followed by the phases D = diag(R_ii / |R_ii|) gives the same Q and R),
+// corr = sum ln R_ii.  Computed as Cholesky QR applied twice: S = A^H A,
+// S = R^H R, A <- A R^{-1}; the second pass restores orthogonality to FP64
+// rounding for any condition number below ~1e8, and R = R2 R1.  The N x n
+// block lives in LDS column-major; the Gram entries and the rows of the
+// triangular solve spread over the block, the n x n Cholesky runs in one wave.
 // ===========================================================================
 
-constexpr int QR_THREADS = 256;
+constexpr int QR_THREADS = 512;
 
-size_t qr_lds_bytes(const StepDims& d) {
-  return (size_t)d.N * d.nmax * sizeof(double2) + 2 * (size_t)d.nmax * sizeof(double2) + 64;
+// LDS column stride: N rounded up to 1 mod 8 complex doubles, so that one row
+// of different columns spreads over the LDS banks
+static __host__ __device__ inline int qr_col_stride(int N) { return N + ((9 - N % 8) % 8); }
+
+size_t qr_lds_bytes_for(int N, int n) {
+  return (size_t)n * qr_col_stride(N) * sizeof(double2) + (size_t)n * n * sizeof(double2) + n * sizeof(double) + 64;
 }
+size_t qr_lds_bytes(const StepDims& d) { return qr_lds_bytes_for(d.N, d.nmax); }
 
 __global__ __launch_bounds__(QR_THREADS) void qr_kernel(StepDims d, double2* __restrict__ phi_a,
                                                         double2* __restrict__ phi_b,
                                                         double* __restrict__ corr,
                                                         int* __restrict__ status) {
   extern __shared__ double2 qr_lds[];
+  constexpr int NWAVE = QR_THREADS / 64;
   const int z = blockIdx.x, sp = blockIdx.y;
   const int n = sp == 0 ? d.na : d.nb;
-  const int N = d.N;
+  const int N = d.N, Np = qr_col_stride(N);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  constexpr int NWAVE = QR_THREADS / 64;
   if (n == 0) {
     if (tid == 0) corr[2 * z + sp] = 0.0;
     return;
   }
-  double2* A = qr_lds;                        // A[j * N + p]
-  double2* alpha = A + (size_t)N * n;         // R_kk
-  double* beta = reinterpret_cast<double*>(alpha + n);
+  double2* A = qr_lds;                              // A[j * Np + p]
+  double2* R = A + (size_t)n * Np;                  // R[i * n + j], i <= j: Gram, then its factor
+  double* rinv = reinterpret_cast<double*>(R + n * n);  // 1 / R_jj
+  int* flag = reinterpret_cast<int*>(rinv + n);            // a pivot vanished (set by the Cholesky wave)
   double2* phi = (sp == 0 ? phi_a : phi_b) + (size_t)z * N * n;
 
   for (int e = tid; e < N * n; e += QR_THREADS) {
-    const int p = e / n, j = e % n;
-    A[j * N + p] = phi[e];
+    const int p = e / n, j = e - p * n;
+    A[j * Np + p] = phi[e];
   }
+  bool failed = false;
+  if (tid == 0) *flag = 0;
+  double lnr = 0.0;  // sum ln R_kk of both passes (wave 0, lane 0 = thread 0)
   __syncthreads();
 
-  // ---- factorisation ----
-  for (int k = 0; k < n; ++k) {
+  const int npair = n * (n + 1) / 2;
+  for (int pass = 0; pass < 2; ++pass) {
+    // Gram S = A^H A (upper triangle), one entry per thread, summed over p in
+    // a fixed order (four interleaved partial sums)
+    for (int e = tid; e < npair; e += QR_THREADS) {
+      int i = 0, r = e;
+      while (r >= n - i) r -= n - i, ++i;  // e -> (i, j = i + r)
+      const int j = i + r;
+      const double2* ai = A + (size_t)i * Np;
+      const double2* aj = A + (size_t)j * Np;
+      double2 s0 = make_double2(0.0, 0.0), s1 = s0, s2 = s0, s3 = s0;
+      int q = 0;
+      for (; q + 4 <= N; q += 4) {
+        s0 = cadd(s0, cmul(cconj(ai[q]), aj[q]));
+        s1 = cadd(s1, cmul(cconj(ai[q + 1]), aj[q + 1]));
+        s2 = cadd(s2, cmul(cconj(ai[q + 2]), aj[q + 2]));
+        s3 = cadd(s3, cmul(cconj(ai[q + 3]), aj[q + 3]));
+      }
+      for (; q < N; ++q) s0 = cadd(s0, cmul(cconj(ai[q]), aj[q]));
+      R[i * n + j] = cadd(cadd(s0, s1), cadd(s2, s3));
+    }
+    __syncthreads();
+    // Cholesky S = R^H R in place, right-looking, by one wave (its LDS
+    // accesses stay in program order, so the steps need no barrier): row k of
+    // R from the updated S, then the trailing block S_ij -= conj(R_ki) R_kj
     if (wid == 0) {
-      double s = 0.0;
-      for (int p = k + lane; p < N; p += 64) s += cabs2(A[k * N + p]);
-      s = wave_sum(s);
-      const double xn = sqrt(s);
-      const double2 x0 = A[k * N + k];
-      const double a0 = sqrt(cabs2(x0));
-      const double2 ph = a0 > 0.0 ? cscale(x0, 1.0 / a0) : make_double2(1.0, 0.0);
-      const double2 al = cscale(ph, -xn);             // alpha = -e^{i arg x0} ||x||
-      const double2 v0 = csub(x0, al);
-      const double vn2 = s - a0 * a0 + cabs2(v0);
-      if (lane == 0) {
-        alpha[k] = al;
-        beta[k] = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
-        A[k * N + k] = v0;
-        if (!(xn > 0.0)) atomicOr(status, AFQMC_STATUS_QR_ZERO);
+      for (int k = 0; k < n; ++k) {
+        const double dk = R[k * n + k].x;
+        if (!(dk > 0.0) || !isfinite(dk)) {  // a vanished column (uniform in the wave)
+          if (lane == 0) *flag = 1;
+          break;
+        }
+        const double rk = sqrt(dk), ik = 1.0 / rk;
+        for (int jj = k + 1 + lane; jj < n; jj += 64) R[k * n + jj] = cscale(R[k * n + jj], ik);
+        if (lane == 0) {
+          R[k * n + k] = make_double2(rk, 0.0);
+          rinv[k] = ik;
+          lnr += log(rk);
+        }
+        const int m = n - 1 - k;  // trailing size
+        for (int e = lane; e < m * (m + 1) / 2; e += 64) {
+          int a = 0, r = e;
+          while (r >= m - a) r -= m - a, ++a;
+          const int ii = k + 1 + a, jj = ii + r;
+          R[ii * n + jj] = csub(R[ii * n + jj], cmul(cconj(R[k * n + ii]), R[k * n + jj]));
+        }
       }
     }
     __syncthreads();
-    const double bk = beta[k];
-    for (int j = k + 1 + wid; j < n; j += NWAVE) {
-      double2 w = make_double2(0.0, 0.0);
-      for (int p = k + lane; p < N; p += 64) w = cadd(w, cmul(cconj(A[k * N + p]), A[j * N + p]));
-      w = cscale(wave_sum2(w), bk);
-      for (int p = k + lane; p < N; p += 64) A[j * N + p] = csub(A[j * N + p], cmul(A[k * N + p], w));
+    if (*flag) {
+      failed = true;
+      break;
     }
-    __syncthreads();
-  }
-
-  // ---- explicit Q = H_0 ... H_{n-1} [I; 0], accumulated backwards in place ----
-  for (int e = tid; e < n * n; e += QR_THREADS) {
-    const int j = e / n, p = e % n;
-    if (p < j) A[j * N + p] = make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  for (int i = n - 1; i >= 0; --i) {
-    const double bi = beta[i];
-    for (int j = i + 1 + wid; j < n; j += NWAVE) {
-      double2 w = make_double2(0.0, 0.0);
-      for (int p = i + lane; p < N; p += 64) w = cadd(w, cmul(cconj(A[i * N + p]), A[j * N + p]));
-      w = cscale(wave_sum2(w), bi);
-      for (int p = i + lane; p < N; p += 64) A[j * N + p] = csub(A[j * N + p], cmul(A[i * N + p], w));
-    }
-    __syncthreads();
-    if (wid == 0) {
-      const double2 v0c = cconj(A[i * N + i]);
-      for (int p = i + lane; p < N; p += 64) {
-        double2 q = cscale(cmul(A[i * N + p], v0c), -bi);
-        if (p == i) q.x += 1.0;
-        A[i * N + p] = q;
+    // A <- A R^{-1}: forward substitution along each row, in place
+    for (int q = tid; q < N; q += QR_THREADS) {
+      for (int jc = 0; jc < n; ++jc) {
+        double2 u0 = make_double2(0.0, 0.0), u1 = u0;
+        int ic = 0;
+        for (; ic + 2 <= jc; ic += 2) {
+          u0 = cadd(u0, cmul(A[(size_t)ic * Np + q], R[ic * n + jc]));
+          u1 = cadd(u1, cmul(A[(size_t)(ic + 1) * Np + q], R[(ic + 1) * n + jc]));
+        }
+        if (ic < jc) u0 = cadd(u0, cmul(A[(size_t)ic * Np + q], R[ic * n + jc]));
+        A[(size_t)jc * Np + q] = cscale(csub(A[(size_t)jc * Np + q], cadd(u0, u1)), rinv[jc]);
       }
     }
     __syncthreads();
   }
 
-  // ---- phi <- Q D, corr = sum ln |R_kk| ----
+  if (failed) {  // rank-deficient walker: flagged, left as it is, weight ln 0
+    if (tid == 0) {
+      atomicOr(status, AFQMC_STATUS_QR_ZERO);
+      corr[2 * z + sp] = -INFINITY;
+    }
+    return;
+  }
   for (int e = tid; e < N * n; e += QR_THREADS) {
-    const int p = e / n, j = e % n;
-    const double2 al = alpha[j];
-    const double aa = sqrt(cabs2(al));
-    const double2 dj = aa > 0.0 ? cscale(al, 1.0 / aa) : make_double2(1.0, 0.0);
-    phi[e] = cmul(A[j * N + p], dj);
+    const int p = e / n, j = e - p * n;
+    phi[e] = A[j * Np + p];
   }
-  if (wid == 0) {
-    double s = 0.0;
-    for (int k = lane; k < n; k += 64) s += 0.5 * log(cabs2(alpha[k]));
-    s = wave_sum(s);
-    if (lane == 0) corr[2 * z + sp] = s;
-  }
+  if (tid == 0) corr[2 * z + sp] = lnr;
 }
 
 hipError_t launch_qr(const StepDims& d, int W, double2* phi_a, double2* phi_b, double* corr,
