@@ -66,6 +66,11 @@ struct afqmc_ham {
   unsigned short* xs_split = nullptr;  // [W][2][2 ldhK]
   float* xs_unscale = nullptr;         // [W][2]
   float* tk = nullptr;                 // [taylor_order][W][N][ncolp] Taylor terms (split path)
+  unsigned short* fb_lh = nullptr;     // [K][2][nmax][2 ldh] Lh split per Cholesky vector (force bias)
+  float* fb_lh_unscale = nullptr;      // [K]
+  unsigned short* fb_th = nullptr;     // [W][2][2][nmax][2 ldh] theta split per (walker, re|im)
+  float* fb_th_unscale = nullptr;      // [W][2]
+  float* fb_part = nullptr;            // [FB_SPLIT_CHUNKS][2 W][K] split-K partial sums
   float* th_unscale = nullptr;           // [W][2][2][nmax]
   // workspace (sized for max_walkers)
   void* theta = nullptr;    // T [W][2][2][nmax][ldN]
@@ -169,8 +174,24 @@ int seq_theta(afqmc_ham* h, const afqmc_walkers* w, int nw, bool want_e1, hipStr
   return AFQMC_OK;
 }
 
+// The force bias, VHS build and Taylor products run on split operands only
+// in AFQMC_FP16X3, whose 22-bit operands match FP32; bf16 operands (16 bits)
+// would carry ~1e-5 relative errors into every propagated walker, so
+// AFQMC_BF16X3 splits the exchange only.
+static bool vhs_split(const afqmc_ham* h) { return h->split == SPLIT_F16; }
+
 template <typename T>
 int seq_force_bias(afqmc_ham* h, int nw, double2* vbias, hipStream_t s) {
+  if (vhs_split(h)) {
+    const StepDims& d = h->d;
+    PHASE(h, AFQMC_PH_SPLIT, s,
+          launch_split_blocks_mode(h->split, nw * 2, 2, d.nmax, d.N, (const float*)h->theta, d.ldN, d.nmax,
+                                   2L * d.nmax, h->fb_th, d.ldh, h->fb_th_unscale, s));
+    PHASE(h, AFQMC_PH_FORCE_BIAS, s,
+          launch_force_bias_split(h->split, d, nw, h->fb_th, h->fb_th_unscale, h->fb_lh, h->fb_lh_unscale,
+                                  h->fb_part, vbias, s));
+    return AFQMC_OK;
+  }
   PHASE(h, AFQMC_PH_FORCE_BIAS, s,
         (launch_force_bias<T>(h->d, nw, (const T*)h->Lh, (const T*)h->theta, vbias, s)));
   return AFQMC_OK;
@@ -209,11 +230,6 @@ int seq_energy_from_theta(afqmc_ham* h, int nw, double2* e_out, hipStream_t s,
   return AFQMC_OK;
 }
 
-// The VHS build runs on split operands only in AFQMC_FP16X3, whose 22-bit
-// operands match FP32; bf16 operands (16 bits) would carry ~1e-5 relative
-// errors into every propagated walker, so AFQMC_BF16X3 splits the exchange
-// only.
-static bool vhs_split(const afqmc_ham* h) { return h->split == SPLIT_F16; }
 
 // phi' = P T(VHS) P phi with vbias (of phi) already in h->vbias.
 template <typename T>
@@ -346,6 +362,11 @@ int build_working_arrays(afqmc_ham* h, const double* dL, const double* Y_a, cons
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(lt32);
   HIP_TRY(e);
+  // force bias: Lh split with one scale per Cholesky vector (rows (spin, i))
+  if ((rc = dalloc_t(h, &h->fb_lh, (size_t)d.K * 2 * d.nmax * 2 * d.ldh))) return rc;
+  if ((rc = dalloc_t(h, &h->fb_lh_unscale, (size_t)d.K))) return rc;
+  HIP_TRY(launch_split_blocks_mode(h->split, d.K, 2, d.nmax, d.N, (const float*)h->Lh, d.ldN,
+                                   (long)d.K * d.nmax, d.nmax, h->fb_lh, d.ldh, h->fb_lh_unscale, s));
   return AFQMC_OK;
 }
 
@@ -539,6 +560,9 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
     if ((rc = dalloc_t(h, &h->xs_split, W * 2 * 2 * d.ldhK))) return rc;
     if ((rc = dalloc_t(h, &h->xs_unscale, W * 2))) return rc;
     if ((rc = dalloc_t(h, &h->tk, (size_t)p.taylor_order * W * N * d.ncolp))) return rc;
+    if ((rc = dalloc_t(h, &h->fb_th, W * 2 * 2 * nmax * 2 * d.ldh))) return rc;
+    if ((rc = dalloc_t(h, &h->fb_th_unscale, W * 2))) return rc;
+    if ((rc = dalloc_t(h, &h->fb_part, (size_t)FB_SPLIT_CHUNKS * 2 * W * K))) return rc;
   }
 
   // ---- E_T ----

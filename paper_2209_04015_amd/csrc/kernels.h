@@ -103,6 +103,16 @@ ExTile exchange_split_tile(int n);
 hipError_t launch_vhs_split(int mode, const StepDims& d, int W, const unsigned short* xs, const float* xs_unscale,
                             const unsigned short* lt, const float* lt_unscale, const int2* pq, float* vhs,
                             unsigned* vmax, double sdt, hipStream_t s);
+// Block split: one power-of-two scale per block of nspl x nsub source rows
+// (row s * S1 + b * S2 + i of block b), output rows contiguous per block
+hipError_t launch_split_blocks_mode(int mode, int nblocks, int nspl, int nsub, int ncols, const float* src, int ld_src,
+                                    long S1, long S2, unsigned short* dst, int ldh, float* unscale, hipStream_t s);
+// vbias = sum_k theta_k Lh_k on block-split operands, the k range in
+// FB_SPLIT_CHUNKS chunks; part: [FB_SPLIT_CHUNKS][2 W][K] floats
+constexpr int FB_SPLIT_CHUNKS = 4;
+hipError_t launch_force_bias_split(int mode, const StepDims& d, int W, const unsigned short* th, const float* th_unscale,
+                                   const unsigned short* lh, const float* lh_unscale, float* part, double2* vbias,
+                                   hipStream_t s);
 // Taylor order k on split operands: t_k = VHS t_{k-1} / k (t_0 = acc, FP64)
 hipError_t launch_taylor_split(int mode, const StepDims& d, int W, const float* vhs, const float* t_in,
                                float* t_out, const double* acc, unsigned* tmax, int tstride, int k,

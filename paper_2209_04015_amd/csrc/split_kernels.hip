@@ -572,3 +572,152 @@ hipError_t launch_taylor_split(int mode, const StepDims& d, int W, const float* 
   }
   return hipGetLastError();
 }
+
+// ---------------------------------------------------------------------------
+// Force bias on split operands (Eq. of the optimal force bias, Sec. II.B):
+// vbias[z][g] = sum_{spin, i, p} Lh[spin][g][i][p] theta[z][re|im][spin][i][p],
+// one GEMM over k = (spin, i, p).  Its operands carry one power-of-two scale
+// per contraction row: per Cholesky vector g for Lh, per (walker, re|im) for
+// theta (the per-row scales of the exchange operands vary along this k).
+// ---------------------------------------------------------------------------
+
+// Block split: block b holds rows r = s nsub + i (s < nspl, i < nsub) taken
+// from source row s * S1 + b * S2 + i; one scale for the whole block.  Output
+// rows b * nspl * nsub + r of 2 ldh halves (as split_rows_kernel).
+template <class H>
+__global__ __launch_bounds__(256) void split_blocks_kernel(int nspl, int nsub, int ncols, const float* __restrict__ src,
+                                                           int ld_src, long S1, long S2, unsigned short* __restrict__ dst,
+                                                           int ldh, float* __restrict__ unscale) {
+  __shared__ float red[4];
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int rows = nspl * nsub;
+  float m = 0.f;
+  for (int r = wid; r < rows; r += 4) {
+    const int sp = r / nsub, i = r - sp * nsub;
+    const float* srow = src + ((long)sp * S1 + (long)b * S2 + i) * ld_src;
+    for (int c = lane; c < ncols; c += 64) m = fmaxf(m, fabsf(srow[c]));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if (lane == 0) red[wid] = m;
+  __syncthreads();
+  m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  const float sc = split_row_scale<H>(m);
+  for (int r = wid; r < rows; r += 4) {
+    const int sp = r / nsub, i = r - sp * nsub;
+    const float* srow = src + ((long)sp * S1 + (long)b * S2 + i) * ld_src;
+    unsigned short* d = dst + ((long)b * rows + r) * 2 * ldh;
+    for (int c = lane; c < ldh; c += 64) {
+      const float x = c < ncols ? srow[c] * sc : 0.f;
+      const unsigned short xh = H::from_float(x);
+      unsigned short* o = d + (c >> 5) * SPLIT_KB + (c & 31);
+      o[0] = xh;
+      o[32] = H::from_float(x - H::to_float(xh));
+    }
+  }
+  if (threadIdx.x == 0) unscale[b] = 1.0f / sc;  // power of two: exact
+}
+
+hipError_t launch_split_blocks_mode(int mode, int nblocks, int nspl, int nsub, int ncols, const float* src, int ld_src,
+                                    long S1, long S2, unsigned short* dst, int ldh, float* unscale, hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  if (ldh % 32 != 0 || ldh < ncols) return hipErrorInvalidValue;
+  if (mode == SPLIT_BF16)
+    hipLaunchKernelGGL(split_blocks_kernel<HalfBF16>, dim3(nblocks), dim3(256), 0, s, nspl, nsub, ncols, src, ld_src,
+                       S1, S2, dst, ldh, unscale);
+  else
+    hipLaunchKernelGGL(split_blocks_kernel<HalfF16>, dim3(nblocks), dim3(256), 0, s, nspl, nsub, ncols, src, ld_src,
+                       S1, S2, dst, ldh, unscale);
+  return hipGetLastError();
+}
+
+// C_c[(z, re|im)][g] over the k blocks of chunk c: A = theta block-split rows
+// (2 W), B = Lh block-split rows (K), both 2 nmax sub-rows of 2 ldh halves.
+
+struct FbSplitArgs {
+  const unsigned short* a;  // theta [2 W][2][nmax][2 ldh]
+  const unsigned short* b;  // Lh [K][2][nmax][2 ldh]
+  float* part;              // [chunks][2 W][K]
+  int W, K, rowb, nkb, kchunk;  // rowb: bytes per block row; k blocks per chunk
+};
+
+template <class H>
+__global__ __launch_bounds__(ExSplitCfg::NT, ExSplitCfg::WAVES_PER_EU) void fb_split_kernel(FbSplitArgs p, int ntm,
+                                                                                           int ntn, int per8) {
+  using C = ExSplitCfg;
+  constexpr int FM = C::BM / C::WM / 16, FN = C::BN / C::WN / 16;
+  __shared__ __attribute__((aligned(16))) unsigned short fs_lds[SplitStage<C::BM, C::BN>::BYTES / 2];
+  const int ch = blockIdx.x / per8;  // k chunk; per8 is a multiple of 8, so block % 8 stays the XCD
+  int tm, tn;  // consecutive tiles on one XCD share the Lh tile
+  if (!xcd_tile(blockIdx.x - ch * per8, ntn, ntm, 1, tn, tm)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid / C::WN, wn = wid % C::WN;
+  const int m0 = tm * C::BM, n0 = tn * C::BN;
+  const int nm = min(C::BM, 2 * p.W - m0), nn = min(C::BN, p.K - n0);
+  const int kb0 = ch * p.kchunk;
+  const int nkb = min(p.kchunk, p.nkb - kb0);
+  const __amdgpu_buffer_rsrc_t a_rsrc = split_rsrc(p.a + (size_t)m0 * (p.rowb / 2), nm * p.rowb);
+  const __amdgpu_buffer_rsrc_t b_rsrc = split_rsrc(p.b + (size_t)n0 * (p.rowb / 2), nn * p.rowb);
+  int a_off[C::NA], b_off[C::NB];
+#pragma unroll
+  for (int t = 0; t < C::NA; ++t) a_off[t] = ((tid >> 3) + t * (C::NT / 8)) * p.rowb + kb0 * 128 + (tid & 7) * 16;
+#pragma unroll
+  for (int t = 0; t < C::NB; ++t) b_off[t] = ((tid >> 3) + t * (C::NT / 8)) * p.rowb + kb0 * 128 + (tid & 7) * 16;
+  floatx4 acc[FM][FN];
+  split_tile_mainloop<H, C::BM, C::BN, C::WM, C::WN>(a_rsrc, b_rsrc, a_off, b_off, nkb, acc, fs_lds);
+  float* out = p.part + (size_t)ch * 2 * p.W * p.K;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = n0 + wn * (C::BN / C::WN) + j * 16 + (lane & 15);
+      const int mb = m0 + wm * (C::BM / C::WM) + i * 16 + 4 * (lane >> 4);
+      if (col >= p.K) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (mb + r < 2 * p.W) out[(size_t)(mb + r) * p.K + col] = acc[i][j][r];
+    }
+}
+
+// vbias[z][g] = sum over chunks (fixed order) x the two unscale factors
+__global__ void fb_split_reduce_kernel(int W, int K, int chunks, const float* __restrict__ part,
+                                       const float* __restrict__ th_unscale, const float* __restrict__ lh_unscale,
+                                       double2* __restrict__ vbias) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)W * K) return;
+  const int z = (int)(e / K), g = (int)(e - (size_t)z * K);
+  const size_t cs = (size_t)2 * W * K;
+  double re = 0.0, im = 0.0;
+  for (int c = 0; c < chunks; ++c) {
+    re += (double)part[c * cs + (size_t)(2 * z) * K + g];
+    im += (double)part[c * cs + (size_t)(2 * z + 1) * K + g];
+  }
+  const double ul = (double)lh_unscale[g];
+  vbias[e] = make_double2(re * (double)th_unscale[2 * z] * ul, im * (double)th_unscale[2 * z + 1] * ul);
+}
+
+hipError_t launch_force_bias_split(int mode, const StepDims& d, int W, const unsigned short* th, const float* th_unscale,
+                                   const unsigned short* lh, const float* lh_unscale, float* part, double2* vbias,
+                                   hipStream_t s) {
+  using C = ExSplitCfg;
+  if (W == 0) return hipSuccess;
+  const int rowb = 2 * d.nmax * 2 * d.ldh * 2;  // (spin, i) sub-rows of 2 ldh halves
+  if ((double)C::BM * rowb >= (double)SPLIT_ROW_NONE) return hipErrorInvalidValue;
+  const int nkb = 2 * d.nmax * (d.ldh / 32);
+  const int kchunk = ceil_div(nkb, FB_SPLIT_CHUNKS);
+  const int ntm = ceil_div(2 * W, C::BM), ntn = ceil_div(d.K, C::BN);
+  FbSplitArgs p{th, lh, part, W, d.K, rowb, nkb, kchunk};
+  const int per = ceil_div(ntm * ntn, 8);
+  const dim3 grid((unsigned)(FB_SPLIT_CHUNKS * 8 * per));
+  if (mode == SPLIT_BF16)
+    hipLaunchKernelGGL(fb_split_kernel<HalfBF16>, grid, dim3(C::NT), 0, s, p, ntm, ntn, 8 * per);
+  else
+    hipLaunchKernelGGL(fb_split_kernel<HalfF16>, grid, dim3(C::NT), 0, s, p, ntm, ntn, 8 * per);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t n = (size_t)W * d.K;
+  hipLaunchKernelGGL(fb_split_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, d.K, FB_SPLIT_CHUNKS,
+                     part, th_unscale, lh_unscale, vbias);
+  return hipGetLastError();
+}

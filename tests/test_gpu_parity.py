@@ -137,7 +137,7 @@ def test_overlap_matches_oracle(name, precision, uhf):
     assert np.abs(np.exp(1j * (got.imag - ref.imag)) - 1).max() < 1e-11
 
 
-@pytest.mark.parametrize("name,precision,uhf", PARAMS)
+@pytest.mark.parametrize("name,precision,uhf", PARAMS + SPLIT_PARAMS)
 def test_force_bias_matches_oracle(name, precision, uhf):
     c = case(name, precision, uhf)
     w = c.walkers()
