@@ -127,9 +127,12 @@ int afqmc_propagate(afqmc_ham* ham, afqmc_walkers* w, int nw, const double* fiel
  *   e  complex [nw][3], written.  E_L = e0 + e1 + e2 (complex). */
 int afqmc_local_energy(afqmc_ham* ham, const afqmc_walkers* w, int nw, void* e, void* stream);
 
-/* Re-orthogonalise every walker and spin: phi = Q R (Householder),
- * phi <- Q diag(R_ii/|R_ii|), log_ovlp -= sum ln |R_ii|.  E_L and theta are
- * unchanged by this, up to rounding. */
+/* Re-orthogonalise every walker and spin (R9): phi = Q R with R upper
+ * triangular with a positive real diagonal (the unique such factors, i.e.
+ * Householder QR followed by the phases diag(R_ii/|R_ii|)); phi <- Q,
+ * log_ovlp -= sum ln R_ii.  Computed as Cholesky QR applied twice.  E_L and
+ * theta are unchanged by this, up to rounding.  A rank-deficient walker sets
+ * AFQMC_STATUS_QR_ZERO and is left unchanged with log_ovlp -> +inf. */
 int afqmc_orthogonalise(afqmc_ham* ham, afqmc_walkers* w, int nw, void* stream);
 
 /* One full step: afqmc_propagate, then afqmc_orthogonalise if do_qr, then

@@ -85,7 +85,7 @@ hipError_t launch_energy(const StepDims& d, int W, const double2* e1, const doub
 hipError_t launch_counter_advance(int* ctr, hipStream_t s);
 hipError_t launch_counter_set(int* ctr, int v, hipStream_t s);
 
-// Householder QR of every walker and spin; corr[W][2] = sum ln |R_ii|.
+// QR of every walker and spin (Cholesky QR, twice); corr[W][2] = sum ln R_ii.
 hipError_t launch_qr(const StepDims& d, int W, double2* phi_a, double2* phi_b, double* corr,
                      int* status, hipStream_t s);
 hipError_t launch_ortho_update(int W, const double* corr, double2* log_ovlp, hipStream_t s);
