@@ -40,6 +40,21 @@ Readings where the paper is silent (each is listed in the design doc as well):
 * R10 E1 = sum_s tr(hh^s theta^s); EJ = 1/2 sum_g (sum_s tr T^s_g)^2;
       EK = -1/2 sum_s sum_g tr(T^s_g T^s_g); no nuclear term.
 * R11 G_pq = <a+_p a_q> = (phi S^-1 PhiT^T)_qp with S = PhiT^T phi.
+* R17 Population control (named in Sec. I, no algorithm given) is a comb:
+      with weights w_z = exp(log w_z) (0 for a non-finite log w), inclusive
+      cumulative sums C_z and total W_tot, the nw teeth sit at
+      t_k = (k + u) W_tot / nw for a given u in [0, 1); tooth k selects the
+      first walker z with C_z > t_k (a tooth past the last sum, possible
+      only through rounding, selects the last live walker).  Afterwards
+      every walker has weight W_tot / nw (the total is kept).  Slots: a
+      walker with at least one copy keeps its slot; the extra copies, in
+      increasing walker order, fill the slots of the walkers with no copy,
+      in increasing slot order.  With no live walker nothing changes.
+* R18 Global energy (Sec. III.C): E = sum_z w_z E_L^z / sum_z w_z with the
+      complex E_L = E1 + EJ + EK and w_z as in R17.
+* R19 Block (Sec. IV.A and IV.C): nsteps propagation steps, the last one
+      followed by re-orthogonalisation and the local energy, then the global
+      energy of the block, then the comb.
 
 Array conventions: walkers phi are [W, N, n] complex128 per spin; the trial
 PhiT is [N, n] float64 per spin; theta = phi S^-1 is [W, N, n];
@@ -68,6 +83,9 @@ __all__ = [
     "local_energy",
     "orthogonalise",
     "step",
+    "global_energy",
+    "comb",
+    "block",
 ]
 
 
@@ -300,3 +318,84 @@ def step(ham, phi_a, phi_b, log_ovlp, log_w, x, do_qr):
         phi_a, phi_b, log_ovlp = orthogonalise(phi_a, phi_b, log_ovlp)
     e = local_energy(ham, phi_a, phi_b)
     return phi_a, phi_b, log_ovlp, log_w, e
+
+
+# ---------------------------------------------------------------------------
+# Global energy, population control, block (R17-R19)
+# ---------------------------------------------------------------------------
+
+def _linear_weights(log_w):
+    """w_z / max_z w_z and ln max_z w_z; non-finite log w counts as weight 0."""
+    log_w = np.asarray(log_w, dtype=np.float64)
+    live = np.isfinite(log_w)
+    if not live.any():
+        return np.zeros_like(log_w), -np.inf
+    m = float(np.max(log_w[live]))
+    w = np.zeros_like(log_w)
+    w[live] = np.exp(log_w[live] - m)
+    return w, m
+
+
+def global_energy(log_w, e):
+    """(E, ln sum_z w_z, live walkers): E = sum_z w_z E_L^z / sum_z w_z (R18).
+
+    e is [W, 3] complex (E1, EJ, EK).  With no live walker E is NaN.
+    """
+    w, m = _linear_weights(log_w)
+    den = float(np.sum(w))
+    live = int(np.count_nonzero(w))
+    if live == 0:
+        return complex(np.nan, np.nan), -np.inf, 0
+    el = np.asarray(e).sum(axis=1)
+    return complex(np.sum(w * el) / den), m + math.log(den), live
+
+
+def comb(log_w, u):
+    """Comb population control (R17).
+
+    Returns (parent, new_log_w): the new walker in slot k is a copy of the
+    old walker parent[k]; every new log weight is new_log_w.  With no live
+    walker, parent = identity and new_log_w = None (weights unchanged).
+    """
+    nw = len(log_w)
+    w, m = _linear_weights(log_w)
+    C = np.cumsum(w)                               # inclusive, left to right
+    wtot = float(C[-1]) if nw else 0.0
+    if not (wtot > 0.0) or not math.isfinite(wtot):
+        return np.arange(nw), None
+    teeth = (np.arange(nw) + u) * wtot / nw
+    pick = np.searchsorted(C, teeth, side="right")     # first z with C_z > t_k
+    last_live = int(np.nonzero(w)[0][-1])
+    pick = np.where(pick >= nw, last_live, pick)
+    copies = np.bincount(pick, minlength=nw)
+    extra_src = []
+    for z in range(nw):                            # extra copies in walker order
+        extra_src.extend([z] * max(int(copies[z]) - 1, 0))
+    parent = np.arange(nw)
+    empty = np.nonzero(copies == 0)[0]             # slots freed, in slot order
+    parent[empty] = extra_src
+    return parent, m + math.log(wtot / nw)
+
+
+def block(ham, phi_a, phi_b, log_ovlp, log_w, x, u):
+    """One block (R19): len(x) steps, QR and energy at the last, global energy, comb.
+
+    x is [nsteps, W, K].  Returns (phi_a, phi_b, log_ovlp, log_w, e, E, parent)
+    where e [W, 3] are the local energies before the comb and E the global
+    energy.  u = None skips the comb.
+    """
+    nsteps = len(x)
+    for s in range(nsteps):
+        last = s == nsteps - 1
+        phi_a, phi_b, log_ovlp, log_w = propagate(ham, phi_a, phi_b, log_ovlp, log_w, x[s])
+        if last:
+            phi_a, phi_b, log_ovlp = orthogonalise(phi_a, phi_b, log_ovlp)
+    e = local_energy(ham, phi_a, phi_b)
+    E, _, _ = global_energy(log_w, e)
+    if u is None:                                  # no population control
+        return phi_a, phi_b, log_ovlp, log_w, e, E, np.arange(len(log_w))
+    parent, lw = comb(log_w, u)
+    if lw is not None:
+        phi_a, phi_b, log_ovlp = phi_a[parent], phi_b[parent], log_ovlp[parent]
+        log_w = np.full_like(log_w, lw)
+    return phi_a, phi_b, log_ovlp, log_w, e, E, parent

@@ -410,3 +410,184 @@ def test_orthogonalise_properties():
             assert np.allclose(q[z] @ Rp, p[z], atol=1e-12)
     assert np.allclose(orc.overlap(ham, qa, qb), lo2, atol=1e-11)
     assert np.allclose(orc.local_energy(ham, qa, qb), e0, rtol=1e-11, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# Global energy (Sec. III.C), comb population control (R17), block (R19)
+# ---------------------------------------------------------------------------
+
+def _exact_comb_copies(log_w, u):
+    """Copies per walker of the comb of R17 counted in exact rational arithmetic:
+    tooth k at (k + u) W_tot / nw lands in walker z when C_{z-1} <= t_k < C_z."""
+    from fractions import Fraction
+
+    log_w = np.asarray(log_w, dtype=np.float64)
+    live = np.isfinite(log_w)
+    m = np.max(log_w[live])
+    w = [Fraction(float(np.exp(v - m))) if ok else Fraction(0) for v, ok in zip(log_w, live)]
+    nw = len(w)
+    C = list(itertools.accumulate(w))
+    wtot = C[-1]
+    uf = Fraction(u)
+    copies = [0] * nw
+    gaps = []
+    for k in range(nw):
+        t = (k + uf) * wtot / nw
+        lo = Fraction(0)
+        for z in range(nw):
+            if lo <= t < C[z]:
+                copies[z] += 1
+                break
+            lo = C[z]
+        gaps.append(min(abs(float(t - c)) for c in C) / float(wtot))
+    return np.array(copies), min(gaps)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_comb_matches_exact_tooth_count(seed):
+    rng = np.random.default_rng(seed)
+    nw = 37
+    log_w = rng.normal(0.0, 1.5, nw)
+    log_w[rng.choice(nw, 5, replace=False)] = -np.inf          # discarded walkers
+    u = float(rng.integers(0, 2 ** 20)) / 2 ** 20               # dyadic: exact as a Fraction
+    ref, gap = _exact_comb_copies(log_w, u)
+    assert gap > 1e-9                                           # no tooth on a boundary
+    parent, lw = orc.comb(log_w, u)
+    assert np.array_equal(np.bincount(parent, minlength=nw), ref)
+
+
+def test_comb_equal_weights_is_identity():
+    # teeth exactly on the boundaries C_z = z + 1: tooth k belongs to walker k
+    for nw in (1, 2, 7, 64):
+        parent, lw = orc.comb(np.zeros(nw), 0.0)
+        assert np.array_equal(parent, np.arange(nw))
+        assert lw == pytest.approx(0.0, abs=1e-15)
+        parent, _ = orc.comb(np.full(nw, 3.0), 0.999)
+        assert np.array_equal(parent, np.arange(nw))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_comb_copies_are_floor_or_ceil_of_expectation(seed):
+    rng = np.random.default_rng(seed)
+    nw = 200
+    log_w = rng.normal(0.0, 2.0, nw)
+    w = np.exp(log_w - log_w.max())
+    expect = nw * w / w.sum()
+    for u in rng.random(10):
+        parent, _ = orc.comb(log_w, u)
+        c = np.bincount(parent, minlength=nw)
+        assert c.sum() == nw
+        assert np.all((c >= np.floor(expect) - 0) & (c <= np.ceil(expect)))
+
+
+def test_comb_is_unbiased_over_the_offset():
+    rng = np.random.default_rng(5)
+    nw = 16
+    log_w = rng.normal(0.0, 1.0, nw)
+    w = np.exp(log_w)
+    M = 4096
+    mean = np.zeros(nw)
+    for j in range(M):
+        parent, _ = orc.comb(log_w, (j + 0.5) / M)
+        mean += np.bincount(parent, minlength=nw)
+    mean /= M
+    np.testing.assert_allclose(mean, nw * w / w.sum(), atol=4.0 / M)
+
+
+def test_comb_slots_and_total_weight():
+    rng = np.random.default_rng(9)
+    nw = 50
+    log_w = rng.normal(0.0, 1.0, nw) + 40.0
+    log_w[[3, 17]] = -np.inf
+    log_w[21] = np.nan
+    parent, lw = orc.comb(log_w, 0.37)
+    c = np.bincount(parent, minlength=nw)
+    assert c[3] == c[17] == c[21] == 0                          # non-finite: weight 0
+    kept = np.nonzero(c > 0)[0]
+    assert np.array_equal(parent[kept], kept)                   # survivors keep their slot
+    freed = np.nonzero(c == 0)[0]
+    src = parent[freed]
+    assert np.all(np.diff(src) >= 0)                            # extras in walker order
+    # total weight kept: nw exp(lw) = sum_z exp(log w_z)
+    live = np.isfinite(log_w)
+    tot = np.sum(np.exp(log_w[live] - 40.0))
+    assert nw * math.exp(lw - 40.0) == pytest.approx(tot, rel=1e-12)
+    # worked example: weights (0.5, 1.5, 0, 2), u = 1/4: teeth 0.25, 1.25, 2.25, 3.25
+    parent, lw = orc.comb(np.array([math.log(0.5), math.log(1.5), -np.inf, math.log(2.0)]), 0.25)
+    assert list(parent) == [0, 1, 3, 3]
+    assert lw == pytest.approx(0.0, abs=1e-15)
+
+
+def test_comb_without_live_walkers_changes_nothing():
+    parent, lw = orc.comb(np.array([-np.inf, np.nan, -np.inf]), 0.5)
+    assert list(parent) == [0, 1, 2] and lw is None
+
+
+def test_global_energy_definition():
+    rng = np.random.default_rng(2)
+    W = 30
+    e = rng.normal(size=(W, 3)) + 1j * rng.normal(size=(W, 3))
+    el = e.sum(axis=1)
+    # equal weights: the plain mean
+    E, lsw, live = orc.global_energy(np.full(W, -2.0), e)
+    assert E == pytest.approx(el.mean(), rel=1e-13)
+    assert lsw == pytest.approx(-2.0 + math.log(W), rel=1e-13) and live == W
+    # one live walker: its own energy
+    lw = np.full(W, -np.inf)
+    lw[7] = 3.0
+    E, lsw, live = orc.global_energy(lw, e)
+    assert E == pytest.approx(el[7], rel=1e-14) and lsw == pytest.approx(3.0) and live == 1
+    # moderate weights: the unshifted sums; huge weights: unchanged by a common shift
+    lw = rng.normal(0.0, 1.0, W)
+    E, lsw, _ = orc.global_energy(lw, e)
+    w = np.exp(lw)
+    assert E == pytest.approx(np.dot(w, el) / w.sum(), rel=1e-12)
+    assert lsw == pytest.approx(math.log(w.sum()), rel=1e-12)
+    E2, lsw2, _ = orc.global_energy(lw + 900.0, e)
+    assert E2 == pytest.approx(E, rel=1e-12) and lsw2 == pytest.approx(lsw + 900.0, rel=1e-12)
+    E, lsw, live = orc.global_energy(np.full(W, -np.inf), e)
+    assert np.isnan(E.real) and lsw == -np.inf and live == 0
+
+
+def test_block_is_steps_then_estimator_then_comb():
+    h1, L, phiT, _ = _tiny(N=6, K=8, n=2, seed=4)
+    ham = orc.setup(h1, L, phiT, phiT, dt=0.01)
+    W = 6
+    pa = _rand_walkers(phiT, W, seed=1).astype(np.complex128)
+    pb = pa.copy()
+    lo = orc.overlap(ham, pa, pb)
+    lw = np.random.default_rng(0).normal(0.0, 0.3, W)
+    x = np.random.default_rng(1).normal(size=(3, W, ham.K))
+    out = orc.block(ham, pa, pb, lo, lw, x, 0.6)
+    # the same by hand from the pinned parts
+    a, b, o, w = pa, pb, lo, lw
+    for s in range(3):
+        a, b, o, w = orc.propagate(ham, a, b, o, w, x[s])
+    a, b, o = orc.orthogonalise(a, b, o)
+    e = orc.local_energy(ham, a, b)
+    parent, nlw = orc.comb(w, 0.6)
+    np.testing.assert_array_equal(out[6], parent)
+    np.testing.assert_allclose(out[0], a[parent], rtol=0, atol=0)
+    np.testing.assert_allclose(out[3], np.full(W, nlw), rtol=0, atol=0)
+    assert out[5] == orc.global_energy(w, e)[0]
+    # the comb leaves the weighted energy of the ensemble unbiased on average over u
+    M = 512
+    acc = 0.0
+    for j in range(M):
+        p, nl = orc.comb(w, (j + 0.5) / M)
+        acc += np.mean(e.sum(axis=1)[p])
+    assert acc / M == pytest.approx(orc.global_energy(w, e)[0], abs=2e-2 * abs(e.sum(axis=1)).max())
+
+
+def test_comb_tooth_past_the_last_sum_goes_to_the_last_live_walker():
+    # u just below 1: the last tooth (nw - 1 + u) W / nw rounds to W itself,
+    # past every C_z; it must land on the last live walker (slot 4 here)
+    lw = np.array([-0.13, 0.64, 0.10, -0.54, 0.36, -np.inf])
+    u = 1.0 - 2.0 ** -53
+    nw = len(lw)
+    w = np.exp(lw[:5] - lw[:5].max())
+    assert (nw - 1 + u) * np.cumsum(w)[-1] / nw >= np.cumsum(w)[-1]
+    parent, _ = orc.comb(lw, u)
+    c = np.bincount(parent, minlength=nw)
+    assert c[5] == 0 and c.sum() == nw
+    assert c[4] == np.count_nonzero(((np.arange(nw) + u) * w.sum() / nw) >= np.cumsum(w)[3])
