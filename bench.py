@@ -54,7 +54,10 @@ def step_flops(cfg):
     }
 
 
-def run_gpu(cfg, h1, L, phiT, precision, steps, warmup, fields_dev, device):
+BLOCK_STEPS = 25   # propagation steps per block (the paper's timing convention)
+
+
+def run_gpu(cfg, h1, L, phiT, precision, steps, warmup, fields_dev, block_fields_dev, device):
     import torch
 
     from paper_2209_04015_amd import afqmc
@@ -87,7 +90,31 @@ def run_gpu(cfg, h1, L, phiT, precision, steps, warmup, fields_dev, device):
     ham.profile_enable(0)
     status = ham.status()
     log(f"{precision}: {steps} steps in {ms:.1f} ms ({ms / steps:.2f} ms/step), status {status}")
-    return ham, w, e, ms, phases, status
+    # secondary figures on the same walkers: propagation only (no QR, no
+    # energy), and one block in the paper's convention (BLOCK_STEPS steps,
+    # QR and energy at the last, global energy, comb)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for i in range(steps):
+        ham.step(w, fields_dev[i], do_qr=False, energy_out=None, reuse=True)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_prop = start.elapsed_time(stop)
+    blk_fields = block_fields_dev
+    start.record(stream)
+    ham.block(w, blk_fields, 0.5, energy_out=e, reuse=True)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_block = start.elapsed_time(stop)
+    log(f"{precision}: propagation only {ms_prop / steps:.2f} ms/step; block of {BLOCK_STEPS} "
+        f"steps {ms_block:.1f} ms")
+    extra = {"propagation_only": {"value": round(W * steps / (ms_prop * 1e-3), 2), "unit": "walker-steps/s",
+                                  "ms_per_step": round(ms_prop / steps, 4)},
+             "block": {"value": round(W * BLOCK_STEPS / (ms_block * 1e-3), 2), "unit": "walker-steps/s",
+                       "ms_per_block": round(ms_block, 3),
+                       "definition": f"{BLOCK_STEPS} steps, QR and local energy at the last, "
+                                     "global energy, comb population control"}}
+    return ham, w, e, ms, phases, status, extra
 
 
 # Sources that define each roofline kernel: its HBM traffic figure (from the
@@ -228,6 +255,7 @@ def main():
     nsteps = args.warmup + args.steps
     fields = inputs.fields(cfg.W, cfg.K, nsteps, seed=0)
     fields_dev = torch.as_tensor(fields, device=device)
+    block_fields_dev = torch.as_tensor(inputs.fields(cfg.W, cfg.K, BLOCK_STEPS, seed=1), device=device)
     log(f"inputs {cfg.name}: N={cfg.N} n={cfg.n} K={cfg.K} W={cfg.W} generated in {time.time() - t:.1f} s")
 
     if args.calib_copy:
@@ -240,14 +268,16 @@ def main():
         del src, dst
 
     results = {}
+    extras = {}
     states = {}
     sample = min(args.cpu_sample, cfg.W)
     for precision in MODES:
         if args.only and precision != args.only:
             continue
-        ham, w, e, ms, phases, status = run_gpu(cfg, h1, L, phiT, precision, args.steps, args.warmup,
-                                                fields_dev, device)
+        ham, w, e, ms, phases, status, extra = run_gpu(cfg, h1, L, phiT, precision, args.steps, args.warmup,
+                                                       fields_dev, block_fields_dev, device)
         results[precision] = (ms, phases, status)
+        extras[precision] = extra
         # energies of sampled walkers from this path's own final states
         pa = w.phi_a[:sample].cpu().numpy()
         pb = w.phi_b[:sample].cpu().numpy()
@@ -263,6 +293,7 @@ def main():
                           "unit": "walker-steps/s", "n_gpus": 1, "steps": args.steps,
                           "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 4),
                           "only": args.only, "roofline": roofline(cfg, ph, args.only),
+                          **extras[args.only],
                           "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in ph.items()
                                                  if v[1] > 0}}), flush=True)
         return
@@ -290,7 +321,7 @@ def main():
         paths[p] = {"value": round(rate(ms), 2), "unit": "walker-steps/s",
                     "ms_per_step": round(ms / args.steps, 4), "roofline": roofline(cfg, ph, p),
                     "phases_ms_per_step": phase_table(ph), "status": st,
-                    "energy_error_vs_fp64_oracle": (eerr or {}).get(p)}
+                    "energy_error_vs_fp64_oracle": (eerr or {}).get(p), **extras[p]}
     dtypes = {"fp32": "f32 contractions (MFMA)",
               "fp16x3": "f16 hi/lo x3 exchange and VHS + f32 contractions (MFMA)",
               "bf16x3": "bf16 hi/lo x3 exchange + f32 contractions (MFMA)"}
@@ -319,6 +350,7 @@ def main():
         "fp64": paths["fp64"],
         "mixed_over_fp64": round(ms64 / msh, 3),
         "energy_error_vs_fp64_oracle": (eerr or {}).get(head),
+        **extras[head],
         "phases_ms_per_step": phase_table(phh),
         "paths": paths,
         "algorithmic_gflop_per_walker_step": {k: round(v / 1e9, 4) for k, v in fl.items()},

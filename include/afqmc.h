@@ -66,7 +66,8 @@ enum { AFQMC_FP64 = 0, AFQMC_FP32 = 1, AFQMC_BF16X3 = 2, AFQMC_FP16X3 = 3 };
 enum {
   AFQMC_STATUS_SINGULAR = 1,   /* a walker's overlap matrix PhiT^T phi was singular */
   AFQMC_STATUS_NONFINITE = 2,  /* a NaN appeared in an overlap or a weight */
-  AFQMC_STATUS_QR_ZERO = 4     /* a walker orbital vanished in re-orthogonalisation */
+  AFQMC_STATUS_QR_ZERO = 4,    /* a walker orbital vanished in re-orthogonalisation */
+  AFQMC_STATUS_NO_LIVE = 8     /* population control found no walker with a finite weight */
 };
 
 typedef struct afqmc_params {
@@ -148,6 +149,55 @@ enum { AFQMC_STEP_REUSE = 1 };
 int afqmc_step(afqmc_ham* ham, afqmc_walkers* w, int nw, const double* fields, int do_qr,
                void* e, int flags, void* stream);
 
+/* ---- ensemble: global energy, population control, block ----
+ * Weights are w_z = exp(log_w[z]); a walker whose log_w is not finite (-inf
+ * for a discarded walker, or NaN) has weight 0.  Both reductions run in a
+ * fixed order (deterministic), in FP64 in every precision mode. */
+
+/* Walker-averaged energy E = sum_z w_z E_L^z / sum_z w_z (Sec. III.C, the
+ * global energy estimate), E_L^z = e[z][0] + e[z][1] + e[z][2] (complex).
+ *   e    complex [nw][3] local energy parts as written by afqmc_local_energy
+ *        (may be NULL when nw = 0), read
+ *   out  device double [4], written: Re E, Im E, ln sum_z w_z, number of
+ *        walkers with w_z > 0.  With no such walker: NaN, NaN, -inf, 0. */
+int afqmc_global_energy(afqmc_ham* ham, const afqmc_walkers* w, int nw, const void* e, double* out,
+                        void* stream);
+
+/* Population control by a comb (named in Sec. I; the paper gives no
+ * algorithm, the comb is this library's choice).  With W = sum_z w_z, the nw
+ * teeth t_k = (k + u) W / nw, k = 0 .. nw-1, each select the first walker z
+ * whose cumulative weight w_0 + ... + w_z exceeds t_k (rounding past the
+ * total selects the last walker with w_z > 0).  A walker selected c >= 1
+ * times keeps its slot and its c - 1 extra copies fill, in walker order, the
+ * slots of the unselected walkers, in slot order.  phi_a, phi_b and log_ovlp
+ * are copied accordingly and every log_w becomes ln(W / nw) (the total
+ * weight is kept).  Each walker gets floor or ceil of nw w_z / W copies, and
+ * the expected number over u is nw w_z / W.
+ *   u       comb offset, 0 <= u < 1 (a uniform random number drawn by the
+ *           caller; otherwise AFQMC_EINVAL)
+ *   parent  device int [nw], written (may be NULL): slot k now holds a copy
+ *           of old walker parent[k] (parent[k] = k for survivors)
+ * With no walker of finite weight nothing changes, parent[k] = k and
+ * AFQMC_STATUS_NO_LIVE is set.  The next afqmc_step recomputes the Green's
+ * function (its flags' AFQMC_STEP_REUSE is ignored once). */
+int afqmc_population_control(afqmc_ham* ham, afqmc_walkers* w, int nw, double u, int* parent,
+                             void* stream);
+
+/* One block (Sec. IV.A and IV.C: a number of propagation steps, then one
+ * energy evaluation and one re-orthogonalisation):
+ *   nsteps afqmc_step calls, re-orthogonalisation and the local energy on
+ *   the last; the global energy of the block into out[4]
+ *   (afqmc_global_energy); then, if u >= 0, afqmc_population_control(u).
+ *   fields  device [nsteps][nw][K] auxiliary fields, read
+ *   e       device complex [nw][3]: local energies of the walkers before
+ *           population control, written
+ *   out     device double [4] (afqmc_global_energy), written
+ *   u       comb offset in [0, 1), or negative for no population control
+ *   parent  as in afqmc_population_control (may be NULL)
+ *   flags   AFQMC_STEP_REUSE applies to the first step */
+int afqmc_block(afqmc_ham* ham, afqmc_walkers* w, int nw, const double* fields, int nsteps, double u,
+                void* e, double* out, int* parent, int flags, void* stream);
+
 /* Synchronise `stream`, return the accumulated status bits in *out and clear them. */
 int afqmc_get_status(afqmc_ham* ham, void* stream, int* out);
 
@@ -175,6 +225,7 @@ enum {
   AFQMC_PH_ENERGY,       /* assembly of E1, EJ, EK */
   AFQMC_PH_SPLIT,        /* hi/lo split of theta and of the shifted fields
                             (16-bit split modes) */
+  AFQMC_PH_CONTROL,      /* global energy and population control */
   AFQMC_NPHASE
 };
 int afqmc_profile_enable(afqmc_ham* ham, int max_records);

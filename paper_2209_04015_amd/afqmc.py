@@ -24,6 +24,8 @@ FP32 = 1
 BF16X3 = 2
 FP16X3 = 3
 STEP_REUSE = 1
+# status-word bits (afqmc_get_status)
+STATUS_SINGULAR, STATUS_NONFINITE, STATUS_QR_ZERO, STATUS_NO_LIVE = 1, 2, 4, 8
 _PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3,
                FP64: FP64, FP32: FP32, BF16X3: BF16X3, FP16X3: FP16X3}
 
@@ -35,6 +37,9 @@ EXPORTED = (
     "afqmc_local_energy",
     "afqmc_orthogonalise",
     "afqmc_step",
+    "afqmc_global_energy",
+    "afqmc_population_control",
+    "afqmc_block",
     "afqmc_get_status",
     "afqmc_get_setup",
     "afqmc_profile_enable",
@@ -51,7 +56,7 @@ EXPORTED = (
 
 # kernel phases of afqmc_profile_read, in header order
 PHASES = ("green", "force_bias", "shift", "vhs", "one_body", "taylor", "qr", "weight",
-          "exchange", "energy", "split")
+          "exchange", "energy", "split", "control")
 
 
 class AfqmcError(RuntimeError):
@@ -108,6 +113,9 @@ def load(path: str = LIB_PATH):
     lib.afqmc_local_energy.argtypes = [vp, P(_Walkers), ip, vp, vp]
     lib.afqmc_orthogonalise.argtypes = [vp, P(_Walkers), ip, vp]
     lib.afqmc_step.argtypes = [vp, P(_Walkers), ip, vp, ip, vp, ip, vp]
+    lib.afqmc_global_energy.argtypes = [vp, P(_Walkers), ip, vp, vp, vp]
+    lib.afqmc_population_control.argtypes = [vp, P(_Walkers), ip, ctypes.c_double, vp, vp]
+    lib.afqmc_block.argtypes = [vp, P(_Walkers), ip, vp, ip, ctypes.c_double, vp, vp, vp, ip, vp]
     lib.afqmc_get_status.argtypes = [vp, vp, P(ip)]
     lib.afqmc_get_setup.argtypes = [vp, vp, dp, dp]
     lib.afqmc_profile_enable.argtypes = [vp, ip]
@@ -306,6 +314,57 @@ class Hamiltonian:
         _check(_lib.afqmc_step(self._h, ctypes.byref(s), nw, fp, int(bool(do_qr)), eptr,
                                STEP_REUSE if reuse else 0, _stream_ptr(stream)))
         return energy_out
+
+    def global_energy(self, w: Walkers, e, out=None, nw=None, stream=None):
+        """Device float64 [4]: Re E, Im E, ln sum w, live walkers (E = sum w E_L / sum w)."""
+        import torch
+
+        nw = self._nw(w, nw)
+        if out is None:
+            out = torch.empty(4, dtype=torch.float64, device=w.phi_a.device)
+        optr = _dev(out, torch.float64, (4,), "out")
+        eptr = _dev(e, torch.complex128, (nw, 3), "energy") if nw else None
+        s = w._struct(self, nw)
+        _check(_lib.afqmc_global_energy(self._h, ctypes.byref(s), nw, eptr, optr, _stream_ptr(stream)))
+        return out
+
+    def population_control(self, w: Walkers, u: float, parent=None, nw=None, stream=None):
+        """Comb population control in place; returns the device int32 parent map."""
+        import torch
+
+        nw = self._nw(w, nw)
+        if parent is None:
+            parent = torch.empty(nw, dtype=torch.int32, device=w.phi_a.device)
+        pptr = _dev(parent, torch.int32, (nw,), "parent")
+        s = w._struct(self, nw)
+        _check(_lib.afqmc_population_control(self._h, ctypes.byref(s), nw, float(u), pptr,
+                                             _stream_ptr(stream)))
+        return parent
+
+    def block(self, w: Walkers, fields, u, energy_out=None, out=None, parent=None, reuse=False,
+              nw=None, stream=None):
+        """len(fields) steps (QR and energy at the last), global energy, comb (u >= 0).
+
+        Returns (energy [nw, 3], out [4], parent [nw])."""
+        import torch
+
+        nw = self._nw(w, nw)
+        nsteps = int(fields.shape[0])
+        dev = w.phi_a.device
+        fp = _dev(fields, torch.float64, (nsteps, nw, self.K), "fields")
+        if energy_out is None:
+            energy_out = torch.empty((nw, 3), dtype=torch.complex128, device=dev)
+        if out is None:
+            out = torch.empty(4, dtype=torch.float64, device=dev)
+        if parent is None:
+            parent = torch.empty(nw, dtype=torch.int32, device=dev)
+        s = w._struct(self, nw)
+        _check(_lib.afqmc_block(self._h, ctypes.byref(s), nw, fp, nsteps, float(u),
+                                _dev(energy_out, torch.complex128, (nw, 3), "energy"),
+                                _dev(out, torch.float64, (4,), "out"),
+                                _dev(parent, torch.int32, (nw,), "parent"),
+                                STEP_REUSE if reuse else 0, _stream_ptr(stream)))
+        return energy_out, out, parent
 
     def status(self, stream=None) -> int:
         v = ctypes.c_int()

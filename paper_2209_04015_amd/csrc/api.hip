@@ -87,6 +87,12 @@ struct afqmc_ham {
   double2* part = nullptr;    // [2][ntg][W]
   double* corr = nullptr;     // [W][2]
   int* status = nullptr;
+  // population control (comb): cumulative weights, tooth counts, extra-copy
+  // sources, parents
+  double* pc_csum = nullptr;  // [W]
+  int* pc_cnt = nullptr;      // [W]
+  int* pc_src = nullptr;      // [W]
+  int* pc_parent = nullptr;   // [W]
   int ntg = 0;
   int ex_gs = 0;         // exchange tile-order group size (0: built-in default; set by the autotuner)
   bool capturing = false;  // inside a graph capture: no phase-timing events
@@ -551,6 +557,10 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
   if ((rc = dalloc_t(h, &h->part, (size_t)2 * h->ntg * wtheta))) return rc;
   if ((rc = dalloc_t(h, &h->corr, W * 2))) return rc;
   if ((rc = dalloc_t(h, &h->status, (size_t)1))) return rc;
+  if ((rc = dalloc_t(h, &h->pc_csum, W))) return rc;
+  if ((rc = dalloc_t(h, &h->pc_cnt, W))) return rc;
+  if ((rc = dalloc_t(h, &h->pc_src, W))) return rc;
+  if ((rc = dalloc_t(h, &h->pc_parent, W))) return rc;
   if (h->split != SPLIT_NONE) {
     const size_t rows = wtheta * 4 * nmax;
     if ((rc = dalloc_t(h, &h->th_split, rows * 2 * d.ldh))) return rc;
@@ -712,6 +722,66 @@ int afqmc_step(afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields, int
   io.e = (double2*)e;
   return h->prec != AFQMC_FP64 ? seq_step<float>(h, w, nw, io, do_qr, flags, s)
                                : seq_step<double>(h, w, nw, io, do_qr, flags, s);
+}
+
+int afqmc_global_energy(afqmc_ham* h, const afqmc_walkers* w, int nw, const void* e, double* out,
+                        void* stream) {
+  int rc = check_walkers(h, w, nw);
+  if (rc) return rc;
+  if (!out || (nw > 0 && !e)) return fail(AFQMC_EINVAL, "null energy or output array");
+  if ((rc = set_device(h))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  PHASE(h, AFQMC_PH_CONTROL, s,
+        launch_global_energy(nw, nw ? w->log_w : nullptr, (const double2*)e, out, s));
+  return AFQMC_OK;
+}
+
+namespace {
+
+int seq_comb(afqmc_ham* h, afqmc_walkers* w, int nw, double u, int* parent, hipStream_t s) {
+  PHASE(h, AFQMC_PH_CONTROL, s,
+        launch_comb(h->d, nw, u, (double2*)w->phi_a, (double2*)w->phi_b, (double2*)w->log_ovlp, w->log_w,
+                    h->pc_csum, h->pc_cnt, h->pc_src, parent ? parent : h->pc_parent, h->status, s));
+  h->c_valid = false;  // walkers moved: the cached Green's function no longer matches
+  return AFQMC_OK;
+}
+
+}  // namespace
+
+int afqmc_population_control(afqmc_ham* h, afqmc_walkers* w, int nw, double u, int* parent, void* stream) {
+  int rc = check_walkers(h, w, nw);
+  if (rc || nw == 0) return rc;
+  if (!(u >= 0.0 && u < 1.0)) return fail(AFQMC_EINVAL, "comb offset u = %g outside [0, 1)", u);
+  if ((rc = set_device(h))) return rc;
+  return seq_comb(h, w, nw, u, parent, (hipStream_t)stream);
+}
+
+int afqmc_block(afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields, int nsteps, double u, void* e,
+                double* out, int* parent, int flags, void* stream) {
+  int rc = check_walkers(h, w, nw);
+  if (rc) return rc;
+  if (nsteps < 1) return fail(AFQMC_EINVAL, "nsteps = %d must be >= 1", nsteps);
+  if (!out || (nw > 0 && (!fields || !e))) return fail(AFQMC_EINVAL, "null fields, energy or output array");
+  if (!(u < 1.0)) return fail(AFQMC_EINVAL, "comb offset u = %g must be < 1 (negative: no comb)", u);
+  if ((rc = set_device(h))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (nw == 0) {
+    HIP_TRY(launch_global_energy(0, nullptr, nullptr, out, s));
+    return AFQMC_OK;
+  }
+  for (int st = 0; st < nsteps; ++st) {
+    const bool last = st == nsteps - 1;
+    StepIO io;
+    io.fields = fields + (size_t)st * nw * h->d.K;
+    io.e = last ? (double2*)e : nullptr;
+    const int f = st ? AFQMC_STEP_REUSE : flags;
+    rc = h->prec != AFQMC_FP64 ? seq_step<float>(h, w, nw, io, last, f, s)
+                               : seq_step<double>(h, w, nw, io, last, f, s);
+    if (rc) return rc;
+  }
+  PHASE(h, AFQMC_PH_CONTROL, s, launch_global_energy(nw, w->log_w, (const double2*)e, out, s));
+  if (u >= 0.0) return seq_comb(h, w, nw, u, parent, s);
+  return AFQMC_OK;
 }
 
 int afqmc_get_status(afqmc_ham* h, void* stream, int* out) {

@@ -125,3 +125,10 @@ hipError_t launch_exchange_split(int mode, const StepDims& d, int W, const unsig
                                  double2* part, int sp, int* ntg_out, hipStream_t s, int gs = 0);
 size_t qr_lds_bytes(const StepDims& d);
 size_t qr_lds_bytes_for(int N, int n);
+
+// --- ensemble (control_kernels.hip) ------------------------------------------
+// out[4] = {Re E, Im E, ln sum w, live walkers} of E = sum w E_L / sum w
+hipError_t launch_global_energy(int nw, const double* log_w, const double2* e, double* out, hipStream_t s);
+// comb population control in place; parent[nw] out; csum/cnt/src: [nw] scratch
+hipError_t launch_comb(const StepDims& d, int nw, double u, double2* phi_a, double2* phi_b, double2* log_ovlp,
+                       double* log_w, double* csum, int* cnt, int* src, int* parent, int* status, hipStream_t s);
