@@ -52,6 +52,14 @@ Readings where the paper is silent (each is listed in the design doc as well):
       in increasing slot order.  With no live walker nothing changes.
 * R18 Global energy (Sec. III.C): E = sum_z w_z E_L^z / sum_z w_z with the
       complex E_L = E1 + EJ + EK and w_z as in R17.
+* R20 Mixed S^2 (Sec. IV.B): <Psi_T|S^2|phi>/<Psi_T|phi> =
+      nb + Ms (Ms + 1) - sum_pq G^a_pq G^b_qp, Ms = (na - nb)/2.  The sum is
+      the trace of the product G^a G^b, as Wick's theorem gives for S_- S_+
+      and as the paper's code listing computes; the printed equation's index
+      order (no transpose) differs from it when G is not symmetric.
+* R21 Weighted walker mean of any per-walker value v_z (the reduction of
+      the global energy, R18, and of the mixed estimators of Sec. IV.B):
+      sum_z w_z v_z / sum_z w_z.
 * R19 Block (Sec. IV.A and IV.C): nsteps propagation steps, the last one
       followed by re-orthogonalisation and the local energy, then the global
       energy of the block, then the comb.
@@ -86,6 +94,8 @@ __all__ = [
     "global_energy",
     "comb",
     "block",
+    "s2_mixed",
+    "weighted_mean",
 ]
 
 
@@ -399,3 +409,33 @@ def block(ham, phi_a, phi_b, log_ovlp, log_w, x, u):
         phi_a, phi_b, log_ovlp = phi_a[parent], phi_b[parent], log_ovlp[parent]
         log_w = np.full_like(log_w, lw)
     return phi_a, phi_b, log_ovlp, log_w, e, E, parent
+
+
+# ---------------------------------------------------------------------------
+# Mixed estimators (Sec. IV.B; R20, R21)
+# ---------------------------------------------------------------------------
+
+def s2_mixed(ham, phi_a, phi_b):
+    """<Psi_T|S^2|phi_z>/<Psi_T|phi_z> for each walker (R20), complex [W]."""
+    na, nb = ham.phiT_a.shape[1], ham.phiT_b.shape[1]
+    ms = 0.5 * (na - nb)
+    out = np.full(phi_a.shape[0], nb + ms * (ms + 1.0), dtype=np.complex128)
+    if na == 0 or nb == 0:
+        return out
+    Ga = full_green(ham.phiT_a, phi_a)
+    Gb = full_green(ham.phiT_b, phi_b)
+    return out - np.einsum("zpq,zqp->z", Ga, Gb)
+
+
+def weighted_mean(log_w, v):
+    """(sum_z w_z v_z / sum_z w_z for every column of v [W, m], ln sum w, live walkers) (R21).
+
+    Weights as in R17; with no live walker the means are NaN.
+    """
+    w, m = _linear_weights(log_w)
+    v = np.asarray(v).reshape(len(w), -1)
+    live = int(np.count_nonzero(w))
+    if live == 0:
+        return np.full(v.shape[1], complex(np.nan, np.nan)), -np.inf, 0
+    den = float(np.sum(w))
+    return (w @ v) / den, m + math.log(den), live

@@ -591,3 +591,71 @@ def test_comb_tooth_past_the_last_sum_goes_to_the_last_live_walker():
     c = np.bincount(parent, minlength=nw)
     assert c[5] == 0 and c.sum() == nw
     assert c[4] == np.count_nonzero(((np.arange(nw) + u) * w.sum() / nw) >= np.cumsum(w)[3])
+
+
+# ---------------------------------------------------------------------------
+# Mixed S^2 (Sec. IV.B, R20) and the weighted walker mean (R21)
+# ---------------------------------------------------------------------------
+
+def _fock_s2(fs, v):
+    """S^2 |v> = (S_- S_+ + S_z + S_z^2) |v>, S_+ = sum_p a+_{p up} a_{p down}."""
+    N = fs.N
+    splus = np.zeros_like(v)
+    for p in range(N):
+        splus = splus + fs.cre(p, fs.ann(N + p, v))
+    sms = np.zeros_like(v)
+    for q in range(N):
+        sms = sms + fs.cre(N + q, fs.ann(q, splus))
+    states = np.arange(fs.dim)
+    nup = np.array([bin(int(b & ((1 << N) - 1))).count("1") for b in states])
+    ndn = np.array([bin(int(b >> N)).count("1") for b in states])
+    sz = 0.5 * (nup - ndn)
+    return sms + (sz + sz * sz) * v
+
+
+@pytest.mark.parametrize("na,nb", [(2, 1), (1, 2), (2, 2), (3, 1)])
+def test_s2_mixed_matches_fock_space(na, nb):
+    N = 3
+    h1, L = inputs.hamiltonian(N, 4, decay=3.0, seed=3)
+    phiT_a = inputs.trial(h1, na)
+    phiT_b = inputs.trial(h1 + 0.3 * np.diag([1.0, -0.5, 0.2]), nb)
+    ham = orc.setup(h1, L, phiT_a, phiT_b)
+    pa = _rand_walkers(phiT_a, 3, seed=4, scale=0.5, stream=0)
+    pb = _rand_walkers(phiT_b, 3, seed=4, scale=0.5, stream=1)
+    fs = FockSpace(N)
+    psiT = fs.determinant(phiT_a, phiT_b)
+    got = orc.s2_mixed(ham, pa, pb)
+    for z in range(3):
+        v = fs.determinant(pa[z], pb[z])
+        ref = np.vdot(psiT, _fock_s2(fs, v)) / np.vdot(psiT, v)
+        assert got[z] == pytest.approx(ref, abs=1e-12)
+
+
+def test_s2_of_closed_shell_and_high_spin_determinants():
+    # a closed-shell determinant (same orbitals for both spins) is a singlet;
+    # a single determinant with every electron up has S = Ms = na / 2
+    h1, L = inputs.hamiltonian(6, 8, decay=3.0, seed=5)
+    phiT = inputs.trial(h1, 3)
+    ham = orc.setup(h1, L, phiT, phiT)
+    pa = phiT[None].astype(np.complex128)
+    assert orc.s2_mixed(ham, pa, pa.copy())[0] == pytest.approx(0.0, abs=1e-12)
+    ham_hs = orc.setup(h1, L, phiT, phiT[:, :0])
+    s = 1.5
+    walk = _rand_walkers(phiT, 2, seed=6, scale=0.4)
+    assert np.allclose(orc.s2_mixed(ham_hs, walk, walk[:, :, :0]), s * (s + 1), atol=1e-13)
+
+
+def test_weighted_mean_definition():
+    rng = np.random.default_rng(11)
+    W, m = 25, 4
+    v = rng.normal(size=(W, m)) + 1j * rng.normal(size=(W, m))
+    lw = rng.normal(0.0, 1.0, W)
+    lw[[2, 9]] = -np.inf
+    mean, lsw, live = orc.weighted_mean(lw, v)
+    w = np.where(np.isfinite(lw), np.exp(np.where(np.isfinite(lw), lw, 0.0)), 0.0)
+    for k in range(m):
+        assert mean[k] == pytest.approx(np.sum(w * v[:, k]) / np.sum(w), rel=1e-12)
+    assert lsw == pytest.approx(math.log(np.sum(w)), rel=1e-12) and live == W - 2
+    # the global energy is the weighted mean of E1 + EJ + EK
+    e = rng.normal(size=(W, 3)) + 1j * rng.normal(size=(W, 3))
+    assert orc.weighted_mean(lw, e.sum(axis=1))[0][0] == pytest.approx(orc.global_energy(lw, e)[0], rel=1e-13)
