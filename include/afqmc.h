@@ -198,6 +198,38 @@ int afqmc_population_control(afqmc_ham* ham, afqmc_walkers* w, int nw, double u,
 int afqmc_block(afqmc_ham* ham, afqmc_walkers* w, int nw, const double* fields, int nsteps, double u,
                 void* e, double* out, int* parent, int flags, void* stream);
 
+/* ---- mixed estimators (Sec. IV.B) ----
+ * These calls recompute theta of the walkers they are given (in the working
+ * precision: FP32 in the mixed modes, with FP64 products and sums); a
+ * following afqmc_step with AFQMC_STEP_REUSE on the same walkers stays
+ * valid. */
+
+/* Full one-body Green's functions of every walker and spin (Eqs. gf,
+ * halfgf):  G[z][s][p][q] = <Psi_T|a+_{p s} a_{q s}|phi_z> / <Psi_T|phi_z>
+ *                         = sum_i PhiT_s[p][i] theta^s_z[q][i],
+ * theta = phi (PhiT^T phi)^-1.  G: complex [nw][2][N][N], written (the beta
+ * block is zero when nb = 0).  This is the input of custom one-body mixed
+ * estimators: a caller's kernel forms per-walker values from G and
+ * afqmc_weighted_mean averages them over the ensemble. */
+int afqmc_green_function(afqmc_ham* ham, const afqmc_walkers* w, int nw, void* G, void* stream);
+
+/* Mixed estimator of S^2 for a single-determinant trial (Sec. IV.B):
+ *   s2[z] = nb + Ms (Ms + 1) - sum_pq G^a_pq G^b_qp,  Ms = (na - nb) / 2,
+ * the trace of the product G^a G^b as Wick's theorem gives for S_- S_+
+ * (formed as sum_ij X_ij Y_ji with X = theta_b^T PhiT_a, Y = theta_a^T PhiT_b,
+ * without the N x N matrices).  s2: complex [nw], written. */
+int afqmc_s2_mixed(afqmc_ham* ham, const afqmc_walkers* w, int nw, void* s2, void* stream);
+
+/* Weighted ensemble average of m per-walker values (the reduction of the
+ * global energy, Sec. III.C, for any mixed estimator):
+ *   out[2k], out[2k+1] = Re, Im of sum_z w_z v[z][k] / sum_z w_z, k < m;
+ *   out[2m] = ln sum_z w_z;  out[2m+1] = walkers with w_z > 0.
+ * v: complex [nw][m], read (NULL allowed when nw = 0); out: device double
+ * [2m + 2], written; 1 <= m <= 2^24.  With no live walker the means are NaN,
+ * out[2m] = -inf and out[2m+1] = 0. */
+int afqmc_weighted_mean(afqmc_ham* ham, const afqmc_walkers* w, int nw, const void* v, int m,
+                        double* out, void* stream);
+
 /* Synchronise `stream`, return the accumulated status bits in *out and clear them. */
 int afqmc_get_status(afqmc_ham* ham, void* stream, int* out);
 
@@ -226,6 +258,7 @@ enum {
   AFQMC_PH_SPLIT,        /* hi/lo split of theta and of the shifted fields
                             (16-bit split modes) */
   AFQMC_PH_CONTROL,      /* global energy and population control */
+  AFQMC_PH_ESTIMATOR,    /* mixed estimators: full Green's function, S^2, weighted means */
   AFQMC_NPHASE
 };
 int afqmc_profile_enable(afqmc_ham* ham, int max_records);

@@ -40,6 +40,9 @@ EXPORTED = (
     "afqmc_global_energy",
     "afqmc_population_control",
     "afqmc_block",
+    "afqmc_green_function",
+    "afqmc_s2_mixed",
+    "afqmc_weighted_mean",
     "afqmc_get_status",
     "afqmc_get_setup",
     "afqmc_profile_enable",
@@ -56,7 +59,7 @@ EXPORTED = (
 
 # kernel phases of afqmc_profile_read, in header order
 PHASES = ("green", "force_bias", "shift", "vhs", "one_body", "taylor", "qr", "weight",
-          "exchange", "energy", "split", "control")
+          "exchange", "energy", "split", "control", "estimator")
 
 
 class AfqmcError(RuntimeError):
@@ -116,6 +119,9 @@ def load(path: str = LIB_PATH):
     lib.afqmc_global_energy.argtypes = [vp, P(_Walkers), ip, vp, vp, vp]
     lib.afqmc_population_control.argtypes = [vp, P(_Walkers), ip, ctypes.c_double, vp, vp]
     lib.afqmc_block.argtypes = [vp, P(_Walkers), ip, vp, ip, ctypes.c_double, vp, vp, vp, ip, vp]
+    lib.afqmc_green_function.argtypes = [vp, P(_Walkers), ip, vp, vp]
+    lib.afqmc_s2_mixed.argtypes = [vp, P(_Walkers), ip, vp, vp]
+    lib.afqmc_weighted_mean.argtypes = [vp, P(_Walkers), ip, vp, ip, vp, vp]
     lib.afqmc_get_status.argtypes = [vp, vp, P(ip)]
     lib.afqmc_get_setup.argtypes = [vp, vp, dp, dp]
     lib.afqmc_profile_enable.argtypes = [vp, ip]
@@ -365,6 +371,44 @@ class Hamiltonian:
                                 _dev(parent, torch.int32, (nw,), "parent"),
                                 STEP_REUSE if reuse else 0, _stream_ptr(stream)))
         return energy_out, out, parent
+
+    def green_function(self, w: Walkers, out=None, nw=None, stream=None):
+        """Device complex128 [nw, 2, N, N]: G^s_pq of every walker."""
+        import torch
+
+        nw = self._nw(w, nw)
+        if out is None:
+            out = torch.empty((nw, 2, self.N, self.N), dtype=torch.complex128, device=w.phi_a.device)
+        ptr = _dev(out, torch.complex128, (nw, 2, self.N, self.N), "G")
+        s = w._struct(self, nw)
+        _check(_lib.afqmc_green_function(self._h, ctypes.byref(s), nw, ptr, _stream_ptr(stream)))
+        return out
+
+    def s2_mixed(self, w: Walkers, out=None, nw=None, stream=None):
+        """Device complex128 [nw]: the mixed estimator of S^2 of every walker."""
+        import torch
+
+        nw = self._nw(w, nw)
+        if out is None:
+            out = torch.empty(nw, dtype=torch.complex128, device=w.phi_a.device)
+        ptr = _dev(out, torch.complex128, (nw,), "s2")
+        s = w._struct(self, nw)
+        _check(_lib.afqmc_s2_mixed(self._h, ctypes.byref(s), nw, ptr, _stream_ptr(stream)))
+        return out
+
+    def weighted_mean(self, w: Walkers, values, out=None, nw=None, stream=None):
+        """values complex128 [nw, m] -> device float64 [2m + 2] (means re/im, ln sum w, live)."""
+        import torch
+
+        nw = self._nw(w, nw)
+        m = int(values.shape[1]) if values.dim() == 2 else 1
+        if out is None:
+            out = torch.empty(2 * m + 2, dtype=torch.float64, device=w.phi_a.device)
+        vptr = _dev(values, torch.complex128, (nw, m) if values.dim() == 2 else (nw,), "values")
+        optr = _dev(out, torch.float64, (2 * m + 2,), "out")
+        s = w._struct(self, nw)
+        _check(_lib.afqmc_weighted_mean(self._h, ctypes.byref(s), nw, vptr, m, optr, _stream_ptr(stream)))
+        return out
 
     def status(self, stream=None) -> int:
         v = ctypes.c_int()

@@ -606,6 +606,20 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
 // exported entry points
 // ===========================================================================
 
+namespace {
+
+// theta of the given walkers into the workspace; the step cache survives only
+// if these are the cached walkers (theta is then recomputed bit for bit).
+template <typename T>
+int seq_theta_keep_cache(afqmc_ham* h, const afqmc_walkers* w, int nw, hipStream_t s) {
+  const bool same = h->c_valid && h->c_phi_a == w->phi_a && h->c_phi_b == w->phi_b && h->c_nw == nw;
+  int rc = seq_theta<T>(h, w, nw, false, s);
+  if (!same) h->c_valid = false;
+  return rc;
+}
+
+}  // namespace
+
 extern "C" {
 
 int afqmc_version(void) { return 1; }
@@ -781,6 +795,51 @@ int afqmc_block(afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields, in
   }
   PHASE(h, AFQMC_PH_CONTROL, s, launch_global_energy(nw, w->log_w, (const double2*)e, out, s));
   if (u >= 0.0) return seq_comb(h, w, nw, u, parent, s);
+  return AFQMC_OK;
+}
+
+int afqmc_green_function(afqmc_ham* h, const afqmc_walkers* w, int nw, void* G, void* stream) {
+  int rc = check_walkers(h, w, nw);
+  if (rc || nw == 0) return rc;
+  if (!G) return fail(AFQMC_EINVAL, "null G");
+  if ((rc = set_device(h))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (h->prec != AFQMC_FP64) {
+    if ((rc = seq_theta_keep_cache<float>(h, w, nw, s))) return rc;
+    PHASE(h, AFQMC_PH_ESTIMATOR, s, launch_green_full<float>(h->d, nw, (const float*)h->theta, h->phiT, (double2*)G, s));
+  } else {
+    if ((rc = seq_theta_keep_cache<double>(h, w, nw, s))) return rc;
+    PHASE(h, AFQMC_PH_ESTIMATOR, s, launch_green_full<double>(h->d, nw, (const double*)h->theta, h->phiT, (double2*)G, s));
+  }
+  return AFQMC_OK;
+}
+
+int afqmc_s2_mixed(afqmc_ham* h, const afqmc_walkers* w, int nw, void* s2, void* stream) {
+  int rc = check_walkers(h, w, nw);
+  if (rc || nw == 0) return rc;
+  if (!s2) return fail(AFQMC_EINVAL, "null s2");
+  if ((rc = set_device(h))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (h->prec != AFQMC_FP64) {
+    if ((rc = seq_theta_keep_cache<float>(h, w, nw, s))) return rc;
+    PHASE(h, AFQMC_PH_ESTIMATOR, s, launch_s2<float>(h->d, nw, (const float*)h->theta, h->phiT, (double2*)s2, s));
+  } else {
+    if ((rc = seq_theta_keep_cache<double>(h, w, nw, s))) return rc;
+    PHASE(h, AFQMC_PH_ESTIMATOR, s, launch_s2<double>(h->d, nw, (const double*)h->theta, h->phiT, (double2*)s2, s));
+  }
+  return AFQMC_OK;
+}
+
+int afqmc_weighted_mean(afqmc_ham* h, const afqmc_walkers* w, int nw, const void* v, int m, double* out,
+                        void* stream) {
+  int rc = check_walkers(h, w, nw);
+  if (rc) return rc;
+  if (m < 1 || m > (1 << 24)) return fail(AFQMC_EINVAL, "m = %d outside [1, 2^24]", m);
+  if (!out || (nw > 0 && !v)) return fail(AFQMC_EINVAL, "null value or output array");
+  if ((rc = set_device(h))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  PHASE(h, AFQMC_PH_ESTIMATOR, s,
+        launch_weighted_mean(nw, m, nw ? w->log_w : nullptr, (const double2*)v, out, s));
   return AFQMC_OK;
 }
 

@@ -132,3 +132,14 @@ hipError_t launch_global_energy(int nw, const double* log_w, const double2* e, d
 // comb population control in place; parent[nw] out; csum/cnt/src: [nw] scratch
 hipError_t launch_comb(const StepDims& d, int nw, double u, double2* phi_a, double2* phi_b, double2* log_ovlp,
                        double* log_w, double* csum, int* cnt, int* src, int* parent, int* status, hipStream_t s);
+
+// --- mixed estimators (estimator_kernels.hip) ---------------------------------
+// G [W][2][N][N] complex: G_pq = sum_i PhiT[p][i] theta[q][i] per spin
+template <typename T>
+hipError_t launch_green_full(const StepDims& d, int W, const T* theta, const double* phiT, double2* G,
+                             hipStream_t s);
+// s2 [W] complex: nb + Ms (Ms + 1) - tr(G^a G^b)
+template <typename T>
+hipError_t launch_s2(const StepDims& d, int W, const T* theta, const double* phiT, double2* s2, hipStream_t s);
+// out [2 m + 2]: weighted means of the m columns of v [nw][m], ln sum w, live walkers
+hipError_t launch_weighted_mean(int nw, int m, const double* log_w, const double2* v, double* out, hipStream_t s);

@@ -15,7 +15,7 @@ HEADER = os.path.join(ROOT, "include", "afqmc.h")
 
 def _declared():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(afqmc_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(afqmc_[a-z0-9_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
