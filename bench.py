@@ -35,13 +35,26 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def exchange_flops_per_launch(cfg, W):
-    # one launch = one spin: T = Lh_g theta_z for every (g, z): K * n^2 * N real x complex
-    # multiply-adds (4 flops each); the T_ij T_ji pairing adds 8 K n^2 flops per walker.
-    return W * (4.0 * cfg.K * cfg.n * cfg.n * cfg.N + 8.0 * cfg.K * cfg.n * cfg.n)
+def exchange_flops_per_launch(cfg, W, algo):
+    """Algorithmic flops of one exchange launch (one spin) for the algorithm in use."""
+    N, n, K = cfg.N, cfg.n, cfg.K
+    if algo == "pair":
+        # pair integrals: U = V_ij Theta_i for i <= j, n (n + 1) / 2 N^2 real x complex
+        # multiply-adds per walker (4 flops), then U . Theta_j: n (n + 1) / 2 N complex
+        # multiply-adds (8 flops)
+        P = n * (n + 1) / 2.0
+        return W * (4.0 * P * N * N + 8.0 * P * N)
+    # direct: T = Lh_g theta_z for every (g, z): K n^2 N real x complex multiply-adds
+    # (4 flops each); the T_ij T_ji pairing adds 8 K n^2 flops per walker.
+    return W * (4.0 * K * n * n * N + 8.0 * K * n * n)
 
 
-def step_flops(cfg):
+def vhs_flops_per_launch(cfg, W):
+    # VHS_z = i sqrt(dt) sum_g xs_zg L_g on the N (N + 1) / 2 packed pairs: complex x real
+    return W * 2.0 * cfg.K * cfg.N * (cfg.N + 1)
+
+
+def step_flops(cfg, algo="direct"):
     """Algorithmic flops of one walker-step (both spins), by part."""
     N, n, K = cfg.N, cfg.n, cfg.K
     return {
@@ -50,23 +63,24 @@ def step_flops(cfg):
         "vhs": 2.0 * K * N * (N + 1),
         "one_body": 16.0 * N * N * n,
         "taylor": 96.0 * N * N * n,
-        "exchange": 8.0 * K * n * n * N + 16.0 * K * n * n,
+        "exchange": 2.0 * exchange_flops_per_launch(cfg, 1, algo),
     }
 
 
 BLOCK_STEPS = 25   # propagation steps per block (the paper's timing convention)
 
 
-def run_gpu(cfg, h1, L, phiT, precision, steps, warmup, fields_dev, block_fields_dev, device):
+def run_gpu(cfg, h1, L, phiT, precision, steps, warmup, fields_dev, block_fields_dev, device,
+            exchange="auto"):
     import torch
 
     from paper_2209_04015_amd import afqmc
 
     W = cfg.W
     t = time.time()
-    ham = afqmc.Hamiltonian(h1, L, phiT, phiT, dt=cfg.dt, max_walkers=W, precision=precision,
+    ham = afqmc.Hamiltonian(h1, L, phiT, phiT, dt=cfg.dt, max_walkers=W, precision=precision, exchange=exchange,
                             taylor_order=cfg.taylor_order)
-    log(f"{precision}: init {time.time() - t:.1f} s")
+    log(f"{precision}: init {time.time() - t:.1f} s, exchange algorithm {ham.exchange}")
     pa = torch.as_tensor(np.repeat(phiT[None].astype(np.complex128), W, axis=0), device=device)
     w = afqmc.Walkers(pa, pa.clone())
     ham.overlap(w)
@@ -108,7 +122,8 @@ def run_gpu(cfg, h1, L, phiT, precision, steps, warmup, fields_dev, block_fields
     ms_block = start.elapsed_time(stop)
     log(f"{precision}: propagation only {ms_prop / steps:.2f} ms/step; block of {BLOCK_STEPS} "
         f"steps {ms_block:.1f} ms")
-    extra = {"propagation_only": {"value": round(W * steps / (ms_prop * 1e-3), 2), "unit": "walker-steps/s",
+    extra = {"exchange_algorithm": ham.exchange,
+             "propagation_only": {"value": round(W * steps / (ms_prop * 1e-3), 2), "unit": "walker-steps/s",
                                   "ms_per_step": round(ms_prop / steps, 4)},
              "block": {"value": round(W * BLOCK_STEPS / (ms_block * 1e-3), 2), "unit": "walker-steps/s",
                        "ms_per_block": round(ms_block, 3),
@@ -123,6 +138,11 @@ def run_gpu(cfg, h1, L, phiT, precision, steps, warmup, fields_dev, block_fields
 KERNEL_SOURCES = {
     "exchange_split_kernel": ["split_kernels.hip", "split_tile.h", "exchange_tri.h", "tile_order.h", "common.h"],
     "exchange_kernel": ["step_kernels.hip", "mfma_tile.h", "exchange_epilogue.h", "tile_order.h", "common.h"],
+    "exchange_pair_split_kernel": ["split_kernels.hip", "split_tile.h", "exchange_pair.h", "tile_order.h",
+                                   "common.h"],
+    "exchange_pair_kernel": ["step_kernels.hip", "mfma_tile.h", "exchange_pair.h", "tile_order.h", "common.h"],
+    "vhs_split_kernel": ["split_kernels.hip", "split_tile.h", "tile_order.h", "common.h"],
+    "vhs_kernel": ["step_kernels.hip", "mfma_tile.h", "tile_order.h", "common.h"],
 }
 
 
@@ -158,31 +178,57 @@ def hbm_traffic(kernel, instance, workload):
     return None
 
 
-def roofline(cfg, phases, precision):
-    ms, launches = phases["exchange"]
+# kernel (and its template instance in the rocprofv3 summaries) per phase,
+# precision and exchange algorithm
+def _kernel_of(phase, precision, algo):
+    split = precision in ("fp16x3", "bf16x3")
+    H = {"fp16x3": "HalfF16", "bf16x3": "HalfBF16"}.get(precision)
+    T = {"fp32": "float", "fp64": "double", "bf16x3": "float"}.get(precision)
+    if phase == "exchange":
+        base = ("exchange_pair" if algo == "pair" else "exchange") + ("_split_kernel" if split else "_kernel")
+        return base, f"{base}<{H if split else T}>"
+    if precision == "fp16x3":   # the VHS runs on split operands only in FP16X3
+        return "vhs_split_kernel", "vhs_split_kernel<HalfF16>"
+    return "vhs_kernel", f"vhs_kernel<{T}>"
+
+
+def roofline_of(cfg, phases, precision, algo, phase):
+    ms, launches = phases[phase]
     if launches == 0:
         return None
     avg_ms = ms / launches
-    flops = exchange_flops_per_launch(cfg, cfg.W)
+    flops = (exchange_flops_per_launch(cfg, cfg.W, algo) if phase == "exchange"
+             else vhs_flops_per_launch(cfg, cfg.W))
     achieved = flops / (avg_ms * 1e-3) / 1e12
-    kernel = "exchange_kernel"
+    kernel, instance = _kernel_of(phase, precision, algo)
     note = None
-    if precision in ("fp32", "fp64"):
-        peak = PEAK_TFLOPS[precision]
-        instance = {"fp32": "exchange_kernel<float>", "fp64": "exchange_kernel<double>"}[precision]
-    else:
+    if "split" in kernel:
         # three 16-bit products per algorithmic multiply-add
         peak = round(PEAK_TFLOPS[precision[:4]] / 3.0, 1)
-        kernel = "exchange_split_kernel"
-        instance = {"fp16x3": "exchange_split_kernel<HalfF16>", "bf16x3": "exchange_split_kernel<HalfBF16>"}[precision]
         note = f"{precision[:4]} dense peak / 3 products"
+    else:
+        peak = PEAK_TFLOPS["fp64" if precision == "fp64" else "fp32"]
     out = {"kernel": kernel, "bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
            "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
            "traffic": hbm_traffic(kernel, instance, cfg.name),
-           "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": flops}
+           "avg_launch_ms": round(avg_ms, 4), "launches_per_step_share_ms": round(ms, 3),
+           "flops_per_launch": flops}
     if note:
         out["peak_note"] = note
     return out
+
+
+def rooflines(cfg, phases, precision, algo):
+    """Roofline entries of the exchange and VHS kernels; the first is the one with
+    the larger share of the step (the dominant kernel)."""
+    out = {ph: roofline_of(cfg, phases, precision, algo, ph) for ph in ("exchange", "vhs")}
+    order = sorted(out, key=lambda ph: -phases[ph][0])
+    return {ph: out[ph] for ph in order if out[ph] is not None}
+
+
+def roofline(cfg, phases, precision, algo):
+    r = rooflines(cfg, phases, precision, algo)
+    return next(iter(r.values())) if r else None
 
 
 def cpu_baseline_and_energy_error(cfg, h1, L, phiT, gpu_states, sample, x_sample):
@@ -287,12 +333,27 @@ def main():
         del w, e
         torch.cuda.empty_cache()
 
+    # the paper's direct exchange algorithm on the headline path, for comparison
+    direct = None
+    if not args.only:
+        ham, w, e, ms_d, ph_d, st_d, ex_d = run_gpu(cfg, h1, L, phiT, args.headline, args.steps, args.warmup,
+                                                   fields_dev, block_fields_dev, device, exchange="direct")
+        direct = {"exchange_algorithm": "direct", "value": round(cfg.W * args.steps / (ms_d * 1e-3), 2),
+                  "unit": "walker-steps/s", "ms_per_step": round(ms_d / args.steps, 4),
+                  "roofline": roofline(cfg, ph_d, args.headline, "direct"),
+                  "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in ph_d.items() if v[1] > 0}}
+        ham.close()
+        del w, e
+        torch.cuda.empty_cache()
+
     if args.only:
         ms, ph, st = results[args.only]
         print(json.dumps({"metric": METRIC, "value": round(cfg.W * args.steps / (ms * 1e-3), 2),
                           "unit": "walker-steps/s", "n_gpus": 1, "steps": args.steps,
                           "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 4),
-                          "only": args.only, "roofline": roofline(cfg, ph, args.only),
+                          "only": args.only,
+                          "roofline": roofline(cfg, ph, args.only, extras[args.only]["exchange_algorithm"]),
+                          "rooflines": rooflines(cfg, ph, args.only, extras[args.only]["exchange_algorithm"]),
                           **extras[args.only],
                           "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in ph.items()
                                                  if v[1] > 0}}), flush=True)
@@ -314,12 +375,14 @@ def main():
     head = args.headline
     msh, phh, sth = results[head]
     ms64, ph64, st64 = results["fp64"]
-    fl = step_flops(cfg)
+    fl = step_flops(cfg, extras[head]["exchange_algorithm"])
     paths = {}
     for p in MODES:
         ms, ph, st = results[p]
         paths[p] = {"value": round(rate(ms), 2), "unit": "walker-steps/s",
-                    "ms_per_step": round(ms / args.steps, 4), "roofline": roofline(cfg, ph, p),
+                    "ms_per_step": round(ms / args.steps, 4),
+                    "roofline": roofline(cfg, ph, p, extras[p]["exchange_algorithm"]),
+                    "rooflines": rooflines(cfg, ph, p, extras[p]["exchange_algorithm"]),
                     "phases_ms_per_step": phase_table(ph), "status": st,
                     "energy_error_vs_fp64_oracle": (eerr or {}).get(p), **extras[p]}
     dtypes = {"fp32": "f32 contractions (MFMA)",
@@ -342,16 +405,20 @@ def main():
             "workload": f"{cfg.name}: ph-AFQMC full walker step (propagate + QR + local energy every "
                         f"step), N={cfg.N} orbitals, na=nb={cfg.n}, K={cfg.K} Cholesky vectors, "
                         f"{W} walkers, dt={cfg.dt}, Taylor order {cfg.taylor_order}, QR every "
-                        f"{cfg.qr_interval} step(s)",
+                        f"{cfg.qr_interval} step(s); exchange energy through pair integrals "
+                        f"({extras[head]['exchange_algorithm']})",
+            "exchange_algorithm": extras[head]["exchange_algorithm"],
             "walkers": W, "N": cfg.N, "n_per_spin": cfg.n, "K": cfg.K, "headline_path": head,
         },
-        "roofline": roofline(cfg, phh, head),
+        "roofline": roofline(cfg, phh, head, extras[head]["exchange_algorithm"]),
+        "rooflines": rooflines(cfg, phh, head, extras[head]["exchange_algorithm"]),
         "cpu_baseline": cpu,
         "fp64": paths["fp64"],
         "mixed_over_fp64": round(ms64 / msh, 3),
         "energy_error_vs_fp64_oracle": (eerr or {}).get(head),
         **extras[head],
         "phases_ms_per_step": phase_table(phh),
+        "direct_exchange": direct,
         "paths": paths,
         "algorithmic_gflop_per_walker_step": {k: round(v / 1e9, 4) for k, v in fl.items()},
         "status": sth,

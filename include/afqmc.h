@@ -78,7 +78,26 @@ typedef struct afqmc_params {
   int max_walkers;      /* workspace is sized for this many walkers */
   double mu;            /* scalar factored out of the one-body half step; NaN -> tr(h')/N */
   double e_shift;       /* energy shift E_T of the weights; NaN -> E_L(PhiT) computed in FP64 */
+  int exchange;         /* AFQMC_EXCHANGE_*: algorithm of the exchange energy (0 = automatic) */
 } afqmc_params;
+
+/* Algorithms of the exchange energy E_K = -1/2 sum_s sum_g sum_ij T_ij T_ji
+ * (Sec. III.C).  Both give the same sum up to rounding.
+ *   AFQMC_EXCHANGE_DIRECT  the direct algorithm of the paper: T_g = Lh_g theta
+ *                          formed tile by tile and paired in the tile
+ *                          (K n^2 N products per walker and spin)
+ *   AFQMC_EXCHANGE_PAIR    the same sum with the Cholesky index summed first:
+ *                          pair integrals V_ij[p][q] = sum_g Lh_g[i][p] Lh_g[j][q]
+ *                          (i <= j) built at init, E_K from
+ *                          sum_ij Theta_j V_ij Theta_i^T (n (n + 1) / 2 N^2
+ *                          products; n (n + 1) / 2 N^2 stored values per spin,
+ *                          shared by the spins when their trial orbitals are
+ *                          equal)
+ *   AFQMC_EXCHANGE_AUTO    PAIR when it needs at least 1.5x fewer products
+ *                          (2 K n / ((n + 1) N) > 1.5) and its arrays fit in
+ *                          48 GB, else DIRECT
+ * afqmc_get_exchange_algorithm reports the choice. */
+enum { AFQMC_EXCHANGE_AUTO = 0, AFQMC_EXCHANGE_DIRECT = 1, AFQMC_EXCHANGE_PAIR = 2 };
 
 /* Walker ensemble (Eq. stat_wfs), caller-owned device arrays. */
 typedef struct afqmc_walkers {
@@ -232,6 +251,9 @@ int afqmc_weighted_mean(afqmc_ham* ham, const afqmc_walkers* w, int nw, const vo
 
 /* Synchronise `stream`, return the accumulated status bits in *out and clear them. */
 int afqmc_get_status(afqmc_ham* ham, void* stream, int* out);
+
+/* The exchange algorithm in use (AFQMC_EXCHANGE_DIRECT or _PAIR) into *out. */
+int afqmc_get_exchange_algorithm(afqmc_ham* ham, int* out);
 
 /* Setup results for inspection: host_P [N][N] (may be NULL), *mu, *e_shift
  * (either may be NULL).  Synchronises the device. */

@@ -26,6 +26,8 @@ FP16X3 = 3
 STEP_REUSE = 1
 # status-word bits (afqmc_get_status)
 STATUS_SINGULAR, STATUS_NONFINITE, STATUS_QR_ZERO, STATUS_NO_LIVE = 1, 2, 4, 8
+EXCHANGE_AUTO, EXCHANGE_DIRECT, EXCHANGE_PAIR = 0, 1, 2
+_EXCHANGE = {"auto": EXCHANGE_AUTO, "direct": EXCHANGE_DIRECT, "pair": EXCHANGE_PAIR}
 _PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3,
                FP64: FP64, FP32: FP32, BF16X3: BF16X3, FP16X3: FP16X3}
 
@@ -43,6 +45,7 @@ EXPORTED = (
     "afqmc_green_function",
     "afqmc_s2_mixed",
     "afqmc_weighted_mean",
+    "afqmc_get_exchange_algorithm",
     "afqmc_get_status",
     "afqmc_get_setup",
     "afqmc_profile_enable",
@@ -80,6 +83,7 @@ class _Params(ctypes.Structure):
         ("max_walkers", ctypes.c_int),
         ("mu", ctypes.c_double),
         ("e_shift", ctypes.c_double),
+        ("exchange", ctypes.c_int),
     ]
 
 
@@ -122,6 +126,7 @@ def load(path: str = LIB_PATH):
     lib.afqmc_green_function.argtypes = [vp, P(_Walkers), ip, vp, vp]
     lib.afqmc_s2_mixed.argtypes = [vp, P(_Walkers), ip, vp, vp]
     lib.afqmc_weighted_mean.argtypes = [vp, P(_Walkers), ip, vp, ip, vp, vp]
+    lib.afqmc_get_exchange_algorithm.argtypes = [vp, P(ip)]
     lib.afqmc_get_status.argtypes = [vp, vp, P(ip)]
     lib.afqmc_get_setup.argtypes = [vp, vp, dp, dp]
     lib.afqmc_profile_enable.argtypes = [vp, ip]
@@ -226,7 +231,7 @@ class Hamiltonian:
     """A Hamiltonian handle (afqmc_init_hamiltonian) and its workspace."""
 
     def __init__(self, h1, chol, phiT_a, phiT_b=None, *, dt, max_walkers, taylor_order=6,
-                 precision="fp64", mu=None, e_shift=None, stream=None):
+                 precision="fp64", mu=None, e_shift=None, exchange="auto", stream=None):
         lib = load()
         h1 = np.asarray(h1)
         N = h1.shape[0]
@@ -244,7 +249,8 @@ class Hamiltonian:
         self.precision = _PRECISIONS[precision]
         self.max_walkers = int(max_walkers)
         p = _Params(N, na, nb, K, float(dt), int(taylor_order), self.precision, self.max_walkers,
-                    math.nan if mu is None else float(mu), math.nan if e_shift is None else float(e_shift))
+                    math.nan if mu is None else float(mu), math.nan if e_shift is None else float(e_shift),
+                    _EXCHANGE[exchange])
         h = ctypes.c_void_p()
         _check(lib.afqmc_init_hamiltonian(
             ctypes.byref(p), self._h1.ctypes.data, self._chol.ctypes.data, self._pa.ctypes.data,
@@ -252,6 +258,9 @@ class Hamiltonian:
         self._h = h
         # host copies are not needed after init
         self._chol = None
+        v = ctypes.c_int()
+        _check(lib.afqmc_get_exchange_algorithm(self._h, ctypes.byref(v)))
+        self.exchange = {EXCHANGE_DIRECT: "direct", EXCHANGE_PAIR: "pair"}[v.value]
 
     def close(self):
         if getattr(self, "_h", None):

@@ -94,6 +94,15 @@ struct afqmc_ham {
   int* pc_src = nullptr;      // [W]
   int* pc_parent = nullptr;   // [W]
   int ntg = 0;
+  // exchange through pair integrals (AFQMC_EXCHANGE_PAIR)
+  int ex_algo = AFQMC_EXCHANGE_DIRECT;
+  void* vpair = nullptr;                 // T [rows][ldN] (FP32 / FP64)
+  unsigned short* vpair_split = nullptr; // [rows][2 ldh] (16-bit split modes)
+  float* vpair_unscale = nullptr;        // [rows]
+  PairTab* pair_tab = nullptr;           // device [2]
+  int pair_ntiles[2] = {0, 0};
+  int pair_ntg = 0;
+  long pair_vrow0[2] = {0, 0};
   int ex_gs = 0;         // exchange tile-order group size (0: built-in default; set by the autotuner)
   bool capturing = false;  // inside a graph capture: no phase-timing events
   std::vector<void*> allocs;
@@ -212,6 +221,30 @@ struct StepIO {
   long fstep = 0, estep = 0;
 };
 
+// Exchange partials of one spin into h->part with the handle's algorithm and
+// precision (theta, and its split rows in the split modes, already built).
+hipError_t launch_exchange_spin(afqmc_ham* h, int nw, int sp, int* ntg, hipStream_t s, int gs) {
+  const StepDims& d = h->d;
+  if (h->ex_algo == AFQMC_EXCHANGE_PAIR) {
+    const PairLaunch pl{h->pair_tab + sp, h->pair_ntiles[sp], h->pair_ntg, h->pair_vrow0[sp]};
+    *ntg = h->pair_ntg;
+    if (h->split != SPLIT_NONE)
+      return launch_exchange_pair_split(h->split, d, nw, pl, h->vpair_split, h->vpair_unscale, h->th_split,
+                                        h->th_unscale, (const float*)h->theta, h->part, sp, s, gs);
+    if (h->prec != AFQMC_FP64)
+      return launch_exchange_pair<float>(d, nw, pl, (const float*)h->vpair, (const float*)h->theta, h->part, sp,
+                                         s, gs);
+    return launch_exchange_pair<double>(d, nw, pl, (const double*)h->vpair, (const double*)h->theta, h->part,
+                                        sp, s, gs);
+  }
+  if (h->split != SPLIT_NONE)
+    return launch_exchange_split(h->split, d, nw, h->lh_split, h->lh_unscale, h->th_split, h->th_unscale,
+                                 h->part, sp, ntg, s, gs);
+  if (h->prec != AFQMC_FP64)
+    return launch_exchange<float>(d, nw, (const float*)h->Lh, (const float*)h->theta, h->part, sp, ntg, s, gs);
+  return launch_exchange<double>(d, nw, (const double*)h->Lh, (const double*)h->theta, h->part, sp, ntg, s, gs);
+}
+
 template <typename T>
 int seq_energy_from_theta(afqmc_ham* h, int nw, double2* e_out, hipStream_t s,
                           const int* ctr = nullptr, long estep = 0) {
@@ -221,16 +254,8 @@ int seq_energy_from_theta(afqmc_ham* h, int nw, double2* e_out, hipStream_t s,
     PHASE(h, AFQMC_PH_SPLIT, s,
           launch_split_rows_mode(h->split, (long)nw * 4 * d.nmax, d.N, (const float*)h->theta, d.ldN,
                                  h->th_split, d.ldh, h->th_unscale, s));
-    for (int sp = 0; sp < 2; ++sp)
-      PHASE(h, AFQMC_PH_EXCHANGE, s,
-            launch_exchange_split(h->split, d, nw, h->lh_split, h->lh_unscale, h->th_split,
-                                  h->th_unscale, h->part, sp, &ntg, s, h->ex_gs));
-  } else {
-    for (int sp = 0; sp < 2; ++sp)
-      PHASE(h, AFQMC_PH_EXCHANGE, s,
-            (launch_exchange<T>(h->d, nw, (const T*)h->Lh, (const T*)h->theta, h->part, sp, &ntg, s,
-                                h->ex_gs)));
   }
+  for (int sp = 0; sp < 2; ++sp) PHASE(h, AFQMC_PH_EXCHANGE, s, launch_exchange_spin(h, nw, sp, &ntg, s, h->ex_gs));
   PHASE(h, AFQMC_PH_ENERGY, s,
         launch_energy(h->d, nw, h->e1, h->vbias, h->part, ntg, e_out, ctr, estep, s));
   return AFQMC_OK;
@@ -423,6 +448,98 @@ int trial_energy_fp64(afqmc_ham* h, const double* Y_a, const double* Y_b, hipStr
   return AFQMC_OK;
 }
 
+// Bytes of the pair integrals (both spins, or one when they are shared) and
+// of the largest temporary of their construction.
+void pair_bytes(const afqmc_ham* h, bool shared, double* keep, double* temp) {
+  const StepDims& d = h->d;
+  const double Np = (d.N + 3) & ~3;
+  double rows = 0.0, rmax = 0.0, cmax = 0.0;
+  for (int sp = 0; sp < (shared ? 1 : 2); ++sp) {
+    const double n = sp ? d.nb : d.na;
+    const double r = Np * n * (n + 1) / 2;
+    rows += r;
+    rmax = r > rmax ? r : rmax;
+    const double c = (double)d.N * n * d.N * n * 8.0;
+    cmax = c > cmax ? c : cmax;
+  }
+  const double per = h->split != SPLIT_NONE ? 2.0 * d.ldh * 2 + 4 : (double)d.ldN * h->tsize;
+  *keep = rows * per;
+  *temp = cmax + (h->split != SPLIT_NONE ? rmax * d.ldN * 4.0 : 0.0);
+}
+
+// Pair integrals V_ij = sum_g Lh_g[i] (x) Lh_g[j] of each spin (i <= j,
+// rows (i, j, p) over q, i < j blocks doubled), in the working format of the
+// exchange kernels, and the row-tile tables of both spins.  Y_s: FP64
+// half-rotated vectors [K][N][n_s].  shared: the beta pair integrals are the
+// alpha ones (same trial orbitals).
+int build_pair_integrals(afqmc_ham* h, const double* Y_a, const double* Y_b, bool shared, hipStream_t s) {
+  const StepDims& d = h->d;
+  const int N = d.N, Np = (N + 3) & ~3;
+  const int BM = h->split != SPLIT_NONE ? exchange_pair_split_rows()
+                                        : (h->prec == AFQMC_FP64 ? exchange_pair_rows<double>()
+                                                                 : exchange_pair_rows<float>());
+  PairTab tabs[2];
+  memset(tabs, 0, sizeof tabs);
+  long rows[2] = {0, 0};
+  for (int sp = 0; sp < 2; ++sp) {
+    const int n = sp ? d.nb : d.na;
+    int st = 0, vb = 0;
+    for (int i = 0; i < n; ++i) {
+      tabs[sp].start[i] = st;
+      tabs[sp].vbase[i] = vb;
+      st += ceil_div((n - i) * Np, BM);
+      vb += (n - i) * Np;
+    }
+    tabs[sp].start[n] = st;
+    tabs[sp].vbase[n] = vb;
+    h->pair_ntiles[sp] = st;
+    rows[sp] = vb;
+  }
+  h->pair_ntg = h->pair_ntiles[0] > h->pair_ntiles[1] ? h->pair_ntiles[0] : h->pair_ntiles[1];
+  h->pair_vrow0[0] = 0;
+  h->pair_vrow0[1] = shared ? 0 : rows[0];
+  const long total = shared ? rows[0] : rows[0] + rows[1];
+  int rc;
+  if ((rc = dalloc_t(h, &h->pair_tab, (size_t)2))) return rc;
+  HIP_TRY(hipMemcpy(h->pair_tab, tabs, sizeof tabs, hipMemcpyHostToDevice));
+  if (h->split != SPLIT_NONE) {
+    if ((rc = dalloc_t(h, &h->vpair_split, (size_t)total * 2 * d.ldh))) return rc;
+    if ((rc = dalloc_t(h, &h->vpair_unscale, (size_t)total))) return rc;
+  } else {
+    if ((rc = dalloc(h, &h->vpair, (size_t)total * d.ldN * h->tsize))) return rc;
+  }
+  double* C = nullptr;
+  float* tmp = nullptr;
+  const int nmx = shared ? d.na : d.nmax;
+  HIP_TRY(hipMalloc(&C, (size_t)N * nmx * N * nmx * sizeof(double)));
+  if (h->split != SPLIT_NONE) {
+    const long rmax = rows[0] > rows[1] ? rows[0] : rows[1];
+    HIP_TRY(hipMalloc(&tmp, (size_t)rmax * d.ldN * sizeof(float)));
+  }
+  for (int sp = 0; sp < (shared ? 1 : 2); ++sp) {
+    const int n = sp ? d.nb : d.na;
+    if (n == 0) continue;
+    const double* Y = sp ? Y_b : Y_a;
+    const int M = N * n;
+    // C[p n + i][q n + j] = sum_g Y[g][p][i] Y[g][q][j]
+    HIP_TRY(setup_gemm(M, M, d.K, 1, Y, M, Y, M, C, M, nullptr, 1, s));
+    const long r0 = h->pair_vrow0[sp];
+    if (h->split != SPLIT_NONE) {
+      HIP_TRY(setup_pack_vpair<float>(N, n, Np, d.ldN, rows[sp], C, tmp, s));
+      HIP_TRY(launch_split_rows_mode(h->split, rows[sp], N, tmp, d.ldN, h->vpair_split + (size_t)r0 * 2 * d.ldh,
+                                     d.ldh, h->vpair_unscale + r0, s));
+    } else if (h->prec != AFQMC_FP64) {
+      HIP_TRY(setup_pack_vpair<float>(N, n, Np, d.ldN, rows[sp], C, (float*)h->vpair + (size_t)r0 * d.ldN, s));
+    } else {
+      HIP_TRY(setup_pack_vpair<double>(N, n, Np, d.ldN, rows[sp], C, (double*)h->vpair + (size_t)r0 * d.ldN, s));
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  (void)hipFree(C);
+  if (tmp) (void)hipFree(tmp);
+  return AFQMC_OK;
+}
+
 int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, const double* host_pa,
               const double* host_pb, hipStream_t s) {
   const afqmc_params& p = h->prm;
@@ -530,6 +647,23 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
                                    d.ldh, h->lh_unscale, s));
   }
 
+  // ---- exchange algorithm: pair integrals when they pay and fit ----
+  {
+    bool shared = d.na == d.nb;
+    for (size_t e = 0; shared && e < (size_t)N * d.na; ++e) shared = host_pa[e] == host_pb[e];
+    double keep = 0.0, temp = 0.0;
+    pair_bytes(h, shared, &keep, &temp);
+    const bool fits = keep + temp <= 48.0 * (1 << 30);
+    // direct: K n^2 N products per walker and spin; pair: n (n + 1) / 2 N^2
+    const double gain = 2.0 * K * nmax / ((nmax + 1.0) * N);
+    int algo = p.exchange;
+    if (algo == AFQMC_EXCHANGE_AUTO) algo = (gain > 1.5 && fits) ? AFQMC_EXCHANGE_PAIR : AFQMC_EXCHANGE_DIRECT;
+    if (algo == AFQMC_EXCHANGE_PAIR && !fits)
+      return fail(AFQMC_ENOMEM, "pair integrals need %.1f GB (+%.1f GB during setup)", keep / 1e9, temp / 1e9);
+    h->ex_algo = algo;
+    if (algo == AFQMC_EXCHANGE_PAIR && (rc = build_pair_integrals(h, Y_a, Y_b, shared, s))) return rc;
+  }
+
   // ---- workspace ----
   const size_t W = (size_t)p.max_walkers;
   // the FP64 trial-energy pass may use the FP64 tile even in the mixed path
@@ -538,6 +672,7 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
   int gmin = t32.G < t64.G ? t32.G : t64.G;
   if (tsp.G < gmin) gmin = tsp.G;
   h->ntg = ceil_div(K, gmin);
+  if (h->pair_ntg > h->ntg) h->ntg = h->pair_ntg;
   const size_t ts = h->tsize;
   const size_t wtheta = (W > 1 ? W : 1);
   if ((rc = dalloc(h, &h->theta, wtheta * 4 * nmax * d.ldN * ts))) return rc;
@@ -644,6 +779,8 @@ int afqmc_init_hamiltonian(const afqmc_params* params, const double* host_h1,
   if (p.precision < AFQMC_FP64 || p.precision > AFQMC_FP16X3)
     return fail(AFQMC_EINVAL, "unknown precision %d", p.precision);
   if (p.max_walkers < 1) return fail(AFQMC_EINVAL, "max_walkers must be >= 1");
+  if (p.exchange < AFQMC_EXCHANGE_AUTO || p.exchange > AFQMC_EXCHANGE_PAIR)
+    return fail(AFQMC_EINVAL, "unknown exchange algorithm %d", p.exchange);
   const int nmax = p.na > p.nb ? p.na : p.nb;
   if (qr_lds_bytes_for(p.N, nmax) > 160 * 1024)
     return fail(AFQMC_EUNSUPPORTED, "N * max(na, nb) too large for the in-LDS QR (N=%d, n=%d)", p.N, nmax);
@@ -858,6 +995,12 @@ int afqmc_get_status(afqmc_ham* h, void* stream, int* out) {
   return AFQMC_OK;
 }
 
+int afqmc_get_exchange_algorithm(afqmc_ham* h, int* out) {
+  if (!h || !out) return fail(AFQMC_EINVAL, "null argument");
+  *out = h->ex_algo;
+  return AFQMC_OK;
+}
+
 int afqmc_get_setup(afqmc_ham* h, double* host_P, double* mu, double* e_shift) {
   if (!h) return fail(AFQMC_EINVAL, "null Hamiltonian handle");
   int rc;
@@ -1042,7 +1185,7 @@ std::string tune_key(const afqmc_ham* h, int nw) {
   if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) dev = prop.gcnArchName;
   std::ostringstream k;
   k << "exchange_gs:" << dev << ":N" << h->d.N << ":na" << h->d.na << ":nb" << h->d.nb << ":K"
-    << h->d.K << ":W" << nw << ":p" << h->prec;
+    << h->d.K << ":W" << nw << ":p" << h->prec << ":x" << h->ex_algo;
   return k.str();
 }
 
@@ -1175,19 +1318,7 @@ int afqmc_autotune(afqmc_batch* b, const char* cache_path) {
       for (int rep = 0; rep < 3; ++rep) {
         HIP_TRY(hipEventRecord(t0, s));
         int ntg = 0;
-        for (int sp = 0; sp < 2; ++sp) {
-          hipError_t he;
-          if (h->split != SPLIT_NONE)
-            he = launch_exchange_split(h->split, h->d, b->nw[i], h->lh_split, h->lh_unscale,
-                                       h->th_split, h->th_unscale, h->part, sp, &ntg, s, gs);
-          else if (h->prec != AFQMC_FP64)
-            he = launch_exchange<float>(h->d, b->nw[i], (const float*)h->Lh, (const float*)h->theta,
-                                        h->part, sp, &ntg, s, gs);
-          else
-            he = launch_exchange<double>(h->d, b->nw[i], (const double*)h->Lh,
-                                         (const double*)h->theta, h->part, sp, &ntg, s, gs);
-          HIP_TRY(he);
-        }
+        for (int sp = 0; sp < 2; ++sp) HIP_TRY(launch_exchange_spin(h, b->nw[i], sp, &ntg, s, gs));
         HIP_TRY(hipEventRecord(t1, s));
         HIP_TRY(hipEventSynchronize(t1));
         float ms = 0.f;

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "exchange_pair.h"
+
 // Sizes shared by every kernel of one Hamiltonian.
 struct StepDims {
   int N;      // spatial orbitals
@@ -143,3 +145,23 @@ template <typename T>
 hipError_t launch_s2(const StepDims& d, int W, const T* theta, const double* phiT, double2* s2, hipStream_t s);
 // out [2 m + 2]: weighted means of the m columns of v [nw][m], ln sum w, live walkers
 hipError_t launch_weighted_mean(int nw, int m, const double* log_w, const double2* v, double* out, hipStream_t s);
+
+// --- exchange through pair integrals (exchange_pair.h) -------------------------
+struct PairLaunch {
+  const PairTab* tab;  // device tables of this spin
+  int ntiles;          // row tiles of this spin
+  int ntg;             // row tiles of the larger spin (stride of the partials)
+  long vrow0;          // first pair-integral row of this spin
+};
+// rows per tile (the tables are built for it)
+int exchange_pair_split_rows();
+template <typename T>
+int exchange_pair_rows();
+// one spin; part[sp][row tile][z] (zeros past this spin's tiles)
+hipError_t launch_exchange_pair_split(int mode, const StepDims& d, int W, const PairLaunch& pl,
+                                      const unsigned short* v, const float* v_unscale, const unsigned short* th,
+                                      const float* th_unscale, const float* theta, double2* part, int sp,
+                                      hipStream_t s, int gs = 0);
+template <typename T>
+hipError_t launch_exchange_pair(const StepDims& d, int W, const PairLaunch& pl, const T* v, const T* theta,
+                                double2* part, int sp, hipStream_t s, int gs = 0);

@@ -22,3 +22,6 @@ hipError_t setup_hh(int N, int n, int nmax, const double* phiT, const double* h1
                     hipStream_t s);
 hipError_t setup_trial_walker(int N, int n, int nmax, const double* phiT, double2* phi,
                               hipStream_t s);
+// rows (i, j >= i, p) over q of the pair integrals of one spin from C = Y^T Y
+template <typename T>
+hipError_t setup_pack_vpair(int N, int n, int Np, int ldq, long rows, const double* C, T* V, hipStream_t s);

@@ -296,3 +296,35 @@ hipError_t setup_trial_walker(int N, int n, int nmax, const double* phiT, double
                      phiT, phi);
   return hipGetLastError();
 }
+
+// Pair integrals of one spin for the exchange through pair integrals: row
+// (i, j >= i, p) of group i (groups in order of i, rows of a group in order
+// of j then p < Np) holds c V_ij[p][q] over q < ldq, with
+// V_ij[p][q] = C[p n + i][q n + j], C = Y^T Y the sum over Cholesky vectors
+// of the half-rotated products (Y [K][N][n]), c = 2 for j > i and 1 for
+// j = i; rows p >= N and columns q >= N are zero.
+template <typename T>
+__global__ __launch_bounds__(256) void pack_vpair_kernel(int N, int n, int Np, int ldq, long rows,
+                                                         const double* __restrict__ C, T* __restrict__ V) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * ldq) return;
+  const long v = e / ldq;
+  const int q = (int)(e - v * ldq);
+  const int blk = (int)(v / Np), p = (int)(v - (long)blk * Np);
+  int i = 0;  // pair blocks before group i: i n - i (i - 1) / 2
+  while (i + 1 < n && (i + 1) * n - (i + 1) * i / 2 <= blk) ++i;
+  const int j = i + (blk - (i * n - i * (i - 1) / 2));
+  double x = 0.0;
+  if (p < N && q < N) x = (j > i ? 2.0 : 1.0) * C[((long)p * n + i) * ((long)N * n) + (long)q * n + j];
+  V[e] = (T)x;
+}
+
+template <typename T>
+hipError_t setup_pack_vpair(int N, int n, int Np, int ldq, long rows, const double* C, T* V, hipStream_t s) {
+  const long tot = rows * ldq;
+  hipLaunchKernelGGL(pack_vpair_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, N, n, Np, ldq,
+                     rows, C, V);
+  return hipGetLastError();
+}
+template hipError_t setup_pack_vpair<float>(int, int, int, int, long, const double*, float*, hipStream_t);
+template hipError_t setup_pack_vpair<double>(int, int, int, int, long, const double*, double*, hipStream_t);

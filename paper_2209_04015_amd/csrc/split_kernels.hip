@@ -10,6 +10,7 @@
 #include "split_tile.h"
 #include "tile_order.h"
 #include "exchange_tri.h"
+#include "exchange_pair.h"
 
 // ---------------------------------------------------------------------------
 // Row splitting: src rows (FP32, stride ld_src, ncols valid) -> split rows of
@@ -190,6 +191,98 @@ hipError_t launch_exchange_split(int mode, const StepDims& d, int W, const unsig
   else
     hipLaunchKernelGGL(exchange_split_kernel<HalfF16>, dim3(8 * per), dim3(C::NT), 0, s, p, part, ntg, nwt,
                        zpp, gs);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Exchange through pair integrals on split operands (exchange_pair.h).  Row
+// tile rt of group i: A = pair-integral split rows (j, p) of group i,
+// B = theta split rows (z, re|im, spin, i) of the tile's 80 walkers,
+// contraction over the orbital q.  Same stage, tile and XCD order as the
+// direct split exchange; the epilogue is the Hadamard product with theta.
+// ---------------------------------------------------------------------------
+struct PairSplitArgs {
+  const unsigned short* v;   // pair-integral split rows of this spin: [rows][2 ldh] halves
+  const float* v_unscale;    // [rows]
+  const unsigned short* th;  // theta split rows: [W][re|im][spin][nmax][2 ldh] halves
+  const float* th_unscale;   // [W][re|im][spin][nmax]
+  const float* theta;        // FP32 planar theta [W][re|im][spin][nmax][ldN]
+  const PairTab* tab;        // this spin's row-tile tables
+  int W, n, Np, nmax, ldN, rowb, sp, nkb, ntiles;
+};
+
+template <class H>
+__global__ __launch_bounds__(ExSplitCfg::NT, ExSplitCfg::WAVES_PER_EU) void exchange_pair_split_kernel(
+    PairSplitArgs p, double2* __restrict__ part, int ntg, int nwt, int gs) {
+  using C = ExSplitCfg;
+  int rt, wt;
+  if (!xcd_tile(blockIdx.x, ntg, nwt, gs, rt, wt)) return;
+  const int z0 = wt * (C::BN / 2);
+  double2* out = part + ((size_t)p.sp * ntg + rt) * p.W;
+  if (rt >= p.ntiles) {
+    exchange_pair_zero<C::BN>(z0, p.W, out);
+    return;
+  }
+  __shared__ __attribute__((aligned(16))) char exs_lds[EXS_LDS_BYTES];
+  const int tid = threadIdx.x;
+  const int schunk = tid & 7, srow = tid >> 3;
+  const int i = pair_group(p.tab, p.n, rt);
+  const int lr0 = (rt - p.tab->start[i]) * C::BM;
+  const int R = (p.n - i) * p.Np;
+  const int vb = p.tab->vbase[i];
+  const int nr = min(C::BM, R - lr0);
+  const int nz = min(C::BN / 2, p.W - z0);
+  // buffers from the tile's first pair-integral row and first walker
+  const __amdgpu_buffer_rsrc_t a_rsrc = split_rsrc(p.v + (size_t)(vb + lr0) * (p.rowb / 2), nr * p.rowb);
+  const __amdgpu_buffer_rsrc_t b_rsrc =
+      split_rsrc(p.th + (size_t)z0 * 4 * p.nmax * (p.rowb / 2), nz * 4 * p.nmax * p.rowb);
+  int a_off[C::NA], b_off[C::NB];
+#pragma unroll
+  for (int t = 0; t < C::NA; ++t) {
+    const int r = srow + t * (C::NT / 8);
+    a_off[t] = r < nr ? r * p.rowb + schunk * 16 : SPLIT_ROW_NONE;
+  }
+#pragma unroll
+  for (int t = 0; t < C::NB; ++t) {
+    const int c = srow + t * (C::NT / 8);
+    const int zt = c >> 1, comp = c & 1;
+    b_off[t] = zt < nz ? (((zt * 2 + comp) * 2 + p.sp) * p.nmax + i) * p.rowb + schunk * 16 : SPLIT_ROW_NONE;
+  }
+  floatx4 acc[C::BM / C::WM / 16][C::BN / C::WN / 16];
+  split_tile_mainloop<H, C::BM, C::BN, C::WM, C::WN>(a_rsrc, b_rsrc, a_off, b_off, p.nkb, acc,
+                                                    reinterpret_cast<unsigned short*>(exs_lds));
+  exchange_pair_epilogue<C::BM, C::BN, C::WM, C::WN, H::SCALED>(acc, exs_lds, i, lr0, R, p.Np, vb, z0, p.W, p.sp,
+                                                                p.nmax, p.ldN, p.theta, p.v_unscale, p.th_unscale,
+                                                                out);
+}
+
+int exchange_pair_split_rows() { return ExSplitCfg::BM; }
+
+hipError_t launch_exchange_pair_split(int mode, const StepDims& d, int W, const PairLaunch& pl,
+                                      const unsigned short* v, const float* v_unscale, const unsigned short* th,
+                                      const float* th_unscale, const float* theta, double2* part, int sp,
+                                      hipStream_t s, int gs) {
+  using C = ExSplitCfg;
+  if (gs < 1) gs = C::GS;
+  const int n = sp == 0 ? d.na : d.nb;
+  if (W == 0 || pl.ntg == 0) return hipSuccess;
+  if (d.ldh % 32 != 0 || n > PAIR_MAX_N) return hipErrorInvalidValue;
+  const int rowb = 2 * d.ldh * 2;
+  const int Np = (d.N + 3) & ~3;
+  // per-tile buffers below 2^31 bytes
+  if ((double)C::BM * rowb >= (double)SPLIT_ROW_NONE ||
+      (double)(C::BN / 2) * 4 * d.nmax * rowb >= (double)SPLIT_ROW_NONE)
+    return hipErrorInvalidValue;
+  const int nwt = ceil_div(2 * W, C::BN);
+  PairSplitArgs p{v + (size_t)pl.vrow0 * 2 * d.ldh, v_unscale + pl.vrow0, th, th_unscale, theta, pl.tab,
+                  W, n, Np, d.nmax, d.ldN, rowb, sp, d.ldh / 32, n > 0 ? pl.ntiles : 0};
+  const int per = ceil_div(pl.ntg * nwt, 8);
+  if (mode == SPLIT_BF16)
+    hipLaunchKernelGGL(exchange_pair_split_kernel<HalfBF16>, dim3(8 * per), dim3(C::NT), 0, s, p, part, pl.ntg,
+                       nwt, gs);
+  else
+    hipLaunchKernelGGL(exchange_pair_split_kernel<HalfF16>, dim3(8 * per), dim3(C::NT), 0, s, p, part, pl.ntg,
+                       nwt, gs);
   return hipGetLastError();
 }
 

@@ -813,6 +813,93 @@ template hipError_t launch_exchange<double>(const StepDims&, int, const double*,
                                             double2*, int, int*, hipStream_t, int);
 
 // ===========================================================================
+// Exchange through pair integrals (exchange_pair.h), FP32 / FP64 matrix
+// cores: row tile rt of group i, A = pair-integral rows (j, p) of group i
+// ([rows][ldN], working precision), B = theta rows (z, re|im, spin, i) of
+// the tile's 80 walkers.  Tile shapes and XCD order as the direct exchange.
+// ===========================================================================
+
+template <typename T>
+struct PairProb {
+  using vec_t = typename MF<T>::vec_t;
+  const T* V;      // this tile's first pair-integral row
+  const T* theta;
+  int W, nmax, ldN, sp, i, nr, z0;
+  __device__ vec_t load_a(int, int r, int k) const {
+    if (r >= nr) return MF<T>::vzero();
+    return *reinterpret_cast<const vec_t*>(V + (size_t)r * ldN + k);
+  }
+  __device__ vec_t load_b(int, int c, int k) const {
+    const int z = z0 + (c >> 1);
+    if (z >= W) return MF<T>::vzero();
+    return *reinterpret_cast<const vec_t*>(theta + (((size_t)z * 2 + (c & 1)) * 2 + sp) * (size_t)nmax * ldN +
+                                           (size_t)i * ldN + k);
+  }
+};
+
+template <typename T>
+static size_t pair_lds_bytes() {
+  using C = ExCfg<T>;
+  const size_t stage = (C::DBUF ? 2 : 1) * (size_t)TileLds<T, C::BM, C::BN, C::BK>::BYTES;
+  const size_t red = (size_t)4 * C::WM * C::BN * sizeof(double2);
+  return stage > red ? stage : red;
+}
+
+template <typename T>
+__global__ __launch_bounds__(ExCfg<T>::WM* ExCfg<T>::WN * 64, ExCfg<T>::WAVES_PER_EU) void exchange_pair_kernel(
+    const T* __restrict__ V, const T* __restrict__ theta, const PairTab* __restrict__ tab, int n, int Np, int W,
+    int nmax, int ldN, int sp, int ntiles, double2* __restrict__ part, int ntg, int nwt, int gs) {
+  using C = ExCfg<T>;
+  constexpr int BM = C::BM, BN = C::BN, BK = C::BK, WM = C::WM, WN = C::WN;
+  int rt, wt;
+  if (!xcd_tile(blockIdx.x, ntg, nwt, gs, rt, wt)) return;
+  const int z0 = wt * (BN / 2);
+  double2* out = part + ((size_t)sp * ntg + rt) * W;
+  if (rt >= ntiles) {
+    exchange_pair_zero<BN>(z0, W, out);
+    return;
+  }
+  extern __shared__ double2 ex_lds_raw[];
+  const int i = pair_group(tab, n, rt);
+  const int lr0 = (rt - tab->start[i]) * BM;
+  const int R = (n - i) * Np;
+  const int vb = tab->vbase[i];
+  const PairProb<T> p{V + (size_t)(vb + lr0) * ldN, theta, W, nmax, ldN, sp, i, min(BM, R - lr0), z0};
+  typename MF<T>::acc_t acc[BM / WM / 16][BN / WN / 16];
+  mfma_tile_mainloop<T, BM, BN, BK, WM, WN, false, PairProb<T>, C::PIPE>(p, 0, 0, 0, ldN, acc,
+                                                                         reinterpret_cast<T*>(ex_lds_raw));
+  exchange_pair_epilogue<BM, BN, WM, WN, false>(acc, reinterpret_cast<char*>(ex_lds_raw), i, lr0, R, Np, vb, z0,
+                                                W, sp, nmax, ldN, theta, nullptr, nullptr, out);
+}
+
+template <typename T>
+int exchange_pair_rows() {
+  return ExCfg<T>::BM;
+}
+template int exchange_pair_rows<float>();
+template int exchange_pair_rows<double>();
+
+template <typename T>
+hipError_t launch_exchange_pair(const StepDims& d, int W, const PairLaunch& pl, const T* v, const T* theta,
+                                double2* part, int sp, hipStream_t s, int gs) {
+  using C = ExCfg<T>;
+  const int n = sp == 0 ? d.na : d.nb;
+  if (W == 0 || pl.ntg == 0) return hipSuccess;
+  if (n > PAIR_MAX_N) return hipErrorInvalidValue;
+  const int nwt = ceil_div(2 * W, C::BN);
+  const int per = ceil_div(pl.ntg * nwt, 8);
+  if (gs < 1) gs = C::GS;
+  hipLaunchKernelGGL(exchange_pair_kernel<T>, dim3(8 * per), dim3(C::WM * C::WN * 64), pair_lds_bytes<T>(), s,
+                     v + (size_t)pl.vrow0 * d.ldN, theta, pl.tab, n, (d.N + 3) & ~3, W, d.nmax, d.ldN, sp,
+                     n > 0 ? pl.ntiles : 0, part, pl.ntg, nwt, gs);
+  return hipGetLastError();
+}
+template hipError_t launch_exchange_pair<float>(const StepDims&, int, const PairLaunch&, const float*, const float*,
+                                                double2*, int, hipStream_t, int);
+template hipError_t launch_exchange_pair<double>(const StepDims&, int, const PairLaunch&, const double*,
+                                                 const double*, double2*, int, hipStream_t, int);
+
+// ===========================================================================
 // Energy assembly (R10 of the design): E1 from the Green's function pass,
 // EJ = 1/2 sum_g vbias_g^2, EK = -1/2 sum of the exchange partials.
 // ===========================================================================
@@ -1036,6 +1123,12 @@ hipError_t set_kernel_attributes(const StepDims& d) {
                           hipFuncAttributeMaxDynamicSharedMemorySize, big);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(exchange_kernel<double>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(exchange_pair_kernel<float>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(exchange_pair_kernel<double>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, big);
   (void)d;
   return e;

@@ -42,9 +42,11 @@ def test_version_and_error_string(lib):
 
 
 def test_param_struct_layout_matches_header():
-    # int N, na, nb, K; double dt; int taylor_order, precision, max_walkers; double mu, e_shift
-    assert ctypes.sizeof(afqmc._Params) == 56
+    # int N, na, nb, K; double dt; int taylor_order, precision, max_walkers; double mu, e_shift;
+    # int exchange
+    assert ctypes.sizeof(afqmc._Params) == 64
     assert afqmc._Params.mu.offset == 40
+    assert afqmc._Params.exchange.offset == 56
     assert ctypes.sizeof(afqmc._Walkers) == 32
 
 

@@ -53,7 +53,7 @@ def _walkers(phiT_a, phiT_b, W, seed=0, scale=0.3):
 
 
 class Case:
-    def __init__(self, cfg, precision, uhf=False, seed=0):
+    def __init__(self, cfg, precision, uhf=False, seed=0, exchange="auto"):
         from paper_2209_04015_amd import afqmc
 
         torch = _torch()
@@ -62,7 +62,7 @@ class Case:
         self.h1, self.L, self.pa_T, self.pb_T = _system(cfg, seed=seed, uhf=uhf)
         self.oh = orc.setup(self.h1, self.L, self.pa_T, self.pb_T, dt=cfg.dt)
         self.ham = afqmc.Hamiltonian(self.h1, self.L, self.pa_T, self.pb_T, dt=cfg.dt,
-                                     max_walkers=cfg.W, precision=precision)
+                                     max_walkers=cfg.W, precision=precision, exchange=exchange)
         self.pa, self.pb = _walkers(self.pa_T, self.pb_T, cfg.W, seed=seed)
         self.lo = orc.overlap(self.oh, self.pa, self.pb)
         self.lw = np.linspace(-0.3, 0.2, cfg.W)
@@ -80,12 +80,12 @@ class Case:
 _CASES = {}
 
 
-def case(name, precision, uhf=False):
-    key = (name, precision, uhf)
+def case(name, precision, uhf=False, exchange="auto"):
+    key = (name, precision, uhf, exchange)
     if key not in _CASES:
         cfg = RAGGED if name == "ragged" else inputs.CONFIGS[name]
         print(f"[gpu] building case {key}", flush=True)
-        _CASES[key] = Case(cfg, precision, uhf=uhf)
+        _CASES[key] = Case(cfg, precision, uhf=uhf, exchange=exchange)
     return _CASES[key]
 
 
@@ -147,16 +147,27 @@ def test_force_bias_matches_oracle(name, precision, uhf):
     assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
 
 
+EXCHANGES = ["auto", "direct"]   # auto resolves to the pair integrals at these sizes
+
+
+def test_auto_exchange_uses_pair_integrals_here():
+    for name in ("n20", "ragged"):
+        assert case(name, "fp64").ham.exchange == "pair"
+        assert case(name, "fp64", exchange="direct").ham.exchange == "direct"
+
+
+@pytest.mark.parametrize("exchange", EXCHANGES)
 @pytest.mark.parametrize("name,precision,uhf", PARAMS + SPLIT_PARAMS)
-def test_local_energy_matches_oracle(name, precision, uhf):
-    c = case(name, precision, uhf)
+def test_local_energy_matches_oracle(name, precision, uhf, exchange):
+    c = case(name, precision, uhf, exchange)
     w = c.walkers()
     got = c.ham.local_energy(w).cpu().numpy()
     ref = orc.local_energy(c.oh, c.pa, c.pb)
     S = np.abs(ref).sum(axis=1)
     err = np.abs(got.sum(axis=1) - ref.sum(axis=1))
     tol = _energy_tol(precision, c.cfg)
-    print(f"[gpu] {name} {precision} uhf={uhf}: max |dE|/S = {(err / S).max():.3e} (bar {tol:.1e})", flush=True)
+    print(f"[gpu] {name} {precision} uhf={uhf} {c.ham.exchange}: max |dE|/S = {(err / S).max():.3e} "
+          f"(bar {tol:.1e})", flush=True)
     assert np.all(err <= tol * S)
     for k in range(3):   # each part to the same scale
         assert np.all(np.abs(got[:, k] - ref[:, k]) <= tol * S)
@@ -195,15 +206,16 @@ def test_orthogonalise_matches_oracle(name, precision, uhf):
     assert np.abs(w.log_ovlp.cpu().numpy() - lo).max() < 1e-11
 
 
+@pytest.mark.parametrize("exchange", EXCHANGES)
 @pytest.mark.parametrize("name,precision,uhf", PARAMS + SPLIT_PARAMS)
-def test_fused_step_matches_oracle(name, precision, uhf):
+def test_fused_step_matches_oracle(name, precision, uhf, exchange):
     """afqmc_step (propagate, QR, energy) against the oracle's step, teacher-forced
     on every step.  In FP64 the second call continues from the GPU state and
     reuses its cached Green's function; in the mixed modes both calls start
     from the oracle state, since the cache holds the GPU's own (FP32-rounded)
     walker."""
     torch = _torch()
-    c = case(name, precision, uhf)
+    c = case(name, precision, uhf, exchange)
     w = c.walkers()
     xs = inputs.fields(c.cfg.W, c.cfg.K, 2, seed=5)
     pa, pb, lo, lw = c.pa, c.pb, c.lo, c.lw
