@@ -281,6 +281,8 @@ def main():
     ap.add_argument("--only", choices=MODES, help="run one path only (profiling runs)")
     ap.add_argument("--headline", choices=MODES[1:], default="fp16x3",
                     help="mixed path reported as value (the others are on the same line)")
+    ap.add_argument("--exchange", choices=("auto", "direct", "pair"), default="auto",
+                    help="exchange algorithm of the main paths (profiling runs)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -321,7 +323,7 @@ def main():
         if args.only and precision != args.only:
             continue
         ham, w, e, ms, phases, status, extra = run_gpu(cfg, h1, L, phiT, precision, args.steps, args.warmup,
-                                                       fields_dev, block_fields_dev, device)
+                                                       fields_dev, block_fields_dev, device, exchange=args.exchange)
         results[precision] = (ms, phases, status)
         extras[precision] = extra
         # energies of sampled walkers from this path's own final states

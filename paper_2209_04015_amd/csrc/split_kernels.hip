@@ -293,6 +293,12 @@ hipError_t launch_exchange_pair_split(int mode, const StepDims& d, int W, const 
 // B = packed L split rows (N (N + 1) / 2), contraction over the Cholesky
 // index.
 // ---------------------------------------------------------------------------
+// k blocks of loads in flight in the VHS main loop (a contraction over all
+// Cholesky vectors: about 90 k blocks at n290, operands beyond the L2)
+#ifndef VHS_PREFETCH
+#define VHS_PREFETCH 1
+#endif
+
 struct VhsSplitArgs {
   const unsigned short* a;  // xs split rows [2 W][2 ldhK]
   const float* a_unscale;   // [2 W]
@@ -327,7 +333,7 @@ __global__ __launch_bounds__(ExSplitCfg::NT, ExSplitCfg::WAVES_PER_EU) void vhs_
 #pragma unroll
   for (int t = 0; t < C::NB; ++t) b_off[t] = ((tid >> 3) + t * (C::NT / 8)) * p.rowb + (tid & 7) * 16;
   floatx4 acc[FM][FN];
-  split_tile_mainloop<H, C::BM, C::BN, C::WM, C::WN>(a_rsrc, b_rsrc, a_off, b_off, p.nkb, acc, vs_lds);
+  split_tile_mainloop<H, C::BM, C::BN, C::WM, C::WN, VHS_PREFETCH>(a_rsrc, b_rsrc, a_off, b_off, p.nkb, acc, vs_lds);
   // rows m = 2 z + (re|im): each lane's 4 consecutive rows are 2 whole walkers
   float wmax[FM][2];
 #pragma unroll

@@ -89,15 +89,17 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t split_rsrc(const void* base, i
 }
 
 // Main loop of C[BM x BN] = A B^T with split operands, one k block (32
-// contraction indices) per stage, the next block prefetched into registers
-// while the matrix cores work on the current one.
+// contraction indices) per stage, the next DEPTH blocks prefetched into
+// registers while the matrix cores work on the current one (DEPTH 2 keeps
+// two blocks of loads in flight, for long contractions whose loads come
+// from beyond the L2).
 //   a_rsrc / b_rsrc: buffer resources over the operand rows;
 //   a_off[t] / b_off[t]: byte offset of the 16-byte chunk this thread stages
 //   in slot t for the first k block, or SPLIT_ROW_NONE for rows outside the
 //   problem (the bounds check stages zeros).  k block kb lies kb * 128 bytes
 //   further (scalar offset).
 // Thread tid stages chunk tid % 8 of rows tid / 8 + 32 t.
-template <class H, int BM, int BN, int WM, int WN>
+template <class H, int BM, int BN, int WM, int WN, int DEPTH = 1>
 __device__ __forceinline__ void split_tile_mainloop(__amdgpu_buffer_rsrc_t a_rsrc, __amdgpu_buffer_rsrc_t b_rsrc,
                                                     const int (&a_off)[BM * 8 / (WM * WN * 64)],
                                                     const int (&b_off)[BN * 8 / (WM * WN * 64)],
@@ -125,24 +127,28 @@ __device__ __forceinline__ void split_tile_mainloop(__amdgpu_buffer_rsrc_t a_rsr
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  uint4 ra[NA], rb[NB];
-  auto fetch = [&](int kb) {
+  uint4 ra[DEPTH][NA], rb[DEPTH][NB];
+  // k block kb into register set s (a block past the last one reads rows of
+  // the same buffers or, past their end, zeros: never staged)
+  auto fetch = [&](int s, int kb) {
     const int o = kb * (SPLIT_KB * 2);
 #pragma unroll
     for (int t = 0; t < NA; ++t)
-      ra[t] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(a_rsrc, a_off[t], o, 0));
+      ra[s][t] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(a_rsrc, a_off[t], o, 0));
 #pragma unroll
     for (int t = 0; t < NB; ++t)
-      rb[t] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(b_rsrc, b_off[t], o, 0));
+      rb[s][t] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(b_rsrc, b_off[t], o, 0));
   };
-  auto stash = [&]() {
+  auto stash = [&](int s) {
 #pragma unroll
     for (int t = 0; t < NA; ++t)
-      *reinterpret_cast<uint4*>(lds + (srow + t * (NT / 8)) * SPLIT_SLD + schunk * 8) = ra[t];
+      *reinterpret_cast<uint4*>(lds + (srow + t * (NT / 8)) * SPLIT_SLD + schunk * 8) = ra[s][t];
 #pragma unroll
     for (int t = 0; t < NB; ++t)
-      *reinterpret_cast<uint4*>(lds + (BM + srow + t * (NT / 8)) * SPLIT_SLD + schunk * 8) = rb[t];
+      *reinterpret_cast<uint4*>(lds + (BM + srow + t * (NT / 8)) * SPLIT_SLD + schunk * 8) = rb[s][t];
   };
+  // The B fragments of column block j + 1 are read before the matrix-core
+  // work of block j is issued, so their LDS latency is covered by it.
   auto compute = [&]() {
     vec8 ah[FM], al[FM];
 #pragma unroll
@@ -151,26 +157,53 @@ __device__ __forceinline__ void split_tile_mainloop(__amdgpu_buffer_rsrc_t a_rsr
       ah[i] = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r));
       al[i] = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r + 32));
     }
+    auto bfrag = [&](int j, vec8& bh, vec8& bl) {
+      const unsigned short* r = lds + (BM + wn * (BN / WN) + j * 16 + lrow) * SPLIT_SLD + lk;
+      bh = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r));
+      bl = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r + 32));
+    };
+    vec8 bh[2], bl[2];
+    bfrag(0, bh[0], bl[0]);
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-      const unsigned short* r = lds + (BM + wn * (BN / WN) + j * 16 + lrow) * SPLIT_SLD + lk;
-      const vec8 bh = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r));
-      const vec8 bl = __builtin_bit_cast(vec8, *reinterpret_cast<const uint4*>(r + 32));
+      if (j + 1 < FN) bfrag(j + 1, bh[(j + 1) & 1], bl[(j + 1) & 1]);
+      __builtin_amdgcn_sched_barrier(0);  // keep those reads ahead of this block's MFMAs
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
-        acc[i][j] = H::mma(al[i], bh, acc[i][j]);
-        acc[i][j] = H::mma(ah[i], bl, acc[i][j]);
-        acc[i][j] = H::mma(ah[i], bh, acc[i][j]);
+        acc[i][j] = H::mma(al[i], bh[j & 1], acc[i][j]);
+        acc[i][j] = H::mma(ah[i], bl[j & 1], acc[i][j]);
+        acc[i][j] = H::mma(ah[i], bh[j & 1], acc[i][j]);
       }
     }
   };
 
-  fetch(0);
-  for (int kb = 0; kb < nkb; ++kb) {
-    if (kb) __syncthreads();  // every wave is done with the previous stage
-    stash();
-    __syncthreads();
-    if (kb + 1 < nkb) fetch(kb + 1);
-    compute();
+  if constexpr (DEPTH == 1) {
+    fetch(0, 0);
+    for (int kb = 0; kb < nkb; ++kb) {
+      if (kb) __syncthreads();  // every wave is done with the previous stage
+      stash(0);
+      __syncthreads();
+      if (kb + 1 < nkb) fetch(0, kb + 1);
+      compute();
+    }
+  } else {
+    static_assert(DEPTH == 2, "prefetch depth 1 or 2");
+    // straight-line pairs of blocks with unconditional fetches, so that the
+    // wait before each stash leaves the other set's loads in flight
+    fetch(0, 0);
+    fetch(1, 1);
+    for (int kb = 0; kb < nkb; kb += 2) {
+      if (kb) __syncthreads();
+      stash(0);
+      __syncthreads();
+      fetch(0, kb + 2);
+      compute();
+      if (kb + 1 >= nkb) break;
+      __syncthreads();
+      stash(1);
+      __syncthreads();
+      fetch(1, kb + 3);
+      compute();
+    }
   }
 }
