@@ -624,24 +624,32 @@ __global__ __launch_bounds__(TaylorSplitCfg::NT, 2) void taylor_split_kernel(Tay
 }
 
 // acc += t_1 + ... + t_order in FP64, in order (terms of stride n)
-__global__ void taylor_split_sum_kernel(size_t n, int order, const float* __restrict__ t,
-                                        double* __restrict__ acc) {
+// Four consecutive elements per thread (16-byte term loads, two 16-byte
+// accumulator loads and stores); n is a multiple of 4 (ncolp is).
+__global__ __launch_bounds__(256) void taylor_split_sum_kernel(size_t n4, int order, const float* __restrict__ t,
+                                                               double* __restrict__ acc) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  float tv[32];
-  for (int k = 0; k < order; ++k) tv[k] = t[(size_t)k * n + e];  // independent loads
-  double a = acc[e];
-  for (int k = 0; k < order; ++k) a += (double)tv[k];
-  acc[e] = a;
+  if (e >= n4) return;
+  double2* a2 = reinterpret_cast<double2*>(acc) + 2 * e;
+  double2 a = a2[0], b = a2[1];
+  for (int k = 0; k < order; ++k) {
+    const float4 v = reinterpret_cast<const float4*>(t)[(size_t)k * n4 + e];
+    a.x += (double)v.x;
+    a.y += (double)v.y;
+    b.x += (double)v.z;
+    b.y += (double)v.w;
+  }
+  a2[0] = a;
+  a2[1] = b;
 }
 
 hipError_t launch_taylor_split_sum(const StepDims& d, int W, int order, const float* terms, double* acc,
                                    hipStream_t s) {
   if (W == 0) return hipSuccess;
-  if (order > 32) return hipErrorInvalidValue;
-  const size_t n = (size_t)W * d.N * d.ncolp;
-  hipLaunchKernelGGL(taylor_split_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, order, terms,
-                     acc);
+  if (order > 32 || d.ncolp % 4 != 0) return hipErrorInvalidValue;
+  const size_t n4 = (size_t)W * d.N * d.ncolp / 4;
+  hipLaunchKernelGGL(taylor_split_sum_kernel, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, n4, order,
+                     terms, acc);
   return hipGetLastError();
 }
 

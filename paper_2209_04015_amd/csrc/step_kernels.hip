@@ -406,6 +406,13 @@ template hipError_t launch_vhs<double>(const StepDims&, int, const double*, cons
 // out_z = P in_z for every walker, both spins side by side as real columns.
 // ===========================================================================
 
+#ifndef PPHI_BM
+#define PPHI_BM 64
+#endif
+#ifndef PPHI_BN
+#define PPHI_BN 64
+#endif
+
 struct PphiProb {
   using vec_t = double2;
   const double* P;
@@ -479,7 +486,9 @@ hipError_t launch_pphi(const StepDims& d, int W, const double* P, const double2*
   PphiProb p{P, d.N, d.ldP, d.ncolp, d.na, d.nb,
              reinterpret_cast<const double*>(phi_a_in), reinterpret_cast<const double*>(phi_b_in),
              acc, mode};
-  constexpr int BM = 64, BN = 64, BK = 16, WM = 2, WN = 2;
+  // 64 x 64 tiles: many small workgroups per walker (larger tiles lower the occupancy)
+  constexpr int BK = 16, WM = 2, WN = 2;
+  constexpr int BM = PPHI_BM, BN = PPHI_BN;
   dim3 grid(ceil_div(d.N, BM), ceil_div(d.ncolp, BN), W);
   hipLaunchKernelGGL((pphi_kernel<BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p, acc,
                      phi_a_out, phi_b_out, tmax);
