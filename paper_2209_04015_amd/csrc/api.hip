@@ -61,8 +61,10 @@ struct afqmc_ham {
   unsigned short* lh_split = nullptr;  // [2][K][nmax][2 ldh] split rows
   float* lh_unscale = nullptr;           // [2][K][nmax]
   unsigned short* th_split = nullptr;  // [W][2][2][nmax][2 ldh]
-  unsigned short* lt_split = nullptr;  // [Npk][2 ldhK] split packed L (VHS)
-  float* lt_unscale = nullptr;         // [Npk]
+  unsigned short* lt_split = nullptr;  // [nvblk * 160][2 ldhK] split L in VHS block order
+  float* lt_unscale = nullptr;         // [nvblk * 160]
+  int2* vblk = nullptr;                // [nvblk] VHS blocks (P, Q)
+  int nvblk = 0;
   unsigned short* xs_split = nullptr;  // [W][2][2 ldhK]
   float* xs_unscale = nullptr;         // [W][2]
   float* tk = nullptr;                 // [taylor_order][W][N][ncolp] Taylor terms (split path)
@@ -274,8 +276,8 @@ int seq_propagate_core(afqmc_ham* h, afqmc_walkers* w, int nw, const StepIO& io,
           launch_split_rows_mode(h->split, (long)nw * 2, d.K, (const float*)h->xs, d.ldK, h->xs_split, d.ldhK,
                                  h->xs_unscale, s));
     PHASE(h, AFQMC_PH_VHS, s,
-          launch_vhs_split(h->split, d, nw, h->xs_split, h->xs_unscale, h->lt_split, h->lt_unscale, h->pq,
-                           (float*)h->vhs, h->tmax + h->prm.max_walkers, h->sdt, s));
+          launch_vhs_split(h->split, d, nw, h->xs_split, h->xs_unscale, h->lt_split, h->lt_unscale, h->vblk,
+                           h->nvblk, (float*)h->vhs, h->tmax + h->prm.max_walkers, h->sdt, s));
   } else {
     PHASE(h, AFQMC_PH_VHS, s,
           (launch_vhs<T>(d, nw, (const T*)h->xs, (const T*)h->LT, h->pq, (T*)h->vhs, h->sdt, s)));
@@ -382,16 +384,26 @@ int build_working_arrays(afqmc_ham* h, const double* dL, const double* Y_a, cons
     HIP_TRY((setup_pack_lt<T>(d.K, d.N, d.Npk, d.ldK, h->pq, dL, (T*)h->LT, s)));
     return AFQMC_OK;
   }
-  // the split VHS keeps only the split packed L: the FP32 one is a temporary
-  if ((rc = dalloc_t(h, &h->lt_split, (size_t)d.Npk * 2 * d.ldhK))) return rc;
-  if ((rc = dalloc_t(h, &h->lt_unscale, (size_t)d.Npk))) return rc;
+  // the split VHS keeps only the split L in block order: the FP32 one is a temporary
+  const std::vector<int2> blk = vhs_split_blocks(d.N);
+  const std::vector<int2> pqb = vhs_split_pairs(d.N, blk);
+  const long nrow = (long)pqb.size();
+  h->nvblk = (int)blk.size();
+  int2* pqb_dev = nullptr;
+  if ((rc = dalloc_t(h, &h->vblk, blk.size()))) return rc;
+  HIP_TRY(hipMemcpy(h->vblk, blk.data(), blk.size() * sizeof(int2), hipMemcpyHostToDevice));
+  if ((rc = dalloc_t(h, &h->lt_split, (size_t)nrow * 2 * d.ldhK))) return rc;
+  if ((rc = dalloc_t(h, &h->lt_unscale, (size_t)nrow))) return rc;
   float* lt32 = nullptr;
-  HIP_TRY(hipMalloc(&lt32, (size_t)d.Npk * d.ldK * sizeof(float)));
-  hipError_t e = setup_pack_lt<float>(d.K, d.N, d.Npk, d.ldK, h->pq, dL, lt32, s);
+  HIP_TRY(hipMalloc(&lt32, (size_t)nrow * d.ldK * sizeof(float)));
+  HIP_TRY(hipMalloc(&pqb_dev, (size_t)nrow * sizeof(int2)));
+  hipError_t e = hipMemcpy(pqb_dev, pqb.data(), (size_t)nrow * sizeof(int2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = setup_pack_lt<float>(d.K, d.N, (int)nrow, d.ldK, pqb_dev, dL, lt32, s);
   if (e == hipSuccess)
-    e = launch_split_rows_mode(h->split, (long)d.Npk, d.K, lt32, d.ldK, h->lt_split, d.ldhK, h->lt_unscale, s);
+    e = launch_split_rows_mode(h->split, nrow, d.K, lt32, d.ldK, h->lt_split, d.ldhK, h->lt_unscale, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(lt32);
+  (void)hipFree(pqb_dev);
   HIP_TRY(e);
   // force bias: Lh split with one scale per Cholesky vector (rows (spin, i))
   if ((rc = dalloc_t(h, &h->fb_lh, (size_t)d.K * 2 * d.nmax * 2 * d.ldh))) return rc;

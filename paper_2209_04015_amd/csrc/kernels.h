@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "exchange_pair.h"
 
 // Sizes shared by every kernel of one Hamiltonian.
@@ -101,10 +103,14 @@ hipError_t set_kernel_attributes(const StepDims& d);
 hipError_t launch_split_rows_mode(int mode, long nrows, int ncols, const float* src, int ld_src,
                                   unsigned short* dst, int ldh, float* unscale, hipStream_t s);
 ExTile exchange_split_tile(int n);
-// vmax (optional): per-walker max |VHS| (atomic, bit patterns of floats)
+// vmax (optional): per-walker max |VHS| (atomic, bit patterns of floats).
+// lt: block-packed L split rows (vhs_split_pairs order), blk: the blocks.
 hipError_t launch_vhs_split(int mode, const StepDims& d, int W, const unsigned short* xs, const float* xs_unscale,
-                            const unsigned short* lt, const float* lt_unscale, const int2* pq, float* vhs,
+                            const unsigned short* lt, const float* lt_unscale, const int2* blk, int nblk, float* vhs,
                             unsigned* vmax, double sdt, hipStream_t s);
+// blocks of orbital pairs of the split VHS and the pair of each packed row
+std::vector<int2> vhs_split_blocks(int N);
+std::vector<int2> vhs_split_pairs(int N, const std::vector<int2>& blk);
 // Block split: one power-of-two scale per block of nspl x nsub source rows
 // (row s * S1 + b * S2 + i of block b), output rows contiguous per block
 hipError_t launch_split_blocks_mode(int mode, int nblocks, int nspl, int nsub, int ncols, const float* src, int ld_src,

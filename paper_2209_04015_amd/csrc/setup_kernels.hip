@@ -241,7 +241,7 @@ __global__ __launch_bounds__(256) void pack_lt_kernel(int K, int N, int Npk, int
     T v = (T)0;
     if (g < K && c < Npk) {
       const int2 ij = pq[c];
-      v = (T)L[((long)g * N + ij.x) * N + ij.y];
+      if (ij.x >= 0) v = (T)L[((long)g * N + ij.x) * N + ij.y];  // (-1, -1): a zero row
     }
     tile[r][tx] = v;
   }

@@ -5,6 +5,8 @@
 
 #include <math.h>
 
+#include <vector>
+
 #include "common.h"
 #include "kernels.h"
 #include "split_tile.h"
@@ -293,21 +295,29 @@ hipError_t launch_exchange_pair_split(int mode, const StepDims& d, int W, const 
 // B = packed L split rows (N (N + 1) / 2), contraction over the Cholesky
 // index.
 // ---------------------------------------------------------------------------
-// k blocks of loads in flight in the VHS main loop (a contraction over all
-// Cholesky vectors: about 90 k blocks at n290, operands beyond the L2)
-#ifndef VHS_PREFETCH
-#define VHS_PREFETCH 1
-#endif
+// VHS blocks: the orbital pairs are packed in blocks of VB_P rows p by VB_Q
+// columns q (one 160-column tile per block; blocks that touch the upper
+// triangle q >= p, pairs outside the matrix or below the diagonal are zero
+// rows and are not stored).  The tile's values go through LDS, so that both
+// halves leave as contiguous runs: (p, q) rows of VB_Q pairs and the mirror
+// (q, p) rows of VB_P pairs (full 128-byte lines).
+constexpr int VB_P = 16, VB_Q = 10;
+static_assert(VB_P * VB_Q == ExSplitCfg::BN, "one block per tile");
+// walkers per LDS pass of the store (the waves of one row half)
+constexpr int VHS_ZPASS = ExSplitCfg::BM / 2 / ExSplitCfg::WM;
+constexpr int VHS_LDS_BYTES = SplitStage<ExSplitCfg::BM, ExSplitCfg::BN>::BYTES > VHS_ZPASS * ExSplitCfg::BN * 8
+                                  ? SplitStage<ExSplitCfg::BM, ExSplitCfg::BN>::BYTES
+                                  : VHS_ZPASS * ExSplitCfg::BN * 8;
 
 struct VhsSplitArgs {
   const unsigned short* a;  // xs split rows [2 W][2 ldhK]
   const float* a_unscale;   // [2 W]
-  const unsigned short* b;  // LT split rows [Npk][2 ldhK]
-  const float* b_unscale;   // [Npk]
-  const int2* pq;           // packed index -> (p, q)
+  const unsigned short* b;  // block-packed L split rows [nblk * 160][2 ldhK]
+  const float* b_unscale;   // [nblk * 160]
+  const int2* blk;          // [nblk] (P, Q): rows p = VB_P P + i, columns q = VB_Q Q + j
   float* vhs;               // [W][N][ldV] complex interleaved
   unsigned* vmax;           // [W] max |VHS| (atomic), or null
-  int W, Npk, N, ldV, rowb, nkb;
+  int W, nblk, N, ldV, rowb, nkb;
   float sdt;
 };
 
@@ -318,49 +328,84 @@ __global__ __launch_bounds__(ExSplitCfg::NT, ExSplitCfg::WAVES_PER_EU) void vhs_
   constexpr int FM = C::BM / C::WM / 16, FN = C::BN / C::WN / 16;
   int tn, tm;  // consecutive tiles on one XCD share the packed-L tile
   if (!xcd_tile(blockIdx.x, ntn, ntm, 1, tn, tm)) return;
-  __shared__ __attribute__((aligned(16))) unsigned short vs_lds[SplitStage<C::BM, C::BN>::BYTES / 2];
+  __shared__ __attribute__((aligned(16))) unsigned short vs_lds[VHS_LDS_BYTES / 2];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
   const int wm = wid / C::WN, wn = wid % C::WN;
   const int m0 = tm * C::BM, n0 = tn * C::BN;
-  const int nm = min(C::BM, 2 * p.W - m0), nn = min(C::BN, p.Npk - n0);
-  // rows past nm / nn fall outside the tile buffers: staged as zeros
+  const int nm = min(C::BM, 2 * p.W - m0);
+  // rows past nm fall outside the tile buffer: staged as zeros
   const __amdgpu_buffer_rsrc_t a_rsrc = split_rsrc(p.a + (size_t)m0 * (p.rowb / 2), nm * p.rowb);
-  const __amdgpu_buffer_rsrc_t b_rsrc = split_rsrc(p.b + (size_t)n0 * (p.rowb / 2), nn * p.rowb);
+  const __amdgpu_buffer_rsrc_t b_rsrc = split_rsrc(p.b + (size_t)n0 * (p.rowb / 2), C::BN * p.rowb);
   int a_off[C::NA], b_off[C::NB];
 #pragma unroll
   for (int t = 0; t < C::NA; ++t) a_off[t] = ((tid >> 3) + t * (C::NT / 8)) * p.rowb + (tid & 7) * 16;
 #pragma unroll
   for (int t = 0; t < C::NB; ++t) b_off[t] = ((tid >> 3) + t * (C::NT / 8)) * p.rowb + (tid & 7) * 16;
   floatx4 acc[FM][FN];
-  split_tile_mainloop<H, C::BM, C::BN, C::WM, C::WN, VHS_PREFETCH>(a_rsrc, b_rsrc, a_off, b_off, p.nkb, acc, vs_lds);
-  // rows m = 2 z + (re|im): each lane's 4 consecutive rows are 2 whole walkers
+  split_tile_mainloop<H, C::BM, C::BN, C::WM, C::WN>(a_rsrc, b_rsrc, a_off, b_off, p.nkb, acc, vs_lds);
+
+  // values v = i sqrt(dt) (C_re + i C_im), rows m = 2 z + (re|im): each
+  // lane's 4 consecutive rows are 2 whole walkers; per-walker maxima
+  float cs[FN];
+#pragma unroll
+  for (int f = 0; f < FN; ++f)
+    cs[f] = H::SCALED ? p.b_unscale[n0 + wn * (C::BN / C::WN) + f * 16 + (lane & 15)] : 1.0f;
+  float2 val[FM][FN][2];
   float wmax[FM][2];
 #pragma unroll
-  for (int fi = 0; fi < FM; ++fi) wmax[fi][0] = wmax[fi][1] = 0.f;
+  for (int fi = 0; fi < FM; ++fi) {
+    const int mb = m0 + wm * (C::BM / C::WM) + fi * 16 + 4 * (lane >> 4);
 #pragma unroll
-  for (int f = 0; f < FN; ++f) {
-    const int col = n0 + wn * (C::BN / C::WN) + f * 16 + (lane & 15);
-    if (col >= p.Npk) continue;
-    const int2 ij = p.pq[col];
-    const float cs = H::SCALED ? p.b_unscale[col] : 1.0f;
+    for (int h = 0; h < 2; ++h) {
+      const int z = (mb >> 1) + h;
+      const bool ok = z < p.W;
+      const float ur = ok && H::SCALED ? p.a_unscale[2 * z] : 1.0f;
+      const float ui = ok && H::SCALED ? p.a_unscale[2 * z + 1] : 1.0f;
+      float m = 0.f;
 #pragma unroll
-    for (int fi = 0; fi < FM; ++fi) {
-      const int mb = m0 + wm * (C::BM / C::WM) + fi * 16 + 4 * (lane >> 4);
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int z = (mb >> 1) + h;
-        if (z >= p.W) continue;
-        float cr = acc[fi][f][2 * h], ci = acc[fi][f][2 * h + 1];
-        if (H::SCALED) {  // powers of two: exact
-          cr *= p.a_unscale[2 * z] * cs;
-          ci *= p.a_unscale[2 * z + 1] * cs;
-        }
-        const float2 v = make_float2(-p.sdt * ci, p.sdt * cr);
-        *reinterpret_cast<float2*>(p.vhs + ((size_t)z * p.N + ij.x) * p.ldV + 2 * ij.y) = v;
-        if (ij.x != ij.y) *reinterpret_cast<float2*>(p.vhs + ((size_t)z * p.N + ij.y) * p.ldV + 2 * ij.x) = v;
-        wmax[fi][h] = fmaxf(wmax[fi][h], fmaxf(fabsf(v.x), fabsf(v.y)));
+      for (int f = 0; f < FN; ++f) {  // powers of two: exact
+        const float cr = acc[fi][f][2 * h] * ur * cs[f], ci = acc[fi][f][2 * h + 1] * ui * cs[f];
+        val[fi][f][h] = make_float2(-p.sdt * ci, p.sdt * cr);
+        m = fmaxf(m, fmaxf(fabsf(val[fi][f][h].x), fabsf(val[fi][f][h].y)));
       }
+      wmax[fi][h] = m;
+    }
+  }
+  // stores: one row half of walkers at a time through LDS [walker][pair]
+  const int2 PQ = p.blk[tn];
+  const int pb0 = VB_P * PQ.x, qb0 = VB_Q * PQ.y;
+  float2* sv = reinterpret_cast<float2*>(vs_lds);
+  for (int half = 0; half < C::WM; ++half) {
+    __syncthreads();  // main loop (or the previous pass) done with the LDS
+    if (wm == half) {
+#pragma unroll
+      for (int fi = 0; fi < FM; ++fi)
+#pragma unroll
+        for (int f = 0; f < FN; ++f)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int zl = ((fi * 16 + 4 * (lane >> 4)) >> 1) + h;  // walker within the half
+            sv[zl * C::BN + wn * (C::BN / C::WN) + f * 16 + (lane & 15)] = val[fi][f][h];
+          }
+    }
+    __syncthreads();
+    const int zh = (m0 >> 1) + half * VHS_ZPASS;
+    // (p, q), q >= p: consecutive threads on consecutive q
+    for (int e = tid; e < VHS_ZPASS * C::BN; e += C::NT) {
+      const int zl = e / C::BN, c = e - zl * C::BN;
+      const int pp = c / VB_Q, qq = c - pp * VB_Q;
+      const int z = zh + zl, pr = pb0 + pp, qc = qb0 + qq;
+      if (z < p.W && pr < p.N && qc < p.N && qc >= pr)
+        *reinterpret_cast<float2*>(p.vhs + ((size_t)z * p.N + pr) * p.ldV + 2 * qc) = sv[e];
+    }
+    // mirror (q, p), q > p: consecutive threads on consecutive p
+    for (int e = tid; e < VHS_ZPASS * C::BN; e += C::NT) {
+      const int zl = e / C::BN, c = e - zl * C::BN;
+      const int qq = c / VB_P, pp = c - qq * VB_P;
+      const int z = zh + zl, pr = pb0 + pp, qc = qb0 + qq;
+      if (z < p.W && pr < p.N && qc < p.N && qc > pr)
+        *reinterpret_cast<float2*>(p.vhs + ((size_t)z * p.N + qc) * p.ldV + 2 * pr) = sv[zl * C::BN + pp * VB_Q + qq];
     }
   }
   if (p.vmax) {  // per walker: over the 16 lanes holding its rows, then one atomic
@@ -377,16 +422,39 @@ __global__ __launch_bounds__(ExSplitCfg::NT, ExSplitCfg::WAVES_PER_EU) void vhs_
   }
 }
 
+// (P, Q) of the VHS blocks that touch the upper triangle of an N x N matrix.
+std::vector<int2> vhs_split_blocks(int N) {
+  std::vector<int2> b;
+  for (int P = 0; VB_P * P < N; ++P)
+    for (int Q = 0; VB_Q * Q < N; ++Q)
+      if (VB_Q * Q + VB_Q - 1 >= VB_P * P) b.push_back(make_int2(P, Q));
+  return b;
+}
+
+// Orbital pair (p, q) of each packed row in block order, (-1, -1) for rows
+// outside the matrix or below the diagonal.
+std::vector<int2> vhs_split_pairs(int N, const std::vector<int2>& blk) {
+  std::vector<int2> pq;
+  pq.reserve(blk.size() * VB_P * VB_Q);
+  for (const int2& b : blk)
+    for (int i = 0; i < VB_P; ++i)
+      for (int j = 0; j < VB_Q; ++j) {
+        const int pr = VB_P * b.x + i, qc = VB_Q * b.y + j;
+        pq.push_back(pr < N && qc < N && qc >= pr ? make_int2(pr, qc) : make_int2(-1, -1));
+      }
+  return pq;
+}
+
 hipError_t launch_vhs_split(int mode, const StepDims& d, int W, const unsigned short* xs, const float* xs_unscale,
-                            const unsigned short* lt, const float* lt_unscale, const int2* pq, float* vhs,
+                            const unsigned short* lt, const float* lt_unscale, const int2* blk, int nblk, float* vhs,
                             unsigned* vmax, double sdt, hipStream_t s) {
   using C = ExSplitCfg;
   if (W == 0) return hipSuccess;
   if (d.ldhK % 32 != 0) return hipErrorInvalidValue;
   const int rowb = 2 * d.ldhK * 2;
   if ((double)C::BM * rowb >= (double)SPLIT_ROW_NONE) return hipErrorInvalidValue;
-  const int ntm = ceil_div(2 * W, C::BM), ntn = ceil_div(d.Npk, C::BN);
-  VhsSplitArgs p{xs, xs_unscale, lt, lt_unscale, pq, vhs, vmax, W, d.Npk, d.N, d.ldV, rowb, d.ldhK / 32, (float)sdt};
+  const int ntm = ceil_div(2 * W, C::BM), ntn = nblk;
+  VhsSplitArgs p{xs, xs_unscale, lt, lt_unscale, blk, vhs, vmax, W, nblk, d.N, d.ldV, rowb, d.ldhK / 32, (float)sdt};
   const int per = ceil_div(ntm * ntn, 8);
   if (mode == SPLIT_BF16)
     hipLaunchKernelGGL(vhs_split_kernel<HalfBF16>, dim3(8 * per), dim3(C::NT), 0, s, p, ntn, ntm);
