@@ -107,10 +107,6 @@ struct afqmc_ham {
   long pair_vrow0[2] = {0, 0};
   int ex_gs = 0;         // exchange tile-order group size (0: built-in default; set by the autotuner)
   bool capturing = false;  // inside a graph capture: no phase-timing events
-  // second stream for independent kernels within a call (default priority),
-  // forked from and joined back into the call's stream by events
-  hipStream_t aux = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<void*> allocs;
   // phase timing (afqmc_profile_enable)
   std::vector<hipEvent_t> ev;
@@ -142,14 +138,8 @@ int dalloc_t(afqmc_ham* h, T** p, size_t count) {
 }
 
 void free_all(afqmc_ham* h) {
-  if (h->aux) (void)hipStreamSynchronize(h->aux);
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
-  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
-  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
-  if (h->aux) (void)hipStreamDestroy(h->aux);
-  h->ev_fork = h->ev_join = nullptr;
-  h->aux = nullptr;
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   h->ev.clear();
 }
@@ -188,31 +178,6 @@ void prof_close(afqmc_ham* h, int phase, int e0, hipStream_t s) {
     HIP_TRY(expr);                       \
     prof_close((h), (ph), e0__, (s));    \
   } while (0)
-
-// Independent work of a call goes to aux_stream(h, s): the handle's second
-// stream, ordered after everything queued on s so far by fork_aux and joined
-// back into s by join_aux (event dependencies).  Inside a graph capture
-// (the batch's, or any capture of s) it stays on s and fork / join do
-// nothing: a capture that forked a second stream from a stream already
-// joined into the capture ended the process in the multi-system graph path.
-bool in_capture(const afqmc_ham* h, hipStream_t s) {
-  if (h->capturing) return true;
-  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
-  return hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone;
-}
-hipStream_t aux_stream(const afqmc_ham* h, hipStream_t s) { return in_capture(h, s) ? s : h->aux; }
-int fork_aux(afqmc_ham* h, hipStream_t s) {
-  if (in_capture(h, s)) return AFQMC_OK;
-  HIP_TRY(hipEventRecord(h->ev_fork, s));
-  HIP_TRY(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
-  return AFQMC_OK;
-}
-int join_aux(afqmc_ham* h, hipStream_t s) {
-  if (in_capture(h, s)) return AFQMC_OK;
-  HIP_TRY(hipEventRecord(h->ev_join, h->aux));
-  HIP_TRY(hipStreamWaitEvent(s, h->ev_join, 0));
-  return AFQMC_OK;
-}
 
 // ---------------------------------------------------------------------------
 // step sequences, per working precision
@@ -282,24 +247,17 @@ hipError_t launch_exchange_spin(afqmc_ham* h, int nw, int sp, int* ntg, hipStrea
   return launch_exchange<double>(d, nw, (const double*)h->Lh, (const double*)h->theta, h->part, sp, ntg, s, gs);
 }
 
-// Exchange partials of both spins into h->part (theta already built); *ntg
-// gets the partials' row-tile stride.
-int seq_exchange_partials(afqmc_ham* h, int nw, int* ntg, hipStream_t s) {
+template <typename T>
+int seq_energy_from_theta(afqmc_ham* h, int nw, double2* e_out, hipStream_t s,
+                          const int* ctr = nullptr, long estep = 0) {
+  int ntg = 0;
   if (h->split != SPLIT_NONE) {
     const StepDims& d = h->d;
     PHASE(h, AFQMC_PH_SPLIT, s,
           launch_split_rows_mode(h->split, (long)nw * 4 * d.nmax, d.N, (const float*)h->theta, d.ldN,
                                  h->th_split, d.ldh, h->th_unscale, s));
   }
-  for (int sp = 0; sp < 2; ++sp) PHASE(h, AFQMC_PH_EXCHANGE, s, launch_exchange_spin(h, nw, sp, ntg, s, h->ex_gs));
-  return AFQMC_OK;
-}
-
-template <typename T>
-int seq_energy_from_theta(afqmc_ham* h, int nw, double2* e_out, hipStream_t s,
-                          const int* ctr = nullptr, long estep = 0) {
-  int ntg = 0, rc;
-  if ((rc = seq_exchange_partials(h, nw, &ntg, s))) return rc;
+  for (int sp = 0; sp < 2; ++sp) PHASE(h, AFQMC_PH_EXCHANGE, s, launch_exchange_spin(h, nw, sp, &ntg, s, h->ex_gs));
   PHASE(h, AFQMC_PH_ENERGY, s,
         launch_energy(h->d, nw, h->e1, h->vbias, h->part, ntg, e_out, ctr, estep, s));
   return AFQMC_OK;
@@ -313,14 +271,6 @@ int seq_propagate_core(afqmc_ham* h, afqmc_walkers* w, int nw, const StepIO& io,
   PHASE(h, AFQMC_PH_SHIFT, s,
         (launch_shift<T>(d, nw, h->vbias, io.fields, io.ctr, io.fstep, (T*)h->xs, h->a, h->tmax,
                          h->prm.taylor_order + 2, h->prm.max_walkers, h->sdt, s)));
-  // the first one-body half step needs only phi (and the maxima zeroed by the
-  // shift): it runs beside the VHS build
-  int rc;
-  if ((rc = fork_aux(h, s))) return rc;
-  const hipStream_t sa = aux_stream(h, s);
-  PHASE(h, AFQMC_PH_ONE_BODY, sa,
-        launch_pphi(d, nw, h->P, (const double2*)w->phi_a, (const double2*)w->phi_b, h->acc, nullptr,
-                    nullptr, h->tmax, 0, sa));
   if (vhs_split(h)) {
     PHASE(h, AFQMC_PH_SPLIT, s,
           launch_split_rows_mode(h->split, (long)nw * 2, d.K, (const float*)h->xs, d.ldK, h->xs_split, d.ldhK,
@@ -332,7 +282,9 @@ int seq_propagate_core(afqmc_ham* h, afqmc_walkers* w, int nw, const StepIO& io,
     PHASE(h, AFQMC_PH_VHS, s,
           (launch_vhs<T>(d, nw, (const T*)h->xs, (const T*)h->LT, h->pq, (T*)h->vhs, h->sdt, s)));
   }
-  if ((rc = join_aux(h, s))) return rc;
+  PHASE(h, AFQMC_PH_ONE_BODY, s,
+        launch_pphi(d, nw, h->P, (const double2*)w->phi_a, (const double2*)w->phi_b, h->acc, nullptr,
+                    nullptr, h->tmax, 0, s));
   const int order = h->prm.taylor_order;
   if (vhs_split(h)) {
     // every term kept (tk[k - 1]), summed into acc once at the end
@@ -402,18 +354,9 @@ int seq_step(afqmc_ham* h, afqmc_walkers* w, int nw, const StepIO& io, int do_qr
   PHASE(h, AFQMC_PH_WEIGHT, s,
         launch_weight(nw, h->logdet, do_qr ? h->corr : nullptr, h->a, (double2*)w->log_ovlp,
                       w->log_w, h->cst, h->status, s));
+  if ((rc = seq_force_bias<T>(h, nw, h->vbias, s))) return rc;
   if (io.e) {
-    // the exchange partials and the force bias both read theta only: the
-    // partials run beside the force bias, the energy sum after both
-    int ntg = 0;
-    if ((rc = fork_aux(h, s))) return rc;
-    if ((rc = seq_exchange_partials(h, nw, &ntg, aux_stream(h, s)))) return rc;
-    if ((rc = seq_force_bias<T>(h, nw, h->vbias, s))) return rc;
-    if ((rc = join_aux(h, s))) return rc;
-    PHASE(h, AFQMC_PH_ENERGY, s,
-          launch_energy(h->d, nw, h->e1, h->vbias, h->part, ntg, io.e, io.ctr, io.estep, s));
-  } else {
-    if ((rc = seq_force_bias<T>(h, nw, h->vbias, s))) return rc;
+    if ((rc = seq_energy_from_theta<T>(h, nw, io.e, s, io.ctr, io.estep))) return rc;
   }
   h->c_valid = true;
   h->c_phi_a = w->phi_a;
@@ -634,9 +577,6 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
   h->split = p.precision == AFQMC_BF16X3 ? SPLIT_BF16 : (p.precision == AFQMC_FP16X3 ? SPLIT_F16 : SPLIT_NONE);
   h->sdt = sqrt(p.dt);
   HIP_TRY(set_kernel_attributes(d));
-  HIP_TRY(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
-  HIP_TRY(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-  HIP_TRY(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
 
   const int N = d.N, K = d.K, nmax = d.nmax;
   const size_t NN = (size_t)N * N;
