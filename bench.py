@@ -170,7 +170,8 @@ def hbm_traffic(kernel, instance, workload):
         with open(os.path.join(pdir, name)) as fh:
             for line in fh:
                 f = line.strip().strip("`").split()
-                if len(f) < 4 or f[0] != "hbm-traffic" or f[1] != instance or f[2] != workload:
+                # instance names are written without spaces
+                if len(f) < 4 or f[0] != "hbm-traffic" or f[1] != instance.replace(" ", "") or f[2] != workload:
                     continue
                 kv = dict(x.split("=", 1) for x in f[3:] if "=" in x)
                 if kv.get("sources_sha256") == sha:
@@ -189,7 +190,9 @@ def _kernel_of(phase, precision, algo):
         return base, f"{base}<{H if split else T}>"
     if precision == "fp16x3":   # the VHS runs on split operands only in FP16X3
         return "vhs_split_kernel", "vhs_split_kernel<HalfF16>"
-    return "vhs_kernel", f"vhs_kernel<{T}>"
+    # tile template arguments of the FP32 / FP64 VHS instances (step_kernels.hip)
+    return "vhs_kernel", {"double": "vhs_kernel<double, 64, 64, 16, 2, 2>",
+                          "float": "vhs_kernel<float, 64, 64, 32, 2, 2>"}[T]
 
 
 def roofline_of(cfg, phases, precision, algo, phase):
