@@ -71,7 +71,7 @@ BLOCK_STEPS = 25   # propagation steps per block (the paper's timing convention)
 
 
 def run_gpu(cfg, h1, L, phiT, precision, steps, warmup, fields_dev, block_fields_dev, device,
-            exchange="auto"):
+            exchange="auto", sample=1):
     import torch
 
     from paper_2209_04015_amd import afqmc
@@ -104,6 +104,9 @@ def run_gpu(cfg, h1, L, phiT, precision, steps, warmup, fields_dev, block_fields
     ham.profile_enable(0)
     status = ham.status()
     log(f"{precision}: {steps} steps in {ms:.1f} ms ({ms / steps:.2f} ms/step), status {status}")
+    # the oracle comparison uses the walkers and energies of the last timed step
+    # (re-orthogonalised every step), before the secondary runs below move them
+    sample_state = (w.phi_a[:sample].cpu().numpy(), w.phi_b[:sample].cpu().numpy(), e[:sample].cpu().numpy())
     # secondary figures on the same walkers: propagation only (no QR, no
     # energy), and one block in the paper's convention (BLOCK_STEPS steps,
     # QR and energy at the last, global energy, comb)
@@ -129,7 +132,7 @@ def run_gpu(cfg, h1, L, phiT, precision, steps, warmup, fields_dev, block_fields
                        "ms_per_block": round(ms_block, 3),
                        "definition": f"{BLOCK_STEPS} steps, QR and local energy at the last, "
                                      "global energy, comb population control"}}
-    return ham, w, e, ms, phases, status, extra
+    return ham, w, e, ms, phases, status, extra, sample_state
 
 
 # Sources that define each roofline kernel: its HBM traffic figure (from the
@@ -325,15 +328,12 @@ def main():
     for precision in MODES:
         if args.only and precision != args.only:
             continue
-        ham, w, e, ms, phases, status, extra = run_gpu(cfg, h1, L, phiT, precision, args.steps, args.warmup,
-                                                       fields_dev, block_fields_dev, device, exchange=args.exchange)
+        ham, w, e, ms, phases, status, extra, st = run_gpu(cfg, h1, L, phiT, precision, args.steps, args.warmup,
+                                                           fields_dev, block_fields_dev, device,
+                                                           exchange=args.exchange, sample=sample)
         results[precision] = (ms, phases, status)
         extras[precision] = extra
-        # energies of sampled walkers from this path's own final states
-        pa = w.phi_a[:sample].cpu().numpy()
-        pb = w.phi_b[:sample].cpu().numpy()
-        e_s = ham.local_energy(w).cpu().numpy()[:sample]
-        states[precision] = (pa, pb, e_s)
+        states[precision] = st
         ham.close()
         del w, e
         torch.cuda.empty_cache()
@@ -341,8 +341,8 @@ def main():
     # the paper's direct exchange algorithm on the headline path, for comparison
     direct = None
     if not args.only:
-        ham, w, e, ms_d, ph_d, st_d, ex_d = run_gpu(cfg, h1, L, phiT, args.headline, args.steps, args.warmup,
-                                                   fields_dev, block_fields_dev, device, exchange="direct")
+        ham, w, e, ms_d, ph_d, st_d, ex_d, _ = run_gpu(cfg, h1, L, phiT, args.headline, args.steps, args.warmup,
+                                                      fields_dev, block_fields_dev, device, exchange="direct")
         direct = {"exchange_algorithm": "direct", "value": round(cfg.W * args.steps / (ms_d * 1e-3), 2),
                   "unit": "walker-steps/s", "ms_per_step": round(ms_d / args.steps, 4),
                   "roofline": roofline(cfg, ph_d, args.headline, "direct"),
