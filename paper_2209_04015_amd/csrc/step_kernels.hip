@@ -1055,11 +1055,11 @@ __global__ __launch_bounds__(QR_THREADS) void qr_kernel(StepDims d, double2* __r
           rinv[k] = ik;
           lnr += log(rk);
         }
-        const int m = n - 1 - k;  // trailing size
-        for (int e = lane; e < m * (m + 1) / 2; e += 64) {
-          int a = 0, r = e;
-          while (r >= m - a) r -= m - a, ++a;
-          const int ii = k + 1 + a, jj = ii + r;
+        const int m = n - 1 - k;  // trailing size: the m x m square, lanes below the diagonal idle
+        for (int e = lane; e < m * m; e += 64) {
+          const int a = e / m, b = e - a * m;
+          if (b < a) continue;
+          const int ii = k + 1 + a, jj = k + 1 + b;
           R[ii * n + jj] = csub(R[ii * n + jj], cmul(cconj(R[k * n + ii]), R[k * n + jj]));
         }
       }
