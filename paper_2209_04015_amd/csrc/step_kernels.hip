@@ -85,14 +85,31 @@ __global__ __launch_bounds__(GF_THREADS) void gf_kernel(
       const int e = tid + r * GF_THREADS;
       if (e < n * n) {
         const int i = e / n, j = e % n;
-        double2 s = sacc[r];
-        for (int pr = 0; pr < rows; ++pr) {
-          const double t = tch[pr * n + i];
-          const double2 f = ch[pr * n + j];
-          s.x += t * f.x;
-          s.y += t * f.y;
+        // four interleaved partial sums: the LDS reads of consecutive rows
+        // are independent and stay in flight together
+        double2 s0 = make_double2(0.0, 0.0), s1 = s0, s2 = s0, s3 = s0;
+        int pr = 0;
+        for (; pr + 4 <= rows; pr += 4) {
+          const double t0 = tch[pr * n + i], t1 = tch[(pr + 1) * n + i];
+          const double t2 = tch[(pr + 2) * n + i], t3 = tch[(pr + 3) * n + i];
+          const double2 f0 = ch[pr * n + j], f1 = ch[(pr + 1) * n + j];
+          const double2 f2 = ch[(pr + 2) * n + j], f3 = ch[(pr + 3) * n + j];
+          s0.x += t0 * f0.x;
+          s0.y += t0 * f0.y;
+          s1.x += t1 * f1.x;
+          s1.y += t1 * f1.y;
+          s2.x += t2 * f2.x;
+          s2.y += t2 * f2.y;
+          s3.x += t3 * f3.x;
+          s3.y += t3 * f3.y;
         }
-        sacc[r] = s;
+        for (; pr < rows; ++pr) {
+          const double t0 = tch[pr * n + i];
+          const double2 f0 = ch[pr * n + j];
+          s0.x += t0 * f0.x;
+          s0.y += t0 * f0.y;
+        }
+        sacc[r] = cadd(sacc[r], cadd(cadd(s0, s1), cadd(s2, s3)));
       }
     }
   }
@@ -180,8 +197,17 @@ __global__ __launch_bounds__(GF_THREADS) void gf_kernel(
     for (int e = tid; e < rows * n; e += GF_THREADS) {
       const int j = e / rows, pr = e % rows;
       double2 t = make_double2(0.0, 0.0);
-      if (!singular) {
-        for (int k = 0; k < n; ++k) t = cadd(t, cmul(ch[pr * n + k], aug[k * n2 + n + j]));
+      if (!singular) {  // four interleaved partial sums (independent LDS reads)
+        double2 u0 = t, u1 = t, u2 = t, u3 = t;
+        int k = 0;
+        for (; k + 4 <= n; k += 4) {
+          u0 = cadd(u0, cmul(ch[pr * n + k], aug[k * n2 + n + j]));
+          u1 = cadd(u1, cmul(ch[pr * n + k + 1], aug[(k + 1) * n2 + n + j]));
+          u2 = cadd(u2, cmul(ch[pr * n + k + 2], aug[(k + 2) * n2 + n + j]));
+          u3 = cadd(u3, cmul(ch[pr * n + k + 3], aug[(k + 3) * n2 + n + j]));
+        }
+        for (; k < n; ++k) u0 = cadd(u0, cmul(ch[pr * n + k], aug[k * n2 + n + j]));
+        t = cadd(cadd(u0, u1), cadd(u2, u3));
       }
       const int p = p0 + pr;
       const double h = hs[(size_t)j * N + p];
@@ -412,6 +438,9 @@ template hipError_t launch_vhs<double>(const StepDims&, int, const double*, cons
 #ifndef PPHI_BN
 #define PPHI_BN 64
 #endif
+#ifndef PPHI_BK
+#define PPHI_BK 16
+#endif
 
 struct PphiProb {
   using vec_t = double2;
@@ -487,7 +516,7 @@ hipError_t launch_pphi(const StepDims& d, int W, const double* P, const double2*
              reinterpret_cast<const double*>(phi_a_in), reinterpret_cast<const double*>(phi_b_in),
              acc, mode};
   // 64 x 64 tiles: many small workgroups per walker (larger tiles lower the occupancy)
-  constexpr int BK = 16, WM = 2, WN = 2;
+  constexpr int BK = PPHI_BK, WM = 2, WN = 2;
   constexpr int BM = PPHI_BM, BN = PPHI_BN;
   dim3 grid(ceil_div(d.N, BM), ceil_div(d.ncolp, BN), W);
   hipLaunchKernelGGL((pphi_kernel<BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p, acc,
