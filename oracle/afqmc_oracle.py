@@ -60,6 +60,17 @@ Readings where the paper is silent (each is listed in the design doc as well):
 * R21 Weighted walker mean of any per-walker value v_z (the reduction of
       the global energy, R18, and of the mixed estimators of Sec. IV.B):
       sum_z w_z v_z / sum_z w_z.
+* R23 Multi-determinant trial (Sec. III.A): |Psi_T> = sum_a c_a t_a |psi_0>
+      with real c_a, psi_0 the first n_s columns of an orthogonal orbital
+      matrix C^s per spin, and t_a = prod_s prod_m a+_{s,q_m} a_{s,h_m} in
+      those orbitals (hole h_m paired with particle q_m).  t_a |psi_0> is the
+      determinant D_a whose orbital matrix is psi_0's with column h_m
+      replaced in place by column q_m of C^s, so
+      <Psi_T|phi> = sum_a c_a det(D_a^aT phi^a) det(D_a^bT phi^b).
+* R24 Its Green's function (Eq. gf with the MSD numerator of Sec. III.B):
+      G^s = sum_a c_a O_a G^s_a / sum_a c_a O_a, O_a = <D_a|phi> and G^s_a
+      the single-determinant Green's function of D_a^s (R11).  The force bias
+      of an MSD trial is Eq. (fb) with this G.
 * R19 Block (Sec. IV.A and IV.C): nsteps propagation steps, the last one
       followed by re-orthogonalisation and the local energy, then the global
       energy of the block, then the comb.
@@ -96,6 +107,12 @@ __all__ = [
     "block",
     "s2_mixed",
     "weighted_mean",
+    "OracleMSD",
+    "msd_setup",
+    "msd_determinant",
+    "msd_overlap",
+    "msd_green",
+    "msd_force_bias",
 ]
 
 
@@ -439,3 +456,83 @@ def weighted_mean(log_w, v):
         return np.full(v.shape[1], complex(np.nan, np.nan)), -np.inf, 0
     den = float(np.sum(w))
     return (w @ v) / den, m + math.log(den), live
+
+
+# ---------------------------------------------------------------------------
+# Multi-determinant trial (Sec. III.A, III.B; R23, R24)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class OracleMSD:
+    C: tuple                # (C_a, C_b), each [N, N] orthogonal float64
+    nel: tuple              # (na, nb)
+    coeff: np.ndarray       # [ndet] float64
+    exc: list               # per determinant: ((holes_a, parts_a), (holes_b, parts_b))
+
+
+def msd_setup(C_a, C_b, na, nb, coeff, rank, orbs):
+    """Expansion from the array form: rank [ndet, 2]; orbs [ndet, 2, 2, kmax]
+    (spin, holes | particles, slot), hole m paired with particle m."""
+    exc = []
+    for a in range(len(coeff)):
+        exc.append(tuple((tuple(int(v) for v in orbs[a, s, 0, :rank[a, s]]),
+                          tuple(int(v) for v in orbs[a, s, 1, :rank[a, s]])) for s in range(2)))
+    return OracleMSD((np.asarray(C_a, np.float64), np.asarray(C_b, np.float64)), (na, nb),
+                     np.asarray(coeff, np.float64), exc)
+
+
+def msd_determinant(C, n, holes, parts):
+    """Orbital matrix of t_a psi_0: psi_0 = C[:, :n] with column h_m replaced by C[:, q_m] (R23)."""
+    D = np.array(C[:, :n], copy=True)
+    for h, q in zip(holes, parts):
+        D[:, h] = C[:, q]
+    return D
+
+
+def _msd_terms(msd, phi_a, phi_b):
+    """Per determinant a: complex log of c_a <D_a|phi_z>, and the two spin Green's functions."""
+    W = phi_a.shape[0]
+    logs, greens = [], []
+    for ca, spins in zip(msd.coeff, msd.exc):
+        la = np.full(W, np.log(complex(ca)))
+        gs = []
+        for s, phi in enumerate((phi_a, phi_b)):
+            D = msd_determinant(msd.C[s], msd.nel[s], *spins[s])
+            if D.shape[1] == 0:
+                gs.append(np.zeros((W, phi.shape[1], phi.shape[1]), complex))
+                continue
+            _, ld = theta_and_logdet(D, phi)
+            la = la + ld
+            gs.append(full_green(D, phi))
+        logs.append(la)
+        greens.append(gs)
+    return np.array(logs), greens
+
+
+def msd_overlap(msd, phi_a, phi_b):
+    """log <Psi_T|phi_z> = log sum_a c_a det(D_a^aT phi^a) det(D_a^bT phi^b) (R23), complex [W].
+
+    The sum is taken relative to its largest |term| (exact up to rounding).
+    """
+    logs, _ = _msd_terms(msd, phi_a, phi_b)
+    m = np.max(logs.real, axis=0)
+    return m + np.log(np.sum(np.exp(logs - m), axis=0))
+
+
+def msd_green(msd, phi_a, phi_b):
+    """G[z, s, p, q] = <Psi_T|a+_ps a_qs|phi_z>/<Psi_T|phi_z> (R24), complex [W, 2, N, N]."""
+    logs, greens = _msd_terms(msd, phi_a, phi_b)
+    m = np.max(logs.real, axis=0)
+    w = np.exp(logs - m)                      # c_a O_a / e^m, [ndet, W]
+    N = phi_a.shape[1]
+    G = np.zeros((phi_a.shape[0], 2, N, N), complex)
+    for a in range(len(msd.coeff)):
+        for s in range(2):
+            G[:, s] += w[a][:, None, None] * greens[a][s]
+    return G / np.sum(w, axis=0)[:, None, None, None]
+
+
+def msd_force_bias(msd, L, phi_a, phi_b):
+    """vbias[z, g] = sum_s sum_pq G^s_pq L_g,pq with the MSD Green's function (Eq. fb, R24)."""
+    G = msd_green(msd, phi_a, phi_b)
+    return np.einsum("zspq,gpq->zg", G, L)

@@ -15,6 +15,12 @@ with the same array shapes and structure:
   determinant trial as in Sec. III), each column's sign fixed so that its
   largest-magnitude entry is positive.
 * ``fields``: auxiliary fields ~ N(0, 1), shape (steps, W, K) (Eq. Bx).
+* ``orbitals`` / ``msd_expansion``: a multi-determinant trial (Sec. III.A)
+  as excitations of the reference determinant within the full eigenvector
+  basis of h1, with decaying, sorted coefficients.  The paper's expansions
+  come from selected CI on real molecules; these stand in for them with the
+  same structure (reference first, mostly low-rank excitations of both
+  spins, no duplicates).
 
 Seeding: ``SeedSequence(seed).spawn(3)`` gives independent streams for the
 Hamiltonian, the fields and auxiliary draws (walker perturbations).  All
@@ -27,6 +33,7 @@ inputs.  Both the oracle tests and the GPU tests take their inputs from it.
 from __future__ import annotations
 
 import dataclasses
+import math
 
 import numpy as np
 
@@ -38,6 +45,9 @@ __all__ = [
     "fields",
     "walkers_at_trial",
     "walkers_perturbed",
+    "MSD_MAX_RANK",
+    "orbitals",
+    "msd_expansion",
 ]
 
 
@@ -129,3 +139,76 @@ def walkers_perturbed(phiT: np.ndarray, W: int, scale: float, seed: int = 0,
     else:
         r = rng.standard_normal((W, N, n)).astype(np.complex128)
     return phiT[None, :, :] + scale * r
+
+
+MSD_MAX_RANK = 6  # excitation rank per spin supported by the expansion format
+
+
+def orbitals(h1: np.ndarray) -> np.ndarray:
+    """All eigenvectors of h1, ascending, as an [N, N] float64 orthogonal matrix.
+
+    Column signs follow ``trial``: ``orbitals(h1)[:, :n] == trial(h1, n)``.
+    """
+    return trial(h1, h1.shape[0])
+
+
+def msd_expansion(N: int, na: int, nb: int, ndet: int, max_rank: int = 4, seed: int = 0,
+                  stream: int = 0):
+    """A synthetic multi-determinant expansion of ``ndet`` distinct determinants.
+
+    Returns ``(coeff [ndet] float64, rank [ndet, 2] int32,
+    orbs [ndet, 2, 2, MSD_MAX_RANK] int32)``.  Determinant a excites, in spin
+    s, ``rank[a, s]`` electrons: holes ``orbs[a, s, 0, :rank]`` (ascending,
+    in [0, n_s)) to particles ``orbs[a, s, 1, :rank]`` (in [n_s, N), in a
+    random order: hole m is paired with particle m); unused slots hold -1.
+    Determinant 0 is the reference with coefficient 1.  Per-spin ranks are
+    drawn with probability proportional to 0.45^k (k <= max_rank and the
+    available holes and particles), the pair (0, 0) excluded after the
+    reference; coefficients are +-0.2 exp(-3 a / ndet) (1 - u / 2), u ~ U(0, 1),
+    sorted by decreasing magnitude after the reference.
+    """
+    if not 0 <= max_rank <= MSD_MAX_RANK:
+        raise ValueError("max_rank out of range")
+    _, _, aux_ss = _streams(seed)
+    rng = np.random.default_rng(aux_ss.spawn(stream + 1)[stream])
+    nel = (na, nb)
+    kmax = [min(max_rank, n, N - n) for n in nel]
+    seen = {((), (), (), ())}
+    exc = [((), (), (), ())]
+    limit = 1
+    for k_a in range(kmax[0] + 1):
+        for k_b in range(kmax[1] + 1):
+            limit += (math.comb(na, k_a) * math.comb(N - na, k_a)
+                      * math.comb(nb, k_b) * math.comb(N - nb, k_b))
+    if ndet > limit - 1:
+        raise ValueError("more determinants requested than the excitation space holds")
+    prob = [np.array([0.45 ** k for k in range(km + 1)]) for km in kmax]
+    prob = [pr / pr.sum() for pr in prob]
+    while len(exc) < ndet:
+        ks = [int(rng.choice(len(pr), p=pr)) for pr in prob]
+        if ks == [0, 0]:
+            continue
+        key, ident = [], []
+        for s in range(2):
+            holes = tuple(sorted(int(h) for h in rng.choice(nel[s], ks[s], replace=False)))
+            parts = tuple(int(q) for q in rng.permutation(rng.choice(np.arange(nel[s], N), ks[s],
+                                                                     replace=False)))
+            key += [holes, parts]
+            ident += [holes, tuple(sorted(parts))]   # the determinant, whatever the pairing
+        if tuple(ident) in seen:
+            continue
+        seen.add(tuple(ident))
+        exc.append(tuple(key))
+    mag = 0.2 * np.exp(-3.0 * np.arange(1, ndet) / ndet) * (1.0 - 0.5 * rng.random(ndet - 1))
+    sign = np.where(rng.random(ndet - 1) < 0.5, -1.0, 1.0)
+    order = np.argsort(-mag, kind="stable")
+    coeff = np.concatenate([[1.0], (sign * mag)[order]])
+    exc = [exc[0]] + [exc[1 + i] for i in order]
+    rank = np.zeros((ndet, 2), dtype=np.int32)
+    orbs = np.full((ndet, 2, 2, MSD_MAX_RANK), -1, dtype=np.int32)
+    for a, (ha, pa, hb, pb) in enumerate(exc):
+        for s, (h, q) in enumerate(((ha, pa), (hb, pb))):
+            rank[a, s] = len(h)
+            orbs[a, s, 0, :len(h)] = h
+            orbs[a, s, 1, :len(q)] = q
+    return coeff, rank, orbs
