@@ -326,6 +326,55 @@ int afqmc_autotune(afqmc_batch* b, const char* cache_path);
 
 void afqmc_batch_destroy(afqmc_batch* b);
 
+/* ---------------------------------------------------------------------------
+ * Multi-determinant trial (Sec. III.A, Eq. msdovlp; the MSD numerator of
+ * Eq. gf through the generalised Wick's theorem, Eq. msdgf0).
+ *
+ *   |Psi_T> = sum_a c_a t_a |psi_0>,  psi_0 = columns 0 .. n_s - 1 of C_s,
+ *   t_a = prod_s prod_m a+_{s, q_m} a_{s, h_m}  (orbitals of C_s),
+ * i.e. determinant a is psi_0 with column h_m replaced, in place, by column
+ * q_m of C_s (hole m paired with particle m).  The excitation format:
+ *   coeff  host double [ndet]             c_a (real)
+ *   rank   host int [ndet][2]             k_{a,s} in [0, AFQMC_MSD_MAX_RANK]
+ *   orbs   host int [ndet][2][2][AFQMC_MSD_MAX_RANK]
+ *          orbs[a][s][0][m] = h_m in [0, n_s), distinct;
+ *          orbs[a][s][1][m] = q_m in [n_s, N), distinct; slots m >= k unread.
+ *   C_a, C_b  host double [N][N], orthogonal (C^T C = I; not checked).
+ * afqmc_msd_create copies everything (the caller keeps its arrays), groups
+ * the determinants by their per-spin excitation strings and allocates a
+ * workspace for max_walkers walkers; it synchronises `stream`.  Limits:
+ * 1 <= na <= 45, 0 <= nb <= 45, ndet >= 1.  Errors: AFQMC_EINVAL for bad
+ * sizes or an invalid excitation (message names the determinant),
+ * AFQMC_ENOMEM when the workspace does not fit.
+ * ------------------------------------------------------------------------- */
+#define AFQMC_MSD_MAX_RANK 6
+typedef struct afqmc_msd afqmc_msd;
+
+int afqmc_msd_create(int N, int na, int nb, const double* host_C_a, const double* host_C_b, int ndet,
+                     const double* host_coeff, const int* host_rank, const int* host_orbs,
+                     int max_walkers, void* stream, afqmc_msd** out);
+
+/* log <Psi_T|phi_z> = log det(C_a,occ^T phi_a) + log det(C_b,occ^T phi_b)
+ *                   + log sum_a c_a det A^a_a det A^b_a     (Eq. msdovlp)
+ * with A^s_a[l][m] = Y^s[q_l][h_m], Y^s = C_s,virt^T phi_s (C_s,occ^T phi_s)^-1.
+ * w->phi_a, w->phi_b are read (log_ovlp and log_w are not used);
+ * log_ovlp: device complex [nw], written.  A walker with a singular
+ * reference overlap or a zero sum gets -inf and sets AFQMC_STATUS_SINGULAR
+ * (read with afqmc_msd_get_status).  Asynchronous on `stream`; nw <= max_walkers. */
+int afqmc_msd_overlap(afqmc_msd* t, const afqmc_walkers* w, int nw, void* log_ovlp, void* stream);
+
+/* G[z][s][p][q] = <Psi_T|a+_{p s} a_{q s}|phi_z> / <Psi_T|phi_z> for the
+ * multi-determinant trial (the numerator of Eq. gf through the generalised
+ * Wick's theorem, Sec. III.B).  G: device complex [nw][2][N][N], written
+ * (beta block zero when nb = 0).  Same inputs and status as afqmc_msd_overlap. */
+int afqmc_msd_green_function(afqmc_msd* t, const afqmc_walkers* w, int nw, void* G, void* stream);
+
+/* Excitation strings per spin after grouping (for sizing and reports). */
+int afqmc_msd_get_strings(afqmc_msd* t, int* nstr_a, int* nstr_b);
+/* Synchronise `stream`, return the accumulated status bits in *out and clear them. */
+int afqmc_msd_get_status(afqmc_msd* t, void* stream, int* out);
+void afqmc_msd_destroy(afqmc_msd* t);
+
 void afqmc_destroy(afqmc_ham* ham);
 const char* afqmc_last_error(void);
 int afqmc_version(void);

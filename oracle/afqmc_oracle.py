@@ -216,7 +216,7 @@ def overlap(ham, phi_a, phi_b):
 def full_green(phiT, phi):
     """G[z, p, q] = <Psi_T|a+_p a_q|phi_z>/<Psi_T|phi_z> = (phi S^-1 PhiT^T)_qp (Eq. halfgf, R11)."""
     theta, _ = theta_and_logdet(phiT, phi)
-    Gcal = np.einsum("zpj,qj->zpq", theta, phiT)     # phi S^-1 PhiT^T
+    Gcal = theta @ phiT.T                            # phi S^-1 PhiT^T
     return np.swapaxes(Gcal, 1, 2)
 
 
@@ -489,24 +489,17 @@ def msd_determinant(C, n, holes, parts):
     return D
 
 
-def _msd_terms(msd, phi_a, phi_b):
-    """Per determinant a: complex log of c_a <D_a|phi_z>, and the two spin Green's functions."""
-    W = phi_a.shape[0]
-    logs, greens = [], []
+def _msd_log_terms(msd, phi_a, phi_b):
+    """[ndet, W]: complex log of c_a <D_a|phi_z> = c_a det(D_a^aT phi^a) det(D_a^bT phi^b)."""
+    logs = []
     for ca, spins in zip(msd.coeff, msd.exc):
-        la = np.full(W, np.log(complex(ca)))
-        gs = []
+        la = np.full(phi_a.shape[0], np.log(complex(ca)))
         for s, phi in enumerate((phi_a, phi_b)):
             D = msd_determinant(msd.C[s], msd.nel[s], *spins[s])
-            if D.shape[1] == 0:
-                gs.append(np.zeros((W, phi.shape[1], phi.shape[1]), complex))
-                continue
-            _, ld = theta_and_logdet(D, phi)
-            la = la + ld
-            gs.append(full_green(D, phi))
+            if D.shape[1]:
+                la = la + log_det(D.T @ phi)   # det(D^T phi), Sec. III.A
         logs.append(la)
-        greens.append(gs)
-    return np.array(logs), greens
+    return np.array(logs)
 
 
 def msd_overlap(msd, phi_a, phi_b):
@@ -514,21 +507,23 @@ def msd_overlap(msd, phi_a, phi_b):
 
     The sum is taken relative to its largest |term| (exact up to rounding).
     """
-    logs, _ = _msd_terms(msd, phi_a, phi_b)
+    logs = _msd_log_terms(msd, phi_a, phi_b)
     m = np.max(logs.real, axis=0)
     return m + np.log(np.sum(np.exp(logs - m), axis=0))
 
 
 def msd_green(msd, phi_a, phi_b):
     """G[z, s, p, q] = <Psi_T|a+_ps a_qs|phi_z>/<Psi_T|phi_z> (R24), complex [W, 2, N, N]."""
-    logs, greens = _msd_terms(msd, phi_a, phi_b)
+    logs = _msd_log_terms(msd, phi_a, phi_b)
     m = np.max(logs.real, axis=0)
     w = np.exp(logs - m)                      # c_a O_a / e^m, [ndet, W]
     N = phi_a.shape[1]
     G = np.zeros((phi_a.shape[0], 2, N, N), complex)
-    for a in range(len(msd.coeff)):
-        for s in range(2):
-            G[:, s] += w[a][:, None, None] * greens[a][s]
+    for a, spins in enumerate(msd.exc):
+        for s, phi in enumerate((phi_a, phi_b)):
+            D = msd_determinant(msd.C[s], msd.nel[s], *spins[s])
+            if D.shape[1]:
+                G[:, s] += w[a][:, None, None] * full_green(D, phi)
     return G / np.sum(w, axis=0)[:, None, None, None]
 
 

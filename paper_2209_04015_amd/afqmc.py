@@ -15,7 +15,8 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["FP64", "FP32", "BF16X3", "FP16X3", "AfqmcError", "load", "Hamiltonian", "Walkers", "Batch", "LIB_PATH"]
+__all__ = ["FP64", "FP32", "BF16X3", "FP16X3", "AfqmcError", "load", "Hamiltonian", "Walkers", "Batch", "MSDTrial",
+           "LIB_PATH"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libafqmc.so")
 
@@ -26,6 +27,7 @@ FP16X3 = 3
 STEP_REUSE = 1
 # status-word bits (afqmc_get_status)
 STATUS_SINGULAR, STATUS_NONFINITE, STATUS_QR_ZERO, STATUS_NO_LIVE = 1, 2, 4, 8
+MSD_MAX_RANK = 6  # AFQMC_MSD_MAX_RANK
 EXCHANGE_AUTO, EXCHANGE_DIRECT, EXCHANGE_PAIR = 0, 1, 2
 _EXCHANGE = {"auto": EXCHANGE_AUTO, "direct": EXCHANGE_DIRECT, "pair": EXCHANGE_PAIR}
 _PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3,
@@ -54,6 +56,12 @@ EXPORTED = (
     "afqmc_batch_step",
     "afqmc_autotune",
     "afqmc_batch_destroy",
+    "afqmc_msd_create",
+    "afqmc_msd_overlap",
+    "afqmc_msd_green_function",
+    "afqmc_msd_get_strings",
+    "afqmc_msd_get_status",
+    "afqmc_msd_destroy",
     "afqmc_destroy",
     "afqmc_last_error",
     "afqmc_version",
@@ -136,6 +144,13 @@ def load(path: str = LIB_PATH):
     lib.afqmc_autotune.argtypes = [vp, ctypes.c_char_p]
     lib.afqmc_batch_destroy.argtypes = [vp]
     lib.afqmc_batch_destroy.restype = None
+    lib.afqmc_msd_create.argtypes = [ip, ip, ip, vp, vp, ip, vp, vp, vp, ip, vp, P(vp)]
+    lib.afqmc_msd_overlap.argtypes = [vp, P(_Walkers), ip, vp, vp]
+    lib.afqmc_msd_green_function.argtypes = [vp, P(_Walkers), ip, vp, vp]
+    lib.afqmc_msd_get_strings.argtypes = [vp, P(ip), P(ip)]
+    lib.afqmc_msd_get_status.argtypes = [vp, vp, P(ip)]
+    lib.afqmc_msd_destroy.argtypes = [vp]
+    lib.afqmc_msd_destroy.restype = None
     lib.afqmc_destroy.argtypes = [vp]
     lib.afqmc_destroy.restype = None
     lib.afqmc_last_error.argtypes = []
@@ -143,7 +158,7 @@ def load(path: str = LIB_PATH):
     lib.afqmc_version.argtypes = []
     for name in EXPORTED:
         f = getattr(lib, name)
-        if name not in ("afqmc_destroy", "afqmc_last_error", "afqmc_batch_destroy"):
+        if name not in ("afqmc_destroy", "afqmc_last_error", "afqmc_batch_destroy", "afqmc_msd_destroy"):
             f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -499,3 +514,77 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class MSDTrial:
+    """A multi-determinant trial handle (afqmc_msd_create): the overlap and
+    Green's function of walkers against sum_a c_a t_a |psi_0> (Sec. III.A).
+
+    C_a, C_b: [N, N] orthogonal orbitals (psi_0 = their first na / nb
+    columns); coeff [ndet]; rank [ndet, 2]; orbs [ndet, 2, 2, MSD_MAX_RANK]
+    (the format of ``inputs.msd_expansion``)."""
+
+    def __init__(self, C_a, C_b, na, nb, coeff, rank, orbs, *, max_walkers, stream=None):
+        lib = load()
+        C_a = np.asarray(C_a)
+        N = C_a.shape[0]
+        C_b = C_a if C_b is None else C_b
+        coeff = np.asarray(coeff)
+        ndet = coeff.shape[0]
+        self._ca = _host(C_a, (N, N), "C_a")
+        self._cb = _host(C_b, (N, N), "C_b")
+        self._coeff = _host(coeff, (ndet,), "coeff")
+        self._rank = np.ascontiguousarray(rank, dtype=np.int32)
+        self._orbs = np.ascontiguousarray(orbs, dtype=np.int32)
+        if self._rank.shape != (ndet, 2) or self._orbs.shape != (ndet, 2, 2, MSD_MAX_RANK):
+            raise ValueError("rank must be [ndet, 2] and orbs [ndet, 2, 2, MSD_MAX_RANK]")
+        self.N, self.na, self.nb, self.ndet = N, int(na), int(nb), ndet
+        self.max_walkers = int(max_walkers)
+        h = ctypes.c_void_p()
+        _check(lib.afqmc_msd_create(N, self.na, self.nb, self._ca.ctypes.data, self._cb.ctypes.data, ndet,
+                                    self._coeff.ctypes.data, self._rank.ctypes.data, self._orbs.ctypes.data,
+                                    self.max_walkers, _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(lib.afqmc_msd_get_strings(self._h, ctypes.byref(a), ctypes.byref(b)))
+        self.strings = (a.value, b.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.afqmc_msd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def overlap(self, w: Walkers, out=None, nw=None, stream=None):
+        """Device complex128 [nw]: log <Psi_T|phi_z>."""
+        import torch
+
+        nw = w.W if nw is None else int(nw)
+        if out is None:
+            out = torch.empty((nw,), dtype=torch.complex128, device=w.phi_a.device)
+        ptr = _dev(out, torch.complex128, (nw,), "log_ovlp")
+        s = w._struct(self, nw)
+        _check(_lib.afqmc_msd_overlap(self._h, ctypes.byref(s), nw, ptr, _stream_ptr(stream)))
+        return out
+
+    def green_function(self, w: Walkers, out=None, nw=None, stream=None):
+        """Device complex128 [nw, 2, N, N]: G^s_pq of every walker for this trial."""
+        import torch
+
+        nw = w.W if nw is None else int(nw)
+        if out is None:
+            out = torch.empty((nw, 2, self.N, self.N), dtype=torch.complex128, device=w.phi_a.device)
+        ptr = _dev(out, torch.complex128, (nw, 2, self.N, self.N), "G")
+        s = w._struct(self, nw)
+        _check(_lib.afqmc_msd_green_function(self._h, ctypes.byref(s), nw, ptr, _stream_ptr(stream)))
+        return out
+
+    def status(self, stream=None):
+        v = ctypes.c_int()
+        _check(_lib.afqmc_msd_get_status(self._h, _stream_ptr(stream), ctypes.byref(v)))
+        return v.value

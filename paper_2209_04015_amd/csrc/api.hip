@@ -1,12 +1,13 @@
 // C ABI of the walker-step library: argument checking, workspace ownership
 // and the kernel sequence of each call.  No arithmetic of the method runs on
-// the host; every step is a kernel from step_kernels.hip / setup_kernels.hip.
+// the host; every step is a kernel from the *_kernels.hip sources.
 
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <fstream>
 #include <map>
 #include <sstream>
@@ -122,7 +123,8 @@ struct afqmc_ham {
 
 namespace {
 
-int dalloc(afqmc_ham* h, void** p, size_t bytes) {
+template <class H>
+int dalloc(H* h, void** p, size_t bytes) {
   if (bytes == 0) bytes = 16;
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) return fail(AFQMC_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
@@ -132,8 +134,8 @@ int dalloc(afqmc_ham* h, void** p, size_t bytes) {
   return AFQMC_OK;
 }
 
-template <typename T>
-int dalloc_t(afqmc_ham* h, T** p, size_t count) {
+template <typename T, class H>
+int dalloc_t(H* h, T** p, size_t count) {
   return dalloc(h, reinterpret_cast<void**>(p), count * sizeof(T));
 }
 
@@ -1074,6 +1076,309 @@ void afqmc_destroy(afqmc_ham* h) {
   (void)hipDeviceSynchronize();
   free_all(h);
   delete h;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// multi-determinant trial (Sec. III.A, III.B; kernels in msd_kernels.hip)
+// ===========================================================================
+
+struct afqmc_msd {
+  int device = 0;
+  int max_walkers = 0;
+  int ndet = 0;
+  MsdDims m{};
+  StepDims d{};  // the sizes launch_gf reads (N, na, nb, nmax, ldN)
+  MsdTables t{};
+  double* hh0 = nullptr;  // zero one-body matrix: launch_gf's energy input, unused here
+  double* theta = nullptr;
+  double2* logdet = nullptr;
+  double2* yt = nullptr;
+  double2* sdet = nullptr;
+  double2* sadj = nullptr;
+  double2* uw = nullptr;
+  double2* ratio = nullptr;
+  double2* mt = nullptr;
+  double2* zocc = nullptr;
+  double2* q = nullptr;
+  int* status = nullptr;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+void msd_free(afqmc_msd* t) {
+  for (void* p : t->allocs) (void)hipFree(p);
+  t->allocs.clear();
+}
+
+template <typename T>
+int msd_upload(afqmc_msd* t, const T** dst, const std::vector<T>& v) {
+  T* p = nullptr;
+  int rc = dalloc_t(t, &p, v.size());
+  if (rc) return rc;
+  if (!v.empty()) HIP_TRY(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  *dst = p;
+  return AFQMC_OK;
+}
+
+// Groups the determinants by per-spin excitation string and builds the
+// device tables (layouts in kernels.h).
+int msd_build(afqmc_msd* t, const double* C[2], const double* coeff, const int* rank, const int* orbs) {
+  MsdDims& m = t->m;
+  const int N = m.N, ndet = t->ndet;
+  const int nel[2] = {m.na, m.nb};
+  std::map<std::vector<int>, int> sid[2];
+  std::vector<std::vector<int>> strs[2];
+  std::vector<int> dstr[2] = {std::vector<int>(ndet), std::vector<int>(ndet)};
+  std::vector<char> used(N);
+  for (int a = 0; a < ndet; ++a) {
+    for (int s = 0; s < 2; ++s) {
+      const int k = rank[a * 2 + s];
+      const int n = nel[s];
+      if (k < 0 || k > MSD_KMAX || k > n || k > N - n)
+        return fail(AFQMC_EINVAL, "determinant %d spin %d: rank %d outside [0, min(%d, n, N - n)]", a, s, k,
+                    MSD_KMAX);
+      std::vector<int> key(1 + 2 * k);
+      key[0] = k;
+      std::fill(used.begin(), used.end(), 0);
+      for (int x = 0; x < k; ++x) {
+        const int h = orbs[((a * 2 + s) * 2 + 0) * MSD_KMAX + x];
+        const int q = orbs[((a * 2 + s) * 2 + 1) * MSD_KMAX + x];
+        if (h < 0 || h >= n || q < n || q >= N || used[h] || used[q])
+          return fail(AFQMC_EINVAL, "determinant %d spin %d: invalid or repeated hole %d / particle %d", a, s,
+                      h, q);
+        used[h] = used[q] = 1;
+        key[1 + x] = h;
+        key[1 + k + x] = q;
+      }
+      auto it = sid[s].find(key);
+      if (it == sid[s].end()) {
+        it = sid[s].emplace(key, (int)strs[s].size()).first;
+        strs[s].push_back(key);
+      }
+      dstr[s][a] = it->second;
+    }
+  }
+  m.nstr[0] = (int)strs[0].size();
+  m.nstr[1] = (int)strs[1].size();
+  m.nstr_tot = m.nstr[0] + m.nstr[1];
+  // strings: rank, orbitals, adjugate offsets
+  std::vector<int> srank(m.nstr_tot), sorb((size_t)m.nstr_tot * 2 * MSD_KMAX, -1), saoff(m.nstr_tot);
+  long nadj = 0;
+  for (int s = 0, u = 0; s < 2; ++s) {
+    for (const auto& key : strs[s]) {
+      const int k = key[0];
+      srank[u] = k;
+      saoff[u] = (int)nadj;
+      for (int x = 0; x < k; ++x) {
+        sorb[((size_t)u * 2 + 0) * MSD_KMAX + x] = key[1 + x];
+        sorb[((size_t)u * 2 + 1) * MSD_KMAX + x] = key[1 + k + x] - nel[s];
+      }
+      nadj += (long)k * k;
+      ++u;
+    }
+  }
+  if (nadj > (1L << 30)) return fail(AFQMC_EUNSUPPORTED, "expansion too large (%ld adjugate entries)", nadj);
+  m.nadj_tot = (int)nadj;
+  // CSR over strings: the determinants of each string, in increasing a
+  std::vector<int> crow(m.nstr_tot + 1, 0), cstr(2 * (size_t)ndet);
+  std::vector<double> ccoef(2 * (size_t)ndet);
+  for (int a = 0; a < ndet; ++a) {
+    ++crow[dstr[0][a] + 1];
+    ++crow[m.nstr[0] + dstr[1][a] + 1];
+  }
+  for (int u = 0; u < m.nstr_tot; ++u) crow[u + 1] += crow[u];
+  {
+    std::vector<int> fill(crow.begin(), crow.end() - 1);
+    for (int a = 0; a < ndet; ++a) {
+      const int ua = dstr[0][a], ub = m.nstr[0] + dstr[1][a];
+      ccoef[fill[ua]] = coeff[a];
+      cstr[fill[ua]++] = ub;
+      ccoef[fill[ub]] = coeff[a];
+      cstr[fill[ub]++] = ua;
+    }
+  }
+  // CSR over the (spin, virtual a, hole j) entries of M: contributions in
+  // increasing string, then (m, l) order
+  const int nent0 = m.na * m.nv[0], nent = nent0 + m.nb * m.nv[1];
+  std::vector<std::vector<std::pair<int, int>>> ent(nent);
+  for (int u = 0; u < m.nstr_tot; ++u) {
+    const int s = u >= m.nstr[0] ? 1 : 0;
+    const int k = srank[u], n = nel[s];
+    for (int x = 0; x < k; ++x)      // hole slot m
+      for (int l = 0; l < k; ++l) {  // particle slot l
+        const int j = sorb[((size_t)u * 2 + 0) * MSD_KMAX + x];
+        const int av = sorb[((size_t)u * 2 + 1) * MSD_KMAX + l];
+        ent[(s ? nent0 : 0) + av * n + j].push_back({u, saoff[u] + x * k + l});
+      }
+  }
+  std::vector<int> erow(nent + 1, 0), estr, eoff;
+  for (int e = 0; e < nent; ++e) {
+    erow[e + 1] = erow[e] + (int)ent[e].size();
+    for (const auto& pr : ent[e]) {
+      estr.push_back(pr.first);
+      eoff.push_back(pr.second);
+    }
+  }
+  // orbitals
+  std::vector<double> cocc((size_t)2 * N * m.nmax, 0.0), cvirt((size_t)2 * N * m.ldv, 0.0);
+  for (int s = 0; s < 2; ++s)
+    for (int p = 0; p < N; ++p) {
+      for (int i = 0; i < nel[s]; ++i) cocc[((size_t)s * N + p) * m.nmax + i] = C[s][(size_t)p * N + i];
+      for (int a = 0; a < m.nv[s]; ++a) cvirt[((size_t)s * N + p) * m.ldv + a] = C[s][(size_t)p * N + nel[s] + a];
+    }
+  int rc;
+  MsdTables& tb = t->t;
+  if ((rc = msd_upload(t, &tb.cocc, cocc)) || (rc = msd_upload(t, &tb.cvirt, cvirt)) ||
+      (rc = msd_upload(t, &tb.srank, srank)) || (rc = msd_upload(t, &tb.sorb, sorb)) ||
+      (rc = msd_upload(t, &tb.saoff, saoff)) || (rc = msd_upload(t, &tb.crow, crow)) ||
+      (rc = msd_upload(t, &tb.ccoef, ccoef)) || (rc = msd_upload(t, &tb.cstr, cstr)) ||
+      (rc = msd_upload(t, &tb.erow, erow)) || (rc = msd_upload(t, &tb.estr, estr)) ||
+      (rc = msd_upload(t, &tb.eoff, eoff)))
+    return rc;
+  return AFQMC_OK;
+}
+
+int msd_workspace(afqmc_msd* t) {
+  const MsdDims& m = t->m;
+  const size_t W = (size_t)t->max_walkers;
+  int rc;
+  if ((rc = dalloc_t(t, &t->hh0, (size_t)2 * m.nmax * m.N))) return rc;
+  if ((rc = dalloc_t(t, &t->theta, W * 4 * m.nmax * m.ldN))) return rc;
+  if ((rc = dalloc_t(t, &t->logdet, W * 2))) return rc;
+  if ((rc = dalloc_t(t, &t->yt, W * 2 * m.nmax * m.ldv))) return rc;
+  if ((rc = dalloc_t(t, &t->sdet, W * m.nstr_tot))) return rc;
+  if ((rc = dalloc_t(t, &t->sadj, W * m.nadj_tot))) return rc;
+  if ((rc = dalloc_t(t, &t->uw, W * m.nstr_tot))) return rc;
+  if ((rc = dalloc_t(t, &t->ratio, W))) return rc;
+  if ((rc = dalloc_t(t, &t->mt, W * 2 * m.ldv * m.nmax))) return rc;
+  if ((rc = dalloc_t(t, &t->zocc, W * 2 * m.nmax * m.nmax))) return rc;
+  if ((rc = dalloc_t(t, &t->q, W * 2 * m.N * m.nmax))) return rc;
+  if ((rc = dalloc_t(t, &t->status, (size_t)1))) return rc;
+  return AFQMC_OK;
+}
+
+int msd_check(const afqmc_msd* t, const afqmc_walkers* w, int nw) {
+  if (!t) return fail(AFQMC_EINVAL, "null multi-determinant trial handle");
+  if (nw < 0 || nw > t->max_walkers)
+    return fail(AFQMC_EINVAL, "nw = %d outside [0, max_walkers = %d]", nw, t->max_walkers);
+  if (nw == 0) return AFQMC_OK;
+  if (!w) return fail(AFQMC_EINVAL, "null walkers");
+  if (!w->phi_a || (t->m.nb > 0 && !w->phi_b)) return fail(AFQMC_EINVAL, "null walker array");
+  return AFQMC_OK;
+}
+
+// reference theta and log det, then the string determinants and the overlap ratio
+int msd_ratio(afqmc_msd* t, const afqmc_walkers* w, int nw, hipStream_t s) {
+  HIP_TRY(hipSetDevice(t->device));
+  const double2* pb = (const double2*)(t->m.nb > 0 ? w->phi_b : w->phi_a);  // not read when nb = 0
+  HIP_TRY((launch_gf<double>(t->d, nw, (const double2*)w->phi_a, pb, t->t.cocc, t->hh0, t->theta, t->logdet,
+                             nullptr, t->status, s)));
+  HIP_TRY(launch_msd_ratio(t->m, nw, t->t, t->theta, t->yt, t->sdet, t->sadj, t->uw, t->ratio, s));
+  return AFQMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int afqmc_msd_create(int N, int na, int nb, const double* host_C_a, const double* host_C_b, int ndet,
+                     const double* host_coeff, const int* host_rank, const int* host_orbs, int max_walkers,
+                     void* stream, afqmc_msd** out) {
+  if (!out) return fail(AFQMC_EINVAL, "null output handle pointer");
+  *out = nullptr;
+  if (N < 1 || na < 1 || nb < 0 || na > N || nb > N)
+    return fail(AFQMC_EINVAL, "bad sizes N=%d na=%d nb=%d", N, na, nb);
+  if (na > 45 || nb > 45)
+    return fail(AFQMC_EUNSUPPORTED, "at most 45 electrons per spin are supported (got %d, %d)", na, nb);
+  if (ndet < 1 || ndet > (1 << 28)) return fail(AFQMC_EINVAL, "ndet = %d outside [1, 2^28]", ndet);
+  if (max_walkers < 1) return fail(AFQMC_EINVAL, "max_walkers must be >= 1");
+  if (!host_C_a || (nb > 0 && !host_C_b) || !host_coeff || !host_rank || !host_orbs)
+    return fail(AFQMC_EINVAL, "null input pointer");
+  afqmc_msd* t = new afqmc_msd();
+  int rc = AFQMC_OK;
+  if (hipGetDevice(&t->device) != hipSuccess) rc = fail(AFQMC_EHIP, "hipGetDevice failed");
+  t->max_walkers = max_walkers;
+  t->ndet = ndet;
+  MsdDims& m = t->m;
+  m.N = N;
+  m.na = na;
+  m.nb = nb;
+  m.nmax = na > nb ? na : nb;
+  m.ldN = (N + 15) / 16 * 16;
+  m.nv[0] = N - na;
+  m.nv[1] = N - nb;
+  m.ldv = ((m.nv[0] > m.nv[1] ? m.nv[0] : m.nv[1]) + 3) / 4 * 4;
+  if (m.ldv == 0) m.ldv = 4;
+  t->d.N = N;
+  t->d.na = na;
+  t->d.nb = nb;
+  t->d.nmax = m.nmax;
+  t->d.ldN = m.ldN;
+  const double* C[2] = {host_C_a, nb > 0 ? host_C_b : host_C_a};
+  if (!rc && set_kernel_attributes(t->d) != hipSuccess) rc = fail(AFQMC_EHIP, "kernel attribute setup failed");
+  if (!rc) rc = msd_build(t, C, host_coeff, host_rank, host_orbs);
+  if (!rc) rc = msd_workspace(t);
+  if (!rc && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = fail(AFQMC_EHIP, "stream sync failed");
+  if (rc) {
+    msd_free(t);
+    delete t;
+    return rc;
+  }
+  *out = t;
+  return AFQMC_OK;
+}
+
+int afqmc_msd_overlap(afqmc_msd* t, const afqmc_walkers* w, int nw, void* log_ovlp, void* stream) {
+  int rc = msd_check(t, w, nw);
+  if (rc || nw == 0) return rc;
+  if (!log_ovlp) return fail(AFQMC_EINVAL, "null log_ovlp");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = msd_ratio(t, w, nw, s))) return rc;
+  HIP_TRY(launch_msd_overlap_store(nw, t->logdet, t->ratio, (double2*)log_ovlp, t->status, s));
+  return AFQMC_OK;
+}
+
+int afqmc_msd_green_function(afqmc_msd* t, const afqmc_walkers* w, int nw, void* G, void* stream) {
+  int rc = msd_check(t, w, nw);
+  if (rc || nw == 0) return rc;
+  if (!G) return fail(AFQMC_EINVAL, "null G");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = msd_ratio(t, w, nw, s))) return rc;
+  HIP_TRY(launch_msd_green(t->m, nw, t->t, t->theta, t->yt, t->sadj, t->uw, t->ratio, t->mt, t->zocc, t->q,
+                           (double2*)G, s));
+  return AFQMC_OK;
+}
+
+int afqmc_msd_get_strings(afqmc_msd* t, int* nstr_a, int* nstr_b) {
+  if (!t) return fail(AFQMC_EINVAL, "null multi-determinant trial handle");
+  if (nstr_a) *nstr_a = t->m.nstr[0];
+  if (nstr_b) *nstr_b = t->m.nstr[1];
+  return AFQMC_OK;
+}
+
+int afqmc_msd_get_status(afqmc_msd* t, void* stream, int* out) {
+  if (!t || !out) return fail(AFQMC_EINVAL, "null argument");
+  HIP_TRY(hipSetDevice(t->device));
+  hipStream_t s = (hipStream_t)stream;
+  int v = 0;
+  HIP_TRY(hipMemcpyAsync(&v, t->status, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int zero = 0;
+  HIP_TRY(hipMemcpyAsync(t->status, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = v;
+  return AFQMC_OK;
+}
+
+void afqmc_msd_destroy(afqmc_msd* t) {
+  if (!t) return;
+  (void)hipSetDevice(t->device);
+  (void)hipDeviceSynchronize();
+  msd_free(t);
+  delete t;
 }
 
 }  // extern "C"

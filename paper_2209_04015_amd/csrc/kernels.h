@@ -171,3 +171,45 @@ hipError_t launch_exchange_pair_split(int mode, const StepDims& d, int W, const 
 template <typename T>
 hipError_t launch_exchange_pair(const StepDims& d, int W, const PairLaunch& pl, const T* v, const T* theta,
                                 double2* part, int sp, hipStream_t s, int gs = 0);
+
+// --- multi-determinant trial (msd_kernels.hip) ---------------------------------
+constexpr int MSD_KMAX = 6;  // excitation rank per spin (AFQMC_MSD_MAX_RANK)
+
+struct MsdDims {
+  int N, na, nb, nmax;
+  int ldN;       // orbital stride of theta (as StepDims::ldN)
+  int nv[2];     // virtual orbitals per spin, N - n_s
+  int ldv;       // virtual stride of Y, M and C_virt (>= max nv, multiple of 4)
+  int nstr[2];   // excitation strings per spin (concatenated: alpha, then beta)
+  int nstr_tot;
+  int nadj_tot;  // adjugate entries of all strings (sum of k^2)
+};
+
+// Device tables of one expansion.
+struct MsdTables {
+  const double* cocc;   // [2][N][nmax]  reference orbitals C_s[:, :n_s]
+  const double* cvirt;  // [2][N][ldv]   C_s[:, n_s:], zero-padded
+  const int* srank;     // [nstr_tot]    k of each string
+  const int* sorb;      // [nstr_tot][2][MSD_KMAX] holes; particles as virtual index q - n_s
+  const int* saoff;     // [nstr_tot]    first adjugate entry of the string
+  const int* crow;      // [nstr_tot + 1] CSR over strings: determinants with that string
+  const double* ccoef;  // [2 ndet]      c_a
+  const int* cstr;      // [2 ndet]      the determinant's string of the other spin (concatenated index)
+  const int* erow;      // [na nv_a + nb nv_b + 1] CSR over (spin, virtual a, hole j) entries of M
+  const int* estr;      // string of each contribution
+  const int* eoff;      // adjugate entry of each contribution
+};
+
+// theta [W][2][2][nmax][ldN] FP64 (launch_gf) -> Yt [W][2][nmax][ldv], string dets
+// sdet [W][nstr_tot], adjugates sadj [W][nadj_tot], string weights uw [W][nstr_tot],
+// overlap ratios ratio [W] relative to the reference determinant
+hipError_t launch_msd_ratio(const MsdDims& m, int W, const MsdTables& t, const double* theta, double2* yt,
+                            double2* sdet, double2* sadj, double2* uw, double2* ratio, hipStream_t s);
+// out [W] = logdet[z][0] + logdet[z][1] + log ratio[z]
+hipError_t launch_msd_overlap_store(int W, const double2* logdet, const double2* ratio, double2* out, int* status,
+                                    hipStream_t s);
+// after launch_msd_ratio: M -> mt [W][2][ldv][nmax], zocc [W][2][nmax][nmax], q [W][2][N][nmax],
+// G [W][2][N][N]
+hipError_t launch_msd_green(const MsdDims& m, int W, const MsdTables& t, const double* theta, const double2* yt,
+                            const double2* sadj, const double2* uw, const double2* ratio, double2* mt,
+                            double2* zocc, double2* q, double2* G, hipStream_t s);

@@ -1,0 +1,196 @@
+"""Parity of the multi-determinant trial calls (afqmc_msd_overlap,
+afqmc_msd_green_function) with the FP64 oracle, through the C ABI.
+
+The oracle sums the expansion determinant by determinant (the definition);
+the library goes through the generalised Wick's theorem (reference theta,
+Y = C_virt^T theta, per-string determinants and adjugates).  Both are FP64.
+
+Bar.  The two routes differ by rounding only.  The reference overlap matrix
+S_0 = C_occ^T phi is inverted on both sides, so theta_0 and Y carry a
+relative error of about u cond(S_0) (u = 2^-53); a string determinant of
+rank k (k <= 6) and its adjugate add at most a few k^2 u on top, and the
+expansion sums add one u per term relative to the sum of |terms|.  With
+cond(S_0) < 1e3 for these walkers (perturbations of 0.3 around psi_0) the
+relative error is below 1e-11 at every size here; the tests use 1e-9 of
+max |G| and 1e-9 in log |<Psi_T|phi>| (a relative error of the overlap),
+with the sum of |c_a O_a| / |sum c_a O_a| (the cancellation in the
+expansion, computed from the oracle's terms) as an extra factor.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import afqmc_oracle as orc
+from paper_2209_04015_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(N, na, nb, ndet, max_rank, W, seed=0, uhf=True, scale=0.3):
+    h1, _ = inputs.hamiltonian(N, 4, 3.0, seed=seed)
+    C_a = inputs.orbitals(h1)
+    C_b = inputs.orbitals(h1 + np.diag(np.linspace(0.0, 0.5, N))) if uhf else C_a
+    coeff, rank, orbs = inputs.msd_expansion(N, na, nb, ndet, max_rank=max_rank, seed=seed + 1)
+    pa = inputs.walkers_perturbed(C_a[:, :na], W, scale, seed=seed + 2, stream=0)
+    pb = inputs.walkers_perturbed(C_b[:, :nb], W, scale, seed=seed + 2, stream=1)
+    return C_a, C_b, coeff, rank, orbs, pa, pb
+
+
+def _run(C_a, C_b, na, nb, coeff, rank, orbs, pa, pb, max_walkers=None):
+    from paper_2209_04015_amd import afqmc
+
+    W = pa.shape[0]
+    t = afqmc.MSDTrial(C_a, C_b, na, nb, coeff, rank, orbs, max_walkers=max_walkers or W)
+    w = afqmc.Walkers.from_numpy(pa, pb, device="cuda")
+    lo = t.overlap(w).cpu().numpy()
+    G = t.green_function(w).cpu().numpy()
+    st = t.status()
+    return t, lo, G, st
+
+
+def _cancellation(msd, pa, pb):
+    """sum_a |c_a O_a| / |sum_a c_a O_a| per walker (1 without cancellation)."""
+    logs = orc._msd_log_terms(msd, pa, pb)
+    terms = np.exp(logs - logs.real.max(axis=0))
+    return np.abs(terms).sum(axis=0) / np.abs(terms.sum(axis=0))
+
+
+def _compare(msd, lo, G, pa, pb, rtol=1e-9):
+    ref_lo = orc.msd_overlap(msd, pa, pb)
+    ref_G = orc.msd_green(msd, pa, pb)
+    canc = _cancellation(msd, pa, pb)
+    d = np.exp(lo - ref_lo) - 1.0            # relative overlap error (phase mod 2 pi)
+    assert np.all(np.abs(d) <= rtol * canc), (np.abs(d).max(), canc.max())
+    scale = np.abs(ref_G).max(axis=(1, 2, 3))
+    err = np.abs(G - ref_G).max(axis=(1, 2, 3))
+    assert np.all(err <= rtol * canc * scale), (err / scale).max()
+
+
+CASES = [
+    # N, na, nb, ndet, max_rank, W, uhf
+    (12, 4, 3, 40, 3, 5, True),
+    (37, 9, 6, 300, 6, 37, True),       # ragged sizes, every rank up to 6
+    (20, 5, 5, 120, 4, 16, False),      # one orbital set for both spins
+    (64, 13, 11, 800, 4, 70, True),     # several workgroups of strings and walkers
+]
+
+
+@pytest.mark.parametrize("N,na,nb,ndet,max_rank,W,uhf", CASES)
+def test_msd_overlap_and_green_match_oracle(N, na, nb, ndet, max_rank, W, uhf):
+    print(f"[gpu] msd N={N} na={na} nb={nb} ndet={ndet} rank<={max_rank} W={W}", flush=True)
+    C_a, C_b, coeff, rank, orbs, pa, pb = _problem(N, na, nb, ndet, max_rank, W, uhf=uhf)
+    t, lo, G, st = _run(C_a, C_b, na, nb, coeff, rank, orbs, pa, pb)
+    assert st == 0
+    msd = orc.msd_setup(C_a, C_b, na, nb, coeff, rank, orbs)
+    _compare(msd, lo, G, pa, pb)
+    t.close()
+
+
+def test_msd_without_beta_electrons():
+    N, na, nb = 15, 4, 0
+    C_a, C_b, coeff, rank, orbs, pa, pb = _problem(N, na, nb, 30, 3, 6)
+    print("[gpu] msd nb=0", flush=True)
+    t, lo, G, st = _run(C_a, C_b, na, nb, coeff, rank, orbs, pa, pb)
+    assert st == 0 and np.all(G[:, 1] == 0)
+    _compare(orc.msd_setup(C_a, C_b, na, nb, coeff, rank, orbs), lo, G, pa, pb)
+    t.close()
+
+
+def test_msd_single_reference_is_the_single_determinant_trial():
+    N, na, nb, W = 30, 7, 5, 9
+    C_a, C_b, _, _, _, pa, pb = _problem(N, na, nb, 2, 1, W)
+    rank = np.zeros((1, 2), np.int32)
+    orbs = np.full((1, 2, 2, inputs.MSD_MAX_RANK), -1, np.int32)
+    print("[gpu] msd single reference", flush=True)
+    t, lo, G, st = _run(C_a, C_b, na, nb, np.array([1.0]), rank, orbs, pa, pb)
+    _, la = orc.theta_and_logdet(C_a[:, :na], pa)
+    _, lb = orc.theta_and_logdet(C_b[:, :nb], pb)
+    assert np.all(np.abs(np.exp(lo - la - lb) - 1) <= 1e-12)
+    for s, (C, n, phi) in enumerate(((C_a, na, pa), (C_b, nb, pb))):
+        ref = orc.full_green(C[:, :n], phi)
+        assert np.abs(G[:, s] - ref).max() <= 1e-12 * np.abs(ref).max()
+    t.close()
+
+
+def test_msd_results_are_deterministic_and_nw_prefix_matches():
+    C_a, C_b, coeff, rank, orbs, pa, pb = _problem(40, 8, 7, 400, 4, 33)
+    from paper_2209_04015_amd import afqmc
+
+    print("[gpu] msd determinism", flush=True)
+    t = afqmc.MSDTrial(C_a, C_b, 8, 7, coeff, rank, orbs, max_walkers=33)
+    w = afqmc.Walkers.from_numpy(pa, pb, device="cuda")
+    G1 = t.green_function(w).cpu().numpy()
+    l1 = t.overlap(w).cpu().numpy()
+    G2 = t.green_function(w).cpu().numpy()
+    l2 = t.overlap(w).cpu().numpy()
+    assert np.array_equal(G1, G2) and np.array_equal(l1, l2)
+    G3 = t.green_function(w, nw=10).cpu().numpy()       # smaller call on the same workspace
+    assert np.array_equal(G3, G1[:10])
+    t.close()
+
+
+def test_msd_singular_reference_sets_status():
+    """A walker with a zero orbital has a singular reference overlap matrix and a
+    zero overlap with every determinant: log overlap -inf, status bit set."""
+    from paper_2209_04015_amd import afqmc
+
+    N, na, nb = 14, 3, 3
+    C_a, C_b, coeff, rank, orbs, pa, pb = _problem(N, na, nb, 20, 2, 3)
+    pa = pa.copy()
+    pa[1, :, 0] = 0.0                               # exactly singular C_occ^T phi
+    print("[gpu] msd singular reference", flush=True)
+    t = afqmc.MSDTrial(C_a, C_b, na, nb, coeff, rank, orbs, max_walkers=3)
+    w = afqmc.Walkers.from_numpy(pa, pb, device="cuda")
+    lo = t.overlap(w).cpu().numpy()
+    assert t.status() & afqmc.STATUS_SINGULAR
+    assert lo[1].real == -np.inf and np.all(np.isfinite(lo[[0, 2]]))
+    assert t.status() == 0                          # cleared by the read
+    t.close()
+
+
+def test_msd_rejects_invalid_expansions():
+    from paper_2209_04015_amd import afqmc
+
+    N, na, nb = 10, 3, 2
+    C = inputs.orbitals(inputs.hamiltonian(N, 2, 3.0, seed=1)[0])
+    coeff, rank, orbs = inputs.msd_expansion(N, na, nb, 10, 2, seed=3)
+    bad = []
+    o = orbs.copy(); r = rank.copy(); r[4, 0] = 2; o[4, 0, 0, :2] = [1, 1]; o[4, 0, 1, :2] = [5, 6]
+    bad.append((r, o))                                   # repeated hole
+    o = orbs.copy(); r = rank.copy(); r[5, 1] = 1; o[5, 1, 0, 0] = 0; o[5, 1, 1, 0] = 1
+    bad.append((r, o))                                   # particle inside the reference
+    o = orbs.copy(); r = rank.copy(); r[2, 0] = 7
+    bad.append((r, o))                                   # rank above the maximum
+    o = orbs.copy(); r = rank.copy(); r[3, 1] = 1; o[3, 1, 0, 0] = 0; o[3, 1, 1, 0] = N
+    bad.append((r, o))                                   # particle outside the basis
+    for r, o in bad:
+        with pytest.raises(afqmc.AfqmcError) as e:
+            afqmc.MSDTrial(C, C, na, nb, coeff, r, o, max_walkers=2)
+        assert e.value.code == 1 and "determinant" in str(e.value)
+
+
+def test_msd_at_n290_shape_sampled():
+    """The 290-orbital, 26 + 26 electron shape with 512 walkers and 1000
+    determinants, all walkers in one launch; the oracle checks a sample."""
+    from paper_2209_04015_amd import afqmc
+    import torch
+
+    N, n, W, ndet = 290, 26, 512, 1000
+    h1, _ = inputs.hamiltonian(N, 4, 3.0, seed=4)
+    C = inputs.orbitals(h1)
+    coeff, rank, orbs = inputs.msd_expansion(N, n, n, ndet, max_rank=4, seed=5)
+    pa = inputs.walkers_perturbed(C[:, :n], W, 0.1, seed=6, stream=0)
+    pb = inputs.walkers_perturbed(C[:, :n], W, 0.1, seed=6, stream=1)
+    print("[gpu] msd n290 W=512 ndet=1000", flush=True)
+    t = afqmc.MSDTrial(C, C, n, n, coeff, rank, orbs, max_walkers=W)
+    w = afqmc.Walkers.from_numpy(pa, pb, device="cuda")
+    lo = t.overlap(w).cpu().numpy()
+    G = t.green_function(w)
+    torch.cuda.synchronize()
+    assert t.status() == 0
+    sample = [0, 511]
+    Gs = G[sample].cpu().numpy()
+    del G
+    msd = orc.msd_setup(C, C, n, n, coeff, rank, orbs)
+    _compare(msd, lo[sample], Gs, pa[sample], pb[sample])
+    t.close()
