@@ -135,6 +135,74 @@ def run_gpu(cfg, h1, L, phiT, precision, steps, warmup, fields_dev, block_fields
     return ham, w, e, ms, phases, status, extra, sample_state
 
 
+MSD_DETS = 10000
+
+
+def msd_flops_per_walker(N, n):
+    """Algorithmic FP64 flops per walker of the Green's function call beyond
+    the determinant sums: Y = C_virt^T theta (4 N nv n), M Y (8 n^2 nv),
+    Q (4 N n (n + nv)) and G = theta Q^T (8 N^2 n), per spin."""
+    nv = N - n
+    return 2 * (4 * N * nv * n + 8 * n * n * nv + 4 * N * n * (n + nv) + 8 * N * N * n)
+
+
+def run_msd(cfg, device, steps, ndet=MSD_DETS):
+    """Multi-determinant trial (Sec. III.A): overlap and Green's function of
+    every walker against a synthetic ndet-determinant expansion, timed over
+    `steps` calls each on the current stream."""
+    import torch
+
+    from paper_2209_04015_amd import afqmc, inputs
+
+    N, n, W = cfg.N, cfg.n, cfg.W
+    t = time.time()
+    h1, _ = inputs.hamiltonian(N, 4, 3.0, seed=4)
+    C = inputs.orbitals(h1)
+    coeff, rank, orbs = inputs.msd_expansion(N, n, n, ndet, max_rank=4, seed=5)
+    pa = inputs.walkers_perturbed(C[:, :n], W, 0.1, seed=6, stream=0)
+    pb = inputs.walkers_perturbed(C[:, :n], W, 0.1, seed=6, stream=1)
+    trial = afqmc.MSDTrial(C, C, n, n, coeff, rank, orbs, max_walkers=W)
+    w = afqmc.Walkers.from_numpy(pa, pb, device=device)
+    lo = torch.empty(W, dtype=torch.complex128, device=device)
+    G = torch.empty((W, 2, N, N), dtype=torch.complex128, device=device)
+    log(f"msd: {ndet} determinants, strings {trial.strings}, set up in {time.time() - t:.1f} s")
+    stream = torch.cuda.current_stream()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    trial.overlap(w, out=lo)
+    trial.green_function(w, out=G)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        trial.overlap(w, out=lo)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_o = start.elapsed_time(stop) / steps
+    start.record(stream)
+    for _ in range(steps):
+        trial.green_function(w, out=G)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_g = start.elapsed_time(stop) / steps
+    status = trial.status()
+    trial.close()
+    del G
+    torch.cuda.empty_cache()
+    log(f"msd: overlap {ms_o:.3f} ms, Green's function {ms_g:.3f} ms per call, status {status}")
+    gbytes = W * 2 * N * N * 16
+    return {"workload": f"multi-determinant trial: {ndet} determinants (ranks <= 4 per spin) of "
+                        f"{N} orbitals, na=nb={n}, {W} walkers, FP64",
+            "determinants": ndet, "strings_per_spin": list(trial.strings), "walkers": W,
+            "overlap": {"value": round(W * ndet / (ms_o * 1e-3), 1), "unit": "walker-determinants/s",
+                        "ms_per_call": round(ms_o, 4)},
+            "green_function": {"value": round(W * ndet / (ms_g * 1e-3), 1), "unit": "walker-determinants/s",
+                               "ms_per_call": round(ms_g, 4),
+                               "G_written_GB": round(gbytes / 1e9, 3),
+                               "G_write_bound_ms": round(gbytes / 8e12 * 1e3, 4),
+                               "dense_fp64_gflop": round(W * msd_flops_per_walker(N, n) / 1e9, 2)},
+            "status": status}
+
+
 # Sources that define each roofline kernel: its HBM traffic figure (from the
 # rocprofv3 counter summaries under profiles/) is used only while these are
 # unchanged since the counters were taken.
@@ -289,6 +357,9 @@ def main():
                     help="mixed path reported as value (the others are on the same line)")
     ap.add_argument("--exchange", choices=("auto", "direct", "pair"), default="auto",
                     help="exchange algorithm of the main paths (profiling runs)")
+    ap.add_argument("--msd-only", action="store_true",
+                    help="time the multi-determinant trial calls only (profiling runs)")
+    ap.add_argument("--msd-dets", type=int, default=MSD_DETS, help="determinants of the multi-determinant trial")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -321,6 +392,10 @@ def main():
         log(f"calibration copy: {args.calib_copy} MiB read + {args.calib_copy} MiB written")
         del src, dst
 
+    if args.msd_only:
+        print(json.dumps({"msd": run_msd(cfg, device, args.steps, args.msd_dets)}), flush=True)
+        return
+
     results = {}
     extras = {}
     states = {}
@@ -350,6 +425,8 @@ def main():
         ham.close()
         del w, e
         torch.cuda.empty_cache()
+
+    msd = None if args.only else run_msd(cfg, device, args.steps, args.msd_dets)
 
     if args.only:
         ms, ph, st = results[args.only]
@@ -424,6 +501,7 @@ def main():
         **extras[head],
         "phases_ms_per_step": phase_table(phh),
         "direct_exchange": direct,
+        "multi_determinant_trial": msd,
         "paths": paths,
         "algorithmic_gflop_per_walker_step": {k: round(v / 1e9, 4) for k, v in fl.items()},
         "status": sth,

@@ -1094,10 +1094,12 @@ struct afqmc_msd {
   double* hh0 = nullptr;  // zero one-body matrix: launch_gf's energy input, unused here
   double* theta = nullptr;
   double2* logdet = nullptr;
-  double2* yt = nullptr;
+  double* yp = nullptr;  // planar Y [W][2][2][nmax][ldv]
   double2* sdet = nullptr;
   double2* sadj = nullptr;
+  double2* tpart = nullptr;
   double2* uw = nullptr;
+  double2* rpart = nullptr;
   double2* ratio = nullptr;
   double2* mt = nullptr;
   double2* zocc = nullptr;
@@ -1161,9 +1163,34 @@ int msd_build(afqmc_msd* t, const double* C[2], const double* coeff, const int* 
       dstr[s][a] = it->second;
     }
   }
+  // sort each spin's strings by rank (stable): the waves of the string
+  // kernel then take one branch, and ranks above 4 form a tail
+  for (int s = 0; s < 2; ++s) {
+    std::vector<int> order(strs[s].size());
+    for (size_t u = 0; u < order.size(); ++u) order[u] = (int)u;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return strs[s][x][0] < strs[s][y][0]; });
+    std::vector<int> pos(order.size());
+    std::vector<std::vector<int>> sorted(order.size());
+    for (size_t u = 0; u < order.size(); ++u) {
+      pos[order[u]] = (int)u;
+      sorted[u] = strs[s][order[u]];
+    }
+    strs[s].swap(sorted);
+    for (int a = 0; a < ndet; ++a) dstr[s][a] = pos[dstr[s][a]];
+  }
   m.nstr[0] = (int)strs[0].size();
   m.nstr[1] = (int)strs[1].size();
   m.nstr_tot = m.nstr[0] + m.nstr[1];
+  for (int s = 0; s < 2; ++s) {
+    int first = m.nstr[s];
+    for (int u = 0; u < m.nstr[s]; ++u)
+      if (strs[s][u][0] > 4) {
+        first = u;
+        break;
+      }
+    m.big0[s] = (s ? m.nstr[0] : 0) + first;
+    m.nbig[s] = m.nstr[s] - first;
+  }
   // strings: rank, orbitals, adjugate offsets
   std::vector<int> srank(m.nstr_tot), sorb((size_t)m.nstr_tot * 2 * MSD_KMAX, -1), saoff(m.nstr_tot);
   long nadj = 0;
@@ -1200,6 +1227,15 @@ int msd_build(afqmc_msd* t, const double* C[2], const double* coeff, const int* 
       cstr[fill[ub]++] = ua;
     }
   }
+  // tasks: each string's CSR row cut into pieces of at most MSD_TASK entries
+  std::vector<int> tbeg, trow(m.nstr_tot + 1);
+  for (int u = 0; u < m.nstr_tot; ++u) {
+    trow[u] = (int)tbeg.size();
+    for (int e = crow[u]; e < crow[u + 1]; e += MSD_TASK) tbeg.push_back(e);
+  }
+  trow[m.nstr_tot] = (int)tbeg.size();
+  m.ntask = (int)tbeg.size();
+  tbeg.push_back(crow[m.nstr_tot]);  // every row is non-empty: task t ends at tbeg[t + 1]
   // CSR over the (spin, virtual a, hole j) entries of M: contributions in
   // increasing string, then (m, l) order
   const int nent0 = m.na * m.nv[0], nent = nent0 + m.nb * m.nv[1];
@@ -1235,6 +1271,7 @@ int msd_build(afqmc_msd* t, const double* C[2], const double* coeff, const int* 
       (rc = msd_upload(t, &tb.srank, srank)) || (rc = msd_upload(t, &tb.sorb, sorb)) ||
       (rc = msd_upload(t, &tb.saoff, saoff)) || (rc = msd_upload(t, &tb.crow, crow)) ||
       (rc = msd_upload(t, &tb.ccoef, ccoef)) || (rc = msd_upload(t, &tb.cstr, cstr)) ||
+      (rc = msd_upload(t, &tb.tbeg, tbeg)) || (rc = msd_upload(t, &tb.trow, trow)) ||
       (rc = msd_upload(t, &tb.erow, erow)) || (rc = msd_upload(t, &tb.estr, estr)) ||
       (rc = msd_upload(t, &tb.eoff, eoff)))
     return rc;
@@ -1248,10 +1285,12 @@ int msd_workspace(afqmc_msd* t) {
   if ((rc = dalloc_t(t, &t->hh0, (size_t)2 * m.nmax * m.N))) return rc;
   if ((rc = dalloc_t(t, &t->theta, W * 4 * m.nmax * m.ldN))) return rc;
   if ((rc = dalloc_t(t, &t->logdet, W * 2))) return rc;
-  if ((rc = dalloc_t(t, &t->yt, W * 2 * m.nmax * m.ldv))) return rc;
+  if ((rc = dalloc_t(t, &t->yp, W * 4 * m.nmax * m.ldv))) return rc;
   if ((rc = dalloc_t(t, &t->sdet, W * m.nstr_tot))) return rc;
   if ((rc = dalloc_t(t, &t->sadj, W * m.nadj_tot))) return rc;
+  if ((rc = dalloc_t(t, &t->tpart, W * m.ntask))) return rc;
   if ((rc = dalloc_t(t, &t->uw, W * m.nstr_tot))) return rc;
+  if ((rc = dalloc_t(t, &t->rpart, W * msd_combine_blocks(m)))) return rc;
   if ((rc = dalloc_t(t, &t->ratio, W))) return rc;
   if ((rc = dalloc_t(t, &t->mt, W * 2 * m.ldv * m.nmax))) return rc;
   if ((rc = dalloc_t(t, &t->zocc, W * 2 * m.nmax * m.nmax))) return rc;
@@ -1276,7 +1315,8 @@ int msd_ratio(afqmc_msd* t, const afqmc_walkers* w, int nw, hipStream_t s) {
   const double2* pb = (const double2*)(t->m.nb > 0 ? w->phi_b : w->phi_a);  // not read when nb = 0
   HIP_TRY((launch_gf<double>(t->d, nw, (const double2*)w->phi_a, pb, t->t.cocc, t->hh0, t->theta, t->logdet,
                              nullptr, t->status, s)));
-  HIP_TRY(launch_msd_ratio(t->m, nw, t->t, t->theta, t->yt, t->sdet, t->sadj, t->uw, t->ratio, s));
+  HIP_TRY(launch_msd_ratio(t->m, nw, t->t, t->theta, t->yp, t->sdet, t->sadj, t->tpart, t->uw, t->rpart,
+                           t->ratio, s));
   return AFQMC_OK;
 }
 
@@ -1347,7 +1387,7 @@ int afqmc_msd_green_function(afqmc_msd* t, const afqmc_walkers* w, int nw, void*
   if (!G) return fail(AFQMC_EINVAL, "null G");
   hipStream_t s = (hipStream_t)stream;
   if ((rc = msd_ratio(t, w, nw, s))) return rc;
-  HIP_TRY(launch_msd_green(t->m, nw, t->t, t->theta, t->yt, t->sadj, t->uw, t->ratio, t->mt, t->zocc, t->q,
+  HIP_TRY(launch_msd_green(t->m, nw, t->t, t->theta, t->yp, t->sadj, t->uw, t->ratio, t->mt, t->zocc, t->q,
                            (double2*)G, s));
   return AFQMC_OK;
 }

@@ -183,7 +183,11 @@ struct MsdDims {
   int nstr[2];   // excitation strings per spin (concatenated: alpha, then beta)
   int nstr_tot;
   int nadj_tot;  // adjugate entries of all strings (sum of k^2)
+  int big0[2];   // first string of rank > 4 of each spin (concatenated index; strings sorted by rank)
+  int nbig[2];   // strings of rank > 4 of each spin
+  int ntask;     // expansion-sum tasks (CSR rows cut into pieces of at most MSD_TASK entries)
 };
+constexpr int MSD_TASK = 16;
 
 // Device tables of one expansion.
 struct MsdTables {
@@ -195,21 +199,27 @@ struct MsdTables {
   const int* crow;      // [nstr_tot + 1] CSR over strings: determinants with that string
   const double* ccoef;  // [2 ndet]      c_a
   const int* cstr;      // [2 ndet]      the determinant's string of the other spin (concatenated index)
+  const int* tbeg;      // [ntask + 1]   first CSR entry of each task (tasks in string order)
+  const int* trow;      // [nstr_tot + 1] first task of each string
   const int* erow;      // [na nv_a + nb nv_b + 1] CSR over (spin, virtual a, hole j) entries of M
   const int* estr;      // string of each contribution
   const int* eoff;      // adjugate entry of each contribution
 };
 
-// theta [W][2][2][nmax][ldN] FP64 (launch_gf) -> Yt [W][2][nmax][ldv], string dets
+// workgroups of the expansion sums per walker (rpart holds W of these partials)
+int msd_combine_blocks(const MsdDims& m);
+// theta [W][2][2][nmax][ldN] FP64 (launch_gf) -> planar Y yp [W][2][2][nmax][ldv], string dets
 // sdet [W][nstr_tot], adjugates sadj [W][nadj_tot], string weights uw [W][nstr_tot],
+// task sums tpart [W][ntask], partial sums rpart [W][msd_combine_blocks],
 // overlap ratios ratio [W] relative to the reference determinant
-hipError_t launch_msd_ratio(const MsdDims& m, int W, const MsdTables& t, const double* theta, double2* yt,
-                            double2* sdet, double2* sadj, double2* uw, double2* ratio, hipStream_t s);
+hipError_t launch_msd_ratio(const MsdDims& m, int W, const MsdTables& t, const double* theta, double* yp,
+                            double2* sdet, double2* sadj, double2* tpart, double2* uw, double2* rpart,
+                            double2* ratio, hipStream_t s);
 // out [W] = logdet[z][0] + logdet[z][1] + log ratio[z]
 hipError_t launch_msd_overlap_store(int W, const double2* logdet, const double2* ratio, double2* out, int* status,
                                     hipStream_t s);
 // after launch_msd_ratio: M -> mt [W][2][ldv][nmax], zocc [W][2][nmax][nmax], q [W][2][N][nmax],
 // G [W][2][N][N]
-hipError_t launch_msd_green(const MsdDims& m, int W, const MsdTables& t, const double* theta, const double2* yt,
+hipError_t launch_msd_green(const MsdDims& m, int W, const MsdTables& t, const double* theta, const double* yp,
                             const double2* sadj, const double2* uw, const double2* ratio, double2* mt,
                             double2* zocc, double2* q, double2* G, hipStream_t s);

@@ -23,52 +23,178 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "mfma_tile.h"
 
 namespace {
 
-constexpr int Y_COLS = 256;  // virtual orbitals per workgroup (one per thread)
-constexpr int Y_ROWS = 8;    // occupied orbitals per thread
-constexpr int S_T = 64;      // strings per workgroup (per-thread LDS matrices)
 constexpr int KM = MSD_KMAX;
+constexpr int KREG = 4;      // strings of rank <= KREG: cofactors in registers
+constexpr int S_T = 64;      // strings per workgroup of the rank > KREG kernel (per-thread LDS)
+constexpr int C_T = 256;     // strings per workgroup of the expansion sums
 
 // ---------------------------------------------------------------------------
-// Y^s_z[i][a] = sum_p C_virt[p][a] theta_0[p][i]   (stored Yt[z][s][i][a])
+// Y^s_z[i][a] = sum_p theta_0[p][i] C_virt[p][a]: one FP64 MFMA GEMM per spin
+// over all walkers, A = the theta_0 rows (walker, re | im, i) with p
+// contiguous, B = C_virt (k-major, a contiguous).  Y is stored planar,
+// yp[z][re | im][s][i][ldv], like theta.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(Y_COLS) void msd_y_kernel(MsdDims m, int z0, const double* __restrict__ theta,
-                                                       const double* __restrict__ cvirt,
-                                                       double2* __restrict__ yt) {
-  const int ncb = (m.ldv + Y_COLS - 1) / Y_COLS;
-  const int cb = blockIdx.x % ncb, ib = blockIdx.x / ncb;
-  const int z = z0 + (int)(blockIdx.y >> 1), s = blockIdx.y & 1;
-  const int n = s ? m.nb : m.na, nv = m.nv[s];
-  const int i0 = ib * Y_ROWS;
-  const int a = cb * Y_COLS + threadIdx.x;
-  if (i0 >= n || a >= nv) return;
-  const size_t plane = (size_t)m.nmax * m.ldN;
-  const double* tre = theta + ((size_t)(z * 2 + 0) * 2 + s) * plane;
-  const double* tim = theta + ((size_t)(z * 2 + 1) * 2 + s) * plane;
-  const double* cv = cvirt + (size_t)s * m.N * m.ldv;
-  double2 acc[Y_ROWS];
-#pragma unroll
-  for (int r = 0; r < Y_ROWS; ++r) acc[r] = make_double2(0.0, 0.0);
-  for (int p = 0; p < m.N; ++p) {
-    const double c = cv[(size_t)p * m.ldv + a];
-#pragma unroll
-    for (int r = 0; r < Y_ROWS; ++r) {
-      const int i = i0 + r < n ? i0 + r : n - 1;  // clamped rows are not stored
-      acc[r].x = fma(c, tre[(size_t)i * m.ldN + p], acc[r].x);
-      acc[r].y = fma(c, tim[(size_t)i * m.ldN + p], acc[r].y);
-    }
+struct MsdYProb {
+  const double* theta;
+  const double* cv;  // C_virt of the spin, [N][ldv]
+  int rows;          // (walker, re | im, i) rows: 2 nz nmax
+  int z0, s, nmax, ldN, ldv;
+  __device__ double2 load_a(int, int r, int k) const {
+    if (r >= rows) return make_double2(0.0, 0.0);
+    const int zc = r / nmax, i = r - zc * nmax;  // zc = 2 (z - z0) + (re | im)
+    const size_t plane = (size_t)nmax * ldN;
+    return *reinterpret_cast<const double2*>(theta + ((size_t)(2 * z0 + zc) * 2 + s) * plane + (size_t)i * ldN + k);
   }
-  double2* out = yt + ((size_t)z * 2 + s) * m.nmax * m.ldv;
+  __device__ double2 load_b_km(int, int k, int a) const {
+    if (a >= ldv) return make_double2(0.0, 0.0);
+    return *reinterpret_cast<const double2*>(cv + (size_t)k * ldv + a);
+  }
+};
+
+constexpr int YBM = 64, YBN = 64, YBK = 16, YWM = 2, YWN = 2;
+
+__global__ __launch_bounds__(YWM* YWN * 64) void msd_y_kernel(MsdDims m, MsdYProb p, double* __restrict__ yp) {
+  __shared__ __attribute__((aligned(16))) double lds[TileLds<double, YBM, YBN, YBK>::ELEMS];
+  MF<double>::acc_t acc[YBM / YWM / 16][YBN / YWN / 16];
+  const int m0 = blockIdx.x * YBM, n0 = blockIdx.y * YBN;
+  mfma_tile_mainloop<double, YBM, YBN, YBK, YWM, YWN, true>(p, 0, m0, n0, m.N, acc, lds);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wm = wid / YWN, wn = wid % YWN;
+  const int nv = m.nv[p.s];
+  const size_t yplane = (size_t)m.nmax * m.ldv;
 #pragma unroll
-  for (int r = 0; r < Y_ROWS; ++r)
-    if (i0 + r < n) out[(size_t)(i0 + r) * m.ldv + a] = acc[r];
+  for (int i = 0; i < YBM / YWM / 16; ++i)
+#pragma unroll
+    for (int j = 0; j < YBN / YWN / 16; ++j) {
+      const int rb = m0 + wm * (YBM / YWM) + i * 16 + 4 * (lane >> 4);
+      const int a = n0 + wn * (YBN / YWN) + j * 16 + (lane & 15);
+      if (a >= nv) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rb + r;
+        if (row >= p.rows) continue;
+        const int zc = row / m.nmax, ii = row - zc * m.nmax;
+        yp[((size_t)(2 * p.z0 + zc) * 2 + p.s) * yplane + (size_t)ii * m.ldv + a] = acc[i][j][r];
+      }
+    }
+}
+
+// complex Y^s_z[i][a] from the planar store
+struct YView {
+  const double* re;
+  const double* im;
+  int ldv;
+  __device__ __forceinline__ double2 operator()(int i, int a) const {
+    const size_t o = (size_t)i * ldv + a;
+    return make_double2(re[o], im[o]);
+  }
+};
+__device__ __forceinline__ YView y_view(const MsdDims& m, const double* yp, int z, int s) {
+  const size_t yplane = (size_t)m.nmax * m.ldv;
+  return YView{yp + ((size_t)(2 * z + 0) * 2 + s) * yplane, yp + ((size_t)(2 * z + 1) * 2 + s) * yplane, m.ldv};
 }
 
 // ---------------------------------------------------------------------------
-// det and adjugate of one string's k x k matrix A (per-thread LDS storage)
+// det and adjugate of one string's k x k matrix A, A[l][c] = Y[q_l][h_c];
+// adj(A)[c][l] = (-1)^(l+c) det(A without row l, column c) is stored at
+// sadj[aoff + c k + l].
 // ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double2 cneg(double2 a) { return make_double2(-a.x, -a.y); }
+
+template <int K>
+struct SmallDet;
+template <>
+struct SmallDet<1> {
+  static __device__ __forceinline__ double2 det(const double2 (&a)[1][1]) { return a[0][0]; }
+};
+template <>
+struct SmallDet<2> {
+  static __device__ __forceinline__ double2 det(const double2 (&a)[2][2]) {
+    return csub(cmul(a[0][0], a[1][1]), cmul(a[0][1], a[1][0]));
+  }
+};
+template <>
+struct SmallDet<3> {
+  static __device__ __forceinline__ double2 det(const double2 (&a)[3][3]) {
+    const double2 c0 = csub(cmul(a[1][1], a[2][2]), cmul(a[1][2], a[2][1]));
+    const double2 c1 = csub(cmul(a[1][0], a[2][2]), cmul(a[1][2], a[2][0]));
+    const double2 c2 = csub(cmul(a[1][0], a[2][1]), cmul(a[1][1], a[2][0]));
+    return cadd(csub(cmul(a[0][0], c0), cmul(a[0][1], c1)), cmul(a[0][2], c2));
+  }
+};
+
+// Cofactors in registers (fully unrolled: every index is a constant).
+template <int K>
+__device__ __forceinline__ double2 det_adj_reg(const YView& Y, const int* holes, const int* parts,
+                                               double2* __restrict__ adj) {
+  double2 a[K][K];
+  int h[K], q[K];
+#pragma unroll
+  for (int x = 0; x < K; ++x) {
+    h[x] = holes[x];
+    q[x] = parts[x];
+  }
+#pragma unroll
+  for (int l = 0; l < K; ++l)
+#pragma unroll
+    for (int c = 0; c < K; ++c) a[l][c] = Y(h[c], q[l]);
+  if constexpr (K == 1) {
+    adj[0] = make_double2(1.0, 0.0);
+    return a[0][0];
+  } else {
+    double2 det = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int l = 0; l < K; ++l)
+#pragma unroll
+      for (int c = 0; c < K; ++c) {
+        double2 mi[K - 1][K - 1];
+#pragma unroll
+        for (int r = 0; r < K - 1; ++r)
+#pragma unroll
+          for (int x = 0; x < K - 1; ++x) mi[r][x] = a[r < l ? r : r + 1][x < c ? x : x + 1];
+        double2 cof = SmallDet<K - 1>::det(mi);
+        if ((l + c) & 1) cof = cneg(cof);
+        adj[c * K + l] = cof;
+        if (l == 0) det = cadd(det, cmul(a[0][c], cof));  // Laplace along row 0
+      }
+    return det;
+  }
+}
+
+// Strings of rank <= KREG, one thread per (walker, string).  The strings of
+// a spin are sorted by rank, so a wave takes one branch except at the few
+// rank boundaries.
+__global__ __launch_bounds__(256) void msd_strings_kernel(MsdDims m, int z0, const int* __restrict__ srank,
+                                                          const int* __restrict__ sorb,
+                                                          const int* __restrict__ saoff,
+                                                          const double* __restrict__ yp,
+                                                          double2* __restrict__ sdet,
+                                                          double2* __restrict__ sadj) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  const int z = z0 + (int)blockIdx.y;
+  if (u >= m.nstr_tot) return;
+  const int k = srank[u];
+  if (k > KREG) return;  // msd_strings_big_kernel
+  const int s = u >= m.nstr[0] ? 1 : 0;
+  const int* holes = sorb + (size_t)u * 2 * KM;
+  const int* parts = holes + KM;
+  const YView Y = y_view(m, yp, z, s);
+  double2* adj = sadj + (size_t)z * m.nadj_tot + saoff[u];
+  double2 det;
+  switch (k) {
+    case 1: det = det_adj_reg<1>(Y, holes, parts, adj); break;
+    case 2: det = det_adj_reg<2>(Y, holes, parts, adj); break;
+    case 3: det = det_adj_reg<3>(Y, holes, parts, adj); break;
+    case 4: det = det_adj_reg<4>(Y, holes, parts, adj); break;
+    default: det = make_double2(1.0, 0.0); break;  // the reference string
+  }
+  sdet[(size_t)z * m.nstr_tot + u] = det;
+}
 
 // Determinant of the k x k matrix in w (element e at w[e * S_T]) by Gaussian
 // elimination with partial pivoting; w is overwritten.
@@ -91,7 +217,7 @@ __device__ double2 det_in_place(double2* w, int k) {
         w[(c * k + x) * S_T] = w[(piv * k + x) * S_T];
         w[(piv * k + x) * S_T] = t;
       }
-      det = make_double2(-det.x, -det.y);
+      det = cneg(det);
     }
     const double2 pv = w[(c * k + c) * S_T];
     det = cmul(det, pv);
@@ -104,95 +230,106 @@ __device__ double2 det_in_place(double2* w, int k) {
   return det;
 }
 
-// One thread per (walker, string): A[l][m] = Y[q_l][h_m]; sdet = det A,
-// sadj[aoff + m k + l] = adj(A)[m][l] = (-1)^(l+m) det(A without row l, column m).
-__global__ __launch_bounds__(S_T) void msd_strings_kernel(MsdDims m, int z0, const int* __restrict__ srank,
-                                                          const int* __restrict__ sorb,
-                                                          const int* __restrict__ saoff,
-                                                          const double2* __restrict__ yt,
-                                                          double2* __restrict__ sdet,
-                                                          double2* __restrict__ sadj) {
+// Strings of rank KREG + 1 .. MSD_KMAX (the last ones of each spin after the
+// sort): minors by pivoted elimination in per-thread LDS slots.
+__global__ __launch_bounds__(S_T) void msd_strings_big_kernel(MsdDims m, int z0, const int* __restrict__ srank,
+                                                              const int* __restrict__ sorb,
+                                                              const int* __restrict__ saoff,
+                                                              const double* __restrict__ yp,
+                                                              double2* __restrict__ sdet,
+                                                              double2* __restrict__ sadj) {
   // A and one minor per thread: (36 + 25) x 64 x 16 B = 62.5 KB
   __shared__ double2 lds_a[KM * KM * S_T];
   __shared__ double2 lds_w[(KM - 1) * (KM - 1) * S_T];
   const int lane = threadIdx.x;
-  const int u = blockIdx.x * S_T + lane;
-  const int z = z0 + (int)blockIdx.y;
-  if (u >= m.nstr_tot) return;  // no barrier below: every thread works on its own LDS slots
-  const int s = u >= m.nstr[0] ? 1 : 0;
+  const int z = z0 + (int)(blockIdx.y >> 1), s = blockIdx.y & 1;
+  const int loc = blockIdx.x * S_T + lane;
+  if (loc >= m.nbig[s]) return;  // no barrier below: every thread works on its own LDS slots
+  const int u = m.big0[s] + loc;
   const int k = srank[u];
   const int* holes = sorb + (size_t)u * 2 * KM;
   const int* parts = holes + KM;
-  const double2* Y = yt + ((size_t)z * 2 + s) * m.nmax * m.ldv;
+  const YView Y = y_view(m, yp, z, s);
   double2* A = lds_a + lane;
   double2* Wk = lds_w + lane;
   for (int l = 0; l < k; ++l)
-    for (int c = 0; c < k; ++c) A[(l * k + c) * S_T] = Y[(size_t)holes[c] * m.ldv + parts[l]];
+    for (int c = 0; c < k; ++c) A[(l * k + c) * S_T] = Y(holes[c], parts[l]);
   double2* adj = sadj + (size_t)z * m.nadj_tot + saoff[u];
-  double2 det;
-  if (k == 0) {
-    det = make_double2(1.0, 0.0);
-  } else if (k == 1) {
-    det = A[0];
-    adj[0] = make_double2(1.0, 0.0);
-  } else if (k == 2) {
-    const double2 a00 = A[0], a01 = A[S_T], a10 = A[2 * S_T], a11 = A[3 * S_T];
-    det = csub(cmul(a00, a11), cmul(a01, a10));
-    adj[0] = a11;                                     // [m=0][l=0]
-    adj[1] = make_double2(-a01.x, -a01.y);            // [0][1]
-    adj[2] = make_double2(-a10.x, -a10.y);            // [1][0]
-    adj[3] = a00;                                     // [1][1]
-  } else {
-    const int k1 = k - 1;
-    for (int l = 0; l < k; ++l) {
-      for (int c = 0; c < k; ++c) {
-        int e = 0;
-        for (int r = 0; r < k; ++r) {
-          if (r == l) continue;
-          for (int x = 0; x < k; ++x) {
-            if (x == c) continue;
-            Wk[e * S_T] = A[(r * k + x) * S_T];
-            ++e;
-          }
+  const int k1 = k - 1;
+  for (int l = 0; l < k; ++l) {
+    for (int c = 0; c < k; ++c) {
+      int e = 0;
+      for (int r = 0; r < k; ++r) {
+        if (r == l) continue;
+        for (int x = 0; x < k; ++x) {
+          if (x == c) continue;
+          Wk[e * S_T] = A[(r * k + x) * S_T];
+          ++e;
         }
-        double2 minor = det_in_place(Wk, k1);
-        if ((l + c) & 1) minor = make_double2(-minor.x, -minor.y);
-        adj[c * k + l] = minor;
       }
+      double2 minor = det_in_place(Wk, k1);
+      if ((l + c) & 1) minor = cneg(minor);
+      adj[c * k + l] = minor;
     }
-    det = det_in_place(A, k);  // last: A is not needed afterwards
   }
-  sdet[(size_t)z * m.nstr_tot + u] = det;
+  sdet[(size_t)z * m.nstr_tot + u] = det_in_place(A, k);  // last: A is not needed afterwards
 }
 
 // ---------------------------------------------------------------------------
-// Expansion sums per walker (one workgroup): for a string u of spin s,
+// Expansion sums: for a string u of spin s,
 //   uw[u] = sum over determinants a with that string of c_a det A^{other}_a
-// (CSR rows in increasing a), and s_z = sum_{alpha strings} det A_u uw[u].
+// (CSR rows in increasing a).  A row can hold thousands of determinants (the
+// reference string pairs with every excitation of the other spin), so rows
+// are cut into tasks of at most MSD_TASK entries: msd_task_kernel sums each
+// task, msd_combine_kernel adds a string's tasks in order and writes the
+// workgroup's partial sum of det A_u uw[u] over its alpha strings;
+// msd_ratio_kernel adds the partials of a walker in workgroup order.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void msd_combine_kernel(MsdDims m, int z0, const int* __restrict__ crow,
-                                                          const double* __restrict__ ccoef,
-                                                          const int* __restrict__ cstr,
+__global__ __launch_bounds__(256) void msd_task_kernel(MsdDims m, int z0, const int* __restrict__ tbeg,
+                                                       const double* __restrict__ ccoef,
+                                                       const int* __restrict__ cstr,
+                                                       const double2* __restrict__ sdet,
+                                                       double2* __restrict__ tpart) {
+  const int z = z0 + (int)blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m.ntask) return;
+  const double2* dz = sdet + (size_t)z * m.nstr_tot;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int e = tbeg[t]; e < tbeg[t + 1]; ++e) {
+    const double2 d = dz[cstr[e]];
+    acc.x = fma(ccoef[e], d.x, acc.x);
+    acc.y = fma(ccoef[e], d.y, acc.y);
+  }
+  tpart[(size_t)z * m.ntask + t] = acc;
+}
+
+__global__ __launch_bounds__(C_T) void msd_combine_kernel(MsdDims m, int z0, const int* __restrict__ trow,
+                                                          const double2* __restrict__ tpart,
                                                           const double2* __restrict__ sdet,
                                                           double2* __restrict__ uw,
-                                                          double2* __restrict__ ratio) {
-  __shared__ double2 red[8];
-  const int z = z0 + (int)blockIdx.x;
-  const double2* dz = sdet + (size_t)z * m.nstr_tot;
-  double2* uz = uw + (size_t)z * m.nstr_tot;
+                                                          double2* __restrict__ rpart) {
+  __shared__ double2 red[C_T / 64];
+  const int z = z0 + (int)blockIdx.y;
+  const int u = blockIdx.x * C_T + threadIdx.x;
   double2 part = make_double2(0.0, 0.0);
-  for (int u = threadIdx.x; u < m.nstr_tot; u += blockDim.x) {
+  if (u < m.nstr_tot) {
+    const double2* tz = tpart + (size_t)z * m.ntask;
     double2 acc = make_double2(0.0, 0.0);
-    for (int e = crow[u]; e < crow[u + 1]; ++e) {
-      const double2 d = dz[cstr[e]];
-      acc.x = fma(ccoef[e], d.x, acc.x);
-      acc.y = fma(ccoef[e], d.y, acc.y);
-    }
-    uz[u] = acc;
-    if (u < m.nstr[0]) part = cadd(part, cmul(dz[u], acc));
+    for (int t = trow[u]; t < trow[u + 1]; ++t) acc = cadd(acc, tz[t]);
+    uw[(size_t)z * m.nstr_tot + u] = acc;
+    if (u < m.nstr[0]) part = cmul(sdet[(size_t)z * m.nstr_tot + u], acc);
   }
   const double2 tot = block_sum2(part, red);
-  if (threadIdx.x == 0) ratio[z] = tot;
+  if (threadIdx.x == 0) rpart[(size_t)z * gridDim.x + blockIdx.x] = tot;
+}
+
+__global__ void msd_ratio_kernel(int z0, int nz, int nblk, const double2* __restrict__ rpart,
+                                 double2* __restrict__ ratio) {
+  const int z = z0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (z >= z0 + nz) return;
+  double2 t = make_double2(0.0, 0.0);
+  for (int b = 0; b < nblk; ++b) t = cadd(t, rpart[(size_t)z * nblk + b]);
+  ratio[z] = t;
 }
 
 // ---------------------------------------------------------------------------
@@ -221,84 +358,122 @@ __global__ __launch_bounds__(256) void msd_m_kernel(MsdDims m, int z0, const int
 // Zocc[j][i] = delta_ji - (sum_a M[j][a] Y[a][i]) / s_z   (one workgroup per (walker, spin))
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void msd_zocc_kernel(MsdDims m, int z0, const double2* __restrict__ mt,
-                                                       const double2* __restrict__ yt,
+                                                       const double* __restrict__ yp,
                                                        const double2* __restrict__ ratio,
                                                        double2* __restrict__ zocc) {
   const int z = z0 + (int)(blockIdx.x >> 1), s = blockIdx.x & 1;
   const int n = s ? m.nb : m.na, nv = m.nv[s];
   const double2 is = cinv(ratio[z]);
   const double2* M = mt + ((size_t)z * 2 + s) * m.ldv * m.nmax;
-  const double2* Y = yt + ((size_t)z * 2 + s) * m.nmax * m.ldv;
+  const YView Y = y_view(m, yp, z, s);
   double2* Z = zocc + ((size_t)z * 2 + s) * m.nmax * m.nmax;
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
     const int i = e / n, j = e - i * n;
     double2 acc = make_double2(0.0, 0.0);
-    for (int a = 0; a < nv; ++a) acc = cadd(acc, cmul(M[(size_t)a * m.nmax + j], Y[(size_t)i * m.ldv + a]));
+    for (int a = 0; a < nv; ++a) acc = cadd(acc, cmul(M[(size_t)a * m.nmax + j], Y(i, a)));
     const double2 t = cmul(acc, is);
     Z[(size_t)j * m.nmax + i] = make_double2((i == j ? 1.0 : 0.0) - t.x, -t.y);
   }
 }
 
 // ---------------------------------------------------------------------------
-// Q[p][j] = sum_i C_occ[p][i] Zocc[j][i] + (sum_a C_virt[p][a] M[j][a]) / s_z
+// Q[p][j] = sum_x C[p][x] Zt[j][x],  Zt[j][i] = Zocc[j][i] (i < n),
+// Zt[j][n + a] = M[j][a] / s_z.  One wave per (walker, spin, row block);
+// lane = (row group g, j) with 32 lanes per group when n <= 32 (two groups of
+// QR rows per wave), else 64; chunks of C rows are staged in LDS and read as
+// broadcasts.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void msd_q_kernel(MsdDims m, int z0, const double* __restrict__ cocc,
-                                                    const double* __restrict__ cvirt,
-                                                    const double2* __restrict__ zocc,
-                                                    const double2* __restrict__ mt,
-                                                    const double2* __restrict__ ratio,
-                                                    double2* __restrict__ q) {
+constexpr int QR = 16, QX = 64;
+
+__host__ __device__ inline int q_lanes(int nmax) { return nmax <= 32 ? 32 : 64; }
+
+__global__ __launch_bounds__(64) void msd_q_kernel(MsdDims m, int z0, const double* __restrict__ cocc,
+                                                   const double* __restrict__ cvirt,
+                                                   const double2* __restrict__ zocc,
+                                                   const double2* __restrict__ mt,
+                                                   const double2* __restrict__ ratio,
+                                                   double2* __restrict__ q) {
+  __shared__ double cs[2 * QR * QX];
   const int z = z0 + (int)(blockIdx.y >> 1), s = blockIdx.y & 1;
-  const int n = s ? m.nb : m.na, nv = m.nv[s];
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m.N * n) return;
-  const int p = e / n, j = e - p * n;
-  const double* co = cocc + (size_t)s * m.N * m.nmax + (size_t)p * m.nmax;
-  const double* cv = cvirt + (size_t)s * m.N * m.ldv + (size_t)p * m.ldv;
-  const double2* Z = zocc + ((size_t)z * 2 + s) * m.nmax * m.nmax + (size_t)j * m.nmax;
-  const double2* M = mt + ((size_t)z * 2 + s) * m.ldv * m.nmax + j;
-  double2 occ = make_double2(0.0, 0.0), vir = make_double2(0.0, 0.0);
-  for (int i = 0; i < n; ++i) {
-    occ.x = fma(co[i], Z[i].x, occ.x);
-    occ.y = fma(co[i], Z[i].y, occ.y);
+  const int n = s ? m.nb : m.na;
+  if (n == 0) return;  // uniform
+  const int N = m.N;
+  const int jw = q_lanes(m.nmax), groups = 64 / jw;
+  const int lane = threadIdx.x;
+  const int g = lane / jw, j = lane - g * jw;
+  const int pb0 = blockIdx.x * QR * groups;  // first row of the workgroup
+  const int p0 = pb0 + g * QR;               // first row of this lane's group
+  const int jc = j < n ? j : 0;              // lanes past n are not stored
+  const double2 is = cinv(ratio[z]);
+  const double* co = cocc + (size_t)s * N * m.nmax;
+  const double* cv = cvirt + (size_t)s * N * m.ldv;
+  const double2* Z = zocc + ((size_t)z * 2 + s) * m.nmax * m.nmax + (size_t)jc * m.nmax;
+  const double2* M = mt + ((size_t)z * 2 + s) * m.ldv * m.nmax + jc;
+  double2 acc[QR];
+#pragma unroll
+  for (int r = 0; r < QR; ++r) acc[r] = make_double2(0.0, 0.0);
+  const double* cg = cs + g * QR * QX;
+  for (int x0 = 0; x0 < N; x0 += QX) {
+    __syncthreads();
+    for (int e = lane; e < groups * QR * QX; e += 64) {
+      const int r = e / QX, xx = e - r * QX;
+      const int p = pb0 + r, x = x0 + xx;
+      double c = 0.0;
+      if (p < N && x < N) c = x < n ? co[(size_t)p * m.nmax + x] : cv[(size_t)p * m.ldv + (x - n)];
+      cs[e] = c;
+    }
+    __syncthreads();
+    const int nx = N - x0 < QX ? N - x0 : QX;
+    for (int xx = 0; xx < nx; ++xx) {
+      const int x = x0 + xx;
+      const double2 zv = x < n ? Z[x] : cmul(M[(size_t)(x - n) * m.nmax], is);
+#pragma unroll
+      for (int r = 0; r < QR; ++r) {
+        const double c = cg[r * QX + xx];
+        acc[r].x = fma(c, zv.x, acc[r].x);
+        acc[r].y = fma(c, zv.y, acc[r].y);
+      }
+    }
   }
-  for (int a = 0; a < nv; ++a) {
-    const double2 v = M[(size_t)a * m.nmax];
-    vir.x = fma(cv[a], v.x, vir.x);
-    vir.y = fma(cv[a], v.y, vir.y);
-  }
-  q[(((size_t)z * 2 + s) * m.N + p) * m.nmax + j] = cadd(occ, cmul(vir, cinv(ratio[z])));
+  if (j >= n) return;
+#pragma unroll
+  for (int r = 0; r < QR; ++r)
+    if (p0 + r < N) q[(((size_t)z * 2 + s) * N + p0 + r) * m.nmax + j] = acc[r];
 }
 
 // ---------------------------------------------------------------------------
-// G[z][s][p][q] = sum_j theta_0[q][j] Q[p][j]
+// G[z][s][p][q] = sum_j theta_0[q][j] Q[p][j]; the G_ROWS rows of Q a
+// workgroup needs are staged in LDS.
 // ---------------------------------------------------------------------------
-constexpr int G_ROWS = 16, G_COLS = 256;
+constexpr int G_ROWS = 16, G_COLS = 64, G_LDJ = 48;  // G_LDJ >= 45 electrons
 
 __global__ __launch_bounds__(G_COLS) void msd_green_kernel(MsdDims m, int z0, const double* __restrict__ theta,
                                                            const double2* __restrict__ q,
                                                            double2* __restrict__ G) {
+  __shared__ double2 qs[G_ROWS * G_LDJ];
   const int nqb = (m.N + G_COLS - 1) / G_COLS;
   const int qb = blockIdx.x % nqb, pb = blockIdx.x / nqb;
   const int z = z0 + (int)(blockIdx.y >> 1), s = blockIdx.y & 1;
   const int n = s ? m.nb : m.na;
-  const int c = qb * G_COLS + threadIdx.x;
   const int p0 = pb * G_ROWS;
+  const double2* Q = q + ((size_t)z * 2 + s) * m.N * m.nmax;
+  for (int e = threadIdx.x; e < G_ROWS * n; e += G_COLS) {
+    const int r = e / n, j = e - r * n;
+    qs[r * G_LDJ + j] = p0 + r < m.N ? Q[(size_t)(p0 + r) * m.nmax + j] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const int c = qb * G_COLS + threadIdx.x;
   if (c >= m.N) return;
   const size_t plane = (size_t)m.nmax * m.ldN;
   const double* tre = theta + ((size_t)(z * 2 + 0) * 2 + s) * plane;
   const double* tim = theta + ((size_t)(z * 2 + 1) * 2 + s) * plane;
-  const double2* Q = q + ((size_t)z * 2 + s) * m.N * m.nmax;
   double2 acc[G_ROWS];
 #pragma unroll
   for (int r = 0; r < G_ROWS; ++r) acc[r] = make_double2(0.0, 0.0);
   for (int j = 0; j < n; ++j) {
     const double2 t = make_double2(tre[(size_t)j * m.ldN + c], tim[(size_t)j * m.ldN + c]);
 #pragma unroll
-    for (int r = 0; r < G_ROWS; ++r) {
-      const int p = p0 + r < m.N ? p0 + r : m.N - 1;  // clamped rows are not stored
-      acc[r] = cadd(acc[r], cmul(Q[(size_t)p * m.nmax + j], t));
-    }
+    for (int r = 0; r < G_ROWS; ++r) acc[r] = cadd(acc[r], cmul(qs[r * G_LDJ + j], t));
   }
   double2* out = G + ((size_t)z * 2 + s) * m.N * m.N;
 #pragma unroll
@@ -326,19 +501,37 @@ constexpr int ZCHUNK = 16384;  // walkers per launch (grid y <= 2 per walker)
 
 }  // namespace
 
-hipError_t launch_msd_ratio(const MsdDims& m, int W, const MsdTables& t, const double* theta, double2* yt,
-                            double2* sdet, double2* sadj, double2* uw, double2* ratio, hipStream_t s) {
+int msd_combine_blocks(const MsdDims& m) { return (m.nstr_tot + C_T - 1) / C_T; }
+
+hipError_t launch_msd_ratio(const MsdDims& m, int W, const MsdTables& t, const double* theta, double* yp,
+                            double2* sdet, double2* sadj, double2* tpart, double2* uw, double2* rpart,
+                            double2* ratio, hipStream_t s) {
+  const int nblk = msd_combine_blocks(m);
   for (int z0 = 0; z0 < W; z0 += ZCHUNK) {
     const int nz = W - z0 < ZCHUNK ? W - z0 : ZCHUNK;
-    const int ncb = (m.ldv + Y_COLS - 1) / Y_COLS, nib = (m.nmax + Y_ROWS - 1) / Y_ROWS;
-    hipLaunchKernelGGL(msd_y_kernel, dim3(ncb * nib, 2 * nz), dim3(Y_COLS), 0, s, m, z0, theta, t.cvirt, yt);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(msd_strings_kernel, dim3((m.nstr_tot + S_T - 1) / S_T, nz), dim3(S_T), 0, s, m, z0,
-                       t.srank, t.sorb, t.saoff, yt, sdet, sadj);
+    hipError_t e;
+    for (int sp = 0; sp < 2; ++sp) {
+      if ((sp ? m.nb : m.na) == 0 || m.nv[sp] == 0) continue;
+      MsdYProb p{theta, t.cvirt + (size_t)sp * m.N * m.ldv, 2 * nz * m.nmax, z0, sp, m.nmax, m.ldN, m.ldv};
+      const dim3 grid((p.rows + YBM - 1) / YBM, (m.nv[sp] + YBN - 1) / YBN);
+      hipLaunchKernelGGL(msd_y_kernel, grid, dim3(YWM * YWN * 64), 0, s, m, p, yp);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(msd_strings_kernel, dim3((m.nstr_tot + 255) / 256, nz), dim3(256), 0, s, m, z0, t.srank,
+                       t.sorb, t.saoff, yp, sdet, sadj);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(msd_combine_kernel, dim3(nz), dim3(256), 0, s, m, z0, t.crow, t.ccoef, t.cstr, sdet, uw,
-                       ratio);
+    const int nbig = m.nbig[0] > m.nbig[1] ? m.nbig[0] : m.nbig[1];
+    if (nbig > 0) {
+      hipLaunchKernelGGL(msd_strings_big_kernel, dim3((nbig + S_T - 1) / S_T, 2 * nz), dim3(S_T), 0, s, m, z0,
+                         t.srank, t.sorb, t.saoff, yp, sdet, sadj);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(msd_task_kernel, dim3((m.ntask + 255) / 256, nz), dim3(256), 0, s, m, z0, t.tbeg, t.ccoef,
+                       t.cstr, sdet, tpart);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(msd_combine_kernel, dim3(nblk, nz), dim3(C_T), 0, s, m, z0, t.trow, tpart, sdet, uw, rpart);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(msd_ratio_kernel, dim3((nz + 255) / 256), dim3(256), 0, s, z0, nz, nblk, rpart, ratio);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -350,7 +543,7 @@ hipError_t launch_msd_overlap_store(int W, const double2* logdet, const double2*
   return hipGetLastError();
 }
 
-hipError_t launch_msd_green(const MsdDims& m, int W, const MsdTables& t, const double* theta, const double2* yt,
+hipError_t launch_msd_green(const MsdDims& m, int W, const MsdTables& t, const double* theta, const double* yp,
                             const double2* sadj, const double2* uw, const double2* ratio, double2* mt,
                             double2* zocc, double2* q, double2* G, hipStream_t s) {
   for (int z0 = 0; z0 < W; z0 += ZCHUNK) {
@@ -360,9 +553,10 @@ hipError_t launch_msd_green(const MsdDims& m, int W, const MsdTables& t, const d
                        t.eoff, uw, sadj, mt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(msd_zocc_kernel, dim3(2 * nz), dim3(256), 0, s, m, z0, mt, yt, ratio, zocc);
+    hipLaunchKernelGGL(msd_zocc_kernel, dim3(2 * nz), dim3(256), 0, s, m, z0, mt, yp, ratio, zocc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(msd_q_kernel, dim3((m.N * m.nmax + 255) / 256, 2 * nz), dim3(256), 0, s, m, z0, t.cocc,
+    const int qrows = QR * (64 / q_lanes(m.nmax));
+    hipLaunchKernelGGL(msd_q_kernel, dim3((m.N + qrows - 1) / qrows, 2 * nz), dim3(64), 0, s, m, z0, t.cocc,
                        t.cvirt, zocc, mt, ratio, q);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int nqb = (m.N + G_COLS - 1) / G_COLS, npb = (m.N + G_ROWS - 1) / G_ROWS;
