@@ -1101,9 +1101,8 @@ struct afqmc_msd {
   double2* uw = nullptr;
   double2* rpart = nullptr;
   double2* ratio = nullptr;
-  double2* mt = nullptr;
-  double2* zocc = nullptr;
-  double2* q = nullptr;
+  double* zt = nullptr;  // planar Zt [W][2][2][nmax][ldN]
+  double* qp = nullptr;  // planar Q [W][2][2][N][ldq]
   int* status = nullptr;
   std::vector<void*> allocs;
 };
@@ -1236,7 +1235,7 @@ int msd_build(afqmc_msd* t, const double* C[2], const double* coeff, const int* 
   trow[m.nstr_tot] = (int)tbeg.size();
   m.ntask = (int)tbeg.size();
   tbeg.push_back(crow[m.nstr_tot]);  // every row is non-empty: task t ends at tbeg[t + 1]
-  // CSR over the (spin, virtual a, hole j) entries of M: contributions in
+  // CSR over the (spin, hole j, virtual a) entries of M: contributions in
   // increasing string, then (m, l) order
   const int nent0 = m.na * m.nv[0], nent = nent0 + m.nb * m.nv[1];
   std::vector<std::vector<std::pair<int, int>>> ent(nent);
@@ -1247,7 +1246,7 @@ int msd_build(afqmc_msd* t, const double* C[2], const double* coeff, const int* 
       for (int l = 0; l < k; ++l) {  // particle slot l
         const int j = sorb[((size_t)u * 2 + 0) * MSD_KMAX + x];
         const int av = sorb[((size_t)u * 2 + 1) * MSD_KMAX + l];
-        ent[(s ? nent0 : 0) + av * n + j].push_back({u, saoff[u] + x * k + l});
+        ent[(s ? nent0 : 0) + j * m.nv[s] + av].push_back({u, saoff[u] + x * k + l});
       }
   }
   std::vector<int> erow(nent + 1, 0), estr, eoff;
@@ -1260,14 +1259,17 @@ int msd_build(afqmc_msd* t, const double* C[2], const double* coeff, const int* 
   }
   // orbitals
   std::vector<double> cocc((size_t)2 * N * m.nmax, 0.0), cvirt((size_t)2 * N * m.ldv, 0.0);
+  std::vector<double> cfull((size_t)2 * N * m.ldN, 0.0);
   for (int s = 0; s < 2; ++s)
     for (int p = 0; p < N; ++p) {
+      for (int x = 0; x < N; ++x) cfull[((size_t)s * N + p) * m.ldN + x] = C[s][(size_t)p * N + x];
       for (int i = 0; i < nel[s]; ++i) cocc[((size_t)s * N + p) * m.nmax + i] = C[s][(size_t)p * N + i];
       for (int a = 0; a < m.nv[s]; ++a) cvirt[((size_t)s * N + p) * m.ldv + a] = C[s][(size_t)p * N + nel[s] + a];
     }
   int rc;
   MsdTables& tb = t->t;
   if ((rc = msd_upload(t, &tb.cocc, cocc)) || (rc = msd_upload(t, &tb.cvirt, cvirt)) ||
+      (rc = msd_upload(t, &tb.cfull, cfull)) ||
       (rc = msd_upload(t, &tb.srank, srank)) || (rc = msd_upload(t, &tb.sorb, sorb)) ||
       (rc = msd_upload(t, &tb.saoff, saoff)) || (rc = msd_upload(t, &tb.crow, crow)) ||
       (rc = msd_upload(t, &tb.ccoef, ccoef)) || (rc = msd_upload(t, &tb.cstr, cstr)) ||
@@ -1292,9 +1294,8 @@ int msd_workspace(afqmc_msd* t) {
   if ((rc = dalloc_t(t, &t->uw, W * m.nstr_tot))) return rc;
   if ((rc = dalloc_t(t, &t->rpart, W * msd_combine_blocks(m)))) return rc;
   if ((rc = dalloc_t(t, &t->ratio, W))) return rc;
-  if ((rc = dalloc_t(t, &t->mt, W * 2 * m.ldv * m.nmax))) return rc;
-  if ((rc = dalloc_t(t, &t->zocc, W * 2 * m.nmax * m.nmax))) return rc;
-  if ((rc = dalloc_t(t, &t->q, W * 2 * m.N * m.nmax))) return rc;
+  if ((rc = dalloc_t(t, &t->zt, W * 4 * m.nmax * m.ldN))) return rc;
+  if ((rc = dalloc_t(t, &t->qp, W * 4 * m.N * m.ldq))) return rc;
   if ((rc = dalloc_t(t, &t->status, (size_t)1))) return rc;
   return AFQMC_OK;
 }
@@ -1352,6 +1353,7 @@ int afqmc_msd_create(int N, int na, int nb, const double* host_C_a, const double
   m.nv[1] = N - nb;
   m.ldv = ((m.nv[0] > m.nv[1] ? m.nv[0] : m.nv[1]) + 3) / 4 * 4;
   if (m.ldv == 0) m.ldv = 4;
+  m.ldq = (m.nmax + 1) / 2 * 2;
   t->d.N = N;
   t->d.na = na;
   t->d.nb = nb;
@@ -1387,8 +1389,8 @@ int afqmc_msd_green_function(afqmc_msd* t, const afqmc_walkers* w, int nw, void*
   if (!G) return fail(AFQMC_EINVAL, "null G");
   hipStream_t s = (hipStream_t)stream;
   if ((rc = msd_ratio(t, w, nw, s))) return rc;
-  HIP_TRY(launch_msd_green(t->m, nw, t->t, t->theta, t->yp, t->sadj, t->uw, t->ratio, t->mt, t->zocc, t->q,
-                           (double2*)G, s));
+  HIP_TRY(launch_msd_green(t->m, nw, t->t, t->theta, t->yp, t->sadj, t->uw, t->ratio, t->zt, t->qp, (double2*)G,
+                           s));
   return AFQMC_OK;
 }
 

@@ -179,7 +179,8 @@ struct MsdDims {
   int N, na, nb, nmax;
   int ldN;       // orbital stride of theta (as StepDims::ldN)
   int nv[2];     // virtual orbitals per spin, N - n_s
-  int ldv;       // virtual stride of Y, M and C_virt (>= max nv, multiple of 4)
+  int ldv;       // virtual stride of Y and C_virt (>= max nv, multiple of 4)
+  int ldq;       // electron stride of planar Q (nmax rounded up to 2)
   int nstr[2];   // excitation strings per spin (concatenated: alpha, then beta)
   int nstr_tot;
   int nadj_tot;  // adjugate entries of all strings (sum of k^2)
@@ -193,6 +194,7 @@ constexpr int MSD_TASK = 16;
 struct MsdTables {
   const double* cocc;   // [2][N][nmax]  reference orbitals C_s[:, :n_s]
   const double* cvirt;  // [2][N][ldv]   C_s[:, n_s:], zero-padded
+  const double* cfull;  // [2][N][ldN]   C_s, zero-padded
   const int* srank;     // [nstr_tot]    k of each string
   const int* sorb;      // [nstr_tot][2][MSD_KMAX] holes; particles as virtual index q - n_s
   const int* saoff;     // [nstr_tot]    first adjugate entry of the string
@@ -201,7 +203,7 @@ struct MsdTables {
   const int* cstr;      // [2 ndet]      the determinant's string of the other spin (concatenated index)
   const int* tbeg;      // [ntask + 1]   first CSR entry of each task (tasks in string order)
   const int* trow;      // [nstr_tot + 1] first task of each string
-  const int* erow;      // [na nv_a + nb nv_b + 1] CSR over (spin, virtual a, hole j) entries of M
+  const int* erow;      // [na nv_a + nb nv_b + 1] CSR over (spin, hole j, virtual a) entries of M
   const int* estr;      // string of each contribution
   const int* eoff;      // adjugate entry of each contribution
 };
@@ -218,8 +220,9 @@ hipError_t launch_msd_ratio(const MsdDims& m, int W, const MsdTables& t, const d
 // out [W] = logdet[z][0] + logdet[z][1] + log ratio[z]
 hipError_t launch_msd_overlap_store(int W, const double2* logdet, const double2* ratio, double2* out, int* status,
                                     hipStream_t s);
-// after launch_msd_ratio: M -> mt [W][2][ldv][nmax], zocc [W][2][nmax][nmax], q [W][2][N][nmax],
-// G [W][2][N][N]
+// after launch_msd_ratio: planar Zt zt [W][2][2][nmax][ldN] (M / s in the
+// virtual columns, I - M Y / s in the occupied ones), planar Q qp
+// [W][2][2][N][ldq], G [W][2][N][N] complex
 hipError_t launch_msd_green(const MsdDims& m, int W, const MsdTables& t, const double* theta, const double* yp,
-                            const double2* sadj, const double2* uw, const double2* ratio, double2* mt,
-                            double2* zocc, double2* q, double2* G, hipStream_t s);
+                            const double2* sadj, const double2* uw, const double2* ratio, double* zt, double* qp,
+                            double2* G, hipStream_t s);

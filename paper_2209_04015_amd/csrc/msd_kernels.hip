@@ -334,151 +334,205 @@ __global__ void msd_ratio_kernel(int z0, int nz, int nblk, const double2* __rest
 
 // ---------------------------------------------------------------------------
 // M^s[j][a] = sum over (string u, adjugate slot) entries of uw[u] adj_u[slot]
-// (CSR per (a, j) entry of the spin, fixed order), stored Mt[z][s][a][j].
+// (CSR per (j, a) entry of the spin, fixed order), divided by s_z and stored
+// as the virtual columns of Zt: zt[z][re | im][s][j][n + a] (planar, theta's
+// layout).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void msd_m_kernel(MsdDims m, int z0, const int* __restrict__ erow,
                                                     const int* __restrict__ estr, const int* __restrict__ eoff,
                                                     const double2* __restrict__ uw,
                                                     const double2* __restrict__ sadj,
-                                                    double2* __restrict__ mt) {
+                                                    const double2* __restrict__ ratio, double* __restrict__ zt) {
   const int z = z0 + (int)(blockIdx.y >> 1), s = blockIdx.y & 1;
   const int n = s ? m.nb : m.na, nv = m.nv[s];
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * nv) return;
-  const int a = e / n, j = e - a * n;
+  const int j = e / nv, a = e - j * nv;
   const int r = (s ? m.na * m.nv[0] : 0) + e;
   const double2* uz = uw + (size_t)z * m.nstr_tot;
   const double2* az = sadj + (size_t)z * m.nadj_tot;
   double2 acc = make_double2(0.0, 0.0);
   for (int x = erow[r]; x < erow[r + 1]; ++x) acc = cadd(acc, cmul(uz[estr[x]], az[eoff[x]]));
-  mt[(((size_t)z * 2 + s) * m.ldv + a) * m.nmax + j] = acc;
+  acc = cmul(acc, cinv(ratio[z]));
+  const size_t plane = (size_t)m.nmax * m.ldN;
+  const size_t o = (size_t)j * m.ldN + n + a;
+  zt[((size_t)(2 * z + 0) * 2 + s) * plane + o] = acc.x;
+  zt[((size_t)(2 * z + 1) * 2 + s) * plane + o] = acc.y;
 }
 
 // ---------------------------------------------------------------------------
-// Zocc[j][i] = delta_ji - (sum_a M[j][a] Y[a][i]) / s_z   (one workgroup per (walker, spin))
+// Occupied columns of Zt: Zt[j][i] = delta_ji - sum_a Zt[j][n + a] Y[a][i]
+// (= delta_ji - (M Y)[j][i] / s_z), one small real GEMM per (walker, spin)
+// over k = (re | im, a): A row j = [Zr[j], Zi[j]] (virtual columns), B column
+// 2i = [Yr[i], -Yi[i]] and 2i + 1 = [Yi[i], Yr[i]] (real and imaginary parts).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void msd_zocc_kernel(MsdDims m, int z0, const double2* __restrict__ mt,
-                                                       const double* __restrict__ yp,
-                                                       const double2* __restrict__ ratio,
-                                                       double2* __restrict__ zocc) {
-  const int z = z0 + (int)(blockIdx.x >> 1), s = blockIdx.x & 1;
-  const int n = s ? m.nb : m.na, nv = m.nv[s];
-  const double2 is = cinv(ratio[z]);
-  const double2* M = mt + ((size_t)z * 2 + s) * m.ldv * m.nmax;
-  const YView Y = y_view(m, yp, z, s);
-  double2* Z = zocc + ((size_t)z * 2 + s) * m.nmax * m.nmax;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int i = e / n, j = e - i * n;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int a = 0; a < nv; ++a) acc = cadd(acc, cmul(M[(size_t)a * m.nmax + j], Y(i, a)));
-    const double2 t = cmul(acc, is);
-    Z[(size_t)j * m.nmax + i] = make_double2((i == j ? 1.0 : 0.0) - t.x, -t.y);
+struct MsdZProb {
+  const double* zt;
+  const double* yp;
+  int z0, nmax, ldN, ldv, na, nb, nv0, nv1;
+  __device__ double2 load_a(int b, int j, int k) const {
+    const int z = z0 + (b >> 1), s = b & 1;
+    const int n = s ? nb : na, nv = s ? nv1 : nv0;
+    const int c = k < ldv ? 0 : 1, a = k - c * ldv;
+    if (j >= n) return make_double2(0.0, 0.0);
+    const double* row = zt + ((size_t)(2 * z + c) * 2 + s) * nmax * ldN + (size_t)j * ldN + n;
+    return make_double2(a < nv ? row[a] : 0.0, a + 1 < nv ? row[a + 1] : 0.0);
   }
-}
+  __device__ double2 load_b(int b, int col, int k) const {
+    const int z = z0 + (b >> 1), s = b & 1;
+    const int n = s ? nb : na;
+    const int i = col >> 1, part = col & 1;
+    const int c = k < ldv ? 0 : 1, a = k - c * ldv;  // a even, a + 1 < ldv (ldv a multiple of 4)
+    if (i >= n) return make_double2(0.0, 0.0);
+    const size_t yplane = (size_t)nmax * ldv;
+    const double2 yr = *reinterpret_cast<const double2*>(yp + ((size_t)(2 * z + 0) * 2 + s) * yplane + (size_t)i * ldv + a);
+    const double2 yi = *reinterpret_cast<const double2*>(yp + ((size_t)(2 * z + 1) * 2 + s) * yplane + (size_t)i * ldv + a);
+    // Y entries a >= nv are zero (never written), so no guard is needed here
+    if (part == 0) return c == 0 ? yr : make_double2(-yi.x, -yi.y);
+    return c == 0 ? yi : yr;
+  }
+};
 
-// ---------------------------------------------------------------------------
-// Q[p][j] = sum_x C[p][x] Zt[j][x],  Zt[j][i] = Zocc[j][i] (i < n),
-// Zt[j][n + a] = M[j][a] / s_z.  One wave per (walker, spin, row block);
-// lane = (row group g, j) with 32 lanes per group when n <= 32 (two groups of
-// QR rows per wave), else 64; chunks of C rows are staged in LDS and read as
-// broadcasts.
-// ---------------------------------------------------------------------------
-constexpr int QR = 16, QX = 64;
+constexpr int ZBM = 64, ZBN = 64, ZBK = 16, ZWM = 2, ZWN = 2;
 
-__host__ __device__ inline int q_lanes(int nmax) { return nmax <= 32 ? 32 : 64; }
-
-__global__ __launch_bounds__(64) void msd_q_kernel(MsdDims m, int z0, const double* __restrict__ cocc,
-                                                   const double* __restrict__ cvirt,
-                                                   const double2* __restrict__ zocc,
-                                                   const double2* __restrict__ mt,
-                                                   const double2* __restrict__ ratio,
-                                                   double2* __restrict__ q) {
-  __shared__ double cs[2 * QR * QX];
-  const int z = z0 + (int)(blockIdx.y >> 1), s = blockIdx.y & 1;
+__global__ __launch_bounds__(ZWM* ZWN * 64) void msd_zocc_kernel(MsdDims m, MsdZProb p, double* __restrict__ zt) {
+  __shared__ __attribute__((aligned(16))) double lds[TileLds<double, ZBM, ZBN, ZBK>::ELEMS];
+  MF<double>::acc_t acc[ZBM / ZWM / 16][ZBN / ZWN / 16];
+  const int b = blockIdx.z;
+  const int m0 = blockIdx.x * ZBM, n0 = blockIdx.y * ZBN;
+  mfma_tile_mainloop<double, ZBM, ZBN, ZBK, ZWM, ZWN, false>(p, b, m0, n0, 2 * m.ldv, acc, lds);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wm = wid / ZWN, wn = wid % ZWN;
+  const int z = p.z0 + (b >> 1), s = b & 1;
   const int n = s ? m.nb : m.na;
-  if (n == 0) return;  // uniform
-  const int N = m.N;
-  const int jw = q_lanes(m.nmax), groups = 64 / jw;
-  const int lane = threadIdx.x;
-  const int g = lane / jw, j = lane - g * jw;
-  const int pb0 = blockIdx.x * QR * groups;  // first row of the workgroup
-  const int p0 = pb0 + g * QR;               // first row of this lane's group
-  const int jc = j < n ? j : 0;              // lanes past n are not stored
-  const double2 is = cinv(ratio[z]);
-  const double* co = cocc + (size_t)s * N * m.nmax;
-  const double* cv = cvirt + (size_t)s * N * m.ldv;
-  const double2* Z = zocc + ((size_t)z * 2 + s) * m.nmax * m.nmax + (size_t)jc * m.nmax;
-  const double2* M = mt + ((size_t)z * 2 + s) * m.ldv * m.nmax + jc;
-  double2 acc[QR];
+  const size_t plane = (size_t)m.nmax * m.ldN;
 #pragma unroll
-  for (int r = 0; r < QR; ++r) acc[r] = make_double2(0.0, 0.0);
-  const double* cg = cs + g * QR * QX;
-  for (int x0 = 0; x0 < N; x0 += QX) {
-    __syncthreads();
-    for (int e = lane; e < groups * QR * QX; e += 64) {
-      const int r = e / QX, xx = e - r * QX;
-      const int p = pb0 + r, x = x0 + xx;
-      double c = 0.0;
-      if (p < N && x < N) c = x < n ? co[(size_t)p * m.nmax + x] : cv[(size_t)p * m.ldv + (x - n)];
-      cs[e] = c;
-    }
-    __syncthreads();
-    const int nx = N - x0 < QX ? N - x0 : QX;
-    for (int xx = 0; xx < nx; ++xx) {
-      const int x = x0 + xx;
-      const double2 zv = x < n ? Z[x] : cmul(M[(size_t)(x - n) * m.nmax], is);
+  for (int i = 0; i < ZBM / ZWM / 16; ++i)
 #pragma unroll
-      for (int r = 0; r < QR; ++r) {
-        const double c = cg[r * QX + xx];
-        acc[r].x = fma(c, zv.x, acc[r].x);
-        acc[r].y = fma(c, zv.y, acc[r].y);
+    for (int jj = 0; jj < ZBN / ZWN / 16; ++jj) {
+      const int jb = m0 + wm * (ZBM / ZWM) + i * 16 + 4 * (lane >> 4);
+      const int col = n0 + wn * (ZBN / ZWN) + jj * 16 + (lane & 15);
+      const int ii = col >> 1, part = col & 1;
+      if (ii >= n) continue;
+      double* dst = zt + ((size_t)(2 * z + part) * 2 + s) * plane + ii;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = jb + r;
+        if (j < n) dst[(size_t)j * m.ldN] = (part == 0 && j == ii ? 1.0 : 0.0) - acc[i][jj][r];
       }
     }
-  }
-  if (j >= n) return;
-#pragma unroll
-  for (int r = 0; r < QR; ++r)
-    if (p0 + r < N) q[(((size_t)z * 2 + s) * N + p0 + r) * m.nmax + j] = acc[r];
 }
 
 // ---------------------------------------------------------------------------
-// G[z][s][p][q] = sum_j theta_0[q][j] Q[p][j]; the G_ROWS rows of Q a
-// workgroup needs are staged in LDS.
+// Q[p][j] = sum_x C[p][x] Zt[j][x]: one FP64 MFMA GEMM per spin, A = C of
+// the spin ([N][ldN], x contiguous), B = the Zt rows (walker, re | im, j).
+// Q is stored planar, qp[z][re | im][s][p][ldq] (ldq = nmax rounded up to 2;
+// columns j >= n stay zero).
 // ---------------------------------------------------------------------------
-constexpr int G_ROWS = 16, G_COLS = 64, G_LDJ = 48;  // G_LDJ >= 45 electrons
+struct MsdQProb {
+  const double* cf;  // C of the spin, [N][ldN]
+  const double* zt;
+  int N, rows;       // B rows: 2 nz nmax
+  int z0, s, nmax, ldN;
+  __device__ double2 load_a(int, int p, int k) const {
+    if (p >= N) return make_double2(0.0, 0.0);
+    return *reinterpret_cast<const double2*>(cf + (size_t)p * ldN + k);
+  }
+  __device__ double2 load_b(int, int r, int k) const {
+    if (r >= rows) return make_double2(0.0, 0.0);
+    const int zc = r / nmax, j = r - zc * nmax;
+    const size_t plane = (size_t)nmax * ldN;
+    return *reinterpret_cast<const double2*>(zt + ((size_t)(2 * z0 + zc) * 2 + s) * plane + (size_t)j * ldN + k);
+  }
+};
 
-__global__ __launch_bounds__(G_COLS) void msd_green_kernel(MsdDims m, int z0, const double* __restrict__ theta,
-                                                           const double2* __restrict__ q,
-                                                           double2* __restrict__ G) {
-  __shared__ double2 qs[G_ROWS * G_LDJ];
-  const int nqb = (m.N + G_COLS - 1) / G_COLS;
-  const int qb = blockIdx.x % nqb, pb = blockIdx.x / nqb;
-  const int z = z0 + (int)(blockIdx.y >> 1), s = blockIdx.y & 1;
-  const int n = s ? m.nb : m.na;
-  const int p0 = pb * G_ROWS;
-  const double2* Q = q + ((size_t)z * 2 + s) * m.N * m.nmax;
-  for (int e = threadIdx.x; e < G_ROWS * n; e += G_COLS) {
-    const int r = e / n, j = e - r * n;
-    qs[r * G_LDJ + j] = p0 + r < m.N ? Q[(size_t)(p0 + r) * m.nmax + j] : make_double2(0.0, 0.0);
+constexpr int GBM = 64, GBN = 64, GBK = 16, GWM = 2, GWN = 2;
+
+__global__ __launch_bounds__(GWM* GWN * 64) void msd_q_kernel(MsdDims m, MsdQProb p, double* __restrict__ qp) {
+  __shared__ __attribute__((aligned(16))) double lds[TileLds<double, GBM, GBN, GBK>::ELEMS];
+  MF<double>::acc_t acc[GBM / GWM / 16][GBN / GWN / 16];
+  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
+  mfma_tile_mainloop<double, GBM, GBN, GBK, GWM, GWN, false>(p, 0, m0, n0, m.N, acc, lds);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wm = wid / GWN, wn = wid % GWN;
+  const int n = p.s ? m.nb : m.na;
+#pragma unroll
+  for (int i = 0; i < GBM / GWM / 16; ++i)
+#pragma unroll
+    for (int jj = 0; jj < GBN / GWN / 16; ++jj) {
+      const int pb = m0 + wm * (GBM / GWM) + i * 16 + 4 * (lane >> 4);
+      const int col = n0 + wn * (GBN / GWN) + jj * 16 + (lane & 15);
+      if (col >= p.rows) continue;
+      const int zc = col / m.nmax, j = col - zc * m.nmax;
+      if (j >= n) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = pb + r;
+        if (row < m.N) qp[(((size_t)(2 * p.z0 + zc) * 2 + p.s) * m.N + row) * m.ldq + j] = acc[i][jj][r];
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// G[z][s][p][q] = sum_j Q[p][j] theta_0[q][j] as a real GEMM per (walker,
+// spin) over k = (re | im, j) (ldq values each): A row p = [Q_re[p], Q_im[p]],
+// B column 2q = [theta_re[q], -theta_im[q]] (real part) and 2q + 1 =
+// [theta_im[q], theta_re[q]] (imaginary part).  Output columns 2q, 2q + 1 are
+// the real and imaginary parts of G[p][q], so the stores are contiguous.
+// ---------------------------------------------------------------------------
+struct MsdGProb {
+  const double* qp;
+  const double* theta;
+  int N, nmax, ldN, ldq, z0;
+  __device__ double2 load_a(int b, int p, int k) const {
+    if (p >= N) return make_double2(0.0, 0.0);
+    const int z = z0 + (b >> 1), s = b & 1;
+    const int c = k < ldq ? 0 : 1, kk = k - c * ldq;
+    return *reinterpret_cast<const double2*>(qp + (((size_t)(2 * z + c) * 2 + s) * N + p) * ldq + kk);
   }
-  __syncthreads();
-  const int c = qb * G_COLS + threadIdx.x;
-  if (c >= m.N) return;
-  const size_t plane = (size_t)m.nmax * m.ldN;
-  const double* tre = theta + ((size_t)(z * 2 + 0) * 2 + s) * plane;
-  const double* tim = theta + ((size_t)(z * 2 + 1) * 2 + s) * plane;
-  double2 acc[G_ROWS];
-#pragma unroll
-  for (int r = 0; r < G_ROWS; ++r) acc[r] = make_double2(0.0, 0.0);
-  for (int j = 0; j < n; ++j) {
-    const double2 t = make_double2(tre[(size_t)j * m.ldN + c], tim[(size_t)j * m.ldN + c]);
-#pragma unroll
-    for (int r = 0; r < G_ROWS; ++r) acc[r] = cadd(acc[r], cmul(qs[r * G_LDJ + j], t));
+  __device__ double2 load_b_km(int b, int k, int col) const {
+    const int q = col >> 1;
+    const int c = k < ldq ? 0 : 1, j = k - c * ldq;
+    if (q >= N || j >= nmax) return make_double2(0.0, 0.0);
+    const int z = z0 + (b >> 1), s = b & 1;
+    const size_t plane = (size_t)nmax * ldN;
+    const double tr = theta[((size_t)(2 * z + 0) * 2 + s) * plane + (size_t)j * ldN + q];
+    const double ti = theta[((size_t)(2 * z + 1) * 2 + s) * plane + (size_t)j * ldN + q];
+    return c == 0 ? make_double2(tr, ti) : make_double2(-ti, tr);
   }
-  double2* out = G + ((size_t)z * 2 + s) * m.N * m.N;
+};
+
+// Workgroups are dispatched to the 8 XCDs in turn (XCD = linear id mod 8);
+// the tiles of one (walker, spin) are given ids with the same residue, so
+// its Q and theta are read into one XCD's L2 only.
+constexpr int NXCD = 8;
+
+__global__ __launch_bounds__(GWM* GWN * 64) void msd_green_kernel(MsdDims m, MsdGProb p, int nbatch, int mt, int ntile,
+                                                                  double* __restrict__ G) {
+  __shared__ __attribute__((aligned(16))) double lds[TileLds<double, GBM, GBN, GBK>::ELEMS];
+  MF<double>::acc_t acc[GBM / GWM / 16][GBN / GWN / 16];
+  const int L = blockIdx.x;
+  const int xcd = L % NXCD, r = L / NXCD;
+  const int t = r % ntile;
+  const int b = xcd + NXCD * (r / ntile);
+  if (b >= nbatch) return;  // whole workgroup, before any barrier
+  const int m0 = (t % mt) * GBM, n0 = (t / mt) * GBN;
+  mfma_tile_mainloop<double, GBM, GBN, GBK, GWM, GWN, true>(p, b, m0, n0, 2 * m.ldq, acc, lds);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wm = wid / GWN, wn = wid % GWN;
+  const int z = p.z0 + (b >> 1), s = b & 1;
+  double* out = G + ((size_t)z * 2 + s) * m.N * 2 * m.N;
 #pragma unroll
-  for (int r = 0; r < G_ROWS; ++r)
-    if (p0 + r < m.N) out[(size_t)(p0 + r) * m.N + c] = acc[r];
+  for (int i = 0; i < GBM / GWM / 16; ++i)
+#pragma unroll
+    for (int jj = 0; jj < GBN / GWN / 16; ++jj) {
+      const int pb = m0 + wm * (GBM / GWM) + i * 16 + 4 * (lane >> 4);
+      const int col = n0 + wn * (GBN / GWN) + jj * 16 + (lane & 15);
+      if (col >= 2 * m.N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (pb + r < m.N) out[(size_t)(pb + r) * 2 * m.N + col] = acc[i][jj][r];
+    }
 }
 
 // log <Psi_T|phi_z> = log det S^a + log det S^b + log s_z
@@ -497,7 +551,7 @@ __global__ void msd_overlap_kernel(int W, const double2* __restrict__ logdet, co
   out[z] = lo;
 }
 
-constexpr int ZCHUNK = 16384;  // walkers per launch (grid y <= 2 per walker)
+constexpr int ZCHUNK = 16384;  // walkers per launch (grid y, z <= 2 per walker)
 
 }  // namespace
 
@@ -544,23 +598,33 @@ hipError_t launch_msd_overlap_store(int W, const double2* logdet, const double2*
 }
 
 hipError_t launch_msd_green(const MsdDims& m, int W, const MsdTables& t, const double* theta, const double* yp,
-                            const double2* sadj, const double2* uw, const double2* ratio, double2* mt,
-                            double2* zocc, double2* q, double2* G, hipStream_t s) {
+                            const double2* sadj, const double2* uw, const double2* ratio, double* zt, double* qp,
+                            double2* G, hipStream_t s) {
   for (int z0 = 0; z0 < W; z0 += ZCHUNK) {
     const int nz = W - z0 < ZCHUNK ? W - z0 : ZCHUNK;
     const int nent = m.nmax * m.ldv;
     hipLaunchKernelGGL(msd_m_kernel, dim3((nent + 255) / 256, 2 * nz), dim3(256), 0, s, m, z0, t.erow, t.estr,
-                       t.eoff, uw, sadj, mt);
+                       t.eoff, uw, sadj, ratio, zt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(msd_zocc_kernel, dim3(2 * nz), dim3(256), 0, s, m, z0, mt, yp, ratio, zocc);
+    {
+      MsdZProb pz{zt, yp, z0, m.nmax, m.ldN, m.ldv, m.na, m.nb, m.nv[0], m.nv[1]};
+      const dim3 grid((m.nmax + ZBM - 1) / ZBM, (2 * m.nmax + ZBN - 1) / ZBN, 2 * nz);
+      hipLaunchKernelGGL(msd_zocc_kernel, grid, dim3(ZWM * ZWN * 64), 0, s, m, pz, zt);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int qrows = QR * (64 / q_lanes(m.nmax));
-    hipLaunchKernelGGL(msd_q_kernel, dim3((m.N + qrows - 1) / qrows, 2 * nz), dim3(64), 0, s, m, z0, t.cocc,
-                       t.cvirt, zocc, mt, ratio, q);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int nqb = (m.N + G_COLS - 1) / G_COLS, npb = (m.N + G_ROWS - 1) / G_ROWS;
-    hipLaunchKernelGGL(msd_green_kernel, dim3(nqb * npb, 2 * nz), dim3(G_COLS), 0, s, m, z0, theta, q, G);
+    for (int sp = 0; sp < 2; ++sp) {
+      if ((sp ? m.nb : m.na) == 0) continue;
+      MsdQProb p{t.cfull + (size_t)sp * m.N * m.ldN, zt, m.N, 2 * nz * m.nmax, z0, sp, m.nmax, m.ldN};
+      const dim3 grid((m.N + GBM - 1) / GBM, (p.rows + GBN - 1) / GBN);
+      hipLaunchKernelGGL(msd_q_kernel, grid, dim3(GWM * GWN * 64), 0, s, m, p, qp);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    MsdGProb pg{qp, theta, m.N, m.nmax, m.ldN, m.ldq, z0};
+    const int mt = (m.N + GBM - 1) / GBM, ntile = mt * ((2 * m.N + GBN - 1) / GBN);
+    const int nbatch = 2 * nz, nbp = (nbatch + NXCD - 1) / NXCD * NXCD;
+    hipLaunchKernelGGL(msd_green_kernel, dim3(ntile * nbp), dim3(GWM * GWN * 64), 0, s, m, pg, nbatch, mt, ntile,
+                       reinterpret_cast<double*>(G));
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
