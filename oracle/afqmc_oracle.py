@@ -18,6 +18,10 @@ What it computes follows arXiv 2209.04015 (ipie):
   Sec. III.B, Eqs. (fb), (gf), (halfgf), (rfb).
 * Local energy (one-body, Coulomb, exchange): Sec. III.C, the E_L
   definition, the exchange formula and the T intermediate.
+* Multi-determinant trial: Sec. III.A (the expansion and Eq. msdovlp) and
+  the MSD Green's function of Sec. III.B, each taken by its definition, a
+  sum over determinants (R23, R24); the generalised Wick's theorem that the
+  paper uses to evaluate them is not used here.
 
 Readings where the paper is silent (each is listed in the design doc as well):
 

@@ -10,11 +10,12 @@ S_0 = C_occ^T phi is inverted on both sides, so theta_0 and Y carry a
 relative error of about u cond(S_0) (u = 2^-53); a string determinant of
 rank k (k <= 6) and its adjugate add at most a few k^2 u on top, and the
 expansion sums add one u per term relative to the sum of |terms|.  With
-cond(S_0) < 1e3 for these walkers (perturbations of 0.3 around psi_0) the
-relative error is below 1e-11 at every size here; the tests use 1e-9 of
-max |G| and 1e-9 in log |<Psi_T|phi>| (a relative error of the overlap),
-with the sum of |c_a O_a| / |sum c_a O_a| (the cancellation in the
-expansion, computed from the oracle's terms) as an extra factor.
+cond(S_0) < 1e3 for these walkers (perturbations of 0.3 around psi_0) and
+u = 1.1e-16 the relative error stays below 1e-13 times a small factor; the
+tests use 1e-12 of max |G| and 1e-12 relative on <Psi_T|phi>, times the
+cancellation of the expansion sum_a |c_a O_a| / |sum_a c_a O_a| (computed
+from the oracle's terms).  Measured on the MI355X: at most 7e-15 (overlap)
+and 1e-14 (G) with cancellations up to 71.
 """
 
 import numpy as np
@@ -55,14 +56,16 @@ def _cancellation(msd, pa, pb):
     return np.abs(terms).sum(axis=0) / np.abs(terms.sum(axis=0))
 
 
-def _compare(msd, lo, G, pa, pb, rtol=1e-9):
+def _compare(msd, lo, G, pa, pb, rtol=1e-12):
     ref_lo = orc.msd_overlap(msd, pa, pb)
     ref_G = orc.msd_green(msd, pa, pb)
     canc = _cancellation(msd, pa, pb)
     d = np.exp(lo - ref_lo) - 1.0            # relative overlap error (phase mod 2 pi)
-    assert np.all(np.abs(d) <= rtol * canc), (np.abs(d).max(), canc.max())
     scale = np.abs(ref_G).max(axis=(1, 2, 3))
     err = np.abs(G - ref_G).max(axis=(1, 2, 3))
+    print(f"[gpu] msd errors: overlap {np.abs(d).max():.2e}, G {(err / scale).max():.2e} of max|G|, "
+          f"cancellation {canc.max():.2f}", flush=True)
+    assert np.all(np.abs(d) <= rtol * canc), (np.abs(d).max(), canc.max())
     assert np.all(err <= rtol * canc * scale), (err / scale).max()
 
 
