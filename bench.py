@@ -146,52 +146,59 @@ def msd_flops_per_walker(N, n):
     return 2 * (4 * N * nv * n + 8 * n * n * nv + 4 * N * n * (n + nv) + 8 * N * N * n)
 
 
-def run_msd(cfg, device, steps, ndet=MSD_DETS):
-    """Multi-determinant trial (Sec. III.A): overlap and Green's function of
-    every walker against a synthetic ndet-determinant expansion, timed over
-    `steps` calls each on the current stream."""
+def run_msd(cfg, h1, L, device, steps, ndet=MSD_DETS):
+    """Multi-determinant trial (Sec. III.A): overlap, Green's function and
+    force bias of every walker against a synthetic ndet-determinant expansion
+    in the eigenvector basis of the workload's h1, timed over `steps` calls
+    each on the current stream.  The force bias contracts with the packed L
+    of an FP64 Hamiltonian of the same workload."""
     import torch
 
     from paper_2209_04015_amd import afqmc, inputs
 
-    N, n, W = cfg.N, cfg.n, cfg.W
+    N, n, W, K = cfg.N, cfg.n, cfg.W, cfg.K
     t = time.time()
-    h1, _ = inputs.hamiltonian(N, 4, 3.0, seed=4)
     C = inputs.orbitals(h1)
     coeff, rank, orbs = inputs.msd_expansion(N, n, n, ndet, max_rank=4, seed=5)
     pa = inputs.walkers_perturbed(C[:, :n], W, 0.1, seed=6, stream=0)
     pb = inputs.walkers_perturbed(C[:, :n], W, 0.1, seed=6, stream=1)
     trial = afqmc.MSDTrial(C, C, n, n, coeff, rank, orbs, max_walkers=W)
+    ham = afqmc.Hamiltonian(h1, L, C[:, :n], C[:, :n], dt=cfg.dt, max_walkers=W, precision="fp64")
     w = afqmc.Walkers.from_numpy(pa, pb, device=device)
     lo = torch.empty(W, dtype=torch.complex128, device=device)
     G = torch.empty((W, 2, N, N), dtype=torch.complex128, device=device)
+    vb = torch.empty((W, K), dtype=torch.complex128, device=device)
     log(f"msd: {ndet} determinants, strings {trial.strings}, set up in {time.time() - t:.1f} s")
     stream = torch.cuda.current_stream()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
-    trial.overlap(w, out=lo)
-    trial.green_function(w, out=G)
-    torch.cuda.synchronize()
-    start.record(stream)
-    for _ in range(steps):
-        trial.overlap(w, out=lo)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    ms_o = start.elapsed_time(stop) / steps
-    start.record(stream)
-    for _ in range(steps):
-        trial.green_function(w, out=G)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    ms_g = start.elapsed_time(stop) / steps
-    status = trial.status()
-    trial.close()
+
+    def timed(f):
+        f()
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(steps):
+            f()
+        stop.record(stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop) / steps
+
+    ms_o = timed(lambda: trial.overlap(w, out=lo))
+    ms_g = timed(lambda: trial.green_function(w, out=G))
     del G
     torch.cuda.empty_cache()
-    log(f"msd: overlap {ms_o:.3f} ms, Green's function {ms_g:.3f} ms per call, status {status}")
+    ms_f = timed(lambda: trial.force_bias(ham, w, out=vb))
+    status = trial.status()
+    trial.close()
+    ham.close()
+    torch.cuda.empty_cache()
+    log(f"msd: overlap {ms_o:.3f} ms, Green's function {ms_g:.3f} ms, force bias {ms_f:.3f} ms per call, "
+        f"status {status}")
     gbytes = W * 2 * N * N * 16
-    return {"workload": f"multi-determinant trial: {ndet} determinants (ranks <= 4 per spin) of "
-                        f"{N} orbitals, na=nb={n}, {W} walkers, FP64",
+    npk = N * (N + 1) // 2
+    return {"workload": f"multi-determinant trial: {ndet} determinants (ranks <= 4 per spin) in the eigenvector "
+                        f"basis of the {cfg.name} h1, {N} orbitals, na=nb={n}, {W} walkers, K={K} for the force "
+                        f"bias, FP64",
             "determinants": ndet, "strings_per_spin": list(trial.strings), "walkers": W,
             "overlap": {"value": round(W * ndet / (ms_o * 1e-3), 1), "unit": "walker-determinants/s",
                         "ms_per_call": round(ms_o, 4)},
@@ -200,6 +207,9 @@ def run_msd(cfg, device, steps, ndet=MSD_DETS):
                                "G_written_GB": round(gbytes / 1e9, 3),
                                "G_write_bound_ms": round(gbytes / 8e12 * 1e3, 4),
                                "dense_fp64_gflop": round(W * msd_flops_per_walker(N, n) / 1e9, 2)},
+            "force_bias": {"value": round(W / (ms_f * 1e-3), 1), "unit": "walkers/s",
+                           "ms_per_call": round(ms_f, 4),
+                           "contraction_fp64_gflop": round(2 * 2 * W * npk * K / 1e9, 1)},
             "status": status}
 
 
@@ -393,7 +403,7 @@ def main():
         del src, dst
 
     if args.msd_only:
-        print(json.dumps({"msd": run_msd(cfg, device, args.steps, args.msd_dets)}), flush=True)
+        print(json.dumps({"msd": run_msd(cfg, h1, L, device, args.steps, args.msd_dets)}), flush=True)
         return
 
     results = {}
@@ -426,7 +436,7 @@ def main():
         del w, e
         torch.cuda.empty_cache()
 
-    msd = None if args.only else run_msd(cfg, device, args.steps, args.msd_dets)
+    msd = None if args.only else run_msd(cfg, h1, L, device, args.steps, args.msd_dets)
 
     if args.only:
         ms, ph, st = results[args.only]

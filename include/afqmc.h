@@ -43,7 +43,7 @@ extern "C" {
 enum {
   AFQMC_OK = 0,
   AFQMC_EINVAL = 1,        /* bad argument or shape */
-  AFQMC_ENOMEM = 2,        /* device allocation failed (init only) */
+  AFQMC_ENOMEM = 2,        /* device allocation failed (init, afqmc_msd_create) */
   AFQMC_EHIP = 3,          /* a HIP runtime call failed */
   AFQMC_EUNSUPPORTED = 4   /* shape outside what the kernels support */
 };
@@ -368,6 +368,16 @@ int afqmc_msd_overlap(afqmc_msd* t, const afqmc_walkers* w, int nw, void* log_ov
  * Wick's theorem, Sec. III.B).  G: device complex [nw][2][N][N], written
  * (beta block zero when nb = 0).  Same inputs and status as afqmc_msd_overlap. */
 int afqmc_msd_green_function(afqmc_msd* t, const afqmc_walkers* w, int nw, void* G, void* stream);
+
+/* Force bias of the multi-determinant trial (Eq. fb with the G above):
+ *   vbias[z][g] = sum_s sum_pq G^s_pq L_g,pq,
+ * formed from the packed symmetric sum_s (G^s + G^s^T) and the packed L of
+ * `ham` without storing G.  ham: an FP64 Hamiltonian (AFQMC_EUNSUPPORTED
+ * otherwise) with the same N; nw <= both handles' max_walkers.  vbias:
+ * device complex [nw][K], written.  The call uses ham's VHS workspace as
+ * scratch: it must not overlap a call on the same Hamiltonian (the next
+ * afqmc_step recomputes that workspace).  Asynchronous on `stream`. */
+int afqmc_msd_force_bias(afqmc_msd* t, afqmc_ham* ham, const afqmc_walkers* w, int nw, void* vbias, void* stream);
 
 /* Excitation strings per spin after grouping (for sizing and reports). */
 int afqmc_msd_get_strings(afqmc_msd* t, int* nstr_a, int* nstr_b);

@@ -59,6 +59,7 @@ EXPORTED = (
     "afqmc_msd_create",
     "afqmc_msd_overlap",
     "afqmc_msd_green_function",
+    "afqmc_msd_force_bias",
     "afqmc_msd_get_strings",
     "afqmc_msd_get_status",
     "afqmc_msd_destroy",
@@ -147,6 +148,7 @@ def load(path: str = LIB_PATH):
     lib.afqmc_msd_create.argtypes = [ip, ip, ip, vp, vp, ip, vp, vp, vp, ip, vp, P(vp)]
     lib.afqmc_msd_overlap.argtypes = [vp, P(_Walkers), ip, vp, vp]
     lib.afqmc_msd_green_function.argtypes = [vp, P(_Walkers), ip, vp, vp]
+    lib.afqmc_msd_force_bias.argtypes = [vp, vp, P(_Walkers), ip, vp, vp]
     lib.afqmc_msd_get_strings.argtypes = [vp, P(ip), P(ip)]
     lib.afqmc_msd_get_status.argtypes = [vp, vp, P(ip)]
     lib.afqmc_msd_destroy.argtypes = [vp]
@@ -582,6 +584,18 @@ class MSDTrial:
         ptr = _dev(out, torch.complex128, (nw, 2, self.N, self.N), "G")
         s = w._struct(self, nw)
         _check(_lib.afqmc_msd_green_function(self._h, ctypes.byref(s), nw, ptr, _stream_ptr(stream)))
+        return out
+
+    def force_bias(self, ham: "Hamiltonian", w: Walkers, out=None, nw=None, stream=None):
+        """Device complex128 [nw, K]: sum_s sum_pq G^s_pq L_g,pq for this trial (ham: FP64)."""
+        import torch
+
+        nw = w.W if nw is None else int(nw)
+        if out is None:
+            out = torch.empty((nw, ham.K), dtype=torch.complex128, device=w.phi_a.device)
+        ptr = _dev(out, torch.complex128, (nw, ham.K), "vbias")
+        s = w._struct(self, nw)
+        _check(_lib.afqmc_msd_force_bias(self._h, ham._h, ctypes.byref(s), nw, ptr, _stream_ptr(stream)))
         return out
 
     def status(self, stream=None):

@@ -1394,6 +1394,31 @@ int afqmc_msd_green_function(afqmc_msd* t, const afqmc_walkers* w, int nw, void*
   return AFQMC_OK;
 }
 
+int afqmc_msd_force_bias(afqmc_msd* t, afqmc_ham* h, const afqmc_walkers* w, int nw, void* vbias, void* stream) {
+  int rc = msd_check(t, w, nw);
+  if (rc) return rc;
+  if (!h) return fail(AFQMC_EINVAL, "null Hamiltonian handle");
+  if (h->prec != AFQMC_FP64)
+    return fail(AFQMC_EUNSUPPORTED, "the multi-determinant force bias needs an FP64 Hamiltonian (its packed L)");
+  if (h->d.N != t->m.N) return fail(AFQMC_EINVAL, "orbital counts differ (%d, %d)", h->d.N, t->m.N);
+  if (nw > h->prm.max_walkers)
+    return fail(AFQMC_EINVAL, "nw = %d above the Hamiltonian's max_walkers = %d", nw, h->prm.max_walkers);
+  if (nw == 0) return AFQMC_OK;
+  if (!vbias) return fail(AFQMC_EINVAL, "null vbias");
+  const int npk = t->m.N * (t->m.N + 1) / 2;
+  const int ldpk = (npk + 15) / 16 * 16;
+  // scratch: the Hamiltonian's VHS workspace, idle outside its own steps
+  const size_t cap = (size_t)h->prm.max_walkers * h->d.N * h->d.ldV;
+  const int nsplit = msd_fb_splits(nw, t->m.N, h->d.K, h->d.ldK, ldpk, cap);
+  if (nsplit < 1) return fail(AFQMC_EUNSUPPORTED, "force-bias scratch does not fit the Hamiltonian's workspace");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = msd_ratio(t, w, nw, s))) return rc;
+  HIP_TRY(launch_msd_q(t->m, nw, t->t, t->yp, t->sadj, t->uw, t->ratio, t->zt, t->qp, s));
+  HIP_TRY(launch_msd_force_bias(t->m, nw, t->theta, t->qp, (const double*)h->LT, h->d.K, h->d.ldK, ldpk, nsplit,
+                                (double*)h->vhs, (double2*)vbias, s));
+  return AFQMC_OK;
+}
+
 int afqmc_msd_get_strings(afqmc_msd* t, int* nstr_a, int* nstr_b) {
   if (!t) return fail(AFQMC_EINVAL, "null multi-determinant trial handle");
   if (nstr_a) *nstr_a = t->m.nstr[0];

@@ -226,3 +226,14 @@ hipError_t launch_msd_overlap_store(int W, const double2* logdet, const double2*
 hipError_t launch_msd_green(const MsdDims& m, int W, const MsdTables& t, const double* theta, const double* yp,
                             const double2* sadj, const double2* uw, const double2* ratio, double* zt, double* qp,
                             double2* G, hipStream_t s);
+// after launch_msd_ratio: M / s and the occupied block into zt, Q into qp
+hipError_t launch_msd_q(const MsdDims& m, int W, const MsdTables& t, const double* yp, const double2* sadj,
+                        const double2* uw, const double2* ratio, double* zt, double* qp, hipStream_t s);
+// pair-range splits of the force-bias GEMM that fit a scratch of scratch_doubles (0: does not fit)
+int msd_fb_splits(int W, int N, int K, int ldK, int ldpk, size_t scratch_doubles);
+// after launch_msd_q: vbias [W][K] complex = sum_s sum_pq G^s_pq L_g,pq through the packed
+// symmetric G (scratch: [W][2][ldpk] then [nsplit][2 W][ldK] doubles) and the FP64 packed L
+// lt [N (N + 1) / 2][ldK] (row-major upper triangle)
+hipError_t launch_msd_force_bias(const MsdDims& m, int W, const double* theta, const double* qp, const double* lt,
+                                 int K, int ldK, int ldpk, int nsplit, double* scratch, double2* vbias,
+                                 hipStream_t s);

@@ -535,6 +535,148 @@ __global__ __launch_bounds__(GWM* GWN * 64) void msd_green_kernel(MsdDims m, Msd
     }
 }
 
+// ---------------------------------------------------------------------------
+// Force bias of the multi-determinant trial (Eq. fb with the MSD G):
+//   vbias_g = sum_s sum_pq G^s_pq L_g,pq = sum_{p <= q} L_g,pq c_pq Gsym_pq,
+//   Gsym = sum_s (G^s + G^s^T), c = 1 (p < q) or 1/2 (p = q),
+// with G^s_pq = sum_j Q^s[p][j] theta_0^s[q][j], so that
+//   Gsym_pq = sum_s sum_j (Q^s[p][j] theta^s[q][j] + theta^s[p][j] Q^s[q][j]).
+// msd_gsym_kernel forms the packed c Gsym (upper triangle, the row order of
+// the packed L) as one real GEMM per walker over
+// k = (spin, half, re | im of the A factor, j): A row p = Q[p] (half 0) or
+// theta[p] (half 1), B column 2q (+1) = the real (imaginary) part of the
+// product with theta[q] (half 0) or Q[q] (half 1).  Tiles entirely below
+// the diagonal are skipped.
+// ---------------------------------------------------------------------------
+struct MsdSProb {
+  const double* qp;
+  const double* theta;
+  int N, nmax, ldN, ldq, z0;
+  __device__ double2 load_a(int b, int p, int k) const {
+    if (p >= N) return make_double2(0.0, 0.0);
+    const int z = z0 + b;
+    const int j = k % ldq, t = k / ldq;  // j even: ldq and k are even
+    const int c = t & 1, h = (t >> 1) & 1, s = t >> 2;
+    if (h == 0)
+      return *reinterpret_cast<const double2*>(qp + (((size_t)(2 * z + c) * 2 + s) * N + p) * ldq + j);
+    const double* th = theta + ((size_t)(2 * z + c) * 2 + s) * nmax * ldN + p;
+    return make_double2(j < nmax ? th[(size_t)j * ldN] : 0.0, j + 1 < nmax ? th[(size_t)(j + 1) * ldN] : 0.0);
+  }
+  __device__ double2 load_b_km(int b, int k, int col) const {
+    const int q = col >> 1;
+    const int j = k % ldq, t = k / ldq;
+    const int c = t & 1, h = (t >> 1) & 1, s = t >> 2;
+    if (q >= N) return make_double2(0.0, 0.0);
+    const int z = z0 + b;
+    double br, bi;
+    if (h == 0) {
+      if (j >= nmax) return make_double2(0.0, 0.0);
+      const size_t plane = (size_t)nmax * ldN;
+      br = theta[((size_t)(2 * z + 0) * 2 + s) * plane + (size_t)j * ldN + q];
+      bi = theta[((size_t)(2 * z + 1) * 2 + s) * plane + (size_t)j * ldN + q];
+    } else {
+      br = qp[(((size_t)(2 * z + 0) * 2 + s) * N + q) * ldq + j];
+      bi = qp[(((size_t)(2 * z + 1) * 2 + s) * N + q) * ldq + j];
+    }
+    return c == 0 ? make_double2(br, bi) : make_double2(-bi, br);
+  }
+};
+
+__global__ __launch_bounds__(GWM* GWN * 64) void msd_gsym_kernel(MsdDims m, MsdSProb p, int nz, int mt, int ntile,
+                                                                 int ldpk, double* __restrict__ gs) {
+  __shared__ __attribute__((aligned(16))) double lds[TileLds<double, GBM, GBN, GBK>::ELEMS];
+  MF<double>::acc_t acc[GBM / GWM / 16][GBN / GWN / 16];
+  const int L = blockIdx.x;
+  const int xcd = L % NXCD, r = L / NXCD;
+  const int t = r % ntile;
+  const int b = xcd + NXCD * (r / ntile);  // walker - z0: tiles of a walker on one XCD
+  if (b >= nz) return;
+  const int m0 = (t % mt) * GBM, n0 = (t / mt) * GBN;
+  if (m0 > (n0 + GBN - 1) / 2) return;  // every p > every q of the tile
+  mfma_tile_mainloop<double, GBM, GBN, GBK, GWM, GWN, true>(p, b, m0, n0, 8 * m.ldq, acc, lds);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wm = wid / GWN, wn = wid % GWN;
+  const int z = p.z0 + b;
+  const int N = m.N;
+#pragma unroll
+  for (int i = 0; i < GBM / GWM / 16; ++i)
+#pragma unroll
+    for (int jj = 0; jj < GBN / GWN / 16; ++jj) {
+      const int pb = m0 + wm * (GBM / GWM) + i * 16 + 4 * (lane >> 4);
+      const int col = n0 + wn * (GBN / GWN) + jj * 16 + (lane & 15);
+      const int q = col >> 1, part = col & 1;
+      if (q >= N) continue;
+      double* dst = gs + (size_t)(2 * z + part) * ldpk;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int pp = pb + rr;
+        if (pp > q) continue;
+        const long idx = (long)pp * (2 * N - pp + 1) / 2 + (q - pp);  // row-major upper triangle
+        dst[idx] = (pp == q ? 0.5 : 1.0) * acc[i][jj][rr];
+      }
+    }
+}
+
+// vbias rows (z, re | im) = gs rows . packed L, split over the pair index into
+// nsplit ranges of `chunk` pairs; partials fbp[split][2 z + c][ldK].
+struct MsdFbProb {
+  const double* gs;
+  const double* lt;
+  int rows, ldpk, ldK, z0, chunk, npk;
+  __device__ double2 load_a(int split, int r, int k) const {
+    if (r >= rows) return make_double2(0.0, 0.0);
+    const int kk = split * chunk + k;
+    const double* row = gs + (size_t)(2 * z0 + r) * ldpk;
+    // entries past the packed triangle are not written (the scratch is reused): read as zero
+    if (kk + 1 >= npk) return make_double2(row[kk], 0.0);
+    return *reinterpret_cast<const double2*>(row + kk);
+  }
+  __device__ double2 load_b_km(int split, int k, int g) const {
+    if (g >= ldK) return make_double2(0.0, 0.0);
+    return *reinterpret_cast<const double2*>(lt + ((size_t)split * chunk + k) * ldK + g);
+  }
+};
+
+__global__ __launch_bounds__(GWM* GWN * 64) void msd_fb_kernel(MsdFbProb p, int npk, int K, int W,
+                                                               double* __restrict__ fbp) {
+  __shared__ __attribute__((aligned(16))) double lds[TileLds<double, GBM, GBN, GBK>::ELEMS];
+  MF<double>::acc_t acc[GBM / GWM / 16][GBN / GWN / 16];
+  const int split = blockIdx.z;
+  const int k0 = split * p.chunk;
+  const int kdim = npk - k0 < p.chunk ? npk - k0 : p.chunk;
+  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
+  mfma_tile_mainloop<double, GBM, GBN, GBK, GWM, GWN, true>(p, split, m0, n0, kdim, acc, lds);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wm = wid / GWN, wn = wid % GWN;
+  double* out = fbp + (size_t)split * 2 * W * p.ldK;
+#pragma unroll
+  for (int i = 0; i < GBM / GWM / 16; ++i)
+#pragma unroll
+    for (int jj = 0; jj < GBN / GWN / 16; ++jj) {
+      const int rb = m0 + wm * (GBM / GWM) + i * 16 + 4 * (lane >> 4);
+      const int g = n0 + wn * (GBN / GWN) + jj * 16 + (lane & 15);
+      if (g >= K) continue;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr)
+        if (rb + rr < p.rows) out[(size_t)(2 * p.z0 + rb + rr) * p.ldK + g] = acc[i][jj][rr];
+    }
+}
+
+// vbias[z][g] = sum over splits, in order, of the (re, im) partial rows
+__global__ void msd_fb_reduce_kernel(int W, int K, int ldK, int nsplit, const double* __restrict__ fbp,
+                                     double2* __restrict__ vbias) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)W * K) return;
+  const int z = (int)(e / K), g = (int)(e - (long)z * K);
+  double re = 0.0, im = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) {
+    const double* o = fbp + (size_t)sp * 2 * W * ldK;
+    re += o[(size_t)(2 * z) * ldK + g];
+    im += o[(size_t)(2 * z + 1) * ldK + g];
+  }
+  vbias[e] = make_double2(re, im);
+}
+
 // log <Psi_T|phi_z> = log det S^a + log det S^b + log s_z
 __global__ void msd_overlap_kernel(int W, const double2* __restrict__ logdet, const double2* __restrict__ ratio,
                                    double2* __restrict__ out, int* __restrict__ status) {
@@ -597,9 +739,8 @@ hipError_t launch_msd_overlap_store(int W, const double2* logdet, const double2*
   return hipGetLastError();
 }
 
-hipError_t launch_msd_green(const MsdDims& m, int W, const MsdTables& t, const double* theta, const double* yp,
-                            const double2* sadj, const double2* uw, const double2* ratio, double* zt, double* qp,
-                            double2* G, hipStream_t s) {
+hipError_t launch_msd_q(const MsdDims& m, int W, const MsdTables& t, const double* yp, const double2* sadj,
+                        const double2* uw, const double2* ratio, double* zt, double* qp, hipStream_t s) {
   for (int z0 = 0; z0 < W; z0 += ZCHUNK) {
     const int nz = W - z0 < ZCHUNK ? W - z0 : ZCHUNK;
     const int nent = m.nmax * m.ldv;
@@ -620,6 +761,17 @@ hipError_t launch_msd_green(const MsdDims& m, int W, const MsdTables& t, const d
       hipLaunchKernelGGL(msd_q_kernel, grid, dim3(GWM * GWN * 64), 0, s, m, p, qp);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_msd_green(const MsdDims& m, int W, const MsdTables& t, const double* theta, const double* yp,
+                            const double2* sadj, const double2* uw, const double2* ratio, double* zt, double* qp,
+                            double2* G, hipStream_t s) {
+  hipError_t e = launch_msd_q(m, W, t, yp, sadj, uw, ratio, zt, qp, s);
+  if (e != hipSuccess) return e;
+  for (int z0 = 0; z0 < W; z0 += ZCHUNK) {
+    const int nz = W - z0 < ZCHUNK ? W - z0 : ZCHUNK;
     MsdGProb pg{qp, theta, m.N, m.nmax, m.ldN, m.ldq, z0};
     const int mt = (m.N + GBM - 1) / GBM, ntile = mt * ((2 * m.N + GBN - 1) / GBN);
     const int nbatch = 2 * nz, nbp = (nbatch + NXCD - 1) / NXCD * NXCD;
@@ -628,4 +780,49 @@ hipError_t launch_msd_green(const MsdDims& m, int W, const MsdTables& t, const d
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+int msd_fb_splits(int W, int N, int K, int ldK, int ldpk, size_t scratch_doubles) {
+  const size_t gsd = (size_t)2 * W * ldpk, per = (size_t)2 * W * ldK;
+  if (scratch_doubles < gsd + per) return 0;
+  size_t sp = (scratch_doubles - gsd) / per;
+  const int npk = N * (N + 1) / 2;
+  const int maxs = (npk + 255) / 256;  // at least 256 pairs per split
+  if (sp > 8) sp = 8;
+  if ((int)sp > maxs) sp = maxs;
+  (void)K;
+  return (int)sp;
+}
+
+hipError_t launch_msd_force_bias(const MsdDims& m, int W, const double* theta, const double* qp, const double* lt,
+                                 int K, int ldK, int ldpk, int nsplit, double* scratch, double2* vbias,
+                                 hipStream_t s) {
+  double* gs = scratch;                               // [W][2][ldpk]
+  double* fbp = scratch + (size_t)2 * W * ldpk;      // [nsplit][2 W][ldK]
+  const int npk = m.N * (m.N + 1) / 2;
+  hipError_t e;
+  for (int z0 = 0; z0 < W; z0 += ZCHUNK) {
+    const int nz = W - z0 < ZCHUNK ? W - z0 : ZCHUNK;
+    MsdSProb ps{qp, theta, m.N, m.nmax, m.ldN, m.ldq, z0};
+    const int mt = (m.N + GBM - 1) / GBM, ntile = mt * ((2 * m.N + GBN - 1) / GBN);
+    const int nbp = (nz + NXCD - 1) / NXCD * NXCD;
+    hipLaunchKernelGGL(msd_gsym_kernel, dim3(ntile * nbp), dim3(GWM * GWN * 64), 0, s, m, ps, nz, mt, ntile, ldpk,
+                       gs);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  // the pair range of each split is a multiple of 16 (whole k steps, aligned operand rows)
+  int chunk = (npk + nsplit - 1) / nsplit;
+  chunk = (chunk + 15) / 16 * 16;
+  const int ns = (npk + chunk - 1) / chunk;
+  for (int z0 = 0; z0 < W; z0 += ZCHUNK) {
+    const int nz = W - z0 < ZCHUNK ? W - z0 : ZCHUNK;
+    MsdFbProb pf{gs, lt, 2 * nz, ldpk, ldK, z0, chunk, npk};
+    const dim3 grid((2 * nz + GBM - 1) / GBM, (K + GBN - 1) / GBN, ns);
+    hipLaunchKernelGGL(msd_fb_kernel, grid, dim3(GWM * GWN * 64), 0, s, pf, npk, K, W, fbp);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const long tot = (long)W * K;
+  hipLaunchKernelGGL(msd_fb_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, W, K, ldK, ns, fbp,
+                     vbias);
+  return hipGetLastError();
 }

@@ -197,3 +197,125 @@ def test_msd_at_n290_shape_sampled():
     msd = orc.msd_setup(C, C, n, n, coeff, rank, orbs)
     _compare(msd, lo[sample], Gs, pa[sample], pb[sample])
     t.close()
+
+
+# ---------------------------------------------------------------------------
+# Force bias of the multi-determinant trial (Eq. fb with the MSD G)
+# ---------------------------------------------------------------------------
+# Bar: vbias_g = sum_pq G_pq L_g,pq in FP64 on both sides; the GPU forms the
+# packed symmetric G from theta_0 and Q (each ~1e-14 relative, as above) and
+# contracts it with L.  Per (walker, g) the bar is 1e-12 times the
+# cancellation of the expansion times sum_s sum_pq |G^s_pq| |L_g,pq|.
+
+FB_CASES = [
+    # N, na, nb, K, ndet, max_rank, W
+    (12, 4, 3, 10, 40, 3, 5),
+    (37, 9, 6, 50, 300, 6, 37),
+    (64, 13, 11, 120, 500, 4, 70),
+]
+
+
+def _fb_problem(N, na, nb, K, ndet, max_rank, W, seed=0):
+    from paper_2209_04015_amd import afqmc
+
+    h1, L = inputs.hamiltonian(N, K, K / 5.0, seed=seed)
+    C_a = inputs.orbitals(h1)
+    C_b = inputs.orbitals(h1 + np.diag(np.linspace(0.0, 0.5, N)))
+    coeff, rank, orbs = inputs.msd_expansion(N, na, nb, ndet, max_rank=max_rank, seed=seed + 1)
+    pa = inputs.walkers_perturbed(C_a[:, :na], W, 0.3, seed=seed + 2, stream=0)
+    pb = inputs.walkers_perturbed(C_b[:, :nb], W, 0.3, seed=seed + 2, stream=1)
+    ham = afqmc.Hamiltonian(h1, L, C_a[:, :na], C_b[:, :nb], dt=0.005, max_walkers=W, precision="fp64")
+    t = afqmc.MSDTrial(C_a, C_b, na, nb, coeff, rank, orbs, max_walkers=W)
+    return h1, L, C_a, C_b, coeff, rank, orbs, pa, pb, ham, t
+
+
+def _fb_compare(msd, L, vb, pa, pb, rtol=1e-12):
+    ref = orc.msd_force_bias(msd, L, pa, pb)
+    G = orc.msd_green(msd, pa, pb)
+    scale = np.einsum("zspq,gpq->zg", np.abs(G), np.abs(L))
+    canc = _cancellation(msd, pa, pb)
+    err = np.abs(vb - ref)
+    print(f"[gpu] msd force bias error {(err / scale).max():.2e} of sum |G||L|", flush=True)
+    assert np.all(err <= rtol * canc[:, None] * scale)
+
+
+@pytest.mark.parametrize("N,na,nb,K,ndet,max_rank,W", FB_CASES)
+def test_msd_force_bias_matches_oracle(N, na, nb, K, ndet, max_rank, W):
+    from paper_2209_04015_amd import afqmc
+
+    print(f"[gpu] msd force bias N={N} na={na} nb={nb} K={K} ndet={ndet} W={W}", flush=True)
+    h1, L, C_a, C_b, coeff, rank, orbs, pa, pb, ham, t = _fb_problem(N, na, nb, K, ndet, max_rank, W)
+    w = afqmc.Walkers.from_numpy(pa, pb, device="cuda")
+    vb = t.force_bias(ham, w).cpu().numpy()
+    assert t.status() == 0
+    _fb_compare(orc.msd_setup(C_a, C_b, na, nb, coeff, rank, orbs), L, vb, pa, pb)
+    t.close()
+    ham.close()
+
+
+def test_msd_force_bias_leaves_the_hamiltonian_step_unchanged():
+    """The call borrows the Hamiltonian's VHS workspace; a step after it equals one without it."""
+    import torch
+    from paper_2209_04015_amd import afqmc
+
+    N, na, nb, K, W = 20, 5, 4, 30, 8
+    h1, L, C_a, C_b, coeff, rank, orbs, pa, pb, ham, t = _fb_problem(N, na, nb, K, 60, 3, W, seed=3)
+    x = torch.as_tensor(inputs.fields(W, K, 1, seed=2)[0], device="cuda")
+    print("[gpu] msd force bias then step", flush=True)
+
+    def run(between):
+        w = afqmc.Walkers.from_numpy(pa, pb, device="cuda")
+        ham.overlap(w)
+        between(w)
+        ham.step(w, x, reuse=False)
+        torch.cuda.synchronize()
+        return w.phi_a.cpu().numpy(), w.log_w.cpu().numpy()
+
+    a0, l0 = run(lambda w: None)
+    a1, l1 = run(lambda w: t.force_bias(ham, w))
+    assert np.array_equal(a0, a1) and np.array_equal(l0, l1)
+    t.close()
+    ham.close()
+
+
+def test_msd_force_bias_needs_an_fp64_hamiltonian():
+    from paper_2209_04015_amd import afqmc
+
+    N, na, nb, K = 12, 3, 3, 8
+    h1, L = inputs.hamiltonian(N, K, 2.0, seed=1)
+    C = inputs.orbitals(h1)
+    coeff, rank, orbs = inputs.msd_expansion(N, na, nb, 10, 2, seed=2)
+    ham = afqmc.Hamiltonian(h1, L, C[:, :na], C[:, :nb], dt=0.005, max_walkers=2, precision="fp32")
+    t = afqmc.MSDTrial(C, C, na, nb, coeff, rank, orbs, max_walkers=2)
+    w = afqmc.Walkers.from_numpy(inputs.walkers_perturbed(C[:, :na], 2, 0.2, seed=1),
+                                 inputs.walkers_perturbed(C[:, :nb], 2, 0.2, seed=1, stream=1), device="cuda")
+    with pytest.raises(afqmc.AfqmcError) as e:
+        t.force_bias(ham, w)
+    assert e.value.code == 4
+    t.close()
+    ham.close()
+
+
+def test_msd_force_bias_at_n290_shape_sampled():
+    """290 orbitals, 26 + 26 electrons, K = 2900, 512 walkers and 300
+    determinants in one call; the oracle checks two walkers."""
+    from paper_2209_04015_amd import afqmc
+
+    cfg = inputs.CONFIGS["n290"]
+    N, n, W, ndet = cfg.N, cfg.n, cfg.W, 300
+    h1, L = inputs.hamiltonian(N, cfg.K, cfg.decay, seed=0)
+    C = inputs.orbitals(h1)
+    coeff, rank, orbs = inputs.msd_expansion(N, n, n, ndet, max_rank=4, seed=5)
+    pa = inputs.walkers_perturbed(C[:, :n], W, 0.1, seed=6, stream=0)
+    pb = inputs.walkers_perturbed(C[:, :n], W, 0.1, seed=6, stream=1)
+    print("[gpu] msd force bias n290 W=512 ndet=300", flush=True)
+    ham = afqmc.Hamiltonian(h1, L, C[:, :n], C[:, :n], dt=cfg.dt, max_walkers=W, precision="fp64")
+    t = afqmc.MSDTrial(C, C, n, n, coeff, rank, orbs, max_walkers=W)
+    w = afqmc.Walkers.from_numpy(pa, pb, device="cuda")
+    vb = t.force_bias(ham, w).cpu().numpy()
+    assert t.status() == 0
+    sample = [0, 511]
+    msd = orc.msd_setup(C, C, n, n, coeff, rank, orbs)
+    _fb_compare(msd, L, vb[sample], pa[sample], pb[sample])
+    t.close()
+    ham.close()
