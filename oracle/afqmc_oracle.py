@@ -21,7 +21,8 @@ What it computes follows arXiv 2209.04015 (ipie):
 * Multi-determinant trial: Sec. III.A (the expansion and Eq. msdovlp) and
   the MSD Green's function of Sec. III.B, each taken by its definition, a
   sum over determinants (R23, R24); the generalised Wick's theorem that the
-  paper uses to evaluate them is not used here.
+  paper uses to evaluate them is not used here.  The phaseless step under
+  that trial (Sec. II.B) takes its force bias and overlap from them.
 
 Readings where the paper is silent (each is listed in the design doc as well):
 
@@ -117,6 +118,7 @@ __all__ = [
     "msd_overlap",
     "msd_green",
     "msd_force_bias",
+    "msd_propagate",
 ]
 
 
@@ -281,12 +283,19 @@ def propagate(ham, phi_a, phi_b, log_ovlp, log_w, x):
     Order: theta -> vbias -> xbar, xs, a -> VHS -> phi' = B phi ->
     ln O_z = log<Psi_T|phi'> - log<Psi_T|phi> -> phase -> log w.
     """
-    vb = force_bias(ham, phi_a, phi_b)
+    return _propagate(ham, lambda a, b: force_bias(ham, a, b), lambda a, b: overlap(ham, a, b),
+                      phi_a, phi_b, log_ovlp, log_w, x)
+
+
+def _propagate(ham, vbias_of, overlap_of, phi_a, phi_b, log_ovlp, log_w, x):
+    """The step of `propagate` with the trial entering only through the
+    force bias and the overlap (a single determinant, or R23's expansion)."""
+    vb = vbias_of(phi_a, phi_b)
     xs, a = shift(ham, vb, x)
     V = vhs(ham, xs)
     na = _b_apply(ham, V, phi_a)
     nb = _b_apply(ham, V, phi_b)
-    new_lo = overlap(ham, na, nb)
+    new_lo = overlap_of(na, nb)
     ln_o = new_lo - log_ovlp
     theta_ph = np.imag(ln_o)                       # arg O_z (Eq. theta, R8)
     cos_t = np.cos(theta_ph)
@@ -535,3 +544,14 @@ def msd_force_bias(msd, L, phi_a, phi_b):
     """vbias[z, g] = sum_s sum_pq G^s_pq L_g,pq with the MSD Green's function (Eq. fb, R24)."""
     G = msd_green(msd, phi_a, phi_b)
     return np.einsum("zspq,gpq->zg", G, L)
+
+
+def msd_propagate(ham, msd, phi_a, phi_b, log_ovlp, log_w, x):
+    """One phaseless step under the multi-determinant trial (Sec. II.B with
+    R23, R24): the force bias is Eq. fb with the MSD Green's function and the
+    overlap ratio of the importance function is that of the expansion; the
+    propagator is the Hamiltonian's (P, VHS, Taylor series).  log_ovlp holds
+    log <Psi_T|phi> of the expansion.  Returns new (phi_a, phi_b, log_ovlp, log_w).
+    """
+    return _propagate(ham, lambda a, b: msd_force_bias(msd, ham.L, a, b), lambda a, b: msd_overlap(msd, a, b),
+                      phi_a, phi_b, log_ovlp, log_w, x)

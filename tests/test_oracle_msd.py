@@ -196,3 +196,79 @@ def test_msd_expansion_format():
             key.append((tuple(h), tuple(sorted(q))))
         keys.add(tuple(key))
     assert len(keys) == len(coeff)
+
+
+# ---------------------------------------------------------------------------
+# Phaseless step under the multi-determinant trial (Sec. II.B with R23, R24)
+# ---------------------------------------------------------------------------
+
+def test_msd_propagate_with_one_reference_is_the_single_determinant_step():
+    N, na, nb, K, W = 10, 3, 2, 6, 3
+    h1, L, C_a, C_b = _orbitals(N, K=K, seed=15)
+    ham = orc.setup(h1, L, C_a[:, :na], C_b[:, :nb], dt=0.01)
+    msd = orc.OracleMSD((C_a, C_b), (na, nb), np.array([1.0]), [(((), ()), ((), ()))])
+    pa = _walkers(C_a, na, W, 15, 0, scale=0.3)
+    pb = _walkers(C_b, nb, W, 15, 1, scale=0.3)
+    lo = orc.overlap(ham, pa, pb)
+    lw = np.zeros(W)
+    x = inputs.fields(W, K, 1, seed=15)[0]
+    ref = orc.propagate(ham, pa, pb, lo, lw, x)
+    got = orc.msd_propagate(ham, msd, pa, pb, orc.msd_overlap(msd, pa, pb), lw, x)
+    for r, g in zip(ref, got):
+        assert np.allclose(g, r, rtol=1e-11, atol=1e-11)
+
+
+def test_msd_optimal_force_bias_cancels_first_order_field_dependence():
+    """With the MSD force bias, d ln I / dx = O(dt), not O(sqrt(dt)), where the
+    importance function carries the expansion's overlap (Eq. import, force bias)."""
+    N, na, nb, K = 8, 2, 2, 3
+    h1, L, C_a, C_b = _orbitals(N, K=K, seed=16)
+    coeff, rank, orbs = inputs.msd_expansion(N, na, nb, 12, max_rank=2, seed=16)
+    coeff = coeff * np.where(np.arange(len(coeff)) == 0, 1.0, 3.0)   # far from one determinant
+    msd = orc.msd_setup(C_a, C_b, na, nb, coeff, rank, orbs)
+    pa = _walkers(C_a, na, 1, 16, 0, scale=0.3)
+    pb = _walkers(C_b, nb, 1, 16, 1, scale=0.3)
+
+    def ln_i(ham, x):
+        vb = orc.msd_force_bias(msd, ham.L, pa, pb)
+        xs, a = orc.shift(ham, vb, x)
+        V = orc.vhs(ham, xs)
+        qa = orc._b_apply(ham, V, pa)
+        qb = orc._b_apply(ham, V, pb)
+        return orc.msd_overlap(msd, qa, qb) - orc.msd_overlap(msd, pa, pb) + a
+
+    grads = []
+    for dt in (1e-3, 1e-5):
+        ham = orc.setup(h1, L, C_a[:, :na], C_b[:, :nb], dt=dt, taylor_order=12)
+        g = []
+        for k in range(K):
+            e = np.zeros((1, K))
+            e[0, k] = 1e-3
+            g.append((ln_i(ham, e) - ln_i(ham, -e))[0] / 2e-3)
+        grads.append(np.linalg.norm(g))
+    assert grads[0] / grads[1] > 50.0        # O(dt); O(sqrt dt) would give ~10
+
+
+def test_msd_propagate_overlap_bookkeeping():
+    """The returned log overlap is the expansion's overlap of the new walkers,
+    and without the two-body part (L = 0) the weight follows in closed form."""
+    N, na, nb, K, W = 9, 3, 2, 2, 4
+    h1, _, C_a, C_b = _orbitals(N, K=K, seed=17)
+    L = np.zeros((K, N, N))
+    coeff, rank, orbs = inputs.msd_expansion(N, na, nb, 20, max_rank=2, seed=17)
+    msd = orc.msd_setup(C_a, C_b, na, nb, coeff, rank, orbs)
+    ham = orc.setup(h1, L, C_a[:, :na], C_b[:, :nb], dt=0.02)
+    pa = _walkers(C_a, na, W, 17, 0, scale=0.3)
+    pb = _walkers(C_b, nb, W, 17, 1, scale=0.3)
+    lo = orc.msd_overlap(msd, pa, pb)
+    lw = np.linspace(-0.3, 0.2, W)
+    na_, nb_, lo2, lw2 = orc.msd_propagate(ham, msd, pa, pb, lo, lw, np.zeros((W, K)))
+    # L = 0: B = P^2 (h' = h1), a = 0, and the new walkers are P^2 phi exactly
+    P2 = scipy.linalg.expm(-ham.dt * (h1 - ham.mu * np.eye(N)))
+    assert np.allclose(na_, P2 @ pa, atol=1e-12) and np.allclose(nb_, P2 @ pb, atol=1e-12)
+    assert np.allclose(lo2, orc.msd_overlap(msd, na_, nb_), atol=1e-12)
+    d = lo2 - lo
+    cos_t = np.cos(d.imag)
+    expect = lw + d.real - ham.dt * (ham.mu * (na + nb) - ham.e_shift) + np.log(np.where(cos_t > 0, cos_t, np.nan))
+    ok = cos_t > 0
+    assert np.allclose(lw2[ok], expect[ok], atol=1e-12) and np.all(lw2[~ok] == -np.inf)
