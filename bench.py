@@ -188,12 +188,22 @@ def run_msd(cfg, h1, L, device, steps, ndet=MSD_DETS):
     del G
     torch.cuda.empty_cache()
     ms_f = timed(lambda: trial.force_bias(ham, w, out=vb))
-    status = trial.status()
+    # phaseless steps under the trial, re-orthogonalised every step (the
+    # workload's schedule), from the expansion's overlap of these walkers
+    x = torch.as_tensor(inputs.fields(W, K, 1, seed=7)[0], device=device)
+    trial.overlap(w, out=w.log_ovlp)
+
+    def step():
+        trial.propagate(ham, w, x)
+        ham.orthogonalise(w)
+
+    ms_s = timed(step)
+    status = trial.status() | ham.status()
     trial.close()
     ham.close()
     torch.cuda.empty_cache()
     log(f"msd: overlap {ms_o:.3f} ms, Green's function {ms_g:.3f} ms, force bias {ms_f:.3f} ms per call, "
-        f"status {status}")
+        f"step {ms_s:.3f} ms, status {status}")
     gbytes = W * 2 * N * N * 16
     npk = N * (N + 1) // 2
     return {"workload": f"multi-determinant trial: {ndet} determinants (ranks <= 4 per spin) in the eigenvector "
@@ -210,6 +220,10 @@ def run_msd(cfg, h1, L, device, steps, ndet=MSD_DETS):
             "force_bias": {"value": round(W / (ms_f * 1e-3), 1), "unit": "walkers/s",
                            "ms_per_call": round(ms_f, 4),
                            "contraction_fp64_gflop": round(2 * 2 * W * npk * K / 1e9, 1)},
+            "step": {"value": round(W / (ms_s * 1e-3), 1), "unit": "walker-steps/s",
+                     "ms_per_step": round(ms_s, 4),
+                     "definition": "afqmc_msd_propagate (force bias, VHS, P T6(VHS) P, the expansion's overlap "
+                                   "ratio, weights) + QR; no local energy"},
             "status": status}
 
 

@@ -379,6 +379,23 @@ int afqmc_msd_green_function(afqmc_msd* t, const afqmc_walkers* w, int nw, void*
  * afqmc_step recomputes that workspace).  Asynchronous on `stream`. */
 int afqmc_msd_force_bias(afqmc_msd* t, afqmc_ham* ham, const afqmc_walkers* w, int nw, void* vbias, void* stream);
 
+/* One phaseless step under the multi-determinant trial (Sec. II.B with the
+ * force bias above and the expansion's overlap ratio): the same propagator
+ * as afqmc_propagate (P, VHS, Taylor series of `ham`), with
+ *   vbias = the multi-determinant force bias, and
+ *   ln O_z = log <Psi_T|phi'_z> - w->log_ovlp[z] from the expansion.
+ * w->phi_a, w->phi_b, w->log_ovlp (must hold log <Psi_T|phi> of the
+ * expansion, e.g. from afqmc_msd_overlap) and w->log_w are updated in place.
+ * fields: device [nw][K].  ham: FP64, with the trial's N, na and nb (its own
+ * trial orbitals are not used here except through its energy shift, a
+ * constant per step); ham's VHS and force-bias workspaces are used, so the
+ * call must not overlap another call on ham.  afqmc_orthogonalise(ham, ...)
+ * may follow: it rescales every determinant's overlap alike.  A walker with
+ * a singular reference overlap or a zero expansion sum is discarded
+ * (log_w = -inf) and sets AFQMC_STATUS_SINGULAR in the trial's status. */
+int afqmc_msd_propagate(afqmc_msd* t, afqmc_ham* ham, afqmc_walkers* w, int nw, const double* fields,
+                        void* stream);
+
 /* Excitation strings per spin after grouping (for sizing and reports). */
 int afqmc_msd_get_strings(afqmc_msd* t, int* nstr_a, int* nstr_b);
 /* Synchronise `stream`, return the accumulated status bits in *out and clear them. */

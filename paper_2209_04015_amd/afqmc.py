@@ -60,6 +60,7 @@ EXPORTED = (
     "afqmc_msd_overlap",
     "afqmc_msd_green_function",
     "afqmc_msd_force_bias",
+    "afqmc_msd_propagate",
     "afqmc_msd_get_strings",
     "afqmc_msd_get_status",
     "afqmc_msd_destroy",
@@ -149,6 +150,7 @@ def load(path: str = LIB_PATH):
     lib.afqmc_msd_overlap.argtypes = [vp, P(_Walkers), ip, vp, vp]
     lib.afqmc_msd_green_function.argtypes = [vp, P(_Walkers), ip, vp, vp]
     lib.afqmc_msd_force_bias.argtypes = [vp, vp, P(_Walkers), ip, vp, vp]
+    lib.afqmc_msd_propagate.argtypes = [vp, vp, P(_Walkers), ip, vp, vp]
     lib.afqmc_msd_get_strings.argtypes = [vp, P(ip), P(ip)]
     lib.afqmc_msd_get_status.argtypes = [vp, vp, P(ip)]
     lib.afqmc_msd_destroy.argtypes = [vp]
@@ -597,6 +599,16 @@ class MSDTrial:
         s = w._struct(self, nw)
         _check(_lib.afqmc_msd_force_bias(self._h, ham._h, ctypes.byref(s), nw, ptr, _stream_ptr(stream)))
         return out
+
+    def propagate(self, ham: "Hamiltonian", w: Walkers, fields, nw=None, stream=None):
+        """One phaseless step of w under this trial (ham: FP64); w.log_ovlp must
+        hold the expansion's log overlap (see overlap)."""
+        import torch
+
+        nw = w.W if nw is None else int(nw)
+        fp = _dev(fields, torch.float64, (nw, ham.K), "fields")
+        s = w._struct(self, nw)
+        _check(_lib.afqmc_msd_propagate(self._h, ham._h, ctypes.byref(s), nw, fp, _stream_ptr(stream)))
 
     def status(self, stream=None):
         v = ctypes.c_int()

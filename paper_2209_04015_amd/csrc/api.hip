@@ -1101,6 +1101,7 @@ struct afqmc_msd {
   double2* uw = nullptr;
   double2* rpart = nullptr;
   double2* ratio = nullptr;
+  double2* lpair = nullptr;  // [W][2] (log overlap, 0) for the weight update
   double* zt = nullptr;  // planar Zt [W][2][2][nmax][ldN]
   double* qp = nullptr;  // planar Q [W][2][2][N][ldq]
   int* status = nullptr;
@@ -1294,6 +1295,7 @@ int msd_workspace(afqmc_msd* t) {
   if ((rc = dalloc_t(t, &t->uw, W * m.nstr_tot))) return rc;
   if ((rc = dalloc_t(t, &t->rpart, W * msd_combine_blocks(m)))) return rc;
   if ((rc = dalloc_t(t, &t->ratio, W))) return rc;
+  if ((rc = dalloc_t(t, &t->lpair, W * 2))) return rc;
   if ((rc = dalloc_t(t, &t->zt, W * 4 * m.nmax * m.ldN))) return rc;
   if ((rc = dalloc_t(t, &t->qp, W * 4 * m.N * m.ldq))) return rc;
   if ((rc = dalloc_t(t, &t->status, (size_t)1))) return rc;
@@ -1318,6 +1320,34 @@ int msd_ratio(afqmc_msd* t, const afqmc_walkers* w, int nw, hipStream_t s) {
                              nullptr, t->status, s)));
   HIP_TRY(launch_msd_ratio(t->m, nw, t->t, t->theta, t->yp, t->sdet, t->sadj, t->tpart, t->uw, t->rpart,
                            t->ratio, s));
+  return AFQMC_OK;
+}
+
+// checks shared by the calls that combine the trial with a Hamiltonian
+int msd_check_ham(const afqmc_msd* t, const afqmc_ham* h, int nw, int* nsplit, int* ldpk) {
+  if (!h) return fail(AFQMC_EINVAL, "null Hamiltonian handle");
+  if (h->prec != AFQMC_FP64)
+    return fail(AFQMC_EUNSUPPORTED, "the multi-determinant force bias needs an FP64 Hamiltonian (its packed L)");
+  if (h->d.N != t->m.N) return fail(AFQMC_EINVAL, "orbital counts differ (%d, %d)", h->d.N, t->m.N);
+  if (nw > h->prm.max_walkers)
+    return fail(AFQMC_EINVAL, "nw = %d above the Hamiltonian's max_walkers = %d", nw, h->prm.max_walkers);
+  const int npk = t->m.N * (t->m.N + 1) / 2;
+  *ldpk = (npk + 15) / 16 * 16;
+  // scratch: the Hamiltonian's VHS workspace, idle outside its own steps
+  const size_t cap = (size_t)h->prm.max_walkers * h->d.N * h->d.ldV;
+  *nsplit = msd_fb_splits(nw > 0 ? nw : 1, t->m.N, h->d.K, h->d.ldK, *ldpk, cap);
+  if (*nsplit < 1) return fail(AFQMC_EUNSUPPORTED, "force-bias scratch does not fit the Hamiltonian's workspace");
+  return AFQMC_OK;
+}
+
+// vbias of the walkers w for the trial t into `vbias` (scratch: h's VHS workspace)
+int msd_vbias(afqmc_msd* t, afqmc_ham* h, const afqmc_walkers* w, int nw, int nsplit, int ldpk, double2* vbias,
+              hipStream_t s) {
+  int rc;
+  if ((rc = msd_ratio(t, w, nw, s))) return rc;
+  HIP_TRY(launch_msd_q(t->m, nw, t->t, t->yp, t->sadj, t->uw, t->ratio, t->zt, t->qp, s));
+  HIP_TRY(launch_msd_force_bias(t->m, nw, t->theta, t->qp, (const double*)h->LT, h->d.K, h->d.ldK, ldpk, nsplit,
+                                (double*)h->vhs, vbias, s));
   return AFQMC_OK;
 }
 
@@ -1397,27 +1427,35 @@ int afqmc_msd_green_function(afqmc_msd* t, const afqmc_walkers* w, int nw, void*
 int afqmc_msd_force_bias(afqmc_msd* t, afqmc_ham* h, const afqmc_walkers* w, int nw, void* vbias, void* stream) {
   int rc = msd_check(t, w, nw);
   if (rc) return rc;
-  if (!h) return fail(AFQMC_EINVAL, "null Hamiltonian handle");
-  if (h->prec != AFQMC_FP64)
-    return fail(AFQMC_EUNSUPPORTED, "the multi-determinant force bias needs an FP64 Hamiltonian (its packed L)");
-  if (h->d.N != t->m.N) return fail(AFQMC_EINVAL, "orbital counts differ (%d, %d)", h->d.N, t->m.N);
-  if (nw > h->prm.max_walkers)
-    return fail(AFQMC_EINVAL, "nw = %d above the Hamiltonian's max_walkers = %d", nw, h->prm.max_walkers);
+  int nsplit, ldpk;
+  if ((rc = msd_check_ham(t, h, nw, &nsplit, &ldpk))) return rc;
   if (nw == 0) return AFQMC_OK;
   if (!vbias) return fail(AFQMC_EINVAL, "null vbias");
-  const int npk = t->m.N * (t->m.N + 1) / 2;
-  const int ldpk = (npk + 15) / 16 * 16;
-  // scratch: the Hamiltonian's VHS workspace, idle outside its own steps
-  const size_t cap = (size_t)h->prm.max_walkers * h->d.N * h->d.ldV;
-  const int nsplit = msd_fb_splits(nw, t->m.N, h->d.K, h->d.ldK, ldpk, cap);
-  if (nsplit < 1) return fail(AFQMC_EUNSUPPORTED, "force-bias scratch does not fit the Hamiltonian's workspace");
+  return msd_vbias(t, h, w, nw, nsplit, ldpk, (double2*)vbias, (hipStream_t)stream);
+}
+
+int afqmc_msd_propagate(afqmc_msd* t, afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields, void* stream) {
+  int rc = msd_check(t, w, nw);
+  if (rc) return rc;
+  int nsplit, ldpk;
+  if ((rc = msd_check_ham(t, h, nw, &nsplit, &ldpk))) return rc;
+  if (h->d.na != t->m.na || h->d.nb != t->m.nb)
+    return fail(AFQMC_EINVAL, "electron counts differ (%d, %d) vs (%d, %d)", h->d.na, h->d.nb, t->m.na, t->m.nb);
+  if (nw == 0) return AFQMC_OK;
+  if (!fields) return fail(AFQMC_EINVAL, "null fields");
+  if (!w->log_ovlp || !w->log_w) return fail(AFQMC_EINVAL, "null walker array");
   hipStream_t s = (hipStream_t)stream;
+  if ((rc = msd_vbias(t, h, w, nw, nsplit, ldpk, h->vbias, s))) return rc;
+  StepIO io;
+  io.fields = fields;
+  if ((rc = seq_propagate_core<double>(h, w, nw, io, s))) return rc;
   if ((rc = msd_ratio(t, w, nw, s))) return rc;
-  HIP_TRY(launch_msd_q(t->m, nw, t->t, t->yp, t->sadj, t->uw, t->ratio, t->zt, t->qp, s));
-  HIP_TRY(launch_msd_force_bias(t->m, nw, t->theta, t->qp, (const double*)h->LT, h->d.K, h->d.ldK, ldpk, nsplit,
-                                (double*)h->vhs, (double2*)vbias, s));
+  HIP_TRY(launch_msd_overlap_pairs(nw, t->logdet, t->ratio, t->lpair, t->status, s));
+  HIP_TRY(launch_weight(nw, t->lpair, nullptr, h->a, (double2*)w->log_ovlp, w->log_w, h->cst, h->status, s));
+  h->c_valid = false;
   return AFQMC_OK;
 }
+
 
 int afqmc_msd_get_strings(afqmc_msd* t, int* nstr_a, int* nstr_b) {
   if (!t) return fail(AFQMC_EINVAL, "null multi-determinant trial handle");

@@ -220,6 +220,9 @@ hipError_t launch_msd_ratio(const MsdDims& m, int W, const MsdTables& t, const d
 // out [W] = logdet[z][0] + logdet[z][1] + log ratio[z]
 hipError_t launch_msd_overlap_store(int W, const double2* logdet, const double2* ratio, double2* out, int* status,
                                     hipStream_t s);
+// out [W][2] = (log <Psi_T|phi_z>, 0): the per-spin pair layout of the weight update
+hipError_t launch_msd_overlap_pairs(int W, const double2* logdet, const double2* ratio, double2* out, int* status,
+                                    hipStream_t s);
 // after launch_msd_ratio: planar Zt zt [W][2][2][nmax][ldN] (M / s in the
 // virtual columns, I - M Y / s in the occupied ones), planar Q qp
 // [W][2][2][N][ldq], G [W][2][N][N] complex

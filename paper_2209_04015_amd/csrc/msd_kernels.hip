@@ -733,6 +733,30 @@ hipError_t launch_msd_ratio(const MsdDims& m, int W, const MsdTables& t, const d
   return hipSuccess;
 }
 
+// (log <Psi_T|phi_z>, 0) pairs: the [W][2] per-spin layout the weight update reads
+__global__ void msd_overlap_pairs_kernel(int W, const double2* __restrict__ logdet, const double2* __restrict__ ratio,
+                                         double2* __restrict__ out, int* __restrict__ status) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= W) return;
+  const double2 r = ratio[z];
+  double2 lo = cadd(logdet[2 * z], logdet[2 * z + 1]);
+  if (cabs2(r) == 0.0) {
+    lo = make_double2(-INFINITY, 0.0);
+    atomicOr(status, AFQMC_STATUS_SINGULAR);
+  } else {
+    lo = cadd(lo, clog(r));
+  }
+  out[2 * z] = lo;
+  out[2 * z + 1] = make_double2(0.0, 0.0);
+}
+
+hipError_t launch_msd_overlap_pairs(int W, const double2* logdet, const double2* ratio, double2* out, int* status,
+                                    hipStream_t s) {
+  hipLaunchKernelGGL(msd_overlap_pairs_kernel, dim3((W + 255) / 256), dim3(256), 0, s, W, logdet, ratio, out,
+                     status);
+  return hipGetLastError();
+}
+
 hipError_t launch_msd_overlap_store(int W, const double2* logdet, const double2* ratio, double2* out, int* status,
                                     hipStream_t s) {
   hipLaunchKernelGGL(msd_overlap_kernel, dim3((W + 255) / 256), dim3(256), 0, s, W, logdet, ratio, out, status);

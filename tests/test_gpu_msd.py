@@ -319,3 +319,87 @@ def test_msd_force_bias_at_n290_shape_sampled():
     _fb_compare(msd, L, vb[sample], pa[sample], pb[sample])
     t.close()
     ham.close()
+
+
+# ---------------------------------------------------------------------------
+# Phaseless step under the multi-determinant trial (Sec. II.B)
+# ---------------------------------------------------------------------------
+# Bars as for the single-determinant step in FP64 (the same propagator
+# kernels; the force bias and overlap add errors of ~1e-15 relative):
+# orbitals 1e-11 of max|phi|, log overlap and log weight 1e-10 absolute.
+
+def _assert_step(w, ref, tol_phi=1e-11, tol_log=1e-10):
+    na, nb, lo, lw = ref
+    for g, r in ((w.phi_a.cpu().numpy(), na), (w.phi_b.cpu().numpy(), nb)):
+        scale = np.abs(r).reshape(r.shape[0], -1).max(axis=1)
+        err = np.abs(g - r).reshape(r.shape[0], -1).max(axis=1)
+        print(f"[gpu] msd step: max rel phi err {(err / scale).max():.3e}", flush=True)
+        assert np.all(err <= tol_phi * scale)
+    glo, glw = w.log_ovlp.cpu().numpy(), w.log_w.cpu().numpy()
+    assert np.abs(glo.real - lo.real).max() < tol_log
+    assert np.abs(np.exp(1j * (glo.imag - lo.imag)) - 1).max() < tol_log
+    live = np.isfinite(lw)
+    assert np.array_equal(np.isfinite(glw), live)
+    assert np.abs(glw[live] - lw[live]).max(initial=0.0) < tol_log
+
+
+@pytest.mark.parametrize("N,na,nb,K,ndet,max_rank,W", FB_CASES[:2])
+def test_msd_propagate_matches_oracle(N, na, nb, K, ndet, max_rank, W):
+    import torch
+    from paper_2209_04015_amd import afqmc
+
+    print(f"[gpu] msd step N={N} na={na} nb={nb} K={K} ndet={ndet} W={W}", flush=True)
+    h1, L, C_a, C_b, coeff, rank, orbs, pa, pb, ham, t = _fb_problem(N, na, nb, K, ndet, max_rank, W)
+    msd = orc.msd_setup(C_a, C_b, na, nb, coeff, rank, orbs)
+    oh = orc.setup(h1, L, C_a[:, :na], C_b[:, :nb], dt=0.005)
+    x = inputs.fields(W, K, 2, seed=4)
+    lw0 = np.linspace(-0.5, 0.5, W)
+    w = afqmc.Walkers.from_numpy(pa, pb, None, lw0, device="cuda")
+    t.overlap(w, out=w.log_ovlp)
+    t.propagate(ham, w, torch.as_tensor(x[0], device="cuda"))
+    ref = orc.msd_propagate(oh, msd, pa, pb, orc.msd_overlap(msd, pa, pb), lw0, x[0])
+    _assert_step(w, ref)
+    # re-orthogonalise, then a second step from the oracle's own first step
+    ham.orthogonalise(w)
+    qa, qb, lo = orc.orthogonalise(ref[0], ref[1], ref[2])
+    t.propagate(ham, w, torch.as_tensor(x[1], device="cuda"))
+    ref2 = orc.msd_propagate(oh, msd, qa, qb, lo, ref[3], x[1])
+    _assert_step(w, ref2, tol_phi=1e-10, tol_log=1e-9)
+    assert t.status() == 0
+    t.close()
+    ham.close()
+
+
+def test_msd_propagate_with_one_reference_equals_the_single_determinant_step():
+    """An expansion of the reference alone (c = 1) gives the Hamiltonian's own
+    step when the Hamiltonian's trial is that reference."""
+    import torch
+    from paper_2209_04015_amd import afqmc
+
+    N, na, nb, K, W = 30, 7, 6, 40, 16
+    h1, L = inputs.hamiltonian(N, K, K / 5.0, seed=9)
+    C = inputs.orbitals(h1)
+    pa = inputs.walkers_perturbed(C[:, :na], W, 0.3, seed=9, stream=0)
+    pb = inputs.walkers_perturbed(C[:, :nb], W, 0.3, seed=9, stream=1)
+    ham = afqmc.Hamiltonian(h1, L, C[:, :na], C[:, :nb], dt=0.005, max_walkers=W, precision="fp64")
+    t = afqmc.MSDTrial(C, C, na, nb, np.array([1.0]), np.zeros((1, 2), np.int32),
+                       np.full((1, 2, 2, inputs.MSD_MAX_RANK), -1, np.int32), max_walkers=W)
+    x = torch.as_tensor(inputs.fields(W, K, 1, seed=9)[0], device="cuda")
+    print("[gpu] msd step with one reference", flush=True)
+    w1 = afqmc.Walkers.from_numpy(pa, pb, device="cuda")
+    ham.overlap(w1)
+    ham.propagate(w1, x)
+    w2 = afqmc.Walkers.from_numpy(pa, pb, device="cuda")
+    t.overlap(w2, out=w2.log_ovlp)
+    t.propagate(ham, w2, x)
+    for a, b in ((w1.phi_a, w2.phi_a), (w1.phi_b, w2.phi_b)):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        assert np.abs(a - b).max() <= 1e-11 * np.abs(a).max()
+    l1, l2 = w1.log_w.cpu().numpy(), w2.log_w.cpu().numpy()
+    live = np.isfinite(l1)                          # the phaseless projection discards the same walkers
+    assert np.array_equal(live, np.isfinite(l2)) and live.any()
+    assert np.abs(l1[live] - l2[live]).max() < 1e-10
+    d = w1.log_ovlp.cpu().numpy() - w2.log_ovlp.cpu().numpy()
+    assert np.abs(d.real).max() < 1e-10 and np.abs(np.exp(1j * d.imag) - 1).max() < 1e-10
+    t.close()
+    ham.close()
