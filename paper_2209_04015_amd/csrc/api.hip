@@ -1125,6 +1125,31 @@ int msd_upload(afqmc_msd* t, const T** dst, const std::vector<T>& v) {
   return AFQMC_OK;
 }
 
+// Host-only check of the excitation format (before any device call).
+int msd_validate(int N, int na, int nb, int ndet, const int* rank, const int* orbs) {
+  const int nel[2] = {na, nb};
+  std::vector<char> used(N);
+  for (int a = 0; a < ndet; ++a) {
+    for (int s = 0; s < 2; ++s) {
+      const int k = rank[a * 2 + s];
+      const int n = nel[s];
+      if (k < 0 || k > MSD_KMAX || k > n || k > N - n)
+        return fail(AFQMC_EINVAL, "determinant %d spin %d: rank %d outside [0, min(%d, n, N - n)]", a, s, k,
+                    MSD_KMAX);
+      std::fill(used.begin(), used.end(), 0);
+      for (int x = 0; x < k; ++x) {
+        const int h = orbs[((a * 2 + s) * 2 + 0) * MSD_KMAX + x];
+        const int q = orbs[((a * 2 + s) * 2 + 1) * MSD_KMAX + x];
+        if (h < 0 || h >= n || q < n || q >= N || used[h] || used[q])
+          return fail(AFQMC_EINVAL, "determinant %d spin %d: invalid or repeated hole %d / particle %d", a, s,
+                      h, q);
+        used[h] = used[q] = 1;
+      }
+    }
+  }
+  return AFQMC_OK;
+}
+
 // Groups the determinants by per-spin excitation string and builds the
 // device tables (layouts in kernels.h).
 int msd_build(afqmc_msd* t, const double* C[2], const double* coeff, const int* rank, const int* orbs) {
@@ -1134,26 +1159,14 @@ int msd_build(afqmc_msd* t, const double* C[2], const double* coeff, const int* 
   std::map<std::vector<int>, int> sid[2];
   std::vector<std::vector<int>> strs[2];
   std::vector<int> dstr[2] = {std::vector<int>(ndet), std::vector<int>(ndet)};
-  std::vector<char> used(N);
   for (int a = 0; a < ndet; ++a) {
     for (int s = 0; s < 2; ++s) {
-      const int k = rank[a * 2 + s];
-      const int n = nel[s];
-      if (k < 0 || k > MSD_KMAX || k > n || k > N - n)
-        return fail(AFQMC_EINVAL, "determinant %d spin %d: rank %d outside [0, min(%d, n, N - n)]", a, s, k,
-                    MSD_KMAX);
+      const int k = rank[a * 2 + s];  // validated by msd_validate
       std::vector<int> key(1 + 2 * k);
       key[0] = k;
-      std::fill(used.begin(), used.end(), 0);
       for (int x = 0; x < k; ++x) {
-        const int h = orbs[((a * 2 + s) * 2 + 0) * MSD_KMAX + x];
-        const int q = orbs[((a * 2 + s) * 2 + 1) * MSD_KMAX + x];
-        if (h < 0 || h >= n || q < n || q >= N || used[h] || used[q])
-          return fail(AFQMC_EINVAL, "determinant %d spin %d: invalid or repeated hole %d / particle %d", a, s,
-                      h, q);
-        used[h] = used[q] = 1;
-        key[1 + x] = h;
-        key[1 + k + x] = q;
+        key[1 + x] = orbs[((a * 2 + s) * 2 + 0) * MSD_KMAX + x];
+        key[1 + k + x] = orbs[((a * 2 + s) * 2 + 1) * MSD_KMAX + x];
       }
       auto it = sid[s].find(key);
       if (it == sid[s].end()) {
@@ -1368,6 +1381,10 @@ int afqmc_msd_create(int N, int na, int nb, const double* host_C_a, const double
   if (max_walkers < 1) return fail(AFQMC_EINVAL, "max_walkers must be >= 1");
   if (!host_C_a || (nb > 0 && !host_C_b) || !host_coeff || !host_rank || !host_orbs)
     return fail(AFQMC_EINVAL, "null input pointer");
+  {
+    const int rv = msd_validate(N, na, nb, ndet, host_rank, host_orbs);
+    if (rv) return rv;
+  }
   afqmc_msd* t = new afqmc_msd();
   int rc = AFQMC_OK;
   if (hipGetDevice(&t->device) != hipSuccess) rc = fail(AFQMC_EHIP, "hipGetDevice failed");

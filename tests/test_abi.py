@@ -70,3 +70,44 @@ def test_init_rejects_bad_arguments_without_touching_the_device(lib):
                                            z.ctypes.data, z.ctypes.data, None, ctypes.byref(h))
     assert rc == 1
     assert not h.value
+
+
+def test_msd_create_rejects_bad_arguments_without_touching_the_device(lib):
+    """Sizes, null pointers and the excitation format are checked on the host
+    before any device call (so this runs without a GPU)."""
+    import numpy as np
+
+    afqmc.load()
+    N, na, nb, ndet = 10, 3, 2, 3
+    C = np.eye(N)
+    coeff = np.ones(ndet)
+    rank = np.zeros((ndet, 2), np.int32)
+    orbs = np.full((ndet, 2, 2, afqmc.MSD_MAX_RANK), -1, np.int32)
+
+    def create(N=N, na=na, nb=nb, ndet=ndet, rank=rank, orbs=orbs, coeff=coeff, C=C):
+        h = ctypes.c_void_p()
+        rc = afqmc._lib.afqmc_msd_create(N, na, nb, C.ctypes.data, C.ctypes.data, ndet, coeff.ctypes.data,
+                                         rank.ctypes.data, orbs.ctypes.data, 4, None, ctypes.byref(h))
+        return rc, afqmc._lib.afqmc_last_error().decode(), h.value
+
+    assert create(N=0)[0] == 1
+    assert create(na=11)[0] == 1                    # more electrons than orbitals
+    assert create(na=46, N=60)[0] == 4              # beyond the kernels' electron limit
+    assert create(ndet=0)[0] == 1
+    bad = rank.copy(); bad[1, 0] = 7
+    rc, msg, h = create(rank=bad)
+    assert rc == 1 and "determinant 1" in msg and h is None
+    r2, o2 = rank.copy(), orbs.copy()
+    r2[2, 1] = 1; o2[2, 1, 0, 0] = 0; o2[2, 1, 1, 0] = 1     # particle inside the reference
+    rc, msg, h = create(rank=r2, orbs=o2)
+    assert rc == 1 and "determinant 2 spin 1" in msg and h is None
+
+
+def test_msd_calls_reject_a_null_handle(lib):
+    afqmc.load()
+    w = afqmc._Walkers()
+    assert afqmc._lib.afqmc_msd_overlap(None, ctypes.byref(w), 1, ctypes.c_void_p(1), None) == 1
+    assert afqmc._lib.afqmc_msd_green_function(None, ctypes.byref(w), 1, ctypes.c_void_p(1), None) == 1
+    assert afqmc._lib.afqmc_msd_force_bias(None, None, ctypes.byref(w), 1, ctypes.c_void_p(1), None) == 1
+    assert afqmc._lib.afqmc_msd_propagate(None, None, ctypes.byref(w), 1, ctypes.c_void_p(1), None) == 1
+    afqmc._lib.afqmc_msd_destroy(None)              # no-op
