@@ -227,6 +227,78 @@ def run_msd(cfg, h1, L, device, steps, ndet=MSD_DETS):
             "status": status}
 
 
+def run_batch(device, steps, precision="fp16x3"):
+    """The uneven multi-system workload (8 systems, N = 40 .. 200) advanced
+    together by one hipGraph launch per step (autotuned exchange tile order),
+    QR and local energy every step; and the same steps taken system after
+    system with afqmc_step on one stream, for comparison."""
+    import torch
+
+    from paper_2209_04015_amd import afqmc, inputs
+
+    t = time.time()
+    systems = inputs.uneven_batch()
+    hams, ws, fs, es, starts = [], [], [], [], []
+    for (N, n, K, decay, W, seed) in systems:
+        h1, L = inputs.hamiltonian(N, K, decay, seed=seed)
+        phiT = inputs.trial(h1, n)
+        ham = afqmc.Hamiltonian(h1, L, phiT, phiT, dt=0.005, max_walkers=W, precision=precision)
+        pa = np.repeat(phiT[None].astype(np.complex128), W, axis=0)
+        w = afqmc.Walkers.from_numpy(pa, pa.copy(), device=device)
+        ham.overlap(w)
+        hams.append(ham)
+        ws.append(w)
+        starts.append((w.phi_a.clone(), w.phi_b.clone(), w.log_ovlp.clone(), w.log_w.clone()))
+        fs.append(torch.as_tensor(inputs.fields(W, K, steps, seed=seed), device=device))
+        es.append(torch.empty((steps, W, 3), dtype=torch.complex128, device=device))
+    wtot = sum(s[4] for s in systems)
+    log(f"batch: {len(systems)} systems, {wtot} walkers, set up in {time.time() - t:.1f} s")
+    b = afqmc.Batch(hams, ws, use_graph=True)
+    b.autotune()
+    stream = torch.cuda.current_stream()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    b.step(fs, es, do_qr=True)          # capture + first replays (untimed)
+    torch.cuda.synchronize()
+    start.record(stream)
+    b.step(fs, es, do_qr=True)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_b = start.elapsed_time(stop)
+    st_b = sum(h.status() for h in hams)
+    b.close()
+    # the same steps system after system (eager, one stream), from the same start
+    for w, (a0, b0, l0, lw0) in zip(ws, starts):
+        w.phi_a.copy_(a0)
+        w.phi_b.copy_(b0)
+        w.log_ovlp.copy_(l0)
+        w.log_w.copy_(lw0)
+
+    def seq():
+        for ham, w, f, e in zip(hams, ws, fs, es):
+            for k in range(steps):
+                ham.step(w, f[k], do_qr=True, energy_out=e[k], reuse=k > 0)
+
+    seq()
+    torch.cuda.synchronize()
+    start.record(stream)
+    seq()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_s = start.elapsed_time(stop)
+    for h in hams:
+        h.close()
+    torch.cuda.empty_cache()
+    log(f"batch: {steps} steps in {ms_b:.1f} ms (graph) vs {ms_s:.1f} ms (systems in turn)")
+    return {"workload": "uneven multi-system batch: 8 systems, N = 40, 60, ..., 160, 200, n = N/5, K = 4N, "
+                        f"walkers {[s[4] for s in systems]}, {precision}, QR and local energy every step, "
+                        "one hipGraph launch per step, autotuned exchange tile order",
+            "value": round(wtot * steps / (ms_b * 1e-3), 1), "unit": "walker-steps/s",
+            "ms_per_step": round(ms_b / steps, 4), "status": st_b,
+            "systems_in_turn": {"value": round(wtot * steps / (ms_s * 1e-3), 1), "unit": "walker-steps/s",
+                                "ms_per_step": round(ms_s / steps, 4)}}
+
+
 # Sources that define each roofline kernel: its HBM traffic figure (from the
 # rocprofv3 counter summaries under profiles/) is used only while these are
 # unchanged since the counters were taken.
@@ -384,6 +456,7 @@ def main():
     ap.add_argument("--msd-only", action="store_true",
                     help="time the multi-determinant trial calls only (profiling runs)")
     ap.add_argument("--msd-dets", type=int, default=MSD_DETS, help="determinants of the multi-determinant trial")
+    ap.add_argument("--batch-only", action="store_true", help="time the uneven multi-system batch only")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -419,6 +492,9 @@ def main():
     if args.msd_only:
         print(json.dumps({"msd": run_msd(cfg, h1, L, device, args.steps, args.msd_dets)}), flush=True)
         return
+    if args.batch_only:
+        print(json.dumps({"uneven_batch": run_batch(device, args.steps)}), flush=True)
+        return
 
     results = {}
     extras = {}
@@ -451,6 +527,7 @@ def main():
         torch.cuda.empty_cache()
 
     msd = None if args.only else run_msd(cfg, h1, L, device, args.steps, args.msd_dets)
+    batch = None if args.only else run_batch(device, args.steps)
 
     if args.only:
         ms, ph, st = results[args.only]
@@ -526,6 +603,7 @@ def main():
         "phases_ms_per_step": phase_table(phh),
         "direct_exchange": direct,
         "multi_determinant_trial": msd,
+        "uneven_batch": batch,
         "paths": paths,
         "algorithmic_gflop_per_walker_step": {k: round(v / 1e9, 4) for k, v in fl.items()},
         "status": sth,

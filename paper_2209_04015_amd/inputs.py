@@ -45,6 +45,7 @@ __all__ = [
     "fields",
     "walkers_at_trial",
     "walkers_perturbed",
+    "uneven_batch",
     "MSD_MAX_RANK",
     "orbitals",
     "msd_expansion",
@@ -139,6 +140,19 @@ def walkers_perturbed(phiT: np.ndarray, W: int, scale: float, seed: int = 0,
     else:
         r = rng.standard_normal((W, N, n)).astype(np.complex128)
     return phiT[None, :, :] + scale * r
+
+
+def uneven_batch(seed: int = 0):
+    """The uneven multi-system workload: 8 systems with N in {40, 60, ..., 160, 200},
+    n = N / 5 electrons per spin, K = 4 N, decay = K / 5; walkers per system
+    drawn from {64, ..., 512} with the auxiliary stream of `seed`.  System s
+    draws its Hamiltonian and fields with seed s.  Returns a list of
+    (N, n, K, decay, walkers, seed)."""
+    _, _, aux_ss = _streams(seed)
+    rng = np.random.default_rng(aux_ss)
+    sizes = [40, 60, 80, 100, 120, 140, 160, 200]
+    walkers = rng.integers(64, 513, size=len(sizes))
+    return [(N, N // 5, 4 * N, 4 * N / 5.0, int(w), s) for s, (N, w) in enumerate(zip(sizes, walkers))]
 
 
 MSD_MAX_RANK = 6  # excitation rank per spin supported by the expansion format
