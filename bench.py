@@ -199,11 +199,22 @@ def run_msd(cfg, h1, L, device, steps, ndet=MSD_DETS):
 
     ms_s = timed(step)
     status = trial.status() | ham.status()
-    trial.close()
     ham.close()
+    # the same step on the FP32 path (FP32 packed L, FP32 VHS and Taylor products)
+    ham32 = afqmc.Hamiltonian(h1, L, C[:, :n], C[:, :n], dt=cfg.dt, max_walkers=W, precision="fp32")
+    trial.overlap(w, out=w.log_ovlp)
+
+    def step32():
+        trial.propagate(ham32, w, x)
+        ham32.orthogonalise(w)
+
+    ms_s32 = timed(step32)
+    status |= trial.status() | ham32.status()
+    ham32.close()
+    trial.close()
     torch.cuda.empty_cache()
     log(f"msd: overlap {ms_o:.3f} ms, Green's function {ms_g:.3f} ms, force bias {ms_f:.3f} ms per call, "
-        f"step {ms_s:.3f} ms, status {status}")
+        f"step {ms_s:.3f} ms (FP32 path {ms_s32:.3f} ms), status {status}")
     gbytes = W * 2 * N * N * 16
     npk = N * (N + 1) // 2
     return {"workload": f"multi-determinant trial: {ndet} determinants (ranks <= 4 per spin) in the eigenvector "
@@ -223,7 +234,10 @@ def run_msd(cfg, h1, L, device, steps, ndet=MSD_DETS):
             "step": {"value": round(W / (ms_s * 1e-3), 1), "unit": "walker-steps/s",
                      "ms_per_step": round(ms_s, 4),
                      "definition": "afqmc_msd_propagate (force bias, VHS, P T6(VHS) P, the expansion's overlap "
-                                   "ratio, weights) + QR; no local energy"},
+                                   "ratio, weights) + QR; no local energy; FP64 path"},
+            "step_fp32": {"value": round(W / (ms_s32 * 1e-3), 1), "unit": "walker-steps/s",
+                          "ms_per_step": round(ms_s32, 4),
+                          "definition": "the same on the FP32 path (FP32 packed L, VHS and Taylor products)"},
             "status": status}
 
 

@@ -372,8 +372,10 @@ int afqmc_msd_green_function(afqmc_msd* t, const afqmc_walkers* w, int nw, void*
 /* Force bias of the multi-determinant trial (Eq. fb with the G above):
  *   vbias[z][g] = sum_s sum_pq G^s_pq L_g,pq,
  * formed from the packed symmetric sum_s (G^s + G^s^T) and the packed L of
- * `ham` without storing G.  ham: an FP64 Hamiltonian (AFQMC_EUNSUPPORTED
- * otherwise) with the same N; nw <= both handles' max_walkers.  vbias:
+ * `ham` without storing G.  ham: an FP64, FP32 or BF16X3 Hamiltonian with
+ * the same N (its packed L: FP64, or FP32 with the packed G rounded to FP32
+ * and FP32 accumulation on the matrix cores; FP16X3 keeps no FP32 packed L:
+ * AFQMC_EUNSUPPORTED); nw <= both handles' max_walkers.  vbias:
  * device complex [nw][K], written.  The call uses ham's VHS workspace as
  * scratch: it must not overlap a call on the same Hamiltonian (the next
  * afqmc_step recomputes that workspace).  Asynchronous on `stream`. */
@@ -386,7 +388,8 @@ int afqmc_msd_force_bias(afqmc_msd* t, afqmc_ham* ham, const afqmc_walkers* w, i
  *   ln O_z = log <Psi_T|phi'_z> - w->log_ovlp[z] from the expansion.
  * w->phi_a, w->phi_b, w->log_ovlp (must hold log <Psi_T|phi> of the
  * expansion, e.g. from afqmc_msd_overlap) and w->log_w are updated in place.
- * fields: device [nw][K].  ham: FP64, with the trial's N, na and nb (its own
+ * fields: device [nw][K].  ham: FP64, FP32 or BF16X3 (its working precision
+ * for the force bias, VHS and Taylor products), with the trial's N, na and nb (its own
  * trial orbitals are not used here except through its energy shift, a
  * constant per step); ham's VHS and force-bias workspaces are used, so the
  * call must not overlap another call on ham.  afqmc_orthogonalise(ham, ...)

@@ -1339,16 +1339,17 @@ int msd_ratio(afqmc_msd* t, const afqmc_walkers* w, int nw, hipStream_t s) {
 // checks shared by the calls that combine the trial with a Hamiltonian
 int msd_check_ham(const afqmc_msd* t, const afqmc_ham* h, int nw, int* nsplit, int* ldpk) {
   if (!h) return fail(AFQMC_EINVAL, "null Hamiltonian handle");
-  if (h->prec != AFQMC_FP64)
-    return fail(AFQMC_EUNSUPPORTED, "the multi-determinant force bias needs an FP64 Hamiltonian (its packed L)");
+  if (h->prec != AFQMC_FP64 && h->prec != AFQMC_FP32 && h->prec != AFQMC_BF16X3)
+    return fail(AFQMC_EUNSUPPORTED,
+                "the multi-determinant force bias needs the packed L of an FP64, FP32 or BF16X3 Hamiltonian");
   if (h->d.N != t->m.N) return fail(AFQMC_EINVAL, "orbital counts differ (%d, %d)", h->d.N, t->m.N);
   if (nw > h->prm.max_walkers)
     return fail(AFQMC_EINVAL, "nw = %d above the Hamiltonian's max_walkers = %d", nw, h->prm.max_walkers);
   const int npk = t->m.N * (t->m.N + 1) / 2;
   *ldpk = (npk + 15) / 16 * 16;
   // scratch: the Hamiltonian's VHS workspace, idle outside its own steps
-  const size_t cap = (size_t)h->prm.max_walkers * h->d.N * h->d.ldV;
-  *nsplit = msd_fb_splits(nw > 0 ? nw : 1, t->m.N, h->d.K, h->d.ldK, *ldpk, cap);
+  const size_t cap = (size_t)h->prm.max_walkers * h->d.N * h->d.ldV * h->tsize;
+  *nsplit = msd_fb_splits(nw > 0 ? nw : 1, t->m.N, h->d.K, h->d.ldK, *ldpk, h->tsize, cap);
   if (*nsplit < 1) return fail(AFQMC_EUNSUPPORTED, "force-bias scratch does not fit the Hamiltonian's workspace");
   return AFQMC_OK;
 }
@@ -1359,8 +1360,13 @@ int msd_vbias(afqmc_msd* t, afqmc_ham* h, const afqmc_walkers* w, int nw, int ns
   int rc;
   if ((rc = msd_ratio(t, w, nw, s))) return rc;
   HIP_TRY(launch_msd_q(t->m, nw, t->t, t->yp, t->sadj, t->uw, t->ratio, t->zt, t->qp, s));
-  HIP_TRY(launch_msd_force_bias(t->m, nw, t->theta, t->qp, (const double*)h->LT, h->d.K, h->d.ldK, ldpk, nsplit,
-                                (double*)h->vhs, vbias, s));
+  if (h->prec == AFQMC_FP64) {
+    HIP_TRY(launch_msd_force_bias<double>(t->m, nw, t->theta, t->qp, (const double*)h->LT, h->d.K, h->d.ldK, ldpk,
+                                          nsplit, h->vhs, vbias, s));
+  } else {
+    HIP_TRY(launch_msd_force_bias<float>(t->m, nw, t->theta, t->qp, (const float*)h->LT, h->d.K, h->d.ldK, ldpk,
+                                         nsplit, h->vhs, vbias, s));
+  }
   return AFQMC_OK;
 }
 
@@ -1465,7 +1471,11 @@ int afqmc_msd_propagate(afqmc_msd* t, afqmc_ham* h, afqmc_walkers* w, int nw, co
   if ((rc = msd_vbias(t, h, w, nw, nsplit, ldpk, h->vbias, s))) return rc;
   StepIO io;
   io.fields = fields;
-  if ((rc = seq_propagate_core<double>(h, w, nw, io, s))) return rc;
+  if (h->prec == AFQMC_FP64)
+    rc = seq_propagate_core<double>(h, w, nw, io, s);
+  else
+    rc = seq_propagate_core<float>(h, w, nw, io, s);
+  if (rc) return rc;
   if ((rc = msd_ratio(t, w, nw, s))) return rc;
   HIP_TRY(launch_msd_overlap_pairs(nw, t->logdet, t->ratio, t->lpair, t->status, s));
   HIP_TRY(launch_weight(nw, t->lpair, nullptr, h->a, (double2*)w->log_ovlp, w->log_w, h->cst, h->status, s));

@@ -232,11 +232,12 @@ hipError_t launch_msd_green(const MsdDims& m, int W, const MsdTables& t, const d
 // after launch_msd_ratio: M / s and the occupied block into zt, Q into qp
 hipError_t launch_msd_q(const MsdDims& m, int W, const MsdTables& t, const double* yp, const double2* sadj,
                         const double2* uw, const double2* ratio, double* zt, double* qp, hipStream_t s);
-// pair-range splits of the force-bias GEMM that fit a scratch of scratch_doubles (0: does not fit)
-int msd_fb_splits(int W, int N, int K, int ldK, int ldpk, size_t scratch_doubles);
+// pair-range splits of the force-bias GEMM whose scratch (packed G of gs_elem_bytes
+// per value, then FP64 partials) fits scratch_bytes (0: does not fit)
+int msd_fb_splits(int W, int N, int K, int ldK, int ldpk, size_t gs_elem_bytes, size_t scratch_bytes);
 // after launch_msd_q: vbias [W][K] complex = sum_s sum_pq G^s_pq L_g,pq through the packed
-// symmetric G (scratch: [W][2][ldpk] then [nsplit][2 W][ldK] doubles) and the FP64 packed L
-// lt [N (N + 1) / 2][ldK] (row-major upper triangle)
-hipError_t launch_msd_force_bias(const MsdDims& m, int W, const double* theta, const double* qp, const double* lt,
-                                 int K, int ldK, int ldpk, int nsplit, double* scratch, double2* vbias,
-                                 hipStream_t s);
+// symmetric G (scratch: [W][2][ldpk] values of T, then [nsplit][2 W][ldK] doubles) and the
+// packed L lt [N (N + 1) / 2][ldK] of type T (row-major upper triangle)
+template <typename T>
+hipError_t launch_msd_force_bias(const MsdDims& m, int W, const double* theta, const double* qp, const T* lt, int K,
+                                 int ldK, int ldpk, int nsplit, void* scratch, double2* vbias, hipStream_t s);

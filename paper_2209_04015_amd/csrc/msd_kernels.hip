@@ -582,8 +582,9 @@ struct MsdSProb {
   }
 };
 
+template <typename GT>
 __global__ __launch_bounds__(GWM* GWN * 64) void msd_gsym_kernel(MsdDims m, MsdSProb p, int nz, int mt, int ntile,
-                                                                 int ldpk, double* __restrict__ gs) {
+                                                                 int ldpk, GT* __restrict__ gs) {
   __shared__ __attribute__((aligned(16))) double lds[TileLds<double, GBM, GBN, GBK>::ELEMS];
   MF<double>::acc_t acc[GBM / GWM / 16][GBN / GWN / 16];
   const int L = blockIdx.x;
@@ -606,46 +607,61 @@ __global__ __launch_bounds__(GWM* GWN * 64) void msd_gsym_kernel(MsdDims m, MsdS
       const int col = n0 + wn * (GBN / GWN) + jj * 16 + (lane & 15);
       const int q = col >> 1, part = col & 1;
       if (q >= N) continue;
-      double* dst = gs + (size_t)(2 * z + part) * ldpk;
+      GT* dst = gs + (size_t)(2 * z + part) * ldpk;
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
         const int pp = pb + rr;
         if (pp > q) continue;
         const long idx = (long)pp * (2 * N - pp + 1) / 2 + (q - pp);  // row-major upper triangle
-        dst[idx] = (pp == q ? 0.5 : 1.0) * acc[i][jj][rr];
+        dst[idx] = (GT)((pp == q ? 0.5 : 1.0) * acc[i][jj][rr]);
       }
     }
 }
 
 // vbias rows (z, re | im) = gs rows . packed L, split over the pair index into
-// nsplit ranges of `chunk` pairs; partials fbp[split][2 z + c][ldK].
+// nsplit ranges of `chunk` pairs; partials fbp[split][2 z + c][ldK].  T is the
+// type of both operands (FP64, or FP32 with the FP32 packed L of the mixed
+// paths; accumulation in T on the matrix cores, partials summed in FP64).
+template <typename T>
 struct MsdFbProb {
-  const double* gs;
-  const double* lt;
+  using vec_t = typename MF<T>::vec_t;
+  static constexpr int VEC = MF<T>::VEC;
+  const T* gs;
+  const T* lt;
   int rows, ldpk, ldK, z0, chunk, npk;
-  __device__ double2 load_a(int split, int r, int k) const {
-    if (r >= rows) return make_double2(0.0, 0.0);
+  __device__ vec_t load_a(int split, int r, int k) const {
+    if (r >= rows) return MF<T>::vzero();
     const int kk = split * chunk + k;
-    const double* row = gs + (size_t)(2 * z0 + r) * ldpk;
+    const T* row = gs + (size_t)(2 * z0 + r) * ldpk;
     // entries past the packed triangle are not written (the scratch is reused): read as zero
-    if (kk + 1 >= npk) return make_double2(row[kk], 0.0);
-    return *reinterpret_cast<const double2*>(row + kk);
+    if (kk + VEC > npk) {
+      T v[4] = {T(0), T(0), T(0), T(0)};
+      for (int e = 0; e < VEC; ++e)
+        if (kk + e < npk) v[e] = row[kk + e];
+      if constexpr (VEC == 4)
+        return make_float4(v[0], v[1], v[2], v[3]);
+      else
+        return make_double2(v[0], v[1]);
+    }
+    return *reinterpret_cast<const vec_t*>(row + kk);
   }
-  __device__ double2 load_b_km(int split, int k, int g) const {
-    if (g >= ldK) return make_double2(0.0, 0.0);
-    return *reinterpret_cast<const double2*>(lt + ((size_t)split * chunk + k) * ldK + g);
+  __device__ vec_t load_b_km(int split, int k, int g) const {
+    if (g >= ldK) return MF<T>::vzero();
+    return *reinterpret_cast<const vec_t*>(lt + ((size_t)split * chunk + k) * ldK + g);
   }
 };
 
-__global__ __launch_bounds__(GWM* GWN * 64) void msd_fb_kernel(MsdFbProb p, int npk, int K, int W,
+template <typename T>
+__global__ __launch_bounds__(GWM* GWN * 64) void msd_fb_kernel(MsdFbProb<T> p, int npk, int K, int W,
                                                                double* __restrict__ fbp) {
-  __shared__ __attribute__((aligned(16))) double lds[TileLds<double, GBM, GBN, GBK>::ELEMS];
-  MF<double>::acc_t acc[GBM / GWM / 16][GBN / GWN / 16];
+  constexpr int BK = sizeof(T) == 4 ? 32 : 16;
+  __shared__ __attribute__((aligned(16))) T lds[TileLds<T, GBM, GBN, BK>::ELEMS];
+  typename MF<T>::acc_t acc[GBM / GWM / 16][GBN / GWN / 16];
   const int split = blockIdx.z;
   const int k0 = split * p.chunk;
   const int kdim = npk - k0 < p.chunk ? npk - k0 : p.chunk;
   const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
-  mfma_tile_mainloop<double, GBM, GBN, GBK, GWM, GWN, true>(p, split, m0, n0, kdim, acc, lds);
+  mfma_tile_mainloop<T, GBM, GBN, BK, GWM, GWN, true>(p, split, m0, n0, kdim, acc, lds);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int wm = wid / GWN, wn = wid % GWN;
   double* out = fbp + (size_t)split * 2 * W * p.ldK;
@@ -658,7 +674,7 @@ __global__ __launch_bounds__(GWM* GWN * 64) void msd_fb_kernel(MsdFbProb p, int 
       if (g >= K) continue;
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr)
-        if (rb + rr < p.rows) out[(size_t)(2 * p.z0 + rb + rr) * p.ldK + g] = acc[i][jj][rr];
+        if (rb + rr < p.rows) out[(size_t)(2 * p.z0 + rb + rr) * p.ldK + g] = (double)acc[i][jj][rr];
     }
 }
 
@@ -806,10 +822,10 @@ hipError_t launch_msd_green(const MsdDims& m, int W, const MsdTables& t, const d
   return hipSuccess;
 }
 
-int msd_fb_splits(int W, int N, int K, int ldK, int ldpk, size_t scratch_doubles) {
-  const size_t gsd = (size_t)2 * W * ldpk, per = (size_t)2 * W * ldK;
-  if (scratch_doubles < gsd + per) return 0;
-  size_t sp = (scratch_doubles - gsd) / per;
+int msd_fb_splits(int W, int N, int K, int ldK, int ldpk, size_t gs_elem_bytes, size_t scratch_bytes) {
+  const size_t gsb = (size_t)2 * W * ldpk * gs_elem_bytes, per = (size_t)2 * W * ldK * sizeof(double);
+  if (scratch_bytes < gsb + per) return 0;
+  size_t sp = (scratch_bytes - gsb) / per;
   const int npk = N * (N + 1) / 2;
   const int maxs = (npk + 255) / 256;  // at least 256 pairs per split
   if (sp > 8) sp = 8;
@@ -818,11 +834,11 @@ int msd_fb_splits(int W, int N, int K, int ldK, int ldpk, size_t scratch_doubles
   return (int)sp;
 }
 
-hipError_t launch_msd_force_bias(const MsdDims& m, int W, const double* theta, const double* qp, const double* lt,
-                                 int K, int ldK, int ldpk, int nsplit, double* scratch, double2* vbias,
-                                 hipStream_t s) {
-  double* gs = scratch;                               // [W][2][ldpk]
-  double* fbp = scratch + (size_t)2 * W * ldpk;      // [nsplit][2 W][ldK]
+template <typename T>
+hipError_t launch_msd_force_bias(const MsdDims& m, int W, const double* theta, const double* qp, const T* lt, int K,
+                                 int ldK, int ldpk, int nsplit, void* scratch, double2* vbias, hipStream_t s) {
+  T* gs = reinterpret_cast<T*>(scratch);  // [W][2][ldpk]
+  double* fbp = reinterpret_cast<double*>(gs + (size_t)2 * W * ldpk);  // [nsplit][2 W][ldK]
   const int npk = m.N * (m.N + 1) / 2;
   hipError_t e;
   for (int z0 = 0; z0 < W; z0 += ZCHUNK) {
@@ -830,19 +846,19 @@ hipError_t launch_msd_force_bias(const MsdDims& m, int W, const double* theta, c
     MsdSProb ps{qp, theta, m.N, m.nmax, m.ldN, m.ldq, z0};
     const int mt = (m.N + GBM - 1) / GBM, ntile = mt * ((2 * m.N + GBN - 1) / GBN);
     const int nbp = (nz + NXCD - 1) / NXCD * NXCD;
-    hipLaunchKernelGGL(msd_gsym_kernel, dim3(ntile * nbp), dim3(GWM * GWN * 64), 0, s, m, ps, nz, mt, ntile, ldpk,
+    hipLaunchKernelGGL(msd_gsym_kernel<T>, dim3(ntile * nbp), dim3(GWM * GWN * 64), 0, s, m, ps, nz, mt, ntile, ldpk,
                        gs);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   // the pair range of each split is a multiple of 16 (whole k steps, aligned operand rows)
   int chunk = (npk + nsplit - 1) / nsplit;
-  chunk = (chunk + 15) / 16 * 16;
+  chunk = (chunk + 31) / 32 * 32;
   const int ns = (npk + chunk - 1) / chunk;
   for (int z0 = 0; z0 < W; z0 += ZCHUNK) {
     const int nz = W - z0 < ZCHUNK ? W - z0 : ZCHUNK;
-    MsdFbProb pf{gs, lt, 2 * nz, ldpk, ldK, z0, chunk, npk};
+    MsdFbProb<T> pf{gs, lt, 2 * nz, ldpk, ldK, z0, chunk, npk};
     const dim3 grid((2 * nz + GBM - 1) / GBM, (K + GBN - 1) / GBN, ns);
-    hipLaunchKernelGGL(msd_fb_kernel, grid, dim3(GWM * GWN * 64), 0, s, pf, npk, K, W, fbp);
+    hipLaunchKernelGGL(msd_fb_kernel<T>, grid, dim3(GWM * GWN * 64), 0, s, pf, npk, K, W, fbp);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   const long tot = (long)W * K;
@@ -850,3 +866,7 @@ hipError_t launch_msd_force_bias(const MsdDims& m, int W, const double* theta, c
                      vbias);
   return hipGetLastError();
 }
+template hipError_t launch_msd_force_bias<double>(const MsdDims&, int, const double*, const double*, const double*,
+                                                  int, int, int, int, void*, double2*, hipStream_t);
+template hipError_t launch_msd_force_bias<float>(const MsdDims&, int, const double*, const double*, const float*,
+                                                 int, int, int, int, void*, double2*, hipStream_t);

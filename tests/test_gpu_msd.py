@@ -215,7 +215,7 @@ FB_CASES = [
 ]
 
 
-def _fb_problem(N, na, nb, K, ndet, max_rank, W, seed=0):
+def _fb_problem(N, na, nb, K, ndet, max_rank, W, seed=0, precision="fp64"):
     from paper_2209_04015_amd import afqmc
 
     h1, L = inputs.hamiltonian(N, K, K / 5.0, seed=seed)
@@ -224,7 +224,7 @@ def _fb_problem(N, na, nb, K, ndet, max_rank, W, seed=0):
     coeff, rank, orbs = inputs.msd_expansion(N, na, nb, ndet, max_rank=max_rank, seed=seed + 1)
     pa = inputs.walkers_perturbed(C_a[:, :na], W, 0.3, seed=seed + 2, stream=0)
     pb = inputs.walkers_perturbed(C_b[:, :nb], W, 0.3, seed=seed + 2, stream=1)
-    ham = afqmc.Hamiltonian(h1, L, C_a[:, :na], C_b[:, :nb], dt=0.005, max_walkers=W, precision="fp64")
+    ham = afqmc.Hamiltonian(h1, L, C_a[:, :na], C_b[:, :nb], dt=0.005, max_walkers=W, precision=precision)
     t = afqmc.MSDTrial(C_a, C_b, na, nb, coeff, rank, orbs, max_walkers=W)
     return h1, L, C_a, C_b, coeff, rank, orbs, pa, pb, ham, t
 
@@ -278,14 +278,15 @@ def test_msd_force_bias_leaves_the_hamiltonian_step_unchanged():
     ham.close()
 
 
-def test_msd_force_bias_needs_an_fp64_hamiltonian():
+def test_msd_force_bias_needs_a_packed_l():
+    """FP16X3 Hamiltonians keep L only as 16-bit splits: the call is refused."""
     from paper_2209_04015_amd import afqmc
 
     N, na, nb, K = 12, 3, 3, 8
     h1, L = inputs.hamiltonian(N, K, 2.0, seed=1)
     C = inputs.orbitals(h1)
     coeff, rank, orbs = inputs.msd_expansion(N, na, nb, 10, 2, seed=2)
-    ham = afqmc.Hamiltonian(h1, L, C[:, :na], C[:, :nb], dt=0.005, max_walkers=2, precision="fp32")
+    ham = afqmc.Hamiltonian(h1, L, C[:, :na], C[:, :nb], dt=0.005, max_walkers=2, precision="fp16x3")
     t = afqmc.MSDTrial(C, C, na, nb, coeff, rank, orbs, max_walkers=2)
     w = afqmc.Walkers.from_numpy(inputs.walkers_perturbed(C[:, :na], 2, 0.2, seed=1),
                                  inputs.walkers_perturbed(C[:, :nb], 2, 0.2, seed=1, stream=1), device="cuda")
@@ -401,5 +402,50 @@ def test_msd_propagate_with_one_reference_equals_the_single_determinant_step():
     assert np.abs(l1[live] - l2[live]).max() < 1e-10
     d = w1.log_ovlp.cpu().numpy() - w2.log_ovlp.cpu().numpy()
     assert np.abs(d.real).max() < 1e-10 and np.abs(np.exp(1j * d.imag) - 1).max() < 1e-10
+    t.close()
+    ham.close()
+
+
+# Mixed paths (FP32 packed L): the packed symmetric G is rounded to FP32
+# (u = 2^-24) and the contraction over the c = N (N + 1) / 2 pairs accumulates
+# in FP32 on the matrix cores, so the bar is 4 u sqrt(c) times the
+# magnitude scale sum |G| |L| (the single-determinant FP32 force bias uses
+# 4 u sqrt(c) with its own contraction length).  The step takes the FP32
+# single-determinant bars: orbitals 1e-4 of max|phi|, logs 1e-3.
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_msd_force_bias_on_the_fp32_packed_l(precision):
+    from paper_2209_04015_amd import afqmc
+
+    N, na, nb, K, ndet, max_rank, W = FB_CASES[1]
+    print(f"[gpu] msd force bias {precision} N={N} K={K}", flush=True)
+    h1, L, C_a, C_b, coeff, rank, orbs, pa, pb, ham, t = _fb_problem(N, na, nb, K, ndet, max_rank, W,
+                                                                     precision=precision)
+    w = afqmc.Walkers.from_numpy(pa, pb, device="cuda")
+    vb = t.force_bias(ham, w).cpu().numpy()
+    c = N * (N + 1) // 2
+    _fb_compare(orc.msd_setup(C_a, C_b, na, nb, coeff, rank, orbs), L, vb, pa, pb,
+                rtol=4 * 2.0 ** -24 * np.sqrt(c))
+    t.close()
+    ham.close()
+
+
+def test_msd_propagate_on_the_fp32_path():
+    import torch
+    from paper_2209_04015_amd import afqmc
+
+    N, na, nb, K, ndet, max_rank, W = FB_CASES[1]
+    print("[gpu] msd step fp32", flush=True)
+    h1, L, C_a, C_b, coeff, rank, orbs, pa, pb, ham, t = _fb_problem(N, na, nb, K, ndet, max_rank, W,
+                                                                     precision="fp32")
+    msd = orc.msd_setup(C_a, C_b, na, nb, coeff, rank, orbs)
+    oh = orc.setup(h1, L, C_a[:, :na], C_b[:, :nb], dt=0.005)
+    x = inputs.fields(W, K, 1, seed=4)[0]
+    lw0 = np.zeros(W)
+    w = afqmc.Walkers.from_numpy(pa, pb, None, lw0, device="cuda")
+    t.overlap(w, out=w.log_ovlp)
+    t.propagate(ham, w, torch.as_tensor(x, device="cuda"))
+    ref = orc.msd_propagate(oh, msd, pa, pb, orc.msd_overlap(msd, pa, pb), lw0, x)
+    _assert_step(w, ref, tol_phi=1e-4, tol_log=1e-3)
     t.close()
     ham.close()
