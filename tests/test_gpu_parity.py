@@ -365,3 +365,74 @@ def test_bad_shapes_raise():
 
     with pytest.raises((AfqmcError, ValueError)):
         c.ham.local_energy(w, nw=c.cfg.W + 1)
+
+
+# ---------------------------------------------------------------------------
+# The full-size workload in the bench's launch configuration, sampled
+# ---------------------------------------------------------------------------
+# n290 (N = 290, n = 26, K = 2900, 512 walkers): one fused step (propagate,
+# QR, energy) of all walkers in one call, as the bench runs it; the oracle
+# takes the same step for three of them (walkers are independent).  Bars as
+# in test_fused_step_matches_oracle, with the orbital bar relative to each
+# walker's max |phi| and the log bars relative to the size of the logs
+# (|log w| and |log <Psi_T|phi>| reach ~1e3 here, and a relative FP64 error
+# of 1e-13 on them is ~1e-10 absolute).
+_N290 = {}
+
+
+def _n290_reference():
+    if not _N290:
+        cfg = inputs.CONFIGS["n290"]
+        h1, L = inputs.hamiltonian(cfg.N, cfg.K, cfg.decay, seed=0)
+        phiT = inputs.trial(h1, cfg.n)
+        pa = inputs.walkers_perturbed(phiT, cfg.W, 0.05, seed=3, stream=0)
+        pb = inputs.walkers_perturbed(phiT, cfg.W, 0.05, seed=3, stream=1)
+        x = inputs.fields(cfg.W, cfg.K, 1, seed=0)[0]
+        oh = orc.setup(h1, L, phiT, phiT, dt=cfg.dt, taylor_order=cfg.taylor_order)
+        sample = np.array([0, 255, 511])
+        lo = orc.overlap(oh, pa[sample], pb[sample])
+        ref = orc.step(oh, pa[sample], pb[sample], lo, np.zeros(len(sample)), x[sample], do_qr=True)
+        _N290.update(cfg=cfg, h1=h1, L=L, phiT=phiT, pa=pa, pb=pb, x=x, sample=sample, ref=ref)
+    return _N290
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16x3", "bf16x3"])
+def test_fused_step_at_n290_sampled(precision):
+    torch = _torch()
+    from paper_2209_04015_amd import afqmc
+
+    r = _n290_reference()
+    cfg = r["cfg"]
+    print(f"[gpu] n290 fused step {precision}", flush=True)
+    ham = afqmc.Hamiltonian(r["h1"], r["L"], r["phiT"], r["phiT"], dt=cfg.dt, max_walkers=cfg.W,
+                            precision=precision, taylor_order=cfg.taylor_order)
+    w = afqmc.Walkers.from_numpy(r["pa"], r["pb"], device="cuda")   # log w = 0
+    ham.overlap(w)                       # the walkers' own log overlap (the oracle computes its own)
+    e = torch.empty((cfg.W, 3), dtype=torch.complex128, device="cuda")
+    ham.step(w, torch.as_tensor(r["x"], device="cuda"), do_qr=True, energy_out=e)
+    torch.cuda.synchronize()
+    assert ham.status() == 0
+    s = r["sample"]
+    pa, pb, lo, lw, er = r["ref"]
+    tol_e = 1e-11 if precision == "fp64" else 1e-4
+    tol_phi = 1e-10 if precision == "fp64" else 1e-4
+    tol_log = 1e-12 if precision == "fp64" else 1e-5      # relative to the log's size (>= 1)
+    got = e.cpu().numpy()[s]
+    S = np.abs(er).sum(axis=1)
+    derr = np.abs(got.sum(axis=1) - er.sum(axis=1)) / S
+    for g, ref in ((w.phi_a.cpu().numpy()[s], pa), (w.phi_b.cpu().numpy()[s], pb)):
+        perr = (np.abs(g - ref).reshape(len(s), -1).max(axis=1) / np.abs(ref).reshape(len(s), -1).max(axis=1))
+        assert np.all(perr <= tol_phi), perr
+    glw = w.log_w.cpu().numpy()[s]
+    glo = w.log_ovlp.cpu().numpy()[s]
+    alive = np.isfinite(lw)
+    assert np.array_equal(alive, np.isfinite(glw))
+    lerr = np.abs(glw[alive] - lw[alive]) / np.maximum(1.0, np.abs(lw[alive]))
+    oerr = np.abs(glo.real - lo.real) / np.maximum(1.0, np.abs(lo.real))
+    print(f"[gpu] n290 {precision}: |dE|/S {derr.max():.2e}, phi {perr.max():.2e}, "
+          f"log w {lerr.max(initial=0):.2e}, log ovlp {oerr.max():.2e} ({int(alive.sum())} of 3 kept)", flush=True)
+    assert np.all(derr <= tol_e)
+    assert np.all(lerr <= tol_log) and np.all(oerr <= tol_log)
+    ham.close()
+    del w, e
+    torch.cuda.empty_cache()
