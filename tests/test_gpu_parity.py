@@ -436,3 +436,48 @@ def test_fused_step_at_n290_sampled(precision):
     ham.close()
     del w, e
     torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------
+# The size limits of the kernels: 45 electrons per spin (the Green's function
+# and exchange tiles) with the largest N the in-LDS QR takes for it, and the
+# largest N for the n290 electron count; one fused step, bars as above.
+# ---------------------------------------------------------------------------
+LIMITS = [inputs.Config("n45_max", N=177, n=45, K=60, decay=20.0, W=6, steps=1, qr_interval=1),
+          inputs.Config("N_max", N=361, n=26, K=40, decay=15.0, W=4, steps=1, qr_interval=1)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp16x3"])
+@pytest.mark.parametrize("cfg", LIMITS, ids=[c.name for c in LIMITS])
+def test_fused_step_at_the_size_limits(cfg, precision):
+    torch = _torch()
+    print(f"[gpu] size limit {cfg.name} {precision}", flush=True)
+    c = Case(cfg, precision)
+    w = c.walkers()
+    x = inputs.fields(cfg.W, cfg.K, 1, seed=5)[0]
+    e = torch.empty((cfg.W, 3), dtype=torch.complex128, device=c.dev)
+    c.ham.step(w, torch.as_tensor(x, device=c.dev), do_qr=True, energy_out=e)
+    pa, pb, lo, lw, er = orc.step(c.oh, c.pa, c.pb, c.lo, c.lw, x, do_qr=True)
+    tol_e = 1e-11 if precision == "fp64" else 1e-4
+    tol_phi = 1e-10 if precision == "fp64" else 1e-4
+    tol_log = 1e-9 if precision == "fp64" else 1e-2
+    S = np.abs(er).sum(axis=1)
+    derr = np.abs(e.cpu().numpy().sum(axis=1) - er.sum(axis=1)) / S
+    print(f"[gpu] size limit {cfg.name} {precision}: max |dE|/S = {derr.max():.3e}", flush=True)
+    assert np.all(derr <= tol_e)
+    assert np.abs(w.phi_a.cpu().numpy() - pa).max() < tol_phi
+    assert np.abs(w.phi_b.cpu().numpy() - pb).max() < tol_phi
+    _assert_logw(w.log_w.cpu().numpy(), lw, tol_log)
+    assert np.abs(w.log_ovlp.cpu().numpy().real - lo.real).max() < tol_log
+    c.ham.close()
+
+
+def test_sizes_beyond_the_limits_are_refused():
+    from paper_2209_04015_amd import afqmc
+
+    for N, n in ((178, 45), (362, 26), (100, 46)):
+        h1, L = inputs.hamiltonian(N, 4, 2.0, seed=1)
+        phiT = inputs.trial(h1, n)
+        with pytest.raises(afqmc.AfqmcError) as e:
+            afqmc.Hamiltonian(h1, L, phiT, phiT, dt=0.005, max_walkers=2, precision="fp64")
+        assert e.value.code == 4
