@@ -5,9 +5,15 @@ bias, VHS, propagation (two one-body half steps around a 6-term Taylor
 series), overlap ratio and phaseless weight, QR re-orthogonalisation on the
 workload's schedule, and the local energy (E1, EJ, EK) of every walker.
 
-The headline is the mixed path (FP32-MFMA contractions, FP64 elsewhere); the
-FP64 path runs on the same seeded inputs and is reported beside it.  Inputs
-are synthetic (seeded generators), resident in HBM before timing starts.
+The headline is the FP16X3 path (16-bit hi/lo split contractions on the
+matrix cores, FP32 elsewhere in the contractions, FP64 for overlaps, solves,
+QR, weights and energy sums); the FP64, FP32 and BF16X3 paths run on the
+same seeded inputs and are reported beside it, with the roofline of the
+dominant kernel, the oracle's CPU rate and the energy error against the
+oracle.  Also on the line: the paper's direct exchange algorithm, the
+propagation-only and 25-step block rates, the multi-determinant trial's
+calls, and the uneven multi-system batch.  Inputs are synthetic (seeded
+generators), resident in HBM before timing starts.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
