@@ -482,7 +482,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the walker-parallel "
-              "multi-GPU layout is described in DESIGN.md and not run here.", file=sys.stderr)
+              "multi-GPU layout (walkers split across GPUs, each with a copy of the Hamiltonian) is not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -24,7 +24,7 @@ What it computes follows arXiv 2209.04015 (ipie):
   paper uses to evaluate them is not used here.  The phaseless step under
   that trial (Sec. II.B) takes its force bias and overlap from them.
 
-Readings where the paper is silent (each is listed in the design doc as well):
+Readings where the paper is silent:
 
 * R1  The one-body operator inside B(x): H is rewritten as
       sum h'_pq a+_p a_q + 1/2 sum_g v_g^2 with v_g = sum L_g,pq a+_p a_q and
