@@ -1326,13 +1326,13 @@ int msd_check(const afqmc_msd* t, const afqmc_walkers* w, int nw) {
 }
 
 // reference theta and log det, then the string determinants and the overlap ratio
-int msd_ratio(afqmc_msd* t, const afqmc_walkers* w, int nw, hipStream_t s) {
+int msd_ratio(afqmc_msd* t, const afqmc_walkers* w, int nw, bool want_adj, hipStream_t s) {
   HIP_TRY(hipSetDevice(t->device));
   const double2* pb = (const double2*)(t->m.nb > 0 ? w->phi_b : w->phi_a);  // not read when nb = 0
   HIP_TRY((launch_gf<double>(t->d, nw, (const double2*)w->phi_a, pb, t->t.cocc, t->hh0, t->theta, t->logdet,
                              nullptr, t->status, s)));
   HIP_TRY(launch_msd_ratio(t->m, nw, t->t, t->theta, t->yp, t->sdet, t->sadj, t->tpart, t->uw, t->rpart,
-                           t->ratio, s));
+                           t->ratio, want_adj, s));
   return AFQMC_OK;
 }
 
@@ -1358,7 +1358,7 @@ int msd_check_ham(const afqmc_msd* t, const afqmc_ham* h, int nw, int* nsplit, i
 int msd_vbias(afqmc_msd* t, afqmc_ham* h, const afqmc_walkers* w, int nw, int nsplit, int ldpk, double2* vbias,
               hipStream_t s) {
   int rc;
-  if ((rc = msd_ratio(t, w, nw, s))) return rc;
+  if ((rc = msd_ratio(t, w, nw, true, s))) return rc;
   HIP_TRY(launch_msd_q(t->m, nw, t->t, t->yp, t->sadj, t->uw, t->ratio, t->zt, t->qp, s));
   if (h->prec == AFQMC_FP64) {
     HIP_TRY(launch_msd_force_bias<double>(t->m, nw, t->theta, t->qp, (const double*)h->LT, h->d.K, h->d.ldK, ldpk,
@@ -1431,7 +1431,7 @@ int afqmc_msd_overlap(afqmc_msd* t, const afqmc_walkers* w, int nw, void* log_ov
   if (rc || nw == 0) return rc;
   if (!log_ovlp) return fail(AFQMC_EINVAL, "null log_ovlp");
   hipStream_t s = (hipStream_t)stream;
-  if ((rc = msd_ratio(t, w, nw, s))) return rc;
+  if ((rc = msd_ratio(t, w, nw, false, s))) return rc;
   HIP_TRY(launch_msd_overlap_store(nw, t->logdet, t->ratio, (double2*)log_ovlp, t->status, s));
   return AFQMC_OK;
 }
@@ -1441,7 +1441,7 @@ int afqmc_msd_green_function(afqmc_msd* t, const afqmc_walkers* w, int nw, void*
   if (rc || nw == 0) return rc;
   if (!G) return fail(AFQMC_EINVAL, "null G");
   hipStream_t s = (hipStream_t)stream;
-  if ((rc = msd_ratio(t, w, nw, s))) return rc;
+  if ((rc = msd_ratio(t, w, nw, true, s))) return rc;
   HIP_TRY(launch_msd_green(t->m, nw, t->t, t->theta, t->yp, t->sadj, t->uw, t->ratio, t->zt, t->qp, (double2*)G,
                            s));
   return AFQMC_OK;
@@ -1476,7 +1476,7 @@ int afqmc_msd_propagate(afqmc_msd* t, afqmc_ham* h, afqmc_walkers* w, int nw, co
   else
     rc = seq_propagate_core<float>(h, w, nw, io, s);
   if (rc) return rc;
-  if ((rc = msd_ratio(t, w, nw, s))) return rc;
+  if ((rc = msd_ratio(t, w, nw, false, s))) return rc;
   HIP_TRY(launch_msd_overlap_pairs(nw, t->logdet, t->ratio, t->lpair, t->status, s));
   HIP_TRY(launch_weight(nw, t->lpair, nullptr, h->a, (double2*)w->log_ovlp, w->log_w, h->cst, h->status, s));
   h->c_valid = false;

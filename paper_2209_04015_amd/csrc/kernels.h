@@ -213,10 +213,11 @@ int msd_combine_blocks(const MsdDims& m);
 // theta [W][2][2][nmax][ldN] FP64 (launch_gf) -> planar Y yp [W][2][2][nmax][ldv], string dets
 // sdet [W][nstr_tot], adjugates sadj [W][nadj_tot], string weights uw [W][nstr_tot],
 // task sums tpart [W][ntask], partial sums rpart [W][msd_combine_blocks],
-// overlap ratios ratio [W] relative to the reference determinant
+// overlap ratios ratio [W] relative to the reference determinant; the
+// adjugates only with want_adj (the overlap alone needs none)
 hipError_t launch_msd_ratio(const MsdDims& m, int W, const MsdTables& t, const double* theta, double* yp,
                             double2* sdet, double2* sadj, double2* tpart, double2* uw, double2* rpart,
-                            double2* ratio, hipStream_t s);
+                            double2* ratio, bool want_adj, hipStream_t s);
 // out [W] = logdet[z][0] + logdet[z][1] + log ratio[z]
 hipError_t launch_msd_overlap_store(int W, const double2* logdet, const double2* ratio, double2* out, int* status,
                                     hipStream_t s);

@@ -128,8 +128,9 @@ struct SmallDet<3> {
   }
 };
 
-// Cofactors in registers (fully unrolled: every index is a constant).
-template <int K>
+// Cofactors in registers (fully unrolled: every index is a constant).  ADJ
+// false: only the row-0 cofactors of the Laplace expansion (det alone).
+template <int K, bool ADJ>
 __device__ __forceinline__ double2 det_adj_reg(const YView& Y, const int* holes, const int* parts,
                                                double2* __restrict__ adj) {
   double2 a[K][K];
@@ -144,12 +145,12 @@ __device__ __forceinline__ double2 det_adj_reg(const YView& Y, const int* holes,
 #pragma unroll
     for (int c = 0; c < K; ++c) a[l][c] = Y(h[c], q[l]);
   if constexpr (K == 1) {
-    adj[0] = make_double2(1.0, 0.0);
+    if constexpr (ADJ) adj[0] = make_double2(1.0, 0.0);
     return a[0][0];
   } else {
     double2 det = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int l = 0; l < K; ++l)
+    for (int l = 0; l < (ADJ ? K : 1); ++l)
 #pragma unroll
       for (int c = 0; c < K; ++c) {
         double2 mi[K - 1][K - 1];
@@ -159,7 +160,7 @@ __device__ __forceinline__ double2 det_adj_reg(const YView& Y, const int* holes,
           for (int x = 0; x < K - 1; ++x) mi[r][x] = a[r < l ? r : r + 1][x < c ? x : x + 1];
         double2 cof = SmallDet<K - 1>::det(mi);
         if ((l + c) & 1) cof = cneg(cof);
-        adj[c * K + l] = cof;
+        if constexpr (ADJ) adj[c * K + l] = cof;
         if (l == 0) det = cadd(det, cmul(a[0][c], cof));  // Laplace along row 0
       }
     return det;
@@ -169,6 +170,7 @@ __device__ __forceinline__ double2 det_adj_reg(const YView& Y, const int* holes,
 // Strings of rank <= KREG, one thread per (walker, string).  The strings of
 // a spin are sorted by rank, so a wave takes one branch except at the few
 // rank boundaries.
+template <bool ADJ>
 __global__ __launch_bounds__(256) void msd_strings_kernel(MsdDims m, int z0, const int* __restrict__ srank,
                                                           const int* __restrict__ sorb,
                                                           const int* __restrict__ saoff,
@@ -187,10 +189,10 @@ __global__ __launch_bounds__(256) void msd_strings_kernel(MsdDims m, int z0, con
   double2* adj = sadj + (size_t)z * m.nadj_tot + saoff[u];
   double2 det;
   switch (k) {
-    case 1: det = det_adj_reg<1>(Y, holes, parts, adj); break;
-    case 2: det = det_adj_reg<2>(Y, holes, parts, adj); break;
-    case 3: det = det_adj_reg<3>(Y, holes, parts, adj); break;
-    case 4: det = det_adj_reg<4>(Y, holes, parts, adj); break;
+    case 1: det = det_adj_reg<1, ADJ>(Y, holes, parts, adj); break;
+    case 2: det = det_adj_reg<2, ADJ>(Y, holes, parts, adj); break;
+    case 3: det = det_adj_reg<3, ADJ>(Y, holes, parts, adj); break;
+    case 4: det = det_adj_reg<4, ADJ>(Y, holes, parts, adj); break;
     default: det = make_double2(1.0, 0.0); break;  // the reference string
   }
   sdet[(size_t)z * m.nstr_tot + u] = det;
@@ -237,7 +239,7 @@ __global__ __launch_bounds__(S_T) void msd_strings_big_kernel(MsdDims m, int z0,
                                                               const int* __restrict__ saoff,
                                                               const double* __restrict__ yp,
                                                               double2* __restrict__ sdet,
-                                                              double2* __restrict__ sadj) {
+                                                              double2* __restrict__ sadj, int want_adj) {
   // A and one minor per thread: (36 + 25) x 64 x 16 B = 62.5 KB
   __shared__ double2 lds_a[KM * KM * S_T];
   __shared__ double2 lds_w[(KM - 1) * (KM - 1) * S_T];
@@ -256,7 +258,7 @@ __global__ __launch_bounds__(S_T) void msd_strings_big_kernel(MsdDims m, int z0,
     for (int c = 0; c < k; ++c) A[(l * k + c) * S_T] = Y(holes[c], parts[l]);
   double2* adj = sadj + (size_t)z * m.nadj_tot + saoff[u];
   const int k1 = k - 1;
-  for (int l = 0; l < k; ++l) {
+  for (int l = 0; l < (want_adj ? k : 0); ++l) {
     for (int c = 0; c < k; ++c) {
       int e = 0;
       for (int r = 0; r < k; ++r) {
@@ -717,7 +719,7 @@ int msd_combine_blocks(const MsdDims& m) { return (m.nstr_tot + C_T - 1) / C_T; 
 
 hipError_t launch_msd_ratio(const MsdDims& m, int W, const MsdTables& t, const double* theta, double* yp,
                             double2* sdet, double2* sadj, double2* tpart, double2* uw, double2* rpart,
-                            double2* ratio, hipStream_t s) {
+                            double2* ratio, bool want_adj, hipStream_t s) {
   const int nblk = msd_combine_blocks(m);
   for (int z0 = 0; z0 < W; z0 += ZCHUNK) {
     const int nz = W - z0 < ZCHUNK ? W - z0 : ZCHUNK;
@@ -729,13 +731,17 @@ hipError_t launch_msd_ratio(const MsdDims& m, int W, const MsdTables& t, const d
       hipLaunchKernelGGL(msd_y_kernel, grid, dim3(YWM * YWN * 64), 0, s, m, p, yp);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(msd_strings_kernel, dim3((m.nstr_tot + 255) / 256, nz), dim3(256), 0, s, m, z0, t.srank,
-                       t.sorb, t.saoff, yp, sdet, sadj);
+    if (want_adj)
+      hipLaunchKernelGGL(msd_strings_kernel<true>, dim3((m.nstr_tot + 255) / 256, nz), dim3(256), 0, s, m, z0,
+                         t.srank, t.sorb, t.saoff, yp, sdet, sadj);
+    else
+      hipLaunchKernelGGL(msd_strings_kernel<false>, dim3((m.nstr_tot + 255) / 256, nz), dim3(256), 0, s, m, z0,
+                         t.srank, t.sorb, t.saoff, yp, sdet, sadj);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int nbig = m.nbig[0] > m.nbig[1] ? m.nbig[0] : m.nbig[1];
     if (nbig > 0) {
       hipLaunchKernelGGL(msd_strings_big_kernel, dim3((nbig + S_T - 1) / S_T, 2 * nz), dim3(S_T), 0, s, m, z0,
-                         t.srank, t.sorb, t.saoff, yp, sdet, sadj);
+                         t.srank, t.sorb, t.saoff, yp, sdet, sadj, want_adj ? 1 : 0);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(msd_task_kernel, dim3((m.ntask + 255) / 256, nz), dim3(256), 0, s, m, z0, t.tbeg, t.ccoef,
