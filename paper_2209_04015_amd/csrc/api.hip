@@ -285,7 +285,7 @@ int seq_propagate_core(afqmc_ham* h, afqmc_walkers* w, int nw, const StepIO& io,
           (launch_vhs<T>(d, nw, (const T*)h->xs, (const T*)h->LT, h->pq, (T*)h->vhs, h->sdt, s)));
   }
   PHASE(h, AFQMC_PH_ONE_BODY, s,
-        launch_pphi(d, nw, h->P, (const double2*)w->phi_a, (const double2*)w->phi_b, h->acc, nullptr,
+        launch_pphi<T>(d, nw, h->P, (const double2*)w->phi_a, (const double2*)w->phi_b, h->acc, nullptr,
                     nullptr, h->tmax, 0, s));
   const int order = h->prm.taylor_order;
   if (vhs_split(h)) {
@@ -307,7 +307,7 @@ int seq_propagate_core(afqmc_ham* h, afqmc_walkers* w, int nw, const StepIO& io,
     }
   }
   PHASE(h, AFQMC_PH_ONE_BODY, s,
-        launch_pphi(d, nw, h->P, nullptr, nullptr, h->acc, (double2*)w->phi_a, (double2*)w->phi_b,
+        launch_pphi<T>(d, nw, h->P, nullptr, nullptr, h->acc, (double2*)w->phi_a, (double2*)w->phi_b,
                     nullptr, 1, s));
   return AFQMC_OK;
 }

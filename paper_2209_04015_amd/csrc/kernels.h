@@ -57,6 +57,7 @@ hipError_t launch_vhs(const StepDims& d, int W, const T* xs, const T* LT, const 
 
 // out = P in, FP64.  mode 0: in = caller walkers, out -> acc (+ per-walker max |.| into tmax)
 //                     mode 1: in = acc, out -> caller walkers
+template <typename T>
 hipError_t launch_pphi(const StepDims& d, int W, const double* P, const double2* phi_a_in,
                        const double2* phi_b_in, double* acc, double2* phi_a_out,
                        double2* phi_b_out, unsigned* tmax, int mode, hipStream_t s);

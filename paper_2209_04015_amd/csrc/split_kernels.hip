@@ -464,8 +464,8 @@ hipError_t launch_vhs_split(int mode, const StepDims& d, int W, const unsigned s
 }
 
 // ---------------------------------------------------------------------------
-// Taylor term on split operands (the propagator's exp(VHS) truncated at order
-// R6): t_k = VHS t_{k-1} / k for one walker per tile column, as a real GEMM
+// Taylor term on split operands (the exp(VHS) of Eq. Bx truncated after the
+// 6th-order term): t_k = VHS t_{k-1} / k for one walker per tile column, as a real GEMM
 // over k = (q, re|im) interleaved:
 //   A[p][2q + c]         = VHS_pq (c = 0 real, 1 imaginary part)
 //   B[(j, re)][2q, 2q+1] = ( Re t_qj, -Im t_qj)

@@ -28,7 +28,7 @@ template <> struct Cplx<double> { using t = double2; };
 
 constexpr int GF_THREADS = 256;
 constexpr int GF_CHUNK = 32;
-constexpr int GF_SACC = 8;  // S entries per thread: n * n <= 8 * 256, n <= 45
+constexpr int GF_SBLK = 3;  // 2 x 2 blocks of S per thread: ceil(n / 2)^2 <= 3 * 256, n <= 45
 
 static size_t gf_lds_bytes(int n) {
   return (size_t)n * 2 * n * sizeof(double2)       // [S | I]
@@ -67,10 +67,14 @@ __global__ __launch_bounds__(GF_THREADS) void gf_kernel(
   const double2* phi = (sp == 0 ? phi_a : phi_b) + (size_t)z * N * n;
   const double* pT = phiT + (size_t)sp * N * d.nmax;
 
-  // ---- S = PhiT^T phi ----
-  double2 sacc[GF_SACC];
+  // ---- S = PhiT^T phi: each thread owns 2 x 2 blocks of entries, so four LDS
+  // reads (two PhiT values, two phi values) feed four products ----
+  const int nbk = (n + 1) >> 1;  // blocks per side (a last odd row / column is clamped, not stored)
+  double2 sacc[GF_SBLK][4];
 #pragma unroll
-  for (int r = 0; r < GF_SACC; ++r) sacc[r] = make_double2(0.0, 0.0);
+  for (int b = 0; b < GF_SBLK; ++b)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sacc[b][q] = make_double2(0.0, 0.0);
   for (int p0 = 0; p0 < N; p0 += GF_CHUNK) {
     const int rows = min(GF_CHUNK, N - p0);
     __syncthreads();
@@ -81,47 +85,48 @@ __global__ __launch_bounds__(GF_THREADS) void gf_kernel(
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < GF_SACC; ++r) {
-      const int e = tid + r * GF_THREADS;
-      if (e < n * n) {
-        const int i = e / n, j = e % n;
-        // four interleaved partial sums: the LDS reads of consecutive rows
-        // are independent and stay in flight together
-        double2 s0 = make_double2(0.0, 0.0), s1 = s0, s2 = s0, s3 = s0;
-        int pr = 0;
-        for (; pr + 4 <= rows; pr += 4) {
-          const double t0 = tch[pr * n + i], t1 = tch[(pr + 1) * n + i];
-          const double t2 = tch[(pr + 2) * n + i], t3 = tch[(pr + 3) * n + i];
-          const double2 f0 = ch[pr * n + j], f1 = ch[(pr + 1) * n + j];
-          const double2 f2 = ch[(pr + 2) * n + j], f3 = ch[(pr + 3) * n + j];
-          s0.x += t0 * f0.x;
-          s0.y += t0 * f0.y;
-          s1.x += t1 * f1.x;
-          s1.y += t1 * f1.y;
-          s2.x += t2 * f2.x;
-          s2.y += t2 * f2.y;
-          s3.x += t3 * f3.x;
-          s3.y += t3 * f3.y;
+    for (int b = 0; b < GF_SBLK; ++b) {
+      const int e = tid + b * GF_THREADS;
+      if (e < nbk * nbk) {
+        const int bi = e / nbk, bj = e - bi * nbk;
+        const int i0 = 2 * bi, j0 = 2 * bj;
+        const int i1 = min(i0 + 1, n - 1), j1 = min(j0 + 1, n - 1);
+        double2 s00 = make_double2(0.0, 0.0), s01 = s00, s10 = s00, s11 = s00;
+        for (int pr = 0; pr < rows; ++pr) {
+          const double t0 = tch[pr * n + i0], t1 = tch[pr * n + i1];
+          const double2 f0 = ch[pr * n + j0], f1 = ch[pr * n + j1];
+          s00.x = fma(t0, f0.x, s00.x);
+          s00.y = fma(t0, f0.y, s00.y);
+          s01.x = fma(t0, f1.x, s01.x);
+          s01.y = fma(t0, f1.y, s01.y);
+          s10.x = fma(t1, f0.x, s10.x);
+          s10.y = fma(t1, f0.y, s10.y);
+          s11.x = fma(t1, f1.x, s11.x);
+          s11.y = fma(t1, f1.y, s11.y);
         }
-        for (; pr < rows; ++pr) {
-          const double t0 = tch[pr * n + i];
-          const double2 f0 = ch[pr * n + j];
-          s0.x += t0 * f0.x;
-          s0.y += t0 * f0.y;
-        }
-        sacc[r] = cadd(sacc[r], cadd(cadd(s0, s1), cadd(s2, s3)));
+        sacc[b][0] = cadd(sacc[b][0], s00);
+        sacc[b][1] = cadd(sacc[b][1], s01);
+        sacc[b][2] = cadd(sacc[b][2], s10);
+        sacc[b][3] = cadd(sacc[b][3], s11);
       }
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < GF_SACC; ++r) {
-    const int e = tid + r * GF_THREADS;
-    if (e < n * n) {
-      const int i = e / n, j = e % n;
-      aug[i * n2 + j] = sacc[r];
-      aug[i * n2 + n + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  for (int b = 0; b < GF_SBLK; ++b) {
+    const int e = tid + b * GF_THREADS;
+    if (e < nbk * nbk) {
+      const int bi = e / nbk, bj = e - bi * nbk;
+      const int i0 = 2 * bi, j0 = 2 * bj;
+      aug[i0 * n2 + j0] = sacc[b][0];
+      if (j0 + 1 < n) aug[i0 * n2 + j0 + 1] = sacc[b][1];
+      if (i0 + 1 < n) aug[(i0 + 1) * n2 + j0] = sacc[b][2];
+      if (i0 + 1 < n && j0 + 1 < n) aug[(i0 + 1) * n2 + j0 + 1] = sacc[b][3];
     }
+  }
+  for (int e = tid; e < n * n; e += GF_THREADS) {
+    const int i = e / n, j = e % n;
+    aug[i * n2 + n + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
 
@@ -194,28 +199,38 @@ __global__ __launch_bounds__(GF_THREADS) void gf_kernel(
       ch[e] = phi[(size_t)(p0 + pr) * n + j];
     }
     __syncthreads();
-    for (int e = tid; e < rows * n; e += GF_THREADS) {
-      const int j = e / rows, pr = e % rows;
-      double2 t = make_double2(0.0, 0.0);
-      if (!singular) {  // four interleaved partial sums (independent LDS reads)
-        double2 u0 = t, u1 = t, u2 = t, u3 = t;
-        int k = 0;
-        for (; k + 4 <= n; k += 4) {
-          u0 = cadd(u0, cmul(ch[pr * n + k], aug[k * n2 + n + j]));
-          u1 = cadd(u1, cmul(ch[pr * n + k + 1], aug[(k + 1) * n2 + n + j]));
-          u2 = cadd(u2, cmul(ch[pr * n + k + 2], aug[(k + 2) * n2 + n + j]));
-          u3 = cadd(u3, cmul(ch[pr * n + k + 3], aug[(k + 3) * n2 + n + j]));
+    // 2 x 2 blocks of outputs (two rows of the chunk, two columns): four LDS
+    // reads feed four products; consecutive threads take consecutive row pairs
+    const int nbp = (rows + 1) >> 1, nbj = (n + 1) >> 1;
+    for (int e = tid; e < nbp * nbj; e += GF_THREADS) {
+      const int bj = e / nbp, bp = e - bj * nbp;
+      const int j0 = 2 * bj, j1 = min(j0 + 1, n - 1);
+      const int q0 = 2 * bp, q1 = min(q0 + 1, rows - 1);
+      double2 t00 = make_double2(0.0, 0.0), t01 = t00, t10 = t00, t11 = t00;
+      if (!singular) {
+        for (int k = 0; k < n; ++k) {
+          const double2 a0 = ch[q0 * n + k], a1 = ch[q1 * n + k];
+          const double2 b0 = aug[k * n2 + n + j0], b1 = aug[k * n2 + n + j1];
+          t00 = cadd(t00, cmul(a0, b0));
+          t01 = cadd(t01, cmul(a0, b1));
+          t10 = cadd(t10, cmul(a1, b0));
+          t11 = cadd(t11, cmul(a1, b1));
         }
-        for (; k < n; ++k) u0 = cadd(u0, cmul(ch[pr * n + k], aug[k * n2 + n + j]));
-        t = cadd(cadd(u0, u1), cadd(u2, u3));
       }
-      const int p = p0 + pr;
-      const double h = hs[(size_t)j * N + p];
-      eacc.x += h * t.x;
-      eacc.y += h * t.y;
-      if (theta) {
-        th_re[(size_t)j * d.ldN + p] = (T)t.x;
-        th_im[(size_t)j * d.ldN + p] = (T)t.y;
+      const double2 tv[4] = {t00, t01, t10, t11};
+#pragma unroll
+      for (int o = 0; o < 4; ++o) {
+        const int j = j0 + (o & 1), q = q0 + (o >> 1);
+        if (j >= n || q >= rows) continue;
+        const int p = p0 + q;
+        const double2 t = tv[o];
+        const double h = hs[(size_t)j * N + p];
+        eacc.x += h * t.x;
+        eacc.y += h * t.y;
+        if (theta) {
+          th_re[(size_t)j * d.ldN + p] = (T)t.x;
+          th_im[(size_t)j * d.ldN + p] = (T)t.y;
+        }
       }
     }
   }
@@ -428,7 +443,9 @@ template hipError_t launch_vhs<double>(const StepDims&, int, const double*, cons
                                        const int2*, double*, double, hipStream_t);
 
 // ===========================================================================
-// One-body half step (R2 of the design: P = exp(-dt (h' - mu) / 2)), FP64:
+// One-body half step of the propagator B(x) of Eq. Bx, split symmetrically
+// (P = exp(-dt (h' - mu) / 2) on each side of exp(VHS); the paper leaves the
+// factorisation open):
 // out_z = P in_z for every walker, both spins side by side as real columns.
 // ===========================================================================
 
@@ -442,38 +459,70 @@ template hipError_t launch_vhs<double>(const StepDims&, int, const double*, cons
 #define PPHI_BK 16
 #endif
 
+// The FP64 path multiplies on the FP64 matrix cores.  The FP32 and split
+// paths, whose VHS and Taylor products already round to single precision,
+// multiply on the FP32 matrix cores (twice the FP64 rate): operands are
+// rounded to FP32 on the way into LDS, the products accumulate in FP32, and
+// the result is stored back in FP64.
+template <typename T>
 struct PphiProb {
-  using vec_t = double2;
+  using vec_t = typename MF<T>::vec_t;
   const double* P;
   int N, ldP, ncolp, na, nb;
   const double* in_a;  // mode 0
   const double* in_b;
   const double* acc;   // mode 1
   int mode;
-  __device__ vec_t load_a(int, int r, int k) const {
-    if (r >= N) return make_double2(0.0, 0.0);
-    return *reinterpret_cast<const double2*>(P + (size_t)r * ldP + k);
-  }
-  __device__ vec_t load_b_km(int z, int q, int col) const {
-    if (q >= N || col >= ncolp) return make_double2(0.0, 0.0);
+  // two consecutive real columns (col even) of row q of walker z's operand
+  __device__ double2 pair(int z, int q, int col) const {
     if (mode == 1) return *reinterpret_cast<const double2*>(acc + ((size_t)z * N + q) * ncolp + col);
     if (col < 2 * na) return *reinterpret_cast<const double2*>(in_a + ((size_t)z * N + q) * 2 * na + col);
     const int c = col - 2 * na;
     if (c >= 2 * nb) return make_double2(0.0, 0.0);
     return *reinterpret_cast<const double2*>(in_b + ((size_t)z * N + q) * 2 * nb + c);
   }
+  // rows of P are zero-padded to ldP (a multiple of 16), so a vector that
+  // starts below N stays inside its row
+  __device__ vec_t load_a(int, int r, int k) const {
+    if (r >= N) return MF<T>::vzero();
+    const double2* src = reinterpret_cast<const double2*>(P + (size_t)r * ldP + k);
+    if constexpr (sizeof(T) == 8) {
+      return src[0];
+    } else {
+      const double2 u = src[0], v = src[1];
+      return make_float4((float)u.x, (float)u.y, (float)v.x, (float)v.y);
+    }
+  }
+  // ncolp is a multiple of 4 and 2 na is even, so each pair lies in one operand
+  __device__ vec_t load_b_km(int z, int q, int col) const {
+    if (q >= N || col >= ncolp) return MF<T>::vzero();
+    if constexpr (sizeof(T) == 8) {
+      return pair(z, q, col);
+    } else {
+      const double2 u = pair(z, q, col), v = pair(z, q, col + 2);
+      return make_float4((float)u.x, (float)u.y, (float)v.x, (float)v.y);
+    }
+  }
 };
 
-template <int BM, int BN, int BK, int WM, int WN>
-__global__ __launch_bounds__(WM* WN * 64) void pphi_kernel(PphiProb p, double* __restrict__ acc_out,
+// 1-D grid in XCD order: workgroups go to the 8 XCDs in turn (XCD = id mod 8)
+// and the ntile tiles of a walker get ids of one residue, row tile fastest, so
+// the row tiles that share a walker's column tile run together on one XCD and
+// read it once into that XCD's L2.
+template <typename T, int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(WM* WN * 64) void pphi_kernel(PphiProb<T> p, int W, int mt, int ntile,
+                                                           double* __restrict__ acc_out,
                                                            double2* __restrict__ out_a,
                                                            double2* __restrict__ out_b,
                                                            unsigned* __restrict__ tmax) {
-  __shared__ __attribute__((aligned(16))) double lds[TileLds<double, BM, BN, BK>::ELEMS];
-  doublex4 acc[BM / WM / 16][BN / WN / 16];
-  const int z = blockIdx.z;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-  mfma_tile_mainloop<double, BM, BN, BK, WM, WN, true>(p, z, m0, n0, p.ldP, acc, lds);
+  __shared__ __attribute__((aligned(16))) T lds[TileLds<T, BM, BN, BK>::ELEMS];
+  typename MF<T>::acc_t acc[BM / WM / 16][BN / WN / 16];
+  const int L = blockIdx.x;
+  const int r8 = L >> 3, t = r8 % ntile;
+  const int z = (L & 7) + 8 * (r8 / ntile);
+  if (z >= W) return;  // whole workgroup, before any barrier
+  const int m0 = (t % mt) * BM, n0 = (t / mt) * BN;
+  mfma_tile_mainloop<T, BM, BN, BK, WM, WN, true>(p, z, m0, n0, p.N, acc, lds);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int wm = wid / WN, wn = wid % WN;
   const int ncol = 2 * (p.na + p.nb);
@@ -509,23 +558,32 @@ __global__ __launch_bounds__(WM* WN * 64) void pphi_kernel(PphiProb p, double* _
   }
 }
 
+template <typename T>
 hipError_t launch_pphi(const StepDims& d, int W, const double* P, const double2* phi_a_in,
                        const double2* phi_b_in, double* acc, double2* phi_a_out,
                        double2* phi_b_out, unsigned* tmax, int mode, hipStream_t s) {
-  PphiProb p{P, d.N, d.ldP, d.ncolp, d.na, d.nb,
-             reinterpret_cast<const double*>(phi_a_in), reinterpret_cast<const double*>(phi_b_in),
-             acc, mode};
+  PphiProb<T> p{P, d.N, d.ldP, d.ncolp, d.na, d.nb,
+                reinterpret_cast<const double*>(phi_a_in), reinterpret_cast<const double*>(phi_b_in),
+                acc, mode};
   // 64 x 64 tiles: many small workgroups per walker (larger tiles lower the occupancy)
-  constexpr int BK = PPHI_BK, WM = 2, WN = 2;
+  constexpr int BK = sizeof(T) == 4 ? 32 : PPHI_BK, WM = 2, WN = 2;
   constexpr int BM = PPHI_BM, BN = PPHI_BN;
-  dim3 grid(ceil_div(d.N, BM), ceil_div(d.ncolp, BN), W);
-  hipLaunchKernelGGL((pphi_kernel<BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p, acc,
-                     phi_a_out, phi_b_out, tmax);
+  const int mt = ceil_div(d.N, BM), ntile = mt * ceil_div(d.ncolp, BN);
+  const long nblk = (long)ntile * ceil_div(W, 8) * 8;
+  hipLaunchKernelGGL((pphi_kernel<T, BM, BN, BK, WM, WN>), dim3((unsigned)nblk), dim3(WM * WN * 64), 0, s,
+                     p, W, mt, ntile, acc, phi_a_out, phi_b_out, tmax);
   return hipGetLastError();
 }
+template hipError_t launch_pphi<float>(const StepDims&, int, const double*, const double2*,
+                                       const double2*, double*, double2*, double2*, unsigned*, int,
+                                       hipStream_t);
+template hipError_t launch_pphi<double>(const StepDims&, int, const double*, const double2*,
+                                        const double2*, double*, double2*, double2*, unsigned*, int,
+                                        hipStream_t);
 
 // ===========================================================================
-// Taylor term: t_k = VHS t_{k-1} / k, acc += t_k (R6: exp(VHS) truncated at k = 6).
+// Taylor term: t_k = VHS t_{k-1} / k, acc += t_k (exp(VHS) of Eq. Bx
+// truncated after the 6th-order term).
 // Complex product as a real GEMM: A = VHS rows with interleaved (re, im)
 // along the contraction, B rows (q, re|im) built on the fly from t:
 //   row (q, re) = t[q][:]              (tr, ti pairs)
@@ -938,7 +996,7 @@ template hipError_t launch_exchange_pair<double>(const StepDims&, int, const Pai
                                                  const double*, double2*, int, hipStream_t, int);
 
 // ===========================================================================
-// Energy assembly (R10 of the design): E1 from the Green's function pass,
+// Energy assembly (Sec. III.C): E1 from the Green's function pass,
 // EJ = 1/2 sum_g vbias_g^2, EK = -1/2 sum of the exchange partials.
 // ===========================================================================
 
@@ -995,7 +1053,7 @@ hipError_t launch_counter_set(int* ctr, int v, hipStream_t s) {
 }
 
 // ===========================================================================
-// Re-orthogonalisation (R9 of the design): phi = Q R with R upper triangular
+// Re-orthogonalisation of the walkers (done once per block, Sec. IV timing runs): phi = Q R with R upper triangular
 // with a positive real diagonal (the unique such factorisation; Householder
 // QR followed by the phases D = diag(R_ii / |R_ii|) gives the same Q and R),
 // corr = sum ln R_ii.  Computed as Cholesky QR applied twice: S = A^H A,
