@@ -455,8 +455,19 @@ template hipError_t launch_vhs<double>(const StepDims&, int, const double*, cons
 #ifndef PPHI_BN
 #define PPHI_BN 64
 #endif
+// k depth and pipelining per type (measured at n290, 512 walkers: FP32 one
+// LDS stage of 64 k, 0.25 ms per half step; FP64 two stages of 16 k, 0.30 ms)
 #ifndef PPHI_BK
 #define PPHI_BK 16
+#endif
+#ifndef PPHI_BK_F32
+#define PPHI_BK_F32 64
+#endif
+#ifndef PPHI_PIPE
+#define PPHI_PIPE 2
+#endif
+#ifndef PPHI_PIPE_F32
+#define PPHI_PIPE_F32 1
 #endif
 
 // The FP64 path multiplies on the FP64 matrix cores.  The FP32 and split
@@ -515,14 +526,15 @@ __global__ __launch_bounds__(WM* WN * 64) void pphi_kernel(PphiProb<T> p, int W,
                                                            double2* __restrict__ out_a,
                                                            double2* __restrict__ out_b,
                                                            unsigned* __restrict__ tmax) {
-  __shared__ __attribute__((aligned(16))) T lds[TileLds<T, BM, BN, BK>::ELEMS];
+  constexpr int PIPE = sizeof(T) == 4 ? PPHI_PIPE_F32 : PPHI_PIPE;
+  __shared__ __attribute__((aligned(16))) T lds[(PIPE == 2 ? 2 : 1) * TileLds<T, BM, BN, BK>::ELEMS];
   typename MF<T>::acc_t acc[BM / WM / 16][BN / WN / 16];
   const int L = blockIdx.x;
   const int r8 = L >> 3, t = r8 % ntile;
   const int z = (L & 7) + 8 * (r8 / ntile);
   if (z >= W) return;  // whole workgroup, before any barrier
   const int m0 = (t % mt) * BM, n0 = (t / mt) * BN;
-  mfma_tile_mainloop<T, BM, BN, BK, WM, WN, true>(p, z, m0, n0, p.N, acc, lds);
+  mfma_tile_mainloop<T, BM, BN, BK, WM, WN, true, PphiProb<T>, PIPE>(p, z, m0, n0, p.N, acc, lds);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int wm = wid / WN, wn = wid % WN;
   const int ncol = 2 * (p.na + p.nb);
@@ -566,7 +578,7 @@ hipError_t launch_pphi(const StepDims& d, int W, const double* P, const double2*
                 reinterpret_cast<const double*>(phi_a_in), reinterpret_cast<const double*>(phi_b_in),
                 acc, mode};
   // 64 x 64 tiles: many small workgroups per walker (larger tiles lower the occupancy)
-  constexpr int BK = sizeof(T) == 4 ? 32 : PPHI_BK, WM = 2, WN = 2;
+  constexpr int BK = sizeof(T) == 4 ? PPHI_BK_F32 : PPHI_BK, WM = 2, WN = 2;
   constexpr int BM = PPHI_BM, BN = PPHI_BN;
   const int mt = ceil_div(d.N, BM), ntile = mt * ceil_div(d.ncolp, BN);
   const long nblk = (long)ntile * ceil_div(W, 8) * 8;
