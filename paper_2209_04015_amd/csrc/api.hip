@@ -1255,7 +1255,7 @@ int msd_build(afqmc_msd* t, const double* C[2], const double* coeff, const int* 
   std::vector<std::vector<std::pair<int, int>>> ent(nent);
   for (int u = 0; u < m.nstr_tot; ++u) {
     const int s = u >= m.nstr[0] ? 1 : 0;
-    const int k = srank[u], n = nel[s];
+    const int k = srank[u];
     for (int x = 0; x < k; ++x)      // hole slot m
       for (int l = 0; l < k; ++l) {  // particle slot l
         const int j = sorb[((size_t)u * 2 + 0) * MSD_KMAX + x];
