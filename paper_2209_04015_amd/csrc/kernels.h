@@ -116,9 +116,9 @@ std::vector<int2> vhs_split_pairs(int N, const std::vector<int2>& blk);
 // (row s * S1 + b * S2 + i of block b), output rows contiguous per block
 hipError_t launch_split_blocks_mode(int mode, int nblocks, int nspl, int nsub, int ncols, const float* src, int ld_src,
                                     long S1, long S2, unsigned short* dst, int ldh, float* unscale, hipStream_t s);
-// vbias = sum_k theta_k Lh_k on block-split operands, the k range in
-// FB_SPLIT_CHUNKS chunks; part: [FB_SPLIT_CHUNKS][2 W][K] floats
-constexpr int FB_SPLIT_CHUNKS = 4;
+// vbias = sum_k theta_k Lh_k on block-split operands, the k range in at most
+// FB_SPLIT_CHUNKS chunks (chosen per launch); part: [FB_SPLIT_CHUNKS][2 W][K] floats
+constexpr int FB_SPLIT_CHUNKS = 8;
 hipError_t launch_force_bias_split(int mode, const StepDims& d, int W, const unsigned short* th, const float* th_unscale,
                                    const unsigned short* lh, const float* lh_unscale, float* part, double2* vbias,
                                    hipStream_t s);

@@ -872,6 +872,27 @@ __global__ void fb_split_reduce_kernel(int W, int K, int chunks, const float* __
   vbias[e] = make_double2(re * (double)th_unscale[2 * z] * ul, im * (double)th_unscale[2 * z + 1] * ul);
 }
 
+// Number of k chunks.  The kernel runs two workgroups per CU (LDS and VGPRs
+// allow no more), 512 at a time on the 256 CUs, and every workgroup of a
+// launch does the same work, so the time goes as rounds x work per workgroup:
+// ceil(c tiles / 512) / c for c chunks.  The smallest minimiser up to
+// FB_SPLIT_CHUNKS is taken (n290, 512 walkers: 133 tiles, 7 chunks in two
+// rounds instead of 4 chunks in two rounds of which the second is 4% full).
+static int fb_split_chunks(int tiles, int nkb) {
+  constexpr int SLOTS = 2 * 256;
+  int best = 1;
+  long bn = 1, bd = 1;  // best cost as the fraction bn / bd
+  for (int c = 2; c <= FB_SPLIT_CHUNKS && c <= nkb; ++c) {
+    const long rounds = ((long)tiles * c + SLOTS - 1) / SLOTS;
+    if (rounds * bd < bn * c) {  // rounds / c < bn / bd
+      best = c;
+      bn = rounds;
+      bd = c;
+    }
+  }
+  return best;
+}
+
 hipError_t launch_force_bias_split(int mode, const StepDims& d, int W, const unsigned short* th, const float* th_unscale,
                                    const unsigned short* lh, const float* lh_unscale, float* part, double2* vbias,
                                    hipStream_t s) {
@@ -880,11 +901,12 @@ hipError_t launch_force_bias_split(int mode, const StepDims& d, int W, const uns
   const int rowb = 2 * d.nmax * 2 * d.ldh * 2;  // (spin, i) sub-rows of 2 ldh halves
   if ((double)C::BM * rowb >= (double)SPLIT_ROW_NONE) return hipErrorInvalidValue;
   const int nkb = 2 * d.nmax * (d.ldh / 32);
-  const int kchunk = ceil_div(nkb, FB_SPLIT_CHUNKS);
   const int ntm = ceil_div(2 * W, C::BM), ntn = ceil_div(d.K, C::BN);
+  const int kchunk = ceil_div(nkb, fb_split_chunks(ntm * ntn, nkb));
+  const int chunks = ceil_div(nkb, kchunk);  // every chunk holds at least one k block
   FbSplitArgs p{th, lh, part, W, d.K, rowb, nkb, kchunk};
   const int per = ceil_div(ntm * ntn, 8);
-  const dim3 grid((unsigned)(FB_SPLIT_CHUNKS * 8 * per));
+  const dim3 grid((unsigned)(chunks * 8 * per));
   if (mode == SPLIT_BF16)
     hipLaunchKernelGGL(fb_split_kernel<HalfBF16>, grid, dim3(C::NT), 0, s, p, ntm, ntn, 8 * per);
   else
@@ -892,7 +914,7 @@ hipError_t launch_force_bias_split(int mode, const StepDims& d, int W, const uns
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t n = (size_t)W * d.K;
-  hipLaunchKernelGGL(fb_split_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, d.K, FB_SPLIT_CHUNKS,
+  hipLaunchKernelGGL(fb_split_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, d.K, chunks,
                      part, th_unscale, lh_unscale, vbias);
   return hipGetLastError();
 }
