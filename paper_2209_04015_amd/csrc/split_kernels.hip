@@ -45,13 +45,46 @@ __global__ __launch_bounds__(256) void split_rows_kernel(long nrows, int ncols, 
   if (lane == 0) unscale[row] = 1.0f / sc;  // power of two: exact
 }
 
+// The same for wide rows, one workgroup (four waves) per row: the fields of
+// a step are only 2 W rows of K, too few waves for a wave per row.
+template <class H>
+__global__ __launch_bounds__(256) void split_rows_wide_kernel(int ncols, const float* __restrict__ src, int ld_src,
+                                                              unsigned short* __restrict__ dst, int ldh,
+                                                              float* __restrict__ unscale) {
+  __shared__ float red[4];
+  const long row = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const float* s = src + row * ld_src;
+  float m = 0.f;
+  for (int c = tid; c < ncols; c += 256) m = fmaxf(m, fabsf(s[c]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if (lane == 0) red[wid] = m;
+  __syncthreads();
+  m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  const float sc = split_row_scale<H>(m);
+  unsigned short* d = dst + row * 2 * ldh;
+  for (int c = tid; c < ldh; c += 256) {
+    const float x = c < ncols ? s[c] * sc : 0.f;
+    const unsigned short xh = H::from_float(x);
+    unsigned short* b = d + (c >> 5) * SPLIT_KB + (c & 31);
+    b[0] = xh;
+    b[32] = H::from_float(x - H::to_float(xh));
+  }
+  if (tid == 0) unscale[row] = 1.0f / sc;  // power of two: exact
+}
+
 template <class H>
 hipError_t launch_split_rows(long nrows, int ncols, const float* src, int ld_src, unsigned short* dst,
                              int ldh, float* unscale, hipStream_t s) {
   if (nrows == 0) return hipSuccess;
   if (ldh % 32 != 0 || ldh < ncols) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(split_rows_kernel<H>, dim3((unsigned)((nrows + 3) / 4)), dim3(256), 0, s, nrows,
-                     ncols, src, ld_src, dst, ldh, unscale);
+  if (ncols >= 1024)
+    hipLaunchKernelGGL(split_rows_wide_kernel<H>, dim3((unsigned)nrows), dim3(256), 0, s, ncols, src, ld_src, dst,
+                       ldh, unscale);
+  else
+    hipLaunchKernelGGL(split_rows_kernel<H>, dim3((unsigned)((nrows + 3) / 4)), dim3(256), 0, s, nrows,
+                       ncols, src, ld_src, dst, ldh, unscale);
   return hipGetLastError();
 }
 
@@ -759,16 +792,19 @@ hipError_t launch_taylor_split(int mode, const StepDims& d, int W, const float* 
 // Block split: block b holds rows r = s nsub + i (s < nspl, i < nsub) taken
 // from source row s * S1 + b * S2 + i; one scale for the whole block.  Output
 // rows b * nspl * nsub + r of 2 ldh halves (as split_rows_kernel).
+// eight waves per block: 2 W blocks of 2 n rows are few rows per wave
+constexpr int SPLIT_BLOCKS_NT = 512;
 template <class H>
-__global__ __launch_bounds__(256) void split_blocks_kernel(int nspl, int nsub, int ncols, const float* __restrict__ src,
+__global__ __launch_bounds__(SPLIT_BLOCKS_NT) void split_blocks_kernel(int nspl, int nsub, int ncols, const float* __restrict__ src,
                                                            int ld_src, long S1, long S2, unsigned short* __restrict__ dst,
                                                            int ldh, float* __restrict__ unscale) {
-  __shared__ float red[4];
+  constexpr int NW = SPLIT_BLOCKS_NT / 64;
+  __shared__ float red[NW];
   const int b = blockIdx.x;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int rows = nspl * nsub;
   float m = 0.f;
-  for (int r = wid; r < rows; r += 4) {
+  for (int r = wid; r < rows; r += NW) {
     const int sp = r / nsub, i = r - sp * nsub;
     const float* srow = src + ((long)sp * S1 + (long)b * S2 + i) * ld_src;
     for (int c = lane; c < ncols; c += 64) m = fmaxf(m, fabsf(srow[c]));
@@ -777,9 +813,11 @@ __global__ __launch_bounds__(256) void split_blocks_kernel(int nspl, int nsub, i
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
   if (lane == 0) red[wid] = m;
   __syncthreads();
-  m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  m = red[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) m = fmaxf(m, red[w]);
   const float sc = split_row_scale<H>(m);
-  for (int r = wid; r < rows; r += 4) {
+  for (int r = wid; r < rows; r += NW) {
     const int sp = r / nsub, i = r - sp * nsub;
     const float* srow = src + ((long)sp * S1 + (long)b * S2 + i) * ld_src;
     unsigned short* d = dst + ((long)b * rows + r) * 2 * ldh;
@@ -799,10 +837,10 @@ hipError_t launch_split_blocks_mode(int mode, int nblocks, int nspl, int nsub, i
   if (nblocks == 0) return hipSuccess;
   if (ldh % 32 != 0 || ldh < ncols) return hipErrorInvalidValue;
   if (mode == SPLIT_BF16)
-    hipLaunchKernelGGL(split_blocks_kernel<HalfBF16>, dim3(nblocks), dim3(256), 0, s, nspl, nsub, ncols, src, ld_src,
+    hipLaunchKernelGGL(split_blocks_kernel<HalfBF16>, dim3(nblocks), dim3(SPLIT_BLOCKS_NT), 0, s, nspl, nsub, ncols, src, ld_src,
                        S1, S2, dst, ldh, unscale);
   else
-    hipLaunchKernelGGL(split_blocks_kernel<HalfF16>, dim3(nblocks), dim3(256), 0, s, nspl, nsub, ncols, src, ld_src,
+    hipLaunchKernelGGL(split_blocks_kernel<HalfF16>, dim3(nblocks), dim3(SPLIT_BLOCKS_NT), 0, s, nspl, nsub, ncols, src, ld_src,
                        S1, S2, dst, ldh, unscale);
   return hipGetLastError();
 }
