@@ -5,15 +5,20 @@ bias, VHS, propagation (two one-body half steps around a 6-term Taylor
 series), overlap ratio and phaseless weight, QR re-orthogonalisation on the
 workload's schedule, and the local energy (E1, EJ, EK) of every walker.
 
-The headline is the FP16X3 path (16-bit hi/lo split contractions on the
-matrix cores, FP32 elsewhere in the contractions, FP64 for overlaps, solves,
-QR, weights and energy sums); the FP64, FP32 and BF16X3 paths run on the
-same seeded inputs and are reported beside it, with the roofline of the
-dominant kernel, the oracle's CPU rate and the energy error against the
-oracle.  Also on the line: the paper's direct exchange algorithm, the
-propagation-only and 25-step block rates, the multi-determinant trial's
-calls, and the uneven multi-system batch.  Inputs are synthetic (seeded
-generators), resident in HBM before timing starts.
+The headline is the FP16X3 path (16-bit hi/lo split force bias, VHS, Taylor
+and exchange contractions on the matrix cores, FP32 one-body half steps, FP64
+walkers, overlaps, solves, QR, weights and energy sums); the FP64, FP32 and
+BF16X3 paths run on the same seeded inputs and are reported beside it.  The
+headline pass runs without events inside the step; a second pass of the same
+steps brackets every kernel phase with HIP events and gives the phase
+breakdown and the rooflines (algorithmic work per phase against the peak of
+the matrix-core dtype, or of HBM).  Also on the line: the oracle's CPU rate
+(median of several steps), the per-walker energy error against the oracle,
+the paper's direct exchange algorithm, the propagation-only and 25-step block
+rates, the n100 and n200 workloads at their own sizes, the multi-determinant
+trial's calls, and the uneven multi-system batch with its per-system energy
+error.  Inputs are synthetic (seeded generators), resident in HBM before
+timing starts.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -34,6 +39,7 @@ if ROOT not in sys.path:
 
 METRIC = "walker-steps/s at N=290 mixed vs FP64 on 1 GPU; energy err vs FP64 oracle"
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0}   # MI355X dense matrix peaks
+HBM_GBS = 8000.0                                                             # MI355X HBM3E peak
 MODES = ("fp64", "fp32", "fp16x3", "bf16x3")
 
 
@@ -77,7 +83,13 @@ BLOCK_STEPS = 25   # propagation steps per block (the paper's timing convention)
 
 
 def run_gpu(cfg, h1, L, phiT, precision, steps, warmup, fields_dev, block_fields_dev, device,
-            exchange="auto", sample=1):
+            exchange="auto", sample=1, secondary=True, profile=True):
+    """Times `steps` full steps (propagate, QR on the workload's schedule,
+    local energy) of the workload with no events inside the step (the
+    headline), then the same number of steps again with HIP events around
+    every kernel phase (phase breakdown and the per-kernel launch times of the
+    rooflines).  Returns the handle, walkers, energies, headline ms, phases,
+    status, secondary rates and the sampled state for the oracle check."""
     import torch
 
     from paper_2209_04015_amd import afqmc
@@ -86,7 +98,7 @@ def run_gpu(cfg, h1, L, phiT, precision, steps, warmup, fields_dev, block_fields
     t = time.time()
     ham = afqmc.Hamiltonian(h1, L, phiT, phiT, dt=cfg.dt, max_walkers=W, precision=precision, exchange=exchange,
                             taylor_order=cfg.taylor_order)
-    log(f"{precision}: init {time.time() - t:.1f} s, exchange algorithm {ham.exchange}")
+    log(f"{cfg.name} {precision}: init {time.time() - t:.1f} s, exchange algorithm {ham.exchange}")
     pa = torch.as_tensor(np.repeat(phiT[None].astype(np.complex128), W, axis=0), device=device)
     w = afqmc.Walkers(pa, pa.clone())
     ham.overlap(w)
@@ -95,49 +107,60 @@ def run_gpu(cfg, h1, L, phiT, precision, steps, warmup, fields_dev, block_fields
     for i in range(warmup):
         ham.step(w, fields_dev[i], do_qr=((i + 1) % cfg.qr_interval == 0), energy_out=e, reuse=(i > 0))
     torch.cuda.synchronize()
-    log(f"{precision}: warmup done")
-    ham.profile_enable(steps * 40)
+    log(f"{cfg.name} {precision}: warmup done")
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(stream)
-    for i in range(warmup, warmup + steps):
-        ham.step(w, fields_dev[i], do_qr=((i + 1) % cfg.qr_interval == 0), energy_out=e, reuse=True)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop)
-    phases = ham.profile_read()
-    ham.profile_enable(0)
+
+    def timed_steps(first):
+        torch.cuda.synchronize()
+        start.record(stream)
+        for i in range(first, first + steps):
+            ham.step(w, fields_dev[i], do_qr=((i + 1) % cfg.qr_interval == 0), energy_out=e, reuse=True)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop)
+
+    ms = timed_steps(warmup)
     status = ham.status()
-    log(f"{precision}: {steps} steps in {ms:.1f} ms ({ms / steps:.2f} ms/step), status {status}")
+    log(f"{cfg.name} {precision}: {steps} steps in {ms:.1f} ms ({ms / steps:.3f} ms/step), status {status}")
     # the oracle comparison uses the walkers and energies of the last timed step
-    # (re-orthogonalised every step), before the secondary runs below move them
+    # (before the runs below move them)
     sample_state = (w.phi_a[:sample].cpu().numpy(), w.phi_b[:sample].cpu().numpy(), e[:sample].cpu().numpy())
-    # secondary figures on the same walkers: propagation only (no QR, no
-    # energy), and one block in the paper's convention (BLOCK_STEPS steps,
-    # QR and energy at the last, global energy, comb)
-    torch.cuda.synchronize()
-    start.record(stream)
-    for i in range(steps):
-        ham.step(w, fields_dev[i], do_qr=False, energy_out=None, reuse=True)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    ms_prop = start.elapsed_time(stop)
-    blk_fields = block_fields_dev
-    start.record(stream)
-    ham.block(w, blk_fields, 0.5, energy_out=e, reuse=True)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    ms_block = start.elapsed_time(stop)
-    log(f"{precision}: propagation only {ms_prop / steps:.2f} ms/step; block of {BLOCK_STEPS} "
-        f"steps {ms_block:.1f} ms")
-    extra = {"exchange_algorithm": ham.exchange,
-             "propagation_only": {"value": round(W * steps / (ms_prop * 1e-3), 2), "unit": "walker-steps/s",
-                                  "ms_per_step": round(ms_prop / steps, 4)},
-             "block": {"value": round(W * BLOCK_STEPS / (ms_block * 1e-3), 2), "unit": "walker-steps/s",
-                       "ms_per_block": round(ms_block, 3),
-                       "definition": f"{BLOCK_STEPS} steps, QR and local energy at the last, "
-                                     "global energy, comb population control"}}
+    phases, ms_prof = None, None
+    if profile:
+        ham.profile_enable(steps * 40)
+        ms_prof = timed_steps(warmup)
+        phases = ham.profile_read()
+        ham.profile_enable(0)
+        log(f"{cfg.name} {precision}: profiled pass {ms_prof / steps:.3f} ms/step")
+    extra = {"exchange_algorithm": ham.exchange}
+    if profile:
+        extra["profiled_pass_ms_per_step"] = round(ms_prof / steps, 4)
+    if secondary:
+        # secondary figures on the same walkers: propagation only (no QR, no
+        # energy), and one block in the paper's convention (BLOCK_STEPS steps,
+        # QR and energy at the last, global energy, comb)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for i in range(steps):
+            ham.step(w, fields_dev[i], do_qr=False, energy_out=None, reuse=True)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        ms_prop = start.elapsed_time(stop)
+        start.record(stream)
+        ham.block(w, block_fields_dev, 0.5, energy_out=e, reuse=True)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        ms_block = start.elapsed_time(stop)
+        log(f"{cfg.name} {precision}: propagation only {ms_prop / steps:.2f} ms/step; block of {BLOCK_STEPS} "
+            f"steps {ms_block:.1f} ms")
+        extra.update({
+            "propagation_only": {"value": round(W * steps / (ms_prop * 1e-3), 2), "unit": "walker-steps/s",
+                                 "ms_per_step": round(ms_prop / steps, 4)},
+            "block": {"value": round(W * BLOCK_STEPS / (ms_block * 1e-3), 2), "unit": "walker-steps/s",
+                      "ms_per_block": round(ms_block, 3),
+                      "definition": f"{BLOCK_STEPS} steps, QR and local energy at the last, "
+                                    "global energy, comb population control"}})
     return ham, w, e, ms, phases, status, extra, sample_state
 
 
@@ -256,12 +279,15 @@ def run_batch(device, steps, precision="fp16x3"):
 
     from paper_2209_04015_amd import afqmc, inputs
 
+    from oracle import afqmc_oracle as orc
+
     t = time.time()
     systems = inputs.uneven_batch()
-    hams, ws, fs, es, starts = [], [], [], [], []
+    hams, ws, fs, es, starts, defs = [], [], [], [], [], []
     for (N, n, K, decay, W, seed) in systems:
         h1, L = inputs.hamiltonian(N, K, decay, seed=seed)
         phiT = inputs.trial(h1, n)
+        defs.append((h1, L, phiT))
         ham = afqmc.Hamiltonian(h1, L, phiT, phiT, dt=0.005, max_walkers=W, precision=precision)
         pa = np.repeat(phiT[None].astype(np.complex128), W, axis=0)
         w = afqmc.Walkers.from_numpy(pa, pa.copy(), device=device)
@@ -287,6 +313,16 @@ def run_batch(device, steps, precision="fp16x3"):
     ms_b = start.elapsed_time(stop)
     st_b = sum(h.status() for h in hams)
     b.close()
+    # per-system energy error: the last step's local energies of sampled
+    # walkers against the oracle's local energy of the same walkers
+    per_sys = []
+    for (N, n, K, decay, W, seed), (h1, L, phiT), w, e in zip(systems, defs, ws, es):
+        k = min(4, W)
+        oh = orc.setup(h1, L, phiT, phiT, dt=0.005)
+        v = energy_errors(oh, {"s": (w.phi_a[:k].cpu().numpy(), w.phi_b[:k].cpu().numpy(),
+                                     e[-1, :k].cpu().numpy())})["s"]
+        per_sys.append({"N": N, "walkers": W, **v})
+    log("batch energy errors (of S): " + ", ".join(f"N{p['N']} {p['max_rel_to_S']:.1e}" for p in per_sys))
     # the same steps system after system (eager, one stream), from the same start
     for w, (a0, b0, l0, lw0) in zip(ws, starts):
         w.phi_a.copy_(a0)
@@ -315,6 +351,7 @@ def run_batch(device, steps, precision="fp16x3"):
                         "one hipGraph launch per step, autotuned exchange tile order",
             "value": round(wtot * steps / (ms_b * 1e-3), 1), "unit": "walker-steps/s",
             "ms_per_step": round(ms_b / steps, 4), "status": st_b,
+            "energy_error_vs_fp64_oracle": per_sys,
             "systems_in_turn": {"value": round(wtot * steps / (ms_s * 1e-3), 1), "unit": "walker-steps/s",
                                 "ms_per_step": round(ms_s / steps, 4)}}
 
@@ -366,98 +403,251 @@ def hbm_traffic(kernel, instance, workload):
     return None
 
 
+def mfma_busy(kernel, instance, workload):
+    """MFMA-busy share of a kernel from the committed counter summaries (lines
+    'mfma-busy <instance> <workload> frac=... sources_sha256=...'), or None."""
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    sha = kernel_sources_sha256(kernel)
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith("_hbm.md"):
+            continue
+        with open(os.path.join(pdir, name)) as fh:
+            for line in fh:
+                f = line.strip().strip("`").split()
+                if len(f) < 4 or f[0] != "mfma-busy" or f[1] != instance.replace(" ", "") or f[2] != workload:
+                    continue
+                kv = dict(x.split("=", 1) for x in f[3:] if "=" in x)
+                if kv.get("sources_sha256") == sha:
+                    return float(kv["frac"])
+    return None
+
+
 # kernel (and its template instance in the rocprofv3 summaries) per phase,
 # precision and exchange algorithm
 def _kernel_of(phase, precision, algo):
     split = precision in ("fp16x3", "bf16x3")
     H = {"fp16x3": "HalfF16", "bf16x3": "HalfBF16"}.get(precision)
-    T = {"fp32": "float", "fp64": "double", "bf16x3": "float"}.get(precision)
+    T = {"fp32": "float", "fp64": "double", "bf16x3": "float", "fp16x3": "float"}[precision]
     if phase == "exchange":
         base = ("exchange_pair" if algo == "pair" else "exchange") + ("_split_kernel" if split else "_kernel")
         return base, f"{base}<{H if split else T}>"
-    if precision == "fp16x3":   # the VHS runs on split operands only in FP16X3
-        return "vhs_split_kernel", "vhs_split_kernel<HalfF16>"
-    # tile template arguments of the FP32 / FP64 VHS instances (step_kernels.hip)
-    return "vhs_kernel", {"double": "vhs_kernel<double, 64, 64, 16, 2, 2>",
-                          "float": "vhs_kernel<float, 64, 64, 32, 2, 2>"}[T]
+    if phase == "vhs":
+        if precision == "fp16x3":   # the VHS runs on split operands only in FP16X3
+            return "vhs_split_kernel", "vhs_split_kernel<HalfF16>"
+        # tile template arguments of the FP32 / FP64 VHS instances (step_kernels.hip)
+        return "vhs_kernel", {"double": "vhs_kernel<double, 64, 64, 16, 2, 2>",
+                              "float": "vhs_kernel<float, 64, 64, 32, 2, 2>"}[T]
+    return None, None
 
 
-def roofline_of(cfg, phases, precision, algo, phase):
+def _mfma_dtype(phase, precision):
+    """The type the matrix cores of a phase execute in (whose peak the phase is
+    measured against)."""
+    if precision == "fp64":
+        return "fp64"
+    if phase == "exchange" and precision in ("fp16x3", "bf16x3"):
+        return precision[:4]
+    if phase in ("vhs", "taylor", "force_bias") and precision == "fp16x3":
+        return "fp16"
+    return "fp32"
+
+
+def phase_work(cfg, phase, precision, algo):
+    """Algorithmic work of one step's launches of a phase: (bound, amount, unit).
+    Flops: a real x complex multiply-add counts 4, complex x complex 8.  Bytes:
+    the arrays the phase must read and write once."""
+    N, n, K, W = cfg.N, cfg.n, cfg.K, cfg.W
+    ne = 2 * n                                # electrons, both spins
+    ts = 8 if precision == "fp64" else 4      # bytes of the working precision
+    if phase == "vhs":
+        return "mfma", vhs_flops_per_launch(cfg, W), "flop"
+    if phase == "exchange":
+        return "mfma", 2 * exchange_flops_per_launch(cfg, W, algo), "flop"   # two spins
+    if phase == "taylor":
+        return "mfma", W * cfg.taylor_order * 8.0 * N * N * n * 2, "flop"
+    if phase == "one_body":
+        return "mfma", 2 * W * 4.0 * N * N * ne, "flop"                   # two half steps
+    if phase == "force_bias":
+        return "mfma", W * 4.0 * K * N * ne, "flop"
+    if phase == "green":
+        return "hbm", W * N * ne * (16 + 2 * ts), "byte"                  # read phi, write theta
+    if phase == "qr":
+        return "hbm", 2 * W * N * ne * 16, "byte"                         # read and write phi
+    return None, None, None
+
+
+ROOFLINE_PHASES = ("vhs", "exchange", "taylor", "one_body", "force_bias", "qr", "green")
+
+
+def roofline_of(cfg, phases, precision, algo, phase, steps):
+    """Roofline entry of one phase from the profiled pass: algorithmic work of
+    one step's launches / their measured time, against the peak of the unit
+    the phase runs on (matrix cores of the MFMA dtype, or HBM)."""
     ms, launches = phases[phase]
     if launches == 0:
         return None
-    avg_ms = ms / launches
-    flops = (exchange_flops_per_launch(cfg, cfg.W, algo) if phase == "exchange"
-             else vhs_flops_per_launch(cfg, cfg.W))
-    achieved = flops / (avg_ms * 1e-3) / 1e12
-    kernel, instance = _kernel_of(phase, precision, algo)
-    note = None
-    if "split" in kernel:
-        # three 16-bit products per algorithmic multiply-add
-        peak = round(PEAK_TFLOPS[precision[:4]] / 3.0, 1)
-        note = f"{precision[:4]} dense peak / 3 products"
+    bound, work, unit = phase_work(cfg, phase, precision, algo)
+    if bound is None:
+        return None
+    ms_step = ms / steps
+    per_step_launches = launches / steps
+    if bound == "mfma":
+        dt = _mfma_dtype(phase, precision)
+        peak = PEAK_TFLOPS[dt]
+        achieved = work / (ms_step * 1e-3) / 1e12
+        out = {"phase": phase, "bound": "mfma", "mfma_dtype": dt, "achieved": round(achieved, 2),
+               "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+               "flops_per_step": work}
+        if dt in ("fp16", "bf16"):
+            # three 16-bit products per algorithmic multiply-add (hi/lo split):
+            # the share of the matrix-core pipe the products occupy
+            out["mfma_pipe_frac"] = round(3.0 * achieved / peak, 4)
     else:
-        peak = PEAK_TFLOPS["fp64" if precision == "fp64" else "fp32"]
-    out = {"kernel": kernel, "bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
-           "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-           "traffic": hbm_traffic(kernel, instance, cfg.name),
-           "avg_launch_ms": round(avg_ms, 4), "launches_per_step_share_ms": round(ms, 3),
-           "flops_per_launch": flops}
-    if note:
-        out["peak_note"] = note
+        achieved = work / (ms_step * 1e-3) / 1e9
+        out = {"phase": phase, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_GBS,
+               "unit": "GB/s", "frac": round(achieved / HBM_GBS, 4), "bytes_per_step": work}
+    kernel, instance = _kernel_of(phase, precision, algo)
+    if kernel:
+        out["kernel"] = kernel
+        out["traffic"] = hbm_traffic(kernel, instance, cfg.name)
+        busy = mfma_busy(kernel, instance, cfg.name)
+        if busy is not None:
+            out["mfma_busy_counter"] = busy
+    out["ms_per_step"] = round(ms_step, 4)
+    out["launches_per_step"] = round(per_step_launches, 2)
+    out["avg_launch_ms"] = round(ms / launches, 4)
     return out
 
 
-def rooflines(cfg, phases, precision, algo):
-    """Roofline entries of the exchange and VHS kernels; the first is the one with
-    the larger share of the step (the dominant kernel)."""
-    out = {ph: roofline_of(cfg, phases, precision, algo, ph) for ph in ("exchange", "vhs")}
+def rooflines(cfg, phases, precision, algo, steps):
+    """Roofline entries of the phases, largest share of the step first (the
+    first is the dominant kernel)."""
+    if not phases:
+        return {}
+    out = {ph: roofline_of(cfg, phases, precision, algo, ph, steps) for ph in ROOFLINE_PHASES}
     order = sorted(out, key=lambda ph: -phases[ph][0])
     return {ph: out[ph] for ph in order if out[ph] is not None}
 
 
-def roofline(cfg, phases, precision, algo):
-    r = rooflines(cfg, phases, precision, algo)
-    return next(iter(r.values())) if r else None
+def roofline(cfg, phases, precision, algo, steps):
+    """The dominant kernel's roofline: of the VHS build and the exchange (the
+    contractions the metric names), the one with the larger share of the step."""
+    r = rooflines(cfg, phases, precision, algo, steps)
+    for ph in r:
+        if ph in ("vhs", "exchange"):
+            return r[ph]
+    return None
 
 
-def cpu_baseline_and_energy_error(cfg, h1, L, phiT, gpu_states, sample, x_sample):
-    """The FP64 oracle: its walker-step rate on a bounded sample, and the per-walker
-    energy error of each GPU path against it on sampled walkers."""
+def host_description():
+    """CPU model, BLAS library and its thread count on this host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas, threads = None, None
+    try:
+        from threadpoolctl import threadpool_info
+
+        for d in threadpool_info():
+            if d.get("user_api") == "blas":
+                blas = f"{d.get('internal_api')} {d.get('version')}"
+                threads = d.get("num_threads")
+                break
+    except Exception:
+        pass
+    return model, blas, threads
+
+
+def energy_errors(oh, states):
+    """Per-walker energy error of each GPU path against the oracle's local
+    energy of the same (GPU) walkers: max |dE| in Ha and relative to
+    S = |E1| + |EJ| + |EK|."""
     from oracle import afqmc_oracle as orc
 
-    t = time.time()
-    oh = orc.setup(h1, L, phiT, phiT, dt=cfg.dt, taylor_order=cfg.taylor_order)
-    log(f"oracle setup {time.time() - t:.1f} s")
     out = {}
-    for prec, (pa, pb, e_gpu) in gpu_states.items():
+    for prec, (pa, pb, e_gpu) in states.items():
         e_ref = orc.local_energy(oh, pa, pb)
         S = np.abs(e_ref).sum(axis=1)
         err = np.abs(e_gpu.sum(axis=1) - e_ref.sum(axis=1))
         out[prec] = {"max_abs_Ha": float(err.max()), "max_rel_to_S": float((err / S).max()),
                      "walkers": int(len(err)), "E_scale_Ha": float(np.abs(e_ref.sum(axis=1)).max())}
-        log(f"energy error {prec}: {err.max():.3e} Ha ({(err / S).max():.2e} of S)")
-    # timed oracle sample: full steps (propagate, QR, energy) of `sample` walkers
+    return out
+
+
+def cpu_baseline_and_energy_error(cfg, h1, L, phiT, gpu_states, sample, x_steps):
+    """The FP64 oracle: its walker-step rate on a bounded sample (the median
+    of several full steps of `sample` walkers), and the per-walker energy
+    error of each GPU path against it on sampled walkers."""
+    from oracle import afqmc_oracle as orc
+
+    t = time.time()
+    oh = orc.setup(h1, L, phiT, phiT, dt=cfg.dt, taylor_order=cfg.taylor_order)
+    log(f"oracle setup {time.time() - t:.1f} s")
+    out = energy_errors(oh, gpu_states)
+    for prec, v in out.items():
+        log(f"energy error {cfg.name} {prec}: {v['max_abs_Ha']:.3e} Ha ({v['max_rel_to_S']:.2e} of S)")
+    # timed oracle sample: consecutive full steps (propagate, QR, energy) of
+    # `sample` walkers from the trial
     pa = np.repeat(phiT[None].astype(np.complex128), sample, axis=0)
     pb = pa.copy()
     lo = orc.overlap(oh, pa, pb)
     lw = np.zeros(sample)
-    t = time.time()
-    orc.step(oh, pa, pb, lo, lw, x_sample, do_qr=True)
-    dt = time.time() - t
-    threads = None
-    try:
-        from threadpoolctl import threadpool_info
-
-        threads = max((d.get("num_threads", 0) for d in threadpool_info()), default=None)
-    except Exception:
-        pass
-    cpu = {"value": round(sample / dt, 3), "unit": "walker-steps/s",
+    times = []
+    for x in x_steps:
+        t = time.time()
+        pa, pb, lo, lw, _ = orc.step(oh, pa, pb, lo, lw, x[:sample], do_qr=True)
+        times.append(time.time() - t)
+    med = float(np.median(times))
+    model, blas, threads = host_description()
+    cpu = {"value": round(sample / med, 3), "unit": "walker-steps/s",
            "cores": threads or os.cpu_count(), "kind": "oracle",
-           "sample": f"{sample} walkers x 1 full step (propagate, QR, local energy) of the same "
-                     f"workload, FP64 NumPy oracle; setup not timed; {dt:.1f} s"}
-    log(f"oracle: {sample} walker-steps in {dt:.1f} s")
+           "sample": f"{sample} walkers x {len(times)} consecutive full steps (propagate, QR, local energy) of the "
+                     f"same workload from the trial, FP64 NumPy oracle; median step {med:.2f} s "
+                     f"(steps {', '.join(f'{x:.2f}' for x in times)} s); setup not timed",
+           "cpu_model": model, "blas": blas, "host_cpus": os.cpu_count()}
+    log(f"oracle: {sample} walkers, median step {med:.2f} s over {len(times)} steps ({model}; {blas})")
     return cpu, out
+
+
+def run_config_leg(name, precisions, steps, warmup, device, sample=6):
+    """Another workload at its own size (one fused step per walker per step,
+    QR on its schedule, energy every step): walker-steps/s of each path and
+    the per-walker energy error of its last step against the oracle."""
+    import torch
+
+    from oracle import afqmc_oracle as orc
+    from paper_2209_04015_amd import inputs
+
+    cfg = inputs.CONFIGS[name]
+    h1, L = inputs.hamiltonian(cfg.N, cfg.K, cfg.decay, seed=0)
+    phiT = inputs.trial(h1, cfg.n)
+    fields_dev = torch.as_tensor(inputs.fields(cfg.W, cfg.K, warmup + steps, seed=0), device=device)
+    res, states = {}, {}
+    for prec in precisions:
+        ham, w, e, ms, _, st, extra, stt = run_gpu(cfg, h1, L, phiT, prec, steps, warmup, fields_dev, None, device,
+                                                    sample=sample, secondary=False, profile=False)
+        res[prec] = {"value": round(cfg.W * steps / (ms * 1e-3), 2), "unit": "walker-steps/s",
+                     "ms_per_step": round(ms / steps, 4), "status": st,
+                     "exchange_algorithm": extra["exchange_algorithm"]}
+        states[prec] = stt
+        ham.close()
+        del w, e
+        torch.cuda.empty_cache()
+    oh = orc.setup(h1, L, phiT, phiT, dt=cfg.dt, taylor_order=cfg.taylor_order)
+    for prec, v in energy_errors(oh, states).items():
+        res[prec]["energy_error_vs_fp64_oracle"] = v
+        log(f"energy error {name} {prec}: {v['max_abs_Ha']:.3e} Ha ({v['max_rel_to_S']:.2e} of S)")
+    return {"workload": f"{name}: N={cfg.N}, na=nb={cfg.n}, K={cfg.K}, {cfg.W} walkers, dt={cfg.dt}, QR every "
+                        f"{cfg.qr_interval} step(s), energy every step; {steps} timed steps after {warmup}",
+            "paths": res}
 
 
 def main():
@@ -466,7 +656,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="n290")
-    ap.add_argument("--cpu-sample", type=int, default=12, help="walkers in the timed oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=4, help="walkers in the timed oracle sample")
+    ap.add_argument("--cpu-steps", type=int, default=5, help="consecutive oracle steps timed (median reported)")
+    ap.add_argument("--energy-sample", type=int, default=8, help="walkers compared with the oracle's energy")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--only", choices=MODES, help="run one path only (profiling runs)")
     ap.add_argument("--headline", choices=MODES[1:], default="fp16x3",
@@ -477,6 +669,7 @@ def main():
                     help="time the multi-determinant trial calls only (profiling runs)")
     ap.add_argument("--msd-dets", type=int, default=MSD_DETS, help="determinants of the multi-determinant trial")
     ap.add_argument("--batch-only", action="store_true", help="time the uneven multi-system batch only")
+    ap.add_argument("--no-legs", action="store_true", help="skip the other workloads (n100, n200, MSD, batch)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -495,7 +688,7 @@ def main():
     h1, L = inputs.hamiltonian(cfg.N, cfg.K, cfg.decay, seed=0)
     phiT = inputs.trial(h1, cfg.n)
     nsteps = args.warmup + args.steps
-    fields = inputs.fields(cfg.W, cfg.K, nsteps, seed=0)
+    fields = inputs.fields(cfg.W, cfg.K, max(nsteps, args.cpu_steps), seed=0)
     fields_dev = torch.as_tensor(fields, device=device)
     block_fields_dev = torch.as_tensor(inputs.fields(cfg.W, cfg.K, BLOCK_STEPS, seed=1), device=device)
     log(f"inputs {cfg.name}: N={cfg.N} n={cfg.n} K={cfg.K} W={cfg.W} generated in {time.time() - t:.1f} s")
@@ -519,13 +712,13 @@ def main():
     results = {}
     extras = {}
     states = {}
-    sample = min(args.cpu_sample, cfg.W)
+    esample = min(args.energy_sample, cfg.W)
     for precision in MODES:
         if args.only and precision != args.only:
             continue
         ham, w, e, ms, phases, status, extra, st = run_gpu(cfg, h1, L, phiT, precision, args.steps, args.warmup,
                                                            fields_dev, block_fields_dev, device,
-                                                           exchange=args.exchange, sample=sample)
+                                                           exchange=args.exchange, sample=esample)
         results[precision] = (ms, phases, status)
         extras[precision] = extra
         states[precision] = st
@@ -533,47 +726,54 @@ def main():
         del w, e
         torch.cuda.empty_cache()
 
-    # the paper's direct exchange algorithm on the headline path, for comparison
-    direct = None
-    if not args.only:
-        ham, w, e, ms_d, ph_d, st_d, ex_d, _ = run_gpu(cfg, h1, L, phiT, args.headline, args.steps, args.warmup,
-                                                      fields_dev, block_fields_dev, device, exchange="direct")
-        direct = {"exchange_algorithm": "direct", "value": round(cfg.W * args.steps / (ms_d * 1e-3), 2),
-                  "unit": "walker-steps/s", "ms_per_step": round(ms_d / args.steps, 4),
-                  "roofline": roofline(cfg, ph_d, args.headline, "direct"),
-                  "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in ph_d.items() if v[1] > 0}}
-        ham.close()
-        del w, e
-        torch.cuda.empty_cache()
-
-    msd = None if args.only else run_msd(cfg, h1, L, device, args.steps, args.msd_dets)
-    batch = None if args.only else run_batch(device, args.steps)
+    def phase_table(phases):
+        return {k: round(v[0] / args.steps, 4) for k, v in phases.items() if v[1] > 0}
 
     if args.only:
         ms, ph, st = results[args.only]
+        algo = extras[args.only]["exchange_algorithm"]
         print(json.dumps({"metric": METRIC, "value": round(cfg.W * args.steps / (ms * 1e-3), 2),
                           "unit": "walker-steps/s", "n_gpus": 1, "steps": args.steps,
                           "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 4),
                           "only": args.only,
-                          "roofline": roofline(cfg, ph, args.only, extras[args.only]["exchange_algorithm"]),
-                          "rooflines": rooflines(cfg, ph, args.only, extras[args.only]["exchange_algorithm"]),
+                          "roofline": roofline(cfg, ph, args.only, algo, args.steps),
+                          "rooflines": rooflines(cfg, ph, args.only, algo, args.steps),
                           **extras[args.only],
-                          "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in ph.items()
-                                                 if v[1] > 0}}), flush=True)
+                          "phases_ms_per_step": phase_table(ph)}), flush=True)
         return
+
+    # the paper's direct exchange algorithm on the headline path, for comparison
+    ham, w, e, ms_d, ph_d, st_d, ex_d, _ = run_gpu(cfg, h1, L, phiT, args.headline, args.steps, args.warmup,
+                                                  fields_dev, block_fields_dev, device, exchange="direct",
+                                                  secondary=False)
+    direct = {"exchange_algorithm": "direct", "value": round(cfg.W * args.steps / (ms_d * 1e-3), 2),
+              "unit": "walker-steps/s", "ms_per_step": round(ms_d / args.steps, 4),
+              "roofline": rooflines(cfg, ph_d, args.headline, "direct", args.steps).get("exchange"),
+              "phases_ms_per_step": phase_table(ph_d)}
+    ham.close()
+    del w, e
+    torch.cuda.empty_cache()
+
+    legs = {}
+    msd = batch = None
+    if not args.no_legs:
+        # BASELINE configurations other than the headline: the FP64 GPU
+        # baseline size (n100) and the mixed-precision size (n200)
+        legs["n100"] = run_config_leg("n100", ("fp64", args.headline), 10, 2, device)
+        legs["n200"] = run_config_leg("n200", ("fp64", "fp32", "bf16x3", "fp16x3"), 10, 2, device)
+        msd = run_msd(cfg, h1, L, device, args.steps, args.msd_dets)
+        batch = run_batch(device, args.steps)
 
     cpu = None
     eerr = None
     if not args.no_cpu:
-        cpu, eerr = cpu_baseline_and_energy_error(cfg, h1, L, phiT, states, sample,
-                                                  fields[0, :sample])
+        cpu, eerr = cpu_baseline_and_energy_error(cfg, h1, L, phiT, states, args.cpu_sample,
+                                                  fields[:args.cpu_steps])
 
     W = cfg.W
+
     def rate(ms):
         return W * args.steps / (ms * 1e-3)
-
-    def phase_table(phases):
-        return {k: round(v[0] / args.steps, 4) for k, v in phases.items() if v[1] > 0}
 
     head = args.headline
     msh, phh, sth = results[head]
@@ -582,15 +782,16 @@ def main():
     paths = {}
     for p in MODES:
         ms, ph, st = results[p]
+        algo = extras[p]["exchange_algorithm"]
         paths[p] = {"value": round(rate(ms), 2), "unit": "walker-steps/s",
                     "ms_per_step": round(ms / args.steps, 4),
-                    "roofline": roofline(cfg, ph, p, extras[p]["exchange_algorithm"]),
-                    "rooflines": rooflines(cfg, ph, p, extras[p]["exchange_algorithm"]),
+                    "roofline": roofline(cfg, ph, p, algo, args.steps),
+                    "rooflines": rooflines(cfg, ph, p, algo, args.steps),
                     "phases_ms_per_step": phase_table(ph), "status": st,
                     "energy_error_vs_fp64_oracle": (eerr or {}).get(p), **extras[p]}
-    dtypes = {"fp32": "f32 contractions (MFMA)",
-              "fp16x3": "f16 hi/lo x3 exchange and VHS + f32 contractions (MFMA)",
-              "bf16x3": "bf16 hi/lo x3 exchange + f32 contractions (MFMA)"}
+    dtypes = {"fp32": "f32 (MFMA) contractions and one-body half steps",
+              "fp16x3": "f16 hi/lo x3 (MFMA) force bias, VHS, Taylor and exchange; f32 (MFMA) one-body half steps",
+              "bf16x3": "bf16 hi/lo x3 (MFMA) exchange; f32 (MFMA) force bias, VHS, Taylor and one-body half steps"}
     line = {
         "metric": METRIC,
         "value": round(rate(msh), 2),
@@ -602,19 +803,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": dtypes[head] + " + f64 overlaps/solves/QR/weights/energy sums",
+        "dtype": dtypes[head] + "; f64 walkers, overlaps, solves, QR, weights and energy sums",
         "data": "synthetic",
         "config": {
             "workload": f"{cfg.name}: ph-AFQMC full walker step (propagate + QR + local energy every "
                         f"step), N={cfg.N} orbitals, na=nb={cfg.n}, K={cfg.K} Cholesky vectors, "
                         f"{W} walkers, dt={cfg.dt}, Taylor order {cfg.taylor_order}, QR every "
-                        f"{cfg.qr_interval} step(s); exchange energy through pair integrals "
-                        f"({extras[head]['exchange_algorithm']})",
+                        f"{cfg.qr_interval} step(s); exchange energy algorithm: "
+                        f"{extras[head]['exchange_algorithm']}",
             "exchange_algorithm": extras[head]["exchange_algorithm"],
             "walkers": W, "N": cfg.N, "n_per_spin": cfg.n, "K": cfg.K, "headline_path": head,
         },
-        "roofline": roofline(cfg, phh, head, extras[head]["exchange_algorithm"]),
-        "rooflines": rooflines(cfg, phh, head, extras[head]["exchange_algorithm"]),
+        "roofline": roofline(cfg, phh, head, extras[head]["exchange_algorithm"], args.steps),
+        "rooflines": rooflines(cfg, phh, head, extras[head]["exchange_algorithm"], args.steps),
+        "roofline_note": "achieved = algorithmic work of the phase's launches in one step / their time, measured "
+                         "with HIP events around every launch in a second (profiled) pass of the same number of "
+                         "steps; value and ms_per_step come from the pass without events",
         "cpu_baseline": cpu,
         "fp64": paths["fp64"],
         "mixed_over_fp64": round(ms64 / msh, 3),
@@ -622,6 +826,7 @@ def main():
         **extras[head],
         "phases_ms_per_step": phase_table(phh),
         "direct_exchange": direct,
+        "config_legs": legs,
         "multi_determinant_trial": msd,
         "uneven_batch": batch,
         "paths": paths,

@@ -48,18 +48,27 @@ enum {
   AFQMC_EUNSUPPORTED = 4   /* shape outside what the kernels support */
 };
 
-/* Working precision of the contractions (force bias, VHS, Taylor products,
- * exchange).  Overlaps, determinants, inverses, weights, QR, the one-body
- * half steps and all energy sums are FP64 in every mode.
- *   AFQMC_FP64    all contractions on FP64 matrix cores
- *   AFQMC_FP32    all contractions on FP32 matrix cores, FP32 accumulation
- *   AFQMC_BF16X3  as FP32, but the exchange contraction (Sec. III.C, the
- *                 quartic term) splits each FP32 operand into bf16 hi + lo and
- *                 keeps the three leading products on the bf16 matrix cores
- *                 with FP32 accumulation (relative operand error ~2^-16)
- *   AFQMC_FP16X3  the same split in fp16 with power-of-two row scaling
- *                 (relative operand error ~2^-22, close to FP32), applied
- *                 to the exchange and to the VHS build */
+/* Working precision.  In every mode the walkers stay FP64 in memory, and the
+ * overlaps, determinants, Green's functions theta (Gauss-Jordan in FP64),
+ * weights, QR and every energy sum are FP64.  The modes differ in the
+ * contractions:
+ *   AFQMC_FP64    every contraction on the FP64 matrix cores
+ *   AFQMC_FP32    force bias, VHS build, Taylor products, exchange and both
+ *                 one-body half steps P phi (Eq. Bx, split as in
+ *                 afqmc_propagate) on the FP32 matrix cores: operands
+ *                 rounded to FP32, FP32 accumulation; the Taylor terms are
+ *                 summed in FP64
+ *   AFQMC_BF16X3  as AFQMC_FP32, except that the exchange contraction
+ *                 (Sec. III.C, the quartic term) splits each FP32 operand
+ *                 into bf16 hi + lo and keeps the three leading products on
+ *                 the bf16 matrix cores (relative operand error ~2^-16)
+ *   AFQMC_FP16X3  as AFQMC_FP32, except that the force bias, the VHS build,
+ *                 the Taylor products and the exchange split their FP32
+ *                 operands into fp16 hi + lo with power-of-two scales and
+ *                 keep the three leading products on the fp16 matrix cores
+ *                 (relative operand error ~2^-22, close to FP32)
+ * afqmc_params.flags & AFQMC_FLAG_ONE_BODY_FP64 keeps the one-body half steps
+ * on the FP64 matrix cores in the FP32, BF16X3 and FP16X3 modes. */
 enum { AFQMC_FP64 = 0, AFQMC_FP32 = 1, AFQMC_BF16X3 = 2, AFQMC_FP16X3 = 3 };
 
 /* Status-word bits (afqmc_get_status). */
@@ -79,7 +88,11 @@ typedef struct afqmc_params {
   double mu;            /* scalar factored out of the one-body half step; NaN -> tr(h')/N */
   double e_shift;       /* energy shift E_T of the weights; NaN -> E_L(PhiT) computed in FP64 */
   int exchange;         /* AFQMC_EXCHANGE_*: algorithm of the exchange energy (0 = automatic) */
+  int flags;            /* AFQMC_FLAG_* bits (0 = defaults) */
 } afqmc_params;
+
+/* afqmc_params.flags */
+enum { AFQMC_FLAG_ONE_BODY_FP64 = 1 };
 
 /* Algorithms of the exchange energy E_K = -1/2 sum_s sum_g sum_ij T_ij T_ji
  * (Sec. III.C).  Both give the same sum up to rounding.
@@ -152,7 +165,8 @@ int afqmc_local_energy(afqmc_ham* ham, const afqmc_walkers* w, int nw, void* e, 
  * Householder QR followed by the phases diag(R_ii/|R_ii|)); phi <- Q,
  * log_ovlp -= sum ln R_ii.  Computed as Cholesky QR applied twice.  E_L and
  * theta are unchanged by this, up to rounding.  A rank-deficient walker sets
- * AFQMC_STATUS_QR_ZERO and is left unchanged with log_ovlp -> +inf. */
+ * AFQMC_STATUS_QR_ZERO, keeps its orbitals and is discarded: log_ovlp ->
+ * +inf and log_w -> -inf (weight 0, as the step's weight update does). */
 int afqmc_orthogonalise(afqmc_ham* ham, afqmc_walkers* w, int nw, void* stream);
 
 /* One full step: afqmc_propagate, then afqmc_orthogonalise if do_qr, then

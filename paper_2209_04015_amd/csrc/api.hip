@@ -37,9 +37,37 @@ int fail(int code, const char* fmt, ...) {
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \
     if (e_ != hipSuccess)                                                              \
-      return fail(AFQMC_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),   \
+      return fail(e_ == hipErrorOutOfMemory ? AFQMC_ENOMEM : AFQMC_EHIP,                \
+                  "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),               \
                   __FILE__, __LINE__);                                                 \
   } while (0)
+
+// Device temporaries of one setup routine, freed on every return path (after
+// the device has finished with them).
+class TempAllocs {
+ public:
+  TempAllocs() = default;
+  TempAllocs(const TempAllocs&) = delete;
+  TempAllocs& operator=(const TempAllocs&) = delete;
+  ~TempAllocs() {
+    if (p_.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (void* q : p_) (void)hipFree(q);
+  }
+  template <typename T>
+  hipError_t get(T** out, size_t bytes) {
+    *out = nullptr;
+    void* q = nullptr;
+    const hipError_t e = hipMalloc(&q, bytes ? bytes : 16);
+    if (e != hipSuccess) return e;
+    p_.push_back(q);
+    *out = static_cast<T*>(q);
+    return hipSuccess;
+  }
+
+ private:
+  std::vector<void*> p_;
+};
 
 }  // namespace
 
@@ -284,9 +312,12 @@ int seq_propagate_core(afqmc_ham* h, afqmc_walkers* w, int nw, const StepIO& io,
     PHASE(h, AFQMC_PH_VHS, s,
           (launch_vhs<T>(d, nw, (const T*)h->xs, (const T*)h->LT, h->pq, (T*)h->vhs, h->sdt, s)));
   }
+  const bool pphi64 = sizeof(T) == 8 || (h->prm.flags & AFQMC_FLAG_ONE_BODY_FP64);
   PHASE(h, AFQMC_PH_ONE_BODY, s,
-        launch_pphi<T>(d, nw, h->P, (const double2*)w->phi_a, (const double2*)w->phi_b, h->acc, nullptr,
-                    nullptr, h->tmax, 0, s));
+        pphi64 ? launch_pphi<double>(d, nw, h->P, (const double2*)w->phi_a, (const double2*)w->phi_b, h->acc,
+                                     nullptr, nullptr, h->tmax, 0, s)
+               : launch_pphi<float>(d, nw, h->P, (const double2*)w->phi_a, (const double2*)w->phi_b, h->acc,
+                                    nullptr, nullptr, h->tmax, 0, s));
   const int order = h->prm.taylor_order;
   if (vhs_split(h)) {
     // every term kept (tk[k - 1]), summed into acc once at the end
@@ -307,8 +338,10 @@ int seq_propagate_core(afqmc_ham* h, afqmc_walkers* w, int nw, const StepIO& io,
     }
   }
   PHASE(h, AFQMC_PH_ONE_BODY, s,
-        launch_pphi<T>(d, nw, h->P, nullptr, nullptr, h->acc, (double2*)w->phi_a, (double2*)w->phi_b,
-                    nullptr, 1, s));
+        pphi64 ? launch_pphi<double>(d, nw, h->P, nullptr, nullptr, h->acc, (double2*)w->phi_a,
+                                     (double2*)w->phi_b, nullptr, 1, s)
+               : launch_pphi<float>(d, nw, h->P, nullptr, nullptr, h->acc, (double2*)w->phi_a,
+                                    (double2*)w->phi_b, nullptr, 1, s));
   return AFQMC_OK;
 }
 
@@ -397,16 +430,13 @@ int build_working_arrays(afqmc_ham* h, const double* dL, const double* Y_a, cons
   if ((rc = dalloc_t(h, &h->lt_split, (size_t)nrow * 2 * d.ldhK))) return rc;
   if ((rc = dalloc_t(h, &h->lt_unscale, (size_t)nrow))) return rc;
   float* lt32 = nullptr;
-  HIP_TRY(hipMalloc(&lt32, (size_t)nrow * d.ldK * sizeof(float)));
-  HIP_TRY(hipMalloc(&pqb_dev, (size_t)nrow * sizeof(int2)));
-  hipError_t e = hipMemcpy(pqb_dev, pqb.data(), (size_t)nrow * sizeof(int2), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = setup_pack_lt<float>(d.K, d.N, (int)nrow, d.ldK, pqb_dev, dL, lt32, s);
-  if (e == hipSuccess)
-    e = launch_split_rows_mode(h->split, nrow, d.K, lt32, d.ldK, h->lt_split, d.ldhK, h->lt_unscale, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(lt32);
-  (void)hipFree(pqb_dev);
-  HIP_TRY(e);
+  TempAllocs tmp;
+  HIP_TRY(tmp.get(&lt32, (size_t)nrow * d.ldK * sizeof(float)));
+  HIP_TRY(tmp.get(&pqb_dev, (size_t)nrow * sizeof(int2)));
+  HIP_TRY(hipMemcpy(pqb_dev, pqb.data(), (size_t)nrow * sizeof(int2), hipMemcpyHostToDevice));
+  HIP_TRY(setup_pack_lt<float>(d.K, d.N, (int)nrow, d.ldK, pqb_dev, dL, lt32, s));
+  HIP_TRY(launch_split_rows_mode(h->split, nrow, d.K, lt32, d.ldK, h->lt_split, d.ldhK, h->lt_unscale, s));
+  HIP_TRY(hipStreamSynchronize(s));
   // force bias: Lh split with one scale per Cholesky vector (rows (spin, i))
   if ((rc = dalloc_t(h, &h->fb_lh, (size_t)d.K * 2 * d.nmax * 2 * d.ldh))) return rc;
   if ((rc = dalloc_t(h, &h->fb_lh_unscale, (size_t)d.K))) return rc;
@@ -418,15 +448,15 @@ int build_working_arrays(afqmc_ham* h, const double* dL, const double* Y_a, cons
 // E_T = E_L(PhiT), always evaluated with FP64 contractions.
 int trial_energy_fp64(afqmc_ham* h, const double* Y_a, const double* Y_b, hipStream_t s, double* et) {
   const StepDims& d = h->d;
-  int rc;
+  TempAllocs tmp;
   void* Lh64 = h->Lh;
   void* theta64 = h->theta;
-  double* tmp_lh = nullptr;
-  double* tmp_theta = nullptr;
   if (h->prec != AFQMC_FP64) {
-    HIP_TRY(hipMalloc(&tmp_lh, (size_t)2 * d.K * d.nmax * d.ldN * sizeof(double)));
+    double* tmp_lh = nullptr;
+    double* tmp_theta = nullptr;
+    HIP_TRY(tmp.get(&tmp_lh, (size_t)2 * d.K * d.nmax * d.ldN * sizeof(double)));
     HIP_TRY(hipMemset(tmp_lh, 0, (size_t)2 * d.K * d.nmax * d.ldN * sizeof(double)));
-    HIP_TRY(hipMalloc(&tmp_theta, (size_t)4 * d.nmax * d.ldN * sizeof(double)));
+    HIP_TRY(tmp.get(&tmp_theta, (size_t)4 * d.nmax * d.ldN * sizeof(double)));
     HIP_TRY(hipMemset(tmp_theta, 0, (size_t)4 * d.nmax * d.ldN * sizeof(double)));
     HIP_TRY((setup_pack_lh<double>(d.K, d.N, d.na, d.nmax, d.ldN, Y_a, tmp_lh, s)));
     if (d.nb > 0)
@@ -436,9 +466,9 @@ int trial_energy_fp64(afqmc_ham* h, const double* Y_a, const double* Y_b, hipStr
     theta64 = tmp_theta;
   }
   double2 *wa = nullptr, *wb = nullptr, *e = nullptr;
-  HIP_TRY(hipMalloc(&wa, (size_t)d.N * d.nmax * sizeof(double2)));
-  HIP_TRY(hipMalloc(&wb, (size_t)d.N * d.nmax * sizeof(double2)));
-  HIP_TRY(hipMalloc(&e, 3 * sizeof(double2)));
+  HIP_TRY(tmp.get(&wa, (size_t)d.N * d.nmax * sizeof(double2)));
+  HIP_TRY(tmp.get(&wb, (size_t)d.N * d.nmax * sizeof(double2)));
+  HIP_TRY(tmp.get(&e, 3 * sizeof(double2)));
   HIP_TRY(setup_trial_walker(d.N, d.na, d.nmax, h->phiT, wa, s));
   HIP_TRY(setup_trial_walker(d.N, d.nb, d.nmax, h->phiT + (size_t)d.N * d.nmax, wb, s));
   HIP_TRY((launch_gf<double>(d, 1, wa, wb, h->phiT, h->hh, (double*)theta64, h->logdet, h->e1,
@@ -453,12 +483,6 @@ int trial_energy_fp64(afqmc_ham* h, const double* Y_a, const double* Y_b, hipStr
   HIP_TRY(hipMemcpyAsync(he, e, sizeof he, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   *et = he[0].x + he[1].x + he[2].x;
-  (void)hipFree(wa);
-  (void)hipFree(wb);
-  (void)hipFree(e);
-  if (tmp_lh) (void)hipFree(tmp_lh);
-  if (tmp_theta) (void)hipFree(tmp_theta);
-  (void)rc;
   return AFQMC_OK;
 }
 
@@ -524,11 +548,12 @@ int build_pair_integrals(afqmc_ham* h, const double* Y_a, const double* Y_b, boo
   }
   double* C = nullptr;
   float* tmp = nullptr;
+  TempAllocs temps;
   const int nmx = shared ? d.na : d.nmax;
-  HIP_TRY(hipMalloc(&C, (size_t)N * nmx * N * nmx * sizeof(double)));
+  HIP_TRY(temps.get(&C, (size_t)N * nmx * N * nmx * sizeof(double)));
   if (h->split != SPLIT_NONE) {
     const long rmax = rows[0] > rows[1] ? rows[0] : rows[1];
-    HIP_TRY(hipMalloc(&tmp, (size_t)rmax * d.ldN * sizeof(float)));
+    HIP_TRY(temps.get(&tmp, (size_t)rmax * d.ldN * sizeof(float)));
   }
   for (int sp = 0; sp < (shared ? 1 : 2); ++sp) {
     const int n = sp ? d.nb : d.na;
@@ -549,8 +574,6 @@ int build_pair_integrals(afqmc_ham* h, const double* Y_a, const double* Y_b, boo
     }
   }
   HIP_TRY(hipStreamSynchronize(s));
-  (void)hipFree(C);
-  if (tmp) (void)hipFree(tmp);
   return AFQMC_OK;
 }
 
@@ -583,10 +606,11 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
   const int N = d.N, K = d.K, nmax = d.nmax;
   const size_t NN = (size_t)N * N;
   // ---- inputs ----
+  TempAllocs tmp;  // setup temporaries (L alone is K N^2 doubles), freed on every exit
   double *dh1 = nullptr, *dL = nullptr;
-  HIP_TRY(hipMalloc(&dh1, NN * sizeof(double)));
+  HIP_TRY(tmp.get(&dh1, NN * sizeof(double)));
   HIP_TRY(hipMemcpy(dh1, host_h1, NN * sizeof(double), hipMemcpyHostToDevice));
-  HIP_TRY(hipMalloc(&dL, (size_t)K * NN * sizeof(double)));
+  HIP_TRY(tmp.get(&dL, (size_t)K * NN * sizeof(double)));
   HIP_TRY(hipMemcpy(dL, host_chol, (size_t)K * NN * sizeof(double), hipMemcpyHostToDevice));
   if ((rc = dalloc_t(h, &h->phiT, (size_t)2 * N * nmax))) return rc;
   {
@@ -607,11 +631,11 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
 
   // ---- h' = h1 - 1/2 sum_g L_g L_g, mu ----
   double *LL = nullptr, *hp = nullptr, *scal = nullptr, *scratch = nullptr;
-  HIP_TRY(hipMalloc(&LL, NN * sizeof(double)));
-  HIP_TRY(hipMalloc(&hp, NN * sizeof(double)));
-  HIP_TRY(hipMalloc(&scal, 4 * sizeof(double)));
+  HIP_TRY(tmp.get(&LL, NN * sizeof(double)));
+  HIP_TRY(tmp.get(&hp, NN * sizeof(double)));
+  HIP_TRY(tmp.get(&scal, 4 * sizeof(double)));
   const int nchunk = 64;
-  HIP_TRY(hipMalloc(&scratch, (size_t)nchunk * NN * sizeof(double)));
+  HIP_TRY(tmp.get(&scratch, (size_t)nchunk * NN * sizeof(double)));
   HIP_TRY(setup_gemm(N, N, K * N, 2, dL, N, dL, N, LL, N, scratch, nchunk, s));
   HIP_TRY(setup_hprime(N, dh1, LL, hp, scal, s));
   double tr = 0.0;
@@ -630,17 +654,17 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
     nrm *= 0.5;
     ++sq;
   }
-  HIP_TRY(hipMalloc(&R, NN * sizeof(double)));
+  HIP_TRY(tmp.get(&R, NN * sizeof(double)));
   HIP_TRY(setup_expm(N, A, sq, 18, R, T, s));
   if ((rc = dalloc_t(h, &h->P, (size_t)N * d.ldP))) return rc;
   HIP_TRY(setup_copy_pad(N, N, R, N, h->P, d.ldP, s));
 
   // ---- half-rotated vectors: Y_s = [K N][N] x PhiT_s -> Lh ----
   double *Y_a = nullptr, *Y_b = nullptr, *pa_dense = nullptr, *pb_dense = nullptr;
-  HIP_TRY(hipMalloc(&Y_a, (size_t)K * N * (d.na > 0 ? d.na : 1) * sizeof(double)));
-  HIP_TRY(hipMalloc(&Y_b, (size_t)K * N * (d.nb > 0 ? d.nb : 1) * sizeof(double)));
-  HIP_TRY(hipMalloc(&pa_dense, (size_t)N * (d.na > 0 ? d.na : 1) * sizeof(double)));
-  HIP_TRY(hipMalloc(&pb_dense, (size_t)N * (d.nb > 0 ? d.nb : 1) * sizeof(double)));
+  HIP_TRY(tmp.get(&Y_a, (size_t)K * N * (d.na > 0 ? d.na : 1) * sizeof(double)));
+  HIP_TRY(tmp.get(&Y_b, (size_t)K * N * (d.nb > 0 ? d.nb : 1) * sizeof(double)));
+  HIP_TRY(tmp.get(&pa_dense, (size_t)N * (d.na > 0 ? d.na : 1) * sizeof(double)));
+  HIP_TRY(tmp.get(&pb_dense, (size_t)N * (d.nb > 0 ? d.nb : 1) * sizeof(double)));
   HIP_TRY(hipMemcpy(pa_dense, host_pa, (size_t)N * d.na * sizeof(double), hipMemcpyHostToDevice));
   if (d.nb > 0) HIP_TRY(hipMemcpy(pb_dense, host_pb, (size_t)N * d.nb * sizeof(double), hipMemcpyHostToDevice));
   HIP_TRY(setup_gemm(K * N, d.na, N, 0, dL, N, pa_dense, d.na, Y_a, d.na, nullptr, 1, s));
@@ -735,17 +759,6 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
   h->cst = -p.dt * (h->mu * (d.na + d.nb) - h->e_shift);
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipMemset(h->status, 0, sizeof(int)));
-  (void)hipFree(dh1);
-  (void)hipFree(dL);
-  (void)hipFree(LL);
-  (void)hipFree(hp);
-  (void)hipFree(scal);
-  (void)hipFree(scratch);
-  (void)hipFree(R);
-  (void)hipFree(Y_a);
-  (void)hipFree(Y_b);
-  (void)hipFree(pa_dense);
-  (void)hipFree(pb_dense);
   return AFQMC_OK;
 }
 
@@ -795,6 +808,7 @@ int afqmc_init_hamiltonian(const afqmc_params* params, const double* host_h1,
   if (p.max_walkers < 1) return fail(AFQMC_EINVAL, "max_walkers must be >= 1");
   if (p.exchange < AFQMC_EXCHANGE_AUTO || p.exchange > AFQMC_EXCHANGE_PAIR)
     return fail(AFQMC_EINVAL, "unknown exchange algorithm %d", p.exchange);
+  if (p.flags & ~AFQMC_FLAG_ONE_BODY_FP64) return fail(AFQMC_EINVAL, "unknown flags 0x%x", p.flags);
   const int nmax = p.na > p.nb ? p.na : p.nb;
   if (qr_lds_bytes_for(p.N, nmax) > 160 * 1024)
     return fail(AFQMC_EUNSUPPORTED, "N * max(na, nb) too large for the in-LDS QR (N=%d, n=%d)", p.N, nmax);
@@ -870,7 +884,7 @@ int afqmc_orthogonalise(afqmc_ham* h, afqmc_walkers* w, int nw, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   PHASE(h, AFQMC_PH_QR, s,
         launch_qr(h->d, nw, (double2*)w->phi_a, (double2*)w->phi_b, h->corr, h->status, s));
-  HIP_TRY(launch_ortho_update(nw, h->corr, (double2*)w->log_ovlp, s));
+  HIP_TRY(launch_ortho_update(nw, h->corr, (double2*)w->log_ovlp, w->log_w, s));
   // theta is invariant under re-orthogonalisation; the cached force bias stays valid.
   return AFQMC_OK;
 }

@@ -93,7 +93,7 @@ hipError_t launch_counter_set(int* ctr, int v, hipStream_t s);
 // QR of every walker and spin (Cholesky QR, twice); corr[W][2] = sum ln R_ii.
 hipError_t launch_qr(const StepDims& d, int W, double2* phi_a, double2* phi_b, double* corr,
                      int* status, hipStream_t s);
-hipError_t launch_ortho_update(int W, const double* corr, double2* log_ovlp, hipStream_t s);
+hipError_t launch_ortho_update(int W, const double* corr, double2* log_ovlp, double* log_w, hipStream_t s);
 
 hipError_t set_kernel_attributes(const StepDims& d);
 

@@ -1163,6 +1163,9 @@ __global__ __launch_bounds__(QR_THREADS) void qr_kernel(StepDims d, double2* __r
           rinv[k] = ik;
           lnr += log(rk);
         }
+        // row k is read by other lanes below: keep the compiler from moving
+        // LDS accesses across (the wave's LDS operations run in order)
+        __builtin_amdgcn_wave_barrier();
         const int m = n - 1 - k;  // trailing size: the m x m square, lanes below the diagonal idle
         for (int e = lane; e < m * m; e += 64) {
           const int a = e / m, b = e - a * m;
@@ -1170,6 +1173,7 @@ __global__ __launch_bounds__(QR_THREADS) void qr_kernel(StepDims d, double2* __r
           const int ii = k + 1 + a, jj = k + 1 + b;
           R[ii * n + jj] = csub(R[ii * n + jj], cmul(cconj(R[k * n + ii]), R[k * n + jj]));
         }
+        __builtin_amdgcn_wave_barrier();  // the next pivot reads the updated block
       }
     }
     __syncthreads();
@@ -1214,13 +1218,20 @@ hipError_t launch_qr(const StepDims& d, int W, double2* phi_a, double2* phi_b, d
   return hipGetLastError();
 }
 
-__global__ void ortho_update_kernel(int W, const double* __restrict__ corr, double2* __restrict__ log_ovlp) {
+// log overlap -= sum ln R_ii; a rank-deficient walker (corr = -inf from the
+// QR) is discarded: log overlap +inf, weight 0 (log w = -inf), as the step's
+// weight update does for it
+__global__ void ortho_update_kernel(int W, const double* __restrict__ corr, double2* __restrict__ log_ovlp,
+                                    double* __restrict__ log_w) {
   const int z = blockIdx.x * blockDim.x + threadIdx.x;
-  if (z < W) log_ovlp[z].x -= corr[2 * z] + corr[2 * z + 1];
+  if (z >= W) return;
+  const double c = corr[2 * z] + corr[2 * z + 1];
+  log_ovlp[z].x -= c;
+  if (!isfinite(c)) log_w[z] = -INFINITY;
 }
 
-hipError_t launch_ortho_update(int W, const double* corr, double2* log_ovlp, hipStream_t s) {
-  hipLaunchKernelGGL(ortho_update_kernel, dim3(ceil_div(W, 256)), dim3(256), 0, s, W, corr, log_ovlp);
+hipError_t launch_ortho_update(int W, const double* corr, double2* log_ovlp, double* log_w, hipStream_t s) {
+  hipLaunchKernelGGL(ortho_update_kernel, dim3(ceil_div(W, 256)), dim3(256), 0, s, W, corr, log_ovlp, log_w);
   return hipGetLastError();
 }
 

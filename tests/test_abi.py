@@ -43,10 +43,11 @@ def test_version_and_error_string(lib):
 
 def test_param_struct_layout_matches_header():
     # int N, na, nb, K; double dt; int taylor_order, precision, max_walkers; double mu, e_shift;
-    # int exchange
+    # int exchange, flags
     assert ctypes.sizeof(afqmc._Params) == 64
     assert afqmc._Params.mu.offset == 40
     assert afqmc._Params.exchange.offset == 56
+    assert afqmc._Params.flags.offset == 60
     assert ctypes.sizeof(afqmc._Walkers) == 32
 
 
@@ -69,6 +70,10 @@ def test_init_rejects_bad_arguments_without_touching_the_device(lib):
     rc = afqmc._lib.afqmc_init_hamiltonian(ctypes.byref(p), z.ctypes.data, z.ctypes.data,
                                            z.ctypes.data, z.ctypes.data, None, ctypes.byref(h))
     assert rc == 1
+    p = afqmc._Params(4, 2, 2, 1, 0.01, 6, 0, 1, float("nan"), float("nan"), 0, 6)
+    rc = afqmc._lib.afqmc_init_hamiltonian(ctypes.byref(p), z.ctypes.data, z.ctypes.data,
+                                           z.ctypes.data, z.ctypes.data, None, ctypes.byref(h))
+    assert rc == 1 and b"flags" in afqmc._lib.afqmc_last_error()
     assert not h.value
 
 

@@ -181,6 +181,13 @@ def test_block_matches_oracle(precision):
     x = inputs.fields(W, cfg.K, nsteps, seed=4)
     u = 0.3141
     ra, rb, rlo, rlw, re, rE, rpar = orc.block(oh, pa, pb, lo, lw, x, u)
+    # the GPU's own pre-comb log weights: the same block without the comb (u < 0)
+    # from the same start; the block is deterministic, so these are the weights
+    # the comb below acts on
+    w0 = afqmc.Walkers.from_numpy(pa, pb, lo, lw, device="cuda")
+    print(f"[gpu] block {precision} (no comb)", flush=True)
+    ham.block(w0, torch.as_tensor(x, device="cuda"), -1.0)
+    lw_gpu = w0.log_w.cpu().numpy()
     w = afqmc.Walkers.from_numpy(pa, pb, lo, lw, device="cuda")
     print(f"[gpu] block {precision}", flush=True)
     e, out, parent = ham.block(w, torch.as_tensor(x, device="cuda"), u)
@@ -202,7 +209,12 @@ def test_block_matches_oracle(precision):
         ga = w.phi_a.cpu().numpy()
         assert np.abs(ga - ra).max() <= tol_phi * np.abs(ra).max()
         assert np.abs(w.log_w.cpu().numpy() - rlw).max() <= (1e-10 if precision == "fp64" else 1e-3)
-    else:
-        # valid comb of the GPU's own weights
-        assert np.bincount(parent, minlength=W).sum() == W
+    # whatever the gap to the oracle's weights, the GPU's parent map is the
+    # comb (R17) of the GPU's own pre-comb weights, decided in FP64 on both
+    # sides: exact unless a tooth lies within rounding of a boundary of those
+    # weights
+    assert _min_gap(lw_gpu, u) > 1e-12
+    gref, glw = orc.comb(lw_gpu, u)
+    assert np.array_equal(parent, gref)
+    assert np.all(np.abs(w.log_w.cpu().numpy() - glw) <= 1e-13 * max(1.0, abs(glw)))
     ham.close()

@@ -206,6 +206,26 @@ def test_orthogonalise_matches_oracle(name, precision, uhf):
     assert np.abs(w.log_ovlp.cpu().numpy() - lo).max() < 1e-11
 
 
+def test_orthogonalise_discards_a_rank_deficient_walker():
+    """A walker with a vanished orbital: QR_ZERO is set, the walker keeps its
+    orbitals and gets weight 0 (log w = -inf); the others are orthogonalised."""
+    c = case("ragged", "fp64")
+    pa = c.pa.copy()
+    pa[5, :, 3] = 0.0
+    w = c.walkers(pa=pa)
+    c.ham.status()                        # clear
+    c.ham.orthogonalise(w)
+    assert c.ham.status() & 4             # AFQMC_STATUS_QR_ZERO
+    lw = w.log_w.cpu().numpy()
+    assert lw[5] == -np.inf
+    others = np.array([z for z in range(c.cfg.W) if z != 5])
+    assert np.array_equal(lw[others], c.lw[others])
+    assert np.array_equal(w.phi_a.cpu().numpy()[5], pa[5])
+    assert w.log_ovlp.cpu().numpy()[5].real == np.inf
+    qa, qb, lo = orc.orthogonalise(pa[others], c.pb[others], c.lo[others])
+    assert np.abs(w.phi_a.cpu().numpy()[others] - qa).max() < 1e-12
+
+
 @pytest.mark.parametrize("exchange", EXCHANGES)
 @pytest.mark.parametrize("name,precision,uhf", PARAMS + SPLIT_PARAMS)
 def test_fused_step_matches_oracle(name, precision, uhf, exchange):
@@ -392,20 +412,165 @@ def _n290_reference():
         sample = np.array([0, 255, 511])
         lo = orc.overlap(oh, pa[sample], pb[sample])
         ref = orc.step(oh, pa[sample], pb[sample], lo, np.zeros(len(sample)), x[sample], do_qr=True)
-        _N290.update(cfg=cfg, h1=h1, L=L, phiT=phiT, pa=pa, pb=pb, x=x, sample=sample, ref=ref)
+        _N290.update(cfg=cfg, h1=h1, L=L, phiT=phiT, pa=pa, pb=pb, x=x, sample=sample, ref=ref, oh=oh)
     return _N290
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16x3", "bf16x3"])
-def test_fused_step_at_n290_sampled(precision):
+# walkers of the n290 batch checked one by one in the per-call tests
+N290_CALL_SAMPLE = np.array([0, 97, 255, 388, 511])
+
+
+def _n290_call_reference():
+    """Oracle outputs of the single calls (force bias, local energy, propagate)
+    for the sampled walkers of the n290 batch."""
+    r = _n290_reference()
+    if "calls" not in r:
+        s = N290_CALL_SAMPLE
+        oh, pa, pb = r["oh"], r["pa"][s], r["pb"][s]
+        lo = orc.overlap(oh, pa, pb)
+        lw = np.linspace(-0.3, 0.2, len(s))
+        r["calls"] = dict(vbias=orc.force_bias(oh, pa, pb), e=orc.local_energy(oh, pa, pb),
+                          prop=orc.propagate(oh, pa, pb, lo, lw, r["x"][s]), lw=lw)
+    return r
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
+def test_single_calls_at_n290_sampled(precision):
+    """force_bias, local_energy and propagate of all 512 walkers of n290 in one
+    call each (the bench's launch configuration), the sampled walkers against
+    the oracle, at the per-call bars: 4 u sqrt(2 n N) S for the energy and
+    4 u sqrt(2 n N) max|vbias_z| for the force bias (FP32 and FP16X3, whose
+    hi + lo operands carry 22 bits), 1e-4 S in BF16X3 (16-bit exchange
+    operands); orbitals 1e-4 max|phi'_z|, log overlap and log weight 1e-5
+    relative to their size (at least 1)."""
+    torch = _torch()
+    from paper_2209_04015_amd import afqmc
+
+    r = _n290_call_reference()
+    cfg, s, ref = r["cfg"], N290_CALL_SAMPLE, r["calls"]
+    print(f"[gpu] n290 single calls {precision}", flush=True)
+    ham = afqmc.Hamiltonian(r["h1"], r["L"], r["phiT"], r["phiT"], dt=cfg.dt, max_walkers=cfg.W,
+                            precision=precision, taylor_order=cfg.taylor_order)
+    w = afqmc.Walkers.from_numpy(r["pa"], r["pb"], device="cuda")
+    tol = _energy_tol(precision, cfg)
+    vb = ham.force_bias(w).cpu().numpy()[s]
+    vscale = np.abs(ref["vbias"]).max(axis=1)
+    verr = np.abs(vb - ref["vbias"]).max(axis=1) / vscale
+    e = ham.local_energy(w).cpu().numpy()[s]
+    er = ref["e"]
+    S = np.abs(er).sum(axis=1)
+    eabs = np.abs(e.sum(axis=1) - er.sum(axis=1))
+    print(f"[gpu] n290 {precision}: force bias max rel {verr.max():.2e}; energy max |dE| "
+          f"{eabs.max():.3e} Ha = {(eabs / S).max():.2e} S (S up to {S.max():.3e} Ha; bar {tol:.2e} S)",
+          flush=True)
+    assert np.all(verr <= tol)
+    assert np.all(eabs <= tol * S)
+    for k in range(3):
+        assert np.all(np.abs(e[:, k] - er[:, k]) <= tol * S)
+    # propagate: the walkers' own log overlap (FP64 on the device), the
+    # oracle's log weights of the sample
+    lw = np.zeros(cfg.W)
+    lw[s] = ref["lw"]
+    w = afqmc.Walkers.from_numpy(r["pa"], r["pb"], lw=lw, device="cuda")
+    ham.overlap(w)
+    ham.propagate(w, torch.as_tensor(r["x"], device="cuda"))
+    na, nb, lo, lwr = ref["prop"]
+    perr = 0.0
+    for g, rr in ((w.phi_a.cpu().numpy()[s], na), (w.phi_b.cpu().numpy()[s], nb)):
+        sc = np.abs(rr).reshape(len(s), -1).max(axis=1)
+        perr = max(perr, (np.abs(g - rr).reshape(len(s), -1).max(axis=1) / sc).max())
+    glw = w.log_w.cpu().numpy()[s]
+    glo = w.log_ovlp.cpu().numpy()[s]
+    alive = np.isfinite(lwr)
+    assert np.array_equal(alive, np.isfinite(glw))
+    lerr = np.abs(glw[alive] - lwr[alive]) / np.maximum(1.0, np.abs(lwr[alive]))
+    oerr = np.abs(glo.real - lo.real) / np.maximum(1.0, np.abs(lo.real))
+    print(f"[gpu] n290 {precision} propagate: phi {perr:.2e}, log w {lerr.max(initial=0):.2e}, "
+          f"log ovlp {oerr.max():.2e} ({int(alive.sum())} of {len(s)} kept)", flush=True)
+    assert perr <= 1e-4
+    assert np.all(lerr <= 1e-5) and np.all(oerr <= 1e-5)
+    assert ham.status() == 0
+    ham.close()
+    del w
+    torch.cuda.empty_cache()
+
+
+# The FP64 baseline and mixed-precision workloads at their own sizes (n100:
+# N = 100, n = 20, K = 400, 640 walkers, QR every 5 steps; n200: N = 200,
+# n = 32, K = 1000, 1000 walkers, QR every step): one fused step of every
+# walker in one call, sampled walkers against the oracle's step.
+CFG_SAMPLE = {"n100": np.array([0, 213, 427, 639]), "n200": np.array([0, 333, 666, 999])}
+
+
+@pytest.mark.parametrize("name", ["n100", "n200"])
+@pytest.mark.parametrize("precision", ["fp64", "fp16x3"])
+def test_fused_step_at_config_size_sampled(name, precision):
+    torch = _torch()
+    from paper_2209_04015_amd import afqmc
+
+    cfg = inputs.CONFIGS[name]
+    s = CFG_SAMPLE[name]
+    h1, L = inputs.hamiltonian(cfg.N, cfg.K, cfg.decay, seed=0)
+    phiT = inputs.trial(h1, cfg.n)
+    pa = inputs.walkers_perturbed(phiT, cfg.W, 0.05, seed=4, stream=0)
+    pb = inputs.walkers_perturbed(phiT, cfg.W, 0.05, seed=4, stream=1)
+    x = inputs.fields(cfg.W, cfg.K, 1, seed=2)[0]
+    do_qr = cfg.qr_interval == 1
+    oh = orc.setup(h1, L, phiT, phiT, dt=cfg.dt, taylor_order=cfg.taylor_order)
+    lo = orc.overlap(oh, pa[s], pb[s])
+    ra, rb, rlo, rlw, er = orc.step(oh, pa[s], pb[s], lo, np.zeros(len(s)), x[s], do_qr=do_qr)
+    print(f"[gpu] {name} fused step {precision} (W = {cfg.W}, QR {do_qr})", flush=True)
+    ham = afqmc.Hamiltonian(h1, L, phiT, phiT, dt=cfg.dt, max_walkers=cfg.W, precision=precision,
+                            taylor_order=cfg.taylor_order)
+    w = afqmc.Walkers.from_numpy(pa, pb, device="cuda")
+    ham.overlap(w)
+    e = torch.empty((cfg.W, 3), dtype=torch.complex128, device="cuda")
+    ham.step(w, torch.as_tensor(x, device="cuda"), do_qr=do_qr, energy_out=e)
+    torch.cuda.synchronize()
+    assert ham.status() == 0
+    got = e.cpu().numpy()[s]
+    S = np.abs(er).sum(axis=1)
+    eabs = np.abs(got.sum(axis=1) - er.sum(axis=1))
+    perr = 0.0
+    for g, rr in ((w.phi_a.cpu().numpy()[s], ra), (w.phi_b.cpu().numpy()[s], rb)):
+        sc = np.abs(rr).reshape(len(s), -1).max(axis=1)
+        perr = max(perr, (np.abs(g - rr).reshape(len(s), -1).max(axis=1) / sc).max())
+    glw, glo = w.log_w.cpu().numpy()[s], w.log_ovlp.cpu().numpy()[s]
+    alive = np.isfinite(rlw)
+    assert np.array_equal(alive, np.isfinite(glw))
+    lerr = np.abs(glw[alive] - rlw[alive]) / np.maximum(1.0, np.abs(rlw[alive]))
+    oerr = np.abs(glo.real - rlo.real) / np.maximum(1.0, np.abs(rlo.real))
+    print(f"[gpu] {name} {precision}: |dE| {eabs.max():.3e} Ha = {(eabs / S).max():.2e} S "
+          f"(S up to {S.max():.3e} Ha), phi {perr:.2e}, log w {lerr.max(initial=0):.2e}, "
+          f"log ovlp {oerr.max():.2e} ({int(alive.sum())} of {len(s)} kept)", flush=True)
+    tol_e = 1e-11 if precision == "fp64" else 1e-4
+    tol_phi = 1e-10 if precision == "fp64" else 1e-4
+    tol_log = 1e-12 if precision == "fp64" else 1e-5
+    assert np.all(eabs <= tol_e * S)
+    assert perr <= tol_phi
+    assert np.all(lerr <= tol_log) and np.all(oerr <= tol_log)
+    ham.close()
+    del w, e
+    torch.cuda.empty_cache()
+
+
+N290_FUSED = [("fp64", False), ("fp32", False), ("fp16x3", False), ("bf16x3", False),
+              ("fp32", True), ("fp16x3", True)]
+
+
+@pytest.mark.parametrize("precision,one_body_fp64", N290_FUSED)
+def test_fused_step_at_n290_sampled(precision, one_body_fp64):
+    """One fused step of the 512 n290 walkers; the mixed paths also with the
+    one-body half steps on the FP64 matrix cores (AFQMC_FLAG_ONE_BODY_FP64),
+    which measures what the FP32 one-body products cost."""
     torch = _torch()
     from paper_2209_04015_amd import afqmc
 
     r = _n290_reference()
     cfg = r["cfg"]
-    print(f"[gpu] n290 fused step {precision}", flush=True)
+    print(f"[gpu] n290 fused step {precision} one_body_fp64={one_body_fp64}", flush=True)
     ham = afqmc.Hamiltonian(r["h1"], r["L"], r["phiT"], r["phiT"], dt=cfg.dt, max_walkers=cfg.W,
-                            precision=precision, taylor_order=cfg.taylor_order)
+                            precision=precision, taylor_order=cfg.taylor_order, one_body_fp64=one_body_fp64)
     w = afqmc.Walkers.from_numpy(r["pa"], r["pb"], device="cuda")   # log w = 0
     ham.overlap(w)                       # the walkers' own log overlap (the oracle computes its own)
     e = torch.empty((cfg.W, 3), dtype=torch.complex128, device="cuda")
@@ -429,7 +594,7 @@ def test_fused_step_at_n290_sampled(precision):
     assert np.array_equal(alive, np.isfinite(glw))
     lerr = np.abs(glw[alive] - lw[alive]) / np.maximum(1.0, np.abs(lw[alive]))
     oerr = np.abs(glo.real - lo.real) / np.maximum(1.0, np.abs(lo.real))
-    print(f"[gpu] n290 {precision}: |dE|/S {derr.max():.2e}, phi {perr.max():.2e}, "
+    print(f"[gpu] n290 {precision} one_body_fp64={one_body_fp64}: |dE|/S {derr.max():.2e}, phi {perr.max():.2e}, "
           f"log w {lerr.max(initial=0):.2e}, log ovlp {oerr.max():.2e} ({int(alive.sum())} of 3 kept)", flush=True)
     assert np.all(derr <= tol_e)
     assert np.all(lerr <= tol_log) and np.all(oerr <= tol_log)
