@@ -76,6 +76,12 @@ Readings where the paper is silent:
       G^s = sum_a c_a O_a G^s_a / sum_a c_a O_a, O_a = <D_a|phi> and G^s_a
       the single-determinant Green's function of D_a^s (R11).  The force bias
       of an MSD trial is Eq. (fb) with this G.
+* R25 Local energy of a multi-determinant trial (Sec. III.C with the
+      expansion of R23): E_L = <Psi_T|H|phi>/<Psi_T|phi>
+      = sum_a c_a O_a E_L^a / sum_a c_a O_a, O_a = <D_a|phi> and E_L^a the
+      single-determinant local energy of phi with trial D_a (R10).  Each part
+      (E1, EJ, EK) is reported with the same weights; E1 so equals
+      sum_s tr(h G^s) with the Green's function of R24.
 * R19 Block (Sec. IV.A and IV.C): nsteps propagation steps, the last one
       followed by re-orthogonalisation and the local energy, then the global
       energy of the block, then the comb.
@@ -119,6 +125,7 @@ __all__ = [
     "msd_green",
     "msd_force_bias",
     "msd_propagate",
+    "msd_local_energy",
 ]
 
 
@@ -555,3 +562,39 @@ def msd_propagate(ham, msd, phi_a, phi_b, log_ovlp, log_w, x):
     """
     return _propagate(ham, lambda a, b: msd_force_bias(msd, ham.L, a, b), lambda a, b: msd_overlap(msd, a, b),
                       phi_a, phi_b, log_ovlp, log_w, x)
+
+
+def _sd_local_energy(h1, L, D_a, D_b, phi_a, phi_b):
+    """Single-determinant local energy parts [W, 3] of phi with trial orbitals
+    (D_a, D_b) (Sec. III.C, R10): the half-rotated vectors D^T L_g and
+    D^T h1 of this trial, then the same sums as local_energy."""
+    Lh_a = np.matmul(D_a.T[None, :, :], L)
+    Lh_b = np.matmul(D_b.T[None, :, :], L)
+    ta, _ = theta_and_logdet(D_a, phi_a)
+    tb, _ = theta_and_logdet(D_b, phi_b)
+    W = phi_a.shape[0]
+    out = np.zeros((W, 3), dtype=np.complex128)
+    for z in range(W):
+        e1a, tra, eka = _energy_spin(Lh_a, D_a.T @ h1, ta[z])
+        if D_b.shape[1]:
+            e1b, trb, ekb = _energy_spin(Lh_b, D_b.T @ h1, tb[z])
+        else:
+            e1b, trb, ekb = 0.0, 0.0, 0.0
+        out[z, 0] = e1a + e1b
+        out[z, 1] = 0.5 * np.sum((tra + trb) ** 2)
+        out[z, 2] = eka + ekb
+    return out
+
+
+def msd_local_energy(msd, h1, L, phi_a, phi_b):
+    """E_L split [W, 3] complex (E1, EJ, EK) for the multi-determinant trial
+    (R25): sum_a c_a O_a E_L^a / sum_a c_a O_a, one determinant at a time."""
+    logs = _msd_log_terms(msd, phi_a, phi_b)
+    m = np.max(logs.real, axis=0)
+    w = np.exp(logs - m)                      # c_a O_a / e^m, [ndet, W]
+    out = np.zeros((phi_a.shape[0], 3), dtype=np.complex128)
+    for a, spins in enumerate(msd.exc):
+        D_a = msd_determinant(msd.C[0], msd.nel[0], *spins[0])
+        D_b = msd_determinant(msd.C[1], msd.nel[1], *spins[1])
+        out += w[a][:, None] * _sd_local_energy(h1, L, D_a, D_b, phi_a, phi_b)
+    return out / np.sum(w, axis=0)[:, None]

@@ -272,3 +272,66 @@ def test_msd_propagate_overlap_bookkeeping():
     expect = lw + d.real - ham.dt * (ham.mu * (na + nb) - ham.e_shift) + np.log(np.where(cos_t > 0, cos_t, np.nan))
     ok = cos_t > 0
     assert np.allclose(lw2[ok], expect[ok], atol=1e-12) and np.all(lw2[~ok] == -np.inf)
+
+
+# ---------------------------------------------------------------------------
+# Local energy of the multi-determinant trial (Sec. III.C with R23; R25)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("na,nb,ndet,seed", [(2, 1, 9, 21), (2, 2, 12, 22), (1, 2, 6, 23)])
+def test_msd_local_energy_matches_fock_space(na, nb, ndet, seed):
+    """<Psi_T|H|phi> / <Psi_T|phi> with H of Eq. Habinitio written literally in
+    Fock space and the trial built from the excitation operators."""
+    N, K = 4, 3
+    h1, L, C_a, C_b = _orbitals(N, K=K, seed=seed)
+    coeff, rank, orbs = inputs.msd_expansion(N, na, nb, ndet, max_rank=2, seed=seed)
+    msd = orc.msd_setup(C_a, C_b, na, nb, coeff, rank, orbs)
+    pa = _walkers(C_a, na, 2, seed, 0)
+    pb = _walkers(C_b, nb, 2, seed, 1)
+    fs = FockSpace(N)
+    psiT = _fock_trial(fs, msd)
+    e = orc.msd_local_energy(msd, h1, L, pa, pb)
+    for z in range(2):
+        v = fs.determinant(pa[z], pb[z])
+        ref = np.vdot(psiT, fs.hamiltonian(h1, L, v)) / np.vdot(psiT, v)
+        assert e[z].sum() == pytest.approx(ref, rel=1e-11, abs=1e-11)
+        # the one-body part alone: the same Fock-space ratio with h1 only
+        ref1 = np.vdot(psiT, fs.one_body(h1, v)) / np.vdot(psiT, v)
+        assert e[z, 0] == pytest.approx(ref1, rel=1e-11, abs=1e-11)
+
+
+def test_msd_local_energy_single_reference_is_the_single_determinant_energy():
+    N, na, nb, K = 9, 3, 2, 5
+    h1, L, C_a, C_b = _orbitals(N, K=K, seed=24)
+    msd = orc.OracleMSD((C_a, C_b), (na, nb), np.array([-1.3]), [(((), ()), ((), ()))])
+    ham = orc.setup(h1, L, C_a[:, :na], C_b[:, :nb], dt=0.01)
+    pa = _walkers(C_a, na, 3, 24, 0)
+    pb = _walkers(C_b, nb, 3, 24, 1)
+    assert np.allclose(orc.msd_local_energy(msd, h1, L, pa, pb), orc.local_energy(ham, pa, pb),
+                       rtol=1e-12, atol=1e-12)
+
+
+def test_msd_local_energy_complete_expansion_is_the_determinant_energy():
+    """The complete expansion of one determinant psi (c = det(D^T psi), Cauchy-Binet)
+    has the local energy of psi itself as a single-determinant trial."""
+    N, na, nb, K = 6, 3, 2, 4
+    rng = np.random.default_rng(25)
+    h1, L, C_a, C_b = _orbitals(N, K=K, seed=25)
+    psi_a = rng.normal(size=(N, na))
+    psi_b = rng.normal(size=(N, nb))
+    ea = _complete_expansion(C_a, na, psi_a)
+    eb = _complete_expansion(C_b, nb, psi_b)
+    exc, coeff = [], []
+    for (ha, qa, ca), (hb, qb, cb) in itertools.product(ea, eb):
+        exc.append(((ha, qa), (hb, qb)))
+        coeff.append(ca * cb)
+    msd = orc.OracleMSD((C_a, C_b), (na, nb), np.array(coeff), exc)
+    pa = _walkers(C_a, na, 3, 25, 0)
+    pb = _walkers(C_b, nb, 3, 25, 1)
+    ham = orc.setup(h1, L, psi_a, psi_b, dt=0.01)
+    got = orc.msd_local_energy(msd, h1, L, pa, pb)
+    ref = orc.local_energy(ham, pa, pb)
+    # the total and the one-body part are trial-expansion invariants; the
+    # split of the two-body part between EJ and EK is per determinant
+    assert np.allclose(got.sum(axis=1), ref.sum(axis=1), rtol=1e-10, atol=1e-10)
+    assert np.allclose(got[:, 0], ref[:, 0], rtol=1e-10, atol=1e-10)
