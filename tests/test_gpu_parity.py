@@ -471,7 +471,7 @@ def test_single_calls_at_n290_sampled(precision):
     # oracle's log weights of the sample
     lw = np.zeros(cfg.W)
     lw[s] = ref["lw"]
-    w = afqmc.Walkers.from_numpy(r["pa"], r["pb"], lw=lw, device="cuda")
+    w = afqmc.Walkers.from_numpy(r["pa"], r["pb"], None, lw, device="cuda")
     ham.overlap(w)
     ham.propagate(w, torch.as_tensor(r["x"], device="cuda"))
     na, nb, lo, lwr = ref["prop"]
