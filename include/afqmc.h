@@ -216,6 +216,26 @@ int afqmc_global_energy(afqmc_ham* ham, const afqmc_walkers* w, int nw, const vo
 int afqmc_population_control(afqmc_ham* ham, afqmc_walkers* w, int nw, double u, int* parent,
                              void* stream);
 
+/* The comb of afqmc_population_control without a Hamiltonian handle and
+ * without any allocation, for callers that cannot allocate device memory
+ * (code under graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same selection, copies, weights and parent map as
+ * afqmc_population_control, bit for bit.  Its scratch (cumulative weights,
+ * tooth counts, copy sources, 1.25 MB) is a static device array that each
+ * GPU holds until the process ends; every call on a GPU shares that GPU's
+ * copy, so calls that overlap on one GPU (other streams, other threads)
+ * race: serialise them.  Nothing in the scratch is read before the call
+ * writes it.
+ *   N, na, nb  orbitals and electrons per spin of the walkers
+ *   nw         0 <= nw <= 65536 (the scratch's size; larger: AFQMC_EINVAL)
+ *   u          comb offset, 0 <= u < 1
+ *   parent     device int [nw], written (may be NULL)
+ *   status     device int, AFQMC_STATUS_NO_LIVE or-ed in when no walker has a
+ *              finite weight (may be NULL)
+ * The walkers are on the current device; the call runs on `stream`. */
+int afqmc_population_control_noalloc(int N, int na, int nb, afqmc_walkers* w, int nw, double u, int* parent,
+                                     int* status, void* stream);
+
 /* One block (Sec. IV.A and IV.C: a number of propagation steps, then one
  * energy evaluation and one re-orthogonalisation):
  *   nsteps afqmc_step calls, re-orthogonalisation and the local energy on

@@ -16,7 +16,7 @@ from typing import Optional
 import numpy as np
 
 __all__ = ["FP64", "FP32", "BF16X3", "FP16X3", "AfqmcError", "load", "Hamiltonian", "Walkers", "Batch", "MSDTrial",
-           "LIB_PATH"]
+           "population_control_noalloc", "LIB_PATH"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libafqmc.so")
 
@@ -44,6 +44,7 @@ EXPORTED = (
     "afqmc_step",
     "afqmc_global_energy",
     "afqmc_population_control",
+    "afqmc_population_control_noalloc",
     "afqmc_block",
     "afqmc_green_function",
     "afqmc_s2_mixed",
@@ -134,6 +135,7 @@ def load(path: str = LIB_PATH):
     lib.afqmc_step.argtypes = [vp, P(_Walkers), ip, vp, ip, vp, ip, vp]
     lib.afqmc_global_energy.argtypes = [vp, P(_Walkers), ip, vp, vp, vp]
     lib.afqmc_population_control.argtypes = [vp, P(_Walkers), ip, ctypes.c_double, vp, vp]
+    lib.afqmc_population_control_noalloc.argtypes = [ip, ip, ip, P(_Walkers), ip, ctypes.c_double, vp, vp, vp]
     lib.afqmc_block.argtypes = [vp, P(_Walkers), ip, vp, ip, ctypes.c_double, vp, vp, vp, ip, vp]
     lib.afqmc_green_function.argtypes = [vp, P(_Walkers), ip, vp, vp]
     lib.afqmc_s2_mixed.argtypes = [vp, P(_Walkers), ip, vp, vp]
@@ -246,6 +248,31 @@ class Walkers:
         if nw > self.W:
             raise ValueError(f"nw = {nw} exceeds the {self.W} walkers held")
         return s
+
+
+class _WalkerShape:
+    def __init__(self, w):
+        _, self.N, self.na = w.phi_a.shape
+        self.nb = w.phi_b.shape[2]
+
+
+def population_control_noalloc(w: Walkers, u: float, parent=None, status=None, nw=None, stream=None):
+    """afqmc_population_control_noalloc: the comb on the library's static
+    scratch, without a Hamiltonian handle (sizes from the walker arrays).
+    parent (device int32 [nw]) and status (device int32 [1]) are optional
+    outputs; returns parent."""
+    import torch
+
+    load()
+    nw = w.W if nw is None else int(nw)
+    shape = _WalkerShape(w)
+    pptr = _dev(parent, torch.int32, (nw,), "parent") if parent is not None else None
+    sptr = _dev(status, torch.int32, (1,), "status") if status is not None else None
+    s = w._struct(shape, nw)
+    with torch.cuda.device(w.phi_a.device):
+        _check(_lib.afqmc_population_control_noalloc(shape.N, shape.na, shape.nb, ctypes.byref(s), nw, float(u),
+                                                     pptr, sptr, _stream_ptr(stream)))
+    return parent
 
 
 class Hamiltonian:

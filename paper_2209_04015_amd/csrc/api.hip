@@ -935,6 +935,27 @@ int afqmc_population_control(afqmc_ham* h, afqmc_walkers* w, int nw, double u, i
   return seq_comb(h, w, nw, u, parent, (hipStream_t)stream);
 }
 
+int afqmc_population_control_noalloc(int N, int na, int nb, afqmc_walkers* w, int nw, double u, int* parent,
+                                     int* status, void* stream) {
+  if (N < 1 || na < 0 || nb < 0 || na > N || nb > N)
+    return fail(AFQMC_EINVAL, "bad sizes N = %d, na = %d, nb = %d", N, na, nb);
+  if (nw < 0 || nw > COMB_STATIC_MAX_WALKERS)
+    return fail(AFQMC_EINVAL, "nw = %d outside [0, %d] (the static scratch's limit)", nw, COMB_STATIC_MAX_WALKERS);
+  if (nw == 0) return AFQMC_OK;
+  if (!w || (na > 0 && !w->phi_a) || (nb > 0 && !w->phi_b) || !w->log_ovlp || !w->log_w)
+    return fail(AFQMC_EINVAL, "null walker array");
+  if (!(u >= 0.0 && u < 1.0)) return fail(AFQMC_EINVAL, "comb offset u = %g outside [0, 1)", u);
+  void* sp = nullptr;
+  HIP_TRY(comb_static_scratch(&sp));
+  StepDims d{};
+  d.N = N;
+  d.na = na;
+  d.nb = nb;
+  HIP_TRY(launch_comb_static(sp, d, nw, u, (double2*)w->phi_a, (double2*)w->phi_b, (double2*)w->log_ovlp, w->log_w,
+                             parent, status, (hipStream_t)stream));
+  return AFQMC_OK;
+}
+
 int afqmc_block(afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields, int nsteps, double u, void* e,
                 double* out, int* parent, int flags, void* stream) {
   int rc = check_walkers(h, w, nw);

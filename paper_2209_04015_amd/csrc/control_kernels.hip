@@ -7,6 +7,9 @@
 // Weights: w_z = exp(log_w_z - m) with m the largest finite log weight; a
 // non-finite log weight (-inf for a discarded walker, NaN) counts as 0.
 
+#include <mutex>
+#include <vector>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -228,4 +231,58 @@ hipError_t launch_comb(const StepDims& d, int nw, double u, double2* phi_a, doub
   hipLaunchKernelGGL(comb_copy_kernel, dim3(nw, ychunks), dim3(256), 0, s, parent, ea, eb,
                      phi_a, phi_b, log_ovlp);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch of the allocation-free comb: csum double [MAX], cnt, src
+// and parent int [MAX], one status int.  Every GPU the library runs on holds
+// its own copy until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t COMB_CSUM_OFF = 0;
+constexpr size_t COMB_CNT_OFF = COMB_CSUM_OFF + sizeof(double) * COMB_STATIC_MAX_WALKERS;
+constexpr size_t COMB_SRC_OFF = COMB_CNT_OFF + sizeof(int) * COMB_STATIC_MAX_WALKERS;
+constexpr size_t COMB_PARENT_OFF = COMB_SRC_OFF + sizeof(int) * COMB_STATIC_MAX_WALKERS;
+constexpr size_t COMB_STATUS_OFF = COMB_PARENT_OFF + sizeof(int) * COMB_STATIC_MAX_WALKERS;
+constexpr size_t COMB_SCRATCH_BYTES = COMB_STATUS_OFF + 256;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[COMB_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // per device ordinal; null until looked up
+
+}  // namespace
+
+hipError_t comb_static_scratch(void** ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_comb_static(void* scratch_ptr, const StepDims& d, int nw, double u, double2* phi_a,
+                              double2* phi_b, double2* log_ovlp, double* log_w, int* parent, int* status,
+                              hipStream_t s) {
+  if (nw <= 0) return hipSuccess;
+  if (nw > COMB_STATIC_MAX_WALKERS || !scratch_ptr) return hipErrorInvalidValue;
+  unsigned char* base = static_cast<unsigned char*>(scratch_ptr);
+  return launch_comb(d, nw, u, phi_a, phi_b, log_ovlp, log_w, reinterpret_cast<double*>(base + COMB_CSUM_OFF),
+                     reinterpret_cast<int*>(base + COMB_CNT_OFF), reinterpret_cast<int*>(base + COMB_SRC_OFF),
+                     parent ? parent : reinterpret_cast<int*>(base + COMB_PARENT_OFF),
+                     status ? status : reinterpret_cast<int*>(base + COMB_STATUS_OFF), s);
 }

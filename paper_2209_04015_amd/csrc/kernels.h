@@ -141,6 +141,14 @@ hipError_t launch_global_energy(int nw, const double* log_w, const double2* e, d
 // comb population control in place; parent[nw] out; csum/cnt/src: [nw] scratch
 hipError_t launch_comb(const StepDims& d, int nw, double u, double2* phi_a, double2* phi_b, double2* log_ovlp,
                        double* log_w, double* csum, int* cnt, int* src, int* parent, int* status, hipStream_t s);
+// The comb on the library's static scratch (no allocation): walkers up to
+// COMB_STATIC_MAX_WALKERS.  comb_static_scratch gives the scratch's address on
+// the current device (looked up once per device).
+constexpr int COMB_STATIC_MAX_WALKERS = 65536;
+hipError_t comb_static_scratch(void** ptr);
+hipError_t launch_comb_static(void* scratch_ptr, const StepDims& d, int nw, double u, double2* phi_a,
+                              double2* phi_b, double2* log_ovlp, double* log_w, int* parent, int* status,
+                              hipStream_t s);
 
 // --- mixed estimators (estimator_kernels.hip) ---------------------------------
 // G [W][2][N][N] complex: G_pq = sum_i PhiT[p][i] theta[q][i] per spin

@@ -116,3 +116,15 @@ def test_msd_calls_reject_a_null_handle(lib):
     assert afqmc._lib.afqmc_msd_force_bias(None, None, ctypes.byref(w), 1, ctypes.c_void_p(1), None) == 1
     assert afqmc._lib.afqmc_msd_propagate(None, None, ctypes.byref(w), 1, ctypes.c_void_p(1), None) == 1
     afqmc._lib.afqmc_msd_destroy(None)              # no-op
+
+
+def test_noalloc_comb_rejects_bad_arguments_without_touching_the_device(lib):
+    afqmc.load()
+    w = afqmc._Walkers()
+    f = afqmc._lib.afqmc_population_control_noalloc
+    assert f(0, 1, 1, ctypes.byref(w), 4, 0.5, None, None, None) == 1
+    assert f(4, 5, 1, ctypes.byref(w), 4, 0.5, None, None, None) == 1
+    assert f(4, 2, 2, ctypes.byref(w), 65537, 0.5, None, None, None) == 1
+    assert b"65536" in afqmc._lib.afqmc_last_error()
+    assert f(4, 2, 2, ctypes.byref(w), 4, 0.5, None, None, None) == 1     # null walker arrays
+    assert f(4, 2, 2, ctypes.byref(w), 0, 0.5, None, None, None) == 0     # nothing to do
