@@ -5,9 +5,10 @@ bias, VHS, propagation (two one-body half steps around a 6-term Taylor
 series), overlap ratio and phaseless weight, QR re-orthogonalisation on the
 workload's schedule, and the local energy (E1, EJ, EK) of every walker.
 
-The headline is the FP16X3 path (16-bit hi/lo split force bias, VHS, Taylor
-and exchange contractions on the matrix cores, FP32 one-body half steps, FP64
-walkers, overlaps, solves, QR, weights and energy sums); the FP64, FP32 and
+The headline is the FP16X3 path (16-bit hi/lo split force bias, VHS and
+exchange contractions on the matrix cores, and the propagation P T6(VHS) P as
+one launch of split products per (walker, spin); FP64 walkers, overlaps,
+solves, QR, weights and energy sums); the FP64, FP32 and
 BF16X3 paths run on the same seeded inputs and are reported beside it.  The
 headline pass runs without events inside the step; a second pass of the same
 steps brackets every kernel phase with HIP events and gives the phase
@@ -367,6 +368,7 @@ KERNEL_SOURCES = {
     "exchange_pair_kernel": ["step_kernels.hip", "mfma_tile.h", "exchange_pair.h", "tile_order.h", "common.h"],
     "vhs_split_kernel": ["split_kernels.hip", "split_tile.h", "tile_order.h", "common.h"],
     "vhs_kernel": ["step_kernels.hip", "mfma_tile.h", "tile_order.h", "common.h"],
+    "prop_fused_kernel": ["prop_kernels.hip", "split_tile.h", "common.h"],
 }
 
 
@@ -433,6 +435,8 @@ def _kernel_of(phase, precision, algo):
     if phase == "exchange":
         base = ("exchange_pair" if algo == "pair" else "exchange") + ("_split_kernel" if split else "_kernel")
         return base, f"{base}<{H if split else T}>"
+    if phase == "propagate":
+        return "prop_fused_kernel", "prop_fused_kernel<4>"
     if phase == "vhs":
         if precision == "fp16x3":   # the VHS runs on split operands only in FP16X3
             return "vhs_split_kernel", "vhs_split_kernel<HalfF16>"
@@ -449,7 +453,7 @@ def _mfma_dtype(phase, precision):
         return "fp64"
     if phase == "exchange" and precision in ("fp16x3", "bf16x3"):
         return precision[:4]
-    if phase in ("vhs", "taylor", "force_bias") and precision == "fp16x3":
+    if phase in ("vhs", "taylor", "force_bias", "propagate") and precision == "fp16x3":
         return "fp16"
     return "fp32"
 
@@ -469,6 +473,9 @@ def phase_work(cfg, phase, precision, algo):
         return "mfma", W * cfg.taylor_order * 8.0 * N * N * n * 2, "flop"
     if phase == "one_body":
         return "mfma", 2 * W * 4.0 * N * N * ne, "flop"                   # two half steps
+    if phase == "propagate":   # one launch: both one-body half steps and the Taylor series
+        return ("mfma", phase_work(cfg, "one_body", precision, algo)[1]
+                + phase_work(cfg, "taylor", precision, algo)[1], "flop")
     if phase == "force_bias":
         return "mfma", W * 4.0 * K * N * ne, "flop"
     if phase == "green":
@@ -478,7 +485,7 @@ def phase_work(cfg, phase, precision, algo):
     return None, None, None
 
 
-ROOFLINE_PHASES = ("vhs", "exchange", "taylor", "one_body", "force_bias", "qr", "green")
+ROOFLINE_PHASES = ("vhs", "exchange", "propagate", "taylor", "one_body", "force_bias", "qr", "green")
 
 
 def roofline_of(cfg, phases, precision, algo, phase, steps):
@@ -790,7 +797,8 @@ def main():
                     "phases_ms_per_step": phase_table(ph), "status": st,
                     "energy_error_vs_fp64_oracle": (eerr or {}).get(p), **extras[p]}
     dtypes = {"fp32": "f32 (MFMA) contractions and one-body half steps",
-              "fp16x3": "f16 hi/lo x3 (MFMA) force bias, VHS, Taylor and exchange; f32 (MFMA) one-body half steps",
+              "fp16x3": "f16 hi/lo x3 (MFMA) force bias, VHS, exchange and the propagation P T6(VHS) P in one launch "
+                        "(Horner's rule, f32 sums)",
               "bf16x3": "bf16 hi/lo x3 (MFMA) exchange; f32 (MFMA) force bias, VHS, Taylor and one-body half steps"}
     line = {
         "metric": METRIC,

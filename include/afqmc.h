@@ -66,9 +66,17 @@ enum {
  *                 the Taylor products and the exchange split their FP32
  *                 operands into fp16 hi + lo with power-of-two scales and
  *                 keep the three leading products on the fp16 matrix cores
- *                 (relative operand error ~2^-22, close to FP32)
+ *                 (relative operand error ~2^-22, close to FP32).  The
+ *                 propagation P T(VHS) P phi (Eq. Bx) runs as one launch per
+ *                 step in which both one-body half steps are split fp16
+ *                 products too and the series is summed by Horner's rule
+ *                 (v = t0 + VHS v / k, k = order .. 1, t0 = P phi) in FP32
+ *                 (N <= 320 and na, nb <= 32; larger shapes, and
+ *                 AFQMC_FLAG_UNFUSED_PROPAGATION, take the term-by-term
+ *                 kernels with FP32 one-body half steps and an FP64 sum)
  * afqmc_params.flags & AFQMC_FLAG_ONE_BODY_FP64 keeps the one-body half steps
- * on the FP64 matrix cores in the FP32, BF16X3 and FP16X3 modes. */
+ * on the FP64 matrix cores in the FP32, BF16X3 and FP16X3 modes (FP16X3 then
+ * takes the term-by-term kernels). */
 enum { AFQMC_FP64 = 0, AFQMC_FP32 = 1, AFQMC_BF16X3 = 2, AFQMC_FP16X3 = 3 };
 
 /* Status-word bits (afqmc_get_status). */
@@ -92,7 +100,7 @@ typedef struct afqmc_params {
 } afqmc_params;
 
 /* afqmc_params.flags */
-enum { AFQMC_FLAG_ONE_BODY_FP64 = 1 };
+enum { AFQMC_FLAG_ONE_BODY_FP64 = 1, AFQMC_FLAG_UNFUSED_PROPAGATION = 2 };
 
 /* Algorithms of the exchange energy E_K = -1/2 sum_s sum_g sum_ij T_ij T_ji
  * (Sec. III.C).  Both give the same sum up to rounding.
@@ -315,6 +323,7 @@ enum {
                             (16-bit split modes) */
   AFQMC_PH_CONTROL,      /* global energy and population control */
   AFQMC_PH_ESTIMATOR,    /* mixed estimators: full Green's function, S^2, weighted means */
+  AFQMC_PH_PROPAGATE,    /* P T(VHS) P phi in one launch (AFQMC_FP16X3) */
   AFQMC_NPHASE
 };
 int afqmc_profile_enable(afqmc_ham* ham, int max_records);

@@ -26,6 +26,7 @@ BF16X3 = 2
 FP16X3 = 3
 STEP_REUSE = 1
 FLAG_ONE_BODY_FP64 = 1  # AFQMC_FLAG_ONE_BODY_FP64
+FLAG_UNFUSED_PROPAGATION = 2  # AFQMC_FLAG_UNFUSED_PROPAGATION
 # status-word bits (afqmc_get_status)
 STATUS_SINGULAR, STATUS_NONFINITE, STATUS_QR_ZERO, STATUS_NO_LIVE = 1, 2, 4, 8
 MSD_MAX_RANK = 6  # AFQMC_MSD_MAX_RANK
@@ -74,7 +75,7 @@ EXPORTED = (
 
 # kernel phases of afqmc_profile_read, in header order
 PHASES = ("green", "force_bias", "shift", "vhs", "one_body", "taylor", "qr", "weight",
-          "exchange", "energy", "split", "control", "estimator")
+          "exchange", "energy", "split", "control", "estimator", "propagate")
 
 
 class AfqmcError(RuntimeError):
@@ -280,6 +281,7 @@ class Hamiltonian:
 
     def __init__(self, h1, chol, phiT_a, phiT_b=None, *, dt, max_walkers, taylor_order=6,
                  precision="fp64", mu=None, e_shift=None, exchange="auto", one_body_fp64=False,
+                 unfused_propagation=False,
                  stream=None):
         lib = load()
         h1 = np.asarray(h1)
@@ -299,7 +301,8 @@ class Hamiltonian:
         self.max_walkers = int(max_walkers)
         p = _Params(N, na, nb, K, float(dt), int(taylor_order), self.precision, self.max_walkers,
                     math.nan if mu is None else float(mu), math.nan if e_shift is None else float(e_shift),
-                    _EXCHANGE[exchange], FLAG_ONE_BODY_FP64 if one_body_fp64 else 0)
+                    _EXCHANGE[exchange], (FLAG_ONE_BODY_FP64 if one_body_fp64 else 0)
+                    | (FLAG_UNFUSED_PROPAGATION if unfused_propagation else 0))
         h = ctypes.c_void_p()
         _check(lib.afqmc_init_hamiltonian(
             ctypes.byref(p), self._h1.ctypes.data, self._chol.ctypes.data, self._pa.ctypes.data,

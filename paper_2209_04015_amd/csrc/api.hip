@@ -102,6 +102,10 @@ struct afqmc_ham {
   unsigned short* fb_th = nullptr;     // [W][2][2][nmax][2 ldh] theta split per (walker, re|im)
   float* fb_th_unscale = nullptr;      // [W][2]
   float* fb_part = nullptr;            // [FB_SPLIT_CHUNKS][2 W][K] split-K partial sums
+  // fused propagation (FP16X3)
+  bool prop_fused = false;
+  unsigned short* psplit = nullptr;    // P split into fp16 hi/lo, scaled by 2^pexp
+  int pexp = 0;
   float* th_unscale = nullptr;           // [W][2][2][nmax]
   // workspace (sized for max_walkers)
   void* theta = nullptr;    // T [W][2][2][nmax][ldN]
@@ -311,6 +315,12 @@ int seq_propagate_core(afqmc_ham* h, afqmc_walkers* w, int nw, const StepIO& io,
   } else {
     PHASE(h, AFQMC_PH_VHS, s,
           (launch_vhs<T>(d, nw, (const T*)h->xs, (const T*)h->LT, h->pq, (T*)h->vhs, h->sdt, s)));
+  }
+  if (h->prop_fused) {
+    PHASE(h, AFQMC_PH_PROPAGATE, s,
+          launch_prop_fused(d, nw, (double2*)w->phi_a, (double2*)w->phi_b, (const float*)h->vhs,
+                            h->tmax + h->prm.max_walkers, h->psplit, h->pexp, h->prm.taylor_order, s));
+    return AFQMC_OK;
   }
   const bool pphi64 = sizeof(T) == 8 || (h->prm.flags & AFQMC_FLAG_ONE_BODY_FP64);
   PHASE(h, AFQMC_PH_ONE_BODY, s,
@@ -742,7 +752,16 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
   if (vhs_split(h)) {
     if ((rc = dalloc_t(h, &h->xs_split, W * 2 * 2 * d.ldhK))) return rc;
     if ((rc = dalloc_t(h, &h->xs_unscale, W * 2))) return rc;
-    if ((rc = dalloc_t(h, &h->tk, (size_t)p.taylor_order * W * N * d.ncolp))) return rc;
+    const PropFusedGeom pg = prop_fused_geom(d);
+    h->prop_fused = pg.ok && !(p.flags & (AFQMC_FLAG_ONE_BODY_FP64 | AFQMC_FLAG_UNFUSED_PROPAGATION));
+    if (h->prop_fused) {
+      if ((rc = dalloc_t(h, &h->psplit, pg.psplit_halves))) return rc;
+      unsigned* pmax = nullptr;
+      HIP_TRY(tmp.get(&pmax, sizeof(unsigned)));
+      HIP_TRY(setup_prop_fused(d, h->P, h->psplit, pmax, &h->pexp, s));
+    } else {
+      if ((rc = dalloc_t(h, &h->tk, (size_t)p.taylor_order * W * N * d.ncolp))) return rc;
+    }
     if ((rc = dalloc_t(h, &h->fb_th, W * 2 * 2 * nmax * 2 * d.ldh))) return rc;
     if ((rc = dalloc_t(h, &h->fb_th_unscale, W * 2))) return rc;
     if ((rc = dalloc_t(h, &h->fb_part, (size_t)FB_SPLIT_CHUNKS * 2 * W * K))) return rc;
@@ -808,7 +827,8 @@ int afqmc_init_hamiltonian(const afqmc_params* params, const double* host_h1,
   if (p.max_walkers < 1) return fail(AFQMC_EINVAL, "max_walkers must be >= 1");
   if (p.exchange < AFQMC_EXCHANGE_AUTO || p.exchange > AFQMC_EXCHANGE_PAIR)
     return fail(AFQMC_EINVAL, "unknown exchange algorithm %d", p.exchange);
-  if (p.flags & ~AFQMC_FLAG_ONE_BODY_FP64) return fail(AFQMC_EINVAL, "unknown flags 0x%x", p.flags);
+  if (p.flags & ~(AFQMC_FLAG_ONE_BODY_FP64 | AFQMC_FLAG_UNFUSED_PROPAGATION))
+    return fail(AFQMC_EINVAL, "unknown flags 0x%x", p.flags);
   const int nmax = p.na > p.nb ? p.na : p.nb;
   if (qr_lds_bytes_for(p.N, nmax) > 160 * 1024)
     return fail(AFQMC_EUNSUPPORTED, "N * max(na, nb) too large for the in-LDS QR (N=%d, n=%d)", p.N, nmax);

@@ -150,6 +150,22 @@ hipError_t launch_comb_static(void* scratch_ptr, const StepDims& d, int nw, doub
                               double2* phi_b, double2* log_ovlp, double* log_w, int* parent, int* status,
                               hipStream_t s);
 
+// --- fused propagation P T(VHS) P phi on split fp16 operands (prop_kernels.hip) ---
+struct PropFusedGeom {
+  int RT, QP, QCH, TQS, CT, nkbP;
+  size_t lds_bytes, psplit_halves;
+  bool ok;  // the shape fits the kernel (N <= 320, n_s <= 32, LDS)
+};
+PropFusedGeom prop_fused_geom(const StepDims& d);
+// P (FP64 [N][ldP]) into its split copy with the power-of-two scale 2^pexp
+// (pexp out, host; synchronises s); sets the kernel's LDS attribute.
+hipError_t setup_prop_fused(const StepDims& d, const double* P, unsigned short* psplit, unsigned* pmax_scratch,
+                            int* pexp_host, hipStream_t s);
+// phi <- P T_order(VHS) P phi for W walkers in place; vmax [W] max |VHS|
+hipError_t launch_prop_fused(const StepDims& d, int W, double2* phi_a, double2* phi_b, const float* vhs,
+                             const unsigned* vmax, const unsigned short* psplit, int pexp, int order,
+                             hipStream_t s);
+
 // --- mixed estimators (estimator_kernels.hip) ---------------------------------
 // G [W][2][N][N] complex: G_pq = sum_i PhiT[p][i] theta[q][i] per spin
 template <typename T>

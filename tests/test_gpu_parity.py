@@ -194,6 +194,50 @@ def test_propagate_matches_oracle(name, precision, uhf):
     _assert_logw(glw, lw, tol_log)
 
 
+@pytest.mark.parametrize("name,uhf", [("n20", False), ("ragged", False), ("ragged", True)])
+def test_fused_and_term_by_term_propagation_agree(name, uhf):
+    """FP16X3: the one-launch propagation (split P, Horner's rule in FP32)
+    and the term-by-term kernels (FP32 one-body half steps, terms summed in
+    FP64) both meet the mixed orbital bar against the oracle, and the phase
+    profile shows which kernels ran (one fused launch; or two one-body
+    launches, six Taylor orders and the sum)."""
+    torch = _torch()
+    from paper_2209_04015_amd import afqmc
+
+    c = case(name, "fp16x3", uhf)
+    unfused = afqmc.Hamiltonian(c.h1, c.L, c.pa_T, c.pb_T, dt=c.cfg.dt, max_walkers=c.cfg.W,
+                                precision="fp16x3", unfused_propagation=True)
+    na, nb, lo, lw = orc.propagate(c.oh, c.pa, c.pb, c.lo, c.lw, c.x)
+    errs = {}
+    for label, ham in (("fused", c.ham), ("term by term", unfused)):
+        # the same call twice on one handle: the second must not see what the
+        # first left in the workspace (the fused path splits its VHS in place)
+        w0 = c.walkers()
+        ham.propagate(w0, torch.as_tensor(c.x, device=c.dev))
+        w = c.walkers()
+        ham.profile_enable(64)
+        ham.propagate(w, torch.as_tensor(c.x, device=c.dev))
+        ph = ham.profile_read()
+        ham.profile_enable(0)
+        assert torch.equal(w0.phi_a, w.phi_a) and torch.equal(w0.phi_b, w.phi_b)
+        assert torch.equal(w0.log_w, w.log_w)
+        if label == "fused":
+            assert ph["propagate"][1] == 1 and ph["taylor"][1] == 0 and ph["one_body"][1] == 0
+        else:
+            assert ph["propagate"][1] == 0 and ph["taylor"][1] == 7 and ph["one_body"][1] == 2
+        e = 0.0
+        for g, r in ((w.phi_a.cpu().numpy(), na), (w.phi_b.cpu().numpy(), nb)):
+            sc = np.abs(r).reshape(r.shape[0], -1).max(axis=1)
+            e = max(e, (np.abs(g - r).reshape(r.shape[0], -1).max(axis=1) / sc).max())
+        errs[label] = e
+        _assert_logw(w.log_w.cpu().numpy(), lw, 1e-3)
+        assert np.abs(w.log_ovlp.cpu().numpy().real - lo.real).max() < 1e-3
+    print(f"[gpu] {name} uhf={uhf} fp16x3 propagation: max rel phi err fused {errs['fused']:.3e}, "
+          f"term by term {errs['term by term']:.3e}", flush=True)
+    assert errs["fused"] <= 1e-4 and errs["term by term"] <= 1e-4
+    unfused.close()
+
+
 @pytest.mark.parametrize("name,precision,uhf", PARAMS)
 def test_orthogonalise_matches_oracle(name, precision, uhf):
     c = case(name, precision, uhf)
