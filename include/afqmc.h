@@ -442,6 +442,33 @@ int afqmc_msd_force_bias(afqmc_msd* t, afqmc_ham* ham, const afqmc_walkers* w, i
 int afqmc_msd_propagate(afqmc_msd* t, afqmc_ham* ham, afqmc_walkers* w, int nw, const double* fields,
                         void* stream);
 
+/* Attach the Hamiltonian whose local energy afqmc_msd_local_energy takes:
+ *   K          number of Cholesky vectors
+ *   host_h1    host [N][N] one-body integrals (the energy uses h1, Sec. III.C)
+ *   host_chol  host [K][N][N] real symmetric Cholesky vectors
+ * Builds, in FP64, the rotated rows C_S^T L_g and C_S^T h1 of each spin,
+ * where S = the reference's occupied orbitals and the active particles
+ * (the virtual orbitals some determinant excites into), and a workspace for
+ * passes over a few walkers at a time.  Allocates and synchronises `stream`;
+ * once per trial (AFQMC_EINVAL otherwise).  The number of (active particle,
+ * active hole) pairs of a spin must not exceed 1024: expansions within an
+ * active space, as selected-CI trials are (AFQMC_EUNSUPPORTED otherwise). */
+int afqmc_msd_set_hamiltonian(afqmc_msd* t, int K, const double* host_h1, const double* host_chol,
+                              void* stream);
+
+/* Local energy of every walker against the multi-determinant trial
+ * (Sec. III.C: the one-body part through the expansion's Green's function,
+ * the two-body numerator through the generalised Wick's theorem):
+ *   E_L = sum_a c_a <D_a|phi> E_L(D_a, phi) / sum_a c_a <D_a|phi>,
+ * split like afqmc_local_energy: e[z] = (E1, EJ, EK), device complex
+ * [nw][3], written.  The Cholesky sum is taken once per walker through the
+ * Gram matrices of the active blocks (FP64 matrix cores); the expansion
+ * enters through per-string and per-determinant contractions with them.
+ * A determinant whose overlap with a walker is exactly zero contributes only
+ * its linear terms (its own local energy is undefined).  Requires
+ * afqmc_msd_set_hamiltonian.  Asynchronous on `stream`; nw <= max_walkers. */
+int afqmc_msd_local_energy(afqmc_msd* t, const afqmc_walkers* w, int nw, void* e, void* stream);
+
 /* Excitation strings per spin after grouping (for sizing and reports). */
 int afqmc_msd_get_strings(afqmc_msd* t, int* nstr_a, int* nstr_b);
 /* Synchronise `stream`, return the accumulated status bits in *out and clear them. */

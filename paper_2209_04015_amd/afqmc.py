@@ -64,6 +64,8 @@ EXPORTED = (
     "afqmc_msd_green_function",
     "afqmc_msd_force_bias",
     "afqmc_msd_propagate",
+    "afqmc_msd_set_hamiltonian",
+    "afqmc_msd_local_energy",
     "afqmc_msd_get_strings",
     "afqmc_msd_get_status",
     "afqmc_msd_destroy",
@@ -156,6 +158,8 @@ def load(path: str = LIB_PATH):
     lib.afqmc_msd_green_function.argtypes = [vp, P(_Walkers), ip, vp, vp]
     lib.afqmc_msd_force_bias.argtypes = [vp, vp, P(_Walkers), ip, vp, vp]
     lib.afqmc_msd_propagate.argtypes = [vp, vp, P(_Walkers), ip, vp, vp]
+    lib.afqmc_msd_set_hamiltonian.argtypes = [vp, ip, vp, vp, vp]
+    lib.afqmc_msd_local_energy.argtypes = [vp, P(_Walkers), ip, vp, vp]
     lib.afqmc_msd_get_strings.argtypes = [vp, P(ip), P(ip)]
     lib.afqmc_msd_get_status.argtypes = [vp, vp, P(ip)]
     lib.afqmc_msd_destroy.argtypes = [vp]
@@ -642,6 +646,28 @@ class MSDTrial:
         fp = _dev(fields, torch.float64, (nw, ham.K), "fields")
         s = w._struct(self, nw)
         _check(_lib.afqmc_msd_propagate(self._h, ham._h, ctypes.byref(s), nw, fp, _stream_ptr(stream)))
+
+    def set_hamiltonian(self, h1, chol, stream=None):
+        """Attach h1 [N, N] and the Cholesky vectors [K, N, N] (host arrays) for
+        local_energy (afqmc_msd_set_hamiltonian)."""
+        h1 = _host(h1, (self.N, self.N), "h1")
+        chol = np.asarray(chol)
+        K = chol.shape[0]
+        chol = _host(chol, (K, self.N, self.N), "chol")
+        _check(_lib.afqmc_msd_set_hamiltonian(self._h, K, h1.ctypes.data, chol.ctypes.data, _stream_ptr(stream)))
+        self.K = K
+
+    def local_energy(self, w: Walkers, out=None, nw=None, stream=None):
+        """E_L of each walker against the expansion: complex [nw, 3] (E1, EJ, EK)."""
+        import torch
+
+        nw = w.W if nw is None else int(nw)
+        if out is None:
+            out = torch.empty((nw, 3), dtype=torch.complex128, device=w.phi_a.device)
+        optr = _dev(out, torch.complex128, (nw, 3), "energy")
+        s = w._struct(self, nw)
+        _check(_lib.afqmc_msd_local_energy(self._h, ctypes.byref(s), nw, optr, _stream_ptr(stream)))
+        return out
 
     def status(self, stream=None):
         v = ctypes.c_int()

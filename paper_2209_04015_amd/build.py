@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libafqmc.so")
-SOURCES = ["step_kernels.hip", "split_kernels.hip", "setup_kernels.hip", "control_kernels.hip", "estimator_kernels.hip", "msd_kernels.hip", "prop_kernels.hip", "api.hip"]
+SOURCES = ["step_kernels.hip", "split_kernels.hip", "setup_kernels.hip", "control_kernels.hip", "estimator_kernels.hip", "msd_kernels.hip", "msd_energy.hip", "prop_kernels.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

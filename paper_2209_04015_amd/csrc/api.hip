@@ -1161,6 +1161,14 @@ struct afqmc_msd {
   double* qp = nullptr;  // planar Q [W][2][2][N][ldq]
   int* status = nullptr;
   std::vector<void*> allocs;
+  // local energy (afqmc_msd_set_hamiltonian): host copies of the orbitals,
+  // the active sets, the tables and workspace of msd_energy.hip
+  std::vector<double> C_host[2];
+  std::vector<int> hl[2], ql[2];
+  MsdEnergyDims ed{};
+  MsdEnergyTables et{};
+  MsdEnergyWork ew{};
+  bool has_ham = false;
 };
 
 namespace {
@@ -1326,6 +1334,83 @@ int msd_build(afqmc_msd* t, const double* C[2], const double* coeff, const int* 
       eoff.push_back(pr.second);
     }
   }
+  // local energy: the active holes and particles of each spin (those that
+  // some string excites), every string slot's position among them, and the
+  // determinants excited in both spins
+  {
+    std::vector<int> hpos[2], qpos[2];
+    for (int s = 0; s < 2; ++s) {
+      std::vector<char> hu(nel[s], 0), qu(m.nv[s], 0);
+      for (const auto& key : strs[s])
+        for (int x = 0; x < key[0]; ++x) {
+          hu[key[1 + x]] = 1;
+          qu[key[1 + key[0] + x] - nel[s]] = 1;
+        }
+      hpos[s].assign(nel[s], -1);
+      qpos[s].assign(m.nv[s], -1);
+      t->hl[s].clear();
+      t->ql[s].clear();
+      for (int i = 0; i < nel[s]; ++i)
+        if (hu[i]) {
+          hpos[s][i] = (int)t->hl[s].size();
+          t->hl[s].push_back(i);
+        }
+      for (int a = 0; a < m.nv[s]; ++a)
+        if (qu[a]) {
+          qpos[s][a] = (int)t->ql[s].size();
+          t->ql[s].push_back(a);
+        }
+    }
+    const int hmax = std::max<int>(1, std::max(t->hl[0].size(), t->hl[1].size()));
+    const int qmax = std::max<int>(1, std::max(t->ql[0].size(), t->ql[1].size()));
+    std::vector<int> hlist((size_t)2 * hmax, 0), qlist((size_t)2 * qmax, 0);
+    for (int s = 0; s < 2; ++s) {
+      for (size_t x = 0; x < t->hl[s].size(); ++x) hlist[(size_t)s * hmax + x] = t->hl[s][x];
+      for (size_t x = 0; x < t->ql[s].size(); ++x) qlist[(size_t)s * qmax + x] = t->ql[s][x];
+    }
+    std::vector<int> spos((size_t)m.nstr_tot * 2 * MSD_KMAX, 0);
+    for (int u = 0; u < m.nstr_tot; ++u) {
+      const int s = u >= m.nstr[0] ? 1 : 0;
+      for (int x = 0; x < srank[u]; ++x) {
+        spos[((size_t)u * 2 + 0) * MSD_KMAX + x] = hpos[s][sorb[((size_t)u * 2 + 0) * MSD_KMAX + x]];
+        spos[((size_t)u * 2 + 1) * MSD_KMAX + x] = qpos[s][sorb[((size_t)u * 2 + 1) * MSD_KMAX + x]];
+      }
+    }
+    std::vector<int> xa, xb;
+    std::vector<double> xc;
+    for (int a = 0; a < ndet; ++a) {
+      const int ua = dstr[0][a], ub = m.nstr[0] + dstr[1][a];
+      if (srank[ua] > 0 && srank[ub] > 0) {
+        xa.push_back(ua);
+        xb.push_back(ub);
+        xc.push_back(coeff[a]);
+      }
+    }
+    MsdEnergyDims& e = t->ed;
+    e.Hmax = hmax;
+    e.Qmax = qmax;
+    for (int s = 0; s < 2; ++s) {
+      e.nh[s] = (int)t->hl[s].size();
+      e.nq[s] = (int)t->ql[s].size();
+      e.D[s] = e.nh[s] * e.nq[s];
+      e.S[s] = nel[s] + e.nq[s];
+    }
+    e.Dmax = std::max(1, std::max(e.D[0], e.D[1]));
+    e.Smax = std::max(e.S[0], e.S[1]);
+    e.nmax = m.nmax;
+    int rc2;
+    MsdEnergyTables& et = t->et;
+    et.ncross = (int)xa.size();
+    if (xa.empty()) {  // keep valid device pointers
+      xa.push_back(0);
+      xb.push_back(0);
+      xc.push_back(0.0);
+    }
+    if ((rc2 = msd_upload(t, &et.hlist, hlist)) || (rc2 = msd_upload(t, &et.qlist, qlist)) ||
+        (rc2 = msd_upload(t, &et.spos, spos)) || (rc2 = msd_upload(t, &et.xa, xa)) ||
+        (rc2 = msd_upload(t, &et.xb, xb)) || (rc2 = msd_upload(t, &et.xc, xc)))
+      return rc2;
+  }
   // orbitals
   std::vector<double> cocc((size_t)2 * N * m.nmax, 0.0), cvirt((size_t)2 * N * m.ldv, 0.0);
   std::vector<double> cfull((size_t)2 * N * m.ldN, 0.0);
@@ -1346,6 +1431,9 @@ int msd_build(afqmc_msd* t, const double* C[2], const double* coeff, const int* 
       (rc = msd_upload(t, &tb.erow, erow)) || (rc = msd_upload(t, &tb.estr, estr)) ||
       (rc = msd_upload(t, &tb.eoff, eoff)))
     return rc;
+  t->et.srank = tb.srank;
+  t->et.saoff = tb.saoff;
+  for (int s = 0; s < 2; ++s) t->C_host[s].assign(C[s], C[s] + (size_t)N * N);
   return AFQMC_OK;
 }
 
@@ -1538,6 +1626,95 @@ int afqmc_msd_propagate(afqmc_msd* t, afqmc_ham* h, afqmc_walkers* w, int nw, co
   return AFQMC_OK;
 }
 
+
+int afqmc_msd_set_hamiltonian(afqmc_msd* t, int K, const double* host_h1, const double* host_chol, void* stream) {
+  if (!t) return fail(AFQMC_EINVAL, "null trial handle");
+  if (K < 1) return fail(AFQMC_EINVAL, "K = %d must be >= 1", K);
+  if (!host_h1 || !host_chol) return fail(AFQMC_EINVAL, "null h1 or Cholesky vectors");
+  if (t->has_ham) return fail(AFQMC_EINVAL, "the trial already has a Hamiltonian");
+  MsdEnergyDims& e = t->ed;
+  const MsdDims& m = t->m;
+  if (e.Dmax > 1024)
+    return fail(AFQMC_EUNSUPPORTED,
+                "the local energy needs at most 1024 (active particle, active hole) pairs per spin; the expansion "
+                "excites %d x %d (alpha) and %d x %d (beta)",
+                e.nq[0], e.nh[0], e.nq[1], e.nh[1]);
+  e.K = K;
+  e.ldL = m.ldN;
+  e.ldG = round_up(K, 8);
+  e.gchunk = 8;
+  e.nchunk = ceil_div(K + 1, e.gchunk);
+  const size_t lds = msd_energy_rp_lds(e);
+  if (lds > 160 * 1024)
+    return fail(AFQMC_EUNSUPPORTED, "the active space is too large for the local energy (%zu bytes of LDS)", lds);
+  // walkers per pass: the workspace of one walker, within about 4 GB
+  const size_t K1 = (size_t)K + 1;
+  const size_t per = 2 * K1 * 2 * e.Smax * m.nmax * sizeof(double) + 2 * (size_t)e.Dmax * e.ldG * 16 +
+                     4 * (size_t)e.nchunk * e.Dmax * 16 + 3 * (size_t)e.Dmax * e.Dmax * 16 + 8 * K1 * 16;
+  e.Wc = (int)std::max<size_t>(1, std::min<size_t>({(size_t)32, (size_t)t->max_walkers, (size_t(4) << 30) / per}));
+  int rc;
+  HIP_TRY(hipSetDevice(t->device));
+  HIP_TRY(msd_energy_set_attributes(lds));
+  hipStream_t s = (hipStream_t)stream;
+  const int N = m.N;
+  const size_t NN = (size_t)N * N;
+  {
+    // rotated rows C_S^T L_g (and C_S^T h1 as block K), C_S = [C_occ | C_virt[:, Q]]
+    TempAllocs tmp;
+    double *dL = nullptr, *cs = nullptr, *out = nullptr;
+    HIP_TRY(tmp.get(&dL, K1 * NN * sizeof(double)));
+    HIP_TRY(hipMemcpy(dL, host_chol, (size_t)K * NN * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dL + (size_t)K * NN, host_h1, NN * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(tmp.get(&cs, NN * sizeof(double)));
+    HIP_TRY(tmp.get(&out, K1 * N * e.Smax * sizeof(double)));
+    const int nel[2] = {m.na, m.nb};
+    for (int sp = 0; sp < 2; ++sp) {
+      const int S = e.S[sp];
+      double* lr = nullptr;
+      if ((rc = dalloc_t(t, &lr, K1 * (size_t)std::max(S, 1) * e.ldL))) return rc;
+      t->et.lr[sp] = lr;
+      if (nel[sp] == 0) continue;
+      std::vector<double> h((size_t)N * S);
+      for (int p = 0; p < N; ++p) {
+        for (int i = 0; i < nel[sp]; ++i) h[(size_t)p * S + i] = t->C_host[sp][(size_t)p * N + i];
+        for (int q = 0; q < e.nq[sp]; ++q)
+          h[(size_t)p * S + nel[sp] + q] = t->C_host[sp][(size_t)p * N + nel[sp] + t->ql[sp][q]];
+      }
+      HIP_TRY(hipMemcpy(cs, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+      // out[(g, p)][r] = sum_q L_g[p][q] C_S[q][r] = (C_S^T L_g)[r][p] (L_g symmetric)
+      HIP_TRY(setup_gemm((int)(K1 * N), S, N, 0, dL, N, cs, S, out, S, nullptr, 1, s));
+      HIP_TRY(msd_lr_pack((long)K1 * N, N, S, e.ldL, out, lr, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  // workspace for Wc walkers
+  const size_t Wc = (size_t)e.Wc;
+  MsdEnergyWork& w = t->ew;
+  if ((rc = dalloc_t(t, &w.u, Wc * 2 * K1 * 2 * e.Smax * m.nmax)) || (rc = dalloc_t(t, &w.rbuf, Wc * 2 * e.Dmax * e.ldG)) ||
+      (rc = dalloc_t(t, &w.jpart, Wc * 2 * e.nchunk * e.Dmax)) ||
+      (rc = dalloc_t(t, &w.ppart, Wc * 2 * e.nchunk * e.Dmax)) || (rc = dalloc_t(t, &w.tt, Wc * 2 * K1)) ||
+      (rc = dalloc_t(t, &w.kt, Wc * 2 * (size_t)K)) || (rc = dalloc_t(t, &w.r1, Wc * 2 * e.Dmax)) ||
+      (rc = dalloc_t(t, &w.vj, Wc * 2 * e.Dmax)) || (rc = dalloc_t(t, &w.vp, Wc * 2 * e.Dmax)) ||
+      (rc = dalloc_t(t, &w.sc, Wc * 4)) || (rc = dalloc_t(t, &w.G, Wc * 3 * e.Dmax * e.Dmax)))
+    return rc;
+  t->has_ham = true;
+  return AFQMC_OK;
+}
+
+int afqmc_msd_local_energy(afqmc_msd* t, const afqmc_walkers* w, int nw, void* e, void* stream) {
+  int rc;
+  if ((rc = msd_check(t, w, nw)) || nw == 0) return rc;
+  if (!e) return fail(AFQMC_EINVAL, "null energy output");
+  if (!t->has_ham) return fail(AFQMC_EINVAL, "the trial has no Hamiltonian (afqmc_msd_set_hamiltonian)");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = msd_ratio(t, w, nw, true, s))) return rc;
+  for (int z0 = 0; z0 < nw; z0 += t->ed.Wc) {
+    const int nz = std::min(t->ed.Wc, nw - z0);
+    HIP_TRY(launch_msd_energy_chunk(t->m, t->ed, t->et, z0, nz, t->theta, t->yp, t->sdet, t->sadj, t->uw, t->ratio,
+                                    t->ew, (double2*)e, s));
+  }
+  return AFQMC_OK;
+}
 
 int afqmc_msd_get_strings(afqmc_msd* t, int* nstr_a, int* nstr_b) {
   if (!t) return fail(AFQMC_EINVAL, "null multi-determinant trial handle");

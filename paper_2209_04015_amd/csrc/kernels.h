@@ -267,3 +267,53 @@ int msd_fb_splits(int W, int N, int K, int ldK, int ldpk, size_t gs_elem_bytes, 
 template <typename T>
 hipError_t launch_msd_force_bias(const MsdDims& m, int W, const double* theta, const double* qp, const T* lt, int K,
                                  int ldK, int ldpk, int nsplit, void* scratch, double2* vbias, hipStream_t s);
+
+// --- local energy of the multi-determinant trial (msd_energy.hip) --------------
+struct MsdEnergyDims {
+  int K;               // Cholesky vectors (rotated block K holds h1)
+  int S[2], Smax;      // rotated rows per spin: n_s occupied + the active particles
+  int nh[2], nq[2];    // active holes / particles per spin
+  int Hmax, Qmax;      // their maxima (strides of the lists)
+  int D[2], Dmax;      // nq * nh per spin (<= 1024)
+  int ldL;             // orbital stride of the rotated rows (= MsdDims::ldN)
+  int ldG;             // Cholesky stride of the r rows (>= K)
+  int gchunk, nchunk;  // Cholesky blocks per workgroup of the r / p kernel, and their count over K + 1
+  int Wc;              // walkers per pass
+  int nmax;            // electron stride (MsdDims::nmax)
+};
+struct MsdEnergyTables {
+  const double* lr[2];  // [K + 1][S_s][ldL] rotated rows C_S^T L_g (g < K), C_S^T h1 (g = K)
+  const int* hlist;     // [2][Hmax] active holes
+  const int* qlist;     // [2][Qmax] active particles (virtual index)
+  const int* spos;      // [nstr_tot][2][MSD_KMAX] slot positions in H (holes) and Q (particles)
+  const int* srank;
+  const int* saoff;
+  const int* xa;        // determinants excited in both spins: alpha string,
+  const int* xb;        // beta string (concatenated index),
+  const double* xc;     // coefficient
+  int ncross;
+};
+struct MsdEnergyWork {
+  double* u;       // [Wc][2][K + 1][2][Smax][nmax]
+  double2* rbuf;   // [Wc][2][Dmax][ldG]
+  double2* jpart;  // [Wc][2][nchunk][Dmax]
+  double2* ppart;  // [Wc][2][nchunk][Dmax]
+  double2* tt;     // [Wc][2][K + 1]
+  double2* kt;     // [Wc][2][K]
+  double2* r1;     // [Wc][2][Dmax]
+  double2* vj;     // [Wc][2][Dmax]
+  double2* vp;     // [Wc][2][Dmax]
+  double2* sc;     // [Wc][4]
+  double2* G;      // [Wc][3][Dmax][Dmax]
+};
+size_t msd_energy_rp_lds(const MsdEnergyDims& e);
+hipError_t msd_energy_set_attributes(size_t rp_lds);
+// lr[g][r][ldL] from out[(g, p)][r] (rows_gp = (K + 1) N rows of S)
+hipError_t msd_lr_pack(long rows_gp, int N, int S, int ldL, const double* out, double* lr, hipStream_t s);
+// local energies e[z][3] of walkers z0 .. z0 + nz - 1 (nz <= Wc) from the
+// reference theta, Y, string dets, adjugates, string weights and ratios of
+// launch_msd_ratio (want_adj)
+hipError_t launch_msd_energy_chunk(const MsdDims& m, const MsdEnergyDims& e, const MsdEnergyTables& t, int z0,
+                                   int nz, const double* theta, const double* yp, const double2* sdet,
+                                   const double2* sadj, const double2* uw, const double2* ratio,
+                                   const MsdEnergyWork& w, double2* eout, hipStream_t s);

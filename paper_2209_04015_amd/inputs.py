@@ -167,7 +167,7 @@ def orbitals(h1: np.ndarray) -> np.ndarray:
 
 
 def msd_expansion(N: int, na: int, nb: int, ndet: int, max_rank: int = 4, seed: int = 0,
-                  stream: int = 0):
+                  stream: int = 0, active=None):
     """A synthetic multi-determinant expansion of ``ndet`` distinct determinants.
 
     Returns ``(coeff [ndet] float64, rank [ndet, 2] int32,
@@ -180,20 +180,33 @@ def msd_expansion(N: int, na: int, nb: int, ndet: int, max_rank: int = 4, seed: 
     available holes and particles), the pair (0, 0) excluded after the
     reference; coefficients are +-0.2 exp(-3 a / ndet) (1 - u / 2), u ~ U(0, 1),
     sorted by decreasing magnitude after the reference.
+
+    ``active = (n_ao, n_av)`` confines the excitations to an active space, as
+    selected-CI trials are: holes among the n_ao highest occupied orbitals
+    [n_s - n_ao, n_s), particles among the n_av lowest virtual ones
+    [n_s, n_s + n_av) (None: every orbital).
     """
     if not 0 <= max_rank <= MSD_MAX_RANK:
         raise ValueError("max_rank out of range")
     _, _, aux_ss = _streams(seed)
     rng = np.random.default_rng(aux_ss.spawn(stream + 1)[stream])
     nel = (na, nb)
-    kmax = [min(max_rank, n, N - n) for n in nel]
+    if active is None:
+        hole_lo = [0, 0]
+        nvirt = [N - na, N - nb]
+    else:
+        n_ao, n_av = active
+        hole_lo = [max(0, n - n_ao) for n in nel]
+        nvirt = [min(n_av, N - n) for n in nel]
+    nocc_act = [nel[s] - hole_lo[s] for s in range(2)]
+    kmax = [min(max_rank, nocc_act[s], nvirt[s]) for s in range(2)]
     seen = {((), (), (), ())}
     exc = [((), (), (), ())]
     limit = 1
     for k_a in range(kmax[0] + 1):
         for k_b in range(kmax[1] + 1):
-            limit += (math.comb(na, k_a) * math.comb(N - na, k_a)
-                      * math.comb(nb, k_b) * math.comb(N - nb, k_b))
+            limit += (math.comb(nocc_act[0], k_a) * math.comb(nvirt[0], k_a)
+                      * math.comb(nocc_act[1], k_b) * math.comb(nvirt[1], k_b))
     if ndet > limit - 1:
         raise ValueError("more determinants requested than the excitation space holds")
     prob = [np.array([0.45 ** k for k in range(km + 1)]) for km in kmax]
@@ -204,9 +217,14 @@ def msd_expansion(N: int, na: int, nb: int, ndet: int, max_rank: int = 4, seed: 
             continue
         key, ident = [], []
         for s in range(2):
-            holes = tuple(sorted(int(h) for h in rng.choice(nel[s], ks[s], replace=False)))
-            parts = tuple(int(q) for q in rng.permutation(rng.choice(np.arange(nel[s], N), ks[s],
-                                                                     replace=False)))
+            if active is None:
+                holes = tuple(sorted(int(h) for h in rng.choice(nel[s], ks[s], replace=False)))
+                parts = tuple(int(q) for q in rng.permutation(rng.choice(np.arange(nel[s], N), ks[s],
+                                                                         replace=False)))
+            else:
+                holes = tuple(sorted(hole_lo[s] + int(h) for h in rng.choice(nocc_act[s], ks[s], replace=False)))
+                parts = tuple(int(q) for q in rng.permutation(
+                    rng.choice(np.arange(nel[s], nel[s] + nvirt[s]), ks[s], replace=False)))
             key += [holes, parts]
             ident += [holes, tuple(sorted(parts))]   # the determinant, whatever the pairing
         if tuple(ident) in seen:

@@ -449,3 +449,133 @@ def test_msd_propagate_on_the_fp32_path():
     _assert_step(w, ref, tol_phi=1e-4, tol_log=1e-3)
     t.close()
     ham.close()
+
+
+# ---------------------------------------------------------------------------
+# Local energy against the expansion (afqmc_msd_local_energy): the library
+# takes the generalised Wick route (Gram matrices of the active blocks over
+# the Cholesky index, per-string and per-determinant contractions); the
+# oracle evaluates sum_a c_a O_a E_L(D_a) / sum_a c_a O_a determinant by
+# determinant.  Both FP64.  Bar: 1e-11 of S = |E1| + |EJ| + |EK| per walker,
+# times the expansion's cancellation (the terms are inverted determinants
+# and products of Cholesky contractions: a few hundred roundings of
+# relative size u = 1.1e-16, amplified by cond(S_0) and by the cancellation
+# of sum_a c_a O_a).
+# ---------------------------------------------------------------------------
+ENERGY_CASES = [
+    # N, na, nb, K, ndet, max_rank, W, uhf, active
+    (12, 4, 3, 10, 40, 3, 5, True, None),
+    (20, 5, 5, 30, 120, 4, 16, False, None),
+    (37, 9, 6, 25, 200, 4, 11, True, (6, 8)),        # ragged, an active space
+    (52, 11, 11, 70, 300, 4, 37, False, (8, 10)),     # several Cholesky chunks and Gram tiles
+]
+
+
+def _energy_problem(N, na, nb, K, ndet, max_rank, W, uhf, active, seed=3):
+    h1, L = inputs.hamiltonian(N, K, max(2.0, K / 5), seed=seed)
+    C_a = inputs.orbitals(h1)
+    C_b = inputs.orbitals(h1 + np.diag(np.linspace(0.0, 0.5, N))) if uhf else C_a
+    coeff, rank, orbs = inputs.msd_expansion(N, na, nb, ndet, max_rank=max_rank, seed=seed + 1, active=active)
+    pa = inputs.walkers_perturbed(C_a[:, :na], W, 0.3, seed=seed + 2, stream=0)
+    pb = inputs.walkers_perturbed(C_b[:, :nb], W, 0.3, seed=seed + 2, stream=1)
+    return h1, L, C_a, C_b, coeff, rank, orbs, pa, pb
+
+
+def _energy_compare(e, ref, canc, rtol=1e-11):
+    S = np.abs(ref).sum(axis=1)
+    err = np.abs(e - ref).max(axis=1)
+    print(f"[gpu] msd local energy: max |dE| {err.max():.3e} Ha = {(err / S).max():.2e} of S "
+          f"(S up to {S.max():.3e} Ha), cancellation {canc.max():.2f}", flush=True)
+    assert np.all(err <= rtol * canc * S), (err / S / canc).max()
+
+
+@pytest.mark.parametrize("N,na,nb,K,ndet,max_rank,W,uhf,active", ENERGY_CASES)
+def test_msd_local_energy_matches_oracle(N, na, nb, K, ndet, max_rank, W, uhf, active):
+    from paper_2209_04015_amd import afqmc
+
+    print(f"[gpu] msd local energy N={N} na={na} nb={nb} K={K} ndet={ndet} W={W} active={active}", flush=True)
+    h1, L, C_a, C_b, coeff, rank, orbs, pa, pb = _energy_problem(N, na, nb, K, ndet, max_rank, W, uhf, active)
+    t = afqmc.MSDTrial(C_a, C_b, na, nb, coeff, rank, orbs, max_walkers=W)
+    t.set_hamiltonian(h1, L)
+    w = afqmc.Walkers.from_numpy(pa, pb, device="cuda")
+    e = t.local_energy(w).cpu().numpy()
+    assert t.status() == 0
+    msd = orc.msd_setup(C_a, C_b, na, nb, coeff, rank, orbs)
+    ref = orc.msd_local_energy(msd, h1, L, pa, pb)
+    _energy_compare(e, ref, _cancellation(msd, pa, pb))
+    # a prefix of the walkers gives the same values (passes of a few walkers)
+    e5 = t.local_energy(w, nw=min(5, W)).cpu().numpy()
+    assert np.array_equal(e5, e[:min(5, W)])
+    t.close()
+
+
+def test_msd_local_energy_without_beta_electrons():
+    from paper_2209_04015_amd import afqmc
+
+    N, na, nb, K, W = 15, 4, 0, 8, 6
+    h1, L, C_a, C_b, coeff, rank, orbs, pa, pb = _energy_problem(N, na, nb, K, 30, 3, W, True, None)
+    print("[gpu] msd local energy nb=0", flush=True)
+    t = afqmc.MSDTrial(C_a, C_b, na, nb, coeff, rank, orbs, max_walkers=W)
+    t.set_hamiltonian(h1, L)
+    e = t.local_energy(afqmc.Walkers.from_numpy(pa, pb, device="cuda")).cpu().numpy()
+    msd = orc.msd_setup(C_a, C_b, na, nb, coeff, rank, orbs)
+    _energy_compare(e, orc.msd_local_energy(msd, h1, L, pa, pb), _cancellation(msd, pa, pb))
+    t.close()
+
+
+def test_msd_local_energy_single_reference_is_the_single_determinant_energy():
+    from paper_2209_04015_amd import afqmc
+
+    N, na, nb, K, W = 24, 6, 5, 20, 9
+    h1, L, C_a, C_b, _, _, _, pa, pb = _energy_problem(N, na, nb, K, 2, 1, W, True, None)
+    rank = np.zeros((1, 2), np.int32)
+    orbs = np.full((1, 2, 2, inputs.MSD_MAX_RANK), -1, np.int32)
+    print("[gpu] msd local energy, single reference", flush=True)
+    t = afqmc.MSDTrial(C_a, C_b, na, nb, np.array([1.0]), rank, orbs, max_walkers=W)
+    t.set_hamiltonian(h1, L)
+    e = t.local_energy(afqmc.Walkers.from_numpy(pa, pb, device="cuda")).cpu().numpy()
+    oh = orc.setup(h1, L, C_a[:, :na], C_b[:, :nb])
+    ref = orc.local_energy(oh, pa, pb)
+    _energy_compare(e, ref, np.ones(W))
+    t.close()
+
+
+def test_msd_local_energy_refuses_a_large_excitation_space():
+    from paper_2209_04015_amd import afqmc
+
+    N, na, nb = 120, 30, 30
+    h1, L = inputs.hamiltonian(N, 4, 3.0, seed=0)
+    C = inputs.orbitals(h1)
+    coeff, rank, orbs = inputs.msd_expansion(N, na, nb, 3000, max_rank=3, seed=2)
+    t = afqmc.MSDTrial(C, C, na, nb, coeff, rank, orbs, max_walkers=2)
+    with pytest.raises(afqmc.AfqmcError, match="1024"):
+        t.set_hamiltonian(h1, L)
+    w = afqmc.Walkers.from_numpy(C[None, :, :na].astype(complex), C[None, :, :nb].astype(complex), device="cuda")
+    with pytest.raises(afqmc.AfqmcError, match="no Hamiltonian"):
+        t.local_energy(w)
+    t.close()
+
+
+def test_msd_local_energy_at_n290_sampled():
+    """The n290 shape (N = 290, 26 + 26 electrons, K = 2900) with an expansion
+    in a (32e, 32o) active space, 512 walkers in one call, two of them
+    against the oracle (whose cost is one full half-rotation of L per
+    determinant, so the expansion is kept to 12 determinants here)."""
+    from paper_2209_04015_amd import afqmc
+
+    cfg = inputs.CONFIGS["n290"]
+    h1, L = inputs.hamiltonian(cfg.N, cfg.K, cfg.decay, seed=0)
+    C = inputs.orbitals(h1)
+    coeff, rank, orbs = inputs.msd_expansion(cfg.N, cfg.n, cfg.n, 12, max_rank=3, seed=5, active=(16, 16))
+    pa = inputs.walkers_perturbed(C[:, :cfg.n], cfg.W, 0.2, seed=6, stream=0)
+    pb = inputs.walkers_perturbed(C[:, :cfg.n], cfg.W, 0.2, seed=6, stream=1)
+    print("[gpu] msd local energy n290 (512 walkers, 12 determinants)", flush=True)
+    t = afqmc.MSDTrial(C, C, cfg.n, cfg.n, coeff, rank, orbs, max_walkers=cfg.W)
+    t.set_hamiltonian(h1, L)
+    e = t.local_energy(afqmc.Walkers.from_numpy(pa, pb, device="cuda")).cpu().numpy()
+    assert t.status() == 0
+    s = np.array([0, 511])
+    msd = orc.msd_setup(C, C, cfg.n, cfg.n, coeff, rank, orbs)
+    ref = orc.msd_local_energy(msd, h1, L, pa[s], pb[s])
+    _energy_compare(e[s], ref, _cancellation(msd, pa[s], pb[s]))
+    t.close()
