@@ -176,12 +176,26 @@ def msd_flops_per_walker(N, n):
     return 2 * (4 * N * nv * n + 8 * n * n * nv + 4 * N * n * (n + nv) + 8 * N * N * n)
 
 
+MSD_ACTIVE = (16, 16)   # holes, particles per spin: the (32e, 32o) active space of the Cu2O2 trials (Sec. IV)
+MSD_BLOCK_STEPS = 25    # propagation steps per energy evaluation in the paper's block timings (Sec. IV)
+
+
+def msd_energy_flops_per_walker(N, n, K, S, D):
+    """Algorithmic FP64 flops per walker of the expansion's local energy on
+    the matrix cores: the rotated vectors against theta_0 (S rows of each of
+    K + 1 blocks by 2n real columns over N, per spin) and the three Gram
+    matrices (D x D over the 2K real Cholesky components)."""
+    return 2 * (2 * (K + 1) * S * 2 * n * N) + 3 * 8 * D * D * K
+
+
 def run_msd(cfg, h1, L, device, steps, ndet=MSD_DETS):
     """Multi-determinant trial (Sec. III.A): overlap, Green's function and
     force bias of every walker against a synthetic ndet-determinant expansion
-    in the eigenvector basis of the workload's h1, timed over `steps` calls
-    each on the current stream.  The force bias contracts with the packed L
-    of an FP64 Hamiltonian of the same workload."""
+    in a (16 holes, 16 particles per spin) active window of the eigenvector
+    basis of the workload's h1, timed over `steps` calls each on the current
+    stream; the expansion's local energy (Sec. III.C), and one block of 25
+    steps with the energy at its end.  The force bias contracts with the
+    packed L of an FP64 Hamiltonian of the same workload."""
     import torch
 
     from paper_2209_04015_amd import afqmc, inputs
@@ -189,7 +203,7 @@ def run_msd(cfg, h1, L, device, steps, ndet=MSD_DETS):
     N, n, W, K = cfg.N, cfg.n, cfg.W, cfg.K
     t = time.time()
     C = inputs.orbitals(h1)
-    coeff, rank, orbs = inputs.msd_expansion(N, n, n, ndet, max_rank=4, seed=5)
+    coeff, rank, orbs = inputs.msd_expansion(N, n, n, ndet, max_rank=4, seed=5, active=MSD_ACTIVE)
     pa = inputs.walkers_perturbed(C[:, :n], W, 0.1, seed=6, stream=0)
     pb = inputs.walkers_perturbed(C[:, :n], W, 0.1, seed=6, stream=1)
     trial = afqmc.MSDTrial(C, C, n, n, coeff, rank, orbs, max_walkers=W)
@@ -239,17 +253,47 @@ def run_msd(cfg, h1, L, device, steps, ndet=MSD_DETS):
         ham32.orthogonalise(w)
 
     ms_s32 = timed(step32)
+    # the expansion's local energy (FP64), then one block: 25 steps on the
+    # FP32 path and the energy at its end
+    t = time.time()
+    trial.set_hamiltonian(h1, L)
+    log(f"msd: local energy set up in {time.time() - t:.1f} s")
+    E = torch.empty((W, 3), dtype=torch.complex128, device=device)
+    esteps = max(1, min(steps, 5))
+    trial.local_energy(w, out=E)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(esteps):
+        trial.local_energy(w, out=E)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_e = start.elapsed_time(stop) / esteps
+    e_finite = bool(torch.isfinite(torch.view_as_real(E)).all())
+    start.record(stream)
+    for _ in range(MSD_BLOCK_STEPS):
+        step32()
+    trial.local_energy(w, out=E)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_block = start.elapsed_time(stop)
     status |= trial.status() | ham32.status()
     ham32.close()
     trial.close()
+    del E
     torch.cuda.empty_cache()
+    S = n + MSD_ACTIVE[1]
+    D = MSD_ACTIVE[0] * MSD_ACTIVE[1]
+    e_gflop = W * msd_energy_flops_per_walker(N, n, K, S, D) / 1e9
     log(f"msd: overlap {ms_o:.3f} ms, Green's function {ms_g:.3f} ms, force bias {ms_f:.3f} ms per call, "
-        f"step {ms_s:.3f} ms (FP32 path {ms_s32:.3f} ms), status {status}")
+        f"step {ms_s:.3f} ms (FP32 path {ms_s32:.3f} ms), local energy {ms_e:.3f} ms "
+        f"({e_gflop / ms_e:.1f} TFLOP/s on the dense parts), block of {MSD_BLOCK_STEPS} steps + energy "
+        f"{ms_block:.1f} ms, status {status}")
     gbytes = W * 2 * N * N * 16
     npk = N * (N + 1) // 2
-    return {"workload": f"multi-determinant trial: {ndet} determinants (ranks <= 4 per spin) in the eigenvector "
-                        f"basis of the {cfg.name} h1, {N} orbitals, na=nb={n}, {W} walkers, K={K} for the force "
-                        f"bias, FP64",
+    return {"workload": f"multi-determinant trial: {ndet} determinants (ranks <= 4 per spin) in a "
+                        f"({2 * MSD_ACTIVE[0]}e, {MSD_ACTIVE[0] + MSD_ACTIVE[1]}o) active space "
+                        f"({MSD_ACTIVE[0]} holes, {MSD_ACTIVE[1]} particles per spin) of the eigenvector "
+                        f"basis of the {cfg.name} h1, {N} orbitals, na=nb={n}, {W} walkers, K={K}, FP64",
             "determinants": ndet, "strings_per_spin": list(trial.strings), "walkers": W,
             "overlap": {"value": round(W * ndet / (ms_o * 1e-3), 1), "unit": "walker-determinants/s",
                         "ms_per_call": round(ms_o, 4)},
@@ -268,6 +312,17 @@ def run_msd(cfg, h1, L, device, steps, ndet=MSD_DETS):
             "step_fp32": {"value": round(W / (ms_s32 * 1e-3), 1), "unit": "walker-steps/s",
                           "ms_per_step": round(ms_s32, 4),
                           "definition": "the same on the FP32 path (FP32 packed L, VHS and Taylor products)"},
+            "local_energy": {"value": round(W / (ms_e * 1e-3), 1), "unit": "walkers/s",
+                             "ms_per_call": round(ms_e, 3), "finite": e_finite,
+                             "dense_fp64_gflop": round(e_gflop, 1),
+                             "dense_fp64_tflops": round(e_gflop / ms_e, 2),
+                             "definition": "afqmc_msd_local_energy: E1, EJ, EK of every walker against the "
+                                           "whole expansion (generalised Wick, Gram matrices over the "
+                                           "Cholesky index), FP64"},
+            "block": {"ms_per_block": round(ms_block, 2),
+                      "value": round(W * MSD_BLOCK_STEPS / (ms_block * 1e-3), 1), "unit": "walker-steps/s",
+                      "definition": f"{MSD_BLOCK_STEPS} steps on the FP32 path (afqmc_msd_propagate + QR) and "
+                                    "the expansion's local energy at the end"},
             "status": status}
 
 
