@@ -28,10 +28,14 @@
 // g sum does not grow with the number of determinants.  The one-body part
 // is the same linear form with h1 in place of L_g (block g = K).
 //
-// Numbers are FP64 throughout.  A determinant whose overlap with the walker
-// is exactly zero has no local energy of its own (the definition divides by
-// it); its quadratic terms are left out (its linear terms, weighted by the
-// adjugate, are exact).
+// Numbers are FP64 throughout.  Where a string's determinant d_u is exactly
+// zero (a walker exactly at the reference, say: Y = 0), its Coulomb and
+// exchange quadratic terms diverge separately but their sum stays finite:
+// with F = adj A, ((tr F R)^2 - tr (F R)^2) / d = 2 [t^2] det(A + t R), and
+// the t^2 coefficient expands over pairs of columns (Laplace) into the
+// complementary minors of A times 2 x 2 minors of R, whose sum over g is a
+// difference of two Gram entries.  That sum is added to EJ for such a
+// string (the split between EJ and EK is not defined there).
 
 #include "common.h"
 #include "kernels.h"
@@ -359,11 +363,86 @@ struct MsdContractArgs {
   const double2* vp;    // [Wc][2][Dmax]
   const double2* r1;    // [Wc][2][Dmax]
   const double2* sc;    // [Wc][4]
+  const double* yp;     // planar Y [W][2][2][nmax][ldv] (zero-determinant strings)
+  const int* hlist;     // [2][Hmax]
+  const int* qlist;     // [2][Qmax]
   double2* e;           // [W][3]
-  int z0, nstr0, nstr_tot, nadj_tot, ncross, Dmax, nh[2];
+  int z0, nstr0, nstr_tot, nadj_tot, ncross, Dmax, nh[2], nmax, ldv, Hmax, Qmax;
 };
 
 __device__ __forceinline__ double2 cdivs(double2 a, double2 b) { return cmul(a, cinv(b)); }
+
+// determinant of the leading n x n block of M (n <= KM; M is overwritten),
+// elimination with partial pivoting
+__device__ double2 small_det(double2 (&M)[KM][KM], int n) {
+  double2 det = make_double2(1.0, 0.0);
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    double best = cabs2(M[c][c]);
+    for (int r = c + 1; r < n; ++r) {
+      const double v = cabs2(M[r][c]);
+      if (v > best) {
+        best = v;
+        p = r;
+      }
+    }
+    if (best == 0.0) return make_double2(0.0, 0.0);
+    if (p != c) {
+      for (int j = 0; j < n; ++j) {
+        const double2 t = M[c][j];
+        M[c][j] = M[p][j];
+        M[p][j] = t;
+      }
+      det = make_double2(-det.x, -det.y);
+    }
+    det = cmul(det, M[c][c]);
+    const double2 ip = cinv(M[c][c]);
+    for (int r = c + 1; r < n; ++r) {
+      const double2 f = cmul(M[r][c], ip);
+      for (int j = c + 1; j < n; ++j) M[r][j] = csub(M[r][j], cmul(f, M[c][j]));
+    }
+  }
+  return det;
+}
+
+// sum_g [t^2] det(A + t R_g) for the string u of spin s (A = its Y block):
+// sum over row pairs l1 < l2 and column pairs m1 < m2 of the signed
+// complementary minor of A times sum_g det R_g[{l1, l2}][{m1, m2}]
+__device__ double2 zero_det_quadratic(const MsdContractArgs& a, int u, int s, int k, int z, const int (&dix)[KM][KM],
+                                      const double2* Gs) {
+  double2 A[KM][KM];
+  const size_t yplane = (size_t)a.nmax * a.ldv;
+  const double* yr = a.yp + ((size_t)(2 * z + 0) * 2 + s) * yplane;
+  const double* yi = a.yp + ((size_t)(2 * z + 1) * 2 + s) * yplane;
+  for (int l = 0; l < k; ++l) {
+    const int av = a.qlist[s * a.Qmax + a.spos[((size_t)u * 2 + 1) * KM + l]];
+    for (int m = 0; m < k; ++m) {
+      const int h = a.hlist[s * a.Hmax + a.spos[((size_t)u * 2 + 0) * KM + m]];
+      A[l][m] = make_double2(yr[(size_t)h * a.ldv + av], yi[(size_t)h * a.ldv + av]);
+    }
+  }
+  double2 q2 = make_double2(0.0, 0.0);
+  for (int l1 = 0; l1 < k; ++l1)
+    for (int l2 = l1 + 1; l2 < k; ++l2)
+      for (int m1 = 0; m1 < k; ++m1)
+        for (int m2 = m1 + 1; m2 < k; ++m2) {
+          double2 M[KM][KM];
+          for (int r = 0, rr = 0; r < k; ++r) {
+            if (r == l1 || r == l2) continue;
+            for (int c = 0, cc = 0; c < k; ++c) {
+              if (c == m1 || c == m2) continue;
+              M[rr][cc++] = A[r][c];
+            }
+            ++rr;
+          }
+          double2 mn = small_det(M, k - 2);
+          if ((l1 + l2 + m1 + m2) & 1) mn = make_double2(-mn.x, -mn.y);
+          const double2 g2 = csub(Gs[(size_t)dix[l1][m1] * a.Dmax + dix[l2][m2]],
+                                  Gs[(size_t)dix[l1][m2] * a.Dmax + dix[l2][m1]]);
+          q2 = cadd(q2, cmul(mn, g2));
+        }
+  return q2;
+}
 
 __global__ __launch_bounds__(CT_T) void msd_contract_kernel(MsdContractArgs a) {
   __shared__ double2 red[CT_T / 64];
@@ -409,6 +488,8 @@ __global__ __launch_bounds__(CT_T) void msd_contract_kernel(MsdContractArgs a) {
       const double2 f = cdivs(w, dd);
       ej = cadd(ej, cscale(cmul(f, qj), 0.5));
       ek = csub(ek, cscale(cmul(f, qk), 0.5));
+    } else if (k >= 2) {
+      ej = cadd(ej, cmul(w, zero_det_quadratic(a, u, s, k, z, dix, Gs)));
     }
   }
   const double2* Gab = a.G + ((size_t)zl * 3 + 2) * a.Dmax * a.Dmax;
@@ -561,6 +642,13 @@ hipError_t launch_msd_energy_chunk(const MsdDims& m, const MsdEnergyDims& e, con
     a.Dmax = e.Dmax;
     a.nh[0] = e.nh[0];
     a.nh[1] = e.nh[1];
+    a.yp = yp;
+    a.hlist = t.hlist;
+    a.qlist = t.qlist;
+    a.nmax = m.nmax;
+    a.ldv = m.ldv;
+    a.Hmax = e.Hmax;
+    a.Qmax = e.Qmax;
     hipLaunchKernelGGL(msd_contract_kernel, dim3(nz), dim3(CT_T), 0, s, a);
     if ((err = hipGetLastError()) != hipSuccess) return err;
   }

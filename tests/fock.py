@@ -118,3 +118,40 @@ class FockSpace:
 
     def expm_one_body(self, A, v):
         return scipy.linalg.expm(self.one_body_matrix(A)) @ v
+
+
+# ---------------------------------------------------------------------------
+# Multi-determinant trials built from excitation operators
+# ---------------------------------------------------------------------------
+
+def _mo_cre(fs, C, off, x, v):
+    """a+ of orbital x (column x of C) on the Fock vector v."""
+    out = np.zeros_like(v)
+    for p in range(C.shape[0]):
+        if C[p, x] != 0:
+            out = out + C[p, x] * fs.cre(off + p, v)
+    return out
+
+
+def _mo_ann(fs, C, off, x, v):
+    out = np.zeros_like(v)
+    for p in range(C.shape[0]):
+        if C[p, x] != 0:
+            out = out + C[p, x] * fs.ann(off + p, v)
+    return out
+
+
+def excitation_trial(fs, C, nel, coeff, exc):
+    """sum_a c_a t_a |psi_0>, t_a = prod_s prod_m a+_{s,q_m} a_{s,h_m} applied in
+    Fock space; psi_0 per spin is the first nel[s] columns of C[s], and exc[a]
+    holds per spin the (holes, particles) orbital indices of determinant a."""
+    N = fs.N
+    psi0 = fs.determinant(C[0][:, :nel[0]], C[1][:, :nel[1]])
+    out = np.zeros_like(psi0)
+    for ca, spins in zip(coeff, exc):
+        v = psi0
+        for s, (holes, parts) in enumerate(spins):
+            for h, q in zip(holes, parts):
+                v = _mo_cre(fs, C[s], s * N, q, _mo_ann(fs, C[s], s * N, h, v))
+        out = out + ca * v
+    return out

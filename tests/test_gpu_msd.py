@@ -579,3 +579,52 @@ def test_msd_local_energy_at_n290_sampled():
     ref = orc.msd_local_energy(msd, h1, L, pa[s], pb[s])
     _energy_compare(e[s], ref, _cancellation(msd, pa[s], pb[s]))
     t.close()
+
+
+@pytest.mark.parametrize("N,na,nb,ndet,max_rank", [(6, 3, 2, 24, 3), (8, 4, 3, 40, 4)])
+def test_msd_local_energy_with_walkers_at_the_reference(N, na, nb, ndet, max_rank):
+    """Walkers whose virtual rows are exactly zero in the orbital basis (C = I,
+    phi = psi_0 R): Y = 0, so every excited string's determinant is exactly
+    zero and the doubles enter only through the zero-determinant form of the
+    quadratic terms.  Compared with <Psi_T|H|phi> / <Psi_T|phi> in Fock space
+    (H written literally, the trial built from the excitation operators), the
+    total and the one-body part; EJ and EK are not separately defined there."""
+    from fock import FockSpace, excitation_trial
+
+    from paper_2209_04015_amd import afqmc
+
+    K = 4
+    h1, L = inputs.hamiltonian(N, K, 3.0, seed=31)
+    C = np.eye(N)
+    coeff, rank, orbs = inputs.msd_expansion(N, na, nb, ndet, max_rank=max_rank, seed=32)
+    assert rank.max() == max_rank
+    msd = orc.msd_setup(C, C, na, nb, coeff, rank, orbs)
+    rng = np.random.default_rng(33)
+    pert_a = inputs.walkers_perturbed(C[:, :na], 1, 0.3, seed=34, stream=0)[0]
+    pert_b = inputs.walkers_perturbed(C[:, :nb], 1, 0.3, seed=34, stream=1)[0]
+    ref_a, ref_b = C[:, :na].astype(complex), C[:, :nb].astype(complex)
+    mix_a = ref_a @ (rng.normal(size=(na, na)) + 1j * rng.normal(size=(na, na)) + 3 * np.eye(na))
+    mix_b = ref_b @ (rng.normal(size=(nb, nb)) + 1j * rng.normal(size=(nb, nb)) + 3 * np.eye(nb))
+    pa = np.stack([ref_a, ref_a, pert_a, mix_a, pert_a])
+    pb = np.stack([ref_b, pert_b, ref_b, mix_b, pert_b])
+    print(f"[gpu] msd local energy at the reference N={N} na={na} nb={nb} ranks<={max_rank}", flush=True)
+    t = afqmc.MSDTrial(C, C, na, nb, coeff, rank, orbs, max_walkers=pa.shape[0])
+    t.set_hamiltonian(h1, L)
+    e = t.local_energy(afqmc.Walkers.from_numpy(pa, pb, device="cuda")).cpu().numpy()
+    assert t.status() == 0
+    fs = FockSpace(N)
+    psiT = excitation_trial(fs, msd.C, msd.nel, msd.coeff, msd.exc)
+    for z in range(pa.shape[0]):
+        v = fs.determinant(pa[z], pb[z])
+        ov = np.vdot(psiT, v)
+        ref = np.vdot(psiT, fs.hamiltonian(h1, L, v)) / ov
+        ref1 = np.vdot(psiT, fs.one_body(h1, v)) / ov
+        S = np.abs(e[z]).sum() + abs(ref)
+        print(f"[gpu]   walker {z}: |dE| {abs(e[z].sum() - ref):.2e}, |dE1| {abs(e[z, 0] - ref1):.2e} (S {S:.2e})",
+              flush=True)
+        assert abs(e[z].sum() - ref) <= 1e-12 * S
+        assert abs(e[z, 0] - ref1) <= 1e-12 * S
+    # the generic walker also matches the oracle part by part
+    ref = orc.msd_local_energy(msd, h1, L, pa[4:], pb[4:])
+    _energy_compare(e[4:], ref, _cancellation(msd, pa[4:], pb[4:]))
+    t.close()

@@ -21,7 +21,7 @@ import scipy.linalg
 
 from oracle import afqmc_oracle as orc
 from paper_2209_04015_amd import inputs
-from fock import FockSpace
+from fock import FockSpace, excitation_trial
 
 
 def _orbitals(N, K=4, seed=3):
@@ -35,35 +35,8 @@ def _walkers(C, n, W, seed, stream, scale=0.5):
     return inputs.walkers_perturbed(C[:, :n], W, scale, seed=seed, stream=stream)
 
 
-def _mo_cre(fs, C, off, x, v):
-    """a+ of orbital x (column x of C) on the Fock vector v."""
-    out = np.zeros_like(v)
-    for p in range(C.shape[0]):
-        if C[p, x] != 0:
-            out = out + C[p, x] * fs.cre(off + p, v)
-    return out
-
-
-def _mo_ann(fs, C, off, x, v):
-    out = np.zeros_like(v)
-    for p in range(C.shape[0]):
-        if C[p, x] != 0:
-            out = out + C[p, x] * fs.ann(off + p, v)
-    return out
-
-
 def _fock_trial(fs, msd):
-    """sum_a c_a t_a |psi_0>, t_a = prod_s prod_m a+_{s,q_m} a_{s,h_m} applied in Fock space."""
-    N = fs.N
-    psi0 = fs.determinant(msd.C[0][:, :msd.nel[0]], msd.C[1][:, :msd.nel[1]])
-    out = np.zeros_like(psi0)
-    for ca, spins in zip(msd.coeff, msd.exc):
-        v = psi0
-        for s, (holes, parts) in enumerate(spins):
-            for h, q in zip(holes, parts):
-                v = _mo_cre(fs, msd.C[s], s * N, q, _mo_ann(fs, msd.C[s], s * N, h, v))
-        out = out + ca * v
-    return out
+    return excitation_trial(fs, msd.C, msd.nel, msd.coeff, msd.exc)
 
 
 @pytest.mark.parametrize("na,nb,ndet,seed", [(2, 1, 9, 1), (2, 2, 12, 2), (1, 3, 7, 3)])
