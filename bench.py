@@ -253,8 +253,22 @@ def run_msd(cfg, h1, L, device, steps, ndet=MSD_DETS):
         ham32.orthogonalise(w)
 
     ms_s32 = timed(step32)
+    status |= trial.status() | ham32.status()
+    ham32.close()
+    torch.cuda.empty_cache()
+    # the FP16X3 path (split force bias against the transposed split L, split
+    # VHS build, the fused propagation)
+    ham16 = afqmc.Hamiltonian(h1, L, C[:, :n], C[:, :n], dt=cfg.dt, max_walkers=W, precision="fp16x3")
+    ms_f16 = timed(lambda: trial.force_bias(ham16, w, out=vb))
+    trial.overlap(w, out=w.log_ovlp)
+
+    def step16():
+        trial.propagate(ham16, w, x)
+        ham16.orthogonalise(w)
+
+    ms_s16 = timed(step16)
     # the expansion's local energy (FP64), then one block: 25 steps on the
-    # FP32 path and the energy at its end
+    # FP16X3 path and the energy at its end
     t = time.time()
     trial.set_hamiltonian(h1, L)
     log(f"msd: local energy set up in {time.time() - t:.1f} s")
@@ -271,13 +285,13 @@ def run_msd(cfg, h1, L, device, steps, ndet=MSD_DETS):
     e_finite = bool(torch.isfinite(torch.view_as_real(E)).all())
     start.record(stream)
     for _ in range(MSD_BLOCK_STEPS):
-        step32()
+        step16()
     trial.local_energy(w, out=E)
     stop.record(stream)
     torch.cuda.synchronize()
     ms_block = start.elapsed_time(stop)
-    status |= trial.status() | ham32.status()
-    ham32.close()
+    status |= trial.status() | ham16.status()
+    ham16.close()
     trial.close()
     del E
     torch.cuda.empty_cache()
@@ -285,7 +299,8 @@ def run_msd(cfg, h1, L, device, steps, ndet=MSD_DETS):
     D = MSD_ACTIVE[0] * MSD_ACTIVE[1]
     e_gflop = W * msd_energy_flops_per_walker(N, n, K, S, D) / 1e9
     log(f"msd: overlap {ms_o:.3f} ms, Green's function {ms_g:.3f} ms, force bias {ms_f:.3f} ms per call, "
-        f"step {ms_s:.3f} ms (FP32 path {ms_s32:.3f} ms), local energy {ms_e:.3f} ms "
+        f"step {ms_s:.3f} ms (FP32 path {ms_s32:.3f} ms; FP16X3 force bias {ms_f16:.3f} ms, step {ms_s16:.3f} ms), "
+        f"local energy {ms_e:.3f} ms "
         f"({e_gflop / ms_e:.1f} TFLOP/s on the dense parts), block of {MSD_BLOCK_STEPS} steps + energy "
         f"{ms_block:.1f} ms, status {status}")
     gbytes = W * 2 * N * N * 16
@@ -312,6 +327,13 @@ def run_msd(cfg, h1, L, device, steps, ndet=MSD_DETS):
             "step_fp32": {"value": round(W / (ms_s32 * 1e-3), 1), "unit": "walker-steps/s",
                           "ms_per_step": round(ms_s32, 4),
                           "definition": "the same on the FP32 path (FP32 packed L, VHS and Taylor products)"},
+            "force_bias_fp16x3": {"value": round(W / (ms_f16 * 1e-3), 1), "unit": "walkers/s",
+                                  "ms_per_call": round(ms_f16, 4),
+                                  "split_tflops": round(2 * 2 * W * npk * K / 1e9 / ms_f16, 1)},
+            "step_fp16x3": {"value": round(W / (ms_s16 * 1e-3), 1), "unit": "walker-steps/s",
+                            "ms_per_step": round(ms_s16, 4),
+                            "definition": "the same on the FP16X3 path (split force bias against the transposed "
+                                          "split L, split VHS build, fused propagation)"},
             "local_energy": {"value": round(W / (ms_e * 1e-3), 1), "unit": "walkers/s",
                              "ms_per_call": round(ms_e, 3), "finite": e_finite,
                              "dense_fp64_gflop": round(e_gflop, 1),
@@ -321,7 +343,7 @@ def run_msd(cfg, h1, L, device, steps, ndet=MSD_DETS):
                                            "Cholesky index), FP64"},
             "block": {"ms_per_block": round(ms_block, 2),
                       "value": round(W * MSD_BLOCK_STEPS / (ms_block * 1e-3), 1), "unit": "walker-steps/s",
-                      "definition": f"{MSD_BLOCK_STEPS} steps on the FP32 path (afqmc_msd_propagate + QR) and "
+                      "definition": f"{MSD_BLOCK_STEPS} steps on the FP16X3 path (afqmc_msd_propagate + QR) and "
                                     "the expansion's local energy at the end"},
             "status": status}
 

@@ -138,7 +138,9 @@ typedef struct afqmc_ham afqmc_ham;
  *   host_phiT_b [N][nb]     trial orbitals of spin beta (may equal host_phiT_a)
  * Computes h' = h1 - 1/2 sum_g L_g L_g, mu, P = exp(-dt (h' - mu) / 2),
  * the half-rotated vectors Lh^s_g = PhiT_s^T L_g (Sec. III.B), PhiT_s^T h1,
- * the packed L used by the VHS build, and E_T.  Allocates the workspace.
+ * the packed L used by the VHS build (FP16X3 also keeps it transposed and
+ * split per Cholesky vector, for afqmc_msd_force_bias), and E_T.  Allocates
+ * the workspace.
  * On success *out owns device memory until afqmc_destroy. */
 int afqmc_init_hamiltonian(const afqmc_params* params, const double* host_h1,
                            const double* host_chol, const double* host_phiT_a,
@@ -415,13 +417,18 @@ int afqmc_msd_green_function(afqmc_msd* t, const afqmc_walkers* w, int nw, void*
 /* Force bias of the multi-determinant trial (Eq. fb with the G above):
  *   vbias[z][g] = sum_s sum_pq G^s_pq L_g,pq,
  * formed from the packed symmetric sum_s (G^s + G^s^T) and the packed L of
- * `ham` without storing G.  ham: an FP64, FP32 or BF16X3 Hamiltonian with
- * the same N (its packed L: FP64, or FP32 with the packed G rounded to FP32
- * and FP32 accumulation on the matrix cores; FP16X3 keeps no FP32 packed L:
- * AFQMC_EUNSUPPORTED); nw <= both handles' max_walkers.  vbias:
- * device complex [nw][K], written.  The call uses ham's VHS workspace as
- * scratch: it must not overlap a call on the same Hamiltonian (the next
- * afqmc_step recomputes that workspace).  Asynchronous on `stream`. */
+ * `ham` without storing G.  ham: a Hamiltonian of any precision with the
+ * same N: FP64 contracts with its FP64 packed L; FP32 and BF16X3 round the
+ * packed G to FP32 and contract with the FP32 packed L on the FP32 matrix
+ * cores; FP16X3 splits the packed G (one power-of-two scale per walker and
+ * component) and contracts it with the packed L transposed, kept split per
+ * Cholesky vector since init, on the fp16 matrix cores (three products,
+ * FP32 accumulation).  A Hamiltonian of another N, or nw above either
+ * handle's max_walkers: AFQMC_EINVAL.  vbias: device complex [nw][K],
+ * written.  The call uses ham's VHS workspace (and, in FP16X3, its
+ * force-bias partial sums) as scratch: it must not overlap a call on the
+ * same Hamiltonian (the next afqmc_step recomputes both).  Asynchronous on
+ * `stream`. */
 int afqmc_msd_force_bias(afqmc_msd* t, afqmc_ham* ham, const afqmc_walkers* w, int nw, void* vbias, void* stream);
 
 /* One phaseless step under the multi-determinant trial (Sec. II.B with the
@@ -431,8 +438,8 @@ int afqmc_msd_force_bias(afqmc_msd* t, afqmc_ham* ham, const afqmc_walkers* w, i
  *   ln O_z = log <Psi_T|phi'_z> - w->log_ovlp[z] from the expansion.
  * w->phi_a, w->phi_b, w->log_ovlp (must hold log <Psi_T|phi> of the
  * expansion, e.g. from afqmc_msd_overlap) and w->log_w are updated in place.
- * fields: device [nw][K].  ham: FP64, FP32 or BF16X3 (its working precision
- * for the force bias, VHS and Taylor products), with the trial's N, na and nb (its own
+ * fields: device [nw][K].  ham: any precision (its working precision for
+ * the force bias, VHS and propagation), with the trial's N, na and nb (its own
  * trial orbitals are not used here except through its energy shift, a
  * constant per step); ham's VHS and force-bias workspaces are used, so the
  * call must not overlap another call on ham.  afqmc_orthogonalise(ham, ...)

@@ -92,6 +92,9 @@ struct afqmc_ham {
   unsigned short* th_split = nullptr;  // [W][2][2][nmax][2 ldh]
   unsigned short* lt_split = nullptr;  // [nvblk * 160][2 ldhK] split L in VHS block order
   float* lt_unscale = nullptr;         // [nvblk * 160]
+  unsigned short* lt_t_split = nullptr;  // [K][2 ldhp] packed L transposed, split (multi-determinant force bias)
+  float* lt_t_unscale = nullptr;         // [K]
+  int ldhp = 0;                          // pair-index row length: round_up(N (N + 1) / 2, 32)
   int2* vblk = nullptr;                // [nvblk] VHS blocks (P, Q)
   int nvblk = 0;
   unsigned short* xs_split = nullptr;  // [W][2][2 ldhK]
@@ -452,6 +455,11 @@ int build_working_arrays(afqmc_ham* h, const double* dL, const double* Y_a, cons
   if ((rc = dalloc_t(h, &h->fb_lh_unscale, (size_t)d.K))) return rc;
   HIP_TRY(launch_split_blocks_mode(h->split, d.K, 2, d.nmax, d.N, (const float*)h->Lh, d.ldN,
                                    (long)d.K * d.nmax, d.nmax, h->fb_lh, d.ldh, h->fb_lh_unscale, s));
+  // multi-determinant force bias: the packed L transposed, one split row per g
+  h->ldhp = round_up(d.Npk, 32);
+  if ((rc = dalloc_t(h, &h->lt_t_split, (size_t)d.K * 2 * h->ldhp))) return rc;
+  if ((rc = dalloc_t(h, &h->lt_t_unscale, (size_t)d.K))) return rc;
+  HIP_TRY(setup_split_lt_transposed(h->split, d.K, d.N, d.Npk, h->ldhp, h->pq, dL, h->lt_t_split, h->lt_t_unscale, s));
   return AFQMC_OK;
 }
 
@@ -1482,16 +1490,21 @@ int msd_ratio(afqmc_msd* t, const afqmc_walkers* w, int nw, bool want_adj, hipSt
 // checks shared by the calls that combine the trial with a Hamiltonian
 int msd_check_ham(const afqmc_msd* t, const afqmc_ham* h, int nw, int* nsplit, int* ldpk) {
   if (!h) return fail(AFQMC_EINVAL, "null Hamiltonian handle");
-  if (h->prec != AFQMC_FP64 && h->prec != AFQMC_FP32 && h->prec != AFQMC_BF16X3)
-    return fail(AFQMC_EUNSUPPORTED,
-                "the multi-determinant force bias needs the packed L of an FP64, FP32 or BF16X3 Hamiltonian");
   if (h->d.N != t->m.N) return fail(AFQMC_EINVAL, "orbital counts differ (%d, %d)", h->d.N, t->m.N);
   if (nw > h->prm.max_walkers)
     return fail(AFQMC_EINVAL, "nw = %d above the Hamiltonian's max_walkers = %d", nw, h->prm.max_walkers);
   const int npk = t->m.N * (t->m.N + 1) / 2;
-  *ldpk = (npk + 15) / 16 * 16;
   // scratch: the Hamiltonian's VHS workspace, idle outside its own steps
   const size_t cap = (size_t)h->prm.max_walkers * h->d.N * h->d.ldV * h->tsize;
+  if (h->prec == AFQMC_FP16X3) {
+    // packed symmetric G in FP32 rows of ldhp (split in place), then one scale per row
+    *ldpk = h->ldhp;
+    *nsplit = 1;
+    if (!h->lt_t_split || (size_t)2 * h->prm.max_walkers * (h->ldhp + 1) * sizeof(float) > cap)
+      return fail(AFQMC_EUNSUPPORTED, "force-bias scratch does not fit the Hamiltonian's workspace");
+    return AFQMC_OK;
+  }
+  *ldpk = (npk + 15) / 16 * 16;
   *nsplit = msd_fb_splits(nw > 0 ? nw : 1, t->m.N, h->d.K, h->d.ldK, *ldpk, h->tsize, cap);
   if (*nsplit < 1) return fail(AFQMC_EUNSUPPORTED, "force-bias scratch does not fit the Hamiltonian's workspace");
   return AFQMC_OK;
@@ -1506,6 +1519,12 @@ int msd_vbias(afqmc_msd* t, afqmc_ham* h, const afqmc_walkers* w, int nw, int ns
   if (h->prec == AFQMC_FP64) {
     HIP_TRY(launch_msd_force_bias<double>(t->m, nw, t->theta, t->qp, (const double*)h->LT, h->d.K, h->d.ldK, ldpk,
                                           nsplit, h->vhs, vbias, s));
+  } else if (h->prec == AFQMC_FP16X3) {
+    float* gs = (float*)h->vhs;                        // [nw][2][ldhp]
+    float* gs_unscale = gs + (size_t)2 * nw * h->ldhp;  // [2 nw]
+    HIP_TRY(launch_msd_gsym_f32(t->m, nw, t->theta, t->qp, h->ldhp, gs, s));
+    HIP_TRY(launch_msd_fb_split(h->split, nw, h->d.K, h->d.Npk, h->ldhp, gs, gs_unscale, h->lt_t_split,
+                                h->lt_t_unscale, h->fb_part, vbias, s));
   } else {
     HIP_TRY(launch_msd_force_bias<float>(t->m, nw, t->theta, t->qp, (const float*)h->LT, h->d.K, h->d.ldK, ldpk,
                                          nsplit, h->vhs, vbias, s));

@@ -122,6 +122,18 @@ constexpr int FB_SPLIT_CHUNKS = 8;
 hipError_t launch_force_bias_split(int mode, const StepDims& d, int W, const unsigned short* th, const float* th_unscale,
                                    const unsigned short* lh, const float* lh_unscale, float* part, double2* vbias,
                                    hipStream_t s);
+// The packed L transposed for the multi-determinant force bias: one split row
+// per Cholesky vector g over the pair index c of the row-major upper triangle
+// (pq[c] = (p, q), p <= q), 2 ldh halves, scale per g; L is [K][N][N] FP64.
+hipError_t setup_split_lt_transposed(int mode, int K, int N, int npk, int ldh, const int2* pq, const double* L,
+                                     unsigned short* dst, float* unscale, hipStream_t s);
+// vbias [W][K] complex = sum_c gs[(z, re|im)][c] L_g[c]: gs [2 W][ldh] FP32 rows
+// (the first npk meaningful) are split in place into rows of 2 ldh halves
+// (scales into gs_unscale [2 W]), then contracted with the transposed split L
+// on the split engine; part: [FB_SPLIT_CHUNKS][2 W][K] floats.
+hipError_t launch_msd_fb_split(int mode, int W, int K, int npk, int ldh, float* gs, float* gs_unscale,
+                               const unsigned short* lts, const float* lts_unscale, float* part, double2* vbias,
+                               hipStream_t s);
 // Taylor order k on split operands: t_k = VHS t_{k-1} / k (t_0 = acc, FP64)
 hipError_t launch_taylor_split(int mode, const StepDims& d, int W, const float* vhs, const float* t_in,
                                float* t_out, const double* acc, unsigned* tmax, int tstride, int k,
@@ -267,6 +279,10 @@ int msd_fb_splits(int W, int N, int K, int ldK, int ldpk, size_t gs_elem_bytes, 
 template <typename T>
 hipError_t launch_msd_force_bias(const MsdDims& m, int W, const double* theta, const double* qp, const T* lt, int K,
                                  int ldK, int ldpk, int nsplit, void* scratch, double2* vbias, hipStream_t s);
+// after launch_msd_q: only the packed symmetric G, gs [W][2][ldpk] FP32 (entries
+// past the triangle are not written)
+hipError_t launch_msd_gsym_f32(const MsdDims& m, int W, const double* theta, const double* qp, int ldpk, float* gs,
+                               hipStream_t s);
 
 // --- local energy of the multi-determinant trial (msd_energy.hip) --------------
 struct MsdEnergyDims {

@@ -841,12 +841,8 @@ int msd_fb_splits(int W, int N, int K, int ldK, int ldpk, size_t gs_elem_bytes, 
 }
 
 template <typename T>
-hipError_t launch_msd_force_bias(const MsdDims& m, int W, const double* theta, const double* qp, const T* lt, int K,
-                                 int ldK, int ldpk, int nsplit, void* scratch, double2* vbias, hipStream_t s) {
-  T* gs = reinterpret_cast<T*>(scratch);  // [W][2][ldpk]
-  double* fbp = reinterpret_cast<double*>(gs + (size_t)2 * W * ldpk);  // [nsplit][2 W][ldK]
-  const int npk = m.N * (m.N + 1) / 2;
-  hipError_t e;
+static hipError_t launch_msd_gsym(const MsdDims& m, int W, const double* theta, const double* qp, int ldpk, T* gs,
+                                  hipStream_t s) {
   for (int z0 = 0; z0 < W; z0 += ZCHUNK) {
     const int nz = W - z0 < ZCHUNK ? W - z0 : ZCHUNK;
     MsdSProb ps{qp, theta, m.N, m.nmax, m.ldN, m.ldq, z0};
@@ -854,8 +850,25 @@ hipError_t launch_msd_force_bias(const MsdDims& m, int W, const double* theta, c
     const int nbp = (nz + NXCD - 1) / NXCD * NXCD;
     hipLaunchKernelGGL(msd_gsym_kernel<T>, dim3(ntile * nbp), dim3(GWM * GWN * 64), 0, s, m, ps, nz, mt, ntile, ldpk,
                        gs);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
+  return hipSuccess;
+}
+
+hipError_t launch_msd_gsym_f32(const MsdDims& m, int W, const double* theta, const double* qp, int ldpk, float* gs,
+                               hipStream_t s) {
+  return launch_msd_gsym<float>(m, W, theta, qp, ldpk, gs, s);
+}
+
+template <typename T>
+hipError_t launch_msd_force_bias(const MsdDims& m, int W, const double* theta, const double* qp, const T* lt, int K,
+                                 int ldK, int ldpk, int nsplit, void* scratch, double2* vbias, hipStream_t s) {
+  T* gs = reinterpret_cast<T*>(scratch);  // [W][2][ldpk]
+  double* fbp = reinterpret_cast<double*>(gs + (size_t)2 * W * ldpk);  // [nsplit][2 W][ldK]
+  const int npk = m.N * (m.N + 1) / 2;
+  hipError_t e;
+  if ((e = launch_msd_gsym<T>(m, W, theta, qp, ldpk, gs, s)) != hipSuccess) return e;
   // the pair range of each split is a multiple of 16 (whole k steps, aligned operand rows)
   int chunk = (npk + nsplit - 1) / nsplit;
   chunk = (chunk + 31) / 32 * 32;

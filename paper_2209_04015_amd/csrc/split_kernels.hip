@@ -5,6 +5,7 @@
 
 #include <math.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "common.h"
@@ -931,18 +932,19 @@ static int fb_split_chunks(int tiles, int nkb) {
   return best;
 }
 
-hipError_t launch_force_bias_split(int mode, const StepDims& d, int W, const unsigned short* th, const float* th_unscale,
-                                   const unsigned short* lh, const float* lh_unscale, float* part, double2* vbias,
-                                   hipStream_t s) {
+// C = A B^T over split rows of rowb bytes (nkb k blocks), A rows (z, re|im)
+// (2 W), B rows g (K); vbias[z][g] = the chunks' sum x a_unscale x b_unscale.
+static hipError_t launch_fb_split_rows(int mode, int W, int K, int rowb, int nkb, const unsigned short* a,
+                                       const float* a_unscale, const unsigned short* b, const float* b_unscale,
+                                       float* part, double2* vbias, hipStream_t s) {
   using C = ExSplitCfg;
   if (W == 0) return hipSuccess;
-  const int rowb = 2 * d.nmax * 2 * d.ldh * 2;  // (spin, i) sub-rows of 2 ldh halves
-  if ((double)C::BM * rowb >= (double)SPLIT_ROW_NONE) return hipErrorInvalidValue;
-  const int nkb = 2 * d.nmax * (d.ldh / 32);
-  const int ntm = ceil_div(2 * W, C::BM), ntn = ceil_div(d.K, C::BN);
+  if ((double)C::BM * rowb >= (double)SPLIT_ROW_NONE || (double)C::BN * rowb >= (double)SPLIT_ROW_NONE)
+    return hipErrorInvalidValue;
+  const int ntm = ceil_div(2 * W, C::BM), ntn = ceil_div(K, C::BN);
   const int kchunk = ceil_div(nkb, fb_split_chunks(ntm * ntn, nkb));
   const int chunks = ceil_div(nkb, kchunk);  // every chunk holds at least one k block
-  FbSplitArgs p{th, lh, part, W, d.K, rowb, nkb, kchunk};
+  FbSplitArgs p{a, b, part, W, K, rowb, nkb, kchunk};
   const int per = ceil_div(ntm * ntn, 8);
   const dim3 grid((unsigned)(chunks * 8 * per));
   if (mode == SPLIT_BF16)
@@ -951,8 +953,133 @@ hipError_t launch_force_bias_split(int mode, const StepDims& d, int W, const uns
     hipLaunchKernelGGL(fb_split_kernel<HalfF16>, grid, dim3(C::NT), 0, s, p, ntm, ntn, 8 * per);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t n = (size_t)W * d.K;
-  hipLaunchKernelGGL(fb_split_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, d.K, chunks,
-                     part, th_unscale, lh_unscale, vbias);
+  const size_t n = (size_t)W * K;
+  hipLaunchKernelGGL(fb_split_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, K, chunks,
+                     part, a_unscale, b_unscale, vbias);
+  return hipGetLastError();
+}
+
+hipError_t launch_force_bias_split(int mode, const StepDims& d, int W, const unsigned short* th, const float* th_unscale,
+                                   const unsigned short* lh, const float* lh_unscale, float* part, double2* vbias,
+                                   hipStream_t s) {
+  const int rowb = 2 * d.nmax * 2 * d.ldh * 2;  // (spin, i) sub-rows of 2 ldh halves
+  const int nkb = 2 * d.nmax * (d.ldh / 32);
+  return launch_fb_split_rows(mode, W, d.K, rowb, nkb, th, th_unscale, lh, lh_unscale, part, vbias, s);
+}
+
+// ---------------------------------------------------------------------------
+// Multi-determinant force bias on the split engine (FP16X3):
+// vbias_g = sum over pairs c = (p <= q) of Gsym[z][c] L_g[p][q] with the
+// symmetrised Green's function rows of the walkers (A) against the packed L
+// transposed, one split row per Cholesky vector g (B).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float block_max256(float v, float* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+// dst[g] = split row of L_g over the pair index (row-major upper triangle),
+// scale per g; one workgroup per g
+template <class H>
+__global__ __launch_bounds__(256) void split_lt_transposed_kernel(int N, int npk, int ldh, const int2* __restrict__ pq,
+                                                                  const double* __restrict__ L,
+                                                                  unsigned short* __restrict__ dst,
+                                                                  float* __restrict__ unscale) {
+  __shared__ float red[4];
+  const int g = blockIdx.x, tid = threadIdx.x;
+  const double* Lg = L + (size_t)g * N * N;
+  float m = 0.f;
+  for (int c = tid; c < npk; c += 256) {
+    const int2 ab = pq[c];
+    m = fmaxf(m, fabsf((float)Lg[(size_t)ab.x * N + ab.y]));
+  }
+  m = block_max256(m, red);
+  const float sc = split_row_scale<H>(m);
+  unsigned short* d = dst + (size_t)g * 2 * ldh;
+  for (int c = tid; c < ldh; c += 256) {
+    float x = 0.f;
+    if (c < npk) {
+      const int2 ab = pq[c];
+      x = (float)Lg[(size_t)ab.x * N + ab.y] * sc;
+    }
+    const unsigned short xh = H::from_float(x);
+    unsigned short* o = d + (c >> 5) * SPLIT_KB + (c & 31);
+    o[0] = xh;
+    o[32] = H::from_float(x - H::to_float(xh));
+  }
+  if (tid == 0) unscale[g] = 1.0f / sc;
+}
+
+hipError_t setup_split_lt_transposed(int mode, int K, int N, int npk, int ldh, const int2* pq, const double* L,
+                                     unsigned short* dst, float* unscale, hipStream_t s) {
+  if (ldh % 32 != 0 || ldh < npk) return hipErrorInvalidValue;
+  if (mode == SPLIT_BF16)
+    hipLaunchKernelGGL(split_lt_transposed_kernel<HalfBF16>, dim3(K), dim3(256), 0, s, N, npk, ldh, pq, L, dst,
+                       unscale);
+  else
+    hipLaunchKernelGGL(split_lt_transposed_kernel<HalfF16>, dim3(K), dim3(256), 0, s, N, npk, ldh, pq, L, dst,
+                       unscale);
+  return hipGetLastError();
+}
+
+// Row r of `data` (ldh floats, the first ncols meaningful) becomes, in place,
+// the split row of 2 ldh halves (the same bytes), scale per row; one
+// workgroup per row.  Every value is read (for the maximum) before the
+// barrier inside block_max256; after it each k block (32 floats, 128 bytes)
+// is read by one half-wave, one float per lane in a single load, and then
+// overwritten by the same half-wave with its 32 hi and 32 lo halves.
+template <class H>
+__global__ __launch_bounds__(256) void split_rows_inplace_kernel(int ncols, int ldh, float* __restrict__ data,
+                                                                 float* __restrict__ unscale) {
+  __shared__ float red[4];
+  const int r = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  float* row = data + (size_t)r * ldh;
+  float m = 0.f;
+  for (int c = tid; c < ncols; c += 256) m = fmaxf(m, fabsf(row[c]));
+  m = block_max256(m, red);
+  const float sc = split_row_scale<H>(m);
+  unsigned short* d = reinterpret_cast<unsigned short*>(row);
+  const int nkb = ldh / 32, i = lane & 31;
+  for (int kb = 2 * wid + (lane >> 5); kb < nkb; kb += 8) {
+    const int c = kb * 32 + i;
+    const float x = c < ncols ? row[c] * sc : 0.f;
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);  // the block's read stays ahead of its overwrite
+    const unsigned short xh = H::from_float(x);
+    d[kb * SPLIT_KB + i] = xh;
+    d[kb * SPLIT_KB + 32 + i] = H::from_float(x - H::to_float(xh));
+  }
+  if (tid == 0) unscale[r] = 1.0f / sc;
+}
+
+__global__ void zero_fill_kernel(float* __restrict__ p, size_t n) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    p[e] = 0.f;
+}
+
+hipError_t launch_msd_fb_split(int mode, int W, int K, int npk, int ldh, float* gs, float* gs_unscale,
+                               const unsigned short* lts, const float* lts_unscale, float* part, double2* vbias,
+                               hipStream_t s) {
+  if (W == 0) return hipSuccess;
+  if (ldh % 32 != 0 || ldh < npk) return hipErrorInvalidValue;
+  if (mode == SPLIT_BF16)
+    hipLaunchKernelGGL(split_rows_inplace_kernel<HalfBF16>, dim3(2 * W), dim3(256), 0, s, npk, ldh, gs, gs_unscale);
+  else
+    hipLaunchKernelGGL(split_rows_inplace_kernel<HalfF16>, dim3(2 * W), dim3(256), 0, s, npk, ldh, gs, gs_unscale);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = launch_fb_split_rows(mode, W, K, 4 * ldh, ldh / 32, reinterpret_cast<const unsigned short*>(gs),
+                                 gs_unscale, lts, lts_unscale, part, vbias, s)) != hipSuccess)
+    return e;
+  // gs lives in the VHS workspace, whose rows the split propagation kernels
+  // read up to their zero padding: leave the rows zero (a fill kernel, no
+  // memset node under graph capture); gs_unscale follows gs
+  const size_t n = (size_t)2 * W * (ldh + 1);
+  hipLaunchKernelGGL(zero_fill_kernel, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, s, gs,
+                     n);
   return hipGetLastError();
 }

@@ -253,15 +253,18 @@ def test_msd_force_bias_matches_oracle(N, na, nb, K, ndet, max_rank, W):
     ham.close()
 
 
-def test_msd_force_bias_leaves_the_hamiltonian_step_unchanged():
-    """The call borrows the Hamiltonian's VHS workspace; a step after it equals one without it."""
+@pytest.mark.parametrize("precision", ["fp64", "fp16x3"])
+def test_msd_force_bias_leaves_the_hamiltonian_step_unchanged(precision):
+    """The call borrows the Hamiltonian's VHS workspace (and, in FP16X3, its
+    split force-bias partials); a step after it equals one without it."""
     import torch
     from paper_2209_04015_amd import afqmc
 
     N, na, nb, K, W = 20, 5, 4, 30, 8
-    h1, L, C_a, C_b, coeff, rank, orbs, pa, pb, ham, t = _fb_problem(N, na, nb, K, 60, 3, W, seed=3)
+    h1, L, C_a, C_b, coeff, rank, orbs, pa, pb, ham, t = _fb_problem(N, na, nb, K, 60, 3, W, seed=3,
+                                                                     precision=precision)
     x = torch.as_tensor(inputs.fields(W, K, 1, seed=2)[0], device="cuda")
-    print("[gpu] msd force bias then step", flush=True)
+    print(f"[gpu] msd force bias then step ({precision})", flush=True)
 
     def run(between):
         w = afqmc.Walkers.from_numpy(pa, pb, device="cuda")
@@ -278,26 +281,34 @@ def test_msd_force_bias_leaves_the_hamiltonian_step_unchanged():
     ham.close()
 
 
-def test_msd_force_bias_needs_a_packed_l():
-    """FP16X3 Hamiltonians keep L only as 16-bit splits: the call is refused."""
+@pytest.mark.parametrize("precision", ["fp64", "fp16x3"])
+def test_msd_force_bias_checks_the_hamiltonian(precision):
+    """A Hamiltonian of another orbital count, or fewer walkers than asked
+    for, is refused with AFQMC_EINVAL before any work."""
     from paper_2209_04015_amd import afqmc
 
     N, na, nb, K = 12, 3, 3, 8
     h1, L = inputs.hamiltonian(N, K, 2.0, seed=1)
     C = inputs.orbitals(h1)
     coeff, rank, orbs = inputs.msd_expansion(N, na, nb, 10, 2, seed=2)
-    ham = afqmc.Hamiltonian(h1, L, C[:, :na], C[:, :nb], dt=0.005, max_walkers=2, precision="fp16x3")
+    h1b, Lb = inputs.hamiltonian(N + 1, K, 2.0, seed=1)
+    Cb = inputs.orbitals(h1b)
+    other = afqmc.Hamiltonian(h1b, Lb, Cb[:, :na], Cb[:, :nb], dt=0.005, max_walkers=4, precision=precision)
+    small = afqmc.Hamiltonian(h1, L, C[:, :na], C[:, :nb], dt=0.005, max_walkers=1, precision=precision)
     t = afqmc.MSDTrial(C, C, na, nb, coeff, rank, orbs, max_walkers=2)
     w = afqmc.Walkers.from_numpy(inputs.walkers_perturbed(C[:, :na], 2, 0.2, seed=1),
                                  inputs.walkers_perturbed(C[:, :nb], 2, 0.2, seed=1, stream=1), device="cuda")
-    with pytest.raises(afqmc.AfqmcError) as e:
-        t.force_bias(ham, w)
-    assert e.value.code == 4
+    for ham in (other, small):
+        with pytest.raises(afqmc.AfqmcError) as e:
+            t.force_bias(ham, w)
+        assert e.value.code == 1
     t.close()
-    ham.close()
+    other.close()
+    small.close()
 
 
-def test_msd_force_bias_at_n290_shape_sampled():
+@pytest.mark.parametrize("precision", ["fp64", "fp16x3"])
+def test_msd_force_bias_at_n290_shape_sampled(precision):
     """290 orbitals, 26 + 26 electrons, K = 2900, 512 walkers and 300
     determinants in one call; the oracle checks two walkers."""
     from paper_2209_04015_amd import afqmc
@@ -309,15 +320,16 @@ def test_msd_force_bias_at_n290_shape_sampled():
     coeff, rank, orbs = inputs.msd_expansion(N, n, n, ndet, max_rank=4, seed=5)
     pa = inputs.walkers_perturbed(C[:, :n], W, 0.1, seed=6, stream=0)
     pb = inputs.walkers_perturbed(C[:, :n], W, 0.1, seed=6, stream=1)
-    print("[gpu] msd force bias n290 W=512 ndet=300", flush=True)
-    ham = afqmc.Hamiltonian(h1, L, C[:, :n], C[:, :n], dt=cfg.dt, max_walkers=W, precision="fp64")
+    print(f"[gpu] msd force bias n290 W=512 ndet=300 {precision}", flush=True)
+    ham = afqmc.Hamiltonian(h1, L, C[:, :n], C[:, :n], dt=cfg.dt, max_walkers=W, precision=precision)
     t = afqmc.MSDTrial(C, C, n, n, coeff, rank, orbs, max_walkers=W)
     w = afqmc.Walkers.from_numpy(pa, pb, device="cuda")
     vb = t.force_bias(ham, w).cpu().numpy()
     assert t.status() == 0
     sample = [0, 511]
     msd = orc.msd_setup(C, C, n, n, coeff, rank, orbs)
-    _fb_compare(msd, L, vb[sample], pa[sample], pb[sample])
+    rtol = 1e-12 if precision == "fp64" else 4 * 2.0 ** -24 * np.sqrt(N * (N + 1) // 2)
+    _fb_compare(msd, L, vb[sample], pa[sample], pb[sample], rtol=rtol)
     t.close()
     ham.close()
 
@@ -410,10 +422,14 @@ def test_msd_propagate_with_one_reference_equals_the_single_determinant_step():
 # (u = 2^-24) and the contraction over the c = N (N + 1) / 2 pairs accumulates
 # in FP32 on the matrix cores, so the bar is 4 u sqrt(c) times the
 # magnitude scale sum |G| |L| (the single-determinant FP32 force bias uses
-# 4 u sqrt(c) with its own contraction length).  The step takes the FP32
-# single-determinant bars: orbitals 1e-4 of max|phi|, logs 1e-3.
+# 4 u sqrt(c) with its own contraction length).  FP16X3 splits G (per walker
+# row) and L (per Cholesky vector) into fp16 hi + lo, 22 significant bits
+# down to 2^-16 of each row's maximum, every hi x hi, hi x lo, lo x hi
+# product exact in FP32, the dropped lo x lo below 2^-22 of |G||L|: the same
+# FP32 accumulation bar.  The step takes the FP32 single-determinant bars:
+# orbitals 1e-4 of max|phi|, logs 1e-3.
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
 def test_msd_force_bias_on_the_fp32_packed_l(precision):
     from paper_2209_04015_amd import afqmc
 
@@ -430,14 +446,15 @@ def test_msd_force_bias_on_the_fp32_packed_l(precision):
     ham.close()
 
 
-def test_msd_propagate_on_the_fp32_path():
+@pytest.mark.parametrize("precision", ["fp32", "fp16x3"])
+def test_msd_propagate_on_the_mixed_paths(precision):
     import torch
     from paper_2209_04015_amd import afqmc
 
     N, na, nb, K, ndet, max_rank, W = FB_CASES[1]
-    print("[gpu] msd step fp32", flush=True)
+    print(f"[gpu] msd step {precision}", flush=True)
     h1, L, C_a, C_b, coeff, rank, orbs, pa, pb, ham, t = _fb_problem(N, na, nb, K, ndet, max_rank, W,
-                                                                     precision="fp32")
+                                                                     precision=precision)
     msd = orc.msd_setup(C_a, C_b, na, nb, coeff, rank, orbs)
     oh = orc.setup(h1, L, C_a[:, :na], C_b[:, :nb], dt=0.005)
     x = inputs.fields(W, K, 1, seed=4)[0]
