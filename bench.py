@@ -350,7 +350,9 @@ def run_msd(cfg, h1, L, device, steps, ndet=MSD_DETS):
 
 def run_batch(device, steps, precision="fp16x3"):
     """The uneven multi-system workload (8 systems, N = 40 .. 200) advanced
-    together by one hipGraph launch per step (autotuned exchange tile order),
+    together by one hipGraph launch per step (autotuned exchange and VHS tile
+    shapes and exchange tile order; the same graph with the default tiles for
+    comparison),
     QR and local energy every step; and the same steps taken system after
     system with afqmc_step on one stream, for comparison."""
     import torch
@@ -378,17 +380,28 @@ def run_batch(device, steps, precision="fp16x3"):
     wtot = sum(s[4] for s in systems)
     log(f"batch: {len(systems)} systems, {wtot} walkers, set up in {time.time() - t:.1f} s")
     b = afqmc.Batch(hams, ws, use_graph=True)
-    b.autotune()
     stream = torch.cuda.current_stream()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
-    b.step(fs, es, do_qr=True)          # capture + first replays (untimed)
-    torch.cuda.synchronize()
-    start.record(stream)
-    b.step(fs, es, do_qr=True)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    ms_b = start.elapsed_time(stop)
+
+    def graph_ms():
+        for w, (a0, b0, l0, lw0) in zip(ws, starts):
+            w.phi_a.copy_(a0)
+            w.phi_b.copy_(b0)
+            w.log_ovlp.copy_(l0)
+            w.log_w.copy_(lw0)
+        b.step(fs, es, do_qr=True)          # capture + first replays (untimed)
+        torch.cuda.synchronize()
+        start.record(stream)
+        b.step(fs, es, do_qr=True)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop)
+
+    ms_default = graph_ms()             # built-in tiles (80 walkers per exchange and VHS tile)
+    b.autotune()
+    tunings = [h.tuning() for h in hams]
+    ms_b = graph_ms()
     st_b = sum(h.status() for h in hams)
     b.close()
     # per-system energy error: the last step's local energies of sampled
@@ -423,13 +436,19 @@ def run_batch(device, steps, precision="fp16x3"):
     for h in hams:
         h.close()
     torch.cuda.empty_cache()
-    log(f"batch: {steps} steps in {ms_b:.1f} ms (graph) vs {ms_s:.1f} ms (systems in turn)")
+    log(f"batch: {steps} steps in {ms_b:.1f} ms (graph, autotuned tiles; {ms_default:.1f} ms with the default "
+        f"tiles) vs {ms_s:.1f} ms (systems in turn)")
     return {"workload": "uneven multi-system batch: 8 systems, N = 40, 60, ..., 160, 200, n = N/5, K = 4N, "
                         f"walkers {[s[4] for s in systems]}, {precision}, QR and local energy every step, "
-                        "one hipGraph launch per step, autotuned exchange tile order",
+                        "one hipGraph launch per step, autotuned exchange and VHS tile shapes and exchange "
+                        "tile order",
             "value": round(wtot * steps / (ms_b * 1e-3), 1), "unit": "walker-steps/s",
             "ms_per_step": round(ms_b / steps, 4), "status": st_b,
             "energy_error_vs_fp64_oracle": per_sys,
+            "tuning": [{"N": sy[0], "exchange_tile": list(t["exchange_tile"]), "exchange_group": t["exchange_group"],
+                        "vhs_tile": list(t["vhs_tile"])} for sy, t in zip(systems, tunings)],
+            "default_tiles": {"value": round(wtot * steps / (ms_default * 1e-3), 1), "unit": "walker-steps/s",
+                              "ms_per_step": round(ms_default / steps, 4)},
             "systems_in_turn": {"value": round(wtot * steps / (ms_s * 1e-3), 1), "unit": "walker-steps/s",
                                 "ms_per_step": round(ms_s / steps, 4)}}
 

@@ -363,10 +363,42 @@ int afqmc_batch_create(afqmc_ham* const* hams, const afqmc_walkers* ws, const in
 int afqmc_batch_step(afqmc_batch* b, const double* const* fields, void* const* e, int nsteps,
                      int do_qr, void* stream);
 
-/* Choose per system the tile-order group size of the exchange kernel by
- * timing the candidates on the current walkers (or by reading cache_path, a
- * text file of "key choice" lines, when it holds the system's key); new
- * results are appended to cache_path (NULL: no cache).  Synchronises. */
+/* Kernel tiling of one Hamiltonian (no result depends
+ * on it; every output element sums over the same terms in the same order).
+ *   ex_tile_m x ex_tile_n    output tile of the exchange kernels: rows of
+ *                            the Cholesky or pair-integral operand by
+ *                            (walker, re|im) columns
+ *   ex_group                 tile-order group size of the exchange launch
+ *                            (0: the kernel's default)
+ *   vhs_tile_m x vhs_tile_n  output tile of the VHS build: (walker, re|im)
+ *                            rows by orbital-pair columns
+ * Offered shapes: the split pair exchange (BF16X3, FP16X3 with pair
+ * integrals) 160 x 160 or 160 x 64; the split VHS build (FP16X3) 160 x 160
+ * or 64 x 160; every other kernel one shape (exchange 192 x 160, VHS
+ * 64 x 64). */
+typedef struct afqmc_tuning {
+  int ex_tile_m, ex_tile_n;
+  int ex_group;
+  int vhs_tile_m, vhs_tile_n;
+} afqmc_tuning;
+
+/* The handle's current choices into *out. */
+int afqmc_get_tuning(const afqmc_ham* ham, afqmc_tuning* out);
+
+/* Set the choices (a shape the handle does not offer: AFQMC_EUNSUPPORTED;
+ * ex_group outside [0, 1024]: AFQMC_EINVAL).  Applies to the next call; a
+ * batch whose graph holds the old choices recaptures it at its next step.
+ * Must not overlap a call on the handle. */
+int afqmc_set_tuning(afqmc_ham* ham, const afqmc_tuning* t);
+
+/* Choose per system, by timing the candidates on the current walkers, the
+ * exchange tile shape and tile-order group size (every offered shape x
+ * groups 1, 2, 4, 8, 16, 32) and the VHS tile shape (afqmc_tuning); or read
+ * them from cache_path, a text file of lines
+ *   <key> ex=<m>x<n>/<group> vhs=<m>x<n>
+ * when it holds the system's key (device, N, na, nb, K, walkers, precision,
+ * exchange algorithm).  New results are appended to cache_path (NULL: no
+ * cache).  Synchronises. */
 int afqmc_autotune(afqmc_batch* b, const char* cache_path);
 
 void afqmc_batch_destroy(afqmc_batch* b);

@@ -58,6 +58,8 @@ EXPORTED = (
     "afqmc_batch_create",
     "afqmc_batch_step",
     "afqmc_autotune",
+    "afqmc_get_tuning",
+    "afqmc_set_tuning",
     "afqmc_batch_destroy",
     "afqmc_msd_create",
     "afqmc_msd_overlap",
@@ -84,6 +86,11 @@ class AfqmcError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"afqmc error {code}: {msg}")
         self.code = code
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("ex_tile_m", ctypes.c_int), ("ex_tile_n", ctypes.c_int), ("ex_group", ctypes.c_int),
+                ("vhs_tile_m", ctypes.c_int), ("vhs_tile_n", ctypes.c_int)]
 
 
 class _Params(ctypes.Structure):
@@ -151,6 +158,8 @@ def load(path: str = LIB_PATH):
     lib.afqmc_batch_create.argtypes = [vp, vp, vp, ip, P(_BatchOpts), P(vp)]
     lib.afqmc_batch_step.argtypes = [vp, vp, vp, ip, ip, vp]
     lib.afqmc_autotune.argtypes = [vp, ctypes.c_char_p]
+    lib.afqmc_get_tuning.argtypes = [vp, P(_Tuning)]
+    lib.afqmc_set_tuning.argtypes = [vp, P(_Tuning)]
     lib.afqmc_batch_destroy.argtypes = [vp]
     lib.afqmc_batch_destroy.restype = None
     lib.afqmc_msd_create.argtypes = [ip, ip, ip, vp, vp, ip, vp, vp, vp, ip, vp, P(vp)]
@@ -479,6 +488,19 @@ class Hamiltonian:
         v = ctypes.c_int()
         _check(_lib.afqmc_get_status(self._h, _stream_ptr(stream), ctypes.byref(v)))
         return v.value
+
+    def tuning(self) -> dict:
+        """Kernel tiling (afqmc_get_tuning): exchange and VHS output tile shapes, exchange group size."""
+        t = _Tuning()
+        _check(_lib.afqmc_get_tuning(self._h, ctypes.byref(t)))
+        return {"exchange_tile": (t.ex_tile_m, t.ex_tile_n), "exchange_group": t.ex_group,
+                "vhs_tile": (t.vhs_tile_m, t.vhs_tile_n)}
+
+    def set_tuning(self, exchange_tile, exchange_group, vhs_tile):
+        """afqmc_set_tuning: shapes as (rows, columns) tuples."""
+        t = _Tuning(int(exchange_tile[0]), int(exchange_tile[1]), int(exchange_group), int(vhs_tile[0]),
+                    int(vhs_tile[1]))
+        _check(_lib.afqmc_set_tuning(self._h, ctypes.byref(t)))
 
     def profile_enable(self, max_records: int):
         """Bracket every kernel phase with HIP events on its stream (0 turns it off)."""

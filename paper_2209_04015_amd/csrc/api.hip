@@ -142,6 +142,9 @@ struct afqmc_ham {
   int pair_ntg = 0;
   long pair_vrow0[2] = {0, 0};
   int ex_gs = 0;         // exchange tile-order group size (0: built-in default; set by the autotuner)
+  int ex_tile = SPLIT_TILE_WIDE;   // split pair-exchange walker tile (autotuner choice)
+  int vhs_tile = SPLIT_TILE_WIDE;  // split VHS walker tile (autotuner choice)
+  int tune_gen = 0;                // bumped by every change of the three choices above
   bool capturing = false;  // inside a graph capture: no phase-timing events
   std::vector<void*> allocs;
   // phase timing (afqmc_profile_enable)
@@ -262,14 +265,14 @@ struct StepIO {
 
 // Exchange partials of one spin into h->part with the handle's algorithm and
 // precision (theta, and its split rows in the split modes, already built).
-hipError_t launch_exchange_spin(afqmc_ham* h, int nw, int sp, int* ntg, hipStream_t s, int gs) {
+hipError_t launch_exchange_spin(afqmc_ham* h, int nw, int sp, int* ntg, hipStream_t s, int gs, int tile) {
   const StepDims& d = h->d;
   if (h->ex_algo == AFQMC_EXCHANGE_PAIR) {
     const PairLaunch pl{h->pair_tab + sp, h->pair_ntiles[sp], h->pair_ntg, h->pair_vrow0[sp]};
     *ntg = h->pair_ntg;
     if (h->split != SPLIT_NONE)
       return launch_exchange_pair_split(h->split, d, nw, pl, h->vpair_split, h->vpair_unscale, h->th_split,
-                                        h->th_unscale, (const float*)h->theta, h->part, sp, s, gs);
+                                        h->th_unscale, (const float*)h->theta, h->part, sp, s, gs, tile);
     if (h->prec != AFQMC_FP64)
       return launch_exchange_pair<float>(d, nw, pl, (const float*)h->vpair, (const float*)h->theta, h->part, sp,
                                          s, gs);
@@ -294,7 +297,8 @@ int seq_energy_from_theta(afqmc_ham* h, int nw, double2* e_out, hipStream_t s,
           launch_split_rows_mode(h->split, (long)nw * 4 * d.nmax, d.N, (const float*)h->theta, d.ldN,
                                  h->th_split, d.ldh, h->th_unscale, s));
   }
-  for (int sp = 0; sp < 2; ++sp) PHASE(h, AFQMC_PH_EXCHANGE, s, launch_exchange_spin(h, nw, sp, &ntg, s, h->ex_gs));
+  for (int sp = 0; sp < 2; ++sp)
+    PHASE(h, AFQMC_PH_EXCHANGE, s, launch_exchange_spin(h, nw, sp, &ntg, s, h->ex_gs, h->ex_tile));
   PHASE(h, AFQMC_PH_ENERGY, s,
         launch_energy(h->d, nw, h->e1, h->vbias, h->part, ntg, e_out, ctr, estep, s));
   return AFQMC_OK;
@@ -314,7 +318,7 @@ int seq_propagate_core(afqmc_ham* h, afqmc_walkers* w, int nw, const StepIO& io,
                                  h->xs_unscale, s));
     PHASE(h, AFQMC_PH_VHS, s,
           launch_vhs_split(h->split, d, nw, h->xs_split, h->xs_unscale, h->lt_split, h->lt_unscale, h->vblk,
-                           h->nvblk, (float*)h->vhs, h->tmax + h->prm.max_walkers, h->sdt, s));
+                           h->nvblk, (float*)h->vhs, h->tmax + h->prm.max_walkers, h->sdt, s, h->vhs_tile));
   } else {
     PHASE(h, AFQMC_PH_VHS, s,
           (launch_vhs<T>(d, nw, (const T*)h->xs, (const T*)h->LT, h->pq, (T*)h->vhs, h->sdt, s)));
@@ -1786,6 +1790,7 @@ struct afqmc_batch {
   // what the current graph was captured for
   std::vector<const double*> g_fields;
   std::vector<void*> g_e;
+  std::vector<int> g_tune;  // tune_gen of each Hamiltonian
   int g_qr = -1;
 };
 
@@ -1876,6 +1881,8 @@ int batch_capture(afqmc_batch* b, const double* const* fields, void* const* e, i
   if (e)
     for (size_t i = 0; i < b->hams.size(); ++i) b->g_e[i] = e[i];
   b->g_qr = do_qr;
+  b->g_tune.resize(b->hams.size());
+  for (size_t i = 0; i < b->hams.size(); ++i) b->g_tune[i] = b->hams[i]->tune_gen;
   return AFQMC_OK;
 }
 
@@ -1884,9 +1891,71 @@ std::string tune_key(const afqmc_ham* h, int nw) {
   std::string dev = "gfx";
   if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) dev = prop.gcnArchName;
   std::ostringstream k;
-  k << "exchange_gs:" << dev << ":N" << h->d.N << ":na" << h->d.na << ":nb" << h->d.nb << ":K"
-    << h->d.K << ":W" << nw << ":p" << h->prec << ":x" << h->ex_algo;
+  k << "tiles:" << dev << ":N" << h->d.N << ":na" << h->d.na << ":nb" << h->d.nb << ":K" << h->d.K << ":W" << nw
+    << ":p" << h->prec << ":x" << h->ex_algo;
   return k.str();
+}
+
+// Tile shapes the handle's kernels offer: the split pair exchange and the
+// split VHS build come in a wide and a narrow walker tile; every other
+// exchange and VHS kernel has one shape.
+bool ex_tiles_offered(const afqmc_ham* h) { return h->split != SPLIT_NONE && h->ex_algo == AFQMC_EXCHANGE_PAIR; }
+bool vhs_tiles_offered(const afqmc_ham* h) { return vhs_split(h); }
+
+void tile_shapes(const afqmc_ham* h, int ex_tile, int vhs_tile, afqmc_tuning* t) {
+  if (h->split != SPLIT_NONE) {
+    t->ex_tile_m = 160;
+    t->ex_tile_n = ex_tiles_offered(h) && ex_tile == SPLIT_TILE_NARROW ? 64 : 160;
+  } else {
+    t->ex_tile_m = 192;
+    t->ex_tile_n = 160;
+  }
+  if (vhs_split(h)) {
+    t->vhs_tile_m = vhs_tile == SPLIT_TILE_NARROW ? 64 : 160;
+    t->vhs_tile_n = 160;
+  } else {
+    t->vhs_tile_m = 64;
+    t->vhs_tile_n = 64;
+  }
+}
+
+// the tile choices of a shape, or false if the handle does not offer it
+bool tiles_of_shapes(const afqmc_ham* h, const afqmc_tuning& want, int* ex_tile, int* vhs_tile) {
+  for (int et = 0; et < 2; ++et)
+    for (int vt = 0; vt < 2; ++vt) {
+      if ((et && !ex_tiles_offered(h)) || (vt && !vhs_tiles_offered(h))) continue;
+      afqmc_tuning t;
+      tile_shapes(h, et, vt, &t);
+      if (t.ex_tile_m == want.ex_tile_m && t.ex_tile_n == want.ex_tile_n && t.vhs_tile_m == want.vhs_tile_m &&
+          t.vhs_tile_n == want.vhs_tile_n) {
+        *ex_tile = et;
+        *vhs_tile = vt;
+        return true;
+      }
+    }
+  return false;
+}
+
+// one cache line: "<key> ex=<m>x<n>/<group> vhs=<m>x<n>"
+std::string tune_line(const afqmc_ham* h) {
+  afqmc_tuning t;
+  tile_shapes(h, h->ex_tile, h->vhs_tile, &t);
+  std::ostringstream o;
+  o << "ex=" << t.ex_tile_m << "x" << t.ex_tile_n << "/" << h->ex_gs << " vhs=" << t.vhs_tile_m << "x"
+    << t.vhs_tile_n;
+  return o.str();
+}
+
+bool tune_parse(const afqmc_ham* h, const std::string& v, int* ex_tile, int* ex_gs, int* vhs_tile) {
+  afqmc_tuning t;
+  int g = 0;
+  if (std::sscanf(v.c_str(), "ex=%dx%d/%d vhs=%dx%d", &t.ex_tile_m, &t.ex_tile_n, &g, &t.vhs_tile_m,
+                  &t.vhs_tile_n) != 5 ||
+      g < 0)
+    return false;
+  if (!tiles_of_shapes(h, t, ex_tile, vhs_tile)) return false;
+  *ex_gs = g;
+  return true;
 }
 
 }  // namespace
@@ -1966,7 +2035,7 @@ int afqmc_batch_step(afqmc_batch* b, const double* const* fields, void* const* e
   bool same = b->exec && b->g_qr == do_qr;
   for (size_t i = 0; same && i < b->hams.size(); ++i) {
     void* ei = (e && e[i]) ? e[i] : nullptr;
-    same = b->g_fields[i] == fields[i] && b->g_e[i] == ei;
+    same = b->g_fields[i] == fields[i] && b->g_e[i] == ei && b->g_tune[i] == b->hams[i]->tune_gen;
   }
   if (!same) {
     HIP_TRY(hipStreamSynchronize(s));
@@ -1980,58 +2049,97 @@ int afqmc_batch_step(afqmc_batch* b, const double* const* fields, void* const* e
 int afqmc_autotune(afqmc_batch* b, const char* cache_path) {
   if (!b) return fail(AFQMC_EINVAL, "null batch");
   HIP_TRY(hipSetDevice(b->device));
-  std::map<std::string, int> cache;
+  std::map<std::string, std::string> cache;
   if (cache_path) {
     std::ifstream in(cache_path);
-    std::string key;
-    int v;
-    while (in >> key >> v) cache[key] = v;
+    std::string line;
+    while (std::getline(in, line)) {
+      const size_t sp = line.find(' ');
+      if (sp != std::string::npos) cache[line.substr(0, sp)] = line.substr(sp + 1);
+    }
   }
   static const int cand[] = {1, 2, 4, 8, 16, 32};
   hipEvent_t t0, t1;
   HIP_TRY(hipEventCreate(&t0));
   HIP_TRY(hipEventCreate(&t1));
-  std::vector<std::pair<std::string, int>> fresh;
+  std::vector<std::pair<std::string, std::string>> fresh;
   int rc = AFQMC_OK;
+  // mean of launches 2 and 3 of f (the first warms up), in ms
+  auto time3 = [&](hipStream_t s, auto&& f, float* out) -> int {
+    float tot = 0.f;
+    for (int rep = 0; rep < 3; ++rep) {
+      HIP_TRY(hipEventRecord(t0, s));
+      HIP_TRY(f());
+      HIP_TRY(hipEventRecord(t1, s));
+      HIP_TRY(hipEventSynchronize(t1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
+      if (rep > 0) tot += ms;
+    }
+    *out = tot / 2;
+    return AFQMC_OK;
+  };
   for (size_t i = 0; i < b->hams.size() && rc == AFQMC_OK; ++i) {
     afqmc_ham* h = b->hams[i];
-    const std::string key = tune_key(h, b->nw[i]);
+    const int nw = b->nw[i];
+    const std::string key = tune_key(h, nw);
     auto it = cache.find(key);
-    if (it != cache.end()) {
-      h->ex_gs = it->second;
+    if (it != cache.end() && tune_parse(h, it->second, &h->ex_tile, &h->ex_gs, &h->vhs_tile)) {
+      ++h->tune_gen;
       continue;
     }
     hipStream_t s = b->streams[i];
     // theta of the current walkers, then the exchange alone per candidate
-    rc = h->prec != AFQMC_FP64 ? seq_theta<float>(h, &b->ws[i], b->nw[i], false, s)
-                               : seq_theta<double>(h, &b->ws[i], b->nw[i], false, s);
+    rc = h->prec != AFQMC_FP64 ? seq_theta<float>(h, &b->ws[i], nw, false, s)
+                               : seq_theta<double>(h, &b->ws[i], nw, false, s);
     if (rc) break;
-    if (h->split != SPLIT_NONE) {
-      const StepDims& d = h->d;
-      HIP_TRY(launch_split_rows_mode(h->split, (long)b->nw[i] * 4 * d.nmax, d.N, (const float*)h->theta,
-                                     d.ldN, h->th_split, d.ldh, h->th_unscale, s));
-    }
+    const StepDims& d = h->d;
+    if (h->split != SPLIT_NONE)
+      HIP_TRY(launch_split_rows_mode(h->split, (long)nw * 4 * d.nmax, d.N, (const float*)h->theta, d.ldN,
+                                     h->th_split, d.ldh, h->th_unscale, s));
     float best = 1e30f;
-    int best_gs = 0;
-    for (int gs : cand) {
-      float tot = 0.f;
-      for (int rep = 0; rep < 3; ++rep) {
-        HIP_TRY(hipEventRecord(t0, s));
-        int ntg = 0;
-        for (int sp = 0; sp < 2; ++sp) HIP_TRY(launch_exchange_spin(h, b->nw[i], sp, &ntg, s, gs));
-        HIP_TRY(hipEventRecord(t1, s));
-        HIP_TRY(hipEventSynchronize(t1));
+    int best_gs = 0, best_tile = SPLIT_TILE_WIDE;
+    for (int tile = 0; tile < (ex_tiles_offered(h) ? 2 : 1) && !rc; ++tile)
+      for (int gs : cand) {
         float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
-        if (rep > 0) tot += ms;  // first launch warms up
+        rc = time3(s, [&]() -> hipError_t {
+          int ntg = 0;
+          for (int sp = 0; sp < 2; ++sp) {
+            const hipError_t e = launch_exchange_spin(h, nw, sp, &ntg, s, gs, tile);
+            if (e != hipSuccess) return e;
+          }
+          return hipSuccess;
+        }, &ms);
+        if (rc) break;
+        if (ms < best) {
+          best = ms;
+          best_gs = gs;
+          best_tile = tile;
+        }
       }
-      if (tot < best) {
-        best = tot;
-        best_gs = gs;
-      }
-    }
+    if (rc) break;
     h->ex_gs = best_gs;
-    fresh.emplace_back(key, best_gs);
+    h->ex_tile = best_tile;
+    // the VHS build alone per walker tile, on the current shifted fields
+    // (their values do not change the time; the next step rebuilds VHS)
+    h->vhs_tile = SPLIT_TILE_WIDE;
+    if (vhs_tiles_offered(h)) {
+      best = 1e30f;
+      for (int tile = 0; tile < 2 && !rc; ++tile) {
+        float ms = 0.f;
+        rc = time3(s, [&]() -> hipError_t {
+          return launch_vhs_split(h->split, d, nw, h->xs_split, h->xs_unscale, h->lt_split, h->lt_unscale, h->vblk,
+                                  h->nvblk, (float*)h->vhs, h->tmax + h->prm.max_walkers, h->sdt, s, tile);
+        }, &ms);
+        if (!rc && ms < best) {
+          best = ms;
+          h->vhs_tile = tile;
+        }
+      }
+      if (rc) break;
+    }
+    ++h->tune_gen;
+    fresh.emplace_back(key, tune_line(h));
     h->c_valid = false;  // theta was recomputed outside a step
   }
   (void)hipEventDestroy(t0);
@@ -2042,6 +2150,27 @@ int afqmc_autotune(afqmc_batch* b, const char* cache_path) {
     for (auto& kv : fresh) outf << kv.first << " " << kv.second << "\n";
   }
   batch_drop_graph(b);  // tile choices are baked into a captured graph
+  return AFQMC_OK;
+}
+
+int afqmc_get_tuning(const afqmc_ham* h, afqmc_tuning* out) {
+  if (!h || !out) return fail(AFQMC_EINVAL, "null argument");
+  tile_shapes(h, h->ex_tile, h->vhs_tile, out);
+  out->ex_group = h->ex_gs;
+  return AFQMC_OK;
+}
+
+int afqmc_set_tuning(afqmc_ham* h, const afqmc_tuning* t) {
+  if (!h || !t) return fail(AFQMC_EINVAL, "null argument");
+  if (t->ex_group < 0 || t->ex_group > 1024) return fail(AFQMC_EINVAL, "ex_group = %d outside [0, 1024]", t->ex_group);
+  int et = 0, vt = 0;
+  if (!tiles_of_shapes(h, *t, &et, &vt))
+    return fail(AFQMC_EUNSUPPORTED, "tile shapes exchange %dx%d, VHS %dx%d are not offered by this Hamiltonian",
+                t->ex_tile_m, t->ex_tile_n, t->vhs_tile_m, t->vhs_tile_n);
+  h->ex_tile = et;
+  h->vhs_tile = vt;
+  h->ex_gs = t->ex_group;
+  ++h->tune_gen;  // a batch that captured the old choices recaptures
   return AFQMC_OK;
 }
 

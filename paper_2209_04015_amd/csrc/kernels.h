@@ -104,11 +104,16 @@ hipError_t set_kernel_attributes(const StepDims& d);
 hipError_t launch_split_rows_mode(int mode, long nrows, int ncols, const float* src, int ld_src,
                                   unsigned short* dst, int ldh, float* unscale, hipStream_t s);
 ExTile exchange_split_tile(int n);
+// Walker-tile shapes of the split VHS and pair-exchange kernels (autotuner
+// choices): WIDE 80 walkers per tile, NARROW 32 (more workgroups for systems
+// with few walkers).  Every output element sums over the same rows in the
+// same order in both shapes, so the choice does not change any result bit.
+constexpr int SPLIT_TILE_WIDE = 0, SPLIT_TILE_NARROW = 1;
 // vmax (optional): per-walker max |VHS| (atomic, bit patterns of floats).
 // lt: block-packed L split rows (vhs_split_pairs order), blk: the blocks.
 hipError_t launch_vhs_split(int mode, const StepDims& d, int W, const unsigned short* xs, const float* xs_unscale,
                             const unsigned short* lt, const float* lt_unscale, const int2* blk, int nblk, float* vhs,
-                            unsigned* vmax, double sdt, hipStream_t s);
+                            unsigned* vmax, double sdt, hipStream_t s, int tile = SPLIT_TILE_WIDE);
 // blocks of orbital pairs of the split VHS and the pair of each packed row
 std::vector<int2> vhs_split_blocks(int N);
 std::vector<int2> vhs_split_pairs(int N, const std::vector<int2>& blk);
@@ -204,7 +209,7 @@ int exchange_pair_rows();
 hipError_t launch_exchange_pair_split(int mode, const StepDims& d, int W, const PairLaunch& pl,
                                       const unsigned short* v, const float* v_unscale, const unsigned short* th,
                                       const float* th_unscale, const float* theta, double2* part, int sp,
-                                      hipStream_t s, int gs = 0);
+                                      hipStream_t s, int gs = 0, int tile = SPLIT_TILE_WIDE);
 template <typename T>
 hipError_t launch_exchange_pair(const StepDims& d, int W, const PairLaunch& pl, const T* v, const T* theta,
                                 double2* part, int sp, hipStream_t s, int gs = 0);

@@ -101,12 +101,19 @@ hipError_t launch_split_rows_mode(int mode, long nrows, int ncols, const float* 
 // 4-wave workgroups of 80 x 80 wave tiles; register prefetch of the next k
 // block, one LDS stage; two workgroups per CU, so that one workgroup's
 // epilogue runs beside the other's matrix-core work.
-struct ExSplitCfg {
-  static constexpr int BM = 160, BN = 160, WM = 2, WN = 2, GS = 8;
+template <int BM_, int BN_>
+struct SplitCfgT {
+  static constexpr int BM = BM_, BN = BN_, WM = 2, WN = 2, GS = 8;
   static constexpr int NT = WM * WN * 64;
   static constexpr int NA = BM * 8 / NT, NB = BN * 8 / NT;
   static constexpr int WAVES_PER_EU = 2;
+  static_assert(BM % 32 == 0 && BN % 32 == 0, "whole fragments and staging rows");
 };
+using ExSplitCfg = SplitCfgT<160, 160>;
+// narrow walker tiles (autotuner candidates for systems with few walkers):
+// 32 walkers per pair-exchange tile, 32 walkers per VHS tile
+using ExPairNarrowCfg = SplitCfgT<160, 64>;
+using VhsNarrowCfg = SplitCfgT<64, 160>;
 
 struct ExSplitArgs {
   const unsigned short* a;  // Lh split rows of this spin: [K][nmax][2 ldh] halves
@@ -247,10 +254,11 @@ struct PairSplitArgs {
   int W, n, Np, nmax, ldN, rowb, sp, nkb, ntiles;
 };
 
-template <class H>
-__global__ __launch_bounds__(ExSplitCfg::NT, ExSplitCfg::WAVES_PER_EU) void exchange_pair_split_kernel(
+template <class H, class C>
+__global__ __launch_bounds__(C::NT, C::WAVES_PER_EU) void exchange_pair_split_kernel(
     PairSplitArgs p, double2* __restrict__ part, int ntg, int nwt, int gs) {
-  using C = ExSplitCfg;
+  static_assert(SplitStage<C::BM, C::BN>::BYTES <= EXS_TAB_OFF && 4 * C::WM * C::BN * 16 <= EXS_TAB_OFF,
+                "operand stage and column sums fit");
   int rt, wt;
   if (!xcd_tile(blockIdx.x, ntg, nwt, gs, rt, wt)) return;
   const int z0 = wt * (C::BN / 2);
@@ -294,11 +302,11 @@ __global__ __launch_bounds__(ExSplitCfg::NT, ExSplitCfg::WAVES_PER_EU) void exch
 
 int exchange_pair_split_rows() { return ExSplitCfg::BM; }
 
-hipError_t launch_exchange_pair_split(int mode, const StepDims& d, int W, const PairLaunch& pl,
-                                      const unsigned short* v, const float* v_unscale, const unsigned short* th,
-                                      const float* th_unscale, const float* theta, double2* part, int sp,
-                                      hipStream_t s, int gs) {
-  using C = ExSplitCfg;
+template <class C>
+static hipError_t launch_exchange_pair_split_t(int mode, const StepDims& d, int W, const PairLaunch& pl,
+                                               const unsigned short* v, const float* v_unscale,
+                                               const unsigned short* th, const float* th_unscale, const float* theta,
+                                               double2* part, int sp, hipStream_t s, int gs) {
   if (gs < 1) gs = C::GS;
   const int n = sp == 0 ? d.na : d.nb;
   if (W == 0 || pl.ntg == 0) return hipSuccess;
@@ -314,12 +322,23 @@ hipError_t launch_exchange_pair_split(int mode, const StepDims& d, int W, const 
                   W, n, Np, d.nmax, d.ldN, rowb, sp, d.ldh / 32, n > 0 ? pl.ntiles : 0};
   const int per = ceil_div(pl.ntg * nwt, 8);
   if (mode == SPLIT_BF16)
-    hipLaunchKernelGGL(exchange_pair_split_kernel<HalfBF16>, dim3(8 * per), dim3(C::NT), 0, s, p, part, pl.ntg,
+    hipLaunchKernelGGL((exchange_pair_split_kernel<HalfBF16, C>), dim3(8 * per), dim3(C::NT), 0, s, p, part, pl.ntg,
                        nwt, gs);
   else
-    hipLaunchKernelGGL(exchange_pair_split_kernel<HalfF16>, dim3(8 * per), dim3(C::NT), 0, s, p, part, pl.ntg,
+    hipLaunchKernelGGL((exchange_pair_split_kernel<HalfF16, C>), dim3(8 * per), dim3(C::NT), 0, s, p, part, pl.ntg,
                        nwt, gs);
   return hipGetLastError();
+}
+
+hipError_t launch_exchange_pair_split(int mode, const StepDims& d, int W, const PairLaunch& pl,
+                                      const unsigned short* v, const float* v_unscale, const unsigned short* th,
+                                      const float* th_unscale, const float* theta, double2* part, int sp,
+                                      hipStream_t s, int gs, int tile) {
+  if (tile == SPLIT_TILE_NARROW)
+    return launch_exchange_pair_split_t<ExPairNarrowCfg>(mode, d, W, pl, v, v_unscale, th, th_unscale, theta, part,
+                                                         sp, s, gs);
+  return launch_exchange_pair_split_t<ExSplitCfg>(mode, d, W, pl, v, v_unscale, th, th_unscale, theta, part, sp, s,
+                                                  gs);
 }
 
 // ---------------------------------------------------------------------------
@@ -336,12 +355,14 @@ hipError_t launch_exchange_pair_split(int mode, const StepDims& d, int W, const 
 // halves leave as contiguous runs: (p, q) rows of VB_Q pairs and the mirror
 // (q, p) rows of VB_P pairs (full 128-byte lines).
 constexpr int VB_P = 16, VB_Q = 10;
-static_assert(VB_P * VB_Q == ExSplitCfg::BN, "one block per tile");
-// walkers per LDS pass of the store (the waves of one row half)
-constexpr int VHS_ZPASS = ExSplitCfg::BM / 2 / ExSplitCfg::WM;
-constexpr int VHS_LDS_BYTES = SplitStage<ExSplitCfg::BM, ExSplitCfg::BN>::BYTES > VHS_ZPASS * ExSplitCfg::BN * 8
-                                  ? SplitStage<ExSplitCfg::BM, ExSplitCfg::BN>::BYTES
-                                  : VHS_ZPASS * ExSplitCfg::BN * 8;
+// walkers per LDS pass of the store (the waves of one row half), and the LDS
+template <class C>
+struct VhsLds {
+  static_assert(VB_P * VB_Q == C::BN, "one block per tile");
+  static constexpr int ZPASS = C::BM / 2 / C::WM;
+  static constexpr int BYTES = SplitStage<C::BM, C::BN>::BYTES > ZPASS * C::BN * 8 ? SplitStage<C::BM, C::BN>::BYTES
+                                                                                    : ZPASS * C::BN * 8;
+};
 
 struct VhsSplitArgs {
   const unsigned short* a;  // xs split rows [2 W][2 ldhK]
@@ -355,11 +376,10 @@ struct VhsSplitArgs {
   float sdt;
 };
 
-template <class H>
-__global__ __launch_bounds__(ExSplitCfg::NT, ExSplitCfg::WAVES_PER_EU) void vhs_split_kernel(VhsSplitArgs p,
-                                                                                             int ntn, int ntm) {
-  using C = ExSplitCfg;
+template <class H, class C>
+__global__ __launch_bounds__(C::NT, C::WAVES_PER_EU) void vhs_split_kernel(VhsSplitArgs p, int ntn, int ntm) {
   constexpr int FM = C::BM / C::WM / 16, FN = C::BN / C::WN / 16;
+  constexpr int VHS_LDS_BYTES = VhsLds<C>::BYTES, VHS_ZPASS = VhsLds<C>::ZPASS;
   int tn, tm;  // consecutive tiles on one XCD share the packed-L tile
   if (!xcd_tile(blockIdx.x, ntn, ntm, 1, tn, tm)) return;
   __shared__ __attribute__((aligned(16))) unsigned short vs_lds[VHS_LDS_BYTES / 2];
@@ -479,22 +499,30 @@ std::vector<int2> vhs_split_pairs(int N, const std::vector<int2>& blk) {
   return pq;
 }
 
-hipError_t launch_vhs_split(int mode, const StepDims& d, int W, const unsigned short* xs, const float* xs_unscale,
-                            const unsigned short* lt, const float* lt_unscale, const int2* blk, int nblk, float* vhs,
-                            unsigned* vmax, double sdt, hipStream_t s) {
-  using C = ExSplitCfg;
+template <class C>
+static hipError_t launch_vhs_split_t(int mode, const StepDims& d, int W, const unsigned short* xs,
+                                     const float* xs_unscale, const unsigned short* lt, const float* lt_unscale,
+                                     const int2* blk, int nblk, float* vhs, unsigned* vmax, double sdt, hipStream_t s) {
   if (W == 0) return hipSuccess;
   if (d.ldhK % 32 != 0) return hipErrorInvalidValue;
   const int rowb = 2 * d.ldhK * 2;
-  if ((double)C::BM * rowb >= (double)SPLIT_ROW_NONE) return hipErrorInvalidValue;
+  if ((double)(C::BM > C::BN ? C::BM : C::BN) * rowb >= (double)SPLIT_ROW_NONE) return hipErrorInvalidValue;
   const int ntm = ceil_div(2 * W, C::BM), ntn = nblk;
   VhsSplitArgs p{xs, xs_unscale, lt, lt_unscale, blk, vhs, vmax, W, nblk, d.N, d.ldV, rowb, d.ldhK / 32, (float)sdt};
   const int per = ceil_div(ntm * ntn, 8);
   if (mode == SPLIT_BF16)
-    hipLaunchKernelGGL(vhs_split_kernel<HalfBF16>, dim3(8 * per), dim3(C::NT), 0, s, p, ntn, ntm);
+    hipLaunchKernelGGL((vhs_split_kernel<HalfBF16, C>), dim3(8 * per), dim3(C::NT), 0, s, p, ntn, ntm);
   else
-    hipLaunchKernelGGL(vhs_split_kernel<HalfF16>, dim3(8 * per), dim3(C::NT), 0, s, p, ntn, ntm);
+    hipLaunchKernelGGL((vhs_split_kernel<HalfF16, C>), dim3(8 * per), dim3(C::NT), 0, s, p, ntn, ntm);
   return hipGetLastError();
+}
+
+hipError_t launch_vhs_split(int mode, const StepDims& d, int W, const unsigned short* xs, const float* xs_unscale,
+                            const unsigned short* lt, const float* lt_unscale, const int2* blk, int nblk, float* vhs,
+                            unsigned* vmax, double sdt, hipStream_t s, int tile) {
+  if (tile == SPLIT_TILE_NARROW)
+    return launch_vhs_split_t<VhsNarrowCfg>(mode, d, W, xs, xs_unscale, lt, lt_unscale, blk, nblk, vhs, vmax, sdt, s);
+  return launch_vhs_split_t<ExSplitCfg>(mode, d, W, xs, xs_unscale, lt, lt_unscale, blk, nblk, vhs, vmax, sdt, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -152,3 +152,116 @@ def test_autotune_cache_round_trip(tmp_path):
     for e in es:
         assert torch.isfinite(torch.view_as_real(e)).all()
     b.close()
+
+
+# ---------------------------------------------------------------------------
+# Tile shapes (afqmc_get_tuning / afqmc_set_tuning / afqmc_autotune)
+# ---------------------------------------------------------------------------
+TILE_CHOICES = [((160, 160), 0, (160, 160)), ((160, 64), 4, (160, 160)), ((160, 160), 2, (64, 160)),
+                ((160, 64), 32, (64, 160))]
+
+
+def _pair_systems(seed0):
+    import torch
+
+    from paper_2209_04015_amd import afqmc
+
+    out = []
+    for s, (N, n, W) in enumerate(SIZES):
+        K = 4 * N
+        h1, L = inputs.hamiltonian(N, K, K / 5.0, seed=seed0 + s)
+        phiT = inputs.trial(h1, n)
+        pa = inputs.walkers_perturbed(phiT, W, 0.2, seed=seed0 + s, stream=0)
+        pb = inputs.walkers_perturbed(phiT, W, 0.2, seed=seed0 + s, stream=1)
+        ham = afqmc.Hamiltonian(h1, L, phiT, phiT, dt=0.005, max_walkers=W, precision="fp16x3", exchange="pair")
+        xs = torch.as_tensor(inputs.fields(W, K, 3, seed=seed0 + s), device="cuda")
+        out.append(dict(pa=pa, pb=pb, ham=ham, xs=xs, W=W))
+    return out
+
+
+def test_tile_shapes_do_not_change_results():
+    """FP16X3 with pair integrals: every offered exchange and VHS tile shape and
+    group size gives the same bits, step by step (each output element sums
+    the same terms in the same order; only the grid changes)."""
+    import torch
+
+    sysd = _pair_systems(41)
+    outs = []
+    for ex_tile, gs, vhs_tile in TILE_CHOICES:
+        print(f"[gpu] tiles exchange {ex_tile} group {gs} vhs {vhs_tile}", flush=True)
+        res = []
+        for d, w in zip(sysd, _fresh_walkers(sysd)):
+            d["ham"].set_tuning(ex_tile, gs, vhs_tile)
+            assert d["ham"].tuning() == {"exchange_tile": ex_tile, "exchange_group": gs, "vhs_tile": vhs_tile}
+            d["ham"].overlap(w)
+            es = torch.empty((3, d["W"], 3), dtype=torch.complex128, device="cuda")
+            for k in range(3):
+                d["ham"].step(w, d["xs"][k], do_qr=True, energy_out=es[k], reuse=(k > 0))
+            res.append((w.phi_a.clone(), w.phi_b.clone(), w.log_w.clone(), es.clone()))
+        outs.append(res)
+    for c in range(1, len(TILE_CHOICES)):
+        for i in range(len(SIZES)):
+            for a, b in zip(outs[0][i], outs[c][i]):
+                assert torch.equal(a, b), f"choice {TILE_CHOICES[c]} system {i}"
+    for d in sysd:
+        d["ham"].close()
+
+
+def test_tuning_offers_only_built_shapes():
+    from paper_2209_04015_amd import afqmc
+
+    N, n, K, W = 20, 4, 40, 5
+    h1, L = inputs.hamiltonian(N, K, 8.0, seed=3)
+    phiT = inputs.trial(h1, n)
+    h32 = afqmc.Hamiltonian(h1, L, phiT, phiT, dt=0.005, max_walkers=W, precision="fp32")
+    assert h32.tuning() == {"exchange_tile": (192, 160), "exchange_group": 0, "vhs_tile": (64, 64)}
+    with pytest.raises(afqmc.AfqmcError) as e:
+        h32.set_tuning((160, 64), 0, (64, 64))
+    assert e.value.code == 4
+    h16 = afqmc.Hamiltonian(h1, L, phiT, phiT, dt=0.005, max_walkers=W, precision="fp16x3", exchange="pair")
+    assert h16.tuning() == {"exchange_tile": (160, 160), "exchange_group": 0, "vhs_tile": (160, 160)}
+    for bad in (((128, 128), 0, (160, 160)), ((160, 160), 0, (96, 160)), ((160, 160), -1, (160, 160))):
+        with pytest.raises(afqmc.AfqmcError):
+            h16.set_tuning(*bad)
+    assert h16.tuning()["exchange_tile"] == (160, 160)   # a refused call changes nothing
+    h32.close()
+    h16.close()
+
+
+def test_autotune_chooses_tile_shapes_and_caches_them(tmp_path):
+    import torch
+
+    from paper_2209_04015_amd import afqmc
+
+    sysd = _pair_systems(51)
+    ws = _fresh_walkers(sysd)
+    for d, w in zip(sysd, ws):
+        d["ham"].overlap(w)
+    b = afqmc.Batch([d["ham"] for d in sysd], ws, use_graph=True)
+    cache = tmp_path / "tune.txt"
+    b.autotune(cache)
+    lines = [l for l in cache.read_text().split("\n") if l.strip()]
+    assert len(lines) == len(SIZES)
+    chosen = [d["ham"].tuning() for d in sysd]
+    print(f"[gpu] autotune: {lines}", flush=True)
+    for l, t in zip(lines, chosen):
+        key, ex, vhs = l.split(" ")
+        assert key.startswith("tiles:") and ":p3:" in key
+        et, eg = t["exchange_tile"], t["exchange_group"]
+        assert ex == f"ex={et[0]}x{et[1]}/{eg}" and vhs == f"vhs={t['vhs_tile'][0]}x{t['vhs_tile'][1]}"
+        assert et in ((160, 160), (160, 64)) and t["vhs_tile"] in ((160, 160), (64, 160))
+        assert eg in (1, 2, 4, 8, 16, 32)
+    # reset, then the cache restores every choice without timing (nothing appended)
+    for d in sysd:
+        d["ham"].set_tuning((160, 160), 0, (160, 160))
+    b.autotune(cache)
+    assert [l for l in cache.read_text().split("\n") if l.strip()] == lines
+    assert [d["ham"].tuning() for d in sysd] == chosen
+    es = [torch.zeros((3, d["W"], 3), dtype=torch.complex128, device="cuda") for d in sysd]
+    b.step([d["xs"] for d in sysd], es, do_qr=True)
+    torch.cuda.synchronize()
+    for e in es:
+        assert torch.isfinite(torch.view_as_real(e)).all()
+    b.close()
+    for d in sysd:
+        d["ham"].close()
