@@ -1074,14 +1074,25 @@ hipError_t launch_counter_set(int* ctr, int v, hipStream_t s) {
 }
 
 // ===========================================================================
-// Re-orthogonalisation of the walkers (done once per block, Sec. IV timing runs): phi = Q R with R upper triangular
-// with a positive real diagonal (the unique such factorisation; Householder
-// QR followed by the phases D = diag(R_ii / |R_ii|) gives the same Q and R),
+// Re-orthogonalisation of the walkers: phi = Q R with R upper triangular and
+// a positive real diagonal (the unique such factorisation; Householder QR
+// followed by the phases D = diag(R_ii / |R_ii|) gives the same Q and R),
 // corr = sum ln R_ii.  Computed as Cholesky QR applied twice: S = A^H A,
 // S = R^H R, A <- A R^{-1}; the second pass restores orthogonality to FP64
-// rounding for any condition number below ~1e8, and R = R2 R1.  The N x n
-// block lives in LDS column-major; the Gram entries and the rows of the
-// triangular solve spread over the block, the n x n Cholesky runs in one wave.
+// rounding for any condition number below ~1e8, and R = R2 R1.  One
+// workgroup per (walker, spin) holds the N x n block in LDS, column-major.
+//   Gram: the real Gram matrix X^T X of X = [Re a_0, Im a_0, Re a_1, ...]
+//     (N x 2n) on the FP64 matrix cores, one wave per 16 x 16 block of its
+//     upper triangle; S_ij = G[2i][2j] + G[2i+1][2j+1]
+//     + i (G[2i][2j+1] - G[2i+1][2j]) assembled across lanes.
+//   Cholesky: every thread keeps up to QR_NPT entries (i <= j) of S in
+//     registers; step k publishes row k (final once the previous steps are
+//     applied) to LDS, and after one barrier every entry below it is reduced,
+//     S_ij -= conj(S_ki) S_kj / S_kk; the square roots come at the end,
+//     R_ij = S_ij / sqrt(S_ii).
+//   A <- A R^{-1}: forward substitution, one row of A per thread held in
+//     registers (the column count is a template bound), R read from LDS as
+//     broadcasts.
 // ===========================================================================
 
 constexpr int QR_THREADS = 512;
@@ -1090,109 +1101,149 @@ constexpr int QR_THREADS = 512;
 // of different columns spreads over the LDS banks
 static __host__ __device__ inline int qr_col_stride(int N) { return N + ((9 - N % 8) % 8); }
 
+// R rows are read QR_BPAD entries past the last row by the unrolled
+// substitution (values unused): padding behind the n x n block
+constexpr int QR_BPAD = 48;
+
 size_t qr_lds_bytes_for(int N, int n) {
-  return (size_t)n * qr_col_stride(N) * sizeof(double2) + (size_t)n * n * sizeof(double2) + n * sizeof(double) + 64;
+  return (size_t)n * qr_col_stride(N) * sizeof(double2) + ((size_t)n * n + QR_BPAD) * sizeof(double2) +
+         n * sizeof(double) + 64;
 }
 size_t qr_lds_bytes(const StepDims& d) { return qr_lds_bytes_for(d.N, d.nmax); }
 
+template <int NMAX>
 __global__ __launch_bounds__(QR_THREADS) void qr_kernel(StepDims d, double2* __restrict__ phi_a,
                                                         double2* __restrict__ phi_b,
                                                         double* __restrict__ corr,
                                                         int* __restrict__ status) {
   extern __shared__ double2 qr_lds[];
   constexpr int NWAVE = QR_THREADS / 64;
+  constexpr int NPT = (NMAX * (NMAX + 1) / 2 + QR_THREADS - 1) / QR_THREADS;
   const int z = blockIdx.x, sp = blockIdx.y;
   const int n = sp == 0 ? d.na : d.nb;
   const int N = d.N, Np = qr_col_stride(N);
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (n == 0) {
     if (tid == 0) corr[2 * z + sp] = 0.0;
     return;
   }
-  double2* A = qr_lds;                              // A[j * Np + p]
-  double2* R = A + (size_t)n * Np;                  // R[i * n + j], i <= j: Gram, then its factor
-  double* rinv = reinterpret_cast<double*>(R + n * n);  // 1 / R_jj
-  int* flag = reinterpret_cast<int*>(rinv + n);            // a pivot vanished (set by the Cholesky wave)
+  double2* A = qr_lds;                                  // A[j * Np + p]
+  double2* B = A + (size_t)n * Np;                                // [n][n]: S, then the rows of R
+  double* rinv = reinterpret_cast<double*>(B + n * n + QR_BPAD);  // 1 / R_jj
+  const double* Ad = reinterpret_cast<const double*>(A);
   double2* phi = (sp == 0 ? phi_a : phi_b) + (size_t)z * N * n;
 
   for (int e = tid; e < N * n; e += QR_THREADS) {
     const int p = e / n, j = e - p * n;
     A[j * Np + p] = phi[e];
   }
+  // this thread's Cholesky entries (i, j), i <= j, in row-major order
+  const int npair = n * (n + 1) / 2;
+  int ei[NPT], ej[NPT];
+#pragma unroll
+  for (int t = 0; t < NPT; ++t) {
+    int r = tid + t * QR_THREADS, i = 0;
+    if (r < npair) {
+      while (r >= n - i) r -= n - i, ++i;
+      ei[t] = i;
+      ej[t] = i + r;
+    } else {
+      ei[t] = ej[t] = -1;
+    }
+  }
   bool failed = false;
-  if (tid == 0) *flag = 0;
-  double lnr = 0.0;  // sum ln R_kk of both passes (wave 0, lane 0 = thread 0)
+  double lnr = 0.0;  // sum ln R_kk of both passes (thread 0)
   __syncthreads();
 
-  const int npair = n * (n + 1) / 2;
+  const int nc = 2 * n, nbk = (nc + 15) / 16, nblk = nbk * (nbk + 1) / 2;
   for (int pass = 0; pass < 2; ++pass) {
-    // Gram S = A^H A (upper triangle), one entry per thread, summed over p in
-    // a fixed order (four interleaved partial sums)
-    for (int e = tid; e < npair; e += QR_THREADS) {
-      int i = 0, r = e;
-      while (r >= n - i) r -= n - i, ++i;  // e -> (i, j = i + r)
-      const int j = i + r;
-      const double2* ai = A + (size_t)i * Np;
-      const double2* aj = A + (size_t)j * Np;
-      double2 s0 = make_double2(0.0, 0.0), s1 = s0, s2 = s0, s3 = s0;
-      int q = 0;
-      for (; q + 4 <= N; q += 4) {
-        s0 = cadd(s0, cmul(cconj(ai[q]), aj[q]));
-        s1 = cadd(s1, cmul(cconj(ai[q + 1]), aj[q + 1]));
-        s2 = cadd(s2, cmul(cconj(ai[q + 2]), aj[q + 2]));
-        s3 = cadd(s3, cmul(cconj(ai[q + 3]), aj[q + 3]));
+    // ---- Gram: upper 16 x 16 blocks of X^T X, two k steps per iteration ----
+    for (int b = wid; b < nblk; b += NWAVE) {
+      int bi = 0, r = b;
+      while (r >= nbk - bi) r -= nbk - bi, ++bi;
+      const int bj = bi + r;
+      const int c1 = 16 * bi + (lane & 15), c2 = 16 * bj + (lane & 15);
+      const bool ok1 = c1 < nc, ok2 = c2 < nc;
+      const int o1 = 2 * (c1 >> 1) * Np + (c1 & 1), o2 = 2 * (c2 >> 1) * Np + (c2 & 1);
+      doublex4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+      for (int pb = 0; pb < N; pb += 8) {  // uniform trip count: the matrix instructions see every lane
+        const int p0 = pb + (lane >> 4), p1 = p0 + 4;
+        const double a0 = ok1 && p0 < N ? Ad[o1 + 2 * p0] : 0.0, b0 = ok2 && p0 < N ? Ad[o2 + 2 * p0] : 0.0;
+        const double a1 = ok1 && p1 < N ? Ad[o1 + 2 * p1] : 0.0, b1 = ok2 && p1 < N ? Ad[o2 + 2 * p1] : 0.0;
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
       }
-      for (; q < N; ++q) s0 = cadd(s0, cmul(cconj(ai[q]), aj[q]));
-      R[i * n + j] = cadd(cadd(s0, s1), cadd(s2, s3));
+      // register r of lane l: G[16 bi + l / 16 + 4 r][16 bj + l % 16]
+      const int g = lane >> 4, c = lane & 15;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const double v = acc0[rr] + acc1[rr];
+        const double v01 = __shfl(v, lane + 1 < 64 ? lane + 1 : lane, 64);
+        const double v10 = __shfl(v, lane + 16 < 64 ? lane + 16 : lane, 64);
+        const double v11 = __shfl(v, lane + 17 < 64 ? lane + 17 : lane, 64);
+        if (!(g & 1) && !(c & 1)) {
+          const int i = (16 * bi + g + 4 * rr) >> 1, j = (16 * bj + c) >> 1;
+          if (i <= j && j < n) B[i * n + j] = make_double2(v + v11, v01 - v10);
+        }
+      }
     }
     __syncthreads();
-    // Cholesky S = R^H R in place, right-looking, by one wave (its LDS
-    // accesses stay in program order, so the steps need no barrier): row k of
-    // R from the updated S, then the trailing block S_ij -= conj(R_ki) R_kj
+    // ---- Cholesky, entries in registers, one barrier per step ----
+    double2 sv[NPT];
+#pragma unroll
+    for (int t = 0; t < NPT; ++t) sv[t] = ei[t] >= 0 ? B[ei[t] * n + ej[t]] : make_double2(0.0, 0.0);
+    __syncthreads();  // every entry is read before rows are republished
+    for (int k = 0; k < n; ++k) {
+#pragma unroll
+      for (int t = 0; t < NPT; ++t)
+        if (ei[t] == k) B[k * n + ej[t]] = sv[t];
+      __syncthreads();
+      const double dk = B[k * n + k].x;
+      if (!(dk > 0.0) || !isfinite(dk)) {  // a vanished column: every thread reads the same pivot
+        failed = true;
+        break;
+      }
+      const double idk = 1.0 / dk;
+#pragma unroll
+      for (int t = 0; t < NPT; ++t)
+        if (ei[t] > k) sv[t] = csub(sv[t], cscale(cmul(cconj(B[k * n + ei[t]]), B[k * n + ej[t]]), idk));
+    }
+    if (failed) break;
+    __syncthreads();
+    if (tid < n) rinv[tid] = 1.0 / sqrt(B[tid * n + tid].x);
     if (wid == 0) {
-      for (int k = 0; k < n; ++k) {
-        const double dk = R[k * n + k].x;
-        if (!(dk > 0.0) || !isfinite(dk)) {  // a vanished column (uniform in the wave)
-          if (lane == 0) *flag = 1;
-          break;
-        }
-        const double rk = sqrt(dk), ik = 1.0 / rk;
-        for (int jj = k + 1 + lane; jj < n; jj += 64) R[k * n + jj] = cscale(R[k * n + jj], ik);
-        if (lane == 0) {
-          R[k * n + k] = make_double2(rk, 0.0);
-          rinv[k] = ik;
-          lnr += log(rk);
-        }
-        // row k is read by other lanes below: keep the compiler from moving
-        // LDS accesses across (the wave's LDS operations run in order)
-        __builtin_amdgcn_wave_barrier();
-        const int m = n - 1 - k;  // trailing size: the m x m square, lanes below the diagonal idle
-        for (int e = lane; e < m * m; e += 64) {
-          const int a = e / m, b = e - a * m;
-          if (b < a) continue;
-          const int ii = k + 1 + a, jj = k + 1 + b;
-          R[ii * n + jj] = csub(R[ii * n + jj], cmul(cconj(R[k * n + ii]), R[k * n + jj]));
-        }
-        __builtin_amdgcn_wave_barrier();  // the next pivot reads the updated block
-      }
+      double l = lane < n ? 0.5 * log(B[lane * n + lane].x) : 0.0;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o, 64);
+      lnr += l;
     }
     __syncthreads();
-    if (*flag) {
-      failed = true;
-      break;
-    }
-    // A <- A R^{-1}: forward substitution along each row, in place
+#pragma unroll
+    for (int t = 0; t < NPT; ++t)
+      if (ei[t] >= 0 && ej[t] > ei[t]) B[ei[t] * n + ej[t]] = cscale(sv[t], rinv[ei[t]]);
+    __syncthreads();
+    // ---- A <- A R^{-1}: one row per thread, in registers; column i is
+    // final once scaled, then removed from the later columns (their entries
+    // past n use padding values and are never stored) ----
     for (int q = tid; q < N; q += QR_THREADS) {
-      for (int jc = 0; jc < n; ++jc) {
-        double2 u0 = make_double2(0.0, 0.0), u1 = u0;
-        int ic = 0;
-        for (; ic + 2 <= jc; ic += 2) {
-          u0 = cadd(u0, cmul(A[(size_t)ic * Np + q], R[ic * n + jc]));
-          u1 = cadd(u1, cmul(A[(size_t)(ic + 1) * Np + q], R[(ic + 1) * n + jc]));
+      double2 a[NMAX];
+#pragma unroll
+      for (int j = 0; j < NMAX; ++j) a[j] = j < n ? A[(size_t)j * Np + q] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < NMAX; ++i) {
+        if (i < n) {  // uniform
+          const double2 qi = cscale(a[i], rinv[i]);
+          a[i] = qi;
+          const double2* Bi = B + i * n;
+#pragma unroll
+          for (int j = i + 1; j < NMAX; ++j) a[j] = csub(a[j], cmul(qi, Bi[j]));
         }
-        if (ic < jc) u0 = cadd(u0, cmul(A[(size_t)ic * Np + q], R[ic * n + jc]));
-        A[(size_t)jc * Np + q] = cscale(csub(A[(size_t)jc * Np + q], cadd(u0, u1)), rinv[jc]);
+        __builtin_amdgcn_sched_barrier(0);
       }
+#pragma unroll
+      for (int j = 0; j < NMAX; ++j)
+        if (j < n) A[(size_t)j * Np + q] = a[j];
     }
     __syncthreads();
   }
@@ -1213,8 +1264,15 @@ __global__ __launch_bounds__(QR_THREADS) void qr_kernel(StepDims d, double2* __r
 
 hipError_t launch_qr(const StepDims& d, int W, double2* phi_a, double2* phi_b, double* corr,
                      int* status, hipStream_t s) {
-  hipLaunchKernelGGL(qr_kernel, dim3(W, 2), dim3(QR_THREADS), qr_lds_bytes(d), s, d, phi_a, phi_b,
-                     corr, status);
+  const size_t lds = qr_lds_bytes(d);
+  if (d.nmax <= 16)
+    hipLaunchKernelGGL(qr_kernel<16>, dim3(W, 2), dim3(QR_THREADS), lds, s, d, phi_a, phi_b, corr, status);
+  else if (d.nmax <= 32)
+    hipLaunchKernelGGL(qr_kernel<32>, dim3(W, 2), dim3(QR_THREADS), lds, s, d, phi_a, phi_b, corr, status);
+  else if (d.nmax <= 48)
+    hipLaunchKernelGGL(qr_kernel<48>, dim3(W, 2), dim3(QR_THREADS), lds, s, d, phi_a, phi_b, corr, status);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -1238,7 +1296,13 @@ hipError_t launch_ortho_update(int W, const double* corr, double2* log_ovlp, dou
 hipError_t set_kernel_attributes(const StepDims& d) {
   hipError_t e;
   const int big = 160 * 1024;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(qr_kernel),
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(qr_kernel<16>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(qr_kernel<32>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(qr_kernel<48>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, big);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(gf_kernel<float>),
