@@ -530,12 +530,14 @@ def _kernel_of(phase, precision, algo):
     T = {"fp32": "float", "fp64": "double", "bf16x3": "float", "fp16x3": "float"}[precision]
     if phase == "exchange":
         base = ("exchange_pair" if algo == "pair" else "exchange") + ("_split_kernel" if split else "_kernel")
+        if split and algo == "pair":   # the default (wide) walker tile of the split pair kernel
+            return base, f"{base}<{H},SplitCfgT<160,160>>"
         return base, f"{base}<{H if split else T}>"
     if phase == "propagate":
         return "prop_fused_kernel", "prop_fused_kernel<4>"
     if phase == "vhs":
-        if precision == "fp16x3":   # the VHS runs on split operands only in FP16X3
-            return "vhs_split_kernel", "vhs_split_kernel<HalfF16>"
+        if precision == "fp16x3":   # the VHS runs on split operands only in FP16X3 (default wide tile)
+            return "vhs_split_kernel", "vhs_split_kernel<HalfF16,SplitCfgT<160,160>>"
         # tile template arguments of the FP32 / FP64 VHS instances (step_kernels.hip)
         return "vhs_kernel", {"double": "vhs_kernel<double, 64, 64, 16, 2, 2>",
                               "float": "vhs_kernel<float, 64, 64, 32, 2, 2>"}[T]
