@@ -1718,7 +1718,8 @@ int afqmc_msd_set_hamiltonian(afqmc_msd* t, int K, const double* host_h1, const 
       (rc = dalloc_t(t, &w.ppart, Wc * 2 * e.nchunk * e.Dmax)) || (rc = dalloc_t(t, &w.tt, Wc * 2 * K1)) ||
       (rc = dalloc_t(t, &w.kt, Wc * 2 * (size_t)K)) || (rc = dalloc_t(t, &w.r1, Wc * 2 * e.Dmax)) ||
       (rc = dalloc_t(t, &w.vj, Wc * 2 * e.Dmax)) || (rc = dalloc_t(t, &w.vp, Wc * 2 * e.Dmax)) ||
-      (rc = dalloc_t(t, &w.sc, Wc * 4)) || (rc = dalloc_t(t, &w.G, Wc * 3 * e.Dmax * e.Dmax)))
+      (rc = dalloc_t(t, &w.sc, Wc * 4)) || (rc = dalloc_t(t, &w.G, Wc * 3 * e.Dmax * e.Dmax)) ||
+      (rc = dalloc_t(t, &w.cpart, Wc * MSD_CT_SPLITS * 3)))
     return rc;
   t->has_ham = true;
   return AFQMC_OK;

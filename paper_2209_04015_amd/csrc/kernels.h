@@ -326,7 +326,10 @@ struct MsdEnergyWork {
   double2* vp;     // [Wc][2][Dmax]
   double2* sc;     // [Wc][4]
   double2* G;      // [Wc][3][Dmax][Dmax]
+  double2* cpart;  // [Wc][MSD_CT_SPLITS][3] contraction partial sums
 };
+// workgroups per walker of the expansion contraction
+constexpr int MSD_CT_SPLITS = 32;
 size_t msd_energy_rp_lds(const MsdEnergyDims& e);
 hipError_t msd_energy_set_attributes(size_t rp_lds);
 // lr[g][r][ldL] from out[(g, p)][r] (rows_gp = (K + 1) N rows of S)

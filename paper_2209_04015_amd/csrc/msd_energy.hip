@@ -72,15 +72,15 @@ struct MsdUProb {
   }
 };
 
-constexpr int UBM = 64, UBN = 64, UBK = 16, UWM = 2, UWN = 2;
+constexpr int UBM = 128, UBN = 128, UBK = 16, UWM = 4, UWN = 2, UPIPE = 2;
 
 __global__ __launch_bounds__(UWM* UWN * 64) void msd_u_kernel(MsdUProb p, int S, int Smax, int K1,
                                                               double* __restrict__ u) {
-  __shared__ __attribute__((aligned(16))) double lds[TileLds<double, UBM, UBN, UBK>::ELEMS];
+  __shared__ __attribute__((aligned(16))) double lds[(UPIPE == 2 ? 2 : 1) * TileLds<double, UBM, UBN, UBK>::ELEMS];
   MF<double>::acc_t acc[UBM / UWM / 16][UBN / UWN / 16];
   const long m0 = (long)blockIdx.x * UBM;
   const int n0 = blockIdx.y * UBN;
-  mfma_tile_mainloop<double, UBM, UBN, UBK, UWM, UWN, false>(p, 0, (int)m0, n0, p.ldL, acc, lds);
+  mfma_tile_mainloop<double, UBM, UBN, UBK, UWM, UWN, false, MsdUProb, UPIPE>(p, 0, (int)m0, n0, p.ldL, acc, lds);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int wm = wid / UWN, wn = wid % UWN;
 #pragma unroll
@@ -313,11 +313,11 @@ struct MsdGramProb {
   }
 };
 
-constexpr int GBM = 64, GBN = 64, GBK = 16, GWM2 = 2, GWN2 = 2;
+constexpr int GBM = 128, GBN = 64, GBK = 16, GWM2 = 4, GWN2 = 2, GPIPE = 2;
 
 __global__ __launch_bounds__(GWM2* GWN2 * 64) void msd_gram_kernel(MsdGramProb p, int kdim,
                                                                    double2* __restrict__ G) {
-  __shared__ __attribute__((aligned(16))) double lds[TileLds<double, GBM, GBN, GBK>::ELEMS];
+  __shared__ __attribute__((aligned(16))) double lds[(GPIPE == 2 ? 2 : 1) * TileLds<double, GBM, GBN, GBK>::ELEMS];
   MF<double>::acc_t acc[GBM / GWM2 / 16][GBN / GWN2 / 16];
   const int b = blockIdx.z;
   int zl, s, sp;
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(GWM2* GWN2 * 64) void msd_gram_kernel(MsdGramProb p
   const int D = s ? p.D1 : p.D0, Dp = sp ? p.D1 : p.D0;
   const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
   if (m0 >= D || n0 >= 2 * Dp) return;  // uniform: tiles past this pair's sizes
-  mfma_tile_mainloop<double, GBM, GBN, GBK, GWM2, GWN2, false>(p, b, m0, n0, kdim, acc, lds);
+  mfma_tile_mainloop<double, GBM, GBN, GBK, GWM2, GWN2, false, MsdGramProb, GPIPE>(p, b, m0, n0, kdim, acc, lds);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int wm = wid / GWN2, wn = wid % GWN2;
   double* Gd = reinterpret_cast<double*>(G + (size_t)b * p.Dmax * p.Dmax);
@@ -366,6 +366,7 @@ struct MsdContractArgs {
   const double* yp;     // planar Y [W][2][2][nmax][ldv] (zero-determinant strings)
   const int* hlist;     // [2][Hmax]
   const int* qlist;     // [2][Qmax]
+  double2* part;        // [Wc][MSD_CT_SPLITS][3] partial sums of E1, EJ, EK
   double2* e;           // [W][3]
   int z0, nstr0, nstr_tot, nadj_tot, ncross, Dmax, nh[2], nmax, ldv, Hmax, Qmax;
 };
@@ -408,8 +409,13 @@ __device__ double2 small_det(double2 (&M)[KM][KM], int n) {
 // sum_g [t^2] det(A + t R_g) for the string u of spin s (A = its Y block):
 // sum over row pairs l1 < l2 and column pairs m1 < m2 of the signed
 // complementary minor of A times sum_g det R_g[{l1, l2}][{m1, m2}]
-__device__ double2 zero_det_quadratic(const MsdContractArgs& a, int u, int s, int k, int z, const int (&dix)[KM][KM],
-                                      const double2* Gs) {
+__device__ double2 zero_det_quadratic(const MsdContractArgs& a, int u, int s, int k, int z, const double2* Gs) {
+  const int nh = a.nh[s];
+  int qo[KM], hp[KM];
+  for (int l = 0; l < k; ++l) {
+    qo[l] = a.spos[((size_t)u * 2 + 1) * KM + l] * nh;
+    hp[l] = a.spos[((size_t)u * 2 + 0) * KM + l];
+  }
   double2 A[KM][KM];
   const size_t yplane = (size_t)a.nmax * a.ldv;
   const double* yr = a.yp + ((size_t)(2 * z + 0) * 2 + s) * yplane;
@@ -437,48 +443,67 @@ __device__ double2 zero_det_quadratic(const MsdContractArgs& a, int u, int s, in
           }
           double2 mn = small_det(M, k - 2);
           if ((l1 + l2 + m1 + m2) & 1) mn = make_double2(-mn.x, -mn.y);
-          const double2 g2 = csub(Gs[(size_t)dix[l1][m1] * a.Dmax + dix[l2][m2]],
-                                  Gs[(size_t)dix[l1][m2] * a.Dmax + dix[l2][m1]]);
+          const double2 g2 = csub(Gs[(size_t)(qo[l1] + hp[m1]) * a.Dmax + qo[l2] + hp[m2]],
+                                  Gs[(size_t)(qo[l1] + hp[m2]) * a.Dmax + qo[l2] + hp[m1]]);
           q2 = cadd(q2, cmul(mn, g2));
         }
   return q2;
 }
 
+// Workgroup (split, walker): strings u = split, split + MSD_CT_SPLITS, ...
+// and the doubly excited determinants likewise; its partial sums of E1, EJ,
+// EK (times s) go to part.  Each thread keeps the active-pair offsets of its
+// current string in its own LDS column (indexed by slot).
 __global__ __launch_bounds__(CT_T) void msd_contract_kernel(MsdContractArgs a) {
   __shared__ double2 red[CT_T / 64];
-  const int zl = blockIdx.x, z = a.z0 + zl, tid = threadIdx.x;
+  __shared__ int otab[2 * KM][CT_T];  // [slot][thread]: particle offsets q nh, then hole positions
+  const int sp_ = blockIdx.x, zl = blockIdx.y, z = a.z0 + zl, tid = threadIdx.x;
+  const int first = sp_ * CT_T + tid, stride = MSD_CT_SPLITS * CT_T;
   const double2* uz = a.uw + (size_t)z * a.nstr_tot;
   const double2* dz = a.sdet + (size_t)z * a.nstr_tot;
   const double2* az = a.sadj + (size_t)z * a.nadj_tot;
   double2 e1 = make_double2(0.0, 0.0), ej = e1, ek = e1;
-  for (int u = tid; u < a.nstr_tot; u += CT_T) {
+  for (int u = first; u < a.nstr_tot; u += stride) {
     const int k = a.srank[u];
     if (k == 0) continue;
     const int s = u >= a.nstr0 ? 1 : 0;
     const int nh = a.nh[s];
     const double2* adj = az + a.saoff[u];
-    int dix[KM][KM];  // d of (particle slot l, hole slot m)
-    for (int l = 0; l < k; ++l)
-      for (int m = 0; m < k; ++m) dix[l][m] = a.spos[((size_t)u * 2 + 1) * KM + l] * nh + a.spos[((size_t)u * 2 + 0) * KM + m];
+    // d(l, m) = qo[l] + hp[m]: particle slot l, hole slot m
+    int* qo = &otab[0][0] + tid;       // qo[l] at qo[l * CT_T]
+    int* hp = &otab[KM][0] + tid;
+    for (int l = 0; l < k; ++l) {
+      qo[l * CT_T] = a.spos[((size_t)u * 2 + 1) * KM + l] * nh;
+      hp[l * CT_T] = a.spos[((size_t)u * 2 + 0) * KM + l];
+    }
     const double2* r1 = a.r1 + ((size_t)zl * 2 + s) * a.Dmax;
     const double2* vj = a.vj + ((size_t)zl * 2 + s) * a.Dmax;
     const double2* vp = a.vp + ((size_t)zl * 2 + s) * a.Dmax;
     const double2* Gs = a.G + ((size_t)zl * 3 + s) * a.Dmax * a.Dmax;
     double2 l1 = make_double2(0.0, 0.0), lj = l1, lp = l1, qj = l1, qk = l1;
-    for (int m = 0; m < k; ++m)
+    for (int m = 0; m < k; ++m) {
+      const int hm = hp[m * CT_T];
       for (int l = 0; l < k; ++l) {
         const double2 f = adj[m * k + l];  // adj(A)[m][l] at (q_l, h_m)
-        const int d = dix[l][m];
+        const int ql = qo[l * CT_T];
+        const int d = ql + hm;
         l1 = cadd(l1, cmul(f, r1[d]));
         lj = cadd(lj, cmul(f, vj[d]));
         lp = cadd(lp, cmul(f, vp[d]));
-        for (int m2 = 0; m2 < k; ++m2)
+        const double2* Gd = Gs + (size_t)d * a.Dmax;
+        for (int m2 = 0; m2 < k; ++m2) {
+          const int hm2 = hp[m2 * CT_T];
+          const double2* Gl = Gs + (size_t)(ql + hm2) * a.Dmax + hm;
+          const double2* Gdm = Gd + hm2;
           for (int l2 = 0; l2 < k; ++l2) {
+            const int ql2 = qo[l2 * CT_T];
             const double2 ff = cmul(f, adj[m2 * k + l2]);
-            qj = cadd(qj, cmul(ff, Gs[(size_t)d * a.Dmax + dix[l2][m2]]));
-            qk = cadd(qk, cmul(ff, Gs[(size_t)dix[l][m2] * a.Dmax + dix[l2][m]]));
+            qj = cadd(qj, cmul(ff, Gdm[ql2]));
+            qk = cadd(qk, cmul(ff, Gl[ql2]));
           }
+        }
       }
+    }
     const double2 w = uz[u];
     e1 = csub(e1, cmul(w, l1));
     ej = csub(ej, cmul(w, lj));
@@ -489,25 +514,31 @@ __global__ __launch_bounds__(CT_T) void msd_contract_kernel(MsdContractArgs a) {
       ej = cadd(ej, cscale(cmul(f, qj), 0.5));
       ek = csub(ek, cscale(cmul(f, qk), 0.5));
     } else if (k >= 2) {
-      ej = cadd(ej, cmul(w, zero_det_quadratic(a, u, s, k, z, dix, Gs)));
+      ej = cadd(ej, cmul(w, zero_det_quadratic(a, u, s, k, z, Gs)));
     }
   }
   const double2* Gab = a.G + ((size_t)zl * 3 + 2) * a.Dmax * a.Dmax;
-  for (int x = tid; x < a.ncross; x += CT_T) {
+  for (int x = first; x < a.ncross; x += stride) {
     const int ua = a.xa[x], ub = a.xb[x];
     const int ka = a.srank[ua], kb = a.srank[ub];
     const double2* adja = az + a.saoff[ua];
     const double2* adjb = az + a.saoff[ub];
+    int* qb = &otab[0][0] + tid;  // the beta string's offsets
+    int* hb = &otab[KM][0] + tid;
+    for (int l = 0; l < kb; ++l) {
+      qb[l * CT_T] = a.spos[((size_t)ub * 2 + 1) * KM + l] * a.nh[1];
+      hb[l * CT_T] = a.spos[((size_t)ub * 2 + 0) * KM + l];
+    }
     double2 cr = make_double2(0.0, 0.0);
     for (int m = 0; m < ka; ++m)
       for (int l = 0; l < ka; ++l) {
         const int d = a.spos[((size_t)ua * 2 + 1) * KM + l] * a.nh[0] + a.spos[((size_t)ua * 2 + 0) * KM + m];
+        const double2* Gd = Gab + (size_t)d * a.Dmax;
         double2 inner = make_double2(0.0, 0.0);
-        for (int m2 = 0; m2 < kb; ++m2)
-          for (int l2 = 0; l2 < kb; ++l2) {
-            const int d2 = a.spos[((size_t)ub * 2 + 1) * KM + l2] * a.nh[1] + a.spos[((size_t)ub * 2 + 0) * KM + m2];
-            inner = cadd(inner, cmul(adjb[m2 * kb + l2], Gab[(size_t)d * a.Dmax + d2]));
-          }
+        for (int m2 = 0; m2 < kb; ++m2) {
+          const double2* Gdm = Gd + hb[m2 * CT_T];
+          for (int l2 = 0; l2 < kb; ++l2) inner = cadd(inner, cmul(adjb[m2 * kb + l2], Gdm[qb[l2 * CT_T]]));
+        }
         cr = cadd(cr, cmul(adja[m * ka + l], inner));
       }
     ej = cadd(ej, cscale(cr, a.xc[x]));
@@ -516,16 +547,35 @@ __global__ __launch_bounds__(CT_T) void msd_contract_kernel(MsdContractArgs a) {
   ej = block_sum2(ej, red);
   ek = block_sum2(ek, red);
   if (tid == 0) {
-    const double2 s = a.ratio[z];
-    const double2* sc = a.sc + (size_t)zl * 4;
-    e1 = cadd(e1, cmul(s, sc[3]));
-    ej = cadd(ej, cscale(cmul(s, sc[0]), 0.5));
-    ek = csub(ek, cscale(cmul(s, cadd(sc[1], sc[2])), 0.5));
-    const double2 is = cinv(s);
-    a.e[(size_t)z * 3 + 0] = cmul(e1, is);
-    a.e[(size_t)z * 3 + 1] = cmul(ej, is);
-    a.e[(size_t)z * 3 + 2] = cmul(ek, is);
+    double2* o = a.part + ((size_t)zl * MSD_CT_SPLITS + sp_) * 3;
+    o[0] = e1;
+    o[1] = ej;
+    o[2] = ek;
   }
+}
+
+// Per walker: the splits' partial sums in a fixed order, the reference's
+// terms s sum_g ..., division by s.
+__global__ void msd_contract_final_kernel(MsdContractArgs a, int nz) {
+  const int zl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (zl >= nz) return;
+  const int z = a.z0 + zl;
+  double2 e1 = make_double2(0.0, 0.0), ej = e1, ek = e1;
+  for (int sp = 0; sp < MSD_CT_SPLITS; ++sp) {
+    const double2* o = a.part + ((size_t)zl * MSD_CT_SPLITS + sp) * 3;
+    e1 = cadd(e1, o[0]);
+    ej = cadd(ej, o[1]);
+    ek = cadd(ek, o[2]);
+  }
+  const double2 s = a.ratio[z];
+  const double2* sc = a.sc + (size_t)zl * 4;
+  e1 = cadd(e1, cmul(s, sc[3]));
+  ej = cadd(ej, cscale(cmul(s, sc[0]), 0.5));
+  ek = csub(ek, cscale(cmul(s, cadd(sc[1], sc[2])), 0.5));
+  const double2 is = cinv(s);
+  a.e[(size_t)z * 3 + 0] = cmul(e1, is);
+  a.e[(size_t)z * 3 + 1] = cmul(ej, is);
+  a.e[(size_t)z * 3 + 2] = cmul(ek, is);
 }
 
 // rotated rows: lr[g][r][ldL] from the GEMM output out[(g, p)][r] (K1 N x S)
@@ -649,7 +699,10 @@ hipError_t launch_msd_energy_chunk(const MsdDims& m, const MsdEnergyDims& e, con
     a.ldv = m.ldv;
     a.Hmax = e.Hmax;
     a.Qmax = e.Qmax;
-    hipLaunchKernelGGL(msd_contract_kernel, dim3(nz), dim3(CT_T), 0, s, a);
+    a.part = w.cpart;
+    hipLaunchKernelGGL(msd_contract_kernel, dim3(MSD_CT_SPLITS, nz), dim3(CT_T), 0, s, a);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(msd_contract_final_kernel, dim3((unsigned)ceil_div(nz, 64)), dim3(64), 0, s, a, nz);
     if ((err = hipGetLastError()) != hipSuccess) return err;
   }
   return hipSuccess;
