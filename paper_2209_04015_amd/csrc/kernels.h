@@ -316,7 +316,7 @@ struct MsdEnergyTables {
 };
 struct MsdEnergyWork {
   double* u;       // [Wc][2][K + 1][2][Smax][nmax]
-  double2* rbuf;   // [Wc][2][Dmax][ldG]
+  double2* rbuf;   // [Wc][2][ldG][Dmax]
   double2* jpart;  // [Wc][2][nchunk][Dmax]
   double2* ppart;  // [Wc][2][nchunk][Dmax]
   double2* tt;     // [Wc][2][K + 1]

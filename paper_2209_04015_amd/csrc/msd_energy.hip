@@ -104,8 +104,8 @@ __global__ __launch_bounds__(UWM* UWN * 64) void msd_u_kernel(MsdUProb p, int S,
 
 // ---------------------------------------------------------------------------
 // Per (walker, chunk of Cholesky blocks): T, tr T, tr T T, R = Y_Q T - V, the
-// active blocks r = R[Q][H] and p = (R T)[Q][H].  r goes to rbuf[z][s][d][g]
-// (complex, g fastest: the Gram products' contraction runs along it); the
+// active blocks r = R[Q][H] and p = (R T)[Q][H].  r goes to rbuf[z][s][g][d]
+// (complex, d fastest: a block's entries are one contiguous run); the
 // chunk's partial sums of J_g r_g and of p_g, and tr T, tr T T per block, go
 // to their own arrays; block K (h1) fills r1 and tr T1 instead.
 // ---------------------------------------------------------------------------
@@ -114,7 +114,7 @@ struct MsdRpArgs {
   const double* yp;     // planar Y [W][2][2][nmax][ldv]
   const int* hlist;     // [2][Hmax] active holes (occupied index)
   const int* qlist;     // [2][Qmax] active particles (virtual index)
-  double2* rbuf;        // [Wc][2][Dmax][ldG]
+  double2* rbuf;        // [Wc][2][ldG][Dmax]
   double2* jpart;       // [Wc][2][nchunk][Dmax]
   double2* ppart;       // [Wc][2][nchunk][Dmax]
   double2* tt;          // [Wc][2][K1]: tr T_g (g = K: tr T1)
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(RP_T) void msd_rp_kernel(MsdRpArgs a) {
           a.r1[((size_t)zl * 2 + s) * a.Dmax + d] = r;
           continue;
         }
-        a.rbuf[(((size_t)zl * 2 + s) * a.Dmax + d) * a.ldG + g] = r;
+        a.rbuf[(((size_t)zl * 2 + s) * a.ldG + g) * a.Dmax + d] = r;
         accj[m] = cadd(accj[m], cmul(J, r));
         double2 pv = make_double2(0.0, 0.0);
         for (int j = 0; j < n; ++j)
@@ -235,6 +235,217 @@ __global__ __launch_bounds__(RP_T) void msd_rp_kernel(MsdRpArgs a) {
       a.ppart[o] = accp[m];
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// The same on the FP64 matrix cores, one wave per (walker, spin, chunk of
+// Cholesky blocks), for windows of at most 16 MT active particles, 16 NTL
+// electrons and 16 active holes per spin.  Per block g, with lane l = (lg =
+// l / 16, lr = l % 16):
+//   R = Y_Q T - V: A = Y_Q^T (particle q x occupied i, loaded once), B = T
+//     (i x j), the accumulators start at -V; four real products per k step
+//     (Re Re, -Im Im, Re Im, Im Re);
+//   r = the hole columns of R, written to rbuf / r1; J_g r summed in the
+//     accumulator layout (lane (q = 16 mt + lg + 4 rr, j = 16 nt + lr));
+//   p = R T[:, H]: R goes through the wave's LDS block into the A layout,
+//     B = T[j][H_hh]; summed over the chunk in the accumulator layout
+//     (lane (q, hh = lr)).
+// tr T of both spins (for J_g) and tr T T come from direct loads and wave
+// sums.  The chunk's partial sums go to jpart / ppart in the layout of the
+// workgroup kernel, so that the sums kernel serves both.
+// ---------------------------------------------------------------------------
+constexpr int RPM_WAVES = 4;
+
+__device__ __forceinline__ double2 wave_sum2_(double2 v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o, 64);
+    v.y += __shfl_xor(v.y, o, 64);
+  }
+  return v;
+}
+
+template <int MT, int NTL>
+__global__ __launch_bounds__(RPM_WAVES * 64) void msd_rp_mfma_kernel(MsdRpArgs a) {
+  constexpr int KS = 4 * NTL;  // k steps over the electrons (4 per step)
+  constexpr int RLD = 16 * NTL + 1;
+  __shared__ double rl_lds[RPM_WAVES][2][16 * MT][RLD];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int task = blockIdx.x * RPM_WAVES + wv;  // (spin, chunk)
+  const int zl = blockIdx.y, z = a.z0 + zl;
+  const int s = task / a.nchunk, ch = task - s * a.nchunk;
+  if (s >= 2) return;
+  const int n = s ? a.n[1] : a.n[0], nq = s ? a.nq[1] : a.nq[0], nh = s ? a.nh[1] : a.nh[0];
+  const int g0 = ch * a.gchunk, g1 = min(g0 + a.gchunk, a.K1);
+  if (n == 0) {  // no electrons of this spin: tr T = tr T T = 0
+    for (int g = g0 + lane; g < g1; g += 64) {
+      a.tt[((size_t)zl * 2 + s) * a.K1 + g] = make_double2(0.0, 0.0);
+      if (g < a.K) a.kt[((size_t)zl * 2 + s) * a.K + g] = make_double2(0.0, 0.0);
+    }
+    return;
+  }
+  const int lg = lane >> 4, lr = lane & 15;
+  const size_t plane = (size_t)a.Smax * a.nmax;
+  double (*Rl)[16 * MT][RLD] = rl_lds[wv];
+
+  // A = Y_Q^T: [mt][ks] (re, im)
+  double yar[MT][KS], yai[MT][KS];
+  {
+    const size_t yplane = (size_t)a.nmax * a.ldv;
+    const double* yr = a.yp + ((size_t)(2 * z + 0) * 2 + s) * yplane;
+    const double* yi = a.yp + ((size_t)(2 * z + 1) * 2 + s) * yplane;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int q = 16 * mt + lr;
+      const int av = q < nq ? a.qlist[s * a.Qmax + q] : 0;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int i = 4 * ks + lg;
+        const bool ok = q < nq && i < n;
+        yar[mt][ks] = ok ? yr[(size_t)i * a.ldv + av] : 0.0;
+        yai[mt][ks] = ok ? yi[(size_t)i * a.ldv + av] : 0.0;
+      }
+    }
+  }
+  // hole position of this lane's column j in each n tile (-1: not a hole)
+  int hpos[NTL];
+#pragma unroll
+  for (int nt = 0; nt < NTL; ++nt) hpos[nt] = -1;
+  for (int hh = 0; hh < nh; ++hh) {
+    const int h = a.hlist[s * a.Hmax + hh];
+#pragma unroll
+    for (int nt = 0; nt < NTL; ++nt)
+      if (16 * nt + lr == h) hpos[nt] = hh;
+  }
+  // this lane's hole column for the p products (B = T[j][H_lr])
+  const int hcol = lr < nh ? a.hlist[s * a.Hmax + lr] : 0;
+
+  doublex4 jr[MT][NTL], ji[MT][NTL], pr[MT], pi[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    pr[mt] = pi[mt] = doublex4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int nt = 0; nt < NTL; ++nt) jr[mt][nt] = ji[mt][nt] = doublex4{0.0, 0.0, 0.0, 0.0};
+  }
+
+  for (int g = g0; g < g1; ++g) {
+    // tr T of both spins (J_g) and tr T T of this spin
+    double2 trs[2];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int n2 = s2 ? a.n[1] : a.n[0];
+      const double* ub = a.u + ((((size_t)zl * 2 + s2) * a.K1 + g) * 2) * plane;
+      double2 v = make_double2(0.0, 0.0);
+      if (lane < n2) v = make_double2(ub[(size_t)lane * a.nmax + lane], ub[plane + (size_t)lane * a.nmax + lane]);
+      trs[s2] = wave_sum2_(v);
+    }
+    const double2 J = cadd(trs[0], trs[1]);
+    if (lane == 0) a.tt[((size_t)zl * 2 + s) * a.K1 + g] = s ? trs[1] : trs[0];
+    const double* Ur = a.u + ((((size_t)zl * 2 + s) * a.K1 + g) * 2) * plane;
+    const double* Ui = Ur + plane;
+    if (g < a.K) {
+      double2 v = make_double2(0.0, 0.0);
+      for (int e = lane; e < n * n; e += 64) {
+        const int i = e / n, j = e - i * n;
+        const double2 tij = make_double2(Ur[(size_t)i * a.nmax + j], Ui[(size_t)i * a.nmax + j]);
+        const double2 tji = make_double2(Ur[(size_t)j * a.nmax + i], Ui[(size_t)j * a.nmax + i]);
+        v = cadd(v, cmul(tij, tji));
+      }
+      v = wave_sum2_(v);
+      if (lane == 0) a.kt[((size_t)zl * 2 + s) * a.K + g] = v;
+    }
+    // R = Y_Q T - V
+    doublex4 rr_[MT][NTL], ri_[MT][NTL];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NTL; ++nt) {
+        const int j = 16 * nt + lr;
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) {
+          const int q = 16 * mt + lg + 4 * r4;
+          const bool ok = q < nq && j < n;
+          rr_[mt][nt][r4] = ok ? -Ur[(size_t)(n + q) * a.nmax + j] : 0.0;
+          ri_[mt][nt][r4] = ok ? -Ui[(size_t)(n + q) * a.nmax + j] : 0.0;
+        }
+      }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int i = 4 * ks + lg;
+#pragma unroll
+      for (int nt = 0; nt < NTL; ++nt) {
+        const int j = 16 * nt + lr;
+        const bool ok = i < n && j < n;
+        const double tr = ok ? Ur[(size_t)i * a.nmax + j] : 0.0;
+        const double ti = ok ? Ui[(size_t)i * a.nmax + j] : 0.0;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          rr_[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(yar[mt][ks], tr, rr_[mt][nt], 0, 0, 0);
+          rr_[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-yai[mt][ks], ti, rr_[mt][nt], 0, 0, 0);
+          ri_[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(yar[mt][ks], ti, ri_[mt][nt], 0, 0, 0);
+          ri_[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(yai[mt][ks], tr, ri_[mt][nt], 0, 0, 0);
+        }
+      }
+    }
+    // r (the hole columns) out; J_g r into the chunk sums; R into the LDS block
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NTL; ++nt)
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) {
+          const int q = 16 * mt + lg + 4 * r4;
+          const double2 rv = make_double2(rr_[mt][nt][r4], ri_[mt][nt][r4]);
+          Rl[0][q][16 * nt + lr] = rv.x;
+          Rl[1][q][16 * nt + lr] = rv.y;
+          if (q < nq && hpos[nt] >= 0) {
+            const int d = q * nh + hpos[nt];
+            if (g == a.K)
+              a.r1[((size_t)zl * 2 + s) * a.Dmax + d] = rv;
+            else
+              a.rbuf[(((size_t)zl * 2 + s) * a.ldG + g) * a.Dmax + d] = rv;
+          }
+          if (g < a.K) {
+            jr[mt][nt][r4] += J.x * rv.x - J.y * rv.y;
+            ji[mt][nt][r4] += J.x * rv.y + J.y * rv.x;
+          }
+        }
+    __builtin_amdgcn_wave_barrier();  // the block is written before the wave reads it
+    if (g < a.K) {
+      // p = R T[:, H]: A = R (q x j) from LDS, B = T[j][H_lr]
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int j = 4 * ks + lg;
+        const bool ok = j < n && lr < nh;
+        const double br = ok ? Ur[(size_t)j * a.nmax + hcol] : 0.0;
+        const double bi = ok ? Ui[(size_t)j * a.nmax + hcol] : 0.0;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const double ar = Rl[0][16 * mt + lr][j < 16 * NTL ? j : 0];
+          const double ai = Rl[1][16 * mt + lr][j < 16 * NTL ? j : 0];
+          pr[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, pr[mt], 0, 0, 0);
+          pr[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, pr[mt], 0, 0, 0);
+          pi[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, pi[mt], 0, 0, 0);
+          pi[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, pi[mt], 0, 0, 0);
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();  // the block is read before the next block overwrites it
+  }
+  // the chunk's partial sums, every active entry written (zero where no block contributed)
+  const size_t o = (((size_t)zl * 2 + s) * a.nchunk + ch) * a.Dmax;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int r4 = 0; r4 < 4; ++r4) {
+      const int q = 16 * mt + lg + 4 * r4;
+      if (q >= nq) continue;
+#pragma unroll
+      for (int nt = 0; nt < NTL; ++nt)
+        if (hpos[nt] >= 0) a.jpart[o + q * nh + hpos[nt]] = make_double2(jr[mt][nt][r4], ji[mt][nt][r4]);
+      if (lr < nh) a.ppart[o + q * nh + lr] = make_double2(pr[mt][r4], pi[mt][r4]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -289,7 +500,7 @@ __global__ __launch_bounds__(256) void msd_sums_kernel(int K, int K1, int nchunk
 // of r^s'[d'], so that C[d][(d', re|im)] = G[d][d'].
 // ---------------------------------------------------------------------------
 struct MsdGramProb {
-  const double* rbuf;  // [Wc][2][Dmax][ldG] complex as doubles
+  const double* rbuf;  // [Wc][2][ldG][Dmax] complex as doubles
   int Dmax, ldG, D0, D1;
   __device__ void pair(int b, int& zl, int& s, int& sp) const {
     zl = b / 3;
@@ -301,14 +512,14 @@ struct MsdGramProb {
     int zl, s, sp;
     pair(b, zl, s, sp);
     if (d >= (s ? D1 : D0)) return make_double2(0.0, 0.0);
-    return *reinterpret_cast<const double2*>(rbuf + (((size_t)zl * 2 + s) * Dmax + d) * 2 * ldG + k);
+    return *reinterpret_cast<const double2*>(rbuf + ((((size_t)zl * 2 + s) * ldG + (k >> 1)) * Dmax + d) * 2);
   }
   __device__ double2 load_b(int b, int col, int k) const {
     int zl, s, sp;
     pair(b, zl, s, sp);
     const int d = col >> 1, part = col & 1;
     if (d >= (sp ? D1 : D0)) return make_double2(0.0, 0.0);
-    const double2 x = *reinterpret_cast<const double2*>(rbuf + (((size_t)zl * 2 + sp) * Dmax + d) * 2 * ldG + k);
+    const double2 x = *reinterpret_cast<const double2*>(rbuf + ((((size_t)zl * 2 + sp) * ldG + (k >> 1)) * Dmax + d) * 2);
     return part ? make_double2(x.y, x.x) : make_double2(x.x, -x.y);
   }
 };
@@ -654,7 +865,21 @@ hipError_t launch_msd_energy_chunk(const MsdDims& m, const MsdEnergyDims& e, con
       a.nh[sp] = e.nh[sp];
       a.nq[sp] = e.nq[sp];
     }
-    hipLaunchKernelGGL(msd_rp_kernel, dim3(e.nchunk, nz), dim3(RP_T), msd_energy_rp_lds(e), s, a);
+    const int nqm = std::max(e.nq[0], e.nq[1]), nhm = std::max(e.nh[0], e.nh[1]);
+    const dim3 gm((unsigned)ceil_div(2 * e.nchunk, RPM_WAVES), (unsigned)nz), bm(RPM_WAVES * 64);
+    if (nhm <= 16 && nqm <= 32 && m.nmax <= 32) {
+      // the matrix-core kernel: windows of <= 32 particles, <= 16 holes, <= 32 electrons
+      if (nqm <= 16 && m.nmax <= 16)
+        hipLaunchKernelGGL((msd_rp_mfma_kernel<1, 1>), gm, bm, 0, s, a);
+      else if (nqm <= 16)
+        hipLaunchKernelGGL((msd_rp_mfma_kernel<1, 2>), gm, bm, 0, s, a);
+      else if (m.nmax <= 16)
+        hipLaunchKernelGGL((msd_rp_mfma_kernel<2, 1>), gm, bm, 0, s, a);
+      else
+        hipLaunchKernelGGL((msd_rp_mfma_kernel<2, 2>), gm, bm, 0, s, a);
+    } else {
+      hipLaunchKernelGGL(msd_rp_kernel, dim3(e.nchunk, nz), dim3(RP_T), msd_energy_rp_lds(e), s, a);
+    }
     if ((err = hipGetLastError()) != hipSuccess) return err;
   }
   hipLaunchKernelGGL(msd_sums_kernel, dim3(nz), dim3(256), 0, s, e.K, e.K + 1, e.nchunk, e.Dmax, e.D[0], e.D[1], w.jpart,

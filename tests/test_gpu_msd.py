@@ -486,6 +486,9 @@ ENERGY_CASES = [
     (20, 5, 5, 30, 120, 4, 16, False, None),
     (37, 9, 6, 25, 200, 4, 11, True, (6, 8)),        # ragged, an active space
     (52, 11, 11, 70, 300, 4, 37, False, (8, 10)),     # several Cholesky chunks and Gram tiles
+    (60, 10, 9, 40, 200, 4, 9, True, (8, 24)),        # more than 16 active particles
+    (80, 20, 18, 30, 200, 3, 7, False, (10, 20)),     # more than 16 electrons and 16 particles
+    (50, 20, 19, 20, 150, 3, 6, True, (18, 6)),       # more than 16 active holes (workgroup kernel)
 ]
 
 
