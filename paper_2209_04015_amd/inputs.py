@@ -166,6 +166,48 @@ def orbitals(h1: np.ndarray) -> np.ndarray:
     return trial(h1, h1.shape[0])
 
 
+# From this many determinants on, an expansion in an active window is drawn in
+# vectorised batches (same distribution, another sequence of draws).
+MSD_FAST_DETS = 20000
+
+
+def _msd_draw_window(rng, ndet, nel, hole_lo, nocc_act, nvirt, kmax, prob):
+    """Distinct excitations in an active window, drawn in batches: per spin a
+    rank from prob, a random k-subset of the window's holes (the first k of a
+    random order of the window, sorted) and of its particles (the first k of
+    another random order, kept in that order: the pairing), the reference
+    pair (0, 0) excluded; duplicates (same hole and particle sets) are
+    dropped in draw order."""
+    exc = [((), (), (), ())]
+    seen = set()
+    while len(exc) < ndet:
+        B = int(1.3 * (ndet - len(exc))) + 1024
+        ks = [rng.choice(len(pr), size=B, p=pr) for pr in prob]
+        keep = (ks[0] + ks[1]) > 0
+        cols = []
+        for s in range(2):
+            horder = np.argsort(rng.random((B, nocc_act[s])), axis=1)[:, :max(kmax[s], 1)]
+            porder = np.argsort(rng.random((B, nvirt[s])), axis=1)[:, :max(kmax[s], 1)]
+            cols.append((horder, porder))
+        for b in np.nonzero(keep)[0]:
+            key, ident = [], []
+            for s in range(2):
+                k = int(ks[s][b])
+                horder, porder = cols[s]
+                holes = tuple(sorted(hole_lo[s] + int(h) for h in horder[b, :k]))
+                parts = tuple(nel[s] + int(q) for q in porder[b, :k])
+                key += [holes, parts]
+                ident += [holes, tuple(sorted(parts))]
+            ident = tuple(ident)
+            if ident in seen:
+                continue
+            seen.add(ident)
+            exc.append(tuple(key))
+            if len(exc) == ndet:
+                break
+    return exc
+
+
 def msd_expansion(N: int, na: int, nb: int, ndet: int, max_rank: int = 4, seed: int = 0,
                   stream: int = 0, active=None):
     """A synthetic multi-determinant expansion of ``ndet`` distinct determinants.
@@ -211,6 +253,8 @@ def msd_expansion(N: int, na: int, nb: int, ndet: int, max_rank: int = 4, seed: 
         raise ValueError("more determinants requested than the excitation space holds")
     prob = [np.array([0.45 ** k for k in range(km + 1)]) for km in kmax]
     prob = [pr / pr.sum() for pr in prob]
+    if active is not None and ndet >= MSD_FAST_DETS and max(nocc_act) <= 64 and max(nvirt) <= 64:
+        exc = _msd_draw_window(rng, ndet, nel, hole_lo, nocc_act, nvirt, kmax, prob)
     while len(exc) < ndet:
         ks = [int(rng.choice(len(pr), p=pr)) for pr in prob]
         if ks == [0, 0]:
