@@ -109,6 +109,7 @@ struct afqmc_ham {
   bool prop_fused = false;
   unsigned short* psplit = nullptr;    // P split into fp16 hi/lo, scaled by 2^pexp
   int pexp = 0;
+  float* lmax = nullptr;               // [K] max |L_g|: each walker's |VHS| bound, the scale of its split VHS
   float* th_unscale = nullptr;           // [W][2][2][nmax]
   // workspace (sized for max_walkers)
   void* theta = nullptr;    // T [W][2][2][nmax][ldN]
@@ -311,14 +312,15 @@ int seq_propagate_core(afqmc_ham* h, afqmc_walkers* w, int nw, const StepIO& io,
   const StepDims& d = h->d;
   PHASE(h, AFQMC_PH_SHIFT, s,
         (launch_shift<T>(d, nw, h->vbias, io.fields, io.ctr, io.fstep, (T*)h->xs, h->a, h->tmax,
-                         h->prm.taylor_order + 2, h->prm.max_walkers, h->sdt, s)));
+                         h->prm.taylor_order + 2, h->prm.max_walkers, h->sdt, h->lmax, s)));
   if (vhs_split(h)) {
     PHASE(h, AFQMC_PH_SPLIT, s,
           launch_split_rows_mode(h->split, (long)nw * 2, d.K, (const float*)h->xs, d.ldK, h->xs_split, d.ldhK,
                                  h->xs_unscale, s));
     PHASE(h, AFQMC_PH_VHS, s,
           launch_vhs_split(h->split, d, nw, h->xs_split, h->xs_unscale, h->lt_split, h->lt_unscale, h->vblk,
-                           h->nvblk, (float*)h->vhs, h->tmax + h->prm.max_walkers, h->sdt, s, h->vhs_tile));
+                           h->nvblk, (float*)h->vhs, h->tmax + h->prm.max_walkers, h->prop_fused, h->sdt, s,
+                           h->vhs_tile));
   } else {
     PHASE(h, AFQMC_PH_VHS, s,
           (launch_vhs<T>(d, nw, (const T*)h->xs, (const T*)h->LT, h->pq, (T*)h->vhs, h->sdt, s)));
@@ -747,7 +749,8 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
     if ((rc = dalloc(h, &h->t0, W * N * d.ncolp * ts))) return rc;
     if ((rc = dalloc(h, &h->t1, W * N * d.ncolp * ts))) return rc;
   }
-  // running maxima: slot 0 max |P phi|, 1 max |VHS|, 1 + k max |t_k|
+  // running maxima: slot 0 max |P phi|, 1 max |VHS| (fused propagation: a
+  // bound on |VHS|, written by the shift), 1 + k max |t_k|
   if ((rc = dalloc_t(h, &h->tmax, W * (size_t)(p.taylor_order + 2)))) return rc;
   if ((rc = dalloc_t(h, &h->part, (size_t)2 * h->ntg * wtheta))) return rc;
   if ((rc = dalloc_t(h, &h->corr, W * 2))) return rc;
@@ -771,6 +774,8 @@ int init_impl(afqmc_ham* h, const double* host_h1, const double* host_chol, cons
       unsigned* pmax = nullptr;
       HIP_TRY(tmp.get(&pmax, sizeof(unsigned)));
       HIP_TRY(setup_prop_fused(d, h->P, h->psplit, pmax, &h->pexp, s));
+      if ((rc = dalloc_t(h, &h->lmax, (size_t)K))) return rc;
+      HIP_TRY(setup_lmax(K, N, dL, h->lmax, s));
     } else {
       if ((rc = dalloc_t(h, &h->tk, (size_t)p.taylor_order * W * N * d.ncolp))) return rc;
     }
@@ -2130,7 +2135,8 @@ int afqmc_autotune(afqmc_batch* b, const char* cache_path) {
         float ms = 0.f;
         rc = time3(s, [&]() -> hipError_t {
           return launch_vhs_split(h->split, d, nw, h->xs_split, h->xs_unscale, h->lt_split, h->lt_unscale, h->vblk,
-                                  h->nvblk, (float*)h->vhs, h->tmax + h->prm.max_walkers, h->sdt, s, tile);
+                                  h->nvblk, (float*)h->vhs, h->tmax + h->prm.max_walkers, h->prop_fused, h->sdt, s,
+                                  tile);
         }, &ms);
         if (!rc && ms < best) {
           best = ms;

@@ -49,7 +49,10 @@ template <typename T>
 // tmax: tslots running-maximum slots of stride tstride, zeroed per walker
 hipError_t launch_shift(const StepDims& d, int W, const double2* vbias, const double* x, const int* ctr,
                         long x_step, T* xs, double2* a, unsigned* tmax, int tslots, int tstride, double sdt,
-                        hipStream_t s);
+                        const float* lmax, hipStream_t s);
+// m_g = max |L_g| per Cholesky vector (FP32, rounded up): with lmax non-null
+// the shift also writes each walker's |VHS| bound into tmax slot 1
+hipError_t setup_lmax(int K, int N, const double* L, float* lmax, hipStream_t s);
 
 template <typename T>
 hipError_t launch_vhs(const StepDims& d, int W, const T* xs, const T* LT, const int2* pq, T* vhs,
@@ -109,11 +112,16 @@ ExTile exchange_split_tile(int n);
 // with few walkers).  Every output element sums over the same rows in the
 // same order in both shapes, so the choice does not change any result bit.
 constexpr int SPLIT_TILE_WIDE = 0, SPLIT_TILE_NARROW = 1;
-// vmax (optional): per-walker max |VHS| (atomic, bit patterns of floats).
-// lt: block-packed L split rows (vhs_split_pairs order), blk: the blocks.
+// FP32 output (split_out false): vhs [W][N][ldV] interleaved complex; vmax
+// (optional) per-walker max |VHS| (atomic, bit patterns of floats).
+// Split output: each row of ldV floats holds a plane of ldV fp16 hi halves
+// then one of lo halves, (Re, Im) interleaved, scaled by
+// 2^vhs_split_exp(vmax[z]) where vmax (required, read) holds each walker's
+// |VHS| bound.  lt: block-packed L split rows (vhs_split_pairs order), blk:
+// the blocks.
 hipError_t launch_vhs_split(int mode, const StepDims& d, int W, const unsigned short* xs, const float* xs_unscale,
                             const unsigned short* lt, const float* lt_unscale, const int2* blk, int nblk, float* vhs,
-                            unsigned* vmax, double sdt, hipStream_t s, int tile = SPLIT_TILE_WIDE);
+                            unsigned* vmax, bool split_out, double sdt, hipStream_t s, int tile = SPLIT_TILE_WIDE);
 // blocks of orbital pairs of the split VHS and the pair of each packed row
 std::vector<int2> vhs_split_blocks(int N);
 std::vector<int2> vhs_split_pairs(int N, const std::vector<int2>& blk);
@@ -178,9 +186,11 @@ PropFusedGeom prop_fused_geom(const StepDims& d);
 // (pexp out, host; synchronises s); sets the kernel's LDS attribute.
 hipError_t setup_prop_fused(const StepDims& d, const double* P, unsigned short* psplit, unsigned* pmax_scratch,
                             int* pexp_host, hipStream_t s);
-// phi <- P T_order(VHS) P phi for W walkers in place; vmax [W] max |VHS|
+// phi <- P T_order(VHS) P phi for W walkers in place; vhs: the split rows
+// of launch_vhs_split (split output), vbound [W] the |VHS| bounds they were
+// scaled by
 hipError_t launch_prop_fused(const StepDims& d, int W, double2* phi_a, double2* phi_b, const float* vhs,
-                             const unsigned* vmax, const unsigned short* psplit, int pexp, int order,
+                             const unsigned* vbound, const unsigned short* psplit, int pexp, int order,
                              hipStream_t s);
 
 // --- mixed estimators (estimator_kernels.hip) ---------------------------------

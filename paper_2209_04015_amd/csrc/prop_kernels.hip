@@ -8,11 +8,12 @@
 //   v_{K+1} = t0,  v_k = t0 + VHS v_{k+1} / k  (k = K .. 1),  T_K(VHS) t0 = v_1,
 // with t0 = P phi; it equals the sum of the terms VHS^k t0 / k! up to
 // rounding.  v (hi/lo fp16 pairs, the B operand of every product) and t0
-// (FP32) live in LDS; the walker's FP32 VHS rows are streamed from memory
-// straight into registers and split there (the scale from max |VHS| of the
-// finished build), once per order, with no LDS staging and no barrier inside
-// a product.  The two spins of a walker get workgroup ids 8 apart, so they
-// run on one XCD and the second stream of the VHS rows comes from its L2.
+// (FP32) live in LDS; the walker's VHS rows, already split by the VHS build
+// (fp16 hi and lo planes scaled by a power of two from a bound on the
+// walker's |VHS|), are streamed from memory straight into the A registers,
+// once per order, with no LDS staging and no barrier inside a product.  The
+// two spins of a walker get workgroup ids 8 apart, so they run on one XCD
+// and the second stream of the VHS rows comes from its L2.
 //
 // Lanes and fragments (v_mfma_f32_16x16x32_f16): eight waves, two per SIMD
 // (one wave per SIMD issues matrix instructions too slowly to keep the
@@ -31,8 +32,8 @@
 //   P step, k = q: the lane's component of eight consecutive q, two 8-byte
 //   reads.
 // Scales: one power of two per (walker, spin) and operand (max |phi|, max
-// |t0|, max |v_k|; max |VHS| of the walker, recorded by the VHS build) and
-// one for P, exact and undone in each epilogue.
+// |t0|, max |v_k|; the walker's |VHS| bound for the VHS rows) and one for
+// P, exact and undone in each epilogue.
 
 #include <cmath>
 #include <cstring>
@@ -60,17 +61,19 @@ struct PfCols {
 struct PropFusedArgs {
   double2* phi_a;                // [W][N][na] in / out
   double2* phi_b;                // [W][N][nb] in / out
-  const float* vhs;              // [W][N][ldV] interleaved complex
-  const unsigned* vmax;          // [W] max |VHS| (float bits)
+  const float* vhs;              // [W][N][ldV] split rows: ldV hi halves, then ldV lo halves
+  const unsigned* vbound;        // [W] |VHS| bound (float bits): the scale of the split rows
   const unsigned short* psplit;  // [QP][nkbP][64] P split, scaled by 2^pexp
   int W, N, na, nb, ldV, RT, QP, QCH, TQS, nkbP, order, pexp, nspin;
-  float sa;                      // the walker's VHS scale (set per workgroup)
 };
 
+// Maximum over the workgroup.  Every earlier reader of red has passed a
+// barrier since (the one that follows each store of v), so the writes need
+// no barrier of their own; the one barrier here also puts every wave past
+// the product whose results it reduces, so v may be overwritten after it.
 __device__ __forceinline__ float pf_block_max(float v, float* red) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  __syncthreads();  // earlier readers of red are done (and every wave is past its product)
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   float r = red[0];
@@ -99,23 +102,21 @@ __device__ __forceinline__ void pf_split4(float x0, float x1, float x2, float x3
   lo = make_uint2((unsigned)l[0] | ((unsigned)l[1] << 16), (unsigned)l[2] | ((unsigned)l[3] << 16));
 }
 
-// The three products of column tile t for the wave's nv real row tiles (nv
-// is wave-uniform: scalar branches).  Each product kind is issued for all
-// row tiles before the next, so that dependent MFMAs on one accumulator are
+// The three products of column tile t for the wave's NV real row tiles (a
+// compile-time count: the products of a wave are one straight run of MFMAs,
+// with no branch among them).  Each product kind is issued for all row
+// tiles before the next, so that dependent MFMAs on one accumulator are
 // several instructions apart.
-template <int CW>
+template <int CW, int NV>
 __device__ __forceinline__ void pf_mma_tiles(floatx4 (&acc)[PF_FM][CW], const f16x8_t (&ah)[PF_FM],
                                              const f16x8_t (&al)[PF_FM], const f16x8_t& bh, const f16x8_t& bl,
-                                             int t, int nv) {
+                                             int t) {
 #pragma unroll
-  for (int i = 0; i < PF_FM; ++i)
-    if (i < nv) acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], bh, acc[i][t], 0, 0, 0);
+  for (int i = 0; i < NV; ++i) acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], bh, acc[i][t], 0, 0, 0);
 #pragma unroll
-  for (int i = 0; i < PF_FM; ++i)
-    if (i < nv) acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bl, acc[i][t], 0, 0, 0);
+  for (int i = 0; i < NV; ++i) acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bl, acc[i][t], 0, 0, 0);
 #pragma unroll
-  for (int i = 0; i < PF_FM; ++i)
-    if (i < nv) acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bh, acc[i][t], 0, 0, 0);
+  for (int i = 0; i < NV; ++i) acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bh, acc[i][t], 0, 0, 0);
 }
 
 struct PfCtx {
@@ -136,16 +137,15 @@ __device__ __forceinline__ void pf_zero(floatx4 (&acc)[PF_FM][CW]) {
 // first orbital of the wave's column tile t, or -1 past the walker's tiles
 template <int CT>
 __device__ __forceinline__ int pf_col0(const PfCtx& c, int t) {
-  const int tg = c.cg * PfCols<CT>::W + t;
+  const int tg = (PF_CG > 1 ? c.cg * PfCols<CT>::W : 0) + t;  // one column group: known at compile time
   return tg < CT ? 8 * tg : -1;
 }
 
-// acc = P v (k = q), v from the LDS planes
-template <int CT>
-__device__ __forceinline__ void pf_product_p(const PropFusedArgs& p, const PfCtx& c, const uint4* u_hi,
-                                             const uint4* u_lo, floatx4 (&acc)[PF_FM][PfCols<CT>::W]) {
+// acc = P v (k = q), v from the LDS planes, for the wave's NV row tiles
+template <int CT, int NV>
+__device__ __forceinline__ void pf_product_p_nv(const PropFusedArgs& p, const PfCtx& c, const uint4* u_hi,
+                                                const uint4* u_lo, floatx4 (&acc)[PF_FM][PfCols<CT>::W]) {
   constexpr int CW = PfCols<CT>::W;
-  pf_zero<CW>(acc);
   // A rows of this lane: byte offsets of its 16-byte chunks in the first k
   // block (bounds-checked loads: a block past the last reads zeros or rows
   // that are never used)
@@ -159,7 +159,7 @@ __device__ __forceinline__ void pf_product_p(const PropFusedArgs& p, const PfCtx
   uint4 pa_h[PF_FM], pa_l[PF_FM];
   auto fetch = [&](int kb) {
 #pragma unroll
-    for (int i = 0; i < PF_FM; ++i) {
+    for (int i = 0; i < NV; ++i) {
       pa_h[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(prs, arow[i], kb * 128, 0));
       pa_l[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(prs, arow[i], kb * 128 + 64, 0));
     }
@@ -168,47 +168,93 @@ __device__ __forceinline__ void pf_product_p(const PropFusedArgs& p, const PfCtx
   for (int kb = 0; kb < p.nkbP; ++kb) {
     f16x8_t ah[PF_FM], al[PF_FM];
 #pragma unroll
-    for (int i = 0; i < PF_FM; ++i) {
+    for (int i = 0; i < NV; ++i) {
       ah[i] = __builtin_bit_cast(f16x8_t, pa_h[i]);
       al[i] = __builtin_bit_cast(f16x8_t, pa_l[i]);
     }
     fetch(kb + 1);  // unconditional (see above), so the wait counts stay exact
-    const int ch = 8 * kb + 2 * c.kg;  // first of the two chunks of q0 .. q0+7
+    // first of the two chunks of q0 .. q0+7; chunks past the rows read
+    // chunk 0 (in bounds) and are replaced by zeros
+    const int ch = 8 * kb + 2 * c.kg;
     const bool qok = 4 * ch < p.QP;
+    const int chs = qok ? ch : 0;
 #pragma unroll
     for (int t = 0; t < CW; ++t) {
       const int j0 = pf_col0<CT>(c, t);
-      if (j0 < 0) break;  // uniform
-      uint4 hw = make_uint4(0u, 0u, 0u, 0u), lw = hw;
-      if (qok) {
-        const int o = (j0 + c.jl) * p.QCH + ch;
-        const uint2* h = reinterpret_cast<const uint2*>(u_hi + o) + c.comp;
-        const uint2* l = reinterpret_cast<const uint2*>(u_lo + o) + c.comp;
-        const uint2 h0 = h[0], h1 = h[2], l0 = l[0], l1 = l[2];  // chunks ch and ch + 1
-        hw = make_uint4(h0.x, h0.y, h1.x, h1.y);
-        lw = make_uint4(l0.x, l0.y, l1.x, l1.y);
-      }
-      pf_mma_tiles<CW>(acc, ah, al, __builtin_bit_cast(f16x8_t, hw), __builtin_bit_cast(f16x8_t, lw), t, c.nv);
+      if (j0 < 0) break;  // compile time
+      const int o = (j0 + c.jl) * p.QCH + chs;
+      const uint2* h = reinterpret_cast<const uint2*>(u_hi + o) + c.comp;
+      const uint2* l = reinterpret_cast<const uint2*>(u_lo + o) + c.comp;
+      const uint2 h0 = h[0], h1 = h[2], l0 = l[0], l1 = l[2];  // chunks ch and ch + 1
+      const uint4 hw = qok ? make_uint4(h0.x, h0.y, h1.x, h1.y) : make_uint4(0u, 0u, 0u, 0u);
+      const uint4 lw = qok ? make_uint4(l0.x, l0.y, l1.x, l1.y) : make_uint4(0u, 0u, 0u, 0u);
+      pf_mma_tiles<CW, NV>(acc, ah, al, __builtin_bit_cast(f16x8_t, hw), __builtin_bit_cast(f16x8_t, lw), t);
     }
   }
 }
 
-// acc = VHS v (k = (q, re|im)), the VHS rows streamed from memory into
-// registers and split there with the walker's power-of-two scale p.sa
+// acc = P v for the wave's real row tiles (one straight-line loop per count)
 template <int CT>
-__device__ __forceinline__ void pf_product_v(const PropFusedArgs& p, const PfCtx& c, __amdgpu_buffer_rsrc_t vrs,
-                                             const uint4* u_hi, const uint4* u_lo,
-                                             floatx4 (&acc)[PF_FM][PfCols<CT>::W]) {
-  constexpr int CW = PfCols<CT>::W;
-  pf_zero<CW>(acc);
-  // byte offsets of this lane's 8 floats of the first k block; rows past N
-  // (and past the tiles) lie outside the buffer and read as zeros
-  int aoff[PF_FM];
+__device__ __forceinline__ void pf_product_p(const PropFusedArgs& p, const PfCtx& c, const uint4* u_hi,
+                                             const uint4* u_lo, floatx4 (&acc)[PF_FM][PfCols<CT>::W]) {
+  pf_zero<PfCols<CT>::W>(acc);
+  static_assert(PF_FM == 3, "one case per row-tile count");
+  switch (c.nv) {  // wave-uniform
+    case 3: pf_product_p_nv<CT, 3>(p, c, u_hi, u_lo, acc); break;
+    case 2: pf_product_p_nv<CT, 2>(p, c, u_hi, u_lo, acc); break;
+    case 1: pf_product_p_nv<CT, 1>(p, c, u_hi, u_lo, acc); break;
+    default: break;
+  }
+}
+
+// k blocks of VHS rows in flight per wave (a third set spills)
+constexpr int PF_DEPTH = 2;
+
+// The wave's split VHS operands of PF_DEPTH k blocks (the lane's 8 hi and 8
+// lo halves of each of its row tiles), loaded ahead of the products that use
+// them.
+// Successive passes over the rows (one per Horner order) alternate the
+// direction of k, so that each pass starts on the blocks the previous one
+// read last, the ones most likely still in the L2.
+struct PfVhsStream {
+  uint4 rh[PF_DEPTH][PF_FM], rl[PF_DEPTH][PF_FM];
+  int aoff[PF_FM];  // byte offsets of the lane's hi halves in k block 0
+  int lo_off;       // bytes from a row's hi plane to its lo plane
+  int nkb;          // k blocks
+  int nkbe;         // positions per pass: k blocks rounded up to a multiple of PF_DEPTH (set s holds position s mod PF_DEPTH)
+  int dir;          // direction of the current pass: 0 ascending k blocks, 1 descending
+};
+
+// k block at position pos of a pass in direction dir (positions past the
+// count are phantoms: never computed)
+__device__ __forceinline__ int pf_block_at(const PfVhsStream& v, int pos, int dir) {
+  return (dir && pos < v.nkb) ? v.nkb - 1 - pos : pos;
+}
+
+// set s <- position pos of the current pass (positions past its end: of the
+// next pass, in the other direction); phantom blocks and rows past the tiles
+// read in-bounds data or, past the buffer, zeros, and are never used
+__device__ __forceinline__ void pf_vhs_fetch(PfVhsStream& v, __amdgpu_buffer_rsrc_t vrs, int s, int pos) {
+  const int kb = pos >= v.nkbe ? pf_block_at(v, pos - v.nkbe, v.dir ^ 1) : pf_block_at(v, pos, v.dir);
 #pragma unroll
   for (int i = 0; i < PF_FM; ++i) {
-    const int rt = c.rg + PF_RG * i;
-    aoff[i] = rt < p.RT ? ((rt * 16 + c.lrow) * p.ldV + 8 * c.kg) * 4 : SPLIT_ROW_NONE;
+    v.rh[s][i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(vrs, v.aoff[i], kb * 64, 0));
+    v.rl[s][i] =
+        __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(vrs, v.aoff[i], kb * 64 + v.lo_off, 0));
   }
+}
+
+// acc = VHS v (k = (q, re|im)), the split VHS rows streamed from memory into
+// the A registers.  On entry set s of the stream holds (or is loading) the
+// block at position s of this pass; every block is fetched PF_DEPTH
+// positions ahead, wrapping into the next pass, so that on exit the sets
+// hold the first blocks of the next one, already in flight across the
+// epilogue and its barriers.
+template <int CT, int NV>
+__device__ __forceinline__ void pf_product_v_nv(const PropFusedArgs& p, const PfCtx& c, __amdgpu_buffer_rsrc_t vrs,
+                                                PfVhsStream& vs, const uint4* u_hi, const uint4* u_lo,
+                                                floatx4 (&acc)[PF_FM][PfCols<CT>::W]) {
+  constexpr int CW = PfCols<CT>::W;
   // per-lane v_perm selectors: (Re, Im) or (Im, Re) pairs of q0+m, and the
   // sign flip of the high halves for the real-part columns
   const unsigned sel0 = c.comp ? 0x01000504u : 0x05040100u;
@@ -221,61 +267,55 @@ __device__ __forceinline__ void pf_product_v(const PropFusedArgs& p, const PfCtx
                                          __builtin_amdgcn_perm(d.w, d.y, sel0) ^ flip,
                                          __builtin_amdgcn_perm(d.w, d.y, sel1) ^ flip));
   };
-  int ob[CW];  // the wave's column tiles: first LDS chunk of orbital j0 + jl (or none)
+  static_assert(PF_CG == 1, "every wave holds every column tile");
+  int ob[CW];  // the wave's column tiles: first LDS chunk of orbital j0 + jl
 #pragma unroll
-  for (int t = 0; t < CW; ++t) {
-    const int j0 = pf_col0<CT>(c, t);
-    ob[t] = j0 < 0 ? -1 : (j0 + c.jl) * p.QCH + c.kg;
-  }
+  for (int t = 0; t < CW; ++t) ob[t] = (pf_col0<CT>(c, t) + c.jl) * p.QCH + c.kg;
   const int nkb = p.RT;
-  float4 ra[2][PF_FM][2];
-  auto fetch = [&](int s, int kb) {
-#pragma unroll
-    for (int i = 0; i < PF_FM; ++i) {
-      ra[s][i][0] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(vrs, aoff[i], kb * 128, 0));
-      ra[s][i][1] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(vrs, aoff[i], kb * 128 + 16, 0));
-    }
-  };
-  auto compute = [&](int s, int kb) {
+  auto compute = [&](int s, int pos) {
+    const int kb = pf_block_at(vs, pos, vs.dir);
+    if (NV == 0) return;
     f16x8_t ah[PF_FM], al[PF_FM];
 #pragma unroll
-    for (int i = 0; i < PF_FM; ++i) {
-      const float x[8] = {ra[s][i][0].x * p.sa, ra[s][i][0].y * p.sa, ra[s][i][0].z * p.sa, ra[s][i][0].w * p.sa,
-                          ra[s][i][1].x * p.sa, ra[s][i][1].y * p.sa, ra[s][i][1].z * p.sa, ra[s][i][1].w * p.sa};
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const _Float16 h = (_Float16)x[e];
-        ah[i][e] = h;
-        al[i][e] = (_Float16)(x[e] - (float)h);
-      }
+    for (int i = 0; i < NV; ++i) {
+      ah[i] = __builtin_bit_cast(f16x8_t, vs.rh[s][i]);
+      al[i] = __builtin_bit_cast(f16x8_t, vs.rl[s][i]);
     }
 #pragma unroll
     for (int t = 0; t < CW; ++t) {
-      if (ob[t] < 0) break;  // uniform
       const uint4 dh = u_hi[ob[t] + 4 * kb], dl = u_lo[ob[t] + 4 * kb];
-      pf_mma_tiles<CW>(acc, ah, al, bop(dh), bop(dl), t, c.nv);
+      pf_mma_tiles<CW, NV>(acc, ah, al, bop(dh), bop(dl), t);
     }
   };
-  // two k blocks of loads in flight: fetch kb + 2 while working on kb.  The
-  // fetches are unconditional (past the last block they read the next rows
-  // or, past the buffer, zeros; never used), so that every wait leaves the
-  // other set's loads in flight.
-  fetch(0, 0);
-  fetch(1, 1);
-  int kb = 0;
-  // The scheduling barriers keep each set's loads after the work that reads
-  // the set before them, so that no wait covers the other set.
-  for (; kb + 2 <= nkb; kb += 2) {  // one regular body: the waits stay exact across the back edge
-    compute(0, kb);
-    __builtin_amdgcn_sched_barrier(0);
-    fetch(0, kb + 2);
-    __builtin_amdgcn_sched_barrier(0);
-    compute(1, kb + 1);
-    __builtin_amdgcn_sched_barrier(0);
-    fetch(1, kb + 3);
-    __builtin_amdgcn_sched_barrier(0);
+  // The fetches are unconditional, so that every wait leaves the other sets'
+  // loads in flight; the scheduling barriers keep each set's loads after the
+  // work that reads the set before them.
+  for (int kb = 0; kb < vs.nkbe; kb += PF_DEPTH) {  // one regular body: the waits stay exact across the back edge
+#pragma unroll
+    for (int s = 0; s < PF_DEPTH; ++s) {
+      if (kb + s < nkb) compute(s, kb + s);  // uniform: phantom blocks past the count are skipped
+      __builtin_amdgcn_sched_barrier(0);
+      pf_vhs_fetch(vs, vrs, s, kb + s + PF_DEPTH);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
-  if (kb < nkb) compute(0, kb);
+  vs.dir ^= 1;
+}
+
+// acc = VHS v for the wave's real row tiles (one straight-line loop per
+// count; a wave with none still keeps its VHS stream in step)
+template <int CT>
+__device__ __forceinline__ void pf_product_v(const PropFusedArgs& p, const PfCtx& c, __amdgpu_buffer_rsrc_t vrs,
+                                             PfVhsStream& vs, const uint4* u_hi, const uint4* u_lo,
+                                             floatx4 (&acc)[PF_FM][PfCols<CT>::W]) {
+  pf_zero<PfCols<CT>::W>(acc);
+  static_assert(PF_FM == 3, "one case per row-tile count");
+  switch (c.nv) {  // wave-uniform
+    case 3: pf_product_v_nv<CT, 3>(p, c, vrs, vs, u_hi, u_lo, acc); break;
+    case 2: pf_product_v_nv<CT, 2>(p, c, vrs, vs, u_hi, u_lo, acc); break;
+    case 1: pf_product_v_nv<CT, 1>(p, c, vrs, vs, u_hi, u_lo, acc); break;
+    default: pf_product_v_nv<CT, 0>(p, c, vrs, vs, u_hi, u_lo, acc); break;
+  }
 }
 
 // v (values of the accumulator layout, scaled by 2^e) into the LDS planes:
@@ -337,13 +377,43 @@ __global__ __launch_bounds__(PF_NT, 1) void prop_fused_kernel(PropFusedArgs p) {
   c.jl = c.lane & 7;
   c.comp = (c.lane >> 3) & 1;
 
-  // ---- phi into LDS, scaled by 2^e (the scale taken in FP64, so that any
-  // FP64 walker fits the fp16 range) ----
-  double dm = 0.0;
-  for (int e = tid; e < p.N * ns; e += PF_NT) {
-    const double2 x = ph[e];
-    dm = fmax(dm, fmax(fabs(x.x), fabs(x.y)));
+  // ---- the walker's VHS stream ----
+  const int sa_exp = vhs_split_exp(__uint_as_float(p.vbound[z]));  // the scale of the split VHS rows
+  const __amdgpu_buffer_rsrc_t vrs = split_rsrc(p.vhs + (size_t)z * p.N * p.ldV, p.N * p.ldV * 4);
+  PfVhsStream vs;
+  vs.nkb = p.RT;
+  vs.nkbe = (p.RT + PF_DEPTH - 1) / PF_DEPTH * PF_DEPTH;
+  vs.dir = 0;
+  vs.lo_off = 2 * p.ldV;
+#pragma unroll
+  for (int i = 0; i < PF_FM; ++i) {
+    const int rt = c.rg + PF_RG * i;
+    // rows past N (and past the tiles) lie outside the buffer and read as zeros
+    vs.aoff[i] = rt < p.RT ? (rt * 16 + c.lrow) * p.ldV * 4 + 16 * c.kg : SPLIT_ROW_NONE;
   }
+
+  // ---- phi into LDS, scaled by 2^e (the scale taken in FP64, so that any
+  // FP64 walker fits the fp16 range).  One pass: each thread loads its items
+  // (four rows of one orbital) at once, then the block maximum, then the
+  // split. ----
+  constexpr int PHI_IT = (8 * CT * 4 * PF_MAX_RT + PF_NT - 1) / PF_NT;
+  const int nch = p.QP / 4;
+  double2 xv[PHI_IT][4];
+  double dm = 0.0;
+#pragma unroll
+  for (int it = 0; it < PHI_IT; ++it) {
+    const int e = tid + it * PF_NT;
+    const int j = e % JC, ch = e / JC;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int q = 4 * ch + r;
+      xv[it][r] = (ch < nch && q < p.N && j < ns) ? ph[(size_t)q * ns + j] : make_double2(0.0, 0.0);
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < PHI_IT; ++it)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dm = fmax(dm, fmax(fabs(xv[it][r].x), fabs(xv[it][r].y)));
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
   if (c.lane == 0) reinterpret_cast<double*>(red)[c.wid] = dm;
@@ -352,17 +422,16 @@ __global__ __launch_bounds__(PF_NT, 1) void prop_fused_kernel(PropFusedArgs p) {
 #pragma unroll
   for (int w = 1; w < PF_WAVES; ++w) dm = fmax(dm, reinterpret_cast<const double*>(red)[w]);
   int es = (dm > 0.0 && isfinite(dm)) ? 13 - ilogb(dm) : 0;
-  const int nch = p.QP / 4;
-  for (int e = tid; e < JC * nch; e += PF_NT) {
+#pragma unroll
+  for (int it = 0; it < PHI_IT; ++it) {
+    const int e = tid + it * PF_NT;
     const int j = e % JC, ch = e / JC;
+    if (ch >= nch) break;  // the items of later passes lie further out
     float re[4], im[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int q = 4 * ch + r;
-      double2 x = make_double2(0.0, 0.0);
-      if (q < p.N && j < ns) x = ph[(size_t)q * ns + j];
-      re[r] = (float)ldexp(x.x, es);
-      im[r] = (float)ldexp(x.y, es);
+      re[r] = (float)ldexp(xv[it][r].x, es);
+      im[r] = (float)ldexp(xv[it][r].y, es);
     }
     uint2 rh, rl, ih, il;
     pf_split4(re[0], re[1], re[2], re[3], rh, rl);
@@ -379,7 +448,9 @@ __global__ __launch_bounds__(PF_NT, 1) void prop_fused_kernel(PropFusedArgs p) {
     return reinterpret_cast<float4*>(t0p + (c.comp * JC + j0 + c.jl) * p.TQS + q0);
   };
 
-  // ---- t0 = P phi ----
+  // ---- t0 = P phi, the first k blocks of the VHS rows in flight ----
+#pragma unroll
+  for (int s = 0; s < PF_DEPTH; ++s) pf_vhs_fetch(vs, vrs, s, s);
   pf_product_p<CT>(p, c, u_hi, u_lo, acc);
   float m = 0.f;
   {
@@ -405,11 +476,8 @@ __global__ __launch_bounds__(PF_NT, 1) void prop_fused_kernel(PropFusedArgs p) {
   __syncthreads();
 
   // ---- Horner: v = t0 + VHS v / k, k = order .. 1 ----
-  const int sa_exp = pf_scale_exp(__uint_as_float(p.vmax[z]));  // the scale of the split VHS rows
-  p.sa = ldexpf(1.f, sa_exp);
-  const __amdgpu_buffer_rsrc_t vrs = split_rsrc(p.vhs + (size_t)z * p.N * p.ldV, p.N * p.ldV * 4);
   for (int k = p.order; k >= 1; --k) {
-    pf_product_v<CT>(p, c, vrs, u_hi, u_lo, acc);
+    pf_product_v<CT>(p, c, vrs, vs, u_hi, u_lo, acc);
     const int ex = -(es + sa_exp);
     const float rk = 1.f / (float)k;
     m = 0.f;
@@ -534,14 +602,14 @@ hipError_t setup_prop_fused(const StepDims& d, const double* P, unsigned short* 
 }
 
 hipError_t launch_prop_fused(const StepDims& d, int W, double2* phi_a, double2* phi_b, const float* vhs,
-                             const unsigned* vmax, const unsigned short* psplit, int pexp, int order,
+                             const unsigned* vbound, const unsigned short* psplit, int pexp, int order,
                              hipStream_t s) {
   if (W == 0) return hipSuccess;
   const PropFusedGeom g = prop_fused_geom(d);
   if (!g.ok) return hipErrorInvalidValue;
   const int nspin = d.nb > 0 ? 2 : 1;
-  PropFusedArgs p{phi_a, phi_b, vhs, vmax, psplit, W, d.N, d.na, d.nb, d.ldV, g.RT, g.QP, g.QCH, g.TQS,
-                  g.nkbP, order, pexp, nspin, 1.f};
+  PropFusedArgs p{phi_a, phi_b, vhs, vbound, psplit, W, d.N, d.na, d.nb, d.ldV, g.RT, g.QP, g.QCH, g.TQS,
+                  g.nkbP, order, pexp, nspin};
   const dim3 grid((unsigned)(nspin == 2 ? ceil_div(W, 8) * 16 : W)), block(PF_NT);
   switch (g.CT) {
     case 1: hipLaunchKernelGGL(prop_fused_kernel<1>, grid, block, g.lds_bytes, s, p); break;

@@ -82,6 +82,16 @@ struct SplitStage {
 // buffer load from it returns zeros.
 constexpr int SPLIT_ROW_NONE = 0x7fffffff;
 
+// Power-of-two exponent e putting 2^e b in [2^13, 2^14) (0 for b zero, not
+// finite or not positive; at most 64): the scale of a split VHS, from a
+// bound b on the magnitudes of a walker's VHS entries.  The VHS build and
+// the propagation that reads its split rows take it from the same bound.
+__device__ __forceinline__ int vhs_split_exp(float b) {
+  if (!(b > 0.f) || !isfinite(b)) return 0;
+  const int e = 13 - ilogbf(b);
+  return e < 64 ? e : 64;
+}
+
 // Buffer resource over n_bytes (< 2^31) of split rows: raw (stride 0),
 // bounds-checked loads.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t split_rsrc(const void* base, int n_bytes) {

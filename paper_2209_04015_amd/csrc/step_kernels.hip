@@ -344,41 +344,74 @@ __global__ __launch_bounds__(256) void shift_kernel(int K, int ldK, const double
                                                     const int* __restrict__ ctr, long x_step,
                                                     T* __restrict__ xs, double2* __restrict__ a,
                                                     unsigned* __restrict__ tmax, int tslots,
-                                                    int tstride, double sdt) {
+                                                    int tstride, double sdt, const float* __restrict__ lmax) {
   __shared__ double2 red[4];
   const int z = blockIdx.x;
   const double* x = x_base + (ctr ? (size_t)ctr[0] * x_step : 0);
   double2 acc = make_double2(0.0, 0.0);
+  double2 bnd = make_double2(0.0, 0.0);  // sum_g |Re xs_g| m_g, sum_g |Im xs_g| m_g
   for (int g = threadIdx.x; g < K; g += 256) {
     const double2 v = vbias[(size_t)z * K + g];
     const double2 xb = make_double2(sdt * v.y, -sdt * v.x);
     const double xv = x[(size_t)z * K + g];
-    xs[(size_t)(2 * z) * ldK + g] = (T)(xv - xb.x);
-    xs[(size_t)(2 * z + 1) * ldK + g] = (T)(-xb.y);
+    const T re = (T)(xv - xb.x), im = (T)(-xb.y);
+    xs[(size_t)(2 * z) * ldK + g] = re;
+    xs[(size_t)(2 * z + 1) * ldK + g] = im;
     acc.x += xv * xb.x - 0.5 * (xb.x * xb.x - xb.y * xb.y);
     acc.y += xv * xb.y - xb.x * xb.y;
+    if (lmax) {
+      const double m = lmax[g];
+      bnd.x += fabs((double)re) * m;
+      bnd.y += fabs((double)im) * m;
+    }
   }
   const double2 s = block_sum2(acc, red);
+  const double2 b = lmax ? block_sum2(bnd, red) : bnd;
   if (threadIdx.x == 0) {
     a[z] = s;
     for (int t = 0; t < tslots; ++t) tmax[(size_t)t * tstride + z] = 0u;  // running maxima of this step
+    // |VHS| bound of the walker (slot 1): both parts of VHS = i sqrt(dt)
+    // sum_g xs_g L_g are at most sqrt(dt) sum_g |xs part| max|L_g|; the
+    // margin covers the rounding of the FP32 sums of the split build
+    if (lmax) tmax[(size_t)tstride + z] = __float_as_uint((float)(sdt * fmax(b.x, b.y) * (1.0 + 0x1p-9)));
   }
 }
 
 template <typename T>
 hipError_t launch_shift(const StepDims& d, int W, const double2* vbias, const double* x, const int* ctr,
                         long x_step, T* xs, double2* a, unsigned* tmax, int tslots, int tstride, double sdt,
-                        hipStream_t s) {
+                        const float* lmax, hipStream_t s) {
   hipLaunchKernelGGL(shift_kernel<T>, dim3(W), dim3(256), 0, s, d.K, d.ldK, vbias, x, ctr, x_step, xs,
-                     a, tmax, tslots, tstride, sdt);
+                     a, tmax, tslots, tstride, sdt, lmax);
   return hipGetLastError();
 }
 template hipError_t launch_shift<float>(const StepDims&, int, const double2*, const double*,
                                         const int*, long, float*, double2*, unsigned*, int, int, double,
-                                        hipStream_t);
+                                        const float*, hipStream_t);
 template hipError_t launch_shift<double>(const StepDims&, int, const double2*, const double*,
                                          const int*, long, double*, double2*, unsigned*, int, int,
-                                         double, hipStream_t);
+                                         double, const float*, hipStream_t);
+
+// m_g = max over (p, q) of |L_g[p][q]| (rounded up to FP32), one block per g
+__global__ __launch_bounds__(256) void lmax_kernel(int NN, const double* __restrict__ L, float* __restrict__ out) {
+  __shared__ double red[4];
+  const int g = blockIdx.x;
+  double m = 0.0;
+  for (int e = threadIdx.x; e < NN; e += 256) m = fmax(m, fabs(L[(size_t)g * NN + e]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    out[g] = (float)(m * (1.0 + 0x1p-20));
+  }
+}
+
+hipError_t setup_lmax(int K, int N, const double* L, float* lmax, hipStream_t s) {
+  hipLaunchKernelGGL(lmax_kernel, dim3(K), dim3(256), 0, s, N * N, L, lmax);
+  return hipGetLastError();
+}
 
 // ===========================================================================
 // VHS build: VHS_z = i sqrt(dt) sum_g xs_zg L_g over the packed (p <= q)
