@@ -114,9 +114,9 @@ ExTile exchange_split_tile(int n);
 constexpr int SPLIT_TILE_WIDE = 0, SPLIT_TILE_NARROW = 1;
 // FP32 output (split_out false): vhs [W][N][ldV] interleaved complex; vmax
 // (optional) per-walker max |VHS| (atomic, bit patterns of floats).
-// Split output: each row of ldV floats holds a plane of ldV fp16 hi halves
-// then one of lo halves, (Re, Im) interleaved, scaled by
-// 2^vhs_split_exp(vmax[z]) where vmax (required, read) holds each walker's
+// Split output: the same layout with each entry's 8 bytes holding fp16
+// (hi Re, hi Im, lo Re, lo Im) of the entry scaled by
+// 2^vhs_split_exp(vmax[z]), where vmax (required, read) holds each walker's
 // |VHS| bound.  lt: block-packed L split rows (vhs_split_pairs order), blk:
 // the blocks.
 hipError_t launch_vhs_split(int mode, const StepDims& d, int W, const unsigned short* xs, const float* xs_unscale,

@@ -9,8 +9,9 @@
 // with t0 = P phi; it equals the sum of the terms VHS^k t0 / k! up to
 // rounding.  v (hi/lo fp16 pairs, the B operand of every product) and t0
 // (FP32) live in LDS; the walker's VHS rows, already split by the VHS build
-// (fp16 hi and lo planes scaled by a power of two from a bound on the
-// walker's |VHS|), are streamed from memory straight into the A registers,
+// (each entry as fp16 hi and lo (Re, Im) pairs, scaled by a power of two
+// from a bound on the walker's |VHS|), are streamed from memory straight
+// into the A registers,
 // once per order, with no LDS staging and no barrier inside a product.  The
 // two spins of a walker get workgroup ids 8 apart, so they run on one XCD
 // and the second stream of the VHS rows comes from its L2.
@@ -61,7 +62,7 @@ struct PfCols {
 struct PropFusedArgs {
   double2* phi_a;                // [W][N][na] in / out
   double2* phi_b;                // [W][N][nb] in / out
-  const float* vhs;              // [W][N][ldV] split rows: ldV hi halves, then ldV lo halves
+  const float* vhs;              // [W][N][ldV / 2] entries of fp16 (hi Re, hi Im, lo Re, lo Im)
   const unsigned* vbound;        // [W] |VHS| bound (float bits): the scale of the split rows
   const unsigned short* psplit;  // [QP][nkbP][64] P split, scaled by 2^pexp
   int W, N, na, nb, ldV, RT, QP, QCH, TQS, nkbP, order, pexp, nspin;
@@ -207,19 +208,22 @@ __device__ __forceinline__ void pf_product_p(const PropFusedArgs& p, const PfCtx
   }
 }
 
+// four 32-bit words as a native vector (whole-register selects between two
+// of them stay in registers)
+typedef unsigned pf_u32x4 __attribute__((ext_vector_type(4)));
+
 // k blocks of VHS rows in flight per wave (a third set spills)
 constexpr int PF_DEPTH = 2;
 
-// The wave's split VHS operands of PF_DEPTH k blocks (the lane's 8 hi and 8
-// lo halves of each of its row tiles), loaded ahead of the products that use
-// them.
+// The wave's split VHS operands of PF_DEPTH k blocks (per row tile the
+// lane's four entries q0 .. q0+3, 32 contiguous bytes: hi and lo (Re, Im)
+// words alternate), loaded ahead of the products that use them.
 // Successive passes over the rows (one per Horner order) alternate the
 // direction of k, so that each pass starts on the blocks the previous one
 // read last, the ones most likely still in the L2.
 struct PfVhsStream {
-  uint4 rh[PF_DEPTH][PF_FM], rl[PF_DEPTH][PF_FM];
-  int aoff[PF_FM];  // byte offsets of the lane's hi halves in k block 0
-  int lo_off;       // bytes from a row's hi plane to its lo plane
+  pf_u32x4 r0[PF_DEPTH][PF_FM], r1[PF_DEPTH][PF_FM];  // entries q0, q0+1 and q0+2, q0+3
+  int aoff[PF_FM];  // byte offsets of the lane's entries in k block 0
   int nkb;          // k blocks
   int nkbe;         // positions per pass: k blocks rounded up to a multiple of PF_DEPTH (set s holds position s mod PF_DEPTH)
   int dir;          // direction of the current pass: 0 ascending k blocks, 1 descending
@@ -238,9 +242,8 @@ __device__ __forceinline__ void pf_vhs_fetch(PfVhsStream& v, __amdgpu_buffer_rsr
   const int kb = pos >= v.nkbe ? pf_block_at(v, pos - v.nkbe, v.dir ^ 1) : pf_block_at(v, pos, v.dir);
 #pragma unroll
   for (int i = 0; i < PF_FM; ++i) {
-    v.rh[s][i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(vrs, v.aoff[i], kb * 64, 0));
-    v.rl[s][i] =
-        __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(vrs, v.aoff[i], kb * 64 + v.lo_off, 0));
+    v.r0[s][i] = __builtin_bit_cast(pf_u32x4, __builtin_amdgcn_raw_buffer_load_b128(vrs, v.aoff[i], kb * 128, 0));
+    v.r1[s][i] = __builtin_bit_cast(pf_u32x4, __builtin_amdgcn_raw_buffer_load_b128(vrs, v.aoff[i], kb * 128 + 16, 0));
   }
 }
 
@@ -277,9 +280,9 @@ __device__ __forceinline__ void pf_product_v_nv(const PropFusedArgs& p, const Pf
     if (NV == 0) return;
     f16x8_t ah[PF_FM], al[PF_FM];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      ah[i] = __builtin_bit_cast(f16x8_t, vs.rh[s][i]);
-      al[i] = __builtin_bit_cast(f16x8_t, vs.rl[s][i]);
+    for (int i = 0; i < NV; ++i) {  // the hi words and the lo words of the four entries
+      ah[i] = __builtin_bit_cast(f16x8_t, __builtin_shufflevector(vs.r0[s][i], vs.r1[s][i], 0, 2, 4, 6));
+      al[i] = __builtin_bit_cast(f16x8_t, __builtin_shufflevector(vs.r0[s][i], vs.r1[s][i], 1, 3, 5, 7));
     }
 #pragma unroll
     for (int t = 0; t < CW; ++t) {
@@ -384,12 +387,11 @@ __global__ __launch_bounds__(PF_NT, 1) void prop_fused_kernel(PropFusedArgs p) {
   vs.nkb = p.RT;
   vs.nkbe = (p.RT + PF_DEPTH - 1) / PF_DEPTH * PF_DEPTH;
   vs.dir = 0;
-  vs.lo_off = 2 * p.ldV;
 #pragma unroll
   for (int i = 0; i < PF_FM; ++i) {
     const int rt = c.rg + PF_RG * i;
     // rows past N (and past the tiles) lie outside the buffer and read as zeros
-    vs.aoff[i] = rt < p.RT ? (rt * 16 + c.lrow) * p.ldV * 4 + 16 * c.kg : SPLIT_ROW_NONE;
+    vs.aoff[i] = rt < p.RT ? ((rt * 16 + c.lrow) * p.ldV + 8 * c.kg) * 4 : SPLIT_ROW_NONE;
   }
 
   // ---- phi into LDS, scaled by 2^e (the scale taken in FP64, so that any

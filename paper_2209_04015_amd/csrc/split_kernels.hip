@@ -374,7 +374,7 @@ struct VhsSplitArgs {
   unsigned* vmax;           // [W] FP32 output: max |VHS| (atomic), or null; split output: |VHS| bound (read)
   int W, nblk, N, ldV, rowb, nkb;
   float sdt;
-  int split_out;            // 1: rows of fp16 hi / lo planes scaled by 2^vhs_split_exp(bound)
+  int split_out;            // 1: fp16 (hi Re, hi Im, lo Re, lo Im) per entry, scaled by 2^vhs_split_exp(bound)
 };
 
 template <class H, class C>
@@ -427,8 +427,9 @@ __global__ __launch_bounds__(C::NT, C::WAVES_PER_EU) void vhs_split_kernel(VhsSp
       wmax[fi][h] = m;
     }
   }
-  // split output: each walker's values times its power-of-two scale, as
-  // (hi, lo) fp16 pairs of (Re, Im)
+  // split output: each walker's values times its power-of-two scale, as the
+  // 8 bytes (hi Re, hi Im, lo Re, lo Im) in fp16, stored where the FP32
+  // (Re, Im) pair would be
   float zsc[FM][2];
 #pragma unroll
   for (int fi = 0; fi < FM; ++fi)
@@ -438,13 +439,11 @@ __global__ __launch_bounds__(C::NT, C::WAVES_PER_EU) void vhs_split_kernel(VhsSp
       zsc[fi][h] = p.split_out && z < p.W ? ldexpf(1.f, vhs_split_exp(__uint_as_float(p.vmax[z]))) : 1.f;
     }
   // stores: one row half of walkers at a time through LDS [walker][pair]
-  // (a float2, or the split pair: hi (Re, Im) and lo (Re, Im) halves)
+  // (8 bytes per entry in either form, moved as they are)
   const int2 PQ = p.blk[tn];
   const int pb0 = VB_P * PQ.x, qb0 = VB_Q * PQ.y;
   float2* sv = reinterpret_cast<float2*>(vs_lds);
   uint2* su = reinterpret_cast<uint2*>(vs_lds);
-  unsigned* vu = reinterpret_cast<unsigned*>(p.vhs);  // split rows: hi plane [ldV halves], then lo plane
-  const int lo_u = p.ldV / 2;                         // the lo plane, in 4-byte (Re, Im) pairs
   for (int half = 0; half < C::WM; ++half) {
     __syncthreads();  // main loop (or the previous pass) done with the LDS
     if (wm == half) {
@@ -471,44 +470,6 @@ __global__ __launch_bounds__(C::NT, C::WAVES_PER_EU) void vhs_split_kernel(VhsSp
     }
     __syncthreads();
     const int zh = (m0 >> 1) + half * VHS_ZPASS;
-    if (p.split_out) {
-      // two neighbouring entries per thread: 8-byte stores into each plane
-      // (rows are 8-byte aligned: ldV is even; q0 = qb0 + qq and p0 = pb0 + pp
-      // are even)
-      static_assert(VB_P % 2 == 0 && VB_Q % 2 == 0, "pairs of entries");
-      auto put = [&](size_t row, int col, bool ok0, bool ok1, uint2 u0, uint2 u1) {
-        if (ok0 && ok1) {
-          *reinterpret_cast<uint2*>(vu + row + col) = make_uint2(u0.x, u1.x);
-          *reinterpret_cast<uint2*>(vu + row + lo_u + col) = make_uint2(u0.y, u1.y);
-        } else if (ok0) {
-          vu[row + col] = u0.x;
-          vu[row + lo_u + col] = u0.y;
-        } else if (ok1) {
-          vu[row + col + 1] = u1.x;
-          vu[row + lo_u + col + 1] = u1.y;
-        }
-      };
-      // (p, q), q >= p: consecutive threads on consecutive pairs of q
-      for (int e = tid; e < VHS_ZPASS * (C::BN / 2); e += C::NT) {
-        const int zl = e / (C::BN / 2), c2 = e - zl * (C::BN / 2);
-        const int pp = c2 / (VB_Q / 2), qq = 2 * (c2 - pp * (VB_Q / 2));
-        const int z = zh + zl, pr = pb0 + pp, qc = qb0 + qq;
-        if (z >= p.W || pr >= p.N) continue;
-        const int o = zl * C::BN + pp * VB_Q + qq;
-        put(((size_t)z * p.N + pr) * p.ldV, qc, qc < p.N && qc >= pr, qc + 1 < p.N && qc + 1 >= pr, su[o], su[o + 1]);
-      }
-      // mirror (q, p), q > p: consecutive threads on consecutive pairs of p
-      for (int e = tid; e < VHS_ZPASS * (C::BN / 2); e += C::NT) {
-        const int zl = e / (C::BN / 2), c2 = e - zl * (C::BN / 2);
-        const int qq = c2 / (VB_P / 2), pp = 2 * (c2 - qq * (VB_P / 2));
-        const int z = zh + zl, pr = pb0 + pp, qc = qb0 + qq;
-        if (z >= p.W || qc >= p.N) continue;
-        const int o = zl * C::BN + pp * VB_Q + qq;
-        put(((size_t)z * p.N + qc) * p.ldV, pr, pr < p.N && qc > pr, pr + 1 < p.N && qc > pr + 1, su[o],
-            su[o + VB_Q]);
-      }
-      continue;
-    }
     // (p, q), q >= p: consecutive threads on consecutive q
     for (int e = tid; e < VHS_ZPASS * C::BN; e += C::NT) {
       const int zl = e / C::BN, c = e - zl * C::BN;
@@ -573,7 +534,7 @@ static hipError_t launch_vhs_split_t(int mode, const StepDims& d, int W, const u
   const int rowb = 2 * d.ldhK * 2;
   if ((double)(C::BM > C::BN ? C::BM : C::BN) * rowb >= (double)SPLIT_ROW_NONE) return hipErrorInvalidValue;
   const int ntm = ceil_div(2 * W, C::BM), ntn = nblk;
-  if (split_out && (!vmax || d.ldV % 2 != 0)) return hipErrorInvalidValue;
+  if (split_out && !vmax) return hipErrorInvalidValue;
   VhsSplitArgs p{xs,     xs_unscale, lt,   lt_unscale, blk,           vhs,        vmax,
                  W,      nblk,       d.N,  d.ldV,      rowb,          d.ldhK / 32, (float)sdt,
                  split_out ? 1 : 0};
