@@ -37,7 +37,15 @@ template <> struct Cplx<double> { using t = double2; };
 #endif
 constexpr int GF_THREADS = 256;
 constexpr int GF_CHUNK = GF_CHUNK_ROWS;
-constexpr int GF_SBLK = 3;  // 2 x 2 blocks of S per thread: ceil(n / 2)^2 <= 3 * 256, n <= 45
+// Instances by the bound NB on the electrons per spin (32 or 45): 2 x 2
+// blocks of S per thread, ceil(NB / 2)^2 <= GF_SBLK * 256, and walker-chunk
+// entries per thread
+template <int NB>
+struct GfBound {
+  static constexpr int SBLK = ((NB + 1) / 2 * ((NB + 1) / 2) + GF_THREADS - 1) / GF_THREADS;
+  static constexpr int LD = (GF_CHUNK * NB + GF_THREADS - 1) / GF_THREADS;
+  static constexpr bool PREFETCH = NB <= 32;  // the larger instance has no registers to spare
+};
 
 static size_t gf_lds_bytes(int n) {
   return (size_t)n * 2 * n * sizeof(double2)       // [S | I]
@@ -47,12 +55,13 @@ static size_t gf_lds_bytes(int n) {
          + 8 * sizeof(double2) + 16;               // reductions, pivot
 }
 
-template <typename T>
+template <typename T, int NB>
 __global__ __launch_bounds__(GF_THREADS) __attribute__((amdgpu_waves_per_eu(GF_WPE))) void gf_kernel(
     StepDims d, const double2* __restrict__ phi_a, const double2* __restrict__ phi_b,
     const double* __restrict__ phiT, const double* __restrict__ hh, T* __restrict__ theta,
     double2* __restrict__ logdet, double2* __restrict__ e1, int* __restrict__ status) {
   extern __shared__ double2 gf_lds[];
+  constexpr int GF_SBLK = GfBound<NB>::SBLK, GF_LD = GfBound<NB>::LD;
   const int z = blockIdx.x;
   const int sp = blockIdx.y;
   const int n = sp == 0 ? d.na : d.nb;
@@ -84,14 +93,46 @@ __global__ __launch_bounds__(GF_THREADS) __attribute__((amdgpu_waves_per_eu(GF_W
   for (int b = 0; b < GF_SBLK; ++b)
 #pragma unroll
     for (int q = 0; q < 4; ++q) sacc[b][q] = make_double2(0.0, 0.0);
+  // the walker's chunk after the current one is loaded into registers while
+  // the current one is worked on (entry e of chunk p0: row p0 + e / n,
+  // orbital e % n); the trial's rows, shared by every walker, come from the
+  // L2 when the chunk is stored
+  typedef double d2v __attribute__((ext_vector_type(2)));  // a native vector: kept in registers
+  d2v pf[GF_LD];
+  auto load_chunk = [&](int p0) {
+    if (!GfBound<NB>::PREFETCH) return;
+    const int cnt = p0 < N ? min(GF_CHUNK, N - p0) * n : 0;
+#pragma unroll
+    for (int b = 0; b < GF_LD; ++b) {
+      const int e = tid + b * GF_THREADS;
+      pf[b] = e < cnt ? *reinterpret_cast<const d2v*>(phi + (size_t)p0 * n + e) : d2v{0.0, 0.0};
+    }
+  };
+  auto store_chunk = [&](int p0, bool with_trial) {
+    const int cnt = min(GF_CHUNK, N - p0) * n;
+    if (GfBound<NB>::PREFETCH) {
+#pragma unroll
+      for (int b = 0; b < GF_LD; ++b) {
+        const int e = tid + b * GF_THREADS;
+        if (e < cnt) {
+          ch[e] = make_double2(pf[b].x, pf[b].y);
+          if (with_trial) tch[e] = pT[(size_t)(p0 + e / n) * d.nmax + e % n];
+        }
+      }
+    } else {
+#pragma unroll 1
+      for (int e = tid; e < cnt; e += GF_THREADS) {
+        ch[e] = phi[(size_t)p0 * n + e];
+        if (with_trial) tch[e] = pT[(size_t)(p0 + e / n) * d.nmax + e % n];
+      }
+    }
+  };
+  load_chunk(0);
   for (int p0 = 0; p0 < N; p0 += GF_CHUNK) {
     const int rows = min(GF_CHUNK, N - p0);
     __syncthreads();
-    for (int e = tid; e < rows * n; e += GF_THREADS) {
-      const int pr = e / n, j = e % n;
-      ch[e] = phi[(size_t)(p0 + pr) * n + j];
-      tch[e] = pT[(size_t)(p0 + pr) * d.nmax + j];
-    }
+    store_chunk(p0, true);
+    load_chunk(p0 + GF_CHUNK);
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < GF_SBLK; ++b) {
@@ -200,13 +241,12 @@ __global__ __launch_bounds__(GF_THREADS) __attribute__((amdgpu_waves_per_eu(GF_W
   const size_t plane = (size_t)d.nmax * d.ldN;
   T* th_re = theta ? theta + ((size_t)(2 * z + 0) * 2 + sp) * plane : nullptr;
   T* th_im = theta ? theta + ((size_t)(2 * z + 1) * 2 + sp) * plane : nullptr;
+  load_chunk(0);
   for (int p0 = 0; p0 < N; p0 += GF_CHUNK) {
     const int rows = min(GF_CHUNK, N - p0);
     __syncthreads();
-    for (int e = tid; e < rows * n; e += GF_THREADS) {
-      const int pr = e / n, j = e % n;
-      ch[e] = phi[(size_t)(p0 + pr) * n + j];
-    }
+    store_chunk(p0, false);
+    load_chunk(p0 + GF_CHUNK);
     __syncthreads();
     // 2 x 2 blocks of outputs (two rows of the chunk, two columns): four LDS
     // reads feed four products; consecutive threads take consecutive row pairs
@@ -215,6 +255,14 @@ __global__ __launch_bounds__(GF_THREADS) __attribute__((amdgpu_waves_per_eu(GF_W
       const int bj = e / nbp, bp = e - bj * nbp;
       const int j0 = 2 * bj, j1 = min(j0 + 1, n - 1);
       const int q0 = 2 * bp, q1 = min(q0 + 1, rows - 1);
+      // the one-body weights of the four outputs, loaded ahead of the products
+      double hv[4] = {0.0, 0.0, 0.0, 0.0};
+      if (GfBound<NB>::PREFETCH) {
+        hv[0] = hs[(size_t)j0 * N + p0 + q0];
+        hv[1] = hs[(size_t)j1 * N + p0 + q0];
+        hv[2] = hs[(size_t)j0 * N + p0 + q1];
+        hv[3] = hs[(size_t)j1 * N + p0 + q1];
+      }
       double2 t00 = make_double2(0.0, 0.0), t01 = t00, t10 = t00, t11 = t00;
       if (!singular) {
         for (int k = 0; k < n; ++k) {
@@ -233,7 +281,7 @@ __global__ __launch_bounds__(GF_THREADS) __attribute__((amdgpu_waves_per_eu(GF_W
         if (j >= n || q >= rows) continue;
         const int p = p0 + q;
         const double2 t = tv[o];
-        const double h = hs[(size_t)j * N + p];
+        const double h = GfBound<NB>::PREFETCH ? hv[o] : hs[(size_t)j * N + p];
         eacc.x += h * t.x;
         eacc.y += h * t.y;
         if (theta) {
@@ -254,8 +302,12 @@ hipError_t launch_gf(const StepDims& d, int W, const double2* phi_a, const doubl
                      const double* phiT, const double* hh, T* theta, double2* logdet,
                      double2* e1, int* status, hipStream_t s) {
   const size_t lds = gf_lds_bytes(d.nmax);
-  hipLaunchKernelGGL(gf_kernel<T>, dim3(W, 2), dim3(GF_THREADS), lds, s, d, phi_a, phi_b, phiT,
-                     hh, theta, logdet, e1, status);
+  if (d.nmax <= 32)
+    hipLaunchKernelGGL((gf_kernel<T, 32>), dim3(W, 2), dim3(GF_THREADS), lds, s, d, phi_a, phi_b, phiT, hh, theta,
+                       logdet, e1, status);
+  else
+    hipLaunchKernelGGL((gf_kernel<T, 45>), dim3(W, 2), dim3(GF_THREADS), lds, s, d, phi_a, phi_b, phiT, hh, theta,
+                       logdet, e1, status);
   return hipGetLastError();
 }
 template hipError_t launch_gf<float>(const StepDims&, int, const double2*, const double2*,
@@ -1138,6 +1190,9 @@ static __host__ __device__ inline int qr_col_stride(int N) { return N + ((9 - N 
 // substitution (values unused): padding behind the n x n block
 constexpr int QR_BPAD = 48;
 
+// walker loads per thread issued together (one wait per batch)
+constexpr int QR_LD_BATCH = 8;
+
 size_t qr_lds_bytes_for(int N, int n) {
   return (size_t)n * qr_col_stride(N) * sizeof(double2) + ((size_t)n * n + QR_BPAD) * sizeof(double2) +
          n * sizeof(double) + 64;
@@ -1167,9 +1222,23 @@ __global__ __launch_bounds__(QR_THREADS) void qr_kernel(StepDims d, double2* __r
   const double* Ad = reinterpret_cast<const double*>(A);
   double2* phi = (sp == 0 ? phi_a : phi_b) + (size_t)z * N * n;
 
-  for (int e = tid; e < N * n; e += QR_THREADS) {
-    const int p = e / n, j = e - p * n;
-    A[j * Np + p] = phi[e];
+  // phi into LDS, QR_LD_BATCH loads per thread in flight at a time
+  for (int e0 = 0; e0 < N * n; e0 += QR_LD_BATCH * QR_THREADS) {
+    typedef double d2v __attribute__((ext_vector_type(2)));  // a native vector: kept in registers
+    d2v v[QR_LD_BATCH];
+#pragma unroll
+    for (int b = 0; b < QR_LD_BATCH; ++b) {
+      const int e = e0 + b * QR_THREADS + tid;
+      v[b] = e < N * n ? *reinterpret_cast<const d2v*>(phi + e) : d2v{0.0, 0.0};
+    }
+#pragma unroll
+    for (int b = 0; b < QR_LD_BATCH; ++b) {
+      const int e = e0 + b * QR_THREADS + tid;
+      if (e < N * n) {
+        const int p = e / n, j = e - p * n;
+        A[j * Np + p] = make_double2(v[b].x, v[b].y);
+      }
+    }
   }
   // this thread's Cholesky entries (i, j), i <= j, in row-major order
   const int npair = n * (n + 1) / 2;
@@ -1338,12 +1407,13 @@ hipError_t set_kernel_attributes(const StepDims& d) {
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(qr_kernel<48>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, big);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(gf_kernel<float>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(gf_kernel<double>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  if (e != hipSuccess) return e;
+  for (const void* f : {reinterpret_cast<const void*>(gf_kernel<float, 32>),
+                        reinterpret_cast<const void*>(gf_kernel<float, 45>),
+                        reinterpret_cast<const void*>(gf_kernel<double, 32>),
+                        reinterpret_cast<const void*>(gf_kernel<double, 45>)}) {
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+  }
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(exchange_kernel<float>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, big);
   if (e != hipSuccess) return e;

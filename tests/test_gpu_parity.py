@@ -250,6 +250,30 @@ def test_orthogonalise_matches_oracle(name, precision, uhf):
     assert np.abs(w.log_ovlp.cpu().numpy() - lo).max() < 1e-11
 
 
+@pytest.mark.parametrize("name,precision,uhf", [("n20", "fp64", False), ("ragged", "fp64", True)])
+def test_orthogonalise_ill_conditioned_walkers(name, precision, uhf):
+    """Walkers with nearly dependent orbitals (condition number ~1e3 to 1e4):
+    one Cholesky QR pass would leave Q^H Q up to kappa^2 eps ~ 1e-10 from I;
+    with the second pass Q is orthonormal to ~n eps.  Against the oracle the
+    bar is 1e-11 (Q of such a matrix is determined to about kappa eps)."""
+    c = case(name, precision, uhf)
+    rng = np.random.default_rng(11)
+    pa = c.pa.copy()
+    eps = np.logspace(-3, -4, c.cfg.W)[:, None]
+    pa[:, :, 1] = pa[:, :, 0] + eps * pa[:, :, 1]
+    if pa.shape[2] > 2:
+        pa[:, :, 2] = pa[:, :, 0] - eps * pa[:, :, 2] + eps * rng.standard_normal(pa[:, :, 2].shape)
+    w = c.walkers(pa=pa)
+    c.ham.orthogonalise(w)
+    qa, qb, lo = orc.orthogonalise(pa, c.pb, c.lo)
+    ga = w.phi_a.cpu().numpy()
+    gram = np.einsum("zpi,zpj->zij", ga.conj(), ga)
+    assert np.abs(gram - np.eye(ga.shape[2])[None]).max() < 1e-13
+    assert np.abs(ga - qa).max() < 1e-11
+    assert np.abs(w.phi_b.cpu().numpy() - qb).max() < 1e-12
+    assert np.abs(w.log_ovlp.cpu().numpy() - lo).max() < 1e-10
+
+
 def test_orthogonalise_discards_a_rank_deficient_walker():
     """A walker with a vanished orbital: QR_ZERO is set, the walker keeps its
     orbitals and gets weight 0 (log w = -inf); the others are orthogonalised."""
