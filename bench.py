@@ -132,7 +132,18 @@ def run_gpu(cfg, h1, L, phiT, precision, steps, warmup, fields_dev, block_fields
         ham.profile_enable(steps * 40)
         ms_prof = timed_steps(warmup)
         phases = ham.profile_read()
+        # each roofline kernel again in a pass of its own in which only its
+        # phase is bracketed by events (none between the other kernels)
+        iso = {}
+        for ph in ROOFLINE_PHASES:
+            if phases[ph][1] == 0:
+                continue
+            ham.profile_phases([ph])
+            timed_steps(warmup)
+            iso[ph] = ham.profile_read()[ph]
+        ham.profile_phases(None)
         ham.profile_enable(0)
+        phases["_isolated"] = iso
         log(f"{cfg.name} {precision}: profiled pass {ms_prof / steps:.3f} ms/step")
     extra = {"exchange_algorithm": ham.exchange}
     if profile:
@@ -587,10 +598,11 @@ ROOFLINE_PHASES = ("vhs", "exchange", "propagate", "taylor", "one_body", "force_
 
 
 def roofline_of(cfg, phases, precision, algo, phase, steps):
-    """Roofline entry of one phase from the profiled pass: algorithmic work of
-    one step's launches / their measured time, against the peak of the unit
-    the phase runs on (matrix cores of the MFMA dtype, or HBM)."""
-    ms, launches = phases[phase]
+    """Roofline entry of one phase: algorithmic work of one step's launches /
+    their measured time (from the pass in which only this phase is timed, when
+    there is one), against the peak of the unit the phase runs on (matrix
+    cores of the MFMA dtype, or HBM)."""
+    ms, launches = phases.get("_isolated", {}).get(phase, phases[phase])
     if launches == 0:
         return None
     bound, work, unit = phase_work(cfg, phase, precision, algo)
@@ -632,7 +644,7 @@ def rooflines(cfg, phases, precision, algo, steps):
     if not phases:
         return {}
     out = {ph: roofline_of(cfg, phases, precision, algo, ph, steps) for ph in ROOFLINE_PHASES}
-    order = sorted(out, key=lambda ph: -phases[ph][0])
+    order = sorted(out, key=lambda ph: -phases[ph][0])  # shares of the step from the all-phase pass
     return {ph: out[ph] for ph in order if out[ph] is not None}
 
 
@@ -759,7 +771,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--config", default="n290")
     ap.add_argument("--cpu-sample", type=int, default=4, help="walkers in the timed oracle sample")
     ap.add_argument("--cpu-steps", type=int, default=5, help="consecutive oracle steps timed (median reported)")
@@ -832,7 +844,7 @@ def main():
         torch.cuda.empty_cache()
 
     def phase_table(phases):
-        return {k: round(v[0] / args.steps, 4) for k, v in phases.items() if v[1] > 0}
+        return {k: round(v[0] / args.steps, 4) for k, v in phases.items() if not k.startswith("_") and v[1] > 0}
 
     if args.only:
         ms, ph, st = results[args.only]
@@ -923,8 +935,9 @@ def main():
         "roofline": roofline(cfg, phh, head, extras[head]["exchange_algorithm"], args.steps),
         "rooflines": rooflines(cfg, phh, head, extras[head]["exchange_algorithm"], args.steps),
         "roofline_note": "achieved = algorithmic work of the phase's launches in one step / their time, measured "
-                         "with HIP events around every launch in a second (profiled) pass of the same number of "
-                         "steps; value and ms_per_step come from the pass without events",
+                         "with HIP events around the phase's launches in a pass of the same steps in which only "
+                         "that phase is timed; phases_ms_per_step comes from a pass with every phase timed; value "
+                         "and ms_per_step come from the pass without events",
         "cpu_baseline": cpu,
         "fp64": paths["fp64"],
         "mixed_over_fp64": round(ms64 / msh, 3),

@@ -330,6 +330,11 @@ enum {
 };
 int afqmc_profile_enable(afqmc_ham* ham, int max_records);
 int afqmc_profile_read(afqmc_ham* ham, double* ms, int* launches);
+/* Restricts the timing to the phases whose bit (1 << AFQMC_PH_*) is set in
+ * `mask` (initially all): the events of the other phases are not recorded,
+ * so one phase can be timed with no events between the kernels of the rest
+ * of the step.  Takes effect for the calls that follow; no device work. */
+int afqmc_profile_phases(afqmc_ham* ham, unsigned mask);
 
 /* ---- uneven multi-system batch (several Hamiltonians, one graph launch) ----
  *

@@ -55,6 +55,7 @@ EXPORTED = (
     "afqmc_get_setup",
     "afqmc_profile_enable",
     "afqmc_profile_read",
+    "afqmc_profile_phases",
     "afqmc_batch_create",
     "afqmc_batch_step",
     "afqmc_autotune",
@@ -155,6 +156,7 @@ def load(path: str = LIB_PATH):
     lib.afqmc_get_setup.argtypes = [vp, vp, dp, dp]
     lib.afqmc_profile_enable.argtypes = [vp, ip]
     lib.afqmc_profile_read.argtypes = [vp, vp, vp]
+    lib.afqmc_profile_phases.argtypes = [vp, ctypes.c_uint]
     lib.afqmc_batch_create.argtypes = [vp, vp, vp, ip, P(_BatchOpts), P(vp)]
     lib.afqmc_batch_step.argtypes = [vp, vp, vp, ip, ip, vp]
     lib.afqmc_autotune.argtypes = [vp, ctypes.c_char_p]
@@ -505,6 +507,11 @@ class Hamiltonian:
     def profile_enable(self, max_records: int):
         """Bracket every kernel phase with HIP events on its stream (0 turns it off)."""
         _check(_lib.afqmc_profile_enable(self._h, int(max_records)))
+
+    def profile_phases(self, phases=None):
+        """Time only the named phases (None: all) from the next call on."""
+        mask = 0xFFFFFFFF if phases is None else sum(1 << PHASES.index(p) for p in phases)
+        _check(_lib.afqmc_profile_phases(self._h, mask))
 
     def profile_read(self):
         """{phase: (total ms, launches)} since the last read; synchronises."""

@@ -151,6 +151,7 @@ struct afqmc_ham {
   // phase timing (afqmc_profile_enable)
   std::vector<hipEvent_t> ev;
   int ev_used = 0;
+  unsigned prof_mask = ~0u;  // phases that are timed (bit p: phase p)
   struct Rec { int phase, e0, e1; };
   std::vector<Rec> recs;
   // afqmc_step cache
@@ -201,9 +202,11 @@ int set_device(const afqmc_ham* h) {
   return AFQMC_OK;
 }
 
-// Phase timing: an event before and after each kernel phase, on the call's stream.
-int prof_mark(afqmc_ham* h, hipStream_t s) {
+// Phase timing: an event before and after each selected kernel phase, on the
+// call's stream.
+int prof_mark(afqmc_ham* h, int phase, hipStream_t s) {
   if (h->capturing || h->ev.empty() || h->ev_used + 2 > (int)h->ev.size()) return -1;
+  if (!((h->prof_mask >> phase) & 1u)) return -1;
   if (hipEventRecord(h->ev[h->ev_used], s) != hipSuccess) return -1;
   return h->ev_used++;
 }
@@ -215,7 +218,7 @@ void prof_close(afqmc_ham* h, int phase, int e0, hipStream_t s) {
 
 #define PHASE(h, ph, s, expr)            \
   do {                                   \
-    const int e0__ = prof_mark((h), (s)); \
+    const int e0__ = prof_mark((h), (ph), (s)); \
     HIP_TRY(expr);                       \
     prof_close((h), (ph), e0__, (s));    \
   } while (0)
@@ -1119,6 +1122,12 @@ int afqmc_profile_enable(afqmc_ham* h, int max_records) {
     h->ev.push_back(e);
   }
   h->recs.reserve(max_records);
+  return AFQMC_OK;
+}
+
+int afqmc_profile_phases(afqmc_ham* h, unsigned mask) {
+  if (!h) return fail(AFQMC_EINVAL, "null Hamiltonian handle");
+  h->prof_mask = mask;
   return AFQMC_OK;
 }
 

@@ -211,7 +211,7 @@ def test_fused_and_term_by_term_propagation_agree(name, uhf):
     errs = {}
     for label, ham in (("fused", c.ham), ("term by term", unfused)):
         # the same call twice on one handle: the second must not see what the
-        # first left in the workspace (the fused path splits its VHS in place)
+        # first left in the workspace (the VHS rows, split or not, are rebuilt)
         w0 = c.walkers()
         ham.propagate(w0, torch.as_tensor(c.x, device=c.dev))
         w = c.walkers()
@@ -236,6 +236,26 @@ def test_fused_and_term_by_term_propagation_agree(name, uhf):
           f"term by term {errs['term by term']:.3e}", flush=True)
     assert errs["fused"] <= 1e-4 and errs["term by term"] <= 1e-4
     unfused.close()
+
+
+def test_profile_phases_restricts_the_timing():
+    """afqmc_profile_phases: with only the VHS phase selected a propagation
+    records one VHS launch and nothing else; with all phases selected again
+    the force bias, the shift and the propagation are recorded too."""
+    torch = _torch()
+    c = case("n20", "fp16x3")
+    x = torch.as_tensor(c.x, device=c.dev)
+    c.ham.profile_enable(64)
+    c.ham.profile_phases(["vhs"])
+    c.ham.propagate(c.walkers(), x)
+    ph = c.ham.profile_read()
+    assert ph["vhs"][1] == 1 and ph["vhs"][0] > 0.0
+    assert all(n == 0 for p, (_, n) in ph.items() if p != "vhs")
+    c.ham.profile_phases(None)
+    c.ham.propagate(c.walkers(), x)
+    ph = c.ham.profile_read()
+    c.ham.profile_enable(0)
+    assert ph["vhs"][1] == 1 and ph["shift"][1] == 1 and ph["propagate"][1] == 1 and ph["force_bias"][1] >= 1
 
 
 @pytest.mark.parametrize("name,precision,uhf", PARAMS)
