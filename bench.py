@@ -874,8 +874,8 @@ def main():
     legs = {}
     msd = batch = None
     if not args.no_legs:
-        # BASELINE configurations other than the headline: the FP64 GPU
-        # baseline size (n100) and the mixed-precision size (n200)
+        # the paper's other workload sizes beside the headline one: the FP64
+        # GPU comparison size (n100) and the mixed-precision size (n200)
         legs["n100"] = run_config_leg("n100", ("fp64", args.headline), 10, 2, device)
         legs["n200"] = run_config_leg("n200", ("fp64", "fp32", "bf16x3", "fp16x3"), 10, 2, device)
         msd = run_msd(cfg, h1, L, device, args.steps, args.msd_dets)
