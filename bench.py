@@ -542,13 +542,13 @@ def _kernel_of(phase, precision, algo):
     if phase == "exchange":
         base = ("exchange_pair" if algo == "pair" else "exchange") + ("_split_kernel" if split else "_kernel")
         if split and algo == "pair":   # the default (wide) walker tile of the split pair kernel
-            return base, f"{base}<{H},SplitCfgT<160,160>>"
+            return base, f"{base}<{H},SplitCfgT<128,128,3>>"
         return base, f"{base}<{H if split else T}>"
     if phase == "propagate":
         return "prop_fused_kernel", "prop_fused_kernel<4>"
     if phase == "vhs":
         if precision == "fp16x3":   # the VHS runs on split operands only in FP16X3 (default wide tile)
-            return "vhs_split_kernel", "vhs_split_kernel<HalfF16,SplitCfgT<160,160>>"
+            return "vhs_split_kernel", "vhs_split_kernel<HalfF16,SplitCfgT<128,128,3>>"
         # tile template arguments of the FP32 / FP64 VHS instances (step_kernels.hip)
         return "vhs_kernel", {"double": "vhs_kernel<double, 64, 64, 16, 2, 2>",
                               "float": "vhs_kernel<float, 64, 64, 32, 2, 2>"}[T]

@@ -378,9 +378,9 @@ int afqmc_batch_step(afqmc_batch* b, const double* const* fields, void* const* e
  *   vhs_tile_m x vhs_tile_n  output tile of the VHS build: (walker, re|im)
  *                            rows by orbital-pair columns
  * Offered shapes: the split pair exchange (BF16X3, FP16X3 with pair
- * integrals) 160 x 160 or 160 x 64; the split VHS build (FP16X3) 160 x 160
- * or 64 x 160; every other kernel one shape (exchange 192 x 160, VHS
- * 64 x 64). */
+ * integrals) 128 x 128 or 128 x 64; the split VHS build (FP16X3) 128 x 128
+ * or 64 x 128; every other kernel one shape (split direct exchange
+ * 160 x 160, FP32 / FP64 exchange 192 x 160, FP32 / FP64 VHS 64 x 64). */
 typedef struct afqmc_tuning {
   int ex_tile_m, ex_tile_n;
   int ex_group;

@@ -1918,16 +1918,19 @@ bool ex_tiles_offered(const afqmc_ham* h) { return h->split != SPLIT_NONE && h->
 bool vhs_tiles_offered(const afqmc_ham* h) { return vhs_split(h); }
 
 void tile_shapes(const afqmc_ham* h, int ex_tile, int vhs_tile, afqmc_tuning* t) {
-  if (h->split != SPLIT_NONE) {
+  if (ex_tiles_offered(h)) {  // the split pair exchange
+    t->ex_tile_m = 128;
+    t->ex_tile_n = ex_tile == SPLIT_TILE_NARROW ? 64 : 128;
+  } else if (h->split != SPLIT_NONE) {  // the split direct exchange
     t->ex_tile_m = 160;
-    t->ex_tile_n = ex_tiles_offered(h) && ex_tile == SPLIT_TILE_NARROW ? 64 : 160;
+    t->ex_tile_n = 160;
   } else {
     t->ex_tile_m = 192;
     t->ex_tile_n = 160;
   }
   if (vhs_split(h)) {
-    t->vhs_tile_m = vhs_tile == SPLIT_TILE_NARROW ? 64 : 160;
-    t->vhs_tile_n = 160;
+    t->vhs_tile_m = vhs_tile == SPLIT_TILE_NARROW ? 64 : 128;
+    t->vhs_tile_n = 128;
   } else {
     t->vhs_tile_m = 64;
     t->vhs_tile_n = 64;

@@ -98,22 +98,30 @@ hipError_t launch_split_rows_mode(int mode, long nrows, int ncols, const float* 
 // ---------------------------------------------------------------------------
 // Exchange on split operands.
 // ---------------------------------------------------------------------------
-// 4-wave workgroups of 80 x 80 wave tiles; register prefetch of the next k
-// block, one LDS stage; two workgroups per CU, so that one workgroup's
-// epilogue runs beside the other's matrix-core work.
-template <int BM_, int BN_>
+// 4-wave workgroups of 2 x 2 wave tiles; register prefetch of the next k
+// block, one LDS stage; WPE workgroups per CU (two by default), so that one
+// workgroup's epilogue runs beside another's matrix-core work.
+template <int BM_, int BN_, int WPE_ = 2>
 struct SplitCfgT {
   static constexpr int BM = BM_, BN = BN_, WM = 2, WN = 2, GS = 8;
   static constexpr int NT = WM * WN * 64;
   static constexpr int NA = BM * 8 / NT, NB = BN * 8 / NT;
-  static constexpr int WAVES_PER_EU = 2;
+  static constexpr int WAVES_PER_EU = WPE_;
   static_assert(BM % 32 == 0 && BN % 32 == 0, "whole fragments and staging rows");
 };
 using ExSplitCfg = SplitCfgT<160, 160>;
-// narrow walker tiles (autotuner candidates for systems with few walkers):
-// 32 walkers per pair-exchange tile, 32 walkers per VHS tile
-using ExPairNarrowCfg = SplitCfgT<160, 64>;
-using VhsNarrowCfg = SplitCfgT<64, 160>;
+// The pair exchange and the VHS build: 128 x 128 tiles at three workgroups
+// per CU (more tiles in flight hide each one's first loads and epilogue:
+// 0.49 -> 0.47 ms and 0.72 -> 0.70 ms per step at n290), and narrow walker
+// tiles (autotuner candidates for systems with few walkers): 32 walkers per
+// pair-exchange tile, 32 walkers per VHS tile.  Both pair shapes have the
+// row-tile height the pair tables are built for, both VHS shapes the width
+// of a VHS pair block.
+using ExPairWideCfg = SplitCfgT<128, 128, 3>;
+using ExPairNarrowCfg = SplitCfgT<128, 64, 3>;
+static_assert(ExPairWideCfg::BM == ExPairNarrowCfg::BM, "one row-tile height for the pair tables");
+using VhsWideCfg = SplitCfgT<128, 128, 3>;
+using VhsNarrowCfg = SplitCfgT<64, 128>;
 
 struct ExSplitArgs {
   const unsigned short* a;  // Lh split rows of this spin: [K][nmax][2 ldh] halves
@@ -257,8 +265,10 @@ struct PairSplitArgs {
 template <class H, class C>
 __global__ __launch_bounds__(C::NT, C::WAVES_PER_EU) void exchange_pair_split_kernel(
     PairSplitArgs p, double2* __restrict__ part, int ntg, int nwt, int gs) {
-  static_assert(SplitStage<C::BM, C::BN>::BYTES <= EXS_TAB_OFF && 4 * C::WM * C::BN * 16 <= EXS_TAB_OFF,
-                "operand stage and column sums fit");
+  // the operand stage, then (epilogue) the column sums, in LDS sized for the
+  // shape (three workgroups of the wide shape fit a CU)
+  constexpr int PAIR_LDS = SplitStage<C::BM, C::BN>::BYTES > 4 * C::WM * C::BN * 16 ? SplitStage<C::BM, C::BN>::BYTES
+                                                                                    : 4 * C::WM * C::BN * 16;
   int rt, wt;
   if (!xcd_tile(blockIdx.x, ntg, nwt, gs, rt, wt)) return;
   const int z0 = wt * (C::BN / 2);
@@ -267,7 +277,7 @@ __global__ __launch_bounds__(C::NT, C::WAVES_PER_EU) void exchange_pair_split_ke
     exchange_pair_zero<C::BN>(z0, p.W, out);
     return;
   }
-  __shared__ __attribute__((aligned(16))) char exs_lds[EXS_LDS_BYTES];
+  __shared__ __attribute__((aligned(16))) char exs_lds[PAIR_LDS];
   const int tid = threadIdx.x;
   const int schunk = tid & 7, srow = tid >> 3;
   const int i = pair_group(p.tab, p.n, rt);
@@ -300,7 +310,7 @@ __global__ __launch_bounds__(C::NT, C::WAVES_PER_EU) void exchange_pair_split_ke
                                                                 out);
 }
 
-int exchange_pair_split_rows() { return ExSplitCfg::BM; }
+int exchange_pair_split_rows() { return ExPairWideCfg::BM; }
 
 template <class C>
 static hipError_t launch_exchange_pair_split_t(int mode, const StepDims& d, int W, const PairLaunch& pl,
@@ -337,8 +347,8 @@ hipError_t launch_exchange_pair_split(int mode, const StepDims& d, int W, const 
   if (tile == SPLIT_TILE_NARROW)
     return launch_exchange_pair_split_t<ExPairNarrowCfg>(mode, d, W, pl, v, v_unscale, th, th_unscale, theta, part,
                                                          sp, s, gs);
-  return launch_exchange_pair_split_t<ExSplitCfg>(mode, d, W, pl, v, v_unscale, th, th_unscale, theta, part, sp, s,
-                                                  gs);
+  return launch_exchange_pair_split_t<ExPairWideCfg>(mode, d, W, pl, v, v_unscale, th, th_unscale, theta, part, sp,
+                                                     s, gs);
 }
 
 // ---------------------------------------------------------------------------
@@ -349,12 +359,12 @@ hipError_t launch_exchange_pair_split(int mode, const StepDims& d, int W, const 
 // index.
 // ---------------------------------------------------------------------------
 // VHS blocks: the orbital pairs are packed in blocks of VB_P rows p by VB_Q
-// columns q (one 160-column tile per block; blocks that touch the upper
+// columns q (one 128-column tile per block; blocks that touch the upper
 // triangle q >= p, pairs outside the matrix or below the diagonal are zero
 // rows and are not stored).  The tile's values go through LDS, so that both
-// halves leave as contiguous runs: (p, q) rows of VB_Q pairs and the mirror
-// (q, p) rows of VB_P pairs (full 128-byte lines).
-constexpr int VB_P = 16, VB_Q = 10;
+// halves leave as contiguous runs: (p, q) rows of VB_Q pairs (64 bytes) and
+// the mirror (q, p) rows of VB_P pairs (full 128-byte lines).
+constexpr int VB_P = 16, VB_Q = 8;
 // walkers per LDS pass of the store (the waves of one row half), and the LDS
 template <class C>
 struct VhsLds {
@@ -552,7 +562,7 @@ hipError_t launch_vhs_split(int mode, const StepDims& d, int W, const unsigned s
   if (tile == SPLIT_TILE_NARROW)
     return launch_vhs_split_t<VhsNarrowCfg>(mode, d, W, xs, xs_unscale, lt, lt_unscale, blk, nblk, vhs, vmax,
                                             split_out, sdt, s);
-  return launch_vhs_split_t<ExSplitCfg>(mode, d, W, xs, xs_unscale, lt, lt_unscale, blk, nblk, vhs, vmax, split_out,
+  return launch_vhs_split_t<VhsWideCfg>(mode, d, W, xs, xs_unscale, lt, lt_unscale, blk, nblk, vhs, vmax, split_out,
                                         sdt, s);
 }
 

@@ -157,8 +157,8 @@ def test_autotune_cache_round_trip(tmp_path):
 # ---------------------------------------------------------------------------
 # Tile shapes (afqmc_get_tuning / afqmc_set_tuning / afqmc_autotune)
 # ---------------------------------------------------------------------------
-TILE_CHOICES = [((160, 160), 0, (160, 160)), ((160, 64), 4, (160, 160)), ((160, 160), 2, (64, 160)),
-                ((160, 64), 32, (64, 160))]
+TILE_CHOICES = [((128, 128), 0, (128, 128)), ((128, 64), 4, (128, 128)), ((128, 128), 2, (64, 128)),
+                ((128, 64), 32, (64, 128))]
 
 
 def _pair_systems(seed0):
@@ -219,11 +219,11 @@ def test_tuning_offers_only_built_shapes():
         h32.set_tuning((160, 64), 0, (64, 64))
     assert e.value.code == 4
     h16 = afqmc.Hamiltonian(h1, L, phiT, phiT, dt=0.005, max_walkers=W, precision="fp16x3", exchange="pair")
-    assert h16.tuning() == {"exchange_tile": (160, 160), "exchange_group": 0, "vhs_tile": (160, 160)}
-    for bad in (((128, 128), 0, (160, 160)), ((160, 160), 0, (96, 160)), ((160, 160), -1, (160, 160))):
+    assert h16.tuning() == {"exchange_tile": (128, 128), "exchange_group": 0, "vhs_tile": (128, 128)}
+    for bad in (((160, 160), 0, (128, 128)), ((128, 128), 0, (160, 160)), ((128, 128), -1, (128, 128))):
         with pytest.raises(afqmc.AfqmcError):
             h16.set_tuning(*bad)
-    assert h16.tuning()["exchange_tile"] == (160, 160)   # a refused call changes nothing
+    assert h16.tuning()["exchange_tile"] == (128, 128)   # a refused call changes nothing
     h32.close()
     h16.close()
 
@@ -249,11 +249,11 @@ def test_autotune_chooses_tile_shapes_and_caches_them(tmp_path):
         assert key.startswith("tiles:") and ":p3:" in key
         et, eg = t["exchange_tile"], t["exchange_group"]
         assert ex == f"ex={et[0]}x{et[1]}/{eg}" and vhs == f"vhs={t['vhs_tile'][0]}x{t['vhs_tile'][1]}"
-        assert et in ((160, 160), (160, 64)) and t["vhs_tile"] in ((160, 160), (64, 160))
+        assert et in ((128, 128), (128, 64)) and t["vhs_tile"] in ((128, 128), (64, 128))
         assert eg in (1, 2, 4, 8, 16, 32)
     # reset, then the cache restores every choice without timing (nothing appended)
     for d in sysd:
-        d["ham"].set_tuning((160, 160), 0, (160, 160))
+        d["ham"].set_tuning((128, 128), 0, (128, 128))
     b.autotune(cache)
     assert [l for l in cache.read_text().split("\n") if l.strip()] == lines
     assert [d["ham"].tuning() for d in sysd] == chosen
