@@ -63,6 +63,18 @@ __device__ __forceinline__ void pair_load4(const double* p, double (&v)[4]) {
   v[3] = b.y;
 }
 
+// The value of lane ^ 1 (a DPP quad permutation [1, 0, 3, 2]; every lane is
+// active where it is used).
+__device__ __forceinline__ float pair_from_neighbour(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double pair_from_neighbour(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
 // Epilogue of one tile (group i, local rows lr0 .. lr0 + BM - 1 of R, walker
 // columns (z0 + c / 2, c % 2)).  acc holds U scaled by the operand row scales
 // (SCALED: a_unscale per pair-integral row, b_unscale per theta split row;
@@ -130,9 +142,16 @@ __device__ __forceinline__ void exchange_pair_epilogue(const AccV (&acc)[BM / WM
     }
 #pragma unroll
     for (int f = 0; f < FN; ++f) {
-      TT a[4], b[4];
-      pair_load4(theta + (toff[f] + roff), a);
-      pair_load4(theta + (toff[f] + 2 * plane + roff), b);
+      // the two lanes of a walker's columns (z, re) and (z, im) each load one
+      // theta plane (re and im) and take the other from the neighbour
+      TT mine[4], a[4], b[4];
+      pair_load4(theta + (toff[f] + (comp ? 2 * plane : 0) + roff), mine);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const TT other = pair_from_neighbour(mine[r]);
+        a[r] = comp ? other : mine[r];
+        b[r] = comp ? mine[r] : other;
+      }
       AT xr = 0, xi = 0;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
