@@ -26,22 +26,37 @@ template <class H>
 __global__ __launch_bounds__(256) void split_rows_kernel(long nrows, int ncols, const float* __restrict__ src,
                                                          int ld_src, unsigned short* __restrict__ dst,
                                                          int ldh, float* __restrict__ unscale) {
+  // each lane holds two neighbouring columns of every 128-column chunk: the
+  // row is loaded once (all loads in flight together), and the hi and lo
+  // halves of the pair leave as 4-byte words
+  constexpr int CHUNKS = 1024 / 128;  // rows of up to 1024 split columns (ldh < 1024 here)
   const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= nrows) return;
   const float* s = src + row * ld_src;
+  float x0[CHUNKS], x1[CHUNKS];
   float m = 0.f;
-  for (int c = lane; c < ncols; c += 64) m = fmaxf(m, fabsf(s[c]));
+#pragma unroll
+  for (int t = 0; t < CHUNKS; ++t) {
+    const int c = 128 * t + 2 * lane;
+    x0[t] = c < ncols ? s[c] : 0.f;
+    x1[t] = c + 1 < ncols ? s[c + 1] : 0.f;
+    m = fmaxf(m, fmaxf(fabsf(x0[t]), fabsf(x1[t])));
+  }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
   const float sc = split_row_scale<H>(m);
-  unsigned short* d = dst + row * 2 * ldh;
-  for (int c = lane; c < ldh; c += 64) {
-    const float x = c < ncols ? s[c] * sc : 0.f;
-    const unsigned short xh = H::from_float(x);
-    unsigned short* b = d + (c >> 5) * SPLIT_KB + (c & 31);
-    b[0] = xh;
-    b[32] = H::from_float(x - H::to_float(xh));
+  unsigned* d = reinterpret_cast<unsigned*>(dst + row * 2 * ldh);
+#pragma unroll
+  for (int t = 0; t < CHUNKS; ++t) {
+    const int c = 128 * t + 2 * lane;  // even: the pair lies in one 32-column block
+    if (c >= ldh) break;
+    const float a = x0[t] * sc, b = x1[t] * sc;
+    const unsigned short ah = H::from_float(a), bh = H::from_float(b);
+    const unsigned short al = H::from_float(a - H::to_float(ah)), bl = H::from_float(b - H::to_float(bh));
+    const int w = ((c >> 5) * SPLIT_KB + (c & 31)) >> 1;  // 4-byte word of the hi pair
+    d[w] = (unsigned)ah | ((unsigned)bh << 16);
+    d[w + 16] = (unsigned)al | ((unsigned)bl << 16);  // the lo pair, 32 halves further
   }
   if (lane == 0) unscale[row] = 1.0f / sc;  // power of two: exact
 }
@@ -80,7 +95,7 @@ hipError_t launch_split_rows(long nrows, int ncols, const float* src, int ld_src
                              int ldh, float* unscale, hipStream_t s) {
   if (nrows == 0) return hipSuccess;
   if (ldh % 32 != 0 || ldh < ncols) return hipErrorInvalidValue;
-  if (ncols >= 1024)
+  if (ncols >= 1024 || ldh > 1024)  // the one-wave kernel holds up to 1024 split columns
     hipLaunchKernelGGL(split_rows_wide_kernel<H>, dim3((unsigned)nrows), dim3(256), 0, s, ncols, src, ld_src, dst,
                        ldh, unscale);
   else
