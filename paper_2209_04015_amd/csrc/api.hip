@@ -241,13 +241,26 @@ int seq_theta(afqmc_ham* h, const afqmc_walkers* w, int nw, bool want_e1, hipStr
 // AFQMC_BF16X3 splits the exchange only.
 static bool vhs_split(const afqmc_ham* h) { return h->split == SPLIT_F16; }
 
+// Whether the force bias can leave the exchange's split rows of theta beside
+// its own (one pass over theta for both, when the exchange follows).
+static bool split_theta_both(const afqmc_ham* h) {
+  return vhs_split(h) && split_both_fits(2 * h->d.nmax, h->d.ldh);
+}
+
+// rows_too: also write the exchange's split rows of theta (only when
+// split_theta_both holds).
 template <typename T>
-int seq_force_bias(afqmc_ham* h, int nw, double2* vbias, hipStream_t s) {
+int seq_force_bias(afqmc_ham* h, int nw, double2* vbias, hipStream_t s, bool rows_too = false) {
   if (vhs_split(h)) {
     const StepDims& d = h->d;
-    PHASE(h, AFQMC_PH_SPLIT, s,
-          launch_split_blocks_mode(h->split, nw * 2, 2, d.nmax, d.N, (const float*)h->theta, d.ldN, d.nmax,
-                                   2L * d.nmax, h->fb_th, d.ldh, h->fb_th_unscale, s));
+    if (rows_too)
+      PHASE(h, AFQMC_PH_SPLIT, s,
+            launch_split_both_mode(h->split, nw * 2, 2 * d.nmax, d.N, (const float*)h->theta, d.ldN, d.ldh,
+                                   h->fb_th, h->fb_th_unscale, h->th_split, h->th_unscale, s));
+    else
+      PHASE(h, AFQMC_PH_SPLIT, s,
+            launch_split_blocks_mode(h->split, nw * 2, 2, d.nmax, d.N, (const float*)h->theta, d.ldN, d.nmax,
+                                     2L * d.nmax, h->fb_th, d.ldh, h->fb_th_unscale, s));
     PHASE(h, AFQMC_PH_FORCE_BIAS, s,
           launch_force_bias_split(h->split, d, nw, h->fb_th, h->fb_th_unscale, h->fb_lh, h->fb_lh_unscale,
                                   h->fb_part, vbias, s));
@@ -291,11 +304,12 @@ hipError_t launch_exchange_spin(afqmc_ham* h, int nw, int sp, int* ntg, hipStrea
   return launch_exchange<double>(d, nw, (const double*)h->Lh, (const double*)h->theta, h->part, sp, ntg, s, gs);
 }
 
+// rows_ready: the split rows of theta are already built (by the force bias).
 template <typename T>
 int seq_energy_from_theta(afqmc_ham* h, int nw, double2* e_out, hipStream_t s,
-                          const int* ctr = nullptr, long estep = 0) {
+                          const int* ctr = nullptr, long estep = 0, bool rows_ready = false) {
   int ntg = 0;
-  if (h->split != SPLIT_NONE) {
+  if (h->split != SPLIT_NONE && !rows_ready) {
     const StepDims& d = h->d;
     PHASE(h, AFQMC_PH_SPLIT, s,
           launch_split_rows_mode(h->split, (long)nw * 4 * d.nmax, d.N, (const float*)h->theta, d.ldN,
@@ -386,9 +400,10 @@ int seq_propagate(afqmc_ham* h, afqmc_walkers* w, int nw, const double* fields, 
 template <typename T>
 int seq_local_energy(afqmc_ham* h, const afqmc_walkers* w, int nw, double2* e, hipStream_t s) {
   int rc;
+  const bool both = split_theta_both(h);
   if ((rc = seq_theta<T>(h, w, nw, true, s))) return rc;
-  if ((rc = seq_force_bias<T>(h, nw, h->vbias, s))) return rc;
-  if ((rc = seq_energy_from_theta<T>(h, nw, e, s))) return rc;
+  if ((rc = seq_force_bias<T>(h, nw, h->vbias, s, both))) return rc;
+  if ((rc = seq_energy_from_theta<T>(h, nw, e, s, nullptr, 0, both))) return rc;
   h->c_valid = false;
   return AFQMC_OK;
 }
@@ -411,9 +426,10 @@ int seq_step(afqmc_ham* h, afqmc_walkers* w, int nw, const StepIO& io, int do_qr
   PHASE(h, AFQMC_PH_WEIGHT, s,
         launch_weight(nw, h->logdet, do_qr ? h->corr : nullptr, h->a, (double2*)w->log_ovlp,
                       w->log_w, h->cst, h->status, s));
-  if ((rc = seq_force_bias<T>(h, nw, h->vbias, s))) return rc;
+  const bool both = io.e && split_theta_both(h);
+  if ((rc = seq_force_bias<T>(h, nw, h->vbias, s, both))) return rc;
   if (io.e) {
-    if ((rc = seq_energy_from_theta<T>(h, nw, io.e, s, io.ctr, io.estep))) return rc;
+    if ((rc = seq_energy_from_theta<T>(h, nw, io.e, s, io.ctr, io.estep, both))) return rc;
   }
   h->c_valid = true;
   h->c_phi_a = w->phi_a;

@@ -129,6 +129,16 @@ std::vector<int2> vhs_split_pairs(int N, const std::vector<int2>& blk);
 // (row s * S1 + b * S2 + i of block b), output rows contiguous per block
 hipError_t launch_split_blocks_mode(int mode, int nblocks, int nspl, int nsub, int ncols, const float* src, int ld_src,
                                     long S1, long S2, unsigned short* dst, int ldh, float* unscale, hipStream_t s);
+// Block split (one scale per block of rows consecutive source rows) and row
+// split (one scale per row) of the same rows in one pass: output row
+// b * rows + r of dst_blk and dst_row, scales unscale_blk[b] and
+// unscale_row[b * rows + r]; bit for bit what launch_split_blocks_mode
+// (nspl 1, nsub rows) and launch_split_rows_mode write.  Only for blocks of
+// rows and ldh that split_both_fits accepts (hipErrorInvalidValue otherwise).
+bool split_both_fits(int rows, int ldh);
+hipError_t launch_split_both_mode(int mode, int nblocks, int rows, int ncols, const float* src, int ld_src,
+                                  int ldh, unsigned short* dst_blk, float* unscale_blk, unsigned short* dst_row,
+                                  float* unscale_row, hipStream_t s);
 // vbias = sum_k theta_k Lh_k on block-split operands, the k range in at most
 // FB_SPLIT_CHUNKS chunks (chosen per launch); part: [FB_SPLIT_CHUNKS][2 W][K] floats
 constexpr int FB_SPLIT_CHUNKS = 8;

@@ -930,6 +930,103 @@ hipError_t launch_split_blocks_mode(int mode, int nblocks, int nspl, int nsub, i
   return hipGetLastError();
 }
 
+// Both splits of consecutive rows in one pass, for theta when the force
+// bias and the exchange take it in the same step: block b is rows
+// b * rows .. b * rows + rows - 1 (rows contiguous, stride ld_src), split once
+// with the block's scale (as split_blocks_kernel with S1 = nsub, S2 = rows)
+// into dst_blk and once with each row's own scale (as split_rows_kernel) into
+// dst_row, both at output row b * rows + r.  The source is read once, held
+// in registers (two neighbouring columns of every 128-column chunk per lane,
+// SPLIT_BOTH_RPW rows per wave), and the hi / lo pairs leave as 4-byte
+// words.  Every value written equals what the two separate kernels write.
+constexpr int SPLIT_BOTH_NT = 512;
+constexpr int SPLIT_BOTH_RPW = 8;  // blocks of up to 64 rows
+constexpr int SPLIT_BOTH_CH = 3;   // rows of up to 384 split columns
+template <class H>
+__global__ __launch_bounds__(SPLIT_BOTH_NT) void split_both_kernel(int rows, int ncols, const float* __restrict__ src,
+                                                                   int ld_src, int ldh,
+                                                                   unsigned short* __restrict__ dst_blk,
+                                                                   float* __restrict__ unscale_blk,
+                                                                   unsigned short* __restrict__ dst_row,
+                                                                   float* __restrict__ unscale_row) {
+  constexpr int NW = SPLIT_BOTH_NT / 64;
+  constexpr int RPW = SPLIT_BOTH_RPW, CH = SPLIT_BOTH_CH;
+  __shared__ float red[NW];
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  float x0[RPW][CH], x1[RPW][CH], rm[RPW];
+#pragma unroll
+  for (int j = 0; j < RPW; ++j) {
+    const int r = wid + NW * j;
+    const float* s = src + ((long)b * rows + r) * ld_src;
+    float mr = 0.f;
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      const int c = 128 * t + 2 * lane;
+      x0[j][t] = r < rows && c < ncols ? s[c] : 0.f;
+      x1[j][t] = r < rows && c + 1 < ncols ? s[c + 1] : 0.f;
+      mr = fmaxf(mr, fmaxf(fabsf(x0[j][t]), fabsf(x1[j][t])));
+    }
+    rm[j] = mr;
+  }
+  float m = 0.f;
+#pragma unroll
+  for (int j = 0; j < RPW; ++j) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) rm[j] = fmaxf(rm[j], __shfl_xor(rm[j], o, 64));
+    m = fmaxf(m, rm[j]);
+  }
+  if (lane == 0) red[wid] = m;
+  __syncthreads();
+  m = red[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) m = fmaxf(m, red[w]);
+  const float sb = split_row_scale<H>(m);
+  auto put = [&](unsigned* d, int w, float a, float c) {
+    const unsigned short ah = H::from_float(a), ch = H::from_float(c);
+    const unsigned short al = H::from_float(a - H::to_float(ah)), cl = H::from_float(c - H::to_float(ch));
+    d[w] = (unsigned)ah | ((unsigned)ch << 16);
+    d[w + 16] = (unsigned)al | ((unsigned)cl << 16);  // the lo pair, 32 halves further
+  };
+#pragma unroll
+  for (int j = 0; j < RPW; ++j) {
+    const int r = wid + NW * j;
+    if (r >= rows) break;
+    const float sr = split_row_scale<H>(rm[j]);
+    const long o = ((long)b * rows + r) * 2 * ldh;
+    unsigned* db = reinterpret_cast<unsigned*>(dst_blk + o);
+    unsigned* dr = reinterpret_cast<unsigned*>(dst_row + o);
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      const int c = 128 * t + 2 * lane;  // even: the pair lies in one 32-column block
+      if (c >= ldh) break;
+      const int w = ((c >> 5) * SPLIT_KB + (c & 31)) >> 1;  // 4-byte word of the hi pair
+      put(db, w, x0[j][t] * sb, x1[j][t] * sb);
+      put(dr, w, x0[j][t] * sr, x1[j][t] * sr);
+    }
+    if (lane == 0) unscale_row[(long)b * rows + r] = 1.0f / sr;  // powers of two: exact
+  }
+  if (threadIdx.x == 0) unscale_blk[b] = 1.0f / sb;
+}
+
+bool split_both_fits(int rows, int ldh) {
+  return rows <= SPLIT_BOTH_NT / 64 * SPLIT_BOTH_RPW && ldh <= 128 * SPLIT_BOTH_CH;
+}
+
+hipError_t launch_split_both_mode(int mode, int nblocks, int rows, int ncols, const float* src, int ld_src,
+                                  int ldh, unsigned short* dst_blk, float* unscale_blk, unsigned short* dst_row,
+                                  float* unscale_row, hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  if (ldh % 32 != 0 || ldh < ncols || !split_both_fits(rows, ldh)) return hipErrorInvalidValue;
+  if (mode == SPLIT_BF16)
+    hipLaunchKernelGGL(split_both_kernel<HalfBF16>, dim3(nblocks), dim3(SPLIT_BOTH_NT), 0, s, rows, ncols, src,
+                       ld_src, ldh, dst_blk, unscale_blk, dst_row, unscale_row);
+  else
+    hipLaunchKernelGGL(split_both_kernel<HalfF16>, dim3(nblocks), dim3(SPLIT_BOTH_NT), 0, s, rows, ncols, src,
+                       ld_src, ldh, dst_blk, unscale_blk, dst_row, unscale_row);
+  return hipGetLastError();
+}
+
 // C_c[(z, re|im)][g] over the k blocks of chunk c: A = theta block-split rows
 // (2 W), B = Lh block-split rows (K), both 2 nmax sub-rows of 2 ldh halves.
 

@@ -74,6 +74,43 @@ def test_batch_equals_per_system_steps(precision, use_graph):
     b.close()
 
 
+def test_one_pass_theta_split_matches_separate_splits():
+    """A step with the energy splits theta for the force bias and the exchange
+    in one pass (FP16X3); the batch still takes the two splits separately.
+    With 31 + 31 electrons of 260 orbitals (62-row blocks of 288 split
+    columns: the one-pass kernel's third column chunk partly filled, a ragged
+    tail of four columns) the two must agree bit for bit."""
+    import torch
+
+    from paper_2209_04015_amd import afqmc
+
+    N, n, W, K = 260, 31, 8, 260
+    h1, L = inputs.hamiltonian(N, K, K / 5.0, seed=7)
+    phiT = inputs.trial(h1, n)
+    pa = inputs.walkers_perturbed(phiT, W, 0.2, seed=7, stream=0)
+    pb = inputs.walkers_perturbed(phiT, W, 0.2, seed=7, stream=1)
+    ham = afqmc.Hamiltonian(h1, L, phiT, phiT, dt=0.005, max_walkers=W, precision="fp16x3")
+    xs = torch.as_tensor(inputs.fields(W, K, 2, seed=7), device="cuda")
+    out = []
+    for batched in (False, True):
+        w = afqmc.Walkers.from_numpy(pa, pb, np.zeros(W, complex), np.zeros(W))
+        ham.overlap(w)
+        es = torch.zeros((2, W, 3), dtype=torch.complex128, device="cuda")
+        if batched:
+            b = afqmc.Batch([ham], [w], use_graph=False)
+            b.step([xs], [es], do_qr=True)
+            b.close()
+        else:
+            for k in range(2):
+                ham.step(w, xs[k], do_qr=True, energy_out=es[k], reuse=(k > 0))
+        torch.cuda.synchronize()
+        out.append((w.phi_a.clone(), es))
+    assert torch.isfinite(out[0][1].real).all()
+    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][1], out[1][1])
+    ham.close()
+
+
 def test_graph_replays_match_eager_with_work_between():
     import torch
 
