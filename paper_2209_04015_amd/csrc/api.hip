@@ -12,6 +12,7 @@
 #include <map>
 #include <sstream>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/afqmc.h"
@@ -327,13 +328,22 @@ int seq_energy_from_theta(afqmc_ham* h, int nw, double2* e_out, hipStream_t s,
 template <typename T>
 int seq_propagate_core(afqmc_ham* h, afqmc_walkers* w, int nw, const StepIO& io, hipStream_t s) {
   const StepDims& d = h->d;
-  PHASE(h, AFQMC_PH_SHIFT, s,
-        (launch_shift<T>(d, nw, h->vbias, io.fields, io.ctr, io.fstep, (T*)h->xs, h->a, h->tmax,
-                         h->prm.taylor_order + 2, h->prm.max_walkers, h->sdt, h->lmax, s)));
+  // the split VHS build reads only the split rows of the shifted fields: the
+  // shift writes them itself when a walker's row fits its registers
+  const bool shift_split = std::is_same<T, float>::value && vhs_split(h) && shift_split_fits(d.ldhK);
+  if (shift_split)
+    PHASE(h, AFQMC_PH_SHIFT, s,
+          launch_shift_split(h->split, d, nw, h->vbias, io.fields, io.ctr, io.fstep, h->xs_split, h->xs_unscale,
+                             h->a, h->tmax, h->prm.taylor_order + 2, h->prm.max_walkers, h->sdt, h->lmax, s));
+  else
+    PHASE(h, AFQMC_PH_SHIFT, s,
+          (launch_shift<T>(d, nw, h->vbias, io.fields, io.ctr, io.fstep, (T*)h->xs, h->a, h->tmax,
+                           h->prm.taylor_order + 2, h->prm.max_walkers, h->sdt, h->lmax, s)));
   if (vhs_split(h)) {
-    PHASE(h, AFQMC_PH_SPLIT, s,
-          launch_split_rows_mode(h->split, (long)nw * 2, d.K, (const float*)h->xs, d.ldK, h->xs_split, d.ldhK,
-                                 h->xs_unscale, s));
+    if (!shift_split)
+      PHASE(h, AFQMC_PH_SPLIT, s,
+            launch_split_rows_mode(h->split, (long)nw * 2, d.K, (const float*)h->xs, d.ldK, h->xs_split, d.ldhK,
+                                   h->xs_unscale, s));
     PHASE(h, AFQMC_PH_VHS, s,
           launch_vhs_split(h->split, d, nw, h->xs_split, h->xs_unscale, h->lt_split, h->lt_unscale, h->vblk,
                            h->nvblk, (float*)h->vhs, h->tmax + h->prm.max_walkers, h->prop_fused, h->sdt, s,

@@ -106,6 +106,16 @@ hipError_t set_kernel_attributes(const StepDims& d);
 // row scales
 hipError_t launch_split_rows_mode(int mode, long nrows, int ncols, const float* src, int ld_src,
                                   unsigned short* dst, int ldh, float* unscale, hipStream_t s);
+// The FP32 shift (launch_shift<float>: the sums a and the |VHS| bound in
+// tmax) with its rows written only as split rows (rows 2 z and 2 z + 1 of
+// xs_split, 2 ldhK halves, scales xs_unscale), as launch_split_rows_mode over
+// the FP32 shifted fields stores them; for ldhK that shift_split_fits accepts
+// (hipErrorInvalidValue otherwise).
+bool shift_split_fits(int ldhK);
+hipError_t launch_shift_split(int mode, const StepDims& d, int W, const double2* vbias, const double* x,
+                              const int* ctr, long x_step, unsigned short* xs_split, float* xs_unscale, double2* a,
+                              unsigned* tmax, int tslots, int tstride, double sdt, const float* lmax,
+                              hipStream_t s);
 ExTile exchange_split_tile(int n);
 // Walker-tile shapes of the split VHS and pair-exchange kernels (autotuner
 // choices): WIDE 80 walkers per tile, NARROW 32 (more workgroups for systems

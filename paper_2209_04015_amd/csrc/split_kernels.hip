@@ -111,6 +111,116 @@ hipError_t launch_split_rows_mode(int mode, long nrows, int ncols, const float* 
 }
 
 // ---------------------------------------------------------------------------
+// Shift and split in one pass (Eq. of the optimal force bias, Sec. II.B): for
+// the split VHS build, which reads only the split rows of the shifted fields.
+// Per walker z: xbar = -i sqrt(dt) vbias, xs = x - xbar rounded to FP32, the
+// sum a_z = sum_g (x xbar - xbar^2 / 2), and the |VHS| bound
+// sqrt(dt) max(sum_g |Re xs_g| m_g, sum_g |Im xs_g| m_g) (1 + 2^-9) into slot
+// 1 of tmax (every slot zeroed first), each summed in the same order as the
+// FP32 shift kernel; rows 2 z (Re xs) and 2 z + 1 (Im xs) leave as split rows
+// with their row scales, as the row split of that kernel's output would
+// store them.  One workgroup per walker, the row in registers (K <= 256 KI).
+// ---------------------------------------------------------------------------
+constexpr int SHIFT_SPLIT_KI = 16;
+template <class H>
+__global__ __launch_bounds__(256) void shift_split_kernel(int K, const double2* __restrict__ vbias,
+                                                          const double* __restrict__ x_base,
+                                                          const int* __restrict__ ctr, long x_step,
+                                                          unsigned short* __restrict__ xs_split, int ldhK,
+                                                          float* __restrict__ xs_unscale, double2* __restrict__ a,
+                                                          unsigned* __restrict__ tmax, int tslots, int tstride,
+                                                          double sdt, const float* __restrict__ lmax) {
+  constexpr int KI = SHIFT_SPLIT_KI;
+  __shared__ double2 red[4];
+  __shared__ float fred[2][4];
+  const int z = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const double* x = x_base + (ctr ? (size_t)ctr[0] * x_step : 0);
+  double2 acc = make_double2(0.0, 0.0);
+  double2 bnd = make_double2(0.0, 0.0);
+  float re[KI], im[KI];
+  float mre = 0.f, mim = 0.f;
+#pragma unroll
+  for (int i = 0; i < KI; ++i) {
+    const int g = tid + 256 * i;
+    re[i] = 0.f;
+    im[i] = 0.f;
+    if (g < K) {
+      const double2 v = vbias[(size_t)z * K + g];
+      const double2 xb = make_double2(sdt * v.y, -sdt * v.x);
+      const double xv = x[(size_t)z * K + g];
+      re[i] = (float)(xv - xb.x);
+      im[i] = (float)(-xb.y);
+      acc.x += xv * xb.x - 0.5 * (xb.x * xb.x - xb.y * xb.y);
+      acc.y += xv * xb.y - xb.x * xb.y;
+      if (lmax) {
+        const double m = lmax[g];
+        bnd.x += fabs((double)re[i]) * m;
+        bnd.y += fabs((double)im[i]) * m;
+      }
+      mre = fmaxf(mre, fabsf(re[i]));
+      mim = fmaxf(mim, fabsf(im[i]));
+    }
+  }
+  const double2 sum = block_sum2(acc, red);
+  const double2 b = lmax ? block_sum2(bnd, red) : bnd;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mre = fmaxf(mre, __shfl_xor(mre, o, 64));
+    mim = fmaxf(mim, __shfl_xor(mim, o, 64));
+  }
+  if (lane == 0) {
+    fred[0][wid] = mre;
+    fred[1][wid] = mim;
+  }
+  __syncthreads();
+  mre = fmaxf(fmaxf(fred[0][0], fred[0][1]), fmaxf(fred[0][2], fred[0][3]));
+  mim = fmaxf(fmaxf(fred[1][0], fred[1][1]), fmaxf(fred[1][2], fred[1][3]));
+  const float sre = split_row_scale<H>(mre), sim = split_row_scale<H>(mim);
+  unsigned short* dre = xs_split + (size_t)(2 * z) * 2 * ldhK;
+  unsigned short* dim = dre + 2 * ldhK;
+#pragma unroll
+  for (int i = 0; i < KI; ++i) {
+    const int c = tid + 256 * i;
+    if (c >= ldhK) break;
+    const int o = (c >> 5) * SPLIT_KB + (c & 31);
+    const float u = re[i] * sre, v = im[i] * sim;
+    const unsigned short uh = H::from_float(u), vh = H::from_float(v);
+    dre[o] = uh;
+    dre[o + 32] = H::from_float(u - H::to_float(uh));
+    dim[o] = vh;
+    dim[o + 32] = H::from_float(v - H::to_float(vh));
+  }
+  if (tid == 0) {
+    xs_unscale[2 * z] = 1.0f / sre;  // powers of two: exact
+    xs_unscale[2 * z + 1] = 1.0f / sim;
+    a[z] = sum;
+    for (int t = 0; t < tslots; ++t) tmax[(size_t)t * tstride + z] = 0u;  // running maxima of this step
+    // |VHS| bound (slot 1): both parts of VHS = i sqrt(dt) sum_g xs_g L_g are
+    // at most sqrt(dt) sum_g |xs part| max|L_g|; the margin covers the
+    // rounding of the FP32 sums of the split build
+    if (lmax) tmax[(size_t)tstride + z] = __float_as_uint((float)(sdt * fmax(b.x, b.y) * (1.0 + 0x1p-9)));
+  }
+}
+
+bool shift_split_fits(int ldhK) { return ldhK <= 256 * SHIFT_SPLIT_KI; }
+
+hipError_t launch_shift_split(int mode, const StepDims& d, int W, const double2* vbias, const double* x,
+                              const int* ctr, long x_step, unsigned short* xs_split, float* xs_unscale, double2* a,
+                              unsigned* tmax, int tslots, int tstride, double sdt, const float* lmax,
+                              hipStream_t s) {
+  if (W == 0) return hipSuccess;
+  if (d.ldhK % 32 != 0 || d.ldhK < d.K || !shift_split_fits(d.ldhK)) return hipErrorInvalidValue;
+  if (mode == SPLIT_BF16)
+    hipLaunchKernelGGL(shift_split_kernel<HalfBF16>, dim3(W), dim3(256), 0, s, d.K, vbias, x, ctr, x_step,
+                       xs_split, d.ldhK, xs_unscale, a, tmax, tslots, tstride, sdt, lmax);
+  else
+    hipLaunchKernelGGL(shift_split_kernel<HalfF16>, dim3(W), dim3(256), 0, s, d.K, vbias, x, ctr, x_step,
+                       xs_split, d.ldhK, xs_unscale, a, tmax, tslots, tstride, sdt, lmax);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Exchange on split operands.
 // ---------------------------------------------------------------------------
 // 4-wave workgroups of 2 x 2 wave tiles; register prefetch of the next k
