@@ -1113,12 +1113,27 @@ __global__ __launch_bounds__(256) void energy_kernel(int W, int K, int ntg, int 
                                                      double2* __restrict__ e_base,
                                                      const int* __restrict__ ctr, long e_step) {
   __shared__ double2 red[4];
-  const int z = blockIdx.x;
+  // Workgroups go round the 8 XCDs in turn; the exchange partials of 8
+  // neighbouring walkers share cache lines, so when the walker count is a
+  // multiple of 8 each XCD takes a contiguous range of walkers (one L2 fetch
+  // per line instead of one per XCD).
+  const int nb = gridDim.x;
+  const int z = (nb & 7) == 0 ? (int)(blockIdx.x & 7) * (nb >> 3) + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
   double2* e_out = e_base + (ctr ? (size_t)ctr[0] * e_step : 0);
+  // batches of EJ_BATCH loads in flight per thread; each thread still adds
+  // its terms in increasing g
+  constexpr int EJ_BATCH = 8;
   double2 ej = make_double2(0.0, 0.0);
-  for (int g = threadIdx.x; g < K; g += 256) {
-    const double2 v = vbias[(size_t)z * K + g];
-    ej = cadd(ej, cmul(v, v));
+  for (int g0 = threadIdx.x; g0 < K; g0 += 256 * EJ_BATCH) {
+    double2 v[EJ_BATCH];
+#pragma unroll
+    for (int u = 0; u < EJ_BATCH; ++u) {
+      const int g = g0 + 256 * u;
+      v[u] = g < K ? vbias[(size_t)z * K + g] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < EJ_BATCH; ++u)
+      if (g0 + 256 * u < K) ej = cadd(ej, cmul(v[u], v[u]));
   }
   ej = block_sum2(ej, red);
   double2 ek = make_double2(0.0, 0.0);
