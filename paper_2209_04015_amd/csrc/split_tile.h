@@ -55,14 +55,17 @@ struct HalfF16 {
 };
 
 // Power-of-two row scale that puts the row maximum in [2^13, 2^14) (FP16), or 1.
+// The scale stops at 2^127, the largest finite power of two: rows whose
+// maximum lies below 2^-114 come out below 2^13 (their hi / lo parts may fall
+// under the FP16 normal range, at magnitudes far below every other term).
 template <class H>
 __device__ __forceinline__ float split_row_scale(float rowmax) {
   if constexpr (!H::SCALED) {
     return 1.0f;
   } else {
     if (!(rowmax > 0.f) || !isfinite(rowmax)) return 1.0f;
-    const int e = ilogbf(rowmax);  // rowmax in [2^e, 2^(e+1))
-    return ldexpf(1.0f, 13 - e);
+    const int k = 13 - ilogbf(rowmax);  // rowmax in [2^(13-k), 2^(14-k))
+    return ldexpf(1.0f, k < 127 ? k : 127);
   }
 }
 

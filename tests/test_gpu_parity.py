@@ -694,10 +694,17 @@ def test_fused_step_at_n290_sampled(precision, one_body_fp64):
 # ---------------------------------------------------------------------------
 # The size limits of the kernels: 45 electrons per spin (the Green's function
 # and exchange tiles) with the largest N the in-LDS QR takes for it, and the
-# largest N for the n290 electron count; one fused step, bars as above.
+# largest N for the n290 electron count; one fused step, bars as above.  The
+# first also takes theta's two splits separately in FP16X3 (blocks of 90 rows,
+# past the 64 of the one-pass split), and a third case has more Cholesky
+# vectors (4200) than the one-pass shift and split holds in registers (4096),
+# so that the FP16X3 step shifts and splits the fields in two kernels; its
+# vectors decay to below 2^-114, where a row scale putting the maximum at
+# 2^13 would exceed the largest FP32 power of two (the scale stops at 2^127).
 # ---------------------------------------------------------------------------
 LIMITS = [inputs.Config("n45_max", N=177, n=45, K=60, decay=20.0, W=6, steps=1, qr_interval=1),
-          inputs.Config("N_max", N=361, n=26, K=40, decay=15.0, W=4, steps=1, qr_interval=1)]
+          inputs.Config("N_max", N=361, n=26, K=40, decay=15.0, W=4, steps=1, qr_interval=1),
+          inputs.Config("K_wide", N=24, n=5, K=4200, decay=40.0, W=4, steps=1, qr_interval=1)]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp16x3"])
