@@ -119,20 +119,22 @@ hipError_t launch_split_rows_mode(int mode, long nrows, int ncols, const float* 
 // 1 of tmax (every slot zeroed first), each summed in the same order as the
 // FP32 shift kernel; rows 2 z (Re xs) and 2 z + 1 (Im xs) leave as split rows
 // with their row scales, as the row split of that kernel's output would
-// store them.  One workgroup per walker, the row in registers (K <= 256 KI).
+// store them.  One workgroup of eight waves per walker, the row in registers
+// (K <= SHIFT_SPLIT_NT KI).
 // ---------------------------------------------------------------------------
-constexpr int SHIFT_SPLIT_KI = 16;
+constexpr int SHIFT_SPLIT_NT = 512;
+constexpr int SHIFT_SPLIT_KI = 8;
 template <class H>
-__global__ __launch_bounds__(256) void shift_split_kernel(int K, const double2* __restrict__ vbias,
+__global__ __launch_bounds__(SHIFT_SPLIT_NT) void shift_split_kernel(int K, const double2* __restrict__ vbias,
                                                           const double* __restrict__ x_base,
                                                           const int* __restrict__ ctr, long x_step,
                                                           unsigned short* __restrict__ xs_split, int ldhK,
                                                           float* __restrict__ xs_unscale, double2* __restrict__ a,
                                                           unsigned* __restrict__ tmax, int tslots, int tstride,
                                                           double sdt, const float* __restrict__ lmax) {
-  constexpr int KI = SHIFT_SPLIT_KI;
-  __shared__ double2 red[4];
-  __shared__ float fred[2][4];
+  constexpr int KI = SHIFT_SPLIT_KI, NT = SHIFT_SPLIT_NT, NW = NT / 64;
+  __shared__ double2 red[NW];
+  __shared__ float fred[2][NW];
   const int z = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const double* x = x_base + (ctr ? (size_t)ctr[0] * x_step : 0);
@@ -142,7 +144,7 @@ __global__ __launch_bounds__(256) void shift_split_kernel(int K, const double2* 
   float mre = 0.f, mim = 0.f;
 #pragma unroll
   for (int i = 0; i < KI; ++i) {
-    const int g = tid + 256 * i;
+    const int g = tid + NT * i;
     re[i] = 0.f;
     im[i] = 0.f;
     if (g < K) {
@@ -174,14 +176,19 @@ __global__ __launch_bounds__(256) void shift_split_kernel(int K, const double2* 
     fred[1][wid] = mim;
   }
   __syncthreads();
-  mre = fmaxf(fmaxf(fred[0][0], fred[0][1]), fmaxf(fred[0][2], fred[0][3]));
-  mim = fmaxf(fmaxf(fred[1][0], fred[1][1]), fmaxf(fred[1][2], fred[1][3]));
+  mre = fred[0][0];
+  mim = fred[1][0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) {
+    mre = fmaxf(mre, fred[0][w]);
+    mim = fmaxf(mim, fred[1][w]);
+  }
   const float sre = split_row_scale<H>(mre), sim = split_row_scale<H>(mim);
   unsigned short* dre = xs_split + (size_t)(2 * z) * 2 * ldhK;
   unsigned short* dim = dre + 2 * ldhK;
 #pragma unroll
   for (int i = 0; i < KI; ++i) {
-    const int c = tid + 256 * i;
+    const int c = tid + NT * i;
     if (c >= ldhK) break;
     const int o = (c >> 5) * SPLIT_KB + (c & 31);
     const float u = re[i] * sre, v = im[i] * sim;
@@ -203,7 +210,7 @@ __global__ __launch_bounds__(256) void shift_split_kernel(int K, const double2* 
   }
 }
 
-bool shift_split_fits(int ldhK) { return ldhK <= 256 * SHIFT_SPLIT_KI; }
+bool shift_split_fits(int ldhK) { return ldhK <= SHIFT_SPLIT_NT * SHIFT_SPLIT_KI; }
 
 hipError_t launch_shift_split(int mode, const StepDims& d, int W, const double2* vbias, const double* x,
                               const int* ctr, long x_step, unsigned short* xs_split, float* xs_unscale, double2* a,
@@ -212,10 +219,10 @@ hipError_t launch_shift_split(int mode, const StepDims& d, int W, const double2*
   if (W == 0) return hipSuccess;
   if (d.ldhK % 32 != 0 || d.ldhK < d.K || !shift_split_fits(d.ldhK)) return hipErrorInvalidValue;
   if (mode == SPLIT_BF16)
-    hipLaunchKernelGGL(shift_split_kernel<HalfBF16>, dim3(W), dim3(256), 0, s, d.K, vbias, x, ctr, x_step,
+    hipLaunchKernelGGL(shift_split_kernel<HalfBF16>, dim3(W), dim3(SHIFT_SPLIT_NT), 0, s, d.K, vbias, x, ctr, x_step,
                        xs_split, d.ldhK, xs_unscale, a, tmax, tslots, tstride, sdt, lmax);
   else
-    hipLaunchKernelGGL(shift_split_kernel<HalfF16>, dim3(W), dim3(256), 0, s, d.K, vbias, x, ctr, x_step,
+    hipLaunchKernelGGL(shift_split_kernel<HalfF16>, dim3(W), dim3(SHIFT_SPLIT_NT), 0, s, d.K, vbias, x, ctr, x_step,
                        xs_split, d.ldhK, xs_unscale, a, tmax, tslots, tstride, sdt, lmax);
   return hipGetLastError();
 }

@@ -1138,9 +1138,17 @@ __global__ __launch_bounds__(256) void energy_kernel(int W, int K, int ntg, int 
   ej = block_sum2(ej, red);
   double2 ek = make_double2(0.0, 0.0);
   const int nsp = nb_zero ? 1 : 2;
-  for (int e = threadIdx.x; e < nsp * ntg; e += 256) {
-    const int sp = e / ntg, t = e % ntg;
-    ek = cadd(ek, part[((size_t)sp * ntg + t) * W + z]);
+  // the partials of (spin, tile group) e sit at row e (sp ntg + t = e)
+  for (int e0 = threadIdx.x; e0 < nsp * ntg; e0 += 256 * EJ_BATCH) {
+    double2 v[EJ_BATCH];
+#pragma unroll
+    for (int u = 0; u < EJ_BATCH; ++u) {
+      const int e = e0 + 256 * u;
+      v[u] = e < nsp * ntg ? part[(size_t)e * W + z] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < EJ_BATCH; ++u)
+      if (e0 + 256 * u < nsp * ntg) ek = cadd(ek, v[u]);
   }
   ek = block_sum2(ek, red);
   if (threadIdx.x == 0) {
