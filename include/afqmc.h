@@ -313,7 +313,8 @@ int afqmc_get_setup(afqmc_ham* ham, double* host_P, double* mu, double* e_shift)
 enum {
   AFQMC_PH_GREEN = 0,    /* overlap, Green's function theta, one-body energy */
   AFQMC_PH_FORCE_BIAS,   /* vbias = Lh . theta */
-  AFQMC_PH_SHIFT,        /* xbar, x - xbar, importance exponent */
+  AFQMC_PH_SHIFT,        /* xbar, x - xbar, importance exponent (in
+                            AFQMC_FP16X3 also the split of x - xbar) */
   AFQMC_PH_VHS,          /* VHS = i sqrt(dt) sum_g (x - xbar)_g L_g */
   AFQMC_PH_ONE_BODY,     /* P phi (one launch per half step) */
   AFQMC_PH_TAYLOR,       /* one launch per Taylor term */
@@ -321,8 +322,10 @@ enum {
   AFQMC_PH_WEIGHT,       /* overlap ratio, phase, log weight */
   AFQMC_PH_EXCHANGE,     /* one launch per spin */
   AFQMC_PH_ENERGY,       /* assembly of E1, EJ, EK */
-  AFQMC_PH_SPLIT,        /* hi/lo split of theta and of the shifted fields
-                            (16-bit split modes) */
+  AFQMC_PH_SPLIT,        /* hi/lo splits of theta (16-bit split modes;
+                            with the energy in AFQMC_FP16X3 both in one
+                            launch), and of the shifted fields where the
+                            shift does not split them */
   AFQMC_PH_CONTROL,      /* global energy and population control */
   AFQMC_PH_ESTIMATOR,    /* mixed estimators: full Green's function, S^2, weighted means */
   AFQMC_PH_PROPAGATE,    /* P T(VHS) P phi in one launch (AFQMC_FP16X3) */
