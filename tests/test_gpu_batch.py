@@ -74,17 +74,19 @@ def test_batch_equals_per_system_steps(precision, use_graph):
     b.close()
 
 
-def test_one_pass_theta_split_matches_separate_splits():
+@pytest.mark.parametrize("N,n", [(260, 31), (70, 32)])
+def test_one_pass_theta_split_matches_separate_splits(N, n):
     """A step with the energy splits theta for the force bias and the exchange
     in one pass (FP16X3); the batch still takes the two splits separately.
     With 31 + 31 electrons of 260 orbitals (62-row blocks of 288 split
     columns: the one-pass kernel's third column chunk partly filled, a ragged
-    tail of four columns) the two must agree bit for bit."""
+    tail of four columns) and 32 + 32 of 70 (64-row blocks, the most it
+    takes) the two must agree bit for bit."""
     import torch
 
     from paper_2209_04015_amd import afqmc
 
-    N, n, W, K = 260, 31, 8, 260
+    W, K = 8, N
     h1, L = inputs.hamiltonian(N, K, K / 5.0, seed=7)
     phiT = inputs.trial(h1, n)
     pa = inputs.walkers_perturbed(phiT, W, 0.2, seed=7, stream=0)
